@@ -1,0 +1,20 @@
+"""Seeded synthetic inputs for the mortar coupling path.
+
+This package generates surface meshes (nodal coordinates and quad4
+connectivity) and keyed upstream weights.  It holds none of the mortar
+method's arithmetic: no projection, clipping, quadrature or assembly.  Both
+the HIP path's tests/bench and the CPU oracle draw their inputs from here.
+"""
+
+from .meshes import (  # noqa: F401
+    Mesh,
+    Interface,
+    tensor_grid,
+    flat_tied,
+    cylinder,
+    wavy,
+    interface_config,
+    batched_instances,
+    CONFIG_NAMES,
+)
+from .weights import keyed_normal, upstream_weights  # noqa: F401
