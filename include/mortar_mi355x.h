@@ -1,0 +1,249 @@
+/*
+ * mortar_mi355x.h -- C ABI of the MI355X (gfx950) mortar coupling library.
+ *
+ * Evaluates the mortar coupling operators of a non-matching surface
+ * interface (Mayr & Popp, "Scalable computational kernels for mortar finite
+ * element methods"): the slave matrix D and the slave x master matrix M of
+ * eq. (DiscreteWeakFormInterfaceFlux), plus a weighted gap, by segment-based
+ * integration (Alg. 1) over the element pairs found by a bin-based contact
+ * search (Alg. 2 and the bin-sizing rule of Sec. "Geometrically motivated
+ * binning"), and the gradient of a weighted sum of those outputs with respect
+ * to all nodal coordinates (the linearisation every nonlinear iteration
+ * needs, Sec. "Introduction").
+ *
+ * Conventions (apply to every entry point):
+ *  - All array arguments are DEVICE pointers on the context's device unless
+ *    stated otherwise; scalars returned through int64_t* / struct pointers
+ *    are HOST pointers.
+ *  - `stream` is a hipStream_t (NULL = the legacy default stream).  All GPU
+ *    work is enqueued on it.  Entry points that must report a data-dependent
+ *    size (mt_build_pairs, mt_csr_pattern) synchronise that stream once.
+ *  - Inputs and outputs are owned by the caller and must stay valid while a
+ *    call that reads or writes them runs.  Meshes are registered, not
+ *    copied: mt_upload keeps the pointers, and the arrays must stay alive and
+ *    unchanged-in-shape until the next mt_upload of that side or
+ *    mt_destroy.  Intermediate data (bins, candidates, pair list, CSR
+ *    pattern, per-pair staging) lives in device memory owned by the context;
+ *    it grows on demand and is released by mt_destroy.
+ *  - Indices are 0-based int32; coordinates and values are IEEE double.
+ *    Coordinates are structure-of-arrays: x[n], y[n], z[n].  Connectivity is
+ *    int32 conn[n_el][4] (16-byte aligned), nodes counter-clockwise around
+ *    the element normal: parameter corners (-1,-1), (1,-1), (1,1), (-1,1).
+ *  - Return value: MT_OK or one of the MT_E* codes below.  mt_last_error()
+ *    returns a message for the calling thread's last failure.
+ *  - A context is not thread-safe; use one context per host thread.
+ *    Results are bitwise reproducible run to run (no floating-point atomics).
+ */
+#ifndef MORTAR_MI355X_H
+#define MORTAR_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define MT_OK 0
+#define MT_EINVAL 1        /* bad argument: null pointer, size, alignment, index range */
+#define MT_ECAPACITY 2     /* a caller buffer or a fixed capacity is too small */
+#define MT_EHIP 3          /* a HIP runtime call failed */
+#define MT_ENOCONV 4       /* an inverse bilinear map did not converge (values still written) */
+#define MT_EDEGENERATE 5   /* non-positive projected slave area or clip capacity exceeded */
+#define MT_ESTATE 6        /* called out of order (e.g. integrate before build_pairs) */
+#define MT_EUNSUPPORTED 7  /* option not supported by this entry point */
+
+#define MT_SIDE_SLAVE 0
+#define MT_SIDE_MASTER 1
+
+#define MT_BASIS_STANDARD 0 /* Phi_j = N_j */
+#define MT_BASIS_DUAL 1     /* biorthogonal Phi_j (D diagonal on covered slave elements) */
+
+typedef struct mt_ctx mt_ctx;
+
+/* Algorithm parameters.  Defaults (mt_default_params): delta 0, automatic
+ * bins, standard basis, 7-point rule, eps_d = eps_a = 1e-12,
+ * newton_tol = 1e-14, newton_maxit = 30. */
+typedef struct mt_params {
+  double delta;        /* search: slave bounding box enlarged by delta per side */
+  double bin_size;     /* search: minimal bin edge; 0 = automatic (see mt_build_pairs) */
+  int32_t lm_basis;    /* MT_BASIS_STANDARD or MT_BASIS_DUAL */
+  int32_t rule;        /* triangle rule: 3 (degree 2) or 7 (degree 5) */
+  double eps_d;        /* relative merge / collinearity tolerance of the clip cleanup */
+  double eps_a;        /* relative area below which an overlap is not a segment */
+  double newton_tol;   /* inverse bilinear map: stop when max |d xi| <= tol */
+  int32_t newton_maxit;
+  int32_t reserved;
+} mt_params;
+
+/* Counters of the last build / integrate / backward on a context. */
+typedef struct mt_stats {
+  int64_t n_candidates;     /* pairs of overlapping (delta-enlarged) bounding boxes */
+  int64_t n_pairs;          /* candidates whose clip polygon is a segment */
+  int64_t nverts_hist[17];  /* pairs per clip-polygon vertex count (index = count) */
+  int64_t n_noconv;         /* quadrature points whose inverse map did not converge */
+  int64_t n_overflow;       /* candidates whose clip exceeded the working capacity */
+  int64_t n_degenerate_slave;
+  int64_t n_degenerate_master;
+  int64_t nnz_D, nnz_M;
+  int64_t n_bins[3];        /* search grid */
+  double bin_size[3];
+} mt_stats;
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Create a context bound to HIP device `device`.  *ctx receives a host
+ * handle.  Errors: MT_EINVAL (null ctx), MT_EHIP (bad device). */
+int mt_create(mt_ctx** ctx, int device);
+
+/* Release the context and all device memory it owns.  NULL is a no-op. */
+int mt_destroy(mt_ctx* ctx);
+
+/* Fill *p with the defaults listed at mt_params. */
+int mt_default_params(mt_params* p);
+
+/* Set parameters (copied).  Invalidates the pair list.  Errors: MT_EINVAL
+ * for rule not in {3, 7}, lm_basis out of range, negative tolerances. */
+int mt_set_params(mt_ctx* ctx, const mt_params* p);
+
+/* Register one side of the interface (MT_SIDE_SLAVE or MT_SIDE_MASTER):
+ * n_nodes coordinates x, y, z and n_el quad4 elements conn[n_el][4]
+ * (device pointers, kept, not copied; eq. (AnsatzDiscretization) surface
+ * meshes).  Invalidates the pair list.  Connectivity indices are checked
+ * against n_nodes on the device during mt_build_pairs (MT_EINVAL).  Errors:
+ * MT_EINVAL for null pointers with non-zero sizes, conn not 16-byte aligned,
+ * sizes >= 2^31. */
+int mt_upload(mt_ctx* ctx, int side, int64_t n_nodes, const double* x, const double* y,
+              const double* z, int64_t n_el, const int32_t* conn, void* stream);
+
+/* Replace the coordinate arrays of an uploaded side with arrays of the same
+ * length (device pointers, kept), KEEPING the pair list and CSR pattern: the
+ * fixed-topology evaluation a Newton iteration or a gradient check needs.
+ * mt_integrate / mt_backward then use the new coordinates; mt_build_pairs
+ * recomputes the pairs.  Errors: MT_ESTATE (side not uploaded), MT_EINVAL. */
+int mt_update_coordinates(mt_ctx* ctx, int side, const double* x, const double* y, const double* z,
+                          void* stream);
+
+/* Contact search and clipping (Alg. 2, then the projection and clipping
+ * steps of Alg. 1):
+ *  1. per element: bounding box; per slave element: auxiliary plane (centre
+ *     x0, normal n0, in-plane basis t1, t2) and, for the dual basis, its
+ *     coefficient matrix;
+ *  2. Cartesian bins over the nodes' bounding box expanded by the minimal
+ *     bin size beta_min = max(longest slave edge, largest element box extent
+ *     + delta, params.bin_size) (the paper's rule without a motion term,
+ *     raised so that 27 bins are complete); master elements sorted by bin
+ *     with a radix sort, bin ranges by segmented scan;
+ *  3. candidates: (s, m) whose boxes overlap after enlarging the slave box by
+ *     delta, found in the 27 bins around s, sorted by (s, m);
+ *  4. each candidate is projected onto the slave auxiliary plane and the
+ *     slave polygon is clipped by the master polygon (Sutherland-Hodgman,
+ *     then cleanup); a candidate whose cleaned polygon has >= 3 vertices and
+ *     area > eps_a * slave area is a pair.
+ * Writes the counts to *n_cand and *n_pairs (host).  Synchronises `stream`.
+ * Errors: MT_ESTATE (a side not uploaded), MT_EINVAL (connectivity out of
+ * range), MT_EDEGENERATE (a slave element with non-positive projected area
+ * or a clip exceeding capacity; counts still written). */
+int mt_build_pairs(mt_ctx* ctx, int64_t* n_cand, int64_t* n_pairs, void* stream);
+
+/* Copy the pair list, sorted by (slave element, master element): n_pairs
+ * entries each (sizes from mt_build_pairs); nverts = vertex count of the
+ * cleaned clip polygon (3..16).  Any pointer may be NULL to skip it.
+ * Errors: MT_ESTATE before mt_build_pairs. */
+int mt_get_pairs(mt_ctx* ctx, int32_t* slave_el, int32_t* master_el, uint8_t* nverts, void* stream);
+
+/* Copy the candidate list (n_cand entries, sorted by (s, m)) and each
+ * candidate's clip vertex count (0 when it is not a pair).  NULL skips. */
+int mt_get_candidates(mt_ctx* ctx, int32_t* slave_el, int32_t* master_el, uint8_t* nverts,
+                      void* stream);
+
+/* Sparsity of D (slave nodes x slave nodes) and M (slave nodes x master
+ * nodes): the union of the 4x4 nodal blocks of all pairs (D: of every slave
+ * element with at least one pair), columns sorted ascending, structural
+ * zeros kept (the assembly of eq. (DiscreteWeakFormInterfaceFlux)).  Writes
+ * nnz counts (host).  Synchronises `stream`.  Errors: MT_ESTATE. */
+int mt_csr_pattern(mt_ctx* ctx, int64_t* nnz_D, int64_t* nnz_M, void* stream);
+
+/* Copy the CSR arrays: D_rowptr[n_s_nodes+1], D_col[nnz_D],
+ * M_rowptr[n_s_nodes+1], M_col[nnz_M].  NULL skips.  Errors: MT_ESTATE. */
+int mt_get_csr(mt_ctx* ctx, int32_t* D_rowptr, int32_t* D_col, int32_t* M_rowptr, int32_t* M_col,
+               void* stream);
+
+/* Segment-based integration (Alg. 1, triangulation and quadrature steps)
+ * and assembly: for every pair, the clip polygon is split into a fan of
+ * triangles from its vertex 0 and integrated with the triangle rule; local
+ * blocks D_e[j][k] = int Phi_j N_k, M_e[j][l] = int Phi_j (N_l o chi),
+ * g_e[j] = int Phi_j (h_master - h_slave) (heights along n0) are summed into
+ * D_val[nnz_D], M_val[nnz_M] (CSR order of mt_csr_pattern) and gap[n_s_nodes]
+ * (zero where no pair touches a node).  Output arrays are overwritten.
+ * Does not synchronise; quadrature points whose inverse map did not converge
+ * are counted in mt_stats.n_noconv.  Errors: MT_ESTATE (no pattern),
+ * MT_EINVAL (null outputs). */
+int mt_integrate(mt_ctx* ctx, double* D_val, double* M_val, double* gap, void* stream);
+
+/* Gradient of L = <W_D, D_val> + <W_M, M_val> + <w_g, gap> with respect to
+ * the slave and master nodal coordinates, on the current pair list and
+ * pattern (the pair list is held fixed).  W_D[nnz_D], W_M[nnz_M],
+ * w_g[n_s_nodes] in; gXs[3 * n_s_nodes], gXm[3 * n_m_nodes] out, laid out
+ * structure-of-arrays (x block, then y, then z), overwritten.  The clip
+ * geometry is recomputed, then differentiated in reverse mode; the inverse
+ * maps use the implicit-function derivative.  Errors: MT_ESTATE,
+ * MT_EINVAL, MT_EUNSUPPORTED (dual basis). */
+int mt_backward(mt_ctx* ctx, const double* W_D, const double* W_M, const double* w_g,
+                double* gXs, double* gXm, void* stream);
+
+/* Copy the counters of the last calls into *st (host).  Synchronises the
+ * stream of the last call. */
+int mt_get_stats(mt_ctx* ctx, mt_stats* st);
+
+/* Message of the calling thread's last error ("" if none).  Host string
+ * owned by the library, valid until the next call on this thread. */
+const char* mt_last_error(void);
+
+/* ---- batched evaluation of many independent interfaces ------------------
+ * A batch holds references to K contexts (one interface each), all on one
+ * device, each already through mt_build_pairs and mt_csr_pattern.
+ * mt_batch_build concatenates their pair lists into one work queue of
+ * (instance, pair bucket) items balanced over the GPU (the single-GPU
+ * analogue of the paper's interface load balancing, Sec. "Interface domain
+ * decompositions for dynamically evolving interfaces"); mt_batch_forward /
+ * mt_batch_backward run every instance with one persistent launch per
+ * phase, optionally captured once into a HIP graph and replayed. */
+typedef struct mt_batch mt_batch;
+
+/* Tuning knobs of the persistent launch; 0 = autotuned value. */
+typedef struct mt_batch_tuning {
+  int32_t bucket;         /* pairs per work item */
+  int32_t block;          /* threads per block (multiple of 64) */
+  int32_t blocks_per_cu;  /* persistent blocks per compute unit */
+  int32_t reserved;
+} mt_batch_tuning;
+
+int mt_batch_create(mt_batch** b, int device);
+int mt_batch_destroy(mt_batch* b);
+/* Add a context; returns its instance index in *index (host).  The context
+ * must outlive the batch.  Errors: MT_EINVAL (other device), MT_ESTATE. */
+int mt_batch_add(mt_batch* b, mt_ctx* ctx, int32_t* index);
+/* Build the work queue and per-instance tables.  `tuning` may be NULL.  Synchronises. */
+int mt_batch_build(mt_batch* b, const mt_batch_tuning* tuning, void* stream);
+/* Forward for every instance: D_val[i], M_val[i], gap[i] are host arrays of
+ * K device pointers (outputs as for mt_integrate).  use_graph != 0 captures
+ * the launch sequence into a HIP graph on first use and replays it while the
+ * output pointers are unchanged. */
+int mt_batch_forward(mt_batch* b, double* const* D_val, double* const* M_val, double* const* gap,
+                     int use_graph, void* stream);
+/* Backward for every instance (arguments as for mt_backward, per instance). */
+int mt_batch_backward(mt_batch* b, const double* const* W_D, const double* const* W_M,
+                      const double* const* w_g, double* const* gXs, double* const* gXm,
+                      int use_graph, void* stream);
+/* Autotune the tuning knobs on the current instances by timing candidate
+ * settings of the forward launch; writes the choice to *out (host) and uses
+ * it from then on.  Values are unchanged by tuning (bitwise). */
+int mt_batch_autotune(mt_batch* b, mt_batch_tuning* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MORTAR_MI355X_H */

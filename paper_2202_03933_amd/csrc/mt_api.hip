@@ -1,0 +1,505 @@
+// Host side of the C ABI declared in mortar_mi355x.h: context, argument
+// checks, device buffers and the launch sequence of each entry point.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "mt_internal.h"
+
+namespace mt {
+
+namespace {
+thread_local std::string g_err;
+
+// Makes the context's device current for the duration of a call.
+struct DeviceScope {
+  int prev = -1;
+  hipError_t err = hipSuccess;
+  explicit DeviceScope(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    err = hipSetDevice(dev);
+  }
+  ~DeviceScope() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  g_err = std::string(where) + ": " + hipGetErrorString(e);
+  return MT_EHIP;
+}
+
+#define MT_HIP(call)                                   \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return hip_fail(e_, #call);  \
+  } while (0)
+
+int bits_for(int64_t n) {
+  int b = 1;
+  while ((int64_t(1) << b) < n) ++b;
+  return b;
+}
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+hipError_t ensure(Buf& b, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  if (bytes <= b.bytes) return hipSuccess;
+  if (b.p) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return e;
+    e = hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+    if (e != hipSuccess) return e;
+  }
+  const size_t want = bytes + bytes / 4;
+  hipError_t e = hipMalloc(&b.p, want);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    return e;
+  }
+  b.bytes = want;
+  return hipSuccess;
+}
+
+void release(Buf& b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+KParams kparams(const mt_params& p) {
+  KParams k{};
+  k.delta = p.delta;
+  k.eps_d = p.eps_d;
+  k.eps_a = p.eps_a;
+  k.newton_tol = p.newton_tol;
+  k.newton_maxit = p.newton_maxit;
+  k.dual = p.lm_basis == MT_BASIS_DUAL ? 1 : 0;
+  k.rule = p.rule;
+  return k;
+}
+
+}  // namespace mt
+
+using namespace mt;
+
+extern "C" {
+
+const char* mt_last_error(void) { return mt::g_err.c_str(); }
+
+int mt_default_params(mt_params* p) {
+  if (!p) return fail(MT_EINVAL, "mt_default_params: null");
+  std::memset(p, 0, sizeof(*p));
+  p->delta = 0.0;
+  p->bin_size = 0.0;
+  p->lm_basis = MT_BASIS_STANDARD;
+  p->rule = 7;
+  p->eps_d = 1e-12;
+  p->eps_a = 1e-12;
+  p->newton_tol = 1e-14;
+  p->newton_maxit = 30;
+  return MT_OK;
+}
+
+int mt_create(mt_ctx** ctx, int device) {
+  if (!ctx) return fail(MT_EINVAL, "mt_create: null ctx");
+  *ctx = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+  if (device < 0 || device >= n) return fail(MT_EINVAL, "mt_create: no such device");
+  mt_ctx* c = new mt_ctx();
+  c->device = device;
+  mt_default_params(&c->params);
+  *ctx = c;
+  return MT_OK;
+}
+
+int mt_destroy(mt_ctx* c) {
+  if (!c) return MT_OK;
+  DeviceScope ds(c->device);
+  (void)hipDeviceSynchronize();
+  Buf* bufs[] = {&c->box_s, &c->box_m, &c->reduce, &c->counters, &c->keys, &c->vals,
+                 &c->keys_tmp, &c->vals_tmp, &c->cell_start, &c->cell_end, &c->cand_cnt, &c->cand_off,
+                 &c->cand_s, &c->cand_m, &c->cand_nv, &c->cand_flag, &c->cand_scan, &c->pair_s, &c->pair_m,
+                 &c->pair_nv, &c->pair_off, &c->inc_cnt, &c->inc_off, &c->inc_cur, &c->inc_list, &c->minc_cnt,
+                 &c->minc_off, &c->minc_cur, &c->minc_list, &c->rawD_cnt, &c->rawD_off, &c->rawD, &c->rawM_cnt,
+                 &c->rawM_off, &c->rawM, &c->D_cnt, &c->D_rowptr, &c->D_col, &c->M_cnt, &c->M_rowptr,
+                 &c->M_col, &c->posD, &c->posM, &c->blk, &c->gpair, &c->mp_keys, &c->mp_vals, &c->mp_off,
+                 &c->scan_tmp, &c->sort_hist, &c->host_tmp};
+  for (Buf* b : bufs) release(*b);
+  delete c;
+  return MT_OK;
+}
+
+int mt_set_params(mt_ctx* c, const mt_params* p) {
+  if (!c || !p) return fail(MT_EINVAL, "mt_set_params: null");
+  if (p->rule != 3 && p->rule != 7) return fail(MT_EINVAL, "mt_set_params: rule must be 3 or 7");
+  if (p->lm_basis != MT_BASIS_STANDARD && p->lm_basis != MT_BASIS_DUAL)
+    return fail(MT_EINVAL, "mt_set_params: lm_basis");
+  if (!(p->delta >= 0) || !(p->bin_size >= 0) || !(p->eps_d >= 0) || !(p->eps_a >= 0) || !(p->newton_tol > 0) ||
+      p->newton_maxit < 1)
+    return fail(MT_EINVAL, "mt_set_params: negative or invalid tolerance");
+  c->params = *p;
+  c->have_pairs = c->have_pattern = c->have_master_index = false;
+  return MT_OK;
+}
+
+int mt_upload(mt_ctx* c, int side, int64_t n_nodes, const double* x, const double* y, const double* z, int64_t n_el,
+              const int32_t* conn, void* stream) {
+  (void)stream;
+  if (!c) return fail(MT_EINVAL, "mt_upload: null ctx");
+  if (side != MT_SIDE_SLAVE && side != MT_SIDE_MASTER) return fail(MT_EINVAL, "mt_upload: bad side");
+  if (n_nodes < 0 || n_el < 0 || n_nodes >= (int64_t(1) << 31) || n_el >= (int64_t(1) << 29))
+    return fail(MT_EINVAL, "mt_upload: size out of range");
+  if ((n_nodes > 0 && (!x || !y || !z)) || (n_el > 0 && !conn)) return fail(MT_EINVAL, "mt_upload: null array");
+  if (n_el > 0 && (reinterpret_cast<uintptr_t>(conn) & 15))
+    return fail(MT_EINVAL, "mt_upload: connectivity must be 16-byte aligned");
+  DeviceMesh& m = c->side[side];
+  m.x = x; m.y = y; m.z = z; m.conn = conn;
+  m.n_nodes = (int32_t)n_nodes;
+  m.n_el = (int32_t)n_el;
+  m.set = true;
+  c->have_pairs = c->have_pattern = c->have_master_index = false;
+  return MT_OK;
+}
+
+int mt_update_coordinates(mt_ctx* c, int side, const double* x, const double* y, const double* z, void* stream) {
+  (void)stream;
+  if (!c) return fail(MT_EINVAL, "mt_update_coordinates: null ctx");
+  if (side != MT_SIDE_SLAVE && side != MT_SIDE_MASTER) return fail(MT_EINVAL, "mt_update_coordinates: bad side");
+  DeviceMesh& m = c->side[side];
+  if (!m.set) return fail(MT_ESTATE, "mt_update_coordinates: side not uploaded");
+  if (m.n_nodes > 0 && (!x || !y || !z)) return fail(MT_EINVAL, "mt_update_coordinates: null array");
+  m.x = x; m.y = y; m.z = z;
+  return MT_OK;
+}
+
+int mt_build_pairs(mt_ctx* c, int64_t* n_cand_out, int64_t* n_pairs_out, void* stream) {
+  if (!c) return fail(MT_EINVAL, "mt_build_pairs: null ctx");
+  if (!c->side[0].set || !c->side[1].set) return fail(MT_ESTATE, "mt_build_pairs: upload both sides first");
+  DeviceScope ds(c->device);
+  if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  c->last_stream = st;
+  c->have_pairs = c->have_pattern = c->have_master_index = false;
+  const DeviceMesh& S = c->side[0];
+  const DeviceMesh& M = c->side[1];
+  const int32_t ns = S.n_el, nm = M.n_el;
+
+  MT_HIP(ensure(c->reduce, sizeof(PrepReduce)));
+  MT_HIP(ensure(c->counters, sizeof(Counters)));
+  MT_HIP(ensure(c->host_tmp, 64));
+  MT_HIP(ensure(c->box_s, sizeof(double) * 6 * (size_t)ns));
+  MT_HIP(ensure(c->box_m, sizeof(double) * 6 * (size_t)nm));
+  PrepReduce* red = c->reduce.as<PrepReduce>();
+  MT_HIP(launch_init_reduce(red, st));
+  MT_HIP(hipMemsetAsync(c->counters.p, 0, sizeof(Counters), st));
+  MT_HIP(launch_prep(S, true, c->box_s.as<double>(), red, st));
+  MT_HIP(launch_prep(M, false, c->box_m.as<double>(), red, st));
+  PrepReduce hr;
+  MT_HIP(hipMemcpyAsync(&hr, red, sizeof(hr), hipMemcpyDeviceToHost, st));
+  MT_HIP(hipStreamSynchronize(st));
+  if (hr.bad_index) return fail(MT_EINVAL, "mt_build_pairs: connectivity index out of range");
+  grid_from_reduce(hr, c->params.delta, c->params.bin_size, c->grid);
+  const Grid& g = c->grid;
+
+  // master elements sorted by cell, cell ranges from segment heads
+  MT_HIP(ensure(c->keys, sizeof(uint32_t) * (size_t)nm));
+  MT_HIP(ensure(c->vals, sizeof(uint32_t) * (size_t)nm));
+  MT_HIP(ensure(c->keys_tmp, sizeof(uint32_t) * (size_t)nm));
+  MT_HIP(ensure(c->vals_tmp, sizeof(uint32_t) * (size_t)nm));
+  MT_HIP(launch_master_keys(c->box_m.as<double>(), nm, g, c->keys.as<uint32_t>(), c->vals.as<uint32_t>(), st));
+  MT_HIP(radix_sort_pairs(c->keys.as<uint32_t>(), c->vals.as<uint32_t>(), c->keys_tmp.as<uint32_t>(),
+                          c->vals_tmp.as<uint32_t>(), nm, bits_for(g.ncells), c->sort_hist, c->scan_tmp, st));
+  MT_HIP(ensure(c->cell_start, sizeof(int32_t) * (size_t)g.ncells));
+  MT_HIP(ensure(c->cell_end, sizeof(int32_t) * (size_t)g.ncells));
+  MT_HIP(hipMemsetAsync(c->cell_start.p, 0, sizeof(int32_t) * (size_t)g.ncells, st));
+  MT_HIP(hipMemsetAsync(c->cell_end.p, 0, sizeof(int32_t) * (size_t)g.ncells, st));
+  MT_HIP(launch_cell_ranges(c->keys.as<uint32_t>(), nm, c->cell_start.as<int32_t>(), c->cell_end.as<int32_t>(), st));
+
+  // candidates: count, scan, fill (sorted by master within each slave)
+  MT_HIP(ensure(c->cand_cnt, sizeof(int32_t) * ((size_t)ns + 1)));
+  MT_HIP(ensure(c->cand_off, sizeof(int32_t) * ((size_t)ns + 1)));
+  MT_HIP(launch_cand_count(c->box_s.as<double>(), ns, c->box_m.as<double>(), nm, c->vals.as<uint32_t>(),
+                           c->cell_start.as<int32_t>(), c->cell_end.as<int32_t>(), g, c->params.delta,
+                           c->cand_cnt.as<int32_t>(), st));
+  MT_HIP(scan_exclusive(c->cand_cnt.as<int32_t>(), c->cand_off.as<int32_t>(), ns, c->scan_tmp, st));
+  int32_t ncand32 = 0;
+  MT_HIP(hipMemcpyAsync(&ncand32, c->cand_off.as<int32_t>() + ns, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  MT_HIP(hipStreamSynchronize(st));
+  const int64_t n_cand = ncand32;
+  if (n_cand < 0) return fail(MT_ECAPACITY, "mt_build_pairs: more than 2^31 candidates");
+  MT_HIP(ensure(c->cand_s, sizeof(int32_t) * (size_t)n_cand));
+  MT_HIP(ensure(c->cand_m, sizeof(int32_t) * (size_t)n_cand));
+  MT_HIP(ensure(c->cand_nv, (size_t)n_cand));
+  MT_HIP(ensure(c->cand_flag, sizeof(int32_t) * ((size_t)n_cand + 1)));
+  MT_HIP(ensure(c->cand_scan, sizeof(int32_t) * ((size_t)n_cand + 1)));
+  MT_HIP(launch_cand_fill(c->box_s.as<double>(), ns, c->box_m.as<double>(), nm, c->vals.as<uint32_t>(),
+                          c->cell_start.as<int32_t>(), c->cell_end.as<int32_t>(), g, c->params.delta,
+                          c->cand_off.as<int32_t>(), c->cand_s.as<int32_t>(), c->cand_m.as<int32_t>(), st));
+
+  // clip every candidate; compact the pairs
+  const KParams kp = kparams(c->params);
+  Counters* cnt = c->counters.as<Counters>();
+  MT_HIP(launch_clip_count(S, M, kp, c->cand_s.as<int32_t>(), c->cand_m.as<int32_t>(), n_cand,
+                           c->cand_nv.as<uint8_t>(), c->cand_flag.as<int32_t>(), cnt, st));
+  MT_HIP(scan_exclusive(c->cand_flag.as<int32_t>(), c->cand_scan.as<int32_t>(), n_cand, c->scan_tmp, st));
+  int32_t np32 = 0;
+  Counters hc;
+  MT_HIP(hipMemcpyAsync(&np32, c->cand_scan.as<int32_t>() + n_cand, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  MT_HIP(hipMemcpyAsync(&hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, st));
+  MT_HIP(hipStreamSynchronize(st));
+  const int64_t n_pairs = np32;
+  MT_HIP(ensure(c->pair_s, sizeof(int32_t) * (size_t)n_pairs));
+  MT_HIP(ensure(c->pair_m, sizeof(int32_t) * (size_t)n_pairs));
+  MT_HIP(ensure(c->pair_nv, (size_t)n_pairs));
+  MT_HIP(ensure(c->pair_off, sizeof(int32_t) * ((size_t)ns + 1)));
+  MT_HIP(launch_compact(c->cand_s.as<int32_t>(), c->cand_m.as<int32_t>(), c->cand_nv.as<uint8_t>(),
+                        c->cand_scan.as<int32_t>(), n_cand, c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(),
+                        c->pair_nv.as<uint8_t>(), st));
+  MT_HIP(launch_pair_off(c->cand_off.as<int32_t>(), c->cand_scan.as<int32_t>(), ns, c->pair_off.as<int32_t>(), st));
+  c->n_cand = n_cand;
+  c->n_pairs = n_pairs;
+  c->have_pairs = true;
+  if (n_cand_out) *n_cand_out = n_cand;
+  if (n_pairs_out) *n_pairs_out = n_pairs;
+  if (hc.degen_slave || hc.overflow)
+    return fail(MT_EDEGENERATE, "mt_build_pairs: degenerate slave element or clip capacity exceeded");
+  return MT_OK;
+}
+
+int mt_get_pairs(mt_ctx* c, int32_t* s, int32_t* m, uint8_t* nv, void* stream) {
+  if (!c) return fail(MT_EINVAL, "mt_get_pairs: null ctx");
+  if (!c->have_pairs) return fail(MT_ESTATE, "mt_get_pairs: no pair list");
+  DeviceScope ds(c->device);
+  hipStream_t st = (hipStream_t)stream;
+  const size_t n = (size_t)c->n_pairs;
+  if (n == 0) return MT_OK;
+  if (s) MT_HIP(hipMemcpyAsync(s, c->pair_s.p, 4 * n, hipMemcpyDeviceToDevice, st));
+  if (m) MT_HIP(hipMemcpyAsync(m, c->pair_m.p, 4 * n, hipMemcpyDeviceToDevice, st));
+  if (nv) MT_HIP(hipMemcpyAsync(nv, c->pair_nv.p, n, hipMemcpyDeviceToDevice, st));
+  return MT_OK;
+}
+
+int mt_get_candidates(mt_ctx* c, int32_t* s, int32_t* m, uint8_t* nv, void* stream) {
+  if (!c) return fail(MT_EINVAL, "mt_get_candidates: null ctx");
+  if (!c->have_pairs) return fail(MT_ESTATE, "mt_get_candidates: no candidate list");
+  DeviceScope ds(c->device);
+  hipStream_t st = (hipStream_t)stream;
+  const size_t n = (size_t)c->n_cand;
+  if (n == 0) return MT_OK;
+  if (s) MT_HIP(hipMemcpyAsync(s, c->cand_s.p, 4 * n, hipMemcpyDeviceToDevice, st));
+  if (m) MT_HIP(hipMemcpyAsync(m, c->cand_m.p, 4 * n, hipMemcpyDeviceToDevice, st));
+  if (nv) MT_HIP(hipMemcpyAsync(nv, c->cand_nv.p, n, hipMemcpyDeviceToDevice, st));
+  return MT_OK;
+}
+
+// Node -> (element * 4 + local index) incidence, sorted per node.
+static int build_incidence(mt_ctx* c, const DeviceMesh& mesh, Buf& cntb, Buf& offb, Buf& curb, Buf& listb,
+                           hipStream_t st) {
+  const int32_t n = mesh.n_nodes;
+  MT_HIP(ensure(cntb, sizeof(int32_t) * ((size_t)n + 1)));
+  MT_HIP(ensure(offb, sizeof(int32_t) * ((size_t)n + 1)));
+  MT_HIP(ensure(curb, sizeof(int32_t) * ((size_t)n + 1)));
+  MT_HIP(ensure(listb, sizeof(int32_t) * 4 * (size_t)mesh.n_el));
+  MT_HIP(hipMemsetAsync(cntb.p, 0, sizeof(int32_t) * ((size_t)n + 1), st));
+  MT_HIP(hipMemsetAsync(curb.p, 0, sizeof(int32_t) * ((size_t)n + 1), st));
+  MT_HIP(launch_inc_count(mesh.conn, mesh.n_el, cntb.as<int32_t>(), st));
+  MT_HIP(scan_exclusive(cntb.as<int32_t>(), offb.as<int32_t>(), n, c->scan_tmp, st));
+  MT_HIP(launch_inc_fill(mesh.conn, mesh.n_el, offb.as<int32_t>(), curb.as<int32_t>(), listb.as<int32_t>(), st));
+  MT_HIP(launch_inc_sort(offb.as<int32_t>(), n, listb.as<int32_t>(), st));
+  return MT_OK;
+}
+
+int mt_csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, void* stream) {
+  if (!c) return fail(MT_EINVAL, "mt_csr_pattern: null ctx");
+  if (!c->have_pairs) return fail(MT_ESTATE, "mt_csr_pattern: build the pair list first");
+  DeviceScope ds(c->device);
+  hipStream_t st = (hipStream_t)stream;
+  c->last_stream = st;
+  const DeviceMesh& S = c->side[0];
+  const DeviceMesh& M = c->side[1];
+  const int32_t n = S.n_nodes;
+  int rc = build_incidence(c, S, c->inc_cnt, c->inc_off, c->inc_cur, c->inc_list, st);
+  if (rc) return rc;
+  MT_HIP(ensure(c->rawD_cnt, sizeof(int32_t) * ((size_t)n + 1)));
+  MT_HIP(ensure(c->rawM_cnt, sizeof(int32_t) * ((size_t)n + 1)));
+  MT_HIP(ensure(c->rawD_off, sizeof(int32_t) * ((size_t)n + 1)));
+  MT_HIP(ensure(c->rawM_off, sizeof(int32_t) * ((size_t)n + 1)));
+  MT_HIP(launch_raw_count(c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(), n, c->pair_off.as<int32_t>(),
+                          c->rawD_cnt.as<int32_t>(), c->rawM_cnt.as<int32_t>(), st));
+  MT_HIP(scan_exclusive(c->rawD_cnt.as<int32_t>(), c->rawD_off.as<int32_t>(), n, c->scan_tmp, st));
+  MT_HIP(scan_exclusive(c->rawM_cnt.as<int32_t>(), c->rawM_off.as<int32_t>(), n, c->scan_tmp, st));
+  int32_t tot[2] = {0, 0};
+  MT_HIP(hipMemcpyAsync(&tot[0], c->rawD_off.as<int32_t>() + n, 4, hipMemcpyDeviceToHost, st));
+  MT_HIP(hipMemcpyAsync(&tot[1], c->rawM_off.as<int32_t>() + n, 4, hipMemcpyDeviceToHost, st));
+  MT_HIP(hipStreamSynchronize(st));
+  if (tot[0] < 0 || tot[1] < 0) return fail(MT_ECAPACITY, "mt_csr_pattern: more than 2^31 block entries");
+  MT_HIP(ensure(c->rawD, sizeof(int32_t) * (size_t)tot[0]));
+  MT_HIP(ensure(c->rawM, sizeof(int32_t) * (size_t)tot[1]));
+  MT_HIP(ensure(c->D_cnt, sizeof(int32_t) * ((size_t)n + 1)));
+  MT_HIP(ensure(c->M_cnt, sizeof(int32_t) * ((size_t)n + 1)));
+  MT_HIP(ensure(c->D_rowptr, sizeof(int32_t) * ((size_t)n + 1)));
+  MT_HIP(ensure(c->M_rowptr, sizeof(int32_t) * ((size_t)n + 1)));
+  MT_HIP(launch_raw_fill(c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(), n, c->pair_off.as<int32_t>(),
+                         c->pair_m.as<int32_t>(), S.conn, M.conn, c->rawD_off.as<int32_t>(), c->rawD.as<int32_t>(),
+                         c->rawM_off.as<int32_t>(), c->rawM.as<int32_t>(), c->D_cnt.as<int32_t>(),
+                         c->M_cnt.as<int32_t>(), st));
+  MT_HIP(scan_exclusive(c->D_cnt.as<int32_t>(), c->D_rowptr.as<int32_t>(), n, c->scan_tmp, st));
+  MT_HIP(scan_exclusive(c->M_cnt.as<int32_t>(), c->M_rowptr.as<int32_t>(), n, c->scan_tmp, st));
+  MT_HIP(hipMemcpyAsync(&tot[0], c->D_rowptr.as<int32_t>() + n, 4, hipMemcpyDeviceToHost, st));
+  MT_HIP(hipMemcpyAsync(&tot[1], c->M_rowptr.as<int32_t>() + n, 4, hipMemcpyDeviceToHost, st));
+  MT_HIP(hipStreamSynchronize(st));
+  c->nnz_D = tot[0];
+  c->nnz_M = tot[1];
+  MT_HIP(ensure(c->D_col, sizeof(int32_t) * (size_t)c->nnz_D));
+  MT_HIP(ensure(c->M_col, sizeof(int32_t) * (size_t)c->nnz_M));
+  MT_HIP(launch_csr_cols(c->rawD_off.as<int32_t>(), c->rawD.as<int32_t>(), c->D_rowptr.as<int32_t>(), n,
+                         c->D_col.as<int32_t>(), st));
+  MT_HIP(launch_csr_cols(c->rawM_off.as<int32_t>(), c->rawM.as<int32_t>(), c->M_rowptr.as<int32_t>(), n,
+                         c->M_col.as<int32_t>(), st));
+  MT_HIP(ensure(c->posD, sizeof(int32_t) * 16 * (size_t)S.n_el));
+  MT_HIP(ensure(c->posM, sizeof(int32_t) * 16 * (size_t)c->n_pairs));
+  MT_HIP(launch_posD(S.conn, S.n_el, c->pair_off.as<int32_t>(), c->D_rowptr.as<int32_t>(), c->D_col.as<int32_t>(),
+                     c->posD.as<int32_t>(), st));
+  MT_HIP(launch_posM(S.conn, M.conn, c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), c->n_pairs,
+                     c->M_rowptr.as<int32_t>(), c->M_col.as<int32_t>(), c->posM.as<int32_t>(), st));
+  c->have_pattern = true;
+  c->have_master_index = false;
+  if (nnz_D) *nnz_D = c->nnz_D;
+  if (nnz_M) *nnz_M = c->nnz_M;
+  return MT_OK;
+}
+
+int mt_get_csr(mt_ctx* c, int32_t* D_rowptr, int32_t* D_col, int32_t* M_rowptr, int32_t* M_col, void* stream) {
+  if (!c) return fail(MT_EINVAL, "mt_get_csr: null ctx");
+  if (!c->have_pattern) return fail(MT_ESTATE, "mt_get_csr: no pattern");
+  DeviceScope ds(c->device);
+  hipStream_t st = (hipStream_t)stream;
+  const size_t nr = (size_t)c->side[0].n_nodes + 1;
+  if (D_rowptr) MT_HIP(hipMemcpyAsync(D_rowptr, c->D_rowptr.p, 4 * nr, hipMemcpyDeviceToDevice, st));
+  if (M_rowptr) MT_HIP(hipMemcpyAsync(M_rowptr, c->M_rowptr.p, 4 * nr, hipMemcpyDeviceToDevice, st));
+  if (D_col && c->nnz_D) MT_HIP(hipMemcpyAsync(D_col, c->D_col.p, 4 * (size_t)c->nnz_D, hipMemcpyDeviceToDevice, st));
+  if (M_col && c->nnz_M) MT_HIP(hipMemcpyAsync(M_col, c->M_col.p, 4 * (size_t)c->nnz_M, hipMemcpyDeviceToDevice, st));
+  return MT_OK;
+}
+
+int mt_integrate(mt_ctx* c, double* D_val, double* M_val, double* gap, void* stream) {
+  if (!c) return fail(MT_EINVAL, "mt_integrate: null ctx");
+  if (!c->have_pattern) return fail(MT_ESTATE, "mt_integrate: build pairs and pattern first");
+  if ((c->nnz_D && !D_val) || (c->nnz_M && !M_val) || (c->side[0].n_nodes && !gap))
+    return fail(MT_EINVAL, "mt_integrate: null output");
+  DeviceScope ds(c->device);
+  hipStream_t st = (hipStream_t)stream;
+  c->last_stream = st;
+  const DeviceMesh& S = c->side[0];
+  const DeviceMesh& M = c->side[1];
+  const int64_t np = c->n_pairs;
+  MT_HIP(ensure(c->blk, sizeof(double) * 36 * (size_t)std::max<int64_t>(np, 1)));
+  MT_HIP(launch_pair_fwd(S, M, kparams(c->params),
+                         c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), np, c->blk.as<double>(), np,
+                         c->counters.as<Counters>(), st));
+  MT_HIP(launch_assemble(c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(), S.n_nodes, c->pair_off.as<int32_t>(),
+                         c->D_rowptr.as<int32_t>(), c->M_rowptr.as<int32_t>(), c->posD.as<int32_t>(), S.n_el,
+                         c->posM.as<int32_t>(), c->blk.as<double>(), np, D_val, M_val, gap, st));
+  return MT_OK;
+}
+
+namespace {
+__global__ void k_iota(uint32_t* v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = (uint32_t)i;
+}
+}  // namespace
+
+static int build_master_index(mt_ctx* c, hipStream_t st) {
+  const DeviceMesh& M = c->side[1];
+  int rc = build_incidence(c, M, c->minc_cnt, c->minc_off, c->minc_cur, c->minc_list, st);
+  if (rc) return rc;
+  const int64_t np = c->n_pairs;
+  MT_HIP(ensure(c->mp_keys, sizeof(uint32_t) * (size_t)np));
+  MT_HIP(ensure(c->mp_vals, sizeof(uint32_t) * (size_t)np));
+  MT_HIP(ensure(c->keys_tmp, sizeof(uint32_t) * (size_t)np));
+  MT_HIP(ensure(c->vals_tmp, sizeof(uint32_t) * (size_t)np));
+  MT_HIP(ensure(c->mp_off, sizeof(int32_t) * 2 * ((size_t)M.n_el + 1)));
+  if (np > 0) {
+    MT_HIP(hipMemcpyAsync(c->mp_keys.p, c->pair_m.p, 4 * (size_t)np, hipMemcpyDeviceToDevice, st));
+    k_iota<<<(unsigned)((np + 255) / 256), 256, 0, st>>>(c->mp_vals.as<uint32_t>(), np);
+    MT_HIP(hipGetLastError());
+  }
+  MT_HIP(radix_sort_pairs(c->mp_keys.as<uint32_t>(), c->mp_vals.as<uint32_t>(), c->keys_tmp.as<uint32_t>(),
+                          c->vals_tmp.as<uint32_t>(), np, bits_for(std::max<int32_t>(M.n_el, 2)), c->sort_hist,
+                          c->scan_tmp, st));
+  MT_HIP(hipMemsetAsync(c->mp_off.p, 0, sizeof(int32_t) * 2 * ((size_t)M.n_el + 1), st));
+  MT_HIP(launch_mpair_off(c->mp_keys.as<uint32_t>(), np, M.n_el, c->mp_off.as<int32_t>(), st));
+  c->have_master_index = true;
+  return MT_OK;
+}
+
+int mt_backward(mt_ctx* c, const double* W_D, const double* W_M, const double* w_g, double* gXs, double* gXm,
+                void* stream) {
+  if (!c) return fail(MT_EINVAL, "mt_backward: null ctx");
+  if (c->params.lm_basis == MT_BASIS_DUAL)
+    return fail(MT_EUNSUPPORTED, "mt_backward: the dual basis has no backward pass");
+  if (!c->have_pattern) return fail(MT_ESTATE, "mt_backward: build pairs and pattern first");
+  const DeviceMesh& S = c->side[0];
+  const DeviceMesh& M = c->side[1];
+  if ((c->nnz_D && !W_D) || (c->nnz_M && !W_M) || (S.n_nodes && (!w_g || !gXs)) || (M.n_nodes && !gXm))
+    return fail(MT_EINVAL, "mt_backward: null argument");
+  DeviceScope ds(c->device);
+  hipStream_t st = (hipStream_t)stream;
+  c->last_stream = st;
+  if (!c->have_master_index) {
+    int rc = build_master_index(c, st);
+    if (rc) return rc;
+  }
+  const int64_t np = c->n_pairs;
+  MT_HIP(ensure(c->gpair, sizeof(double) * 24 * (size_t)std::max<int64_t>(np, 1)));
+  MT_HIP(launch_pair_bwd(S, M, kparams(c->params), c->pair_s.as<int32_t>(),
+                         c->pair_m.as<int32_t>(), np, c->posD.as<int32_t>(), S.n_el, c->posM.as<int32_t>(), W_D, W_M,
+                         w_g, c->gpair.as<double>(), np, c->counters.as<Counters>(), st));
+  MT_HIP(launch_grad_slave(c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(), S.n_nodes, c->pair_off.as<int32_t>(),
+                           c->gpair.as<double>(), np, gXs, st));
+  const int32_t* mo = c->mp_off.as<int32_t>();
+  MT_HIP(launch_grad_master(c->minc_off.as<int32_t>(), c->minc_list.as<int32_t>(), M.n_nodes, mo, mo + M.n_el,
+                            c->mp_vals.as<uint32_t>(), c->gpair.as<double>(), np, gXm, st));
+  return MT_OK;
+}
+
+int mt_get_stats(mt_ctx* c, mt_stats* out) {
+  if (!c || !out) return fail(MT_EINVAL, "mt_get_stats: null");
+  std::memset(out, 0, sizeof(*out));
+  out->n_candidates = c->n_cand;
+  out->n_pairs = c->n_pairs;
+  out->nnz_D = c->nnz_D;
+  out->nnz_M = c->nnz_M;
+  for (int d = 0; d < 3; ++d) {
+    out->n_bins[d] = c->grid.n[d];
+    out->bin_size[d] = c->grid.beta[d];
+  }
+  if (!c->counters.p) return MT_OK;
+  DeviceScope ds(c->device);
+  Counters hc;
+  MT_HIP(hipMemcpyAsync(&hc, c->counters.p, sizeof(hc), hipMemcpyDeviceToHost, c->last_stream));
+  MT_HIP(hipStreamSynchronize(c->last_stream));
+  for (int i = 0; i < 17; ++i) out->nverts_hist[i] = (int64_t)hc.hist[i];
+  out->n_noconv = (int64_t)hc.noconv;
+  out->n_overflow = (int64_t)hc.overflow;
+  out->n_degenerate_slave = (int64_t)hc.degen_slave;
+  out->n_degenerate_master = (int64_t)hc.degen_master;
+  return MT_OK;
+}
+
+}  // extern "C"

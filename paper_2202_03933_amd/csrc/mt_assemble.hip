@@ -1,0 +1,355 @@
+// Deterministic assembly of the mortar operators into CSR (the assembly of
+// the nodal blocks of eq. (DiscreteWeakFormInterfaceFlux)) and of the nodal
+// gradients, with no floating-point atomics: every output row (slave node)
+// or gradient entry (node) is owned by one thread that sums its
+// contributions in a fixed order (incident elements ascending, then pairs in
+// (slave, master) order), so results are bitwise reproducible.
+#include "mt_internal.h"
+
+namespace mt {
+
+namespace {
+
+constexpr int BS = 256;
+
+__global__ __launch_bounds__(BS) void k_inc_count(const int32_t* __restrict__ conn, int32_t n_el, int32_t* cnt) {
+  const int e = blockIdx.x * BS + threadIdx.x;
+  if (e >= n_el) return;
+  const int4 c = reinterpret_cast<const int4*>(conn)[e];
+  atomicAdd(&cnt[c.x], 1);
+  atomicAdd(&cnt[c.y], 1);
+  atomicAdd(&cnt[c.z], 1);
+  atomicAdd(&cnt[c.w], 1);
+}
+
+__global__ __launch_bounds__(BS) void k_inc_fill(const int32_t* __restrict__ conn, int32_t n_el,
+                                                  const int32_t* __restrict__ off, int32_t* cur, int32_t* list) {
+  const int e = blockIdx.x * BS + threadIdx.x;
+  if (e >= n_el) return;
+  const int4 c = reinterpret_cast<const int4*>(conn)[e];
+  const int id[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int k = atomicAdd(&cur[id[j]], 1);
+    list[off[id[j]] + k] = e * 4 + j;
+  }
+}
+
+// Sort each node's incidence list ascending (element, then local index).
+__global__ __launch_bounds__(BS) void k_inc_sort(const int32_t* __restrict__ off, int32_t n, int32_t* list) {
+  const int a = blockIdx.x * BS + threadIdx.x;
+  if (a >= n) return;
+  const int b = off[a], e = off[a + 1];
+  for (int i = b + 1; i < e; ++i) {
+    const int v = list[i];
+    int j = i - 1;
+    while (j >= b && list[j] > v) {
+      list[j + 1] = list[j];
+      --j;
+    }
+    list[j + 1] = v;
+  }
+}
+
+__global__ __launch_bounds__(BS) void k_raw_count(const int32_t* __restrict__ inc_off,
+                                                   const int32_t* __restrict__ inc_list, int32_t n,
+                                                   const int32_t* __restrict__ pair_off, int32_t* rawD_cnt,
+                                                   int32_t* rawM_cnt) {
+  const int a = blockIdx.x * BS + threadIdx.x;
+  if (a >= n) return;
+  int d = 0, m = 0;
+  for (int i = inc_off[a]; i < inc_off[a + 1]; ++i) {
+    const int e = inc_list[i] >> 2;
+    const int np = pair_off[e + 1] - pair_off[e];
+    if (np > 0) {
+      d += 4;
+      m += 4 * np;
+    }
+  }
+  rawD_cnt[a] = d;
+  rawM_cnt[a] = m;
+}
+
+// Sort a segment ascending and drop duplicates; returns the unique count.
+__device__ int sort_unique(int32_t* v, int n) {
+  for (int i = 1; i < n; ++i) {
+    const int x = v[i];
+    int j = i - 1;
+    while (j >= 0 && v[j] > x) {
+      v[j + 1] = v[j];
+      --j;
+    }
+    v[j + 1] = x;
+  }
+  int u = 0;
+  for (int i = 0; i < n; ++i)
+    if (u == 0 || v[u - 1] != v[i]) v[u++] = v[i];
+  return u;
+}
+
+__global__ __launch_bounds__(BS) void k_raw_fill(const int32_t* __restrict__ inc_off,
+                                                  const int32_t* __restrict__ inc_list, int32_t n,
+                                                  const int32_t* __restrict__ pair_off,
+                                                  const int32_t* __restrict__ pair_m,
+                                                  const int32_t* __restrict__ conn_s,
+                                                  const int32_t* __restrict__ conn_m,
+                                                  const int32_t* __restrict__ rawD_off, int32_t* rawD,
+                                                  const int32_t* __restrict__ rawM_off, int32_t* rawM,
+                                                  int32_t* D_cnt, int32_t* M_cnt) {
+  const int a = blockIdx.x * BS + threadIdx.x;
+  if (a >= n) return;
+  int32_t* rd = rawD + rawD_off[a];
+  int32_t* rm = rawM + rawM_off[a];
+  int nd = 0, nm = 0;
+  for (int i = inc_off[a]; i < inc_off[a + 1]; ++i) {
+    const int e = inc_list[i] >> 2;
+    const int p0 = pair_off[e], p1 = pair_off[e + 1];
+    if (p1 == p0) continue;
+    const int4 c = reinterpret_cast<const int4*>(conn_s)[e];
+    rd[nd++] = c.x; rd[nd++] = c.y; rd[nd++] = c.z; rd[nd++] = c.w;
+    for (int p = p0; p < p1; ++p) {
+      const int4 q = reinterpret_cast<const int4*>(conn_m)[pair_m[p]];
+      rm[nm++] = q.x; rm[nm++] = q.y; rm[nm++] = q.z; rm[nm++] = q.w;
+    }
+  }
+  D_cnt[a] = sort_unique(rd, nd);
+  M_cnt[a] = sort_unique(rm, nm);
+}
+
+__global__ __launch_bounds__(BS) void k_csr_cols(const int32_t* __restrict__ raw_off, const int32_t* __restrict__ raw,
+                                                  const int32_t* __restrict__ rowptr, int32_t n, int32_t* col) {
+  const int a = blockIdx.x * BS + threadIdx.x;
+  if (a >= n) return;
+  const int32_t* r = raw + raw_off[a];
+  const int b = rowptr[a], c = rowptr[a + 1] - b;
+  for (int i = 0; i < c; ++i) col[b + i] = r[i];
+}
+
+__device__ __forceinline__ int find_col(const int32_t* __restrict__ col, int lo, int hi, int key) {
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (col[mid] < key) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(BS) void k_posD(const int32_t* __restrict__ conn_s, int32_t n_el,
+                                              const int32_t* __restrict__ pair_off, const int32_t* __restrict__ rowptr,
+                                              const int32_t* __restrict__ col, int32_t* __restrict__ posD) {
+  const int e = blockIdx.x * BS + threadIdx.x;
+  if (e >= n_el) return;
+  const bool has = pair_off[e + 1] > pair_off[e];
+  const int4 c = reinterpret_cast<const int4*>(conn_s)[e];
+  const int id[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      posD[(int64_t)(j * 4 + k) * n_el + e] = has ? find_col(col, rowptr[id[j]], rowptr[id[j] + 1], id[k]) : -1;
+}
+
+__global__ __launch_bounds__(BS) void k_posM(const int32_t* __restrict__ conn_s, const int32_t* __restrict__ conn_m,
+                                              const int32_t* __restrict__ pair_s, const int32_t* __restrict__ pair_m,
+                                              int64_t np, const int32_t* __restrict__ rowptr,
+                                              const int32_t* __restrict__ col, int32_t* __restrict__ posM) {
+  const int64_t p = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (p >= np) return;
+  const int4 c = reinterpret_cast<const int4*>(conn_s)[pair_s[p]];
+  const int4 q = reinterpret_cast<const int4*>(conn_m)[pair_m[p]];
+  const int rs[4] = {c.x, c.y, c.z, c.w};
+  const int cm[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int lo = rowptr[rs[j]], hi = rowptr[rs[j] + 1];
+#pragma unroll
+    for (int l = 0; l < 4; ++l) posM[(int64_t)(j * 4 + l) * np + p] = find_col(col, lo, hi, cm[l]);
+  }
+}
+
+// One thread per slave node (row): zero the row, then add the local blocks of
+// every pair of every incident element in a fixed order.
+__global__ __launch_bounds__(BS) void k_assemble(const int32_t* __restrict__ inc_off,
+                                                  const int32_t* __restrict__ inc_list, int32_t n,
+                                                  const int32_t* __restrict__ pair_off,
+                                                  const int32_t* __restrict__ D_rowptr,
+                                                  const int32_t* __restrict__ M_rowptr,
+                                                  const int32_t* __restrict__ posD, int32_t n_s_el,
+                                                  const int32_t* __restrict__ posM, const double* __restrict__ blk,
+                                                  int64_t stride, double* __restrict__ D_val,
+                                                  double* __restrict__ M_val, double* __restrict__ gap) {
+  const int a = blockIdx.x * BS + threadIdx.x;
+  if (a >= n) return;
+  for (int i = D_rowptr[a]; i < D_rowptr[a + 1]; ++i) D_val[i] = 0.0;
+  for (int i = M_rowptr[a]; i < M_rowptr[a + 1]; ++i) M_val[i] = 0.0;
+  double g = 0.0;
+  for (int i = inc_off[a]; i < inc_off[a + 1]; ++i) {
+    const int e = inc_list[i] >> 2, j = inc_list[i] & 3;
+    const int p0 = pair_off[e], p1 = pair_off[e + 1];
+    if (p0 == p1) continue;
+    int pd[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pd[k] = posD[(int64_t)(j * 4 + k) * n_s_el + e];
+    for (int p = p0; p < p1; ++p) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) D_val[pd[k]] += blk[(int64_t)(j * 4 + k) * stride + p];
+#pragma unroll
+      for (int l = 0; l < 4; ++l)
+        M_val[posM[(int64_t)(j * 4 + l) * stride + p]] += blk[(int64_t)(16 + j * 4 + l) * stride + p];
+      g += blk[(int64_t)(32 + j) * stride + p];
+    }
+  }
+  gap[a] = g;
+}
+
+__global__ __launch_bounds__(BS) void k_grad_slave(const int32_t* __restrict__ inc_off,
+                                                    const int32_t* __restrict__ inc_list, int32_t n,
+                                                    const int32_t* __restrict__ pair_off,
+                                                    const double* __restrict__ gpair, int64_t stride,
+                                                    double* __restrict__ gX) {
+  const int a = blockIdx.x * BS + threadIdx.x;
+  if (a >= n) return;
+  double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+  for (int i = inc_off[a]; i < inc_off[a + 1]; ++i) {
+    const int e = inc_list[i] >> 2, j = inc_list[i] & 3;
+    for (int p = pair_off[e]; p < pair_off[e + 1]; ++p) {
+      g0 += gpair[(int64_t)(3 * j + 0) * stride + p];
+      g1 += gpair[(int64_t)(3 * j + 1) * stride + p];
+      g2 += gpair[(int64_t)(3 * j + 2) * stride + p];
+    }
+  }
+  gX[a] = g0;
+  gX[(int64_t)n + a] = g1;
+  gX[2 * (int64_t)n + a] = g2;
+}
+
+__global__ __launch_bounds__(BS) void k_mpair_ranges(const uint32_t* __restrict__ keys, int64_t np,
+                                                      int32_t* __restrict__ start, int32_t* __restrict__ end) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i >= np) return;
+  const uint32_t k = keys[i];
+  if (i == 0 || keys[i - 1] != k) start[k] = (int32_t)i;
+  if (i == np - 1 || keys[i + 1] != k) end[k] = (int32_t)(i + 1);
+}
+
+__global__ __launch_bounds__(BS) void k_grad_master(const int32_t* __restrict__ inc_off,
+                                                     const int32_t* __restrict__ inc_list, int32_t n,
+                                                     const int32_t* __restrict__ mstart,
+                                                     const int32_t* __restrict__ mend,
+                                                     const uint32_t* __restrict__ mpairs,
+                                                     const double* __restrict__ gpair, int64_t stride,
+                                                     double* __restrict__ gX) {
+  const int b = blockIdx.x * BS + threadIdx.x;
+  if (b >= n) return;
+  double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+  for (int i = inc_off[b]; i < inc_off[b + 1]; ++i) {
+    const int m = inc_list[i] >> 2, l = inc_list[i] & 3;
+    for (int k = mstart[m]; k < mend[m]; ++k) {
+      const int64_t p = mpairs[k];
+      g0 += gpair[(int64_t)(12 + 3 * l + 0) * stride + p];
+      g1 += gpair[(int64_t)(12 + 3 * l + 1) * stride + p];
+      g2 += gpair[(int64_t)(12 + 3 * l + 2) * stride + p];
+    }
+  }
+  gX[b] = g0;
+  gX[(int64_t)n + b] = g1;
+  gX[2 * (int64_t)n + b] = g2;
+}
+
+inline unsigned grid_of(int64_t n) { return (unsigned)((n + BS - 1) / BS); }
+
+}  // namespace
+
+hipError_t launch_inc_count(const int32_t* conn, int32_t n_el, int32_t* cnt, hipStream_t s) {
+  if (n_el == 0) return hipSuccess;
+  k_inc_count<<<grid_of(n_el), BS, 0, s>>>(conn, n_el, cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_inc_fill(const int32_t* conn, int32_t n_el, const int32_t* off, int32_t* cur, int32_t* list,
+                           hipStream_t s) {
+  if (n_el == 0) return hipSuccess;
+  k_inc_fill<<<grid_of(n_el), BS, 0, s>>>(conn, n_el, off, cur, list);
+  return hipGetLastError();
+}
+
+hipError_t launch_inc_sort(const int32_t* off, int32_t n_nodes, int32_t* list, hipStream_t s) {
+  if (n_nodes == 0) return hipSuccess;
+  k_inc_sort<<<grid_of(n_nodes), BS, 0, s>>>(off, n_nodes, list);
+  return hipGetLastError();
+}
+
+hipError_t launch_raw_count(const int32_t* inc_off, const int32_t* inc_list, int32_t n_nodes,
+                            const int32_t* pair_off, int32_t* rawD_cnt, int32_t* rawM_cnt, hipStream_t s) {
+  if (n_nodes == 0) return hipSuccess;
+  k_raw_count<<<grid_of(n_nodes), BS, 0, s>>>(inc_off, inc_list, n_nodes, pair_off, rawD_cnt, rawM_cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_raw_fill(const int32_t* inc_off, const int32_t* inc_list, int32_t n_nodes, const int32_t* pair_off,
+                           const int32_t* pair_m, const int32_t* conn_s, const int32_t* conn_m,
+                           const int32_t* rawD_off, int32_t* rawD, const int32_t* rawM_off, int32_t* rawM,
+                           int32_t* D_cnt, int32_t* M_cnt, hipStream_t s) {
+  if (n_nodes == 0) return hipSuccess;
+  k_raw_fill<<<grid_of(n_nodes), BS, 0, s>>>(inc_off, inc_list, n_nodes, pair_off, pair_m, conn_s, conn_m, rawD_off,
+                                             rawD, rawM_off, rawM, D_cnt, M_cnt);
+  return hipGetLastError();
+}
+
+hipError_t launch_csr_cols(const int32_t* raw_off, const int32_t* raw, const int32_t* rowptr, int32_t n_rows,
+                           int32_t* col, hipStream_t s) {
+  if (n_rows == 0) return hipSuccess;
+  k_csr_cols<<<grid_of(n_rows), BS, 0, s>>>(raw_off, raw, rowptr, n_rows, col);
+  return hipGetLastError();
+}
+
+hipError_t launch_posD(const int32_t* conn_s, int32_t n_s_el, const int32_t* pair_off, const int32_t* rowptr,
+                       const int32_t* col, int32_t* posD, hipStream_t s) {
+  if (n_s_el == 0) return hipSuccess;
+  k_posD<<<grid_of(n_s_el), BS, 0, s>>>(conn_s, n_s_el, pair_off, rowptr, col, posD);
+  return hipGetLastError();
+}
+
+hipError_t launch_posM(const int32_t* conn_s, const int32_t* conn_m, const int32_t* pair_s, const int32_t* pair_m,
+                       int64_t n_pairs, const int32_t* rowptr, const int32_t* col, int32_t* posM, hipStream_t s) {
+  if (n_pairs == 0) return hipSuccess;
+  k_posM<<<grid_of(n_pairs), BS, 0, s>>>(conn_s, conn_m, pair_s, pair_m, n_pairs, rowptr, col, posM);
+  return hipGetLastError();
+}
+
+hipError_t launch_assemble(const int32_t* inc_off, const int32_t* inc_list, int32_t n_nodes, const int32_t* pair_off,
+                           const int32_t* D_rowptr, const int32_t* M_rowptr, const int32_t* posD, int32_t n_s_el,
+                           const int32_t* posM, const double* blk, int64_t stride, double* D_val, double* M_val,
+                           double* gap, hipStream_t s) {
+  if (n_nodes == 0) return hipSuccess;
+  k_assemble<<<grid_of(n_nodes), BS, 0, s>>>(inc_off, inc_list, n_nodes, pair_off, D_rowptr, M_rowptr, posD, n_s_el,
+                                             posM, blk, stride, D_val, M_val, gap);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_slave(const int32_t* inc_off, const int32_t* inc_list, int32_t n_nodes,
+                             const int32_t* pair_off, const double* gpair, int64_t stride, double* gX,
+                             hipStream_t s) {
+  if (n_nodes == 0) return hipSuccess;
+  k_grad_slave<<<grid_of(n_nodes), BS, 0, s>>>(inc_off, inc_list, n_nodes, pair_off, gpair, stride, gX);
+  return hipGetLastError();
+}
+
+hipError_t launch_mpair_off(const uint32_t* sorted_m, int64_t n_pairs, int32_t n_m_el, int32_t* off,
+                            hipStream_t s) {
+  // off holds start[n_m_el] followed by end[n_m_el]; both pre-zeroed.
+  if (n_pairs == 0) return hipSuccess;
+  k_mpair_ranges<<<grid_of(n_pairs), BS, 0, s>>>(sorted_m, n_pairs, off, off + n_m_el);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_master(const int32_t* inc_off, const int32_t* inc_list, int32_t n_nodes,
+                              const int32_t* mstart, const int32_t* mend, const uint32_t* mp_pairs,
+                              const double* gpair, int64_t stride, double* gX, hipStream_t s) {
+  if (n_nodes == 0) return hipSuccess;
+  k_grad_master<<<grid_of(n_nodes), BS, 0, s>>>(inc_off, inc_list, n_nodes, mstart, mend, mp_pairs, gpair, stride,
+                                                gX);
+  return hipGetLastError();
+}
+
+}  // namespace mt

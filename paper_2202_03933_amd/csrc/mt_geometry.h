@@ -1,0 +1,422 @@
+// Device-side geometry of one slave/master element pair: auxiliary plane,
+// projection, Sutherland-Hodgman clipping with cleanup, triangle rules and
+// the inverse bilinear map.
+//
+// Every expression that decides topology (which candidates are pairs, how
+// many vertices a clip polygon has) is written in one fixed evaluation order
+// and compiled without fused multiply-add (-ffp-contract=off), so the clip
+// polygons are bitwise identical to any implementation evaluating the same
+// expressions under IEEE-754 double arithmetic.  Integration code opts back
+// into contraction locally.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mt {
+
+constexpr int CAP = 16;  // working capacity of a clip polygon (vertices)
+
+struct V2 {
+  double u, v;
+};
+
+// ---- node / element access -------------------------------------------------
+
+__device__ __forceinline__ int4 load_conn(const int32_t* conn, int e) {
+  return reinterpret_cast<const int4*>(conn)[e];
+}
+
+__device__ __forceinline__ void load_nodes(const double* __restrict__ x, const double* __restrict__ y,
+                                           const double* __restrict__ z, int4 c, double X[4][3]) {
+  const int id[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    X[k][0] = x[id[k]];
+    X[k][1] = y[id[k]];
+    X[k][2] = z[id[k]];
+  }
+}
+
+// ---- auxiliary plane of a slave element (Fig. 1: centre x0, normal n0) -----
+
+// f[0..2] = x0, f[3..5] = n0, f[6..8] = t1, f[9..11] = t2.
+__device__ __forceinline__ void slave_frame(const double X[4][3], double f[12]) {
+  double g1[3], g2[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    f[d] = 0.25 * (((X[0][d] + X[1][d]) + X[2][d]) + X[3][d]);
+    g1[d] = 0.25 * (((X[1][d] - X[0][d]) + X[2][d]) - X[3][d]);
+    g2[d] = 0.25 * (((X[2][d] + X[3][d]) - X[0][d]) - X[1][d]);
+  }
+  const double n0 = g1[1] * g2[2] - g1[2] * g2[1];
+  const double n1 = g1[2] * g2[0] - g1[0] * g2[2];
+  const double n2 = g1[0] * g2[1] - g1[1] * g2[0];
+  const double ln = sqrt((n0 * n0 + n1 * n1) + n2 * n2);
+  const double lg = sqrt((g1[0] * g1[0] + g1[1] * g1[1]) + g1[2] * g1[2]);
+  f[3] = n0 / ln;
+  f[4] = n1 / ln;
+  f[5] = n2 / ln;
+  f[6] = g1[0] / lg;
+  f[7] = g1[1] / lg;
+  f[8] = g1[2] / lg;
+  f[9] = f[4] * f[8] - f[5] * f[7];
+  f[10] = f[5] * f[6] - f[3] * f[8];
+  f[11] = f[3] * f[7] - f[4] * f[6];
+}
+
+// In-plane coordinates and height of one node.
+__device__ __forceinline__ void project(const double X[3], const double f[12], V2& p, double& h) {
+  const double d0 = X[0] - f[0], d1 = X[1] - f[1], d2 = X[2] - f[2];
+  p.u = (d0 * f[6] + d1 * f[7]) + d2 * f[8];
+  p.v = (d0 * f[9] + d1 * f[10]) + d2 * f[11];
+  h = (d0 * f[3] + d1 * f[4]) + d2 * f[5];
+}
+
+__device__ __forceinline__ double quad_fan_area(const V2 p[4]) {
+  double a = 0.0;
+#pragma unroll
+  for (int i = 1; i < 3; ++i)
+    a = a + ((p[i].u - p[0].u) * (p[i + 1].v - p[0].v) - (p[i].v - p[0].v) * (p[i + 1].u - p[0].u));
+  return 0.5 * a;
+}
+
+__device__ __forceinline__ double linf(double du, double dv) { return fmax(fabs(du), fabs(dv)); }
+
+// ---- per-lane polygon storage in LDS ---------------------------------------
+// Two ping-pong buffers of CAP vertices per lane, lane-interleaved so that a
+// wavefront touching vertex i of its polygons hits consecutive addresses.
+// With labels, each vertex also carries its provenance (slave node k:
+// 0x80|k, else the two lines it lies on, (la << 4) | lb, line ids 0..3 =
+// slave edges k -> k+1, 4..7 = master clip edges) and the line id of the
+// edge leaving it.
+template <bool LAB>
+struct LdsPoly {
+  double* u;
+  double* v;
+  uint8_t* vl;
+  uint8_t* el;
+  int bs;
+  __device__ __forceinline__ int at(int b, int i) const { return (b * CAP + i) * bs; }
+};
+
+// Clip the slave polygon S (counter-clockwise) by the master polygon Mo
+// (counter-clockwise) with Sutherland-Hodgman: per master edge a -> b keep
+// the closed left half plane, walking subject edges P -> E from vertex 0,
+// emitting P when inside and then the crossing when the sides differ.
+// Returns the vertex count; the polygon is in buffer `res`.  Sets *ovf on
+// capacity overflow (then returns 0).
+template <bool LAB>
+__device__ __forceinline__ int clip_polygon(const V2 S[4], const V2 Mo[4], const LdsPoly<LAB>& P, int& res,
+                                            bool& ovf) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    P.u[P.at(0, k)] = S[k].u;
+    P.v[P.at(0, k)] = S[k].v;
+    if (LAB) {
+      P.vl[P.at(0, k)] = (uint8_t)(0x80 | k);
+      P.el[P.at(0, k)] = (uint8_t)k;
+    }
+  }
+  int n = 4, cur = 0;
+  ovf = false;
+  for (int l = 0; l < 4; ++l) {
+    if (n == 0) break;
+    const V2 a = Mo[l];
+    const V2 b = Mo[(l + 1) & 3];
+    const double dbu = b.u - a.u, dbv = b.v - a.v;
+    const int nxt = cur ^ 1;
+    double Pu = P.u[P.at(cur, 0)], Pv = P.v[P.at(cur, 0)];
+    uint8_t Pl = 0, Pe = 0;
+    if (LAB) { Pl = P.vl[P.at(cur, 0)]; Pe = P.el[P.at(cur, 0)]; }
+    double cP = dbu * (Pv - a.v) - dbv * (Pu - a.u);
+    const double u0 = Pu, v0 = Pv, c0 = cP;
+    const uint8_t l0 = Pl, e0 = Pe;
+    int k = 0;
+    for (int j = 0; j < n; ++j) {
+      double Eu, Ev, cE;
+      uint8_t El = 0, Ee = 0;
+      if (j + 1 < n) {
+        Eu = P.u[P.at(cur, j + 1)];
+        Ev = P.v[P.at(cur, j + 1)];
+        if (LAB) { El = P.vl[P.at(cur, j + 1)]; Ee = P.el[P.at(cur, j + 1)]; }
+        cE = dbu * (Ev - a.v) - dbv * (Eu - a.u);
+      } else {
+        Eu = u0; Ev = v0; cE = c0;
+        if (LAB) { El = l0; Ee = e0; }
+      }
+      const bool pin = cP >= 0.0;
+      const bool ein = cE >= 0.0;
+      if (pin) {
+        if (k == CAP) { ovf = true; return 0; }
+        P.u[P.at(nxt, k)] = Pu;
+        P.v[P.at(nxt, k)] = Pv;
+        if (LAB) { P.vl[P.at(nxt, k)] = Pl; P.el[P.at(nxt, k)] = Pe; }
+        ++k;
+      }
+      if (pin != ein) {
+        if (k == CAP) { ovf = true; return 0; }
+        const double t = cP / (cP - cE);
+        P.u[P.at(nxt, k)] = Pu + t * (Eu - Pu);
+        P.v[P.at(nxt, k)] = Pv + t * (Ev - Pv);
+        if (LAB) {
+          P.vl[P.at(nxt, k)] = (uint8_t)((Pe << 4) | (4 + l));
+          P.el[P.at(nxt, k)] = pin ? (uint8_t)(4 + l) : Pe;
+        }
+        ++k;
+      }
+      Pu = Eu; Pv = Ev; cP = cE;
+      if (LAB) { Pl = El; Pe = Ee; }
+    }
+    n = k;
+    cur = nxt;
+  }
+  res = cur;
+  return n;
+}
+
+template <bool LAB>
+__device__ __forceinline__ void poly_move(const LdsPoly<LAB>& P, int b, int dst, int src) {
+  P.u[P.at(b, dst)] = P.u[P.at(b, src)];
+  P.v[P.at(b, dst)] = P.v[P.at(b, src)];
+  if (LAB) {
+    P.vl[P.at(b, dst)] = P.vl[P.at(b, src)];
+    P.el[P.at(b, dst)] = P.el[P.at(b, src)];
+  }
+}
+
+// Cleanup of a raw clip polygon in buffer b: (i) one pass dropping vertices
+// within tol (max-norm) of the previously kept one, vertex 0 always kept and
+// the last kept one dropped if within tol of vertex 0; (ii) repeated sweeps in
+// index order removing any vertex with |cross(next-prev, v-prev)| <=
+// tol * maxnorm(next-prev), until a sweep removes nothing or n < 3.
+template <bool LAB>
+__device__ __forceinline__ int cleanup(const LdsPoly<LAB>& P, int b, int n, double tol) {
+  if (n == 0) return 0;
+  int m = 1;
+  double lu = P.u[P.at(b, 0)], lv = P.v[P.at(b, 0)];
+  for (int i = 1; i < n; ++i) {
+    const double cu = P.u[P.at(b, i)], cv = P.v[P.at(b, i)];
+    if (linf(cu - lu, cv - lv) > tol) {
+      if (m != i) poly_move(P, b, m, i);
+      ++m;
+      lu = cu;
+      lv = cv;
+    }
+  }
+  if (m > 1 && linf(lu - P.u[P.at(b, 0)], lv - P.v[P.at(b, 0)]) <= tol) --m;
+  n = m;
+  bool changed = true;
+  while (changed && n >= 3) {
+    changed = false;
+    int i = 0;
+    while (i < n && n >= 3) {
+      const int ia = (i + n - 1) % n, ib = (i + 1) % n;
+      const double au = P.u[P.at(b, ia)], av = P.v[P.at(b, ia)];
+      const double bu = P.u[P.at(b, ib)] - au, bv = P.v[P.at(b, ib)] - av;
+      const double cr = bu * (P.v[P.at(b, i)] - av) - bv * (P.u[P.at(b, i)] - au);
+      if (fabs(cr) <= tol * linf(bu, bv)) {
+        for (int j = i; j + 1 < n; ++j) poly_move(P, b, j, j + 1);
+        --n;
+        changed = true;
+      } else {
+        ++i;
+      }
+    }
+  }
+  return n;
+}
+
+template <bool LAB>
+__device__ __forceinline__ double poly_fan_area(const LdsPoly<LAB>& P, int b, int n) {
+  const double u0 = P.u[P.at(b, 0)], v0 = P.v[P.at(b, 0)];
+  double a = 0.0;
+  for (int i = 1; i + 1 < n; ++i) {
+    const double u1 = P.u[P.at(b, i)], v1 = P.v[P.at(b, i)];
+    const double u2 = P.u[P.at(b, i + 1)], v2 = P.v[P.at(b, i + 1)];
+    a = a + ((u1 - u0) * (v2 - v0) - (v1 - v0) * (u2 - u0));
+  }
+  return 0.5 * a;
+}
+
+// Status bits of one pair evaluation.
+enum : int { PS_DEGEN_SLAVE = 1, PS_DEGEN_MASTER = 2, PS_OVERFLOW = 4 };
+
+// Projection, orientation, clip and cleanup of one candidate.  On return:
+// S, Mn = projected slave / master nodes (node order), hs, hm = heights,
+// Mo = master polygon walked counter-clockwise (mo_map: Mo[l] = Mn[mo_map[l]]),
+// polygon in buffer `res` with `n` vertices (0: not a pair).
+template <bool LAB>
+__device__ __forceinline__ int pair_geometry(const double Xs[4][3], const double Xm[4][3], const double f[12],
+                                             double eps_d, double eps_a, V2 S[4], V2 Mn[4], double hs[4],
+                                             double hm[4], int mo_map[4], const LdsPoly<LAB>& P, int& res,
+                                             int& status) {
+  status = 0;
+  res = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) project(Xs[k], f, S[k], hs[k]);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) project(Xm[k], f, Mn[k], hm[k]);
+  const double As = quad_fan_area(S);
+  if (!(As > 0.0)) { status = PS_DEGEN_SLAVE; return 0; }
+  double hmax = 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int e = (k + 1) & 3;
+    hmax = fmax(hmax, linf(S[e].u - S[k].u, S[e].v - S[k].v));
+  }
+  const double tol_d = eps_d * hmax;
+  const double tol_a = eps_a * As;
+  const double Am = quad_fan_area(Mn);
+  if (fabs(Am) <= tol_a) { status = PS_DEGEN_MASTER; return 0; }
+  mo_map[0] = 0; mo_map[1] = 1; mo_map[2] = 2; mo_map[3] = 3;
+  if (Am < 0.0) { mo_map[1] = 3; mo_map[3] = 1; }
+  V2 Mo[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) Mo[k] = Mn[mo_map[k]];
+  bool ovf;
+  int n = clip_polygon<LAB>(S, Mo, P, res, ovf);
+  if (ovf) { status = PS_OVERFLOW; return 0; }
+  n = cleanup<LAB>(P, res, n, tol_d);
+  if (n < 3) return 0;
+  const double Ap = poly_fan_area<LAB>(P, res, n);
+  if (!(Ap > tol_a)) return 0;
+  return n;
+}
+
+// ---- quadrature ------------------------------------------------------------
+
+// Barycentric triangle rules, weights summing to one: 7 points of degree 5
+// (Radon's rule) and 3 points of degree 2 (the rule of Fig. 1).
+struct TriRule {
+  int n;
+  double l[7][3];
+  double w[7];
+};
+
+__device__ __forceinline__ void get_rule(int which, double l[7][3], double w[7], int& n) {
+  if (which == 3) {
+    const double a = 2.0 / 3.0, b = 1.0 / 6.0;
+    n = 3;
+    l[0][0] = a; l[0][1] = b; l[0][2] = b;
+    l[1][0] = b; l[1][1] = a; l[1][2] = b;
+    l[2][0] = b; l[2][1] = b; l[2][2] = a;
+    w[0] = w[1] = w[2] = 1.0 / 3.0;
+    return;
+  }
+  const double a1 = 0.10128650732345634, b1 = 0.7974269853530873, w1 = 0.12593918054482714;
+  const double a2 = 0.4701420641051151, b2 = 0.05971587178976982, w2 = 0.1323941527885062;
+  n = 7;
+  l[0][0] = 1.0 / 3.0; l[0][1] = 1.0 / 3.0; l[0][2] = 1.0 / 3.0; w[0] = 9.0 / 40.0;
+  l[1][0] = b1; l[1][1] = a1; l[1][2] = a1; w[1] = w1;
+  l[2][0] = a1; l[2][1] = b1; l[2][2] = a1; w[2] = w1;
+  l[3][0] = a1; l[3][1] = a1; l[3][2] = b1; w[3] = w1;
+  l[4][0] = b2; l[4][1] = a2; l[4][2] = a2; w[4] = w2;
+  l[5][0] = a2; l[5][1] = b2; l[5][2] = a2; w[5] = w2;
+  l[6][0] = a2; l[6][1] = a2; l[6][2] = b2; w[6] = w2;
+}
+
+// Bilinear shape functions, nodes at (-1,-1), (1,-1), (1,1), (-1,1).
+__device__ __forceinline__ void shape4(double x1, double x2, double N[4]) {
+#pragma clang fp contract(fast)
+  const double a0 = 1.0 - x1, a1 = 1.0 + x1, b0 = 1.0 - x2, b1 = 1.0 + x2;
+  N[0] = 0.25 * a0 * b0;
+  N[1] = 0.25 * a1 * b0;
+  N[2] = 0.25 * a1 * b1;
+  N[3] = 0.25 * a0 * b1;
+}
+
+// Inverse of the bilinear map xi -> sum_k N_k(xi) X_k by Newton's method
+// from xi = 0; stops when max |dxi| <= tol.  Returns false when it did not
+// converge in maxit iterations.  The map is written as
+// x(xi) = c + e1 xi1 + e2 xi2 + e12 xi1 xi2.
+__device__ __forceinline__ bool inverse_bilinear(const V2 X[4], double pu, double pv, double tol, int maxit,
+                                                 double& x1, double& x2) {
+#pragma clang fp contract(fast)
+  const double cu = 0.25 * ((X[0].u + X[1].u) + (X[2].u + X[3].u));
+  const double cv = 0.25 * ((X[0].v + X[1].v) + (X[2].v + X[3].v));
+  const double e1u = 0.25 * ((X[1].u - X[0].u) + (X[2].u - X[3].u));
+  const double e1v = 0.25 * ((X[1].v - X[0].v) + (X[2].v - X[3].v));
+  const double e2u = 0.25 * ((X[2].u - X[1].u) + (X[3].u - X[0].u));
+  const double e2v = 0.25 * ((X[2].v - X[1].v) + (X[3].v - X[0].v));
+  const double fu = 0.25 * ((X[0].u - X[1].u) + (X[2].u - X[3].u));
+  const double fv = 0.25 * ((X[0].v - X[1].v) + (X[2].v - X[3].v));
+  x1 = 0.0;
+  x2 = 0.0;
+  const double ru0 = cu - pu, rv0 = cv - pv;
+  for (int it = 0; it < maxit; ++it) {
+    const double ru = ru0 + e1u * x1 + e2u * x2 + fu * x1 * x2;
+    const double rv = rv0 + e1v * x1 + e2v * x2 + fv * x1 * x2;
+    const double j00 = e1u + fu * x2, j01 = e2u + fu * x1;
+    const double j10 = e1v + fv * x2, j11 = e2v + fv * x1;
+    const double rdet = 1.0 / (j00 * j11 - j01 * j10);
+    const double s1 = (j11 * ru - j01 * rv) * rdet;
+    const double s2 = (j00 * rv - j10 * ru) * rdet;
+    x1 -= s1;
+    x2 -= s2;
+    if (fmax(fabs(s1), fabs(s2)) <= tol) return true;
+  }
+  return false;
+}
+
+// Dual basis coefficients A = De Me^-1 of one slave element from its
+// projected nodes (2x2 Gauss; De = diag int N_j, Me = int N N^T).
+__device__ __forceinline__ void dual_coefficients(const V2 S[4], double A[16]) {
+#pragma clang fp contract(fast)
+  const double g = 0.5773502691896257;
+  double Me[16], De[4];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) Me[i] = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) De[i] = 0.0;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const double x1 = a ? g : -g, x2 = b ? g : -g;
+      double N[4];
+      shape4(x1, x2, N);
+      const double d1[4] = {-0.25 * (1.0 - x2), 0.25 * (1.0 - x2), 0.25 * (1.0 + x2), -0.25 * (1.0 + x2)};
+      const double d2[4] = {-0.25 * (1.0 - x1), -0.25 * (1.0 + x1), 0.25 * (1.0 + x1), 0.25 * (1.0 - x1)};
+      double j00 = 0, j01 = 0, j10 = 0, j11 = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        j00 += d1[k] * S[k].u; j01 += d2[k] * S[k].u;
+        j10 += d1[k] * S[k].v; j11 += d2[k] * S[k].v;
+      }
+      const double det = j00 * j11 - j01 * j10;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        De[j] += N[j] * det;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) Me[j * 4 + k] += N[j] * N[k] * det;
+      }
+    }
+  // Gauss-Jordan inverse of Me (symmetric positive definite: no pivoting).
+  double inv[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) inv[i] = (i % 5 == 0) ? 1.0 : 0.0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const double r = 1.0 / Me[c * 4 + c];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { Me[c * 4 + k] *= r; inv[c * 4 + k] *= r; }
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      if (rr == c) continue;
+      const double fct = Me[rr * 4 + c];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        Me[rr * 4 + k] -= fct * Me[c * 4 + k];
+        inv[rr * 4 + k] -= fct * inv[c * 4 + k];
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) A[j * 4 + k] = De[j] * inv[j * 4 + k];
+}
+
+}  // namespace mt

@@ -1,0 +1,203 @@
+// Internal host-side declarations of the mortar library: context layout,
+// device buffers and the launch wrappers each translation unit provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "mortar_mi355x.h"
+
+namespace mt {
+
+// Grow-only device allocation owned by a context.
+struct Buf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+hipError_t ensure(Buf& b, size_t bytes);
+void release(Buf& b);
+
+struct DeviceMesh {
+  const double* x = nullptr;
+  const double* y = nullptr;
+  const double* z = nullptr;
+  const int32_t* conn = nullptr;  // [n_el][4]
+  int32_t n_nodes = 0;
+  int32_t n_el = 0;
+  bool set = false;
+};
+
+// Cartesian search grid (cells indexed ix + nx * (iy + ny * iz)).
+struct Grid {
+  double lo[3];
+  double inv_beta[3];
+  double beta[3];
+  int32_t n[3];
+  int64_t ncells;
+};
+
+// Device-side scalar reductions of the element preparation step.
+struct PrepReduce {
+  unsigned long long emax_bits;   // largest element box extent (non-negative double bits)
+  unsigned long long edge_bits;   // longest slave element edge
+  unsigned long long lo_key[3];   // node bounding box, order-preserving keys
+  unsigned long long hi_key[3];
+  int32_t bad_index;              // connectivity out of range
+  int32_t pad;
+};
+
+// Device counters of the pair pipeline.
+struct Counters {
+  unsigned long long hist[17];
+  unsigned long long noconv;
+  unsigned long long overflow;
+  unsigned long long degen_slave;
+  unsigned long long degen_master;
+};
+
+struct KParams {
+  double delta;
+  double eps_d;
+  double eps_a;
+  double newton_tol;
+  int32_t newton_maxit;
+  int32_t dual;
+  int32_t rule;
+  int32_t pad;
+};
+
+}  // namespace mt
+
+struct mt_ctx {
+  int device = 0;
+  mt_params params{};
+  mt::DeviceMesh side[2];
+  hipStream_t last_stream = nullptr;
+
+  // state flags
+  bool have_pairs = false;
+  bool have_pattern = false;
+  bool have_master_index = false;
+  int64_t n_cand = 0, n_pairs = 0, nnz_D = 0, nnz_M = 0;
+  mt::Grid grid{};
+
+  // element preparation
+  mt::Buf box_s, box_m;    // [6][n_el] lo xyz, hi xyz
+  mt::Buf reduce;          // PrepReduce
+  mt::Buf counters;        // Counters
+  // binning
+  mt::Buf keys, vals, keys_tmp, vals_tmp;
+  mt::Buf cell_start, cell_end;
+  // candidates
+  mt::Buf cand_cnt;        // [n_s_el + 1]
+  mt::Buf cand_off;        // [n_s_el + 1]
+  mt::Buf cand_s, cand_m;  // [n_cand]
+  mt::Buf cand_nv;         // uint8 [n_cand]
+  mt::Buf cand_flag;       // int32 [n_cand + 1]
+  mt::Buf cand_scan;       // int32 [n_cand + 1]
+  // pairs
+  mt::Buf pair_s, pair_m;  // [n_pairs]
+  mt::Buf pair_nv;         // uint8 [n_pairs]
+  mt::Buf pair_off;        // [n_s_el + 1] first pair of each slave element
+  // pattern
+  mt::Buf inc_cnt, inc_off, inc_cur, inc_list;     // slave node -> (element*4 + local)
+  mt::Buf minc_cnt, minc_off, minc_cur, minc_list; // master node -> (element*4 + local)
+  mt::Buf rawD_cnt, rawD_off, rawD;                // per-row raw column lists
+  mt::Buf rawM_cnt, rawM_off, rawM;
+  mt::Buf D_cnt, D_rowptr, D_col;
+  mt::Buf M_cnt, M_rowptr, M_col;
+  mt::Buf posD;            // [16][n_s_el]
+  mt::Buf posM;            // [16][n_pairs]
+  // forward / backward staging
+  mt::Buf blk;             // [36][n_pairs]
+  mt::Buf gpair;           // [24][n_pairs]
+  mt::Buf mp_keys, mp_vals, mp_off;  // pairs sorted by master element
+  // scan / sort scratch
+  mt::Buf scan_tmp, sort_hist, host_tmp;
+};
+
+namespace mt {
+
+// ---- primitives (mt_prims.hip) ------------------------------------------
+// Exclusive prefix sum of n int32 values into out[0..n]; out[n] = total.
+hipError_t scan_exclusive(const int32_t* in, int32_t* out, int64_t n, Buf& tmp, hipStream_t s);
+// Stable LSD radix sort of (key, value) pairs on key bits [0, bits).
+// Results end in (keys, vals); (keys_tmp, vals_tmp) are scratch of size n.
+hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp,
+                            int64_t n, int bits, Buf& hist, Buf& scan_tmp, hipStream_t s);
+hipError_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+hipError_t fill_f64(double* p, double v, int64_t n, hipStream_t s);
+
+// ---- search (mt_search.hip) ------------------------------------------------
+hipError_t launch_prep(const DeviceMesh& m, bool slave, double* box, PrepReduce* red, hipStream_t s);
+hipError_t launch_init_reduce(PrepReduce* red, hipStream_t s);
+void grid_from_reduce(const PrepReduce& r, double delta, double bin_size, Grid& g);
+hipError_t launch_master_keys(const double* box_m, int32_t n_m, Grid g, uint32_t* keys, uint32_t* vals,
+                              hipStream_t s);
+hipError_t launch_cell_ranges(const uint32_t* keys, int32_t n, int32_t* start, int32_t* end,
+                              hipStream_t s);
+hipError_t launch_cand_count(const double* box_s, int32_t n_s, const double* box_m, int32_t n_m,
+                             const uint32_t* mvals, const int32_t* start, const int32_t* end, Grid g,
+                             double delta, int32_t* count, hipStream_t s);
+hipError_t launch_cand_fill(const double* box_s, int32_t n_s, const double* box_m, int32_t n_m,
+                            const uint32_t* mvals, const int32_t* start, const int32_t* end, Grid g,
+                            double delta, const int32_t* off, int32_t* cand_s, int32_t* cand_m, hipStream_t s);
+
+// ---- pairs (mt_pairs.hip) ----------------------------------------------------
+hipError_t launch_clip_count(const DeviceMesh& S, const DeviceMesh& M, const KParams& kp, const int32_t* cand_s, const int32_t* cand_m,
+                             int64_t n_cand, uint8_t* nv, int32_t* flag, Counters* cnt, hipStream_t s);
+hipError_t launch_compact(const int32_t* cand_s, const int32_t* cand_m, const uint8_t* cand_nv,
+                          const int32_t* scan, int64_t n_cand, int32_t* pair_s, int32_t* pair_m,
+                          uint8_t* pair_nv, hipStream_t s);
+hipError_t launch_pair_off(const int32_t* cand_off, const int32_t* scan, int32_t n_s, int32_t* pair_off,
+                           hipStream_t s);
+hipError_t launch_pair_fwd(const DeviceMesh& S, const DeviceMesh& M, const KParams& kp, const int32_t* pair_s,
+                           const int32_t* pair_m, int64_t n_pairs, double* blk, int64_t blk_stride,
+                           Counters* cnt, hipStream_t s);
+
+// ---- assembly (mt_assemble.hip) ----------------------------------------------
+hipError_t launch_inc_count(const int32_t* conn, int32_t n_el, int32_t* cnt, hipStream_t s);
+hipError_t launch_inc_fill(const int32_t* conn, int32_t n_el, const int32_t* off, int32_t* cur,
+                           int32_t* list, hipStream_t s);
+hipError_t launch_inc_sort(const int32_t* off, int32_t n_nodes, int32_t* list, hipStream_t s);
+hipError_t launch_raw_count(const int32_t* inc_off, const int32_t* inc_list, int32_t n_nodes,
+                            const int32_t* pair_off, int32_t* rawD_cnt, int32_t* rawM_cnt, hipStream_t s);
+hipError_t launch_raw_fill(const int32_t* inc_off, const int32_t* inc_list, int32_t n_nodes,
+                           const int32_t* pair_off, const int32_t* pair_m, const int32_t* conn_s,
+                           const int32_t* conn_m, const int32_t* rawD_off, int32_t* rawD,
+                           const int32_t* rawM_off, int32_t* rawM, int32_t* D_cnt, int32_t* M_cnt,
+                           hipStream_t s);
+hipError_t launch_csr_cols(const int32_t* raw_off, const int32_t* raw, const int32_t* rowptr,
+                           int32_t n_rows, int32_t* col, hipStream_t s);
+hipError_t launch_posD(const int32_t* conn_s, int32_t n_s_el, const int32_t* pair_off,
+                       const int32_t* rowptr, const int32_t* col, int32_t* posD, hipStream_t s);
+hipError_t launch_posM(const int32_t* conn_s, const int32_t* conn_m, const int32_t* pair_s,
+                       const int32_t* pair_m, int64_t n_pairs, const int32_t* rowptr, const int32_t* col,
+                       int32_t* posM, hipStream_t s);
+hipError_t launch_assemble(const int32_t* inc_off, const int32_t* inc_list, int32_t n_nodes,
+                           const int32_t* pair_off, const int32_t* D_rowptr, const int32_t* M_rowptr,
+                           const int32_t* posD, int32_t n_s_el, const int32_t* posM, const double* blk,
+                           int64_t blk_stride, double* D_val, double* M_val, double* gap, hipStream_t s);
+hipError_t launch_grad_slave(const int32_t* inc_off, const int32_t* inc_list, int32_t n_nodes,
+                             const int32_t* pair_off, const double* gpair, int64_t stride, double* gX,
+                             hipStream_t s);
+hipError_t launch_mpair_off(const uint32_t* sorted_m, int64_t n_pairs, int32_t n_m_el, int32_t* off,
+                            hipStream_t s);
+hipError_t launch_grad_master(const int32_t* inc_off, const int32_t* inc_list, int32_t n_nodes,
+                              const int32_t* mstart, const int32_t* mend, const uint32_t* mp_pairs,
+                              const double* gpair, int64_t stride, double* gX, hipStream_t s);
+
+// ---- backward (mt_backward.hip) ----------------------------------------------
+hipError_t launch_pair_bwd(const DeviceMesh& S, const DeviceMesh& M, const KParams& kp, const int32_t* pair_s, const int32_t* pair_m,
+                           int64_t n_pairs, const int32_t* posD, int32_t n_s_el, const int32_t* posM,
+                           const double* W_D, const double* W_M, const double* w_g, double* gpair,
+                           int64_t stride, Counters* cnt, hipStream_t s);
+
+KParams kparams(const mt_params& p);
+void set_error(const std::string& msg);
+
+}  // namespace mt

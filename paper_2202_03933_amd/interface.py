@@ -1,0 +1,190 @@
+"""Torch-facing wrapper of one mortar interface on the GPU.
+
+Torch tensors provide device memory and the stream; all work runs in the HIP
+library through the C ABI.  Coordinates are kept as structure-of-arrays
+(3, n) float64 tensors, connectivity as (n_el, 4) int32.
+"""
+
+import ctypes
+
+import torch
+
+from . import _capi as C
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def default_params(**kw):
+    p = C.mt_params()
+    C.check(C.lib().mt_default_params(ctypes.byref(p)))
+    for k, v in kw.items():
+        if k == "dual":
+            p.lm_basis = C.MT_BASIS_DUAL if v else C.MT_BASIS_STANDARD
+        else:
+            setattr(p, k, v)
+    return p
+
+
+class MortarInterface:
+    """One slave/master interface registered with a library context."""
+
+    def __init__(self, Xs, conn_s, Xm, conn_m, params=None, device=None, stream=None):
+        if device is None:
+            device = torch.device("cuda", torch.cuda.current_device())
+        self.device = torch.device(device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        C.check(C.lib().mt_create(ctypes.byref(h), self.device.index or 0))
+        self.h = h
+        self.params = params if params is not None else default_params()
+        C.check(C.lib().mt_set_params(self.h, ctypes.byref(self.params)))
+        self._uploaded = False
+        self.set_coordinates(Xs, Xm, conn_s, conn_m)
+        self.n_cand = self.n_pairs = self.nnz_D = self.nnz_M = None
+
+    def set_coordinates(self, Xs, Xm, conn_s=None, conn_m=None):
+        """Register coordinates (n, 3) and, optionally, connectivity.  With
+        connectivity (or on first use) the meshes are uploaded and the pair
+        list is invalidated; without, only the coordinates are replaced and
+        the pair list and pattern are kept."""
+        dev = self.device
+        self.Xs = torch.as_tensor(Xs, dtype=torch.float64, device=dev).t().contiguous()
+        self.Xm = torch.as_tensor(Xm, dtype=torch.float64, device=dev).t().contiguous()
+        if conn_s is not None:
+            self.conn_s = torch.as_tensor(conn_s, dtype=torch.int32, device=dev).contiguous()
+        if conn_m is not None:
+            self.conn_m = torch.as_tensor(conn_m, dtype=torch.int32, device=dev).contiguous()
+        L = C.lib()
+        full = conn_s is not None or conn_m is not None or not self._uploaded
+        for side, X, conn in ((C.MT_SIDE_SLAVE, self.Xs, self.conn_s), (C.MT_SIDE_MASTER, self.Xm, self.conn_m)):
+            n = X.shape[1]
+            if full:
+                C.check(L.mt_upload(self.h, side, n, _ptr(X[0]), _ptr(X[1]), _ptr(X[2]), conn.shape[0],
+                                    _ptr(conn), _stream(self.stream)))
+            else:
+                C.check(L.mt_update_coordinates(self.h, side, _ptr(X[0]), _ptr(X[1]), _ptr(X[2]),
+                                                _stream(self.stream)))
+        self._uploaded = True
+
+    @property
+    def n_slave_nodes(self):
+        return int(self.Xs.shape[1])
+
+    @property
+    def n_master_nodes(self):
+        return int(self.Xm.shape[1])
+
+    def build_pairs(self):
+        nc, npairs = ctypes.c_int64(), ctypes.c_int64()
+        C.check(C.lib().mt_build_pairs(self.h, ctypes.byref(nc), ctypes.byref(npairs), _stream(self.stream)))
+        self.n_cand, self.n_pairs = nc.value, npairs.value
+        return self.n_cand, self.n_pairs
+
+    def pairs(self):
+        n = self.n_pairs
+        s = torch.empty(n, dtype=torch.int32, device=self.device)
+        m = torch.empty(n, dtype=torch.int32, device=self.device)
+        nv = torch.empty(n, dtype=torch.uint8, device=self.device)
+        C.check(C.lib().mt_get_pairs(self.h, _ptr(s), _ptr(m), _ptr(nv), _stream(self.stream)))
+        return s, m, nv
+
+    def candidates(self):
+        n = self.n_cand
+        s = torch.empty(n, dtype=torch.int32, device=self.device)
+        m = torch.empty(n, dtype=torch.int32, device=self.device)
+        nv = torch.empty(n, dtype=torch.uint8, device=self.device)
+        C.check(C.lib().mt_get_candidates(self.h, _ptr(s), _ptr(m), _ptr(nv), _stream(self.stream)))
+        return s, m, nv
+
+    def csr_pattern(self):
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        C.check(C.lib().mt_csr_pattern(self.h, ctypes.byref(a), ctypes.byref(b), _stream(self.stream)))
+        self.nnz_D, self.nnz_M = a.value, b.value
+        n1 = self.n_slave_nodes + 1
+        dev = self.device
+        self.D_rowptr = torch.empty(n1, dtype=torch.int32, device=dev)
+        self.M_rowptr = torch.empty(n1, dtype=torch.int32, device=dev)
+        self.D_col = torch.empty(self.nnz_D, dtype=torch.int32, device=dev)
+        self.M_col = torch.empty(self.nnz_M, dtype=torch.int32, device=dev)
+        C.check(C.lib().mt_get_csr(self.h, _ptr(self.D_rowptr), _ptr(self.D_col), _ptr(self.M_rowptr),
+                                   _ptr(self.M_col), _stream(self.stream)))
+        return self.nnz_D, self.nnz_M
+
+    def setup(self):
+        self.build_pairs()
+        self.csr_pattern()
+        return self
+
+    def alloc_outputs(self):
+        dev = self.device
+        return (torch.empty(self.nnz_D, dtype=torch.float64, device=dev),
+                torch.empty(self.nnz_M, dtype=torch.float64, device=dev),
+                torch.empty(self.n_slave_nodes, dtype=torch.float64, device=dev))
+
+    def integrate(self, out=None):
+        D, M, g = out if out is not None else self.alloc_outputs()
+        C.check(C.lib().mt_integrate(self.h, _ptr(D), _ptr(M), _ptr(g), _stream(self.stream)))
+        return D, M, g
+
+    def backward(self, W_D, W_M, w_g, out=None):
+        dev = self.device
+        if out is None:
+            gXs = torch.empty(3, self.n_slave_nodes, dtype=torch.float64, device=dev)
+            gXm = torch.empty(3, self.n_master_nodes, dtype=torch.float64, device=dev)
+        else:
+            gXs, gXm = out
+        W_D = W_D.contiguous()
+        W_M = W_M.contiguous()
+        w_g = w_g.contiguous()
+        C.check(C.lib().mt_backward(self.h, _ptr(W_D), _ptr(W_M), _ptr(w_g), _ptr(gXs), _ptr(gXm),
+                                    _stream(self.stream)))
+        return gXs, gXm
+
+    def stats(self):
+        st = C.mt_stats()
+        C.check(C.lib().mt_get_stats(self.h, ctypes.byref(st)))
+        return {"n_candidates": st.n_candidates, "n_pairs": st.n_pairs, "nverts_hist": list(st.nverts_hist),
+                "n_noconv": st.n_noconv, "n_overflow": st.n_overflow,
+                "n_degenerate_slave": st.n_degenerate_slave, "n_degenerate_master": st.n_degenerate_master,
+                "nnz_D": st.nnz_D, "nnz_M": st.nnz_M, "n_bins": list(st.n_bins), "bin_size": list(st.bin_size)}
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            C.lib().mt_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MortarFunction(torch.autograd.Function):
+    """(Xs (n_s, 3), Xm (n_m, 3)) -> (D_val, M_val, gap) on a fixed pair list
+    and CSR pattern; backward returns dL/dXs, dL/dXm from the hand-written
+    reverse-mode kernel."""
+
+    @staticmethod
+    def forward(ctx, Xs, Xm, iface):
+        iface.set_coordinates(Xs.detach(), Xm.detach())
+        D, M, g = iface.integrate()
+        ctx.iface = iface
+        return D, M, g
+
+    @staticmethod
+    def backward(ctx, gD, gM, gg):
+        iface = ctx.iface
+        dev = iface.device
+        gD = gD if gD is not None else torch.zeros(iface.nnz_D, dtype=torch.float64, device=dev)
+        gM = gM if gM is not None else torch.zeros(iface.nnz_M, dtype=torch.float64, device=dev)
+        gg = gg if gg is not None else torch.zeros(iface.n_slave_nodes, dtype=torch.float64, device=dev)
+        gXs, gXm = iface.backward(gD, gM, gg)
+        return gXs.t().contiguous(), gXm.t().contiguous(), None

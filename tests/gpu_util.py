@@ -1,0 +1,101 @@
+"""Helpers shared by the GPU parity tests: run the HIP path through the C ABI
+on a synthetic interface and compare with the oracle."""
+
+import numpy as np
+import scipy.sparse as sp
+import torch
+
+import oracle
+from synth.weights import keyed_normal, TAG_D, TAG_M, TAG_G
+
+TOL = 1e-10  # relative Frobenius error bar for D, M, gap and gradients
+
+
+def gpu_params(itf, dual=False, rule=7):
+    from paper_2202_03933_amd import default_params
+    return default_params(delta=float(itf.delta), dual=dual, rule=rule)
+
+
+def oracle_params(itf, dual=False, rule=7):
+    return oracle.params(delta=itf.delta, dual=dual, rule=rule)
+
+
+def gpu_run(itf, dual=False, rule=7, backward_seed=None):
+    """Full HIP path; returns numpy results."""
+    from paper_2202_03933_amd import MortarInterface
+    print(f"[gpu] {itf.name} dual={dual} rule={rule}", flush=True)
+    dev = torch.device("cuda", 0)
+    iface = MortarInterface(torch.from_numpy(itf.slave.X), torch.from_numpy(itf.slave.conn),
+                            torch.from_numpy(itf.master.X), torch.from_numpy(itf.master.conn),
+                            params=gpu_params(itf, dual, rule), device=dev)
+    iface.build_pairs()
+    cs, cm, cnv = (t.cpu().numpy() for t in iface.candidates())
+    ps, pm, pnv = (t.cpu().numpy() for t in iface.pairs())
+    iface.csr_pattern()
+    D, M, g = iface.integrate()
+    torch.cuda.synchronize()
+    ns, nmn = itf.slave.n_nodes, itf.master.n_nodes
+    Dc = sp.csr_matrix((D.cpu().numpy(), iface.D_col.cpu().numpy(), iface.D_rowptr.cpu().numpy()), shape=(ns, ns))
+    Mc = sp.csr_matrix((M.cpu().numpy(), iface.M_col.cpu().numpy(), iface.M_rowptr.cpu().numpy()), shape=(ns, nmn))
+    out = {"iface": iface, "cand_s": cs, "cand_m": cm, "cand_nv": cnv, "pair_s": ps, "pair_m": pm, "nverts": pnv,
+           "D": Dc, "M": Mc, "g": g.cpu().numpy(), "stats": iface.stats()}
+    if backward_seed is not None:
+        wD, wM, wg = csr_weights(Dc, Mc, ns, backward_seed)
+        gs, gm = iface.backward(torch.from_numpy(wD).to(dev), torch.from_numpy(wM).to(dev),
+                                torch.from_numpy(wg).to(dev))
+        torch.cuda.synchronize()
+        out["gXs"] = gs.cpu().numpy().T.copy()
+        out["gXm"] = gm.cpu().numpy().T.copy()
+    return out
+
+
+def csr_weights(D, M, n_slave_nodes, seed):
+    """Keyed N(0,1) weights on the nonzeros of D, M (CSR order) and on nodes."""
+    Dr = np.repeat(np.arange(D.shape[0]), np.diff(D.indptr))
+    Mr = np.repeat(np.arange(M.shape[0]), np.diff(M.indptr))
+    wD = keyed_normal(seed, TAG_D, Dr, D.indices)
+    wM = keyed_normal(seed, TAG_M, Mr, M.indices)
+    idx = np.arange(n_slave_nodes)
+    wg = keyed_normal(seed, TAG_G, idx, np.zeros_like(idx))
+    return wD, wM, wg
+
+
+def weight_fns(seed):
+    return (lambda r, c: keyed_normal(seed, TAG_D, r, c),
+            lambda r, c: keyed_normal(seed, TAG_M, r, c),
+            lambda r: keyed_normal(seed, TAG_G, r, np.zeros_like(r)))
+
+
+def rel_err(a, b):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    b = np.asarray(b, dtype=np.float64).ravel()
+    nb = np.linalg.norm(b)
+    d = np.linalg.norm(a - b)
+    if nb == 0.0:
+        return d
+    return d / nb
+
+
+def assert_same_pattern(A, B):
+    assert A.shape == B.shape
+    assert np.array_equal(A.indptr, B.indptr), "row pointers differ"
+    assert np.array_equal(A.indices, B.indices), "column indices differ"
+
+
+def assert_forward_parity(g, o):
+    """Bit-exact candidates / pairs / vertex counts / pattern; values within TOL."""
+    assert np.array_equal(g["cand_s"], o["cand_s"]) and np.array_equal(g["cand_m"], o["cand_m"]), "candidates"
+    assert np.array_equal(g["cand_nv"], o["cand_nverts"]), "clip vertex counts"
+    assert np.array_equal(g["pair_s"], o["pair_s"]) and np.array_equal(g["pair_m"], o["pair_m"]), "pairs"
+    assert np.array_equal(g["nverts"], o["nverts"])
+    assert_same_pattern(g["D"], o["D"])
+    assert_same_pattern(g["M"], o["M"])
+    eD = rel_err(g["D"].data, o["D"].data)
+    eM = rel_err(g["M"].data, o["M"].data)
+    eg = rel_err(g["g"], o["g"])
+    assert eD <= TOL and eM <= TOL, (eD, eM)
+    if np.linalg.norm(o["g"]) == 0.0:
+        assert np.abs(g["g"]).max() <= 1e-15 * max(1.0, np.abs(o["D"].data).max())
+    else:
+        assert eg <= TOL, eg
+    return eD, eM, eg

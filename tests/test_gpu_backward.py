@@ -1,0 +1,169 @@
+"""GPU parity of the backward pass (hand-written reverse mode) with the
+oracle's forward-mode dual-number gradients, central finite differences of
+the GPU's own forward pass, and the torch.autograd.Function wrapper."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.gpu_util import TOL, gpu_run, oracle_params, rel_err, weight_fns
+
+pytestmark = pytest.mark.gpu
+
+
+def oracle_grad(itf, prm, ps, pm, seed):
+    w = oracle.pair_weights(itf.slave, itf.master, ps, pm, *weight_fns(seed))
+    g24, st = oracle.pair_grads(itf.slave, itf.master, prm, ps, pm, w)
+    return oracle.scatter_grads(itf.slave, itf.master, ps, pm, g24)
+
+
+# The tied flat configuration is left out of gradient parity: there slave and
+# master boundary edges are exactly collinear, a clip crossing of two collinear
+# edges can sit anywhere on the common line, and the loss is not
+# differentiable (the oracle's chain rule through the crossing parameter
+# returns values of order 1e14 there).  It is checked by finite differences
+# on interior coordinates instead (test_finite_differences_flat_interior).
+@pytest.mark.parametrize("k,scale", [(2, 41), (1, 37), (2, 90), (1, 64)])
+def test_gradient_parity_reduced(k, scale):
+    itf = synth.interface_config(k, scale=scale)
+    prm = oracle_params(itf)
+    g = gpu_run(itf, backward_seed=3000)
+    o = oracle.evaluate(itf, prm)
+    assert np.array_equal(g["pair_s"], o["pair_s"]) and np.array_equal(g["pair_m"], o["pair_m"])
+    gs, gm = oracle_grad(itf, prm, o["pair_s"], o["pair_m"], 3000)
+    es, em = rel_err(g["gXs"], gs), rel_err(g["gXm"], gm)
+    print(f"grad rel err slave {es:.2e} master {em:.2e}")
+    assert es <= TOL and em <= TOL
+
+
+def test_gradient_parity_full_wavy_sampled():
+    itf = synth.interface_config(2)
+    prm = oracle_params(itf)
+    g = gpu_run(itf, backward_seed=3000)
+    o = oracle.evaluate(itf, prm)
+    assert np.array_equal(g["pair_s"], o["pair_s"]) and np.array_equal(g["pair_m"], o["pair_m"])
+    rng = np.random.default_rng(3002)
+    sn = rng.choice(itf.slave.n_nodes, 300, replace=False)
+    mn = rng.choice(itf.master.n_nodes, 300, replace=False)
+    ps, pm = o["pair_s"], o["pair_m"]
+    sel = np.isin(itf.slave.conn[ps], sn).any(1) | np.isin(itf.master.conn[pm], mn).any(1)
+    gs, gm = oracle_grad(itf, prm, ps[sel], pm[sel], 3000)
+    es, em = rel_err(g["gXs"][sn], gs[sn]), rel_err(g["gXm"][mn], gm[mn])
+    print(f"sampled grad rel err slave {es:.2e} master {em:.2e} over {sel.sum()} pairs")
+    assert es <= TOL and em <= TOL
+
+
+def _fd_check(itf, seed=3000, n_coords=200, interior=0.35):
+    from paper_2202_03933_amd import MortarInterface
+    from tests.gpu_util import csr_weights, gpu_params
+    dev = torch.device("cuda", 0)
+    Xs = torch.from_numpy(itf.slave.X).to(dev)
+    Xm = torch.from_numpy(itf.master.X).to(dev)
+    iface = MortarInterface(Xs, torch.from_numpy(itf.slave.conn), Xm, torch.from_numpy(itf.master.conn),
+                            params=gpu_params(itf), device=dev).setup()
+    import scipy.sparse as sp
+    D, M, gp = iface.integrate()
+    Dc = sp.csr_matrix((D.cpu().numpy(), iface.D_col.cpu().numpy(), iface.D_rowptr.cpu().numpy()),
+                       shape=(itf.slave.n_nodes,) * 2)
+    Mc = sp.csr_matrix((M.cpu().numpy(), iface.M_col.cpu().numpy(), iface.M_rowptr.cpu().numpy()),
+                       shape=(itf.slave.n_nodes, itf.master.n_nodes))
+    wD, wM, wg = (torch.from_numpy(a).to(dev) for a in csr_weights(Dc, Mc, itf.slave.n_nodes, seed))
+    gXs, gXm = iface.backward(wD, wM, wg)
+    gXs, gXm = gXs.cpu().numpy(), gXm.cpu().numpy()
+
+    def dL(side, node, d, h):
+        out = []
+        for sgn in (1.0, -1.0):
+            A, B = Xs.clone(), Xm.clone()
+            (A if side == 0 else B)[node, d] += sgn * h
+            iface.set_coordinates(A, B)
+            out.append(iface.integrate())
+        diff = sum(torch.dot(w, p - q).item() for w, p, q in zip((wD, wM, wg), out[0], out[1]))
+        return diff / (2 * h)
+
+    rng = np.random.default_rng(3001)
+    checked = refined = 0
+    while checked < n_coords:
+        side = int(rng.integers(0, 2))
+        mesh = itf.slave if side == 0 else itf.master
+        node = int(rng.integers(0, mesh.n_nodes))
+        d = int(rng.integers(0, 3))
+        if np.any(np.abs(mesh.X[node, :2] - 0.5) > interior):
+            continue
+        an = (gXs if side == 0 else gXm)[d, node]
+        fd = dL(side, node, d, 1e-6)
+        checked += 1
+        if abs(fd - an) > 1e-4 * abs(an) + 1e-10:
+            refined += 1
+            fd = dL(side, node, d, 1e-7)
+            assert abs(fd - an) <= 1e-4 * abs(an) + 1e-9, (side, node, d, fd, an)
+    iface.set_coordinates(Xs, Xm)
+    print(f"FD: {checked} coordinates, {refined} re-checked with h=1e-7")
+    assert refined <= 0.1 * checked
+
+
+def test_finite_differences_flat_interior():
+    _fd_check(synth.interface_config(0), n_coords=40, interior=0.3)
+
+
+def test_finite_differences_full_wavy():
+    _fd_check(synth.interface_config(2))
+
+
+def test_finite_differences_cylinder():
+    _fd_check(synth.interface_config(1), n_coords=60, interior=0.6)
+
+
+def test_autograd_function_matches_backward():
+    from paper_2202_03933_amd import MortarFunction, MortarInterface
+    from tests.gpu_util import gpu_params
+    itf = synth.interface_config(2, scale=64)
+    dev = torch.device("cuda", 0)
+    Xs = torch.from_numpy(itf.slave.X).to(dev).requires_grad_(True)
+    Xm = torch.from_numpy(itf.master.X).to(dev).requires_grad_(True)
+    iface = MortarInterface(Xs.detach(), torch.from_numpy(itf.slave.conn), Xm.detach(),
+                            torch.from_numpy(itf.master.conn), params=gpu_params(itf), device=dev).setup()
+    D, M, g = MortarFunction.apply(Xs, Xm, iface)
+    gen = torch.Generator(device="cpu").manual_seed(5)
+    wD = torch.randn(D.shape, generator=gen, dtype=torch.float64).to(dev)
+    wM = torch.randn(M.shape, generator=gen, dtype=torch.float64).to(dev)
+    wg = torch.randn(g.shape, generator=gen, dtype=torch.float64).to(dev)
+    L = (wD * D).sum() + (wM * M).sum() + (wg * g).sum()
+    L.backward()
+    gs, gm = iface.backward(wD, wM, wg)
+    assert torch.equal(Xs.grad, gs.t()) and torch.equal(Xm.grad, gm.t())
+
+
+def test_backward_bitwise_deterministic():
+    itf = synth.interface_config(1, scale=80)
+    a = gpu_run(itf, backward_seed=7)
+    b = gpu_run(itf, backward_seed=7)
+    assert np.array_equal(a["gXs"], b["gXs"]) and np.array_equal(a["gXm"], b["gXm"])
+
+
+def test_error_codes():
+    from paper_2202_03933_amd import MortarError, MortarInterface, default_params
+    from paper_2202_03933_amd import _capi as C
+    itf = synth.interface_config(0)
+    dev = torch.device("cuda", 0)
+    iface = MortarInterface(torch.from_numpy(itf.slave.X), torch.from_numpy(itf.slave.conn),
+                            torch.from_numpy(itf.master.X), torch.from_numpy(itf.master.conn),
+                            params=default_params(dual=True), device=dev)
+    with pytest.raises(MortarError) as e:
+        iface.integrate(out=(torch.empty(1, dtype=torch.float64, device=dev),) * 3)
+    assert e.value.code == C.MT_ESTATE
+    iface.setup()
+    z = torch.zeros(max(iface.nnz_M, 1), dtype=torch.float64, device=dev)
+    with pytest.raises(MortarError) as e:
+        iface.backward(z, z, z)
+    assert e.value.code == C.MT_EUNSUPPORTED
+    # connectivity out of range is reported, not read
+    bad = itf.slave.conn.copy()
+    bad[3, 2] = itf.slave.n_nodes + 5
+    iface2 = MortarInterface(torch.from_numpy(itf.slave.X), torch.from_numpy(bad), torch.from_numpy(itf.master.X),
+                             torch.from_numpy(itf.master.conn), device=dev)
+    with pytest.raises(MortarError) as e:
+        iface2.build_pairs()
+    assert e.value.code == C.MT_EINVAL
