@@ -3,8 +3,14 @@
 One step = the whole path on one synthetic interface with inputs resident in
 HBM: contact search and clipping (mt_build_pairs), CSR pattern
 (mt_csr_pattern), segment-based integration and assembly of D, M and the
-weighted gap (mt_integrate), and the backward pass for seeded upstream
-weights (mt_backward).  Prints one JSON line.
+weighted gap (mt_integrate), and the backward pass for keyed N(0,1) upstream
+weights (mt_backward).  Workload: the wavy interface z = 0.05 sin(2 pi x)
+sin(2 pi y), slave 1024x1024 / master 777x777 quad4, master nodes offset
+along the normal by U[-1e-3, 1e-3], delta = 1.25e-3.
+
+Prints one JSON line: value = pairs / (wall time of one step), plus the
+roofline of the dominant kernel (from the library's HIP-event phase timers
+over the timed steps) and the CPU oracle timed on a bounded sample.
 """
 
 import argparse
@@ -16,6 +22,49 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+HBM_PEAK_GBS = 8000.0
+
+
+def cpu_baseline(itf, n_slave_el_sample, seed=3000):
+    """Oracle (serial C++, one core) on a bounded sample of the workload: the
+    slave elements [0, n) against the whole master side -- search, clip,
+    integration, assembly and gradients.  Returns a dict; also counts the
+    oracle's flops per pair for the forward evaluation."""
+    import numpy as np
+
+    import oracle
+    import synth
+    from synth.weights import keyed_normal, TAG_D, TAG_M, TAG_G
+
+    sub = synth.Mesh(itf.slave.X, itf.slave.conn[:n_slave_el_sample].copy())
+    prm = oracle.params(delta=itf.delta)
+    oracle._lib()  # load outside the timed region
+    t0 = time.perf_counter()
+    cs, cm = oracle.search(sub, itf.master, itf.delta)
+    nv, blocks, _ = oracle.eval_candidates(sub, itf.master, prm, cs, cm, integrate=True)
+    keep = nv >= 3
+    ps, pm = cs[keep], cm[keep]
+    D, M, g = oracle.assemble(sub, itf.master, ps, pm, blocks[keep])
+    t_fwd = time.perf_counter() - t0
+    fD = lambda r, c: keyed_normal(seed, TAG_D, r, c)  # noqa: E731
+    fM = lambda r, c: keyed_normal(seed, TAG_M, r, c)  # noqa: E731
+    fg = lambda r: keyed_normal(seed, TAG_G, r, np.zeros_like(r))  # noqa: E731
+    w = oracle.pair_weights(sub, itf.master, ps, pm, fD, fM, fg)
+    g24, _ = oracle.pair_grads(sub, itf.master, prm, ps, pm, w)
+    oracle.scatter_grads(sub, itf.master, ps, pm, g24)
+    t_all = time.perf_counter() - t0
+    # algorithmic flops per pair of the forward evaluation (counted by the
+    # oracle's flop-counting scalar on every 16th pair of the sample)
+    f_clip, f_pair = oracle.count_flops(sub, itf.master, prm, ps[::16], pm[::16])
+    f_cand, _ = oracle.count_flops(sub, itf.master, prm, cs[::16], cm[::16])
+    return {"pairs": int(ps.size), "t_fwd": t_fwd, "t_all": t_all,
+            "flops_per_pair_fwd": f_pair / max(1, ps[::16].size),
+            "flops_per_candidate_clip": f_cand / max(1, cs[::16].size),
+            "sample": f"slave elements 0..{n_slave_el_sample - 1} of the workload (the first "
+                      f"{n_slave_el_sample // 1024} rows of the 1024x1024 slave grid) against the whole master "
+                      f"side: {ps.size} pairs; search + clip + integrate + assemble + gradients"}
+
 
 def main():
     ap = argparse.ArgumentParser()
@@ -23,10 +72,11 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=16384, help="slave elements in the CPU oracle sample")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the mortar path here runs on a single MI355X "
-              "(multi-GPU sharding is a design note, not a measured mode)", file=sys.stderr)
+        print("bench.py measures one GPU: this build runs the mortar path on a single MI355X; "
+              "sharding over several GPUs is a design note, not a measured mode", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -42,7 +92,7 @@ def main():
                             torch.from_numpy(itf.master.X), torch.from_numpy(itf.master.conn),
                             params=default_params(delta=itf.delta), device=dev)
     iface.setup()
-    n_pairs = iface.n_pairs
+    n_pairs, n_cand = iface.n_pairs, iface.n_cand
     Dr = np.repeat(np.arange(itf.slave.n_nodes), np.diff(iface.D_rowptr.cpu().numpy()))
     Mr = np.repeat(np.arange(itf.slave.n_nodes), np.diff(iface.M_rowptr.cpu().numpy()))
     wD = torch.from_numpy(keyed_normal(3000, TAG_D, Dr, iface.D_col.cpu().numpy())).to(dev)
@@ -53,40 +103,50 @@ def main():
     grads = (torch.empty(3, itf.slave.n_nodes, dtype=torch.float64, device=dev),
              torch.empty(3, itf.master.n_nodes, dtype=torch.float64, device=dev))
 
-    phases = ["search", "pattern", "forward", "backward"]
-    ev = {p: [] for p in phases}
-
-    def step(record):
-        s = torch.cuda.current_stream()
-        marks = []
-        if record:
-            e0 = torch.cuda.Event(enable_timing=True)
-            e0.record(s)
-            marks.append(e0)
-        for fn in (iface.build_pairs, iface.csr_pattern, lambda: iface.integrate(outs),
-                   lambda: iface.backward(wD, wM, wg, grads)):
-            fn()
-            if record:
-                e = torch.cuda.Event(enable_timing=True)
-                e.record(s)
-                marks.append(e)
-        return marks
+    def step():
+        iface.build_pairs()
+        iface.csr_pattern()
+        iface.integrate(outs)
+        iface.backward(wD, wM, wg, grads)
 
     for _ in range(args.warmup):
-        step(False)
+        step()
     torch.cuda.synchronize()
-    all_marks = []
+    iface.timings(reset=True)
+    iface.set_timing(True)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        all_marks.append(step(True))
+        step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    for marks in all_marks:
-        for i, p in enumerate(phases):
-            ev[p].append(marks[i].elapsed_time(marks[i + 1]))
+    iface.set_timing(False)
+    tim = iface.timings(reset=True)
+    assert iface.n_pairs == n_pairs and iface.n_cand == n_cand
     ms_step = (t1 - t0) * 1e3 / args.steps
-    assert iface.n_pairs == n_pairs
-    phase_ms = {p: float(np.mean(v)) for p, v in ev.items()}
+    per_step = {k: v[0] / args.steps for k, v in tim.items()}
+    per_launch = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in tim.items()}
+    fwd_ms = sum(per_step[k] for k in ("prep", "bin_sort", "cand", "clip", "compact", "pattern", "pair_fwd",
+                                        "assemble"))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(itf, args.cpu_sample)
+
+    # roofline of the dominant kernel: the forward pair-integration kernel is
+    # FP64-VALU bound; algorithmic flops per launch = oracle-counted flops per
+    # pair x pairs.
+    dominant = max(("pair_fwd", "pair_bwd", "clip"), key=lambda k: per_step[k])
+    flops_pair = cpu["flops_per_pair_fwd"] if cpu else None
+    roof = None
+    if flops_pair is not None:
+        launch_s = per_launch["pair_fwd"] * 1e-3
+        achieved = flops_pair * n_pairs / launch_s / 1e12
+        roof = {"bound": "alu", "kernel": "k_pair_fwd (segment integration, one launch per forward)",
+                "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
+                "flops_per_pair": flops_pair, "launch_ms": per_launch["pair_fwd"],
+                "dominant_kernel_by_time": dominant}
     out = {
         "metric": "mortar element pairs integrated/sec (D,M,gap) fwd and fwd+bwd, 1 MI355X",
         "value": n_pairs / (ms_step * 1e-3),
@@ -100,12 +160,17 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "wavy z=0.05 sin(2pi x) sin(2pi y), slave 1024x1024 / master 777x777 quad4, "
-                               "search + forward + backward",
-                   "n_pairs": n_pairs, "n_candidates": iface.n_cand, "nnz_D": iface.nnz_D, "nnz_M": iface.nnz_M},
-        "phase_ms": phase_ms,
-        "fwd_pairs_per_s": n_pairs / ((phase_ms["search"] + phase_ms["pattern"] + phase_ms["forward"]) * 1e-3),
+        "config": {"workload": "wavy z=0.05 sin(2 pi x) sin(2 pi y), slave 1024x1024 / master 777x777 quad4, "
+                               "normal offsets U[-1e-3,1e-3], delta 1.25e-3: search + forward + backward per step",
+                   "n_pairs": n_pairs, "n_candidates": n_cand, "nnz_D": iface.nnz_D, "nnz_M": iface.nnz_M},
+        "fwd_pairs_per_s": n_pairs / (fwd_ms * 1e-3),
+        "phase_ms_per_step": per_step,
+        "roofline": roof,
     }
+    if cpu:
+        out["cpu_baseline"] = {"value": cpu["pairs"] / cpu["t_all"], "unit": "pairs/s", "cores": 1,
+                               "kind": "oracle", "sample": cpu["sample"],
+                               "fwd_only_pairs_per_s": cpu["pairs"] / cpu["t_fwd"]}
     print(json.dumps(out))
 
 

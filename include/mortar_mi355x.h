@@ -197,6 +197,34 @@ int mt_backward(mt_ctx* ctx, const double* W_D, const double* W_M, const double*
  * stream of the last call. */
 int mt_get_stats(mt_ctx* ctx, mt_stats* st);
 
+/* ---- phase timers ------------------------------------------------------
+ * The per-process phase timings of the paper (contact evaluation, assembly,
+ * Sec. "Numerical experiments") as per-launch HIP events: when enabled, every
+ * phase below is bracketed by two events recorded on the call's stream. */
+#define MT_T_PREP 0        /* element bounding boxes and grid reductions */
+#define MT_T_BIN_SORT 1    /* master bin keys, radix sort, bin ranges */
+#define MT_T_CAND 2        /* candidate count, scan and fill */
+#define MT_T_CLIP 3        /* projection + clip of every candidate (one kernel) */
+#define MT_T_COMPACT 4     /* pair-list compaction */
+#define MT_T_PATTERN 5     /* CSR pattern and position maps */
+#define MT_T_PAIR_FWD 6    /* segment integration of all pairs (one kernel) */
+#define MT_T_ASSEMBLE 7    /* CSR assembly of D, M, gap (one kernel) */
+#define MT_T_PAIR_BWD 8    /* backward of all pairs (one kernel) */
+#define MT_T_GRAD_REDUCE 9 /* per-node gradient sums */
+#define MT_T_COUNT 10
+
+typedef struct mt_timings {
+  double ms[MT_T_COUNT];        /* summed event time per phase */
+  int64_t intervals[MT_T_COUNT]; /* number of timed intervals per phase */
+} mt_timings;
+
+/* Enable (1) or disable (0) the phase timers of a context. */
+int mt_set_timing(mt_ctx* ctx, int enable);
+
+/* Sum the recorded intervals into *t (host); reset != 0 clears them.
+ * Synchronises on the recorded events. */
+int mt_get_timings(mt_ctx* ctx, mt_timings* t, int reset);
+
 /* Message of the calling thread's last error ("" if none).  Host string
  * owned by the library, valid until the next call on this thread. */
 const char* mt_last_error(void);

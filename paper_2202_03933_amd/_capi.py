@@ -33,6 +33,15 @@ class mt_stats(ctypes.Structure):
                 ("n_bins", ctypes.c_int64 * 3), ("bin_size", ctypes.c_double * 3)]
 
 
+MT_T_NAMES = ["prep", "bin_sort", "cand", "clip", "compact", "pattern", "pair_fwd", "assemble", "pair_bwd",
+              "grad_reduce"]
+MT_T_COUNT = len(MT_T_NAMES)
+
+
+class mt_timings(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * MT_T_COUNT), ("intervals", ctypes.c_int64 * MT_T_COUNT)]
+
+
 class mt_batch_tuning(ctypes.Structure):
     _fields_ = [("bucket", ctypes.c_int32), ("block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
@@ -58,6 +67,8 @@ SIGNATURES = {
     "mt_backward": (_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "mt_get_stats": (_int, [_vp, ctypes.POINTER(mt_stats)]),
     "mt_last_error": (ctypes.c_char_p, []),
+    "mt_set_timing": (_int, [_vp, _int]),
+    "mt_get_timings": (_int, [_vp, ctypes.POINTER(mt_timings), _int]),
     "mt_batch_create": (_int, [ctypes.POINTER(_vp), _int]),
     "mt_batch_destroy": (_int, [_vp]),
     "mt_batch_add": (_int, [_vp, _vp, _pi32]),

@@ -47,6 +47,35 @@ int bits_for(int64_t n) {
   return b;
 }
 
+hipEvent_t take_event(mt_ctx* c) {
+  if (!c->event_pool.empty()) {
+    hipEvent_t e = c->event_pool.back();
+    c->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets one phase with two events on the stream when timing is enabled.
+struct PhaseTimer {
+  mt_ctx* c;
+  int phase;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  PhaseTimer(mt_ctx* c_, int ph, hipStream_t s) : c(c_), phase(ph), st(s) {
+    if (c->timing && (a = take_event(c)) != nullptr) (void)hipEventRecord(a, st);
+  }
+  ~PhaseTimer() {
+    if (!a) return;
+    hipEvent_t b = take_event(c);
+    if (!b) return;
+    (void)hipEventRecord(b, st);
+    c->intervals.push_back({phase, a, b});
+  }
+};
+
 }  // namespace
 
 void set_error(const std::string& msg) { g_err = msg; }
@@ -139,6 +168,11 @@ int mt_destroy(mt_ctx* c) {
                  &c->M_col, &c->posD, &c->posM, &c->blk, &c->gpair, &c->mp_keys, &c->mp_vals, &c->mp_off,
                  &c->scan_tmp, &c->sort_hist, &c->host_tmp};
   for (Buf* b : bufs) release(*b);
+  for (auto& iv : c->intervals) {
+    (void)hipEventDestroy(iv.a);
+    (void)hipEventDestroy(iv.b);
+  }
+  for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
   delete c;
   return MT_OK;
 }
@@ -204,10 +238,13 @@ int mt_build_pairs(mt_ctx* c, int64_t* n_cand_out, int64_t* n_pairs_out, void* s
   MT_HIP(ensure(c->box_s, sizeof(double) * 6 * (size_t)ns));
   MT_HIP(ensure(c->box_m, sizeof(double) * 6 * (size_t)nm));
   PrepReduce* red = c->reduce.as<PrepReduce>();
-  MT_HIP(launch_init_reduce(red, st));
-  MT_HIP(hipMemsetAsync(c->counters.p, 0, sizeof(Counters), st));
-  MT_HIP(launch_prep(S, true, c->box_s.as<double>(), red, st));
-  MT_HIP(launch_prep(M, false, c->box_m.as<double>(), red, st));
+  {
+    PhaseTimer t(c, MT_T_PREP, st);
+    MT_HIP(launch_init_reduce(red, st));
+    MT_HIP(hipMemsetAsync(c->counters.p, 0, sizeof(Counters), st));
+    MT_HIP(launch_prep(S, true, c->box_s.as<double>(), red, st));
+    MT_HIP(launch_prep(M, false, c->box_m.as<double>(), red, st));
+  }
   PrepReduce hr;
   MT_HIP(hipMemcpyAsync(&hr, red, sizeof(hr), hipMemcpyDeviceToHost, st));
   MT_HIP(hipStreamSynchronize(st));
@@ -220,22 +257,31 @@ int mt_build_pairs(mt_ctx* c, int64_t* n_cand_out, int64_t* n_pairs_out, void* s
   MT_HIP(ensure(c->vals, sizeof(uint32_t) * (size_t)nm));
   MT_HIP(ensure(c->keys_tmp, sizeof(uint32_t) * (size_t)nm));
   MT_HIP(ensure(c->vals_tmp, sizeof(uint32_t) * (size_t)nm));
-  MT_HIP(launch_master_keys(c->box_m.as<double>(), nm, g, c->keys.as<uint32_t>(), c->vals.as<uint32_t>(), st));
-  MT_HIP(radix_sort_pairs(c->keys.as<uint32_t>(), c->vals.as<uint32_t>(), c->keys_tmp.as<uint32_t>(),
-                          c->vals_tmp.as<uint32_t>(), nm, bits_for(g.ncells), c->sort_hist, c->scan_tmp, st));
   MT_HIP(ensure(c->cell_start, sizeof(int32_t) * (size_t)g.ncells));
   MT_HIP(ensure(c->cell_end, sizeof(int32_t) * (size_t)g.ncells));
-  MT_HIP(hipMemsetAsync(c->cell_start.p, 0, sizeof(int32_t) * (size_t)g.ncells, st));
-  MT_HIP(hipMemsetAsync(c->cell_end.p, 0, sizeof(int32_t) * (size_t)g.ncells, st));
-  MT_HIP(launch_cell_ranges(c->keys.as<uint32_t>(), nm, c->cell_start.as<int32_t>(), c->cell_end.as<int32_t>(), st));
+  MT_HIP(ensure(c->sort_hist, sizeof(int32_t) * (size_t)(2 * 256 * ((nm + 2047) / 2048 + 1) + 1)));
+  MT_HIP(ensure(c->scan_tmp, 1 << 20));
+  {
+    PhaseTimer t(c, MT_T_BIN_SORT, st);
+    MT_HIP(launch_master_keys(c->box_m.as<double>(), nm, g, c->keys.as<uint32_t>(), c->vals.as<uint32_t>(), st));
+    MT_HIP(radix_sort_pairs(c->keys.as<uint32_t>(), c->vals.as<uint32_t>(), c->keys_tmp.as<uint32_t>(),
+                            c->vals_tmp.as<uint32_t>(), nm, bits_for(g.ncells), c->sort_hist, c->scan_tmp, st));
+    MT_HIP(hipMemsetAsync(c->cell_start.p, 0, sizeof(int32_t) * (size_t)g.ncells, st));
+    MT_HIP(hipMemsetAsync(c->cell_end.p, 0, sizeof(int32_t) * (size_t)g.ncells, st));
+    MT_HIP(launch_cell_ranges(c->keys.as<uint32_t>(), nm, c->cell_start.as<int32_t>(), c->cell_end.as<int32_t>(),
+                              st));
+  }
 
   // candidates: count, scan, fill (sorted by master within each slave)
   MT_HIP(ensure(c->cand_cnt, sizeof(int32_t) * ((size_t)ns + 1)));
   MT_HIP(ensure(c->cand_off, sizeof(int32_t) * ((size_t)ns + 1)));
-  MT_HIP(launch_cand_count(c->box_s.as<double>(), ns, c->box_m.as<double>(), nm, c->vals.as<uint32_t>(),
-                           c->cell_start.as<int32_t>(), c->cell_end.as<int32_t>(), g, c->params.delta,
-                           c->cand_cnt.as<int32_t>(), st));
-  MT_HIP(scan_exclusive(c->cand_cnt.as<int32_t>(), c->cand_off.as<int32_t>(), ns, c->scan_tmp, st));
+  {
+    PhaseTimer t(c, MT_T_CAND, st);
+    MT_HIP(launch_cand_count(c->box_s.as<double>(), ns, c->box_m.as<double>(), nm, c->vals.as<uint32_t>(),
+                             c->cell_start.as<int32_t>(), c->cell_end.as<int32_t>(), g, c->params.delta,
+                             c->cand_cnt.as<int32_t>(), st));
+    MT_HIP(scan_exclusive(c->cand_cnt.as<int32_t>(), c->cand_off.as<int32_t>(), ns, c->scan_tmp, st));
+  }
   int32_t ncand32 = 0;
   MT_HIP(hipMemcpyAsync(&ncand32, c->cand_off.as<int32_t>() + ns, sizeof(int32_t), hipMemcpyDeviceToHost, st));
   MT_HIP(hipStreamSynchronize(st));
@@ -246,16 +292,25 @@ int mt_build_pairs(mt_ctx* c, int64_t* n_cand_out, int64_t* n_pairs_out, void* s
   MT_HIP(ensure(c->cand_nv, (size_t)n_cand));
   MT_HIP(ensure(c->cand_flag, sizeof(int32_t) * ((size_t)n_cand + 1)));
   MT_HIP(ensure(c->cand_scan, sizeof(int32_t) * ((size_t)n_cand + 1)));
-  MT_HIP(launch_cand_fill(c->box_s.as<double>(), ns, c->box_m.as<double>(), nm, c->vals.as<uint32_t>(),
-                          c->cell_start.as<int32_t>(), c->cell_end.as<int32_t>(), g, c->params.delta,
-                          c->cand_off.as<int32_t>(), c->cand_s.as<int32_t>(), c->cand_m.as<int32_t>(), st));
+  {
+    PhaseTimer t(c, MT_T_CAND, st);
+    MT_HIP(launch_cand_fill(c->box_s.as<double>(), ns, c->box_m.as<double>(), nm, c->vals.as<uint32_t>(),
+                            c->cell_start.as<int32_t>(), c->cell_end.as<int32_t>(), g, c->params.delta,
+                            c->cand_off.as<int32_t>(), c->cand_s.as<int32_t>(), c->cand_m.as<int32_t>(), st));
+  }
 
   // clip every candidate; compact the pairs
   const KParams kp = kparams(c->params);
   Counters* cnt = c->counters.as<Counters>();
-  MT_HIP(launch_clip_count(S, M, kp, c->cand_s.as<int32_t>(), c->cand_m.as<int32_t>(), n_cand,
-                           c->cand_nv.as<uint8_t>(), c->cand_flag.as<int32_t>(), cnt, st));
-  MT_HIP(scan_exclusive(c->cand_flag.as<int32_t>(), c->cand_scan.as<int32_t>(), n_cand, c->scan_tmp, st));
+  {
+    PhaseTimer t(c, MT_T_CLIP, st);
+    MT_HIP(launch_clip_count(S, M, kp, c->cand_s.as<int32_t>(), c->cand_m.as<int32_t>(), n_cand,
+                             c->cand_nv.as<uint8_t>(), c->cand_flag.as<int32_t>(), cnt, st));
+  }
+  {
+    PhaseTimer t(c, MT_T_COMPACT, st);
+    MT_HIP(scan_exclusive(c->cand_flag.as<int32_t>(), c->cand_scan.as<int32_t>(), n_cand, c->scan_tmp, st));
+  }
   int32_t np32 = 0;
   Counters hc;
   MT_HIP(hipMemcpyAsync(&np32, c->cand_scan.as<int32_t>() + n_cand, sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -266,10 +321,14 @@ int mt_build_pairs(mt_ctx* c, int64_t* n_cand_out, int64_t* n_pairs_out, void* s
   MT_HIP(ensure(c->pair_m, sizeof(int32_t) * (size_t)n_pairs));
   MT_HIP(ensure(c->pair_nv, (size_t)n_pairs));
   MT_HIP(ensure(c->pair_off, sizeof(int32_t) * ((size_t)ns + 1)));
-  MT_HIP(launch_compact(c->cand_s.as<int32_t>(), c->cand_m.as<int32_t>(), c->cand_nv.as<uint8_t>(),
-                        c->cand_scan.as<int32_t>(), n_cand, c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(),
-                        c->pair_nv.as<uint8_t>(), st));
-  MT_HIP(launch_pair_off(c->cand_off.as<int32_t>(), c->cand_scan.as<int32_t>(), ns, c->pair_off.as<int32_t>(), st));
+  {
+    PhaseTimer t(c, MT_T_COMPACT, st);
+    MT_HIP(launch_compact(c->cand_s.as<int32_t>(), c->cand_m.as<int32_t>(), c->cand_nv.as<uint8_t>(),
+                          c->cand_scan.as<int32_t>(), n_cand, c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(),
+                          c->pair_nv.as<uint8_t>(), st));
+    MT_HIP(launch_pair_off(c->cand_off.as<int32_t>(), c->cand_scan.as<int32_t>(), ns, c->pair_off.as<int32_t>(),
+                           st));
+  }
   c->n_cand = n_cand;
   c->n_pairs = n_pairs;
   c->have_pairs = true;
@@ -332,6 +391,7 @@ int mt_csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, void* stream) {
   const DeviceMesh& S = c->side[0];
   const DeviceMesh& M = c->side[1];
   const int32_t n = S.n_nodes;
+  PhaseTimer timer(c, MT_T_PATTERN, st);
   int rc = build_incidence(c, S, c->inc_cnt, c->inc_off, c->inc_cur, c->inc_list, st);
   if (rc) return rc;
   MT_HIP(ensure(c->rawD_cnt, sizeof(int32_t) * ((size_t)n + 1)));
@@ -408,9 +468,12 @@ int mt_integrate(mt_ctx* c, double* D_val, double* M_val, double* gap, void* str
   const DeviceMesh& M = c->side[1];
   const int64_t np = c->n_pairs;
   MT_HIP(ensure(c->blk, sizeof(double) * 36 * (size_t)std::max<int64_t>(np, 1)));
-  MT_HIP(launch_pair_fwd(S, M, kparams(c->params),
-                         c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), np, c->blk.as<double>(), np,
-                         c->counters.as<Counters>(), st));
+  {
+    PhaseTimer t(c, MT_T_PAIR_FWD, st);
+    MT_HIP(launch_pair_fwd(S, M, kparams(c->params), c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), np,
+                           c->blk.as<double>(), np, c->counters.as<Counters>(), st));
+  }
+  PhaseTimer t(c, MT_T_ASSEMBLE, st);
   MT_HIP(launch_assemble(c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(), S.n_nodes, c->pair_off.as<int32_t>(),
                          c->D_rowptr.as<int32_t>(), c->M_rowptr.as<int32_t>(), c->posD.as<int32_t>(), S.n_el,
                          c->posM.as<int32_t>(), c->blk.as<double>(), np, D_val, M_val, gap, st));
@@ -467,14 +530,47 @@ int mt_backward(mt_ctx* c, const double* W_D, const double* W_M, const double* w
   }
   const int64_t np = c->n_pairs;
   MT_HIP(ensure(c->gpair, sizeof(double) * 24 * (size_t)std::max<int64_t>(np, 1)));
-  MT_HIP(launch_pair_bwd(S, M, kparams(c->params), c->pair_s.as<int32_t>(),
-                         c->pair_m.as<int32_t>(), np, c->posD.as<int32_t>(), S.n_el, c->posM.as<int32_t>(), W_D, W_M,
-                         w_g, c->gpair.as<double>(), np, c->counters.as<Counters>(), st));
+  {
+    PhaseTimer t(c, MT_T_PAIR_BWD, st);
+    MT_HIP(launch_pair_bwd(S, M, kparams(c->params), c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), np,
+                           c->posD.as<int32_t>(), S.n_el, c->posM.as<int32_t>(), W_D, W_M, w_g,
+                           c->gpair.as<double>(), np, c->counters.as<Counters>(), st));
+  }
+  PhaseTimer t(c, MT_T_GRAD_REDUCE, st);
   MT_HIP(launch_grad_slave(c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(), S.n_nodes, c->pair_off.as<int32_t>(),
                            c->gpair.as<double>(), np, gXs, st));
   const int32_t* mo = c->mp_off.as<int32_t>();
   MT_HIP(launch_grad_master(c->minc_off.as<int32_t>(), c->minc_list.as<int32_t>(), M.n_nodes, mo, mo + M.n_el,
                             c->mp_vals.as<uint32_t>(), c->gpair.as<double>(), np, gXm, st));
+  return MT_OK;
+}
+
+int mt_set_timing(mt_ctx* c, int enable) {
+  if (!c) return fail(MT_EINVAL, "mt_set_timing: null ctx");
+  c->timing = enable != 0;
+  return MT_OK;
+}
+
+int mt_get_timings(mt_ctx* c, mt_timings* t, int reset) {
+  if (!c || !t) return fail(MT_EINVAL, "mt_get_timings: null");
+  DeviceScope ds(c->device);
+  for (auto& iv : c->intervals) {
+    MT_HIP(hipEventSynchronize(iv.b));
+    float ms = 0.f;
+    MT_HIP(hipEventElapsedTime(&ms, iv.a, iv.b));
+    c->t_ms[iv.phase] += ms;
+    c->t_n[iv.phase] += 1;
+    c->event_pool.push_back(iv.a);
+    c->event_pool.push_back(iv.b);
+  }
+  c->intervals.clear();
+  for (int i = 0; i < MT_T_COUNT; ++i) {
+    t->ms[i] = c->t_ms[i];
+    t->intervals[i] = c->t_n[i];
+  }
+  if (reset) {
+    for (int i = 0; i < MT_T_COUNT; ++i) { c->t_ms[i] = 0.0; c->t_n[i] = 0; }
+  }
   return MT_OK;
 }
 

@@ -7,6 +7,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "mortar_mi355x.h"
 
@@ -74,6 +75,13 @@ struct KParams {
 
 struct mt_ctx {
   int device = 0;
+  // phase timers
+  bool timing = false;
+  struct Interval { int phase; hipEvent_t a, b; };
+  std::vector<Interval> intervals;
+  std::vector<hipEvent_t> event_pool;
+  double t_ms[MT_T_COUNT] = {};
+  int64_t t_n[MT_T_COUNT] = {};
   mt_params params{};
   mt::DeviceMesh side[2];
   hipStream_t last_stream = nullptr;

@@ -155,6 +155,15 @@ class MortarInterface:
                 "n_degenerate_slave": st.n_degenerate_slave, "n_degenerate_master": st.n_degenerate_master,
                 "nnz_D": st.nnz_D, "nnz_M": st.nnz_M, "n_bins": list(st.n_bins), "bin_size": list(st.bin_size)}
 
+    def set_timing(self, enable=True):
+        C.check(C.lib().mt_set_timing(self.h, 1 if enable else 0))
+
+    def timings(self, reset=False):
+        """{phase: (summed ms, intervals)} of the library's phase timers."""
+        t = C.mt_timings()
+        C.check(C.lib().mt_get_timings(self.h, ctypes.byref(t), 1 if reset else 0))
+        return {n: (t.ms[i], t.intervals[i]) for i, n in enumerate(C.MT_T_NAMES)}
+
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:
             C.lib().mt_destroy(self.h)
