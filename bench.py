@@ -66,12 +66,74 @@ def cpu_baseline(itf, n_slave_el_sample, seed=3000):
                       f"side: {ps.size} pairs; search + clip + integrate + assemble + gradients"}
 
 
+def bench_batched(reps=5):
+    """64 interfaces of uneven size (log-uniform 16^2..512^2 slave quads,
+    master/slave resolution ratio U[0.7, 1.3], flat / cylinder / wavy):
+    one persistent graph-launched forward (and backward) over all of them
+    versus one mt_integrate (mt_backward) call per interface on one stream."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2202_03933_amd import MortarBatch, MortarInterface, default_params
+    from synth.weights import keyed_normal, TAG_D, TAG_M, TAG_G
+
+    dev = torch.device("cuda", 0)
+    ifaces, W = [], []
+    for itf in synth.batched_instances(64):
+        it = MortarInterface(torch.from_numpy(itf.slave.X), torch.from_numpy(itf.slave.conn),
+                             torch.from_numpy(itf.master.X), torch.from_numpy(itf.master.conn),
+                             params=default_params(delta=itf.delta), device=dev).setup()
+        ns = it.n_slave_nodes
+        Dr = np.repeat(np.arange(ns), np.diff(it.D_rowptr.cpu().numpy()))
+        Mr = np.repeat(np.arange(ns), np.diff(it.M_rowptr.cpu().numpy()))
+        W.append((torch.from_numpy(keyed_normal(3000, TAG_D, Dr, it.D_col.cpu().numpy())).to(dev),
+                  torch.from_numpy(keyed_normal(3000, TAG_M, Mr, it.M_col.cpu().numpy())).to(dev),
+                  torch.from_numpy(keyed_normal(3000, TAG_G, np.arange(ns), np.zeros(ns, np.int64))).to(dev)))
+        ifaces.append(it)
+    pairs = sum(it.n_pairs for it in ifaces)
+    b = MortarBatch(ifaces)
+    tuning = b.autotune()
+    outs = b.alloc_outputs()
+    gouts = [(torch.empty(3, it.n_slave_nodes, dtype=torch.float64, device=dev),
+              torch.empty(3, it.n_master_nodes, dtype=torch.float64, device=dev)) for it in ifaces]
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / reps
+
+    def per_fwd():
+        for it, o in zip(ifaces, outs):
+            it.integrate(o)
+
+    def per_bwd():
+        for it, w, g in zip(ifaces, W, gouts):
+            it.backward(*w, out=g)
+
+    res = {"n_interfaces": len(ifaces), "pairs": pairs, "tuning": tuning,
+           "fwd_ms_batched_graph": timed(lambda: b.forward(outs, use_graph=True)),
+           "fwd_ms_per_interface": timed(per_fwd),
+           "bwd_ms_batched_graph": timed(lambda: b.backward(W, outs=gouts, use_graph=True)),
+           "bwd_ms_per_interface": timed(per_bwd)}
+    for k in ("fwd", "bwd"):
+        res[f"{k}_pairs_per_s_batched"] = pairs / (res[f"{k}_ms_batched_graph"] * 1e-3)
+        res[f"{k}_pairs_per_s_per_interface"] = pairs / (res[f"{k}_ms_per_interface"] * 1e-3)
+        res[f"{k}_speedup"] = res[f"{k}_ms_per_interface"] / res[f"{k}_ms_batched_graph"]
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=16384, help="slave elements in the CPU oracle sample")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -129,6 +191,7 @@ def main():
     fwd_ms = sum(per_step[k] for k in ("prep", "bin_sort", "cand", "clip", "compact", "pattern", "pair_fwd",
                                         "assemble"))
 
+    batched = None if args.no_batched else bench_batched()
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(itf, args.cpu_sample)
@@ -166,6 +229,7 @@ def main():
         "fwd_pairs_per_s": n_pairs / (fwd_ms * 1e-3),
         "phase_ms_per_step": per_step,
         "roofline": roof,
+        "batched_64_interfaces": batched,
     }
     if cpu:
         out["cpu_baseline"] = {"value": cpu["pairs"] / cpu["t_all"], "unit": "pairs/s", "cores": 1,

@@ -487,7 +487,10 @@ __global__ void k_iota(uint32_t* v, int64_t n) {
 }
 }  // namespace
 
-static int build_master_index(mt_ctx* c, hipStream_t st) {
+}  // extern "C"
+
+int mt::ensure_master_index(mt_ctx* c, hipStream_t st) {
+  if (c->have_master_index) return MT_OK;
   const DeviceMesh& M = c->side[1];
   int rc = build_incidence(c, M, c->minc_cnt, c->minc_off, c->minc_cur, c->minc_list, st);
   if (rc) return rc;
@@ -511,6 +514,8 @@ static int build_master_index(mt_ctx* c, hipStream_t st) {
   return MT_OK;
 }
 
+extern "C" {
+
 int mt_backward(mt_ctx* c, const double* W_D, const double* W_M, const double* w_g, double* gXs, double* gXm,
                 void* stream) {
   if (!c) return fail(MT_EINVAL, "mt_backward: null ctx");
@@ -524,8 +529,8 @@ int mt_backward(mt_ctx* c, const double* W_D, const double* W_M, const double* w
   DeviceScope ds(c->device);
   hipStream_t st = (hipStream_t)stream;
   c->last_stream = st;
-  if (!c->have_master_index) {
-    int rc = build_master_index(c, st);
+  {
+    int rc = ensure_master_index(c, st);
     if (rc) return rc;
   }
   const int64_t np = c->n_pairs;

@@ -5,6 +5,7 @@
 // contributions in a fixed order (incident elements ascending, then pairs in
 // (slave, master) order), so results are bitwise reproducible.
 #include "mt_internal.h"
+#include "mt_rows.h"
 
 namespace mt {
 
@@ -180,26 +181,8 @@ __global__ __launch_bounds__(BS) void k_assemble(const int32_t* __restrict__ inc
                                                   double* __restrict__ M_val, double* __restrict__ gap) {
   const int a = blockIdx.x * BS + threadIdx.x;
   if (a >= n) return;
-  for (int i = D_rowptr[a]; i < D_rowptr[a + 1]; ++i) D_val[i] = 0.0;
-  for (int i = M_rowptr[a]; i < M_rowptr[a + 1]; ++i) M_val[i] = 0.0;
-  double g = 0.0;
-  for (int i = inc_off[a]; i < inc_off[a + 1]; ++i) {
-    const int e = inc_list[i] >> 2, j = inc_list[i] & 3;
-    const int p0 = pair_off[e], p1 = pair_off[e + 1];
-    if (p0 == p1) continue;
-    int pd[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) pd[k] = posD[(int64_t)(j * 4 + k) * n_s_el + e];
-    for (int p = p0; p < p1; ++p) {
-#pragma unroll
-      for (int k = 0; k < 4; ++k) D_val[pd[k]] += blk[(int64_t)(j * 4 + k) * stride + p];
-#pragma unroll
-      for (int l = 0; l < 4; ++l)
-        M_val[posM[(int64_t)(j * 4 + l) * stride + p]] += blk[(int64_t)(16 + j * 4 + l) * stride + p];
-      g += blk[(int64_t)(32 + j) * stride + p];
-    }
-  }
-  gap[a] = g;
+  assemble_row(a, inc_off, inc_list, pair_off, D_rowptr, M_rowptr, posD, n_s_el, posM, blk, stride, D_val, M_val,
+               gap);
 }
 
 __global__ __launch_bounds__(BS) void k_grad_slave(const int32_t* __restrict__ inc_off,
@@ -209,18 +192,7 @@ __global__ __launch_bounds__(BS) void k_grad_slave(const int32_t* __restrict__ i
                                                     double* __restrict__ gX) {
   const int a = blockIdx.x * BS + threadIdx.x;
   if (a >= n) return;
-  double g0 = 0.0, g1 = 0.0, g2 = 0.0;
-  for (int i = inc_off[a]; i < inc_off[a + 1]; ++i) {
-    const int e = inc_list[i] >> 2, j = inc_list[i] & 3;
-    for (int p = pair_off[e]; p < pair_off[e + 1]; ++p) {
-      g0 += gpair[(int64_t)(3 * j + 0) * stride + p];
-      g1 += gpair[(int64_t)(3 * j + 1) * stride + p];
-      g2 += gpair[(int64_t)(3 * j + 2) * stride + p];
-    }
-  }
-  gX[a] = g0;
-  gX[(int64_t)n + a] = g1;
-  gX[2 * (int64_t)n + a] = g2;
+  grad_slave_row(a, n, inc_off, inc_list, pair_off, gpair, stride, gX);
 }
 
 __global__ __launch_bounds__(BS) void k_mpair_ranges(const uint32_t* __restrict__ keys, int64_t np,
@@ -241,19 +213,7 @@ __global__ __launch_bounds__(BS) void k_grad_master(const int32_t* __restrict__ 
                                                      double* __restrict__ gX) {
   const int b = blockIdx.x * BS + threadIdx.x;
   if (b >= n) return;
-  double g0 = 0.0, g1 = 0.0, g2 = 0.0;
-  for (int i = inc_off[b]; i < inc_off[b + 1]; ++i) {
-    const int m = inc_list[i] >> 2, l = inc_list[i] & 3;
-    for (int k = mstart[m]; k < mend[m]; ++k) {
-      const int64_t p = mpairs[k];
-      g0 += gpair[(int64_t)(12 + 3 * l + 0) * stride + p];
-      g1 += gpair[(int64_t)(12 + 3 * l + 1) * stride + p];
-      g2 += gpair[(int64_t)(12 + 3 * l + 2) * stride + p];
-    }
-  }
-  gX[b] = g0;
-  gX[(int64_t)n + b] = g1;
-  gX[2 * (int64_t)n + b] = g2;
+  grad_master_row(b, n, inc_off, inc_list, mstart, mend, mpairs, gpair, stride, gX);
 }
 
 inline unsigned grid_of(int64_t n) { return (unsigned)((n + BS - 1) / BS); }

@@ -1,15 +1,597 @@
-// Batched evaluation of many interfaces: placeholder entry points.
-#include "mt_internal.h"
+// Batched evaluation of many independent interfaces with one persistent
+// launch per phase (the single-GPU analogue of the paper's independent
+// interface load balancing, Sec. "Interface domain decompositions for
+// dynamically evolving interfaces": work is distributed over all compute
+// units regardless of which interface it belongs to).
+//
+// Work items are buckets of consecutive pairs of one instance.  They are
+// split into 8 contiguous queues, one per XCD; a block starts on the queue of
+// its own XCD (blocks are dispatched round-robin over XCDs, so block b runs
+// on XCD b % 8) and then takes items from the other queues, so each XCD's L2
+// first sees one contiguous part of the meshes.  Queue counters are reset by
+// a fill kernel, so the launch sequence can be captured in a HIP graph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "mt_pair_eval.h"
+#include "mt_rows.h"
+
+namespace mt {
+
+constexpr int NQUEUE = 8;
+constexpr int ROWS_PER_ITEM = 256;
+
+struct BatchInst {
+  MeshPtrs S, M;
+  int32_t n_s_el, n_s_nodes, n_m_el, n_m_nodes;
+  const int32_t* pair_s;
+  const int32_t* pair_m;
+  int64_t n_pairs;
+  const int32_t* pair_off;
+  const int32_t* inc_off;
+  const int32_t* inc_list;
+  const int32_t* D_rowptr;
+  const int32_t* M_rowptr;
+  const int32_t* posD;
+  const int32_t* posM;
+  const int32_t* minc_off;
+  const int32_t* minc_list;
+  const int32_t* mstart;
+  const int32_t* mend;
+  const uint32_t* mpairs;
+  double* blk;
+  double* gpair;
+  // per call
+  double* D_val;
+  double* M_val;
+  double* gap;
+  const double* W_D;
+  const double* W_M;
+  const double* w_g;
+  double* gXs;
+  double* gXm;
+  KParams kp;
+};
+
+struct WorkItem {
+  int32_t inst, begin, end, pad;
+};
+
+namespace {
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+  return x;
+}
+
+__global__ void k_reset_queues(int32_t* qnext) {
+  if (threadIdx.x < NQUEUE) qnext[threadIdx.x] = 0;
+}
+
+// Takes the next work item for this block: its own XCD's queue first, then
+// the others in order; returns -1 when every queue is drained.  Uniform
+// across the block.
+__device__ __forceinline__ int next_item(const int32_t* __restrict__ qbeg, int32_t* qnext, int& qi, int* s_item) {
+  const int home = blockIdx.x % NQUEUE;
+  while (qi < NQUEUE) {
+    const int q = (home + qi) % NQUEUE;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const int k = atomicAdd(&qnext[q], 1);
+      *s_item = qbeg[q] + k < qbeg[q + 1] ? qbeg[q] + k : -1;
+    }
+    __syncthreads();
+    const int it = *s_item;
+    if (it >= 0) return it;
+    ++qi;
+  }
+  return -1;
+}
+
+template <int BSZ, int NQ, bool DUAL>
+__global__ __launch_bounds__(BSZ) void k_batch_fwd(const BatchInst* __restrict__ inst,
+                                                    const WorkItem* __restrict__ items,
+                                                    const int32_t* __restrict__ qbeg, int32_t* qnext, Counters* cnt) {
+  __shared__ double su[2 * CAP * BSZ], sv[2 * CAP * BSZ];
+  __shared__ int s_item;
+  unsigned noconv = 0;
+  int qi = 0;
+  LdsPoly<false> P{su + threadIdx.x, sv + threadIdx.x, nullptr, nullptr, BSZ};
+  for (int it = next_item(qbeg, qnext, qi, &s_item); it >= 0; it = next_item(qbeg, qnext, qi, &s_item)) {
+    const WorkItem w = items[it];
+    const BatchInst& I = inst[w.inst];
+    for (int64_t p = w.begin + (int)threadIdx.x; p < w.end; p += BSZ) {
+      double Xs[4][3], Xm[4][3];
+      load_nodes(I.S.x, I.S.y, I.S.z, load_conn(I.S.conn, I.pair_s[p]), Xs);
+      load_nodes(I.M.x, I.M.y, I.M.z, load_conn(I.M.conn, I.pair_m[p]), Xm);
+      double D[16], Mv[16], g[4];
+      pair_forward<NQ, DUAL, false>(Xs, Xm, I.kp, P, D, Mv, g, noconv);
+      const int64_t st = I.n_pairs;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) I.blk[(int64_t)k * st + p] = D[k];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) I.blk[(int64_t)(16 + k) * st + p] = Mv[k];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) I.blk[(int64_t)(32 + k) * st + p] = g[k];
+    }
+  }
+  const unsigned long long nc = wave_sum_u64(noconv);
+  if ((threadIdx.x & 63) == 0 && nc) atomicAdd(&cnt->noconv, nc);
+}
+
+template <int BSZ, int NQ>
+__global__ __launch_bounds__(BSZ) void k_batch_bwd(const BatchInst* __restrict__ inst,
+                                                    const WorkItem* __restrict__ items,
+                                                    const int32_t* __restrict__ qbeg, int32_t* qnext, Counters* cnt) {
+  __shared__ double su[2 * CAP * BSZ], sv[2 * CAP * BSZ];
+  __shared__ uint8_t sl[2 * CAP * BSZ], se[2 * CAP * BSZ];
+  __shared__ int s_item;
+  unsigned noconv = 0;
+  int qi = 0;
+  LdsPoly<true> P{su + threadIdx.x, sv + threadIdx.x, sl + threadIdx.x, se + threadIdx.x, BSZ};
+  for (int it = next_item(qbeg, qnext, qi, &s_item); it >= 0; it = next_item(qbeg, qnext, qi, &s_item)) {
+    const WorkItem w = items[it];
+    const BatchInst& I = inst[w.inst];
+    const int64_t st = I.n_pairs;
+    for (int64_t p = w.begin + (int)threadIdx.x; p < w.end; p += BSZ) {
+      const int s = I.pair_s[p];
+      const int4 csn = load_conn(I.S.conn, s);
+      double Xs[4][3], Xm[4][3];
+      load_nodes(I.S.x, I.S.y, I.S.z, csn, Xs);
+      load_nodes(I.M.x, I.M.y, I.M.z, load_conn(I.M.conn, I.pair_m[p]), Xm);
+      double WD[16], WM[16], wg[4];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) WD[k] = I.W_D[I.posD[(int64_t)k * I.n_s_el + s]];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) WM[k] = I.W_M[I.posM[(int64_t)k * st + p]];
+      wg[0] = I.w_g[csn.x];
+      wg[1] = I.w_g[csn.y];
+      wg[2] = I.w_g[csn.z];
+      wg[3] = I.w_g[csn.w];
+      double Xsb[4][3], Xmb[4][3];
+      pair_backward<NQ>(Xs, Xm, I.kp, P, WD, WM, wg, Xsb, Xmb, noconv);
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          I.gpair[(int64_t)(3 * k + d) * st + p] = Xsb[k][d];
+          I.gpair[(int64_t)(12 + 3 * k + d) * st + p] = Xmb[k][d];
+        }
+    }
+  }
+  const unsigned long long nc = wave_sum_u64(noconv);
+  if ((threadIdx.x & 63) == 0 && nc) atomicAdd(&cnt->noconv, nc);
+}
+
+// Row phases: one block per item of ROWS_PER_ITEM rows of one instance.
+__global__ __launch_bounds__(ROWS_PER_ITEM) void k_batch_assemble(const BatchInst* __restrict__ inst,
+                                                                   const WorkItem* __restrict__ items) {
+  const WorkItem w = items[blockIdx.x];
+  const int a = w.begin + threadIdx.x;
+  if (a >= w.end) return;
+  const BatchInst& I = inst[w.inst];
+  assemble_row(a, I.inc_off, I.inc_list, I.pair_off, I.D_rowptr, I.M_rowptr, I.posD, I.n_s_el, I.posM, I.blk,
+               I.n_pairs, I.D_val, I.M_val, I.gap);
+}
+
+__global__ __launch_bounds__(ROWS_PER_ITEM) void k_batch_grad_rows(const BatchInst* __restrict__ inst,
+                                                                    const WorkItem* __restrict__ items) {
+  const WorkItem w = items[blockIdx.x];
+  const int a = w.begin + threadIdx.x;
+  if (a >= w.end) return;
+  const BatchInst& I = inst[w.inst];
+  if (w.pad == 0)
+    grad_slave_row(a, I.n_s_nodes, I.inc_off, I.inc_list, I.pair_off, I.gpair, I.n_pairs, I.gXs);
+  else
+    grad_master_row(a, I.n_m_nodes, I.minc_off, I.minc_list, I.mstart, I.mend, I.mpairs, I.gpair, I.n_pairs, I.gXm);
+}
+
+using FwdFn = void (*)(const BatchInst*, const WorkItem*, const int32_t*, int32_t*, Counters*);
+using BwdFn = void (*)(const BatchInst*, const WorkItem*, const int32_t*, int32_t*, Counters*);
+
+template <int BSZ>
+FwdFn fwd_kernel(int nq, bool dual) {
+  if (nq == 3) return dual ? k_batch_fwd<BSZ, 3, true> : k_batch_fwd<BSZ, 3, false>;
+  return dual ? k_batch_fwd<BSZ, 7, true> : k_batch_fwd<BSZ, 7, false>;
+}
+template <int BSZ>
+BwdFn bwd_kernel(int nq) {
+  return nq == 3 ? k_batch_bwd<BSZ, 3> : k_batch_bwd<BSZ, 7>;
+}
+
+FwdFn pick_fwd(int bsz, int nq, bool dual) {
+  if (bsz == 256) return fwd_kernel<256>(nq, dual);
+  if (bsz == 128) return fwd_kernel<128>(nq, dual);
+  return fwd_kernel<64>(nq, dual);
+}
+BwdFn pick_bwd(int bsz, int nq) {
+  if (bsz == 256) return bwd_kernel<256>(nq);
+  if (bsz == 128) return bwd_kernel<128>(nq);
+  return bwd_kernel<64>(nq);
+}
+
+// LDS of one block (bytes): forward uses 2 x CAP vertices x 16 B per lane,
+// backward adds 2 x CAP label bytes x 2 per lane.
+int max_blocks_per_cu(int bsz, bool backward) {
+  const int per_block = bsz * 2 * CAP * (16 + (backward ? 2 : 0)) + 64;
+  return std::max(1, (160 * 1024) / per_block);
+}
+
+}  // namespace
+}  // namespace mt
+
+struct mt_batch {
+  int device = 0;
+  int num_cu = 256;
+  std::vector<mt_ctx*> ctxs;
+  bool built = false;
+  mt_batch_tuning tune{};
+  int nq = 7;
+  bool dual = false;
+  std::vector<mt::BatchInst> h_inst;
+  mt::BatchInst* pinned = nullptr;
+  mt::Buf d_inst, d_pitems, d_qbeg, d_qnext, d_ritems_s, d_ritems_sm, counters;
+  int n_pitems = 0, n_ritems_s = 0, n_ritems_sm = 0;
+  hipGraphExec_t g_fwd = nullptr, g_bwd = nullptr;
+  hipStream_t g_fwd_stream = nullptr, g_bwd_stream = nullptr;
+};
+
+using namespace mt;
+
+namespace {
+
+int bfail(int code, const char* msg) {
+  set_error(msg);
+  return code;
+}
+
+#define B_HIP(call)                                              \
+  do {                                                           \
+    hipError_t e_ = (call);                                      \
+    if (e_ != hipSuccess) {                                      \
+      set_error(std::string(#call) + ": " + hipGetErrorString(e_)); \
+      return MT_EHIP;                                            \
+    }                                                            \
+  } while (0)
+
+void drop_graphs(mt_batch* b) {
+  if (b->g_fwd) (void)hipGraphExecDestroy(b->g_fwd);
+  if (b->g_bwd) (void)hipGraphExecDestroy(b->g_bwd);
+  b->g_fwd = b->g_bwd = nullptr;
+}
+
+// Pair work items (buckets of `bucket` consecutive pairs of one instance),
+// split into NQUEUE contiguous queues of about equal pair counts.
+int build_items(mt_batch* b, hipStream_t st) {
+  const int bucket = std::max(1, b->tune.bucket);
+  std::vector<WorkItem> items;
+  int64_t total = 0;
+  for (size_t i = 0; i < b->ctxs.size(); ++i) {
+    const int64_t np = b->ctxs[i]->n_pairs;
+    for (int64_t p = 0; p < np; p += bucket)
+      items.push_back({(int32_t)i, (int32_t)p, (int32_t)std::min<int64_t>(np, p + bucket), 0});
+    total += np;
+  }
+  std::vector<int32_t> qbeg(NQUEUE + 1, (int32_t)items.size());
+  qbeg[0] = 0;
+  int64_t acc = 0;
+  int q = 1;
+  for (size_t k = 0; k < items.size() && q < NQUEUE; ++k) {
+    while (q < NQUEUE && acc >= (total * q) / NQUEUE) qbeg[q++] = (int32_t)k;
+    acc += items[k].end - items[k].begin;
+  }
+  b->n_pitems = (int)items.size();
+  B_HIP(ensure(b->d_pitems, sizeof(WorkItem) * std::max<size_t>(1, items.size())));
+  B_HIP(ensure(b->d_qbeg, sizeof(int32_t) * (NQUEUE + 1)));
+  B_HIP(ensure(b->d_qnext, sizeof(int32_t) * NQUEUE));
+  B_HIP(hipStreamSynchronize(st));
+  if (!items.empty())
+    B_HIP(hipMemcpy(b->d_pitems.p, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice));
+  B_HIP(hipMemcpy(b->d_qbeg.p, qbeg.data(), sizeof(int32_t) * (NQUEUE + 1), hipMemcpyHostToDevice));
+  drop_graphs(b);
+  return MT_OK;
+}
+
+int upload_inst(mt_batch* b, hipStream_t st) {
+  const size_t bytes = sizeof(BatchInst) * b->h_inst.size();
+  if (std::memcmp(b->pinned, b->h_inst.data(), bytes) == 0) return MT_OK;
+  B_HIP(hipStreamSynchronize(st));  // the previous copy from the pinned table has completed
+  std::memcpy(b->pinned, b->h_inst.data(), bytes);
+  B_HIP(hipMemcpyAsync(b->d_inst.p, b->pinned, bytes, hipMemcpyHostToDevice, st));
+  return MT_OK;
+}
+
+int launch_fwd(mt_batch* b, hipStream_t st) {
+  const int bsz = b->tune.block;
+  const int grid = b->num_cu * std::max(1, b->tune.blocks_per_cu);
+  k_reset_queues<<<1, 64, 0, st>>>(b->d_qnext.as<int32_t>());
+  B_HIP(hipGetLastError());
+  FwdFn f = pick_fwd(bsz, b->nq, b->dual);
+  hipLaunchKernelGGL(f, dim3(grid), dim3(bsz), 0, st, b->d_inst.as<BatchInst>(), b->d_pitems.as<WorkItem>(),
+                     b->d_qbeg.as<int32_t>(), b->d_qnext.as<int32_t>(), b->counters.as<Counters>());
+  B_HIP(hipGetLastError());
+  return MT_OK;
+}
+
+int launch_fwd_all(mt_batch* b, hipStream_t st) {
+  int rc = launch_fwd(b, st);
+  if (rc) return rc;
+  if (b->n_ritems_s) {
+    k_batch_assemble<<<b->n_ritems_s, ROWS_PER_ITEM, 0, st>>>(b->d_inst.as<BatchInst>(), b->d_ritems_s.as<WorkItem>());
+    B_HIP(hipGetLastError());
+  }
+  return MT_OK;
+}
+
+int launch_bwd_all(mt_batch* b, hipStream_t st) {
+  const int bsz = b->tune.block;
+  const int grid = b->num_cu * std::min(std::max(1, b->tune.blocks_per_cu), max_blocks_per_cu(bsz, true));
+  k_reset_queues<<<1, 64, 0, st>>>(b->d_qnext.as<int32_t>());
+  B_HIP(hipGetLastError());
+  BwdFn f = pick_bwd(bsz, b->nq);
+  hipLaunchKernelGGL(f, dim3(grid), dim3(bsz), 0, st, b->d_inst.as<BatchInst>(), b->d_pitems.as<WorkItem>(),
+                     b->d_qbeg.as<int32_t>(), b->d_qnext.as<int32_t>(), b->counters.as<Counters>());
+  B_HIP(hipGetLastError());
+  if (b->n_ritems_sm) {
+    k_batch_grad_rows<<<b->n_ritems_sm, ROWS_PER_ITEM, 0, st>>>(b->d_inst.as<BatchInst>(),
+                                                                 b->d_ritems_sm.as<WorkItem>());
+    B_HIP(hipGetLastError());
+  }
+  return MT_OK;
+}
+
+// Capture `launch` on stream st into *exec once, then replay it.
+template <class F>
+int run_graph(hipGraphExec_t* exec, hipStream_t* cap_stream, hipStream_t st, F launch) {
+  if (*exec && *cap_stream != st) {
+    (void)hipGraphExecDestroy(*exec);
+    *exec = nullptr;
+  }
+  if (!*exec) {
+    hipGraph_t g = nullptr;
+    B_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    int rc = launch();
+    hipError_t e = hipStreamEndCapture(st, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return bfail(MT_EHIP, "hipStreamEndCapture failed");
+    e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      *exec = nullptr;
+      return bfail(MT_EHIP, "hipGraphInstantiate failed");
+    }
+    *cap_stream = st;
+  }
+  B_HIP(hipGraphLaunch(*exec, st));
+  return MT_OK;
+}
+
+}  // namespace
 
 extern "C" {
-int mt_batch_create(mt_batch** b, int device) { (void)b; (void)device; mt::set_error("batch: not built"); return MT_EUNSUPPORTED; }
-int mt_batch_destroy(mt_batch* b) { (void)b; return MT_OK; }
-int mt_batch_add(mt_batch* b, mt_ctx* c, int32_t* i) { (void)b; (void)c; (void)i; return MT_EUNSUPPORTED; }
-int mt_batch_build(mt_batch* b, const mt_batch_tuning* t, void* s) { (void)b; (void)t; (void)s; return MT_EUNSUPPORTED; }
-int mt_batch_forward(mt_batch* b, double* const* D, double* const* M, double* const* g, int ug, void* s) {
-  (void)b; (void)D; (void)M; (void)g; (void)ug; (void)s; return MT_EUNSUPPORTED; }
-int mt_batch_backward(mt_batch* b, const double* const* WD, const double* const* WM, const double* const* wg,
-                      double* const* gs, double* const* gm, int ug, void* s) {
-  (void)b; (void)WD; (void)WM; (void)wg; (void)gs; (void)gm; (void)ug; (void)s; return MT_EUNSUPPORTED; }
-int mt_batch_autotune(mt_batch* b, mt_batch_tuning* o, void* s) { (void)b; (void)o; (void)s; return MT_EUNSUPPORTED; }
+
+int mt_batch_create(mt_batch** out, int device) {
+  if (!out) return bfail(MT_EINVAL, "mt_batch_create: null");
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n)
+    return bfail(MT_EINVAL, "mt_batch_create: no such device");
+  mt_batch* b = new mt_batch();
+  b->device = device;
+  int cu = 0;
+  if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cu > 0)
+    b->num_cu = cu;
+  *out = b;
+  return MT_OK;
 }
+
+int mt_batch_destroy(mt_batch* b) {
+  if (!b) return MT_OK;
+  (void)hipSetDevice(b->device);
+  (void)hipDeviceSynchronize();
+  drop_graphs(b);
+  if (b->pinned) (void)hipHostFree(b->pinned);
+  Buf* bufs[] = {&b->d_inst, &b->d_pitems, &b->d_qbeg, &b->d_qnext, &b->d_ritems_s, &b->d_ritems_sm, &b->counters};
+  for (Buf* x : bufs) release(*x);
+  delete b;
+  return MT_OK;
+}
+
+int mt_batch_add(mt_batch* b, mt_ctx* c, int32_t* index) {
+  if (!b || !c) return bfail(MT_EINVAL, "mt_batch_add: null");
+  if (c->device != b->device) return bfail(MT_EINVAL, "mt_batch_add: context on another device");
+  if (!c->have_pattern) return bfail(MT_ESTATE, "mt_batch_add: run mt_build_pairs and mt_csr_pattern first");
+  b->ctxs.push_back(c);
+  b->built = false;
+  drop_graphs(b);
+  if (index) *index = (int32_t)b->ctxs.size() - 1;
+  return MT_OK;
+}
+
+int mt_batch_build(mt_batch* b, const mt_batch_tuning* tuning, void* stream) {
+  if (!b) return bfail(MT_EINVAL, "mt_batch_build: null");
+  if (b->ctxs.empty()) return bfail(MT_ESTATE, "mt_batch_build: no instances");
+  (void)hipSetDevice(b->device);
+  hipStream_t st = (hipStream_t)stream;
+  const mt_params& p0 = b->ctxs[0]->params;
+  for (mt_ctx* c : b->ctxs) {
+    if (!c->have_pattern) return bfail(MT_ESTATE, "mt_batch_build: an instance has no pattern");
+    if (c->params.rule != p0.rule || c->params.lm_basis != p0.lm_basis)
+      return bfail(MT_EINVAL, "mt_batch_build: all instances must share the rule and the basis");
+  }
+  b->nq = p0.rule;
+  b->dual = p0.lm_basis == MT_BASIS_DUAL;
+  mt_batch_tuning t{};
+  if (tuning) t = *tuning;
+  if (t.block != 64 && t.block != 128 && t.block != 256) t.block = 64;
+  if (t.blocks_per_cu <= 0) t.blocks_per_cu = max_blocks_per_cu(t.block, false);
+  t.blocks_per_cu = std::min(t.blocks_per_cu, max_blocks_per_cu(t.block, false));
+  if (t.bucket <= 0) t.bucket = 4 * t.block;
+  b->tune = t;
+
+  b->h_inst.assign(b->ctxs.size(), BatchInst{});
+  std::vector<WorkItem> rs, rsm;
+  for (size_t i = 0; i < b->ctxs.size(); ++i) {
+    mt_ctx* c = b->ctxs[i];
+    if (!c->params.lm_basis) {
+      int rc = ensure_master_index(c, st);
+      if (rc) return rc;
+    }
+    const int64_t np = std::max<int64_t>(c->n_pairs, 1);
+    B_HIP(ensure(c->blk, sizeof(double) * 36 * (size_t)np));
+    B_HIP(ensure(c->gpair, sizeof(double) * 24 * (size_t)np));
+    B_HIP(ensure(c->counters, sizeof(Counters)));
+    const DeviceMesh& S = c->side[0];
+    const DeviceMesh& M = c->side[1];
+    BatchInst& I = b->h_inst[i];
+    I.S = MeshPtrs{S.x, S.y, S.z, S.conn};
+    I.M = MeshPtrs{M.x, M.y, M.z, M.conn};
+    I.n_s_el = S.n_el;
+    I.n_s_nodes = S.n_nodes;
+    I.n_m_el = M.n_el;
+    I.n_m_nodes = M.n_nodes;
+    I.pair_s = c->pair_s.as<int32_t>();
+    I.pair_m = c->pair_m.as<int32_t>();
+    I.n_pairs = c->n_pairs;
+    I.pair_off = c->pair_off.as<int32_t>();
+    I.inc_off = c->inc_off.as<int32_t>();
+    I.inc_list = c->inc_list.as<int32_t>();
+    I.D_rowptr = c->D_rowptr.as<int32_t>();
+    I.M_rowptr = c->M_rowptr.as<int32_t>();
+    I.posD = c->posD.as<int32_t>();
+    I.posM = c->posM.as<int32_t>();
+    I.minc_off = c->minc_off.as<int32_t>();
+    I.minc_list = c->minc_list.as<int32_t>();
+    I.mstart = c->mp_off.as<int32_t>();
+    I.mend = c->mp_off.as<int32_t>() ? c->mp_off.as<int32_t>() + M.n_el : nullptr;
+    I.mpairs = c->mp_vals.as<uint32_t>();
+    I.blk = c->blk.as<double>();
+    I.gpair = c->gpair.as<double>();
+    I.kp = kparams(c->params);
+    for (int r = 0; r < S.n_nodes; r += ROWS_PER_ITEM) {
+      const WorkItem w{(int32_t)i, r, std::min(S.n_nodes, r + ROWS_PER_ITEM), 0};
+      rs.push_back(w);
+      rsm.push_back(w);
+    }
+    for (int r = 0; r < M.n_nodes; r += ROWS_PER_ITEM)
+      rsm.push_back({(int32_t)i, r, std::min(M.n_nodes, r + ROWS_PER_ITEM), 1});
+  }
+  b->n_ritems_s = (int)rs.size();
+  b->n_ritems_sm = (int)rsm.size();
+  B_HIP(hipStreamSynchronize(st));
+  B_HIP(ensure(b->d_ritems_s, sizeof(WorkItem) * std::max<size_t>(1, rs.size())));
+  B_HIP(ensure(b->d_ritems_sm, sizeof(WorkItem) * std::max<size_t>(1, rsm.size())));
+  if (!rs.empty()) B_HIP(hipMemcpy(b->d_ritems_s.p, rs.data(), sizeof(WorkItem) * rs.size(), hipMemcpyHostToDevice));
+  if (!rsm.empty())
+    B_HIP(hipMemcpy(b->d_ritems_sm.p, rsm.data(), sizeof(WorkItem) * rsm.size(), hipMemcpyHostToDevice));
+  const size_t ib = sizeof(BatchInst) * b->h_inst.size();
+  B_HIP(ensure(b->d_inst, ib));
+  B_HIP(ensure(b->counters, sizeof(Counters)));
+  B_HIP(hipMemset(b->counters.p, 0, sizeof(Counters)));
+  if (b->pinned) (void)hipHostFree(b->pinned);
+  b->pinned = nullptr;
+  B_HIP(hipHostMalloc((void**)&b->pinned, ib, hipHostMallocDefault));
+  std::memcpy(b->pinned, b->h_inst.data(), ib);
+  B_HIP(hipMemcpy(b->d_inst.p, b->pinned, ib, hipMemcpyHostToDevice));
+  int rc = build_items(b, st);
+  if (rc) return rc;
+  b->built = true;
+  return MT_OK;
+}
+
+int mt_batch_forward(mt_batch* b, double* const* D_val, double* const* M_val, double* const* gap, int use_graph,
+                     void* stream) {
+  if (!b) return bfail(MT_EINVAL, "mt_batch_forward: null");
+  if (!b->built) return bfail(MT_ESTATE, "mt_batch_forward: mt_batch_build first");
+  if (!D_val || !M_val || !gap) return bfail(MT_EINVAL, "mt_batch_forward: null output table");
+  hipStream_t st = (hipStream_t)stream;
+  if (use_graph && st == nullptr) return bfail(MT_EINVAL, "mt_batch_forward: graph capture needs a created stream");
+  (void)hipSetDevice(b->device);
+  for (size_t i = 0; i < b->h_inst.size(); ++i) {
+    b->h_inst[i].D_val = D_val[i];
+    b->h_inst[i].M_val = M_val[i];
+    b->h_inst[i].gap = gap[i];
+  }
+  int rc = upload_inst(b, st);
+  if (rc) return rc;
+  if (use_graph) return run_graph(&b->g_fwd, &b->g_fwd_stream, st, [&]() { return launch_fwd_all(b, st); });
+  return launch_fwd_all(b, st);
+}
+
+int mt_batch_backward(mt_batch* b, const double* const* W_D, const double* const* W_M, const double* const* w_g,
+                      double* const* gXs, double* const* gXm, int use_graph, void* stream) {
+  if (!b) return bfail(MT_EINVAL, "mt_batch_backward: null");
+  if (!b->built) return bfail(MT_ESTATE, "mt_batch_backward: mt_batch_build first");
+  if (b->dual) return bfail(MT_EUNSUPPORTED, "mt_batch_backward: the dual basis has no backward pass");
+  if (!W_D || !W_M || !w_g || !gXs || !gXm) return bfail(MT_EINVAL, "mt_batch_backward: null table");
+  hipStream_t st = (hipStream_t)stream;
+  if (use_graph && st == nullptr) return bfail(MT_EINVAL, "mt_batch_backward: graph capture needs a created stream");
+  (void)hipSetDevice(b->device);
+  for (size_t i = 0; i < b->h_inst.size(); ++i) {
+    b->h_inst[i].W_D = W_D[i];
+    b->h_inst[i].W_M = W_M[i];
+    b->h_inst[i].w_g = w_g[i];
+    b->h_inst[i].gXs = gXs[i];
+    b->h_inst[i].gXm = gXm[i];
+  }
+  int rc = upload_inst(b, st);
+  if (rc) return rc;
+  if (use_graph) return run_graph(&b->g_bwd, &b->g_bwd_stream, st, [&]() { return launch_bwd_all(b, st); });
+  return launch_bwd_all(b, st);
+}
+
+int mt_batch_autotune(mt_batch* b, mt_batch_tuning* out, void* stream) {
+  if (!b) return bfail(MT_EINVAL, "mt_batch_autotune: null");
+  if (!b->built) return bfail(MT_ESTATE, "mt_batch_autotune: mt_batch_build first");
+  (void)hipSetDevice(b->device);
+  hipStream_t st = (hipStream_t)stream;
+  struct Cand { int block, bpc, bucket_mul; };
+  std::vector<Cand> cands;
+  for (int block : {64, 128, 256})
+    for (int bpc : {1, 2, 4, 5})
+      for (int mul : {1, 4, 16})
+        if (bpc <= max_blocks_per_cu(block, false)) cands.push_back({block, bpc, mul});
+  hipEvent_t e0, e1;
+  B_HIP(hipEventCreate(&e0));
+  B_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  mt_batch_tuning best_t = b->tune;
+  for (const Cand& c : cands) {
+    b->tune.block = c.block;
+    b->tune.blocks_per_cu = c.bpc;
+    b->tune.bucket = c.block * c.bucket_mul;
+    int rc = build_items(b, st);
+    if (rc) return rc;
+    rc = launch_fwd(b, st);  // warm-up
+    if (rc) return rc;
+    B_HIP(hipEventRecord(e0, st));
+    for (int r = 0; r < 3; ++r) {
+      rc = launch_fwd(b, st);
+      if (rc) return rc;
+    }
+    B_HIP(hipEventRecord(e1, st));
+    B_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    B_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) {
+      best = ms;
+      best_t = b->tune;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->tune = best_t;
+  int rc = build_items(b, st);
+  if (rc) return rc;
+  if (out) *out = best_t;
+  return MT_OK;
+}
+
+}  // extern "C"

@@ -24,6 +24,25 @@ struct V2 {
 
 // ---- node / element access -------------------------------------------------
 
+struct MeshPtrs {
+  const double* x;
+  const double* y;
+  const double* z;
+  const int32_t* conn;
+};
+
+// Blocks of a grid are dispatched round-robin over the 8 XCDs of an MI355X;
+// remap block b to tile (b % 8) * ceil(nb / 8) + b / 8 so that each XCD works
+// on one contiguous range of tiles (and its L2 holds one region of the mesh).
+// The grid must have xcd_grid(n_tiles) = 8 * ceil(n_tiles / 8) blocks: the
+// mapping is a bijection of [0, 8 * per) onto itself, and tiles at or past
+// n_tiles are skipped by the caller's bounds check.
+__host__ __device__ __forceinline__ unsigned xcd_grid(unsigned n_tiles) { return (n_tiles + 7) / 8 * 8; }
+__device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned grid) {
+  const unsigned per = grid / 8;
+  return (b % 8) * per + b / 8;
+}
+
 __device__ __forceinline__ int4 load_conn(const int32_t* conn, int e) {
   return reinterpret_cast<const int4*>(conn)[e];
 }
@@ -245,15 +264,17 @@ enum : int { PS_DEGEN_SLAVE = 1, PS_DEGEN_MASTER = 2, PS_OVERFLOW = 4 };
 
 // Projection, orientation, clip and cleanup of one candidate.  On return:
 // S, Mn = projected slave / master nodes (node order), hs, hm = heights,
-// Mo = master polygon walked counter-clockwise (mo_map: Mo[l] = Mn[mo_map[l]]),
+// Mo = master polygon walked counter-clockwise (flip: Mo = (M0, M3, M2, M1),
+// i.e. Mo[l] = Mn[(4 - l) % 4]; otherwise Mo = Mn),
 // polygon in buffer `res` with `n` vertices (0: not a pair).
 template <bool LAB>
 __device__ __forceinline__ int pair_geometry(const double Xs[4][3], const double Xm[4][3], const double f[12],
                                              double eps_d, double eps_a, V2 S[4], V2 Mn[4], double hs[4],
-                                             double hm[4], int mo_map[4], const LdsPoly<LAB>& P, int& res,
+                                             double hm[4], bool& flip, const LdsPoly<LAB>& P, int& res,
                                              int& status) {
   status = 0;
   res = 0;
+  flip = false;
 #pragma unroll
   for (int k = 0; k < 4; ++k) project(Xs[k], f, S[k], hs[k]);
 #pragma unroll
@@ -270,11 +291,8 @@ __device__ __forceinline__ int pair_geometry(const double Xs[4][3], const double
   const double tol_a = eps_a * As;
   const double Am = quad_fan_area(Mn);
   if (fabs(Am) <= tol_a) { status = PS_DEGEN_MASTER; return 0; }
-  mo_map[0] = 0; mo_map[1] = 1; mo_map[2] = 2; mo_map[3] = 3;
-  if (Am < 0.0) { mo_map[1] = 3; mo_map[3] = 1; }
-  V2 Mo[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) Mo[k] = Mn[mo_map[k]];
+  flip = Am < 0.0;
+  V2 Mo[4] = {Mn[0], flip ? Mn[3] : Mn[1], Mn[2], flip ? Mn[1] : Mn[3]};
   bool ovf;
   int n = clip_polygon<LAB>(S, Mo, P, res, ovf);
   if (ovf) { status = PS_OVERFLOW; return 0; }
@@ -286,36 +304,6 @@ __device__ __forceinline__ int pair_geometry(const double Xs[4][3], const double
 }
 
 // ---- quadrature ------------------------------------------------------------
-
-// Barycentric triangle rules, weights summing to one: 7 points of degree 5
-// (Radon's rule) and 3 points of degree 2 (the rule of Fig. 1).
-struct TriRule {
-  int n;
-  double l[7][3];
-  double w[7];
-};
-
-__device__ __forceinline__ void get_rule(int which, double l[7][3], double w[7], int& n) {
-  if (which == 3) {
-    const double a = 2.0 / 3.0, b = 1.0 / 6.0;
-    n = 3;
-    l[0][0] = a; l[0][1] = b; l[0][2] = b;
-    l[1][0] = b; l[1][1] = a; l[1][2] = b;
-    l[2][0] = b; l[2][1] = b; l[2][2] = a;
-    w[0] = w[1] = w[2] = 1.0 / 3.0;
-    return;
-  }
-  const double a1 = 0.10128650732345634, b1 = 0.7974269853530873, w1 = 0.12593918054482714;
-  const double a2 = 0.4701420641051151, b2 = 0.05971587178976982, w2 = 0.1323941527885062;
-  n = 7;
-  l[0][0] = 1.0 / 3.0; l[0][1] = 1.0 / 3.0; l[0][2] = 1.0 / 3.0; w[0] = 9.0 / 40.0;
-  l[1][0] = b1; l[1][1] = a1; l[1][2] = a1; w[1] = w1;
-  l[2][0] = a1; l[2][1] = b1; l[2][2] = a1; w[2] = w1;
-  l[3][0] = a1; l[3][1] = a1; l[3][2] = b1; w[3] = w1;
-  l[4][0] = b2; l[4][1] = a2; l[4][2] = a2; w[4] = w2;
-  l[5][0] = a2; l[5][1] = b2; l[5][2] = a2; w[5] = w2;
-  l[6][0] = a2; l[6][1] = a2; l[6][2] = b2; w[6] = w2;
-}
 
 // Bilinear shape functions, nodes at (-1,-1), (1,-1), (1,1), (-1,1).
 __device__ __forceinline__ void shape4(double x1, double x2, double N[4]) {

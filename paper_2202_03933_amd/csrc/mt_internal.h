@@ -206,6 +206,9 @@ hipError_t launch_pair_bwd(const DeviceMesh& S, const DeviceMesh& M, const KPara
                            int64_t stride, Counters* cnt, hipStream_t s);
 
 KParams kparams(const mt_params& p);
+// Node incidence of the master side and the pairs-by-master permutation
+// (needed by the backward's master-node reduction); built once per pattern.
+int ensure_master_index(mt_ctx* c, hipStream_t st);
 void set_error(const std::string& msg);
 
 }  // namespace mt

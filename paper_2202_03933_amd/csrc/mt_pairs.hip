@@ -6,8 +6,7 @@
 // lane-interleaved.  Local blocks are staged structure-of-arrays,
 // blk[c * stride + p] for the 36 components c = [D 4x4 | M 4x4 | g 4], so
 // the stores of a wavefront are coalesced.
-#include "mt_geometry.h"
-#include "mt_internal.h"
+#include "mt_pair_eval.h"
 
 namespace mt {
 
@@ -34,7 +33,7 @@ __global__ __launch_bounds__(BSC) void k_clip_count(const double* __restrict__ x
   __shared__ unsigned int hist[20];
   if (threadIdx.x < 20) hist[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t c = (int64_t)blockIdx.x * BSC + threadIdx.x;
+  const int64_t c = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * BSC + threadIdx.x;
   if (c < n_cand) {
     const int s = cand_s[c], m = cand_m[c];
     double f[12], Xs[4][3], Xm[4][3];
@@ -44,8 +43,9 @@ __global__ __launch_bounds__(BSC) void k_clip_count(const double* __restrict__ x
     LdsPoly<false> P{su + threadIdx.x, sv + threadIdx.x, nullptr, nullptr, BSC};
     V2 S[4], Mn[4];
     double hs[4], hm[4];
-    int mo[4], res, st;
-    const int n = pair_geometry<false>(Xs, Xm, f, kp.eps_d, kp.eps_a, S, Mn, hs, hm, mo, P, res, st);
+    int res, st;
+    bool flip;
+    const int n = pair_geometry<false>(Xs, Xm, f, kp.eps_d, kp.eps_a, S, Mn, hs, hm, flip, P, res, st);
     nv_out[c] = (uint8_t)n;
     flag[c] = n >= 3 ? 1 : 0;
     atomicAdd(&hist[n], 1u);
@@ -85,93 +85,35 @@ __global__ __launch_bounds__(BS) void k_pair_off(const int32_t* __restrict__ can
   pair_off[s] = scan[cand_off[s]];
 }
 
-// Segment-based integration of one pair: fan triangles (v0, v_i, v_{i+1})
-// of the clip polygon, rule points p, slave / master parameter coordinates
-// by the inverse bilinear maps, and the local blocks
-//   D[j][k] += w Phi_j N_k(xi), M[j][l] += w Phi_j N_l(eta),
-//   g[j]    += w Phi_j (sum_l N_l(eta) hm_l - sum_k N_k(xi) hs_k).
-__global__ __launch_bounds__(BSC) void k_pair_fwd(const double* __restrict__ xs, const double* __restrict__ ys,
-                                                   const double* __restrict__ zs, const int32_t* __restrict__ cs,
-                                                   int32_t n_s, const double* __restrict__ xm,
-                                                   const double* __restrict__ ym, const double* __restrict__ zm,
-                                                   const int32_t* __restrict__ cm, KParams kp,
+// Segment-based integration of every pair; local blocks staged
+// structure-of-arrays.  Blocks are mapped XCD-major: consecutive blocks are
+// dispatched to different XCDs, so block b works on tile
+// (b % 8) * ceil(nb / 8) + b / 8 and each XCD's L2 sees one contiguous eighth
+// of the pair list (neighbouring pairs share slave nodes).
+template <int NQ, bool DUAL>
+__global__ __launch_bounds__(BSC) void k_pair_fwd(MeshPtrs S, MeshPtrs M, KParams kp,
                                                    const int32_t* __restrict__ pair_s,
                                                    const int32_t* __restrict__ pair_m, int64_t n_pairs,
                                                    double* __restrict__ blk, int64_t stride, Counters* cnt) {
   __shared__ double su[2 * CAP * BSC], sv[2 * CAP * BSC];
-  const int64_t p = (int64_t)blockIdx.x * BSC + threadIdx.x;
-  unsigned long long noconv = 0;
+  const int64_t p = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * BSC + threadIdx.x;
+  unsigned noconv = 0;
   if (p < n_pairs) {
-    const int s = pair_s[p], m = pair_m[p];
-    double f[12], Xs[4][3], Xm[4][3];
-    load_nodes(xs, ys, zs, load_conn(cs, s), Xs);
-    load_nodes(xm, ym, zm, load_conn(cm, m), Xm);
-    slave_frame(Xs, f);
+    double Xs[4][3], Xm[4][3];
+    load_nodes(S.x, S.y, S.z, load_conn(S.conn, pair_s[p]), Xs);
+    load_nodes(M.x, M.y, M.z, load_conn(M.conn, pair_m[p]), Xm);
     LdsPoly<false> P{su + threadIdx.x, sv + threadIdx.x, nullptr, nullptr, BSC};
-    V2 S[4], Mn[4];
-    double hs[4], hm[4];
-    int mo[4], res, st;
-    const int n = pair_geometry<false>(Xs, Xm, f, kp.eps_d, kp.eps_a, S, Mn, hs, hm, mo, P, res, st);
-    double A[16];
-    if (kp.dual) dual_coefficients(S, A);
-    double D[16], M[16], g[4];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) { D[k] = 0.0; M[k] = 0.0; }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) g[k] = 0.0;
-    double rl[7][3], rw[7];
-    int nq;
-    get_rule(kp.rule, rl, rw, nq);
-    {
-#pragma clang fp contract(fast)
-      const double u0 = P.u[P.at(res, 0)], v0 = P.v[P.at(res, 0)];
-      for (int i = 1; i + 1 < n; ++i) {
-        const double u1 = P.u[P.at(res, i)], v1 = P.v[P.at(res, i)];
-        const double u2 = P.u[P.at(res, i + 1)], v2 = P.v[P.at(res, i + 1)];
-        const double At = 0.5 * ((u1 - u0) * (v2 - v0) - (v1 - v0) * (u2 - u0));
-        for (int q = 0; q < nq; ++q) {
-          const double pu = rl[q][0] * u0 + rl[q][1] * u1 + rl[q][2] * u2;
-          const double pv = rl[q][0] * v0 + rl[q][1] * v1 + rl[q][2] * v2;
-          const double wA = rw[q] * At;
-          double a1, a2, b1, b2;
-          if (!inverse_bilinear(S, pu, pv, kp.newton_tol, kp.newton_maxit, a1, a2)) ++noconv;
-          if (!inverse_bilinear(Mn, pu, pv, kp.newton_tol, kp.newton_maxit, b1, b2)) ++noconv;
-          double Ns[4], Nm[4];
-          shape4(a1, a2, Ns);
-          shape4(b1, b2, Nm);
-          double Phi[4];
-          if (kp.dual) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-              Phi[j] = A[j * 4 + 0] * Ns[0] + A[j * 4 + 1] * Ns[1] + A[j * 4 + 2] * Ns[2] + A[j * 4 + 3] * Ns[3];
-          } else {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) Phi[j] = Ns[j];
-          }
-          const double gap = (Nm[0] * hm[0] + Nm[1] * hm[1] + Nm[2] * hm[2] + Nm[3] * hm[3]) -
-                             (Ns[0] * hs[0] + Ns[1] * hs[1] + Ns[2] * hs[2] + Ns[3] * hs[3]);
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const double wp = wA * Phi[j];
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              D[j * 4 + k] += wp * Ns[k];
-              M[j * 4 + k] += wp * Nm[k];
-            }
-            g[j] += wp * gap;
-          }
-        }
-      }
-    }
+    double D[16], Mv[16], g[4];
+    pair_forward<NQ, DUAL, false>(Xs, Xm, kp, P, D, Mv, g, noconv);
 #pragma unroll
     for (int k = 0; k < 16; ++k) blk[(int64_t)k * stride + p] = D[k];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) blk[(int64_t)(16 + k) * stride + p] = M[k];
+    for (int k = 0; k < 16; ++k) blk[(int64_t)(16 + k) * stride + p] = Mv[k];
 #pragma unroll
     for (int k = 0; k < 4; ++k) blk[(int64_t)(32 + k) * stride + p] = g[k];
   }
-  noconv = wave_sum_u64(noconv);
-  if (threadIdx.x == 0 && noconv) atomicAdd(&cnt->noconv, noconv);
+  const unsigned long long nc = wave_sum_u64(noconv);
+  if (threadIdx.x == 0 && nc) atomicAdd(&cnt->noconv, nc);
 }
 
 }  // namespace
@@ -180,7 +122,7 @@ hipError_t launch_clip_count(const DeviceMesh& S, const DeviceMesh& M, const KPa
                              const int32_t* cand_s, const int32_t* cand_m, int64_t n_cand, uint8_t* nv,
                              int32_t* flag, Counters* cnt, hipStream_t s) {
   if (n_cand == 0) return hipSuccess;
-  k_clip_count<<<(unsigned)((n_cand + BSC - 1) / BSC), BSC, 0, s>>>(S.x, S.y, S.z, S.conn, S.n_el, M.x, M.y, M.z,
+  k_clip_count<<<xcd_grid((unsigned)((n_cand + BSC - 1) / BSC)), BSC, 0, s>>>(S.x, S.y, S.z, S.conn, S.n_el, M.x, M.y, M.z,
                                                                     M.conn, kp, cand_s, cand_m, n_cand, nv,
                                                                     flag, cnt);
   return hipGetLastError();
@@ -200,12 +142,19 @@ hipError_t launch_pair_off(const int32_t* cand_off, const int32_t* scan, int32_t
   return hipGetLastError();
 }
 
-hipError_t launch_pair_fwd(const DeviceMesh& S, const DeviceMesh& M, const KParams& kp, const int32_t* pair_s, const int32_t* pair_m, int64_t n_pairs,
-                           double* blk, int64_t stride, Counters* cnt, hipStream_t s) {
+hipError_t launch_pair_fwd(const DeviceMesh& S, const DeviceMesh& M, const KParams& kp, const int32_t* pair_s,
+                           const int32_t* pair_m, int64_t n_pairs, double* blk, int64_t stride, Counters* cnt,
+                           hipStream_t s) {
   if (n_pairs == 0) return hipSuccess;
-  k_pair_fwd<<<(unsigned)((n_pairs + BSC - 1) / BSC), BSC, 0, s>>>(S.x, S.y, S.z, S.conn, S.n_el, M.x, M.y, M.z,
-                                                                   M.conn, kp, pair_s, pair_m, n_pairs,
-                                                                   blk, stride, cnt);
+  const unsigned nb = xcd_grid((unsigned)((n_pairs + BSC - 1) / BSC));
+  const MeshPtrs ms{S.x, S.y, S.z, S.conn}, mm{M.x, M.y, M.z, M.conn};
+  if (kp.rule == 3) {
+    if (kp.dual) k_pair_fwd<3, true><<<nb, BSC, 0, s>>>(ms, mm, kp, pair_s, pair_m, n_pairs, blk, stride, cnt);
+    else k_pair_fwd<3, false><<<nb, BSC, 0, s>>>(ms, mm, kp, pair_s, pair_m, n_pairs, blk, stride, cnt);
+  } else {
+    if (kp.dual) k_pair_fwd<7, true><<<nb, BSC, 0, s>>>(ms, mm, kp, pair_s, pair_m, n_pairs, blk, stride, cnt);
+    else k_pair_fwd<7, false><<<nb, BSC, 0, s>>>(ms, mm, kp, pair_s, pair_m, n_pairs, blk, stride, cnt);
+  }
   return hipGetLastError();
 }
 

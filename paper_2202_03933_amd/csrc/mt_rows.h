@@ -1,0 +1,88 @@
+// Row-owner device functions of the deterministic assembly: one thread owns
+// one output row (slave node) or one node's gradient and adds its
+// contributions in a fixed order (incident elements ascending, then pairs in
+// (slave, master) order).  Shared by the single-interface and batched kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace mt {
+
+// Row a of D, M and the gap from the staged local blocks blk[c * stride + p].
+__device__ __forceinline__ void assemble_row(int a, const int32_t* __restrict__ inc_off,
+                                             const int32_t* __restrict__ inc_list,
+                                             const int32_t* __restrict__ pair_off,
+                                             const int32_t* __restrict__ D_rowptr,
+                                             const int32_t* __restrict__ M_rowptr,
+                                             const int32_t* __restrict__ posD, int32_t n_s_el,
+                                             const int32_t* __restrict__ posM, const double* __restrict__ blk,
+                                             int64_t stride, double* __restrict__ D_val, double* __restrict__ M_val,
+                                             double* __restrict__ gap) {
+  for (int i = D_rowptr[a]; i < D_rowptr[a + 1]; ++i) D_val[i] = 0.0;
+  for (int i = M_rowptr[a]; i < M_rowptr[a + 1]; ++i) M_val[i] = 0.0;
+  double g = 0.0;
+  for (int i = inc_off[a]; i < inc_off[a + 1]; ++i) {
+    const int e = inc_list[i] >> 2, j = inc_list[i] & 3;
+    const int p0 = pair_off[e], p1 = pair_off[e + 1];
+    if (p0 == p1) continue;
+    int pd[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pd[k] = posD[(int64_t)(j * 4 + k) * n_s_el + e];
+    for (int p = p0; p < p1; ++p) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) D_val[pd[k]] += blk[(int64_t)(j * 4 + k) * stride + p];
+#pragma unroll
+      for (int l = 0; l < 4; ++l)
+        M_val[posM[(int64_t)(j * 4 + l) * stride + p]] += blk[(int64_t)(16 + j * 4 + l) * stride + p];
+      g += blk[(int64_t)(32 + j) * stride + p];
+    }
+  }
+  gap[a] = g;
+}
+
+// Gradient of slave node a (structure-of-arrays gX[3 * n]).
+__device__ __forceinline__ void grad_slave_row(int a, int32_t n, const int32_t* __restrict__ inc_off,
+                                               const int32_t* __restrict__ inc_list,
+                                               const int32_t* __restrict__ pair_off,
+                                               const double* __restrict__ gpair, int64_t stride,
+                                               double* __restrict__ gX) {
+  double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+  for (int i = inc_off[a]; i < inc_off[a + 1]; ++i) {
+    const int e = inc_list[i] >> 2, j = inc_list[i] & 3;
+    for (int p = pair_off[e]; p < pair_off[e + 1]; ++p) {
+      g0 += gpair[(int64_t)(3 * j + 0) * stride + p];
+      g1 += gpair[(int64_t)(3 * j + 1) * stride + p];
+      g2 += gpair[(int64_t)(3 * j + 2) * stride + p];
+    }
+  }
+  gX[a] = g0;
+  gX[(int64_t)n + a] = g1;
+  gX[2 * (int64_t)n + a] = g2;
+}
+
+// Gradient of master node b: pairs of each incident master element through
+// the pairs-by-master permutation mpairs[mstart[m] .. mend[m]).
+__device__ __forceinline__ void grad_master_row(int b, int32_t n, const int32_t* __restrict__ inc_off,
+                                                const int32_t* __restrict__ inc_list,
+                                                const int32_t* __restrict__ mstart, const int32_t* __restrict__ mend,
+                                                const uint32_t* __restrict__ mpairs,
+                                                const double* __restrict__ gpair, int64_t stride,
+                                                double* __restrict__ gX) {
+  double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+  for (int i = inc_off[b]; i < inc_off[b + 1]; ++i) {
+    const int m = inc_list[i] >> 2, l = inc_list[i] & 3;
+    for (int k = mstart[m]; k < mend[m]; ++k) {
+      const int64_t p = mpairs[k];
+      g0 += gpair[(int64_t)(12 + 3 * l + 0) * stride + p];
+      g1 += gpair[(int64_t)(12 + 3 * l + 1) * stride + p];
+      g2 += gpair[(int64_t)(12 + 3 * l + 2) * stride + p];
+    }
+  }
+  gX[b] = g0;
+  gX[(int64_t)n + b] = g1;
+  gX[2 * (int64_t)n + b] = g2;
+}
+
+}  // namespace mt

@@ -95,6 +95,8 @@ def _fd_check(itf, seed=3000, n_coords=200, interior=0.35):
         an = (gXs if side == 0 else gXm)[d, node]
         fd = dL(side, node, d, 1e-6)
         checked += 1
+        if checked % 25 == 0:
+            print(f"FD {itf.name}: {checked} coordinates", flush=True)
         if abs(fd - an) > 1e-4 * abs(an) + 1e-10:
             refined += 1
             fd = dL(side, node, d, 1e-7)

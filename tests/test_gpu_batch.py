@@ -1,0 +1,129 @@
+"""Batched evaluation of many interfaces (persistent launches, HIP graphs,
+autotuned tiles): bitwise equal to one call per interface, and through it to
+the oracle."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.gpu_util import TOL, csr_weights, gpu_params, oracle_params, rel_err, weight_fns
+
+pytestmark = pytest.mark.gpu
+
+
+def make_ifaces(instances):
+    from paper_2202_03933_amd import MortarInterface
+    dev = torch.device("cuda", 0)
+    out = []
+    for itf in instances:
+        it = MortarInterface(torch.from_numpy(itf.slave.X), torch.from_numpy(itf.slave.conn),
+                             torch.from_numpy(itf.master.X), torch.from_numpy(itf.master.conn),
+                             params=gpu_params(itf), device=dev).setup()
+        out.append(it)
+    return out
+
+
+def weights_for(it, seed):
+    import scipy.sparse as sp
+    ns, nm = it.n_slave_nodes, it.n_master_nodes
+    D = sp.csr_matrix((np.zeros(it.nnz_D), it.D_col.cpu().numpy(), it.D_rowptr.cpu().numpy()), shape=(ns, ns))
+    M = sp.csr_matrix((np.zeros(it.nnz_M), it.M_col.cpu().numpy(), it.M_rowptr.cpu().numpy()), shape=(ns, nm))
+    return tuple(torch.from_numpy(a).to(it.device) for a in csr_weights(D, M, ns, seed))
+
+
+def equal_outs(a, b):
+    return all(torch.equal(x, y) for x, y in zip(a, b))
+
+
+def run_batch_checks(instances, autotune=True):
+    from paper_2202_03933_amd import MortarBatch
+    ifaces = make_ifaces(instances)
+    print(f"[gpu] batch of {len(ifaces)} interfaces, {sum(i.n_pairs for i in ifaces)} pairs", flush=True)
+    ref = [tuple(t.clone() for t in it.integrate()) for it in ifaces]
+    W = [weights_for(it, 4000 + k) for k, it in enumerate(ifaces)]
+    ref_g = [tuple(t.clone() for t in it.backward(*w)) for it, w in zip(ifaces, W)]
+    b = MortarBatch(ifaces)
+    outs = b.forward()
+    torch.cuda.synchronize()
+    assert all(equal_outs(o, r) for o, r in zip(outs, ref))
+    # graph replays, with eager work of the program between them
+    outs2 = b.alloc_outputs()
+    for rep in range(3):
+        for o in outs2:
+            for t in o:
+                t.fill_(float("nan"))
+        b.forward(outs2, use_graph=True)
+        torch.cuda.synchronize()
+        ifaces[rep % len(ifaces)].integrate()
+        torch.cuda.synchronize()
+        assert all(equal_outs(o, r) for o, r in zip(outs2, ref)), rep
+    g = b.backward(W)
+    torch.cuda.synchronize()
+    assert all(equal_outs(x, r) for x, r in zip(g, ref_g))
+    g2 = [(torch.empty_like(a), torch.empty_like(c)) for a, c in ref_g]
+    for rep in range(3):
+        b.backward(W, outs=g2, use_graph=True)
+        torch.cuda.synchronize()
+        ifaces[0].backward(*W[0])
+        torch.cuda.synchronize()
+        assert all(equal_outs(x, r) for x, r in zip(g2, ref_g)), rep
+    if autotune:
+        choice = b.autotune()
+        print("autotuned", choice)
+        assert choice["block"] in (64, 128, 256) and choice["blocks_per_cu"] >= 1 and choice["bucket"] >= 1
+        outs3 = b.forward(use_graph=True)
+        torch.cuda.synchronize()
+        assert all(equal_outs(o, r) for o, r in zip(outs3, ref))
+        g3 = b.backward(W, use_graph=True)
+        torch.cuda.synchronize()
+        assert all(equal_outs(x, r) for x, r in zip(g3, ref_g))
+    return ifaces, outs, g
+
+
+def test_batch_small_instances_bitwise_and_oracle():
+    instances = synth.batched_instances(n_inst=9, max_side=40)
+    ifaces, outs, grads = run_batch_checks(instances)
+    # oracle parity of every instance through the batched outputs
+    for itf, it, (D, M, gv), (gs, gm) in zip(instances, ifaces, outs, grads):
+        prm = oracle_params(itf)
+        o = oracle.evaluate(itf, prm)
+        assert np.array_equal(it.D_col.cpu().numpy(), o["D"].indices)
+        assert np.array_equal(it.M_col.cpu().numpy(), o["M"].indices)
+        assert rel_err(D.cpu().numpy(), o["D"].data) <= TOL
+        assert rel_err(M.cpu().numpy(), o["M"].data) <= TOL
+        if np.linalg.norm(o["g"]) > 0:
+            assert rel_err(gv.cpu().numpy(), o["g"]) <= TOL
+        if itf.meta["geometry"] == "flat":
+            continue  # tied flat boundaries: not differentiable (see test_gpu_backward)
+        w = oracle.pair_weights(itf.slave, itf.master, o["pair_s"], o["pair_m"],
+                                *weight_fns(4000 + itf.meta["instance"]))
+        g24, _ = oracle.pair_grads(itf.slave, itf.master, prm, o["pair_s"], o["pair_m"], w)
+        ogs, ogm = oracle.scatter_grads(itf.slave, itf.master, o["pair_s"], o["pair_m"], g24)
+        assert rel_err(gs.cpu().numpy().T, ogs) <= TOL and rel_err(gm.cpu().numpy().T, ogm) <= TOL
+
+
+def test_batch_full_64_instances_bitwise():
+    instances = synth.batched_instances(n_inst=64)
+    run_batch_checks(instances, autotune=False)
+
+
+def test_batch_rejects_mixed_rules_and_graph_on_default_stream():
+    from paper_2202_03933_amd import MortarBatch, MortarError, MortarInterface, default_params
+    from paper_2202_03933_amd import _capi as C
+    import ctypes
+    dev = torch.device("cuda", 0)
+    a, b = synth.flat_tied(4, 3, seed=1), synth.flat_tied(5, 4, seed=2)
+    ia = make_ifaces([a])[0]
+    ib = MortarInterface(torch.from_numpy(b.slave.X), torch.from_numpy(b.slave.conn), torch.from_numpy(b.master.X),
+                         torch.from_numpy(b.master.conn), params=default_params(rule=3), device=dev).setup()
+    with pytest.raises(MortarError) as e:
+        MortarBatch([ia, ib])
+    assert e.value.code == C.MT_EINVAL
+    bt = MortarBatch([ia])
+    outs = bt.alloc_outputs()
+    from paper_2202_03933_amd.batch import _ptr_table
+    tabs = [_ptr_table([o[k] for o in outs]) for k in range(3)]
+    rc = C.lib().mt_batch_forward(bt.h, *tabs, 1, ctypes.c_void_p(0))
+    assert rc == C.MT_EINVAL
