@@ -134,6 +134,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one plain 1 GiB device copy (calibrates HBM traffic counters)")
     ap.add_argument("--cpu-sample", type=int, default=16384, help="slave elements in the CPU oracle sample")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -191,6 +193,12 @@ def main():
     fwd_ms = sum(per_step[k] for k in ("prep", "bin_sort", "cand", "clip", "compact", "pattern", "pair_fwd",
                                         "assemble"))
 
+    if args.calib_copy:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     batched = None if args.no_batched else bench_batched()
     cpu = None
     if not args.no_cpu_baseline:

@@ -124,10 +124,16 @@ enum {
   ST_DEGEN_MASTER = 8,  // projected master polygon has (near) zero area
 };
 
-// Working capacity of a clip polygon.  A convex quad clipped by four half
-// planes has at most 8 vertices; rounding near coincident edges can emit a
-// few extra (near-duplicate) vertices before cleanup.
-constexpr int CAP = 16;
+// Working capacity of the clip polygons.  The clipper alternates between two
+// buffers: buffer 0 holds the slave polygon and the outputs of stages 2 and
+// 4, buffer 1 the outputs of stages 1 and 3.  A convex quad clipped by k half
+// planes has at most 4 + k vertices (5, 6, 7, 8); the capacities leave two
+// vertices of headroom for near-duplicate vertices that rounding can emit
+// next to coincident edges.  A stage that would exceed its buffer makes the
+// candidate degenerate (no pair, overflow status).
+constexpr int CAP0 = 10;
+constexpr int CAP1 = 9;
+constexpr int CAP = CAP0;  // storage per buffer
 
 template <class T> struct P2 { T u, v; };
 
@@ -205,7 +211,7 @@ T fan_area(int n, const P2<T>* p) {
 // vertex order exactly.
 template <class T>
 int clip_stage(int n, const P2<T>* in, const P2<T>& a, const P2<T>& b,
-               P2<T>* out, int* status) {
+               P2<T>* out, int cap, int* status) {
   if (n == 0) return 0;
   T c[CAP];
   for (int j = 0; j < n; ++j)
@@ -216,11 +222,11 @@ int clip_stage(int n, const P2<T>* in, const P2<T>& a, const P2<T>& b,
     const bool pin = val(c[j]) >= 0.0;
     const bool ein = val(c[e]) >= 0.0;
     if (pin) {
-      if (k == CAP) { *status |= ST_OVERFLOW; return 0; }
+      if (k == cap) { *status |= ST_OVERFLOW; return 0; }
       out[k++] = in[j];
     }
     if (pin != ein) {
-      if (k == CAP) { *status |= ST_OVERFLOW; return 0; }
+      if (k == cap) { *status |= ST_OVERFLOW; return 0; }
       T t = c[j] / (c[j] - c[e]);
       out[k].u = in[j].u + t * (in[e].u - in[j].u);
       out[k].v = in[j].v + t * (in[e].v - in[j].v);
@@ -426,12 +432,31 @@ void eval_pair(const T Xs[4][3], const T Xm[4][3], const Params& prm,
   P2<T> Mo[4] = {Mn[0], Mn[1], Mn[2], Mn[3]};
   if (val(Am) < 0.0) { Mo[1] = Mn[3]; Mo[3] = Mn[1]; }
 
+  // Separating-line quick exit (our addition; exact): when every slave vertex
+  // lies strictly outside one master edge line, or every master vertex
+  // strictly outside one slave edge line, the two convex polygons do not
+  // overlap.  The side test is the clip's own expression.
+  for (int side = 0; side < 2; ++side) {
+    const P2<T>* E = side == 0 ? Mo : S;  // polygon supplying the edge lines
+    const P2<T>* V = side == 0 ? S : Mo;  // polygon tested against them
+    for (int l = 0; l < 4; ++l) {
+      const P2<T>& a = E[l];
+      const P2<T>& b = E[(l + 1) % 4];
+      bool all_out = true;
+      for (int k = 0; k < 4; ++k) {
+        const T c = (b.u - a.u) * (V[k].v - a.v) - (b.v - a.v) * (V[k].u - a.u);
+        if (val(c) >= 0.0) all_out = false;
+      }
+      if (all_out) return;
+    }
+  }
+
   P2<T> buf[2][CAP];
   int n = 4;
   for (int k = 0; k < 4; ++k) buf[0][k] = S[k];
   int cur = 0;
   for (int l = 0; l < 4 && n > 0; ++l) {
-    n = clip_stage(n, buf[cur], Mo[l], Mo[(l + 1) % 4], buf[1 - cur], &out.status);
+    n = clip_stage(n, buf[cur], Mo[l], Mo[(l + 1) % 4], buf[1 - cur], cur == 0 ? CAP1 : CAP0, &out.status);
     cur = 1 - cur;
   }
   if (out.status & ST_OVERFLOW) return;
@@ -710,7 +735,7 @@ int or_clip2d(int ns, const double* su, const double* sv, int nc, const double* 
   for (int i = 0; i < nc; ++i) C[i] = {cu[i], cv[i]};
   int st = 0, n = ns, cur = 0;
   for (int l = 0; l < nc && n > 0; ++l) {
-    n = clip_stage(n, buf[cur], C[l], C[(l + 1) % nc], buf[1 - cur], &st);
+    n = clip_stage(n, buf[cur], C[l], C[(l + 1) % nc], buf[1 - cur], cur == 0 ? CAP1 : CAP0, &st);
     cur = 1 - cur;
   }
   if (st) return -2;

@@ -5,6 +5,7 @@
 #include <cstring>
 #include <string>
 
+#include "mt_geometry.h"
 #include "mt_internal.h"
 
 namespace mt {
@@ -159,12 +160,12 @@ int mt_destroy(mt_ctx* c) {
   if (!c) return MT_OK;
   DeviceScope ds(c->device);
   (void)hipDeviceSynchronize();
-  Buf* bufs[] = {&c->box_s, &c->box_m, &c->reduce, &c->counters, &c->keys, &c->vals,
-                 &c->keys_tmp, &c->vals_tmp, &c->cell_start, &c->cell_end, &c->cand_cnt, &c->cand_off,
+  Buf* bufs[] = {&c->box_s, &c->box_m, &c->sdata, &c->reduce, &c->counters, &c->keys, &c->vals,
+                 &c->keys_tmp, &c->vals_tmp, &c->cell_start, &c->cell_end, &c->cand_cnt, &c->cand_tmp, &c->cand_off,
                  &c->cand_s, &c->cand_m, &c->cand_nv, &c->cand_flag, &c->cand_scan, &c->pair_s, &c->pair_m,
                  &c->pair_nv, &c->pair_off, &c->inc_cnt, &c->inc_off, &c->inc_cur, &c->inc_list, &c->minc_cnt,
                  &c->minc_off, &c->minc_cur, &c->minc_list, &c->rawD_cnt, &c->rawD_off, &c->rawD, &c->rawM_cnt,
-                 &c->rawM_off, &c->rawM, &c->D_cnt, &c->D_rowptr, &c->D_col, &c->M_cnt, &c->M_rowptr,
+                 &c->rawM_off, &c->rawM, &c->pat_keep, &c->D_cnt, &c->D_rowptr, &c->D_col, &c->M_cnt, &c->M_rowptr,
                  &c->M_col, &c->posD, &c->posM, &c->blk, &c->gpair, &c->mp_keys, &c->mp_vals, &c->mp_off,
                  &c->scan_tmp, &c->sort_hist, &c->host_tmp};
   for (Buf* b : bufs) release(*b);
@@ -237,13 +238,14 @@ int mt_build_pairs(mt_ctx* c, int64_t* n_cand_out, int64_t* n_pairs_out, void* s
   MT_HIP(ensure(c->host_tmp, 64));
   MT_HIP(ensure(c->box_s, sizeof(double) * 6 * (size_t)ns));
   MT_HIP(ensure(c->box_m, sizeof(double) * 6 * (size_t)nm));
+  MT_HIP(ensure(c->sdata, sizeof(double) * SD_N * (size_t)ns));
   PrepReduce* red = c->reduce.as<PrepReduce>();
   {
     PhaseTimer t(c, MT_T_PREP, st);
     MT_HIP(launch_init_reduce(red, st));
     MT_HIP(hipMemsetAsync(c->counters.p, 0, sizeof(Counters), st));
-    MT_HIP(launch_prep(S, true, c->box_s.as<double>(), red, st));
-    MT_HIP(launch_prep(M, false, c->box_m.as<double>(), red, st));
+    MT_HIP(launch_prep(S, true, c->box_s.as<double>(), c->sdata.as<double>(), red, st));
+    MT_HIP(launch_prep(M, false, c->box_m.as<double>(), nullptr, red, st));
   }
   PrepReduce hr;
   MT_HIP(hipMemcpyAsync(&hr, red, sizeof(hr), hipMemcpyDeviceToHost, st));
@@ -275,11 +277,12 @@ int mt_build_pairs(mt_ctx* c, int64_t* n_cand_out, int64_t* n_pairs_out, void* s
   // candidates: count, scan, fill (sorted by master within each slave)
   MT_HIP(ensure(c->cand_cnt, sizeof(int32_t) * ((size_t)ns + 1)));
   MT_HIP(ensure(c->cand_off, sizeof(int32_t) * ((size_t)ns + 1)));
+  MT_HIP(ensure(c->cand_tmp, sizeof(int32_t) * (size_t)cand_tmp_per_slave() * (size_t)std::max(ns, 1)));
   {
     PhaseTimer t(c, MT_T_CAND, st);
     MT_HIP(launch_cand_count(c->box_s.as<double>(), ns, c->box_m.as<double>(), nm, c->vals.as<uint32_t>(),
                              c->cell_start.as<int32_t>(), c->cell_end.as<int32_t>(), g, c->params.delta,
-                             c->cand_cnt.as<int32_t>(), st));
+                             c->cand_cnt.as<int32_t>(), c->cand_tmp.as<int32_t>(), st));
     MT_HIP(scan_exclusive(c->cand_cnt.as<int32_t>(), c->cand_off.as<int32_t>(), ns, c->scan_tmp, st));
   }
   int32_t ncand32 = 0;
@@ -296,7 +299,8 @@ int mt_build_pairs(mt_ctx* c, int64_t* n_cand_out, int64_t* n_pairs_out, void* s
     PhaseTimer t(c, MT_T_CAND, st);
     MT_HIP(launch_cand_fill(c->box_s.as<double>(), ns, c->box_m.as<double>(), nm, c->vals.as<uint32_t>(),
                             c->cell_start.as<int32_t>(), c->cell_end.as<int32_t>(), g, c->params.delta,
-                            c->cand_off.as<int32_t>(), c->cand_s.as<int32_t>(), c->cand_m.as<int32_t>(), st));
+                            c->cand_tmp.as<int32_t>(), c->cand_off.as<int32_t>(), c->cand_s.as<int32_t>(),
+                            c->cand_m.as<int32_t>(), st));
   }
 
   // clip every candidate; compact the pairs
@@ -304,7 +308,7 @@ int mt_build_pairs(mt_ctx* c, int64_t* n_cand_out, int64_t* n_pairs_out, void* s
   Counters* cnt = c->counters.as<Counters>();
   {
     PhaseTimer t(c, MT_T_CLIP, st);
-    MT_HIP(launch_clip_count(S, M, kp, c->cand_s.as<int32_t>(), c->cand_m.as<int32_t>(), n_cand,
+    MT_HIP(launch_clip_count(S, M, c->sdata.as<double>(), kp, c->cand_s.as<int32_t>(), c->cand_m.as<int32_t>(), n_cand,
                              c->cand_nv.as<uint8_t>(), c->cand_flag.as<int32_t>(), cnt, st));
   }
   {
@@ -394,6 +398,7 @@ int mt_csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, void* stream) {
   PhaseTimer timer(c, MT_T_PATTERN, st);
   int rc = build_incidence(c, S, c->inc_cnt, c->inc_off, c->inc_cur, c->inc_list, st);
   if (rc) return rc;
+  // rows whose candidate lists exceed the per-thread LDS segment get global scratch
   MT_HIP(ensure(c->rawD_cnt, sizeof(int32_t) * ((size_t)n + 1)));
   MT_HIP(ensure(c->rawM_cnt, sizeof(int32_t) * ((size_t)n + 1)));
   MT_HIP(ensure(c->rawD_off, sizeof(int32_t) * ((size_t)n + 1)));
@@ -409,14 +414,16 @@ int mt_csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, void* stream) {
   if (tot[0] < 0 || tot[1] < 0) return fail(MT_ECAPACITY, "mt_csr_pattern: more than 2^31 block entries");
   MT_HIP(ensure(c->rawD, sizeof(int32_t) * (size_t)tot[0]));
   MT_HIP(ensure(c->rawM, sizeof(int32_t) * (size_t)tot[1]));
+  MT_HIP(ensure(c->pat_keep, sizeof(int32_t) * (size_t)pattern_keep_per_row() * (size_t)std::max(n, 1)));
   MT_HIP(ensure(c->D_cnt, sizeof(int32_t) * ((size_t)n + 1)));
   MT_HIP(ensure(c->M_cnt, sizeof(int32_t) * ((size_t)n + 1)));
   MT_HIP(ensure(c->D_rowptr, sizeof(int32_t) * ((size_t)n + 1)));
   MT_HIP(ensure(c->M_rowptr, sizeof(int32_t) * ((size_t)n + 1)));
-  MT_HIP(launch_raw_fill(c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(), n, c->pair_off.as<int32_t>(),
-                         c->pair_m.as<int32_t>(), S.conn, M.conn, c->rawD_off.as<int32_t>(), c->rawD.as<int32_t>(),
-                         c->rawM_off.as<int32_t>(), c->rawM.as<int32_t>(), c->D_cnt.as<int32_t>(),
-                         c->M_cnt.as<int32_t>(), st));
+  MT_HIP(launch_pattern_rows(false, c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(), n, c->pair_off.as<int32_t>(),
+                             c->pair_m.as<int32_t>(), S.conn, M.conn, c->rawD_off.as<int32_t>(), c->rawD.as<int32_t>(),
+                             c->rawM_off.as<int32_t>(), c->rawM.as<int32_t>(), c->D_cnt.as<int32_t>(),
+                             c->M_cnt.as<int32_t>(), nullptr, nullptr, nullptr, nullptr, c->pat_keep.as<int32_t>(),
+                             st));
   MT_HIP(scan_exclusive(c->D_cnt.as<int32_t>(), c->D_rowptr.as<int32_t>(), n, c->scan_tmp, st));
   MT_HIP(scan_exclusive(c->M_cnt.as<int32_t>(), c->M_rowptr.as<int32_t>(), n, c->scan_tmp, st));
   MT_HIP(hipMemcpyAsync(&tot[0], c->D_rowptr.as<int32_t>() + n, 4, hipMemcpyDeviceToHost, st));
@@ -426,10 +433,11 @@ int mt_csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, void* stream) {
   c->nnz_M = tot[1];
   MT_HIP(ensure(c->D_col, sizeof(int32_t) * (size_t)c->nnz_D));
   MT_HIP(ensure(c->M_col, sizeof(int32_t) * (size_t)c->nnz_M));
-  MT_HIP(launch_csr_cols(c->rawD_off.as<int32_t>(), c->rawD.as<int32_t>(), c->D_rowptr.as<int32_t>(), n,
-                         c->D_col.as<int32_t>(), st));
-  MT_HIP(launch_csr_cols(c->rawM_off.as<int32_t>(), c->rawM.as<int32_t>(), c->M_rowptr.as<int32_t>(), n,
-                         c->M_col.as<int32_t>(), st));
+  MT_HIP(launch_pattern_rows(true, c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(), n, c->pair_off.as<int32_t>(),
+                             c->pair_m.as<int32_t>(), S.conn, M.conn, c->rawD_off.as<int32_t>(), c->rawD.as<int32_t>(),
+                             c->rawM_off.as<int32_t>(), c->rawM.as<int32_t>(), nullptr, nullptr,
+                             c->D_rowptr.as<int32_t>(), c->M_rowptr.as<int32_t>(), c->D_col.as<int32_t>(),
+                             c->M_col.as<int32_t>(), c->pat_keep.as<int32_t>(), st));
   MT_HIP(ensure(c->posD, sizeof(int32_t) * 16 * (size_t)S.n_el));
   MT_HIP(ensure(c->posM, sizeof(int32_t) * 16 * (size_t)c->n_pairs));
   MT_HIP(launch_posD(S.conn, S.n_el, c->pair_off.as<int32_t>(), c->D_rowptr.as<int32_t>(), c->D_col.as<int32_t>(),

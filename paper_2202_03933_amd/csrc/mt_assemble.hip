@@ -4,6 +4,7 @@
 // or gradient entry (node) is owned by one thread that sums its
 // contributions in a fixed order (incident elements ascending, then pairs in
 // (slave, master) order), so results are bitwise reproducible.
+#include "mt_geometry.h"
 #include "mt_internal.h"
 #include "mt_rows.h"
 
@@ -12,6 +13,8 @@ namespace mt {
 namespace {
 
 constexpr int BS = 256;
+constexpr int PB = 128;   // block of the pattern kernels
+constexpr int PCAP = 64;  // per-thread LDS segment of the pattern kernels (ints)
 
 __global__ __launch_bounds__(BS) void k_inc_count(const int32_t* __restrict__ conn, int32_t n_el, int32_t* cnt) {
   const int e = blockIdx.x * BS + threadIdx.x;
@@ -54,8 +57,8 @@ __global__ __launch_bounds__(BS) void k_inc_sort(const int32_t* __restrict__ off
 
 __global__ __launch_bounds__(BS) void k_raw_count(const int32_t* __restrict__ inc_off,
                                                    const int32_t* __restrict__ inc_list, int32_t n,
-                                                   const int32_t* __restrict__ pair_off, int32_t* rawD_cnt,
-                                                   int32_t* rawM_cnt) {
+                                                   const int32_t* __restrict__ pair_off, int32_t* rawD_big,
+                                                   int32_t* rawM_big) {
   const int a = blockIdx.x * BS + threadIdx.x;
   if (a >= n) return;
   int d = 0, m = 0;
@@ -67,63 +70,105 @@ __global__ __launch_bounds__(BS) void k_raw_count(const int32_t* __restrict__ in
       m += 4 * np;
     }
   }
-  rawD_cnt[a] = d;
-  rawM_cnt[a] = m;
+  // candidate lists longer than the per-thread LDS segment go to global scratch
+  rawD_big[a] = d > PCAP ? d : 0;
+  rawM_big[a] = m > PCAP ? m : 0;
 }
 
-// Sort a segment ascending and drop duplicates; returns the unique count.
-__device__ int sort_unique(int32_t* v, int n) {
+// Sort a strided segment ascending and drop duplicates; returns the count.
+__device__ int sort_unique(int32_t* v, int n, int stride) {
   for (int i = 1; i < n; ++i) {
-    const int x = v[i];
+    const int x = v[i * stride];
     int j = i - 1;
-    while (j >= 0 && v[j] > x) {
-      v[j + 1] = v[j];
+    while (j >= 0 && v[j * stride] > x) {
+      v[(j + 1) * stride] = v[j * stride];
       --j;
     }
-    v[j + 1] = x;
+    v[(j + 1) * stride] = x;
   }
   int u = 0;
   for (int i = 0; i < n; ++i)
-    if (u == 0 || v[u - 1] != v[i]) v[u++] = v[i];
+    if (u == 0 || v[(u - 1) * stride] != v[i * stride]) v[(u++) * stride] = v[i * stride];
   return u;
 }
 
-__global__ __launch_bounds__(BS) void k_raw_fill(const int32_t* __restrict__ inc_off,
-                                                  const int32_t* __restrict__ inc_list, int32_t n,
-                                                  const int32_t* __restrict__ pair_off,
-                                                  const int32_t* __restrict__ pair_m,
-                                                  const int32_t* __restrict__ conn_s,
-                                                  const int32_t* __restrict__ conn_m,
-                                                  const int32_t* __restrict__ rawD_off, int32_t* rawD,
-                                                  const int32_t* __restrict__ rawM_off, int32_t* rawM,
-                                                  int32_t* D_cnt, int32_t* M_cnt) {
-  const int a = blockIdx.x * BS + threadIdx.x;
-  if (a >= n) return;
-  int32_t* rd = rawD + rawD_off[a];
-  int32_t* rm = rawM + rawM_off[a];
-  int nd = 0, nm = 0;
+// Column candidates of row a: for D the nodes of every incident slave element
+// that has pairs, for M the master nodes of every pair of those elements.
+template <bool MCOLS>
+__device__ int gather_row(int a, const int32_t* __restrict__ inc_off, const int32_t* __restrict__ inc_list,
+                          const int32_t* __restrict__ pair_off, const int32_t* __restrict__ pair_m,
+                          const int32_t* __restrict__ conn_s, const int32_t* __restrict__ conn_m, int32_t* v,
+                          int stride) {
+  int c = 0;
   for (int i = inc_off[a]; i < inc_off[a + 1]; ++i) {
     const int e = inc_list[i] >> 2;
     const int p0 = pair_off[e], p1 = pair_off[e + 1];
     if (p1 == p0) continue;
-    const int4 c = reinterpret_cast<const int4*>(conn_s)[e];
-    rd[nd++] = c.x; rd[nd++] = c.y; rd[nd++] = c.z; rd[nd++] = c.w;
-    for (int p = p0; p < p1; ++p) {
-      const int4 q = reinterpret_cast<const int4*>(conn_m)[pair_m[p]];
-      rm[nm++] = q.x; rm[nm++] = q.y; rm[nm++] = q.z; rm[nm++] = q.w;
+    if (!MCOLS) {
+      const int4 q = reinterpret_cast<const int4*>(conn_s)[e];
+      v[(c++) * stride] = q.x; v[(c++) * stride] = q.y; v[(c++) * stride] = q.z; v[(c++) * stride] = q.w;
+    } else {
+      for (int p = p0; p < p1; ++p) {
+        const int4 q = reinterpret_cast<const int4*>(conn_m)[pair_m[p]];
+        v[(c++) * stride] = q.x; v[(c++) * stride] = q.y; v[(c++) * stride] = q.z; v[(c++) * stride] = q.w;
+      }
     }
   }
-  D_cnt[a] = sort_unique(rd, nd);
-  M_cnt[a] = sort_unique(rm, nm);
+  return c;
 }
 
-__global__ __launch_bounds__(BS) void k_csr_cols(const int32_t* __restrict__ raw_off, const int32_t* __restrict__ raw,
-                                                  const int32_t* __restrict__ rowptr, int32_t n, int32_t* col) {
-  const int a = blockIdx.x * BS + threadIdx.x;
+// Row patterns of D and M.  Each thread gathers its row's candidates into a
+// lane-interleaved LDS segment (or a global scratch segment when longer than
+// PCAP), sorts and deduplicates them.  The count pass writes the row lengths
+// and keeps rows of at most KD (D) / KM (M) columns in lane-interleaved
+// scratch keep[i * n + a]; the fill pass copies those and recomputes the rest.
+constexpr int KD = 16;
+constexpr int KM = 32;
+
+template <bool FILL>
+__global__ __launch_bounds__(PB) void k_pattern_rows(const int32_t* __restrict__ inc_off,
+                                                      const int32_t* __restrict__ inc_list, int32_t n,
+                                                      const int32_t* __restrict__ pair_off,
+                                                      const int32_t* __restrict__ pair_m,
+                                                      const int32_t* __restrict__ conn_s,
+                                                      const int32_t* __restrict__ conn_m,
+                                                      const int32_t* __restrict__ bigD_off, int32_t* bigD,
+                                                      const int32_t* __restrict__ bigM_off, int32_t* bigM,
+                                                      int32_t* D_cnt, int32_t* M_cnt,
+                                                      const int32_t* __restrict__ D_rowptr,
+                                                      const int32_t* __restrict__ M_rowptr, int32_t* D_col,
+                                                      int32_t* M_col, int32_t* keepD, int32_t* keepM) {
+  __shared__ int32_t lds[PCAP * PB];
+  const int a = blockIdx.x * PB + threadIdx.x;
   if (a >= n) return;
-  const int32_t* r = raw + raw_off[a];
-  const int b = rowptr[a], c = rowptr[a + 1] - b;
-  for (int i = 0; i < c; ++i) col[b + i] = r[i];
+  for (int mode = 0; mode < 2; ++mode) {
+    const int kcap = mode ? KM : KD;
+    int32_t* keep = (mode ? keepM : keepD) + a;
+    if (FILL) {
+      const int32_t* rp = mode ? M_rowptr : D_rowptr;
+      const int u = rp[a + 1] - rp[a];
+      if (u <= kcap) {
+        int32_t* col = (mode ? M_col : D_col) + rp[a];
+        for (int i = 0; i < u; ++i) col[i] = keep[(int64_t)i * n];
+        continue;
+      }
+    }
+    const int32_t* boff = mode ? bigM_off : bigD_off;
+    const bool big = boff[a + 1] > boff[a];
+    int32_t* v = big ? (mode ? bigM : bigD) + boff[a] : lds + threadIdx.x;
+    const int stride = big ? 1 : PB;
+    const int c = mode ? gather_row<true>(a, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m, v, stride)
+                       : gather_row<false>(a, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m, v, stride);
+    const int u = sort_unique(v, c, stride);
+    if (!FILL) {
+      (mode ? M_cnt : D_cnt)[a] = u;
+      if (u <= kcap)
+        for (int i = 0; i < u; ++i) keep[(int64_t)i * n] = v[i * stride];
+    } else {
+      int32_t* col = (mode ? M_col : D_col) + (mode ? M_rowptr : D_rowptr)[a];
+      for (int i = 0; i < u; ++i) col[i] = v[i * stride];
+    }
+  }
 }
 
 __device__ __forceinline__ int find_col(const int32_t* __restrict__ col, int lo, int hi, int key) {
@@ -168,9 +213,12 @@ __global__ __launch_bounds__(BS) void k_posM(const int32_t* __restrict__ conn_s,
   }
 }
 
-// One thread per slave node (row): zero the row, then add the local blocks of
-// every pair of every incident element in a fixed order.
-__global__ __launch_bounds__(BS) void k_assemble(const int32_t* __restrict__ inc_off,
+// One thread per slave node (row): the row is accumulated in a per-thread
+// LDS segment (lane-interleaved) in a fixed order and written once.
+constexpr int AB = 128;   // block of the assembly kernel
+constexpr int ACAP = 32;  // per-thread accumulator entries (D + M of one row)
+
+__global__ __launch_bounds__(AB) void k_assemble(const int32_t* __restrict__ inc_off,
                                                   const int32_t* __restrict__ inc_list, int32_t n,
                                                   const int32_t* __restrict__ pair_off,
                                                   const int32_t* __restrict__ D_rowptr,
@@ -179,10 +227,11 @@ __global__ __launch_bounds__(BS) void k_assemble(const int32_t* __restrict__ inc
                                                   const int32_t* __restrict__ posM, const double* __restrict__ blk,
                                                   int64_t stride, double* __restrict__ D_val,
                                                   double* __restrict__ M_val, double* __restrict__ gap) {
-  const int a = blockIdx.x * BS + threadIdx.x;
+  __shared__ double acc[ACAP * AB];
+  const int a = xcd_tile(blockIdx.x, gridDim.x) * AB + threadIdx.x;
   if (a >= n) return;
-  assemble_row(a, inc_off, inc_list, pair_off, D_rowptr, M_rowptr, posD, n_s_el, posM, blk, stride, D_val, M_val,
-               gap);
+  assemble_row_acc(a, inc_off, inc_list, pair_off, D_rowptr, M_rowptr, posD, n_s_el, posM, blk, stride, D_val,
+                   M_val, gap, acc + threadIdx.x, AB, ACAP);
 }
 
 __global__ __launch_bounds__(BS) void k_grad_slave(const int32_t* __restrict__ inc_off,
@@ -240,28 +289,34 @@ hipError_t launch_inc_sort(const int32_t* off, int32_t n_nodes, int32_t* list, h
 }
 
 hipError_t launch_raw_count(const int32_t* inc_off, const int32_t* inc_list, int32_t n_nodes,
-                            const int32_t* pair_off, int32_t* rawD_cnt, int32_t* rawM_cnt, hipStream_t s) {
+                            const int32_t* pair_off, int32_t* rawD_big, int32_t* rawM_big, hipStream_t s) {
   if (n_nodes == 0) return hipSuccess;
-  k_raw_count<<<grid_of(n_nodes), BS, 0, s>>>(inc_off, inc_list, n_nodes, pair_off, rawD_cnt, rawM_cnt);
+  k_raw_count<<<grid_of(n_nodes), BS, 0, s>>>(inc_off, inc_list, n_nodes, pair_off, rawD_big, rawM_big);
   return hipGetLastError();
 }
 
-hipError_t launch_raw_fill(const int32_t* inc_off, const int32_t* inc_list, int32_t n_nodes, const int32_t* pair_off,
-                           const int32_t* pair_m, const int32_t* conn_s, const int32_t* conn_m,
-                           const int32_t* rawD_off, int32_t* rawD, const int32_t* rawM_off, int32_t* rawM,
-                           int32_t* D_cnt, int32_t* M_cnt, hipStream_t s) {
+hipError_t launch_pattern_rows(bool fill, const int32_t* inc_off, const int32_t* inc_list, int32_t n_nodes,
+                               const int32_t* pair_off, const int32_t* pair_m, const int32_t* conn_s,
+                               const int32_t* conn_m, const int32_t* bigD_off, int32_t* bigD, const int32_t* bigM_off,
+                               int32_t* bigM, int32_t* D_cnt, int32_t* M_cnt, const int32_t* D_rowptr,
+                               const int32_t* M_rowptr, int32_t* D_col, int32_t* M_col, int32_t* keep,
+                               hipStream_t s) {
   if (n_nodes == 0) return hipSuccess;
-  k_raw_fill<<<grid_of(n_nodes), BS, 0, s>>>(inc_off, inc_list, n_nodes, pair_off, pair_m, conn_s, conn_m, rawD_off,
-                                             rawD, rawM_off, rawM, D_cnt, M_cnt);
+  const unsigned g = (unsigned)((n_nodes + PB - 1) / PB);
+  int32_t* keepD = keep;
+  int32_t* keepM = keep + (int64_t)KD * n_nodes;
+  if (fill)
+    k_pattern_rows<true><<<g, PB, 0, s>>>(inc_off, inc_list, n_nodes, pair_off, pair_m, conn_s, conn_m, bigD_off,
+                                          bigD, bigM_off, bigM, D_cnt, M_cnt, D_rowptr, M_rowptr, D_col, M_col, keepD,
+                                          keepM);
+  else
+    k_pattern_rows<false><<<g, PB, 0, s>>>(inc_off, inc_list, n_nodes, pair_off, pair_m, conn_s, conn_m, bigD_off,
+                                           bigD, bigM_off, bigM, D_cnt, M_cnt, D_rowptr, M_rowptr, D_col, M_col,
+                                           keepD, keepM);
   return hipGetLastError();
 }
 
-hipError_t launch_csr_cols(const int32_t* raw_off, const int32_t* raw, const int32_t* rowptr, int32_t n_rows,
-                           int32_t* col, hipStream_t s) {
-  if (n_rows == 0) return hipSuccess;
-  k_csr_cols<<<grid_of(n_rows), BS, 0, s>>>(raw_off, raw, rowptr, n_rows, col);
-  return hipGetLastError();
-}
+int pattern_keep_per_row() { return KD + KM; }
 
 hipError_t launch_posD(const int32_t* conn_s, int32_t n_s_el, const int32_t* pair_off, const int32_t* rowptr,
                        const int32_t* col, int32_t* posD, hipStream_t s) {
@@ -282,7 +337,7 @@ hipError_t launch_assemble(const int32_t* inc_off, const int32_t* inc_list, int3
                            const int32_t* posM, const double* blk, int64_t stride, double* D_val, double* M_val,
                            double* gap, hipStream_t s) {
   if (n_nodes == 0) return hipSuccess;
-  k_assemble<<<grid_of(n_nodes), BS, 0, s>>>(inc_off, inc_list, n_nodes, pair_off, D_rowptr, M_rowptr, posD, n_s_el,
+  k_assemble<<<xcd_grid((unsigned)((n_nodes + AB - 1) / AB)), AB, 0, s>>>(inc_off, inc_list, n_nodes, pair_off, D_rowptr, M_rowptr, posD, n_s_el,
                                              posM, blk, stride, D_val, M_val, gap);
   return hipGetLastError();
 }

@@ -36,8 +36,9 @@ __global__ __launch_bounds__(BSC) void k_pair_bwd(MeshPtrs S, int32_t n_s, MeshP
                                                    const double* __restrict__ W_D, const double* __restrict__ W_M,
                                                    const double* __restrict__ w_g, double* __restrict__ gpair,
                                                    int64_t stride, Counters* cnt) {
-  __shared__ double su[2 * CAP * BSC], sv[2 * CAP * BSC];
-  __shared__ uint8_t sl[2 * CAP * BSC], se[2 * CAP * BSC];
+  __shared__ double su[CAPT * BSC], sv[CAPT * BSC];
+  __shared__ uint8_t sl[CAPT * BSC], se[CAPT * BSC];
+  __shared__ double sau[CAP0 * BSC], sav[CAP0 * BSC];
   const int64_t p = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * BSC + threadIdx.x;
   if (p >= n_pairs) return;
   const int s = pair_s[p];
@@ -50,7 +51,7 @@ __global__ __launch_bounds__(BSC) void k_pair_bwd(MeshPtrs S, int32_t n_s, MeshP
   LdsPoly<true> P{su + threadIdx.x, sv + threadIdx.x, sl + threadIdx.x, se + threadIdx.x, BSC};
   double Xsb[4][3], Xmb[4][3];
   unsigned noconv = 0;
-  pair_backward<NQ>(Xs, Xm, kp, P, WD, WM, wg, Xsb, Xmb, noconv);
+  pair_backward<NQ>(Xs, Xm, kp, P, sau + threadIdx.x, sav + threadIdx.x, WD, WM, wg, Xsb, Xmb, noconv);
 #pragma unroll
   for (int k = 0; k < 4; ++k)
 #pragma unroll

@@ -96,7 +96,7 @@ template <int BSZ, int NQ, bool DUAL>
 __global__ __launch_bounds__(BSZ) void k_batch_fwd(const BatchInst* __restrict__ inst,
                                                     const WorkItem* __restrict__ items,
                                                     const int32_t* __restrict__ qbeg, int32_t* qnext, Counters* cnt) {
-  __shared__ double su[2 * CAP * BSZ], sv[2 * CAP * BSZ];
+  __shared__ double su[CAPT * BSZ], sv[CAPT * BSZ];
   __shared__ int s_item;
   unsigned noconv = 0;
   int qi = 0;
@@ -127,8 +127,9 @@ template <int BSZ, int NQ>
 __global__ __launch_bounds__(BSZ) void k_batch_bwd(const BatchInst* __restrict__ inst,
                                                     const WorkItem* __restrict__ items,
                                                     const int32_t* __restrict__ qbeg, int32_t* qnext, Counters* cnt) {
-  __shared__ double su[2 * CAP * BSZ], sv[2 * CAP * BSZ];
-  __shared__ uint8_t sl[2 * CAP * BSZ], se[2 * CAP * BSZ];
+  __shared__ double su[CAPT * BSZ], sv[CAPT * BSZ];
+  __shared__ uint8_t sl[CAPT * BSZ], se[CAPT * BSZ];
+  __shared__ double sau[CAP0 * BSZ], sav[CAP0 * BSZ];
   __shared__ int s_item;
   unsigned noconv = 0;
   int qi = 0;
@@ -153,7 +154,7 @@ __global__ __launch_bounds__(BSZ) void k_batch_bwd(const BatchInst* __restrict__
       wg[2] = I.w_g[csn.z];
       wg[3] = I.w_g[csn.w];
       double Xsb[4][3], Xmb[4][3];
-      pair_backward<NQ>(Xs, Xm, I.kp, P, WD, WM, wg, Xsb, Xmb, noconv);
+      pair_backward<NQ>(Xs, Xm, I.kp, P, sau + threadIdx.x, sav + threadIdx.x, WD, WM, wg, Xsb, Xmb, noconv);
 #pragma unroll
       for (int k = 0; k < 4; ++k)
 #pragma unroll
@@ -168,14 +169,17 @@ __global__ __launch_bounds__(BSZ) void k_batch_bwd(const BatchInst* __restrict__
 }
 
 // Row phases: one block per item of ROWS_PER_ITEM rows of one instance.
+constexpr int BATCH_ACAP = 24;  // per-thread row accumulator of the batched assembly
+
 __global__ __launch_bounds__(ROWS_PER_ITEM) void k_batch_assemble(const BatchInst* __restrict__ inst,
                                                                    const WorkItem* __restrict__ items) {
+  __shared__ double acc[BATCH_ACAP * ROWS_PER_ITEM];
   const WorkItem w = items[blockIdx.x];
   const int a = w.begin + threadIdx.x;
   if (a >= w.end) return;
   const BatchInst& I = inst[w.inst];
-  assemble_row(a, I.inc_off, I.inc_list, I.pair_off, I.D_rowptr, I.M_rowptr, I.posD, I.n_s_el, I.posM, I.blk,
-               I.n_pairs, I.D_val, I.M_val, I.gap);
+  assemble_row_acc(a, I.inc_off, I.inc_list, I.pair_off, I.D_rowptr, I.M_rowptr, I.posD, I.n_s_el, I.posM, I.blk,
+                   I.n_pairs, I.D_val, I.M_val, I.gap, acc + threadIdx.x, ROWS_PER_ITEM, BATCH_ACAP);
 }
 
 __global__ __launch_bounds__(ROWS_PER_ITEM) void k_batch_grad_rows(const BatchInst* __restrict__ inst,
@@ -214,10 +218,10 @@ BwdFn pick_bwd(int bsz, int nq) {
   return bwd_kernel<64>(nq);
 }
 
-// LDS of one block (bytes): forward uses 2 x CAP vertices x 16 B per lane,
-// backward adds 2 x CAP label bytes x 2 per lane.
+// LDS of one block (bytes): forward uses CAPT vertices x 16 B per lane,
+// backward adds two label bytes per vertex slot and CAP0 adjoint slots.
 int max_blocks_per_cu(int bsz, bool backward) {
-  const int per_block = bsz * 2 * CAP * (16 + (backward ? 2 : 0)) + 64;
+  const int per_block = bsz * (CAPT * 16 + (backward ? CAPT * 2 + CAP0 * 16 : 0)) + 64;
   return std::max(1, (160 * 1024) / per_block);
 }
 
@@ -555,7 +559,7 @@ int mt_batch_autotune(mt_batch* b, mt_batch_tuning* out, void* stream) {
   struct Cand { int block, bpc, bucket_mul; };
   std::vector<Cand> cands;
   for (int block : {64, 128, 256})
-    for (int bpc : {1, 2, 4, 5})
+    for (int bpc : {1, 2, 4, 6, 8})
       for (int mul : {1, 4, 16})
         if (bpc <= max_blocks_per_cu(block, false)) cands.push_back({block, bpc, mul});
   hipEvent_t e0, e1;

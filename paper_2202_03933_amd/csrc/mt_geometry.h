@@ -16,7 +16,14 @@
 
 namespace mt {
 
-constexpr int CAP = 16;  // working capacity of a clip polygon (vertices)
+// Working capacities of the two clip buffers (vertices): buffer 0 holds the
+// slave polygon and the outputs of clip stages 2 and 4, buffer 1 the outputs
+// of stages 1 and 3.  A convex quad clipped by k half planes has at most
+// 4 + k vertices; two vertices of headroom absorb near-duplicates from
+// rounding.  A stage exceeding its buffer marks the candidate degenerate.
+constexpr int CAP0 = 10;
+constexpr int CAP1 = 9;
+constexpr int CAPT = CAP0 + CAP1;  // LDS vertex slots per lane
 
 struct V2 {
   double u, v;
@@ -104,7 +111,7 @@ __device__ __forceinline__ double quad_fan_area(const V2 p[4]) {
 __device__ __forceinline__ double linf(double du, double dv) { return fmax(fabs(du), fabs(dv)); }
 
 // ---- per-lane polygon storage in LDS ---------------------------------------
-// Two ping-pong buffers of CAP vertices per lane, lane-interleaved so that a
+// Two ping-pong buffers (CAP0 + CAP1 vertices) per lane, lane-interleaved so that a
 // wavefront touching vertex i of its polygons hits consecutive addresses.
 // With labels, each vertex also carries its provenance (slave node k:
 // 0x80|k, else the two lines it lies on, (la << 4) | lb, line ids 0..3 =
@@ -117,7 +124,7 @@ struct LdsPoly {
   uint8_t* vl;
   uint8_t* el;
   int bs;
-  __device__ __forceinline__ int at(int b, int i) const { return (b * CAP + i) * bs; }
+  __device__ __forceinline__ int at(int b, int i) const { return ((b ? CAP0 : 0) + i) * bs; }
 };
 
 // Clip the slave polygon S (counter-clockwise) by the master polygon Mo
@@ -146,6 +153,7 @@ __device__ __forceinline__ int clip_polygon(const V2 S[4], const V2 Mo[4], const
     const V2 b = Mo[(l + 1) & 3];
     const double dbu = b.u - a.u, dbv = b.v - a.v;
     const int nxt = cur ^ 1;
+    const int cap = nxt ? CAP1 : CAP0;
     double Pu = P.u[P.at(cur, 0)], Pv = P.v[P.at(cur, 0)];
     uint8_t Pl = 0, Pe = 0;
     if (LAB) { Pl = P.vl[P.at(cur, 0)]; Pe = P.el[P.at(cur, 0)]; }
@@ -168,14 +176,14 @@ __device__ __forceinline__ int clip_polygon(const V2 S[4], const V2 Mo[4], const
       const bool pin = cP >= 0.0;
       const bool ein = cE >= 0.0;
       if (pin) {
-        if (k == CAP) { ovf = true; return 0; }
+        if (k == cap) { ovf = true; return 0; }
         P.u[P.at(nxt, k)] = Pu;
         P.v[P.at(nxt, k)] = Pv;
         if (LAB) { P.vl[P.at(nxt, k)] = Pl; P.el[P.at(nxt, k)] = Pe; }
         ++k;
       }
       if (pin != ein) {
-        if (k == CAP) { ovf = true; return 0; }
+        if (k == cap) { ovf = true; return 0; }
         const double t = cP / (cP - cE);
         P.u[P.at(nxt, k)] = Pu + t * (Eu - Pu);
         P.v[P.at(nxt, k)] = Pv + t * (Ev - Pv);
@@ -267,32 +275,59 @@ enum : int { PS_DEGEN_SLAVE = 1, PS_DEGEN_MASTER = 2, PS_OVERFLOW = 4 };
 // Mo = master polygon walked counter-clockwise (flip: Mo = (M0, M3, M2, M1),
 // i.e. Mo[l] = Mn[(4 - l) % 4]; otherwise Mo = Mn),
 // polygon in buffer `res` with `n` vertices (0: not a pair).
-template <bool LAB>
-__device__ __forceinline__ int pair_geometry(const double Xs[4][3], const double Xm[4][3], const double f[12],
-                                             double eps_d, double eps_a, V2 S[4], V2 Mn[4], double hs[4],
-                                             double hm[4], bool& flip, const LdsPoly<LAB>& P, int& res,
-                                             int& status) {
-  status = 0;
-  res = 0;
-  flip = false;
+// Slave-only part of the pair geometry: projected slave nodes, their area and
+// the longest projected edge (max-norm), from the slave frame f.
+__device__ __forceinline__ void slave_setup(const double Xs[4][3], const double f[12], V2 S[4], double hs[4],
+                                            double& As, double& hmax) {
 #pragma unroll
   for (int k = 0; k < 4; ++k) project(Xs[k], f, S[k], hs[k]);
-#pragma unroll
-  for (int k = 0; k < 4; ++k) project(Xm[k], f, Mn[k], hm[k]);
-  const double As = quad_fan_area(S);
-  if (!(As > 0.0)) { status = PS_DEGEN_SLAVE; return 0; }
-  double hmax = 0.0;
+  As = quad_fan_area(S);
+  hmax = 0.0;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int e = (k + 1) & 3;
     hmax = fmax(hmax, linf(S[e].u - S[k].u, S[e].v - S[k].v));
   }
+}
+
+// Master part: projection of the master nodes onto the slave plane,
+// orientation, clip and cleanup, given the slave setup.
+template <bool LAB>
+__device__ __forceinline__ int pair_clip(const V2 S[4], double As, double hmax, const double Xm[4][3],
+                                         const double f[12], double eps_d, double eps_a, V2 Mn[4], double hm[4],
+                                         bool& flip, const LdsPoly<LAB>& P, int& res, int& status) {
+  status = 0;
+  res = 0;
+  flip = false;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) project(Xm[k], f, Mn[k], hm[k]);
+  if (!(As > 0.0)) { status = PS_DEGEN_SLAVE; return 0; }
   const double tol_d = eps_d * hmax;
   const double tol_a = eps_a * As;
   const double Am = quad_fan_area(Mn);
   if (fabs(Am) <= tol_a) { status = PS_DEGEN_MASTER; return 0; }
   flip = Am < 0.0;
   V2 Mo[4] = {Mn[0], flip ? Mn[3] : Mn[1], Mn[2], flip ? Mn[1] : Mn[3]};
+  // Separating-line quick exit (exact): every slave vertex strictly outside
+  // one master edge line, or every master vertex strictly outside one slave
+  // edge line, means no overlap.  Same side test as the clip.
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      const V2 a = side == 0 ? Mo[l] : S[l];
+      const V2 b = side == 0 ? Mo[(l + 1) & 3] : S[(l + 1) & 3];
+      const double dbu = b.u - a.u, dbv = b.v - a.v;
+      bool all_out = true;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const V2 q = side == 0 ? S[k] : Mo[k];
+        const double c = dbu * (q.v - a.v) - dbv * (q.u - a.u);
+        all_out = all_out && !(c >= 0.0);
+      }
+      if (all_out) return 0;
+    }
+  }
   bool ovf;
   int n = clip_polygon<LAB>(S, Mo, P, res, ovf);
   if (ovf) { status = PS_OVERFLOW; return 0; }
@@ -302,6 +337,20 @@ __device__ __forceinline__ int pair_geometry(const double Xs[4][3], const double
   if (!(Ap > tol_a)) return 0;
   return n;
 }
+
+template <bool LAB>
+__device__ __forceinline__ int pair_geometry(const double Xs[4][3], const double Xm[4][3], const double f[12],
+                                             double eps_d, double eps_a, V2 S[4], V2 Mn[4], double hs[4],
+                                             double hm[4], bool& flip, const LdsPoly<LAB>& P, int& res,
+                                             int& status) {
+  double As, hmax;
+  slave_setup(Xs, f, S, hs, As, hmax);
+  return pair_clip<LAB>(S, As, hmax, Xm, f, eps_d, eps_a, Mn, hm, flip, P, res, status);
+}
+
+// Precomputed slave data for the candidate pass, structure-of-arrays
+// sd[k * n + e]: frame (12), projected nodes u (4), v (4), area, max edge.
+constexpr int SD_N = 22;
 
 // ---- quadrature ------------------------------------------------------------
 

@@ -95,6 +95,7 @@ struct mt_ctx {
 
   // element preparation
   mt::Buf box_s, box_m;    // [6][n_el] lo xyz, hi xyz
+  mt::Buf sdata;           // [SD_N][n_s_el] precomputed slave frame and polygon
   mt::Buf reduce;          // PrepReduce
   mt::Buf counters;        // Counters
   // binning
@@ -102,6 +103,7 @@ struct mt_ctx {
   mt::Buf cell_start, cell_end;
   // candidates
   mt::Buf cand_cnt;        // [n_s_el + 1]
+  mt::Buf cand_tmp;        // [CTMP][n_s_el] candidates kept by the count pass
   mt::Buf cand_off;        // [n_s_el + 1]
   mt::Buf cand_s, cand_m;  // [n_cand]
   mt::Buf cand_nv;         // uint8 [n_cand]
@@ -116,6 +118,7 @@ struct mt_ctx {
   mt::Buf minc_cnt, minc_off, minc_cur, minc_list; // master node -> (element*4 + local)
   mt::Buf rawD_cnt, rawD_off, rawD;                // per-row raw column lists
   mt::Buf rawM_cnt, rawM_off, rawM;
+  mt::Buf pat_keep;        // per-row column lists kept between the pattern passes
   mt::Buf D_cnt, D_rowptr, D_col;
   mt::Buf M_cnt, M_rowptr, M_col;
   mt::Buf posD;            // [16][n_s_el]
@@ -141,7 +144,7 @@ hipError_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 hipError_t fill_f64(double* p, double v, int64_t n, hipStream_t s);
 
 // ---- search (mt_search.hip) ------------------------------------------------
-hipError_t launch_prep(const DeviceMesh& m, bool slave, double* box, PrepReduce* red, hipStream_t s);
+hipError_t launch_prep(const DeviceMesh& m, bool slave, double* box, double* sd, PrepReduce* red, hipStream_t s);
 hipError_t launch_init_reduce(PrepReduce* red, hipStream_t s);
 void grid_from_reduce(const PrepReduce& r, double delta, double bin_size, Grid& g);
 hipError_t launch_master_keys(const double* box_m, int32_t n_m, Grid g, uint32_t* keys, uint32_t* vals,
@@ -150,13 +153,15 @@ hipError_t launch_cell_ranges(const uint32_t* keys, int32_t n, int32_t* start, i
                               hipStream_t s);
 hipError_t launch_cand_count(const double* box_s, int32_t n_s, const double* box_m, int32_t n_m,
                              const uint32_t* mvals, const int32_t* start, const int32_t* end, Grid g,
-                             double delta, int32_t* count, hipStream_t s);
+                             double delta, int32_t* count, int32_t* tmp, hipStream_t s);
 hipError_t launch_cand_fill(const double* box_s, int32_t n_s, const double* box_m, int32_t n_m,
                             const uint32_t* mvals, const int32_t* start, const int32_t* end, Grid g,
-                            double delta, const int32_t* off, int32_t* cand_s, int32_t* cand_m, hipStream_t s);
+                            double delta, const int32_t* tmp, const int32_t* off, int32_t* cand_s, int32_t* cand_m,
+                            hipStream_t s);
+int cand_tmp_per_slave();
 
 // ---- pairs (mt_pairs.hip) ----------------------------------------------------
-hipError_t launch_clip_count(const DeviceMesh& S, const DeviceMesh& M, const KParams& kp, const int32_t* cand_s, const int32_t* cand_m,
+hipError_t launch_clip_count(const DeviceMesh& S, const DeviceMesh& M, const double* sdata, const KParams& kp, const int32_t* cand_s, const int32_t* cand_m,
                              int64_t n_cand, uint8_t* nv, int32_t* flag, Counters* cnt, hipStream_t s);
 hipError_t launch_compact(const int32_t* cand_s, const int32_t* cand_m, const uint8_t* cand_nv,
                           const int32_t* scan, int64_t n_cand, int32_t* pair_s, int32_t* pair_m,
@@ -173,14 +178,14 @@ hipError_t launch_inc_fill(const int32_t* conn, int32_t n_el, const int32_t* off
                            int32_t* list, hipStream_t s);
 hipError_t launch_inc_sort(const int32_t* off, int32_t n_nodes, int32_t* list, hipStream_t s);
 hipError_t launch_raw_count(const int32_t* inc_off, const int32_t* inc_list, int32_t n_nodes,
-                            const int32_t* pair_off, int32_t* rawD_cnt, int32_t* rawM_cnt, hipStream_t s);
-hipError_t launch_raw_fill(const int32_t* inc_off, const int32_t* inc_list, int32_t n_nodes,
-                           const int32_t* pair_off, const int32_t* pair_m, const int32_t* conn_s,
-                           const int32_t* conn_m, const int32_t* rawD_off, int32_t* rawD,
-                           const int32_t* rawM_off, int32_t* rawM, int32_t* D_cnt, int32_t* M_cnt,
-                           hipStream_t s);
-hipError_t launch_csr_cols(const int32_t* raw_off, const int32_t* raw, const int32_t* rowptr,
-                           int32_t n_rows, int32_t* col, hipStream_t s);
+                            const int32_t* pair_off, int32_t* rawD_big, int32_t* rawM_big, hipStream_t s);
+hipError_t launch_pattern_rows(bool fill, const int32_t* inc_off, const int32_t* inc_list, int32_t n_nodes,
+                               const int32_t* pair_off, const int32_t* pair_m, const int32_t* conn_s,
+                               const int32_t* conn_m, const int32_t* bigD_off, int32_t* bigD, const int32_t* bigM_off,
+                               int32_t* bigM, int32_t* D_cnt, int32_t* M_cnt, const int32_t* D_rowptr,
+                               const int32_t* M_rowptr, int32_t* D_col, int32_t* M_col, int32_t* keep,
+                               hipStream_t s);
+int pattern_keep_per_row();
 hipError_t launch_posD(const int32_t* conn_s, int32_t n_s_el, const int32_t* pair_off,
                        const int32_t* rowptr, const int32_t* col, int32_t* posD, hipStream_t s);
 hipError_t launch_posM(const int32_t* conn_s, const int32_t* conn_m, const int32_t* pair_s,

@@ -175,9 +175,12 @@ __device__ __forceinline__ void intersect_adjoint(V2 A1, V2 A2, V2 B1, V2 B2, do
 // clip is recomputed with vertex provenance; reverse mode runs through the
 // quadrature, the inverse maps (implicit-function derivative), the clip
 // vertices (line intersections), the projection and the slave frame.
+// Vertex adjoints of the clip polygon live in a per-lane LDS slot array
+// (au, av: CAP0 lane-interleaved entries, lane stride P.bs).
 template <int NQ>
 __device__ __forceinline__ void pair_backward(const double Xs[4][3], const double Xm[4][3], const KParams& kp,
-                                              const LdsPoly<true>& P, const double WD[16], const double WM[16],
+                                              const LdsPoly<true>& P, double* au, double* av,
+                                              const double WD[16], const double WM[16],
                                               const double wg[4], double Xsb[4][3], double Xmb[4][3],
                                               unsigned& noconv) {
   double f[12];
@@ -197,11 +200,10 @@ __device__ __forceinline__ void pair_backward(const double Xs[4][3], const doubl
     hsb[k] = 0.0;
     hmb[k] = 0.0;
   }
-  // adjoints of the clip vertices live in the free LDS buffer
-  const int vb = res ^ 1;
+  const int bs = P.bs;
   for (int i = 0; i < n; ++i) {
-    P.u[P.at(vb, i)] = 0.0;
-    P.v[P.at(vb, i)] = 0.0;
+    au[i * bs] = 0.0;
+    av[i * bs] = 0.0;
   }
   const Map2 ms = bilinear_map(S), mm = bilinear_map(Mn);
   {
@@ -281,18 +283,18 @@ __device__ __forceinline__ void pair_backward(const double Xs[4][3], const doubl
       }
       // triangle area
       const double hA = 0.5 * Atb;
-      P.u[P.at(vb, 0)] += pb0u + hA * (v1 - v2);
-      P.v[P.at(vb, 0)] += pb0v + hA * (u2 - u1);
-      P.u[P.at(vb, i)] += pb1u + hA * (v2 - v0);
-      P.v[P.at(vb, i)] += pb1v - hA * (u2 - u0);
-      P.u[P.at(vb, i + 1)] += pb2u - hA * (v1 - v0);
-      P.v[P.at(vb, i + 1)] += pb2v + hA * (u1 - u0);
+      au[0] += pb0u + hA * (v1 - v2);
+      av[0] += pb0v + hA * (u2 - u1);
+      au[i * bs] += pb1u + hA * (v2 - v0);
+      av[i * bs] += pb1v - hA * (u2 - u0);
+      au[(i + 1) * bs] += pb2u - hA * (v1 - v0);
+      av[(i + 1) * bs] += pb2v + hA * (u1 - u0);
     }
   }
 
   // clip vertices -> projected nodes, through each vertex's provenance
   for (int i = 0; i < n; ++i) {
-    const double xu = P.u[P.at(vb, i)], xv = P.v[P.at(vb, i)];
+    const double xu = au[i * bs], xv = av[i * bs];
     const uint8_t lab = P.vl[P.at(res, i)];
     if (lab & 0x80) {
       const int k = lab & 3;

@@ -13,6 +13,7 @@ namespace mt {
 namespace {
 
 constexpr int BSC = 64;   // clip / integrate block: one wavefront
+constexpr int CPT = 4;    // candidates per thread in the candidate pass
 constexpr int BS = 256;
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x) {
@@ -21,37 +22,49 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x)
   return x;
 }
 
-__global__ __launch_bounds__(BSC) void k_clip_count(const double* __restrict__ xs, const double* __restrict__ ys,
-                                                     const double* __restrict__ zs, const int32_t* __restrict__ cs,
-                                                     int32_t n_s, const double* __restrict__ xm,
-                                                     const double* __restrict__ ym, const double* __restrict__ zm,
-                                                     const int32_t* __restrict__ cm, KParams kp, const int32_t* __restrict__ cand_s,
+// Candidate pass: projection of the master element onto the precomputed
+// slave plane, clip and cleanup; writes the vertex count (0: not a pair).
+__global__ __launch_bounds__(BSC) void k_clip_count(const double* __restrict__ sd, int32_t n_s,
+                                                     const double* __restrict__ xm, const double* __restrict__ ym,
+                                                     const double* __restrict__ zm, const int32_t* __restrict__ cm,
+                                                     KParams kp, const int32_t* __restrict__ cand_s,
                                                      const int32_t* __restrict__ cand_m, int64_t n_cand,
                                                      uint8_t* __restrict__ nv_out, int32_t* __restrict__ flag,
                                                      Counters* cnt) {
-  __shared__ double su[2 * CAP * BSC], sv[2 * CAP * BSC];
+  __shared__ double su[CAPT * BSC], sv[CAPT * BSC];
   __shared__ unsigned int hist[20];
   if (threadIdx.x < 20) hist[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t c = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * BSC + threadIdx.x;
+  const int64_t tile = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * (BSC * CPT);
+#pragma unroll 1
+  for (int it = 0; it < CPT; ++it) {
+  const int64_t c = tile + it * BSC + threadIdx.x;
   if (c < n_cand) {
     const int s = cand_s[c], m = cand_m[c];
-    double f[12], Xs[4][3], Xm[4][3];
-    load_nodes(xs, ys, zs, load_conn(cs, s), Xs);
+    double f[12], Xm[4][3];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) f[k] = sd[(int64_t)k * n_s + s];
+    V2 S[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      S[k].u = sd[(int64_t)(12 + k) * n_s + s];
+      S[k].v = sd[(int64_t)(16 + k) * n_s + s];
+    }
+    const double As = sd[(int64_t)20 * n_s + s], hmax = sd[(int64_t)21 * n_s + s];
     load_nodes(xm, ym, zm, load_conn(cm, m), Xm);
-    slave_frame(Xs, f);
     LdsPoly<false> P{su + threadIdx.x, sv + threadIdx.x, nullptr, nullptr, BSC};
-    V2 S[4], Mn[4];
-    double hs[4], hm[4];
+    V2 Mn[4];
+    double hm[4];
     int res, st;
     bool flip;
-    const int n = pair_geometry<false>(Xs, Xm, f, kp.eps_d, kp.eps_a, S, Mn, hs, hm, flip, P, res, st);
+    const int n = pair_clip<false>(S, As, hmax, Xm, f, kp.eps_d, kp.eps_a, Mn, hm, flip, P, res, st);
     nv_out[c] = (uint8_t)n;
     flag[c] = n >= 3 ? 1 : 0;
     atomicAdd(&hist[n], 1u);
     if (st & PS_DEGEN_SLAVE) atomicAdd(&hist[17], 1u);
     if (st & PS_DEGEN_MASTER) atomicAdd(&hist[18], 1u);
     if (st & PS_OVERFLOW) atomicAdd(&hist[19], 1u);
+  }
   }
   __syncthreads();
   if (threadIdx.x < 20 && hist[threadIdx.x]) {
@@ -95,7 +108,7 @@ __global__ __launch_bounds__(BSC) void k_pair_fwd(MeshPtrs S, MeshPtrs M, KParam
                                                    const int32_t* __restrict__ pair_s,
                                                    const int32_t* __restrict__ pair_m, int64_t n_pairs,
                                                    double* __restrict__ blk, int64_t stride, Counters* cnt) {
-  __shared__ double su[2 * CAP * BSC], sv[2 * CAP * BSC];
+  __shared__ double su[CAPT * BSC], sv[CAPT * BSC];
   const int64_t p = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * BSC + threadIdx.x;
   unsigned noconv = 0;
   if (p < n_pairs) {
@@ -118,13 +131,13 @@ __global__ __launch_bounds__(BSC) void k_pair_fwd(MeshPtrs S, MeshPtrs M, KParam
 
 }  // namespace
 
-hipError_t launch_clip_count(const DeviceMesh& S, const DeviceMesh& M, const KParams& kp,
+hipError_t launch_clip_count(const DeviceMesh& S, const DeviceMesh& M, const double* sdata, const KParams& kp,
                              const int32_t* cand_s, const int32_t* cand_m, int64_t n_cand, uint8_t* nv,
                              int32_t* flag, Counters* cnt, hipStream_t s) {
   if (n_cand == 0) return hipSuccess;
-  k_clip_count<<<xcd_grid((unsigned)((n_cand + BSC - 1) / BSC)), BSC, 0, s>>>(S.x, S.y, S.z, S.conn, S.n_el, M.x, M.y, M.z,
-                                                                    M.conn, kp, cand_s, cand_m, n_cand, nv,
-                                                                    flag, cnt);
+  k_clip_count<<<xcd_grid((unsigned)((n_cand + BSC * CPT - 1) / (BSC * CPT))), BSC, 0, s>>>(sdata, S.n_el, M.x, M.y, M.z, M.conn,
+                                                                              kp, cand_s, cand_m, n_cand, nv, flag,
+                                                                              cnt);
   return hipGetLastError();
 }
 

@@ -42,6 +42,58 @@ __device__ __forceinline__ void assemble_row(int a, const int32_t* __restrict__ 
   gap[a] = g;
 }
 
+// Same as assemble_row, accumulating the row in a per-thread scratch segment
+// acc[i * stride] (D entries first, then M) and writing it once; rows longer
+// than cap entries fall back to assemble_row.
+__device__ __forceinline__ void assemble_row_acc(int a, const int32_t* __restrict__ inc_off,
+                                                 const int32_t* __restrict__ inc_list,
+                                                 const int32_t* __restrict__ pair_off,
+                                                 const int32_t* __restrict__ D_rowptr,
+                                                 const int32_t* __restrict__ M_rowptr,
+                                                 const int32_t* __restrict__ posD, int32_t n_s_el,
+                                                 const int32_t* __restrict__ posM, const double* __restrict__ blk,
+                                                 int64_t stride, double* __restrict__ D_val,
+                                                 double* __restrict__ M_val, double* __restrict__ gap, double* acc,
+                                                 int astride, int cap) {
+  const int d0 = D_rowptr[a], d1 = D_rowptr[a + 1];
+  const int m0 = M_rowptr[a], m1 = M_rowptr[a + 1];
+  const int nd = d1 - d0, nm = m1 - m0;
+  if (nd + nm > cap) {
+    assemble_row(a, inc_off, inc_list, pair_off, D_rowptr, M_rowptr, posD, n_s_el, posM, blk, stride, D_val, M_val,
+                 gap);
+    return;
+  }
+  for (int i = 0; i < nd + nm; ++i) acc[i * astride] = 0.0;
+  double g = 0.0;
+  const int moff = nd - m0;  // M position q accumulates at acc[(q + moff) * astride]
+  for (int i = inc_off[a]; i < inc_off[a + 1]; ++i) {
+    const int e = inc_list[i] >> 2, j = inc_list[i] & 3;
+    const int p0 = pair_off[e], p1 = pair_off[e + 1];
+    if (p0 == p1) continue;
+    int pd[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pd[k] = posD[(int64_t)(j * 4 + k) * n_s_el + e] - d0;
+    for (int p = p0; p < p1; ++p) {
+      double vd[4], vm[4];
+      int pm[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        vd[k] = blk[(int64_t)(j * 4 + k) * stride + p];
+        vm[k] = blk[(int64_t)(16 + j * 4 + k) * stride + p];
+        pm[k] = posM[(int64_t)(j * 4 + k) * stride + p] + moff;
+      }
+      g += blk[(int64_t)(32 + j) * stride + p];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc[pd[k] * astride] += vd[k];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc[pm[k] * astride] += vm[k];
+    }
+  }
+  for (int i = 0; i < nd; ++i) D_val[d0 + i] = acc[i * astride];
+  for (int i = 0; i < nm; ++i) M_val[m0 + i] = acc[(nd + i) * astride];
+  gap[a] = g;
+}
+
 // Gradient of slave node a (structure-of-arrays gX[3 * n]).
 __device__ __forceinline__ void grad_slave_row(int a, int32_t n, const int32_t* __restrict__ inc_off,
                                                const int32_t* __restrict__ inc_list,

@@ -3,6 +3,7 @@
 // every slave element from its own bin and the 26 neighbouring bins
 // (Alg. 2 and the bin-sizing rule of Sec. "Geometrically motivated binning").
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 
 #include "mt_geometry.h"
@@ -45,60 +46,81 @@ __device__ __forceinline__ T wave_min(T x) {
   return x;
 }
 
+// Element preparation: bounding boxes, the grid reductions (largest box
+// extent, longest slave edge, bounding box of all element boxes) and, for
+// slave elements, the precomputed frame and projected polygon of the
+// candidate pass.  Grid-stride loop; one atomic per block and quantity.
 __global__ __launch_bounds__(BS) void k_prep(const double* __restrict__ x, const double* __restrict__ y,
                                               const double* __restrict__ z, const int32_t* __restrict__ conn,
                                               int32_t n_el, int32_t n_nodes, int slave,
-                                              double* __restrict__ box, PrepReduce* red) {
-  const int e = blockIdx.x * BS + threadIdx.x;
-  const bool live = e < n_el;
+                                              double* __restrict__ box, double* __restrict__ sd, PrepReduce* red) {
+  __shared__ double sh[BS / 64][8];
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
   double ext = 0.0, edge = 0.0;
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  if (live) {
+  for (int e = blockIdx.x * BS + threadIdx.x; e < n_el; e += gridDim.x * BS) {
     const int4 c = load_conn(conn, e);
     const bool ok = c.x >= 0 && c.y >= 0 && c.z >= 0 && c.w >= 0 && c.x < n_nodes && c.y < n_nodes &&
                     c.z < n_nodes && c.w < n_nodes;
     if (!ok) {
-      atomicOr(&red->bad_index, 1);
-    } else {
-      double X[4][3];
-      load_nodes(x, y, z, c, X);
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        lo[d] = fmin(fmin(X[0][d], X[1][d]), fmin(X[2][d], X[3][d]));
-        hi[d] = fmax(fmax(X[0][d], X[1][d]), fmax(X[2][d], X[3][d]));
-        box[(int64_t)d * n_el + e] = lo[d];
-        box[(int64_t)(3 + d) * n_el + e] = hi[d];
-        ext = fmax(ext, hi[d] - lo[d]);
-      }
-      if (slave) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int k1 = (k + 1) & 3;
-          const double a = X[k1][0] - X[k][0], b = X[k1][1] - X[k][1], cc = X[k1][2] - X[k][2];
-          edge = fmax(edge, sqrt(a * a + b * b + cc * cc));
-        }
-      }
+      bad = 1;
+      continue;
     }
-  }
-  ext = wave_max(ext);
-  edge = wave_max(edge);
-  double l3[3], h3[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    l3[d] = wave_min(lo[d]);
-    h3[d] = wave_max(hi[d]);
-  }
-  if ((threadIdx.x & 63) == 0) {
-    atomicMax(&red->emax_bits, (unsigned long long)__double_as_longlong(ext));
-    if (slave) atomicMax(&red->edge_bits, (unsigned long long)__double_as_longlong(edge));
+    double X[4][3];
+    load_nodes(x, y, z, c, X);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-      if (l3[d] <= h3[d]) {
-        atomicMin(&red->lo_key[d], order_key(l3[d]));
-        atomicMax(&red->hi_key[d], order_key(h3[d]));
+      const double l = fmin(fmin(X[0][d], X[1][d]), fmin(X[2][d], X[3][d]));
+      const double h = fmax(fmax(X[0][d], X[1][d]), fmax(X[2][d], X[3][d]));
+      box[(int64_t)d * n_el + e] = l;
+      box[(int64_t)(3 + d) * n_el + e] = h;
+      ext = fmax(ext, h - l);
+      lo[d] = fmin(lo[d], l);
+      hi[d] = fmax(hi[d], h);
+    }
+    if (slave) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int k1 = (k + 1) & 3;
+        const double a = X[k1][0] - X[k][0], b = X[k1][1] - X[k][1], cc = X[k1][2] - X[k][2];
+        edge = fmax(edge, sqrt(a * a + b * b + cc * cc));
       }
+      double f[12], hs[4], As, hmax;
+      V2 S[4];
+      slave_frame(X, f);
+      slave_setup(X, f, S, hs, As, hmax);
+#pragma unroll
+      for (int k = 0; k < 12; ++k) sd[(int64_t)k * n_el + e] = f[k];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        sd[(int64_t)(12 + k) * n_el + e] = S[k].u;
+        sd[(int64_t)(16 + k) * n_el + e] = S[k].v;
+      }
+      sd[(int64_t)20 * n_el + e] = As;
+      sd[(int64_t)21 * n_el + e] = hmax;
     }
   }
+  double v[8] = {ext, edge, -lo[0], -lo[1], -lo[2], hi[0], hi[1], hi[2]};
+#pragma unroll
+  for (int k = 0; k < 8; ++k) v[k] = wave_max(v[k]);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) sh[w][k] = v[k];
+  __syncthreads();
+  if (threadIdx.x < 8) {
+    double m = sh[0][threadIdx.x];
+#pragma unroll
+    for (int i = 1; i < BS / 64; ++i) m = fmax(m, sh[i][threadIdx.x]);
+    const int k = threadIdx.x;
+    if (k == 0) atomicMax(&red->emax_bits, (unsigned long long)__double_as_longlong(m));
+    else if (k == 1) { if (slave) atomicMax(&red->edge_bits, (unsigned long long)__double_as_longlong(m)); }
+    else if (k < 5) { if (-m <= INFINITY && m > -INFINITY) atomicMin(&red->lo_key[k - 2], order_key(-m)); }
+    else { if (m > -INFINITY) atomicMax(&red->hi_key[k - 5], order_key(m)); }
+  }
+  if (threadIdx.x == 0 && bad) atomicOr(&red->bad_index, 1);
 }
 
 __global__ void k_init_reduce(PrepReduce* r) {
@@ -167,21 +189,25 @@ __device__ __forceinline__ bool touch(const SlaveBox& s, const double* __restric
   return true;
 }
 
+constexpr int CCAP = 48;  // per-thread LDS segment of the candidate fill (masters)
+constexpr int CTMP = 32;  // candidates per slave kept by the count pass
+
+// Candidates of one slave element: masters of its own and the 26 neighbouring
+// cells whose boxes touch its delta-enlarged box.  The count pass writes the
+// number and keeps the first CTMP in a lane-interleaved scratch array
+// tmp[k * n_s + s]; the fill pass collects them from there (or walks the
+// cells again when there were more), sorts them by master index in a
+// lane-interleaved LDS segment (in place when longer than CCAP) and writes
+// them out.
 template <bool FILL>
-__global__ __launch_bounds__(BS) void k_cand(const double* __restrict__ box_s, int32_t n_s,
-                                              const double* __restrict__ box_m, int32_t n_m,
-                                              const uint32_t* __restrict__ mvals, const int32_t* __restrict__ start,
-                                              const int32_t* __restrict__ end, Grid g, double delta,
-                                              int32_t* __restrict__ count, const int32_t* __restrict__ off,
-                                              int32_t* __restrict__ cand_s, int32_t* __restrict__ cand_m) {
-  const int s = blockIdx.x * BS + threadIdx.x;
-  if (s >= n_s) return;
-  const SlaveBox b = load_box(box_s, n_s, s);
+__device__ __forceinline__ int walk_cells(const SlaveBox& b, const double* __restrict__ box_m, int32_t n_m,
+                                          const uint32_t* __restrict__ mvals, const int32_t* __restrict__ start,
+                                          const int32_t* __restrict__ end, const Grid& g, double delta, int32_t* v,
+                                          int64_t vs, int vcap) {
   int ix[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) ix[d] = cell_coord(0.5 * (b.lo[d] + b.hi[d]), g.lo[d], g.inv_beta[d], g.n[d]);
   int c = 0;
-  const int base = FILL ? off[s] : 0;
   for (int dz = -1; dz <= 1; ++dz) {
     const int zz = ix[2] + dz;
     if (zz < 0 || zz >= g.n[2]) continue;
@@ -196,28 +222,61 @@ __global__ __launch_bounds__(BS) void k_cand(const double* __restrict__ box_s, i
         for (int i = start[cell]; i < i1; ++i) {
           const int m = (int)mvals[i];
           if (touch(b, box_m, n_m, m, delta)) {
-            if (FILL) cand_m[base + c] = m;
+            if (c < vcap) v[c * vs] = m;
             ++c;
           }
         }
       }
     }
   }
-  if (!FILL) {
-    count[s] = c;
-    return;
+  return c;
+}
+
+__global__ __launch_bounds__(BS) void k_cand_count(const double* __restrict__ box_s, int32_t n_s,
+                                                    const double* __restrict__ box_m, int32_t n_m,
+                                                    const uint32_t* __restrict__ mvals,
+                                                    const int32_t* __restrict__ start, const int32_t* __restrict__ end,
+                                                    Grid g, double delta, int32_t* __restrict__ count,
+                                                    int32_t* __restrict__ tmp) {
+  const int s = blockIdx.x * BS + threadIdx.x;
+  if (s >= n_s) return;
+  const SlaveBox b = load_box(box_s, n_s, s);
+  count[s] = walk_cells<false>(b, box_m, n_m, mvals, start, end, g, delta, tmp + s, n_s, CTMP);
+}
+
+__global__ __launch_bounds__(BS) void k_cand_fill(const double* __restrict__ box_s, int32_t n_s,
+                                                   const double* __restrict__ box_m, int32_t n_m,
+                                                   const uint32_t* __restrict__ mvals,
+                                                   const int32_t* __restrict__ start, const int32_t* __restrict__ end,
+                                                   Grid g, double delta, const int32_t* __restrict__ tmp,
+                                                   const int32_t* __restrict__ off, int32_t* __restrict__ cand_s,
+                                                   int32_t* __restrict__ cand_m) {
+  __shared__ int32_t lds[CCAP * BS];
+  const int s = blockIdx.x * BS + threadIdx.x;
+  if (s >= n_s) return;
+  const int base = off[s];
+  const int c = off[s + 1] - base;
+  const bool in_lds = c <= CCAP;
+  int32_t* v = in_lds ? lds + threadIdx.x : cand_m + base;
+  const int vs = in_lds ? BS : 1;
+  if (c <= CTMP) {
+    for (int i = 0; i < c; ++i) v[i * vs] = tmp[(int64_t)i * n_s + s];
+  } else {
+    walk_cells<true>(load_box(box_s, n_s, s), box_m, n_m, mvals, start, end, g, delta, v, vs, c);
   }
-  // insertion sort of this slave's candidates by master index
   for (int i = 1; i < c; ++i) {
-    const int v = cand_m[base + i];
+    const int x = v[i * vs];
     int j = i - 1;
-    while (j >= 0 && cand_m[base + j] > v) {
-      cand_m[base + j + 1] = cand_m[base + j];
+    while (j >= 0 && v[j * vs] > x) {
+      v[(j + 1) * vs] = v[j * vs];
       --j;
     }
-    cand_m[base + j + 1] = v;
+    v[(j + 1) * vs] = x;
   }
-  for (int i = 0; i < c; ++i) cand_s[base + i] = s;
+  for (int i = 0; i < c; ++i) {
+    if (in_lds) cand_m[base + i] = v[i * vs];
+    cand_s[base + i] = s;
+  }
 }
 
 }  // namespace
@@ -227,9 +286,10 @@ hipError_t launch_init_reduce(PrepReduce* red, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_prep(const DeviceMesh& m, bool slave, double* box, PrepReduce* red, hipStream_t s) {
+hipError_t launch_prep(const DeviceMesh& m, bool slave, double* box, double* sd, PrepReduce* red, hipStream_t s) {
   if (m.n_el == 0) return hipSuccess;
-  k_prep<<<(m.n_el + BS - 1) / BS, BS, 0, s>>>(m.x, m.y, m.z, m.conn, m.n_el, m.n_nodes, slave ? 1 : 0, box, red);
+  const int grid = std::min(2048, (m.n_el + BS - 1) / BS);
+  k_prep<<<grid, BS, 0, s>>>(m.x, m.y, m.z, m.conn, m.n_el, m.n_nodes, slave ? 1 : 0, box, sd, red);
   return hipGetLastError();
 }
 
@@ -278,20 +338,22 @@ hipError_t launch_cell_ranges(const uint32_t* keys, int32_t n, int32_t* start, i
 
 hipError_t launch_cand_count(const double* box_s, int32_t n_s, const double* box_m, int32_t n_m,
                              const uint32_t* mvals, const int32_t* start, const int32_t* end, Grid g,
-                             double delta, int32_t* count, hipStream_t s) {
+                             double delta, int32_t* count, int32_t* tmp, hipStream_t s) {
   if (n_s == 0) return hipSuccess;
-  k_cand<false><<<(n_s + BS - 1) / BS, BS, 0, s>>>(box_s, n_s, box_m, n_m, mvals, start, end, g, delta, count,
-                                                   nullptr, nullptr, nullptr);
+  k_cand_count<<<(n_s + BS - 1) / BS, BS, 0, s>>>(box_s, n_s, box_m, n_m, mvals, start, end, g, delta, count, tmp);
   return hipGetLastError();
 }
 
 hipError_t launch_cand_fill(const double* box_s, int32_t n_s, const double* box_m, int32_t n_m,
                             const uint32_t* mvals, const int32_t* start, const int32_t* end, Grid g,
-                            double delta, const int32_t* off, int32_t* cand_s, int32_t* cand_m, hipStream_t s) {
+                            double delta, const int32_t* tmp, const int32_t* off, int32_t* cand_s, int32_t* cand_m,
+                            hipStream_t s) {
   if (n_s == 0) return hipSuccess;
-  k_cand<true><<<(n_s + BS - 1) / BS, BS, 0, s>>>(box_s, n_s, box_m, n_m, mvals, start, end, g, delta, nullptr,
-                                                  off, cand_s, cand_m);
+  k_cand_fill<<<(n_s + BS - 1) / BS, BS, 0, s>>>(box_s, n_s, box_m, n_m, mvals, start, end, g, delta, tmp, off,
+                                                 cand_s, cand_m);
   return hipGetLastError();
 }
+
+int cand_tmp_per_slave() { return CTMP; }
 
 }  // namespace mt

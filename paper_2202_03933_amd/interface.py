@@ -104,18 +104,28 @@ class MortarInterface:
         return s, m, nv
 
     def csr_pattern(self):
+        """Build the CSR patterns of D and M; the arrays are copied out on
+        first access of D_rowptr / D_col / M_rowptr / M_col."""
         a, b = ctypes.c_int64(), ctypes.c_int64()
         C.check(C.lib().mt_csr_pattern(self.h, ctypes.byref(a), ctypes.byref(b), _stream(self.stream)))
         self.nnz_D, self.nnz_M = a.value, b.value
-        n1 = self.n_slave_nodes + 1
-        dev = self.device
-        self.D_rowptr = torch.empty(n1, dtype=torch.int32, device=dev)
-        self.M_rowptr = torch.empty(n1, dtype=torch.int32, device=dev)
-        self.D_col = torch.empty(self.nnz_D, dtype=torch.int32, device=dev)
-        self.M_col = torch.empty(self.nnz_M, dtype=torch.int32, device=dev)
-        C.check(C.lib().mt_get_csr(self.h, _ptr(self.D_rowptr), _ptr(self.D_col), _ptr(self.M_rowptr),
-                                   _ptr(self.M_col), _stream(self.stream)))
+        self._csr = None
         return self.nnz_D, self.nnz_M
+
+    def _fetch_csr(self):
+        if getattr(self, "_csr", None) is None:
+            n1 = self.n_slave_nodes + 1
+            dev = self.device
+            t = (torch.empty(n1, dtype=torch.int32, device=dev), torch.empty(self.nnz_D, dtype=torch.int32, device=dev),
+                 torch.empty(n1, dtype=torch.int32, device=dev), torch.empty(self.nnz_M, dtype=torch.int32, device=dev))
+            C.check(C.lib().mt_get_csr(self.h, _ptr(t[0]), _ptr(t[1]), _ptr(t[2]), _ptr(t[3]), _stream(self.stream)))
+            self._csr = t
+        return self._csr
+
+    D_rowptr = property(lambda self: self._fetch_csr()[0])
+    D_col = property(lambda self: self._fetch_csr()[1])
+    M_rowptr = property(lambda self: self._fetch_csr()[2])
+    M_col = property(lambda self: self._fetch_csr()[3])
 
     def setup(self):
         self.build_pairs()
