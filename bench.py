@@ -24,6 +24,49 @@ sys.path.insert(0, ROOT)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 HBM_PEAK_GBS = 8000.0
+# Adjoint of one inverse bilinear map by the implicit-function theorem:
+# Jacobian at the solution (8), transposed 2x2 solve (12), node adjoints (16),
+# point adjoint (2).
+IFT_FLOPS = 38
+
+# Kernel name -> (library phase timer, source files whose hash identifies the
+# kernel version, committed traffic summary).
+KERNELS = {
+    "pair_fwd": ("k_pair_fwd", ["mt_pairs.hip", "mt_pair_eval.h", "mt_geometry.h"],
+                 "profiles/k_pair_fwd_wavy1024_traffic.md"),
+    "pair_bwd": ("k_pair_bwd", ["mt_backward.hip", "mt_pair_eval.h", "mt_geometry.h"],
+                 "profiles/k_pair_bwd_wavy1024_traffic.md"),
+}
+
+
+def kernel_source_hash(files):
+    import hashlib
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_2202_03933_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(kernel):
+    """HBM bytes per launch recorded by a committed rocprofv3 --pmc summary,
+    or None when the summary is missing or the kernel sources changed since."""
+    _, files, path = KERNELS[kernel]
+    full = os.path.join(ROOT, path)
+    if not os.path.exists(full):
+        return None
+    rec = {}
+    with open(full) as f:
+        for line in f:
+            if line.startswith("- ") and ":" in line:
+                k, v = line[2:].split(":", 1)
+                rec[k.strip()] = v.strip().strip("`")
+    if rec.get("source_hash") != kernel_source_hash(files):
+        return None
+    try:
+        return float(rec["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(itf, n_slave_el_sample, seed=3000):
@@ -54,12 +97,16 @@ def cpu_baseline(itf, n_slave_el_sample, seed=3000):
     g24, _ = oracle.pair_grads(sub, itf.master, prm, ps, pm, w)
     oracle.scatter_grads(sub, itf.master, ps, pm, g24)
     t_all = time.perf_counter() - t0
-    # algorithmic flops per pair of the forward evaluation (counted by the
-    # oracle's flop-counting scalar on every 16th pair of the sample)
-    f_clip, f_pair = oracle.count_flops(sub, itf.master, prm, ps[::16], pm[::16])
+    # algorithmic flops per pair (oracle's flop-counting scalar on every 16th
+    # pair of the sample): forward evaluation; backward = forward recompute +
+    # reverse-mode adjoint of every operation outside the inverse maps (cost
+    # model: add/sub 2, mul 4, div 4, sqrt 3) + IFT_FLOPS per inverse map
+    _, f_pair, f_adj, n_inv = oracle.count_flops(sub, itf.master, prm, ps[::16], pm[::16], detail=True)
     f_cand, _ = oracle.count_flops(sub, itf.master, prm, cs[::16], cm[::16])
+    npp = max(1, ps[::16].size)
     return {"pairs": int(ps.size), "t_fwd": t_fwd, "t_all": t_all,
-            "flops_per_pair_fwd": f_pair / max(1, ps[::16].size),
+            "flops_per_pair_fwd": f_pair / npp,
+            "flops_per_pair_bwd": (f_pair + f_adj + IFT_FLOPS * n_inv) / npp,
             "flops_per_candidate_clip": f_cand / max(1, cs[::16].size),
             "sample": f"slave elements 0..{n_slave_el_sample - 1} of the workload (the first "
                       f"{n_slave_el_sample // 1024} rows of the 1024x1024 slave grid) against the whole master "
@@ -204,20 +251,24 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(itf, args.cpu_sample)
 
-    # roofline of the dominant kernel: the forward pair-integration kernel is
-    # FP64-VALU bound; algorithmic flops per launch = oracle-counted flops per
-    # pair x pairs.
-    dominant = max(("pair_fwd", "pair_bwd", "clip"), key=lambda k: per_step[k])
-    flops_pair = cpu["flops_per_pair_fwd"] if cpu else None
-    roof = None
-    if flops_pair is not None:
-        launch_s = per_launch["pair_fwd"] * 1e-3
-        achieved = flops_pair * n_pairs / launch_s / 1e12
-        roof = {"bound": "alu", "kernel": "k_pair_fwd (segment integration, one launch per forward)",
-                "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_VECTOR_PEAK_TFLOPS, "traffic": None,
-                "flops_per_pair": flops_pair, "launch_ms": per_launch["pair_fwd"],
-                "dominant_kernel_by_time": dominant}
+    # roofline of the dominant pair kernel (both are FP64-VALU bound):
+    # achieved = oracle-counted algorithmic flops per pair x pairs / average
+    # launch time from the library's event timers over the timed steps
+    def roofline(k):
+        fp = cpu[f"flops_per_pair_{k[5:]}"] if cpu else None
+        if fp is None:
+            return None
+        launch_s = per_launch[k] * 1e-3
+        achieved = fp * n_pairs / launch_s / 1e12
+        traffic = recorded_traffic(k)
+        return {"bound": "alu", "kernel": KERNELS[k][0], "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+                "traffic": traffic, "traffic_unit": "bytes per launch" if traffic else None,
+                "flops_per_pair": fp, "pairs_per_launch": n_pairs, "launch_ms": per_launch[k]}
+
+    dominant = max(("pair_fwd", "pair_bwd"), key=lambda k: per_step[k])
+    roof = roofline(dominant)
+    other = roofline("pair_bwd" if dominant == "pair_fwd" else "pair_fwd")
     out = {
         "metric": "mortar element pairs integrated/sec (D,M,gap) fwd and fwd+bwd, 1 MI355X",
         "value": n_pairs / (ms_step * 1e-3),
@@ -237,6 +288,7 @@ def main():
         "fwd_pairs_per_s": n_pairs / (fwd_ms * 1e-3),
         "phase_ms_per_step": per_step,
         "roofline": roof,
+        "roofline_other_pair_kernel": other,
         "batched_64_interfaces": batched,
     }
     if cpu:

@@ -6,8 +6,8 @@
  * element methods"): the slave matrix D and the slave x master matrix M of
  * eq. (DiscreteWeakFormInterfaceFlux), plus a weighted gap, by segment-based
  * integration (Alg. 1) over the element pairs found by a bin-based contact
- * search (Alg. 2 and the bin-sizing rule of Sec. "Geometrically motivated
- * binning"), and the gradient of a weighted sum of those outputs with respect
+ * search (Alg. 2 and its bin-sizing rule, Sec. "Distributed storage: going
+ * to large problems"), and the gradient of a weighted sum of those outputs with respect
  * to all nodal coordinates (the linearisation every nonlinear iteration
  * needs, Sec. "Introduction").
  *

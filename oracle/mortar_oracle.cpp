@@ -8,8 +8,9 @@
 // finite element methods"):
 //  * contact search: every (slave, master) element pair whose axis-aligned
 //    bounding boxes overlap once the slave box is enlarged by delta; by brute
-//    force over all pairs, and by Cartesian binning (Sec. "Geometrically
-//    motivated binning", Alg. 2, bin sizing rule below it).
+//    force over all pairs, and by Cartesian binning (Sec. "Distributed
+//    storage: going to large problems", Alg. 2 and the bin sizing rule above
+//    it).
 //  * per pair, the steps of Alg. 1 (Sec. "Evaluation of mortar integrals"):
 //    project both elements onto the auxiliary plane of the slave element
 //    (centre x0, normal n0; Fig. 1 and the piecewise-flat integration the
@@ -83,14 +84,22 @@ template <int N> inline Dual<N> fabs(const Dual<N>& a) { return a.v < 0 ? -a : a
 
 // Flop-counting scalar: one count per add, subtract, multiply, divide and
 // square root executed by the algorithm.  Comparisons, abs, min and max are
-// not counted.
+// not counted.  Operations outside the inverse bilinear maps are also tallied
+// by kind, for the reverse-mode cost model of or_count_flops.
 thread_local uint64_t g_flops = 0;
+thread_local uint64_t g_kind[4] = {0, 0, 0, 0};  // add/sub, mul, div, sqrt outside inverse maps
+thread_local bool g_in_inverse_map = false;
+thread_local uint64_t g_inverse_maps = 0;
+inline void count_op(int kind) {
+  ++g_flops;
+  if (!g_in_inverse_map) ++g_kind[kind];
+}
 struct Cnt { double v; Cnt() : v(0.0) {} Cnt(double x) : v(x) {} };  // NOLINT
 inline double val(const Cnt& a) { return a.v; }
-inline Cnt operator+(Cnt a, Cnt b) { ++g_flops; return Cnt(a.v + b.v); }
-inline Cnt operator-(Cnt a, Cnt b) { ++g_flops; return Cnt(a.v - b.v); }
-inline Cnt operator*(Cnt a, Cnt b) { ++g_flops; return Cnt(a.v * b.v); }
-inline Cnt operator/(Cnt a, Cnt b) { ++g_flops; return Cnt(a.v / b.v); }
+inline Cnt operator+(Cnt a, Cnt b) { count_op(0); return Cnt(a.v + b.v); }
+inline Cnt operator-(Cnt a, Cnt b) { count_op(0); return Cnt(a.v - b.v); }
+inline Cnt operator*(Cnt a, Cnt b) { count_op(1); return Cnt(a.v * b.v); }
+inline Cnt operator/(Cnt a, Cnt b) { count_op(2); return Cnt(a.v / b.v); }
 inline Cnt operator-(Cnt a) { return Cnt(-a.v); }
 inline Cnt operator+(double a, Cnt b) { return Cnt(a) + b; }
 inline Cnt operator+(Cnt a, double b) { return a + Cnt(b); }
@@ -99,7 +108,7 @@ inline Cnt operator-(Cnt a, double b) { return a - Cnt(b); }
 inline Cnt operator*(double a, Cnt b) { return Cnt(a) * b; }
 inline Cnt operator*(Cnt a, double b) { return a * Cnt(b); }
 inline Cnt operator/(Cnt a, double b) { return a / Cnt(b); }
-inline Cnt sqrt(Cnt a) { ++g_flops; return Cnt(std::sqrt(a.v)); }
+inline Cnt sqrt(Cnt a) { count_op(3); return Cnt(std::sqrt(a.v)); }
 inline Cnt fabs(Cnt a) { return Cnt(std::fabs(a.v)); }
 
 using std::fabs;
@@ -308,8 +317,17 @@ Rule make_rule(int which) {
 // Parameter coordinates xi of an in-plane point p on the bilinear map of the
 // projected quad X: Newton's method from xi = 0 on sum_k N_k(xi) X_k = p.
 // Equivalent to projecting p along n0 back onto the element.
+template <class T> struct InverseMapScope {
+  InverseMapScope() {}
+};
+template <> struct InverseMapScope<Cnt> {
+  InverseMapScope() { g_in_inverse_map = true; ++g_inverse_maps; }
+  ~InverseMapScope() { g_in_inverse_map = false; }
+};
+
 template <class T>
 int inverse_bilinear(const P2<T> X[4], const P2<T>& p, const Params& prm, T& x1, T& x2) {
+  InverseMapScope<T> scope;
   x1 = 0.0; x2 = 0.0;
   for (int it = 0; it < prm.newton_maxit; ++it) {
     T N[4], d1[4], d2[4];
@@ -833,14 +851,19 @@ int or_pair_grads(int64_t ns_nodes, const double* Xs, int64_t ns_el, const int32
 // Counted floating-point operations of the pair evaluation over a list of
 // candidates: flops[0] = projection + clip + cleanup of every candidate (the
 // candidate test pass), flops[1] = full evaluation (clip + integration) of
-// every candidate that is a pair.
+// every candidate that is a pair, flops[2] = reverse-mode adjoint flops of
+// those pairs by the standard cost model (adjoint of an add or subtract: 2
+// flops, multiply: 4, divide: 4, square root: 3) over every operation outside
+// the inverse bilinear maps, flops[3] = number of inverse bilinear maps
+// evaluated (each differentiated by the implicit-function theorem instead of
+// through its iterations).
 void or_count_flops(int64_t ns_nodes, const double* Xs, int64_t ns_el, const int32_t* Cs,
                     int64_t nm_nodes, const double* Xm, int64_t nm_el, const int32_t* Cm,
                     const OrParams* op, int64_t n, const int32_t* cs, const int32_t* cm, uint64_t* flops) {
   MeshView S{ns_nodes, Xs, ns_el, Cs}, M{nm_nodes, Xm, nm_el, Cm};
   const Params prm = to_params(op);
   const Rule rule = make_rule(prm.rule);
-  flops[0] = 0; flops[1] = 0;
+  flops[0] = 0; flops[1] = 0; flops[2] = 0; flops[3] = 0;
   for (int64_t i = 0; i < n; ++i) {
     Cnt xs[4][3], xm[4][3];
     load_pair(S, M, cs[i], cm[i], xs, xm);
@@ -850,8 +873,12 @@ void or_count_flops(int64_t ns_nodes, const double* Xs, int64_t ns_el, const int
     flops[0] += g_flops;
     if (o.nv >= 3) {
       g_flops = 0;
+      for (int k = 0; k < 4; ++k) g_kind[k] = 0;
+      g_inverse_maps = 0;
       eval_pair(xs, xm, prm, rule, true, o);
       flops[1] += g_flops;
+      flops[2] += 2 * g_kind[0] + 4 * g_kind[1] + 4 * g_kind[2] + 3 * g_kind[3];
+      flops[3] += g_inverse_maps;
     }
   }
 }

@@ -1,7 +1,8 @@
 // Contact search on the GPU: element preparation, Cartesian bins sorted by
 // radix sort with bin ranges from segment heads, and the candidate lists of
 // every slave element from its own bin and the 26 neighbouring bins
-// (Alg. 2 and the bin-sizing rule of Sec. "Geometrically motivated binning").
+// (Alg. 2 and its bin-sizing rule, Sec. "Distributed storage: going to large
+// problems").
 #include <cmath>
 #include <algorithm>
 #include <cstring>
