@@ -29,9 +29,12 @@ HBM_PEAK_GBS = 8000.0
 # point adjoint (2).
 IFT_FLOPS = 38
 
-# Kernel name -> (library phase timer, source files whose hash identifies the
-# kernel version, committed traffic summary).
+# Library phase timer of a single-kernel phase -> (kernel, source files whose
+# hash identifies the kernel version, committed traffic summary).
 KERNELS = {
+    "clip": ("k_clip_count", ["mt_pairs.hip", "mt_geometry.h"], "profiles/k_clip_count_wavy1024_traffic.md"),
+    "pair_poly": ("k_pair_poly", ["mt_pairs.hip", "mt_pair_eval.h", "mt_geometry.h"],
+                  "profiles/k_pair_poly_wavy1024_traffic.md"),
     "pair_fwd": ("k_pair_fwd", ["mt_pairs.hip", "mt_pair_eval.h", "mt_geometry.h"],
                  "profiles/k_pair_fwd_wavy1024_traffic.md"),
     "pair_bwd": ("k_pair_bwd", ["mt_backward.hip", "mt_pair_eval.h", "mt_geometry.h"],
@@ -97,17 +100,23 @@ def cpu_baseline(itf, n_slave_el_sample, seed=3000):
     g24, _ = oracle.pair_grads(sub, itf.master, prm, ps, pm, w)
     oracle.scatter_grads(sub, itf.master, ps, pm, g24)
     t_all = time.perf_counter() - t0
-    # algorithmic flops per pair (oracle's flop-counting scalar on every 16th
-    # pair of the sample): forward evaluation; backward = forward recompute +
-    # reverse-mode adjoint of every operation outside the inverse maps (cost
-    # model: add/sub 2, mul 4, div 4, sqrt 3) + IFT_FLOPS per inverse map
-    _, f_pair, f_adj, n_inv = oracle.count_flops(sub, itf.master, prm, ps[::16], pm[::16], detail=True)
+    # algorithmic flops (oracle's flop-counting scalar on every 16th pair and
+    # every 16th candidate of the sample).  Per kernel:
+    #   k_clip_count: the candidate pass (frame, projection, clip, cleanup) of
+    #     every candidate;
+    #   k_pair_poly:  the candidate pass of every pair;
+    #   k_pair_fwd:   the pair evaluation minus its candidate pass;
+    #   k_pair_bwd:   that forward recompute + the reverse-mode adjoint of the
+    #     pair evaluation minus that of its candidate pass (cost model: adjoint
+    #     of add/sub 2, mul 4, div 4, sqrt 3) + IFT_FLOPS per inverse map.
+    f_cp, f_pair, f_adj, n_inv, f_cadj = oracle.count_flops(sub, itf.master, prm, ps[::16], pm[::16], detail=True)
     f_cand, _ = oracle.count_flops(sub, itf.master, prm, cs[::16], cm[::16])
     npp = max(1, ps[::16].size)
     return {"pairs": int(ps.size), "t_fwd": t_fwd, "t_all": t_all,
-            "flops_per_pair_fwd": f_pair / npp,
-            "flops_per_pair_bwd": (f_pair + f_adj + IFT_FLOPS * n_inv) / npp,
-            "flops_per_candidate_clip": f_cand / max(1, cs[::16].size),
+            "flops_per_unit": {"clip": f_cand / max(1, cs[::16].size),
+                               "pair_poly": f_cp / npp,
+                               "pair_fwd": (f_pair - f_cp) / npp,
+                               "pair_bwd": (f_pair - f_cp + f_adj - f_cadj + IFT_FLOPS * n_inv) / npp},
             "sample": f"slave elements 0..{n_slave_el_sample - 1} of the workload (the first "
                       f"{n_slave_el_sample // 1024} rows of the 1024x1024 slave grid) against the whole master "
                       f"side: {ps.size} pairs; search + clip + integrate + assemble + gradients"}
@@ -237,8 +246,8 @@ def main():
     ms_step = (t1 - t0) * 1e3 / args.steps
     per_step = {k: v[0] / args.steps for k, v in tim.items()}
     per_launch = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in tim.items()}
-    fwd_ms = sum(per_step[k] for k in ("prep", "bin_sort", "cand", "clip", "compact", "pattern", "pair_fwd",
-                                        "assemble"))
+    fwd_ms = sum(per_step[k] for k in ("prep", "bin_sort", "cand", "clip", "compact", "pattern", "pair_poly",
+                                        "pair_fwd", "assemble"))
 
     if args.calib_copy:
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
@@ -251,24 +260,28 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(itf, args.cpu_sample)
 
-    # roofline of the dominant pair kernel (both are FP64-VALU bound):
-    # achieved = oracle-counted algorithmic flops per pair x pairs / average
-    # launch time from the library's event timers over the timed steps
+    # roofline of the dominant single-kernel phase (all are FP64-VALU or
+    # latency bound): achieved = oracle-counted algorithmic flops per unit x
+    # units per launch / average launch time from the library's event timers
+    # over the timed steps
+    units = {"clip": n_cand, "pair_poly": n_pairs, "pair_fwd": n_pairs, "pair_bwd": n_pairs}
+
     def roofline(k):
-        fp = cpu[f"flops_per_pair_{k[5:]}"] if cpu else None
-        if fp is None:
+        fp = cpu["flops_per_unit"][k] if cpu else None
+        if fp is None or not per_launch.get(k):
             return None
         launch_s = per_launch[k] * 1e-3
-        achieved = fp * n_pairs / launch_s / 1e12
+        achieved = fp * units[k] / launch_s / 1e12
         traffic = recorded_traffic(k)
         return {"bound": "alu", "kernel": KERNELS[k][0], "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
                 "traffic": traffic, "traffic_unit": "bytes per launch" if traffic else None,
-                "flops_per_pair": fp, "pairs_per_launch": n_pairs, "launch_ms": per_launch[k]}
+                "flops_per_unit": fp, "unit_kind": "candidate" if k == "clip" else "pair",
+                "units_per_launch": units[k], "launch_ms": per_launch[k]}
 
-    dominant = max(("pair_fwd", "pair_bwd"), key=lambda k: per_step[k])
+    dominant = max(units, key=lambda k: per_launch.get(k, 0.0))
     roof = roofline(dominant)
-    other = roofline("pair_bwd" if dominant == "pair_fwd" else "pair_fwd")
+    others = {KERNELS[k][0]: roofline(k) for k in units if k != dominant}
     out = {
         "metric": "mortar element pairs integrated/sec (D,M,gap) fwd and fwd+bwd, 1 MI355X",
         "value": n_pairs / (ms_step * 1e-3),
@@ -288,7 +301,7 @@ def main():
         "fwd_pairs_per_s": n_pairs / (fwd_ms * 1e-3),
         "phase_ms_per_step": per_step,
         "roofline": roof,
-        "roofline_other_pair_kernel": other,
+        "roofline_other_kernels": others,
         "batched_64_interfaces": batched,
     }
     if cpu:

@@ -121,7 +121,10 @@ int mt_upload(mt_ctx* ctx, int side, int64_t n_nodes, const double* x, const dou
  * length (device pointers, kept), KEEPING the pair list and CSR pattern: the
  * fixed-topology evaluation a Newton iteration or a gradient check needs.
  * mt_integrate / mt_backward then use the new coordinates; mt_build_pairs
- * recomputes the pairs.  Errors: MT_ESTATE (side not uploaded), MT_EINVAL. */
+ * recomputes the pairs.  Coordinates changed in place (same pointers) must
+ * also be announced with this call before mt_backward, which otherwise
+ * reuses the clip polygons of the last mt_integrate.  Errors: MT_ESTATE
+ * (side not uploaded), MT_EINVAL. */
 int mt_update_coordinates(mt_ctx* ctx, int side, const double* x, const double* y, const double* z,
                           void* stream);
 
@@ -171,8 +174,10 @@ int mt_get_csr(mt_ctx* ctx, int32_t* D_rowptr, int32_t* D_col, int32_t* M_rowptr
                void* stream);
 
 /* Segment-based integration (Alg. 1, triangulation and quadrature steps)
- * and assembly: for every pair, the clip polygon is split into a fan of
- * triangles from its vertex 0 and integrated with the triangle rule; local
+ * and assembly: for every pair, the clip polygon is recomputed at the
+ * current coordinates (and kept with each vertex's provenance for
+ * mt_backward), split into a fan of triangles from its vertex 0 and
+ * integrated with the triangle rule; local
  * blocks D_e[j][k] = int Phi_j N_k, M_e[j][l] = int Phi_j (N_l o chi),
  * g_e[j] = int Phi_j (h_master - h_slave) (heights along n0) are summed into
  * D_val[nnz_D], M_val[nnz_M] (CSR order of mt_csr_pattern) and gap[n_s_nodes]
@@ -186,9 +191,12 @@ int mt_integrate(mt_ctx* ctx, double* D_val, double* M_val, double* gap, void* s
  * the slave and master nodal coordinates, on the current pair list and
  * pattern (the pair list is held fixed).  W_D[nnz_D], W_M[nnz_M],
  * w_g[n_s_nodes] in; gXs[3 * n_s_nodes], gXm[3 * n_m_nodes] out, laid out
- * structure-of-arrays (x block, then y, then z), overwritten.  The clip
- * geometry is recomputed, then differentiated in reverse mode; the inverse
- * maps use the implicit-function derivative.  Errors: MT_ESTATE,
+ * structure-of-arrays (x block, then y, then z), overwritten.  Uses the clip
+ * polygons of the last mt_integrate when the coordinates have not been
+ * replaced since (mt_upload / mt_update_coordinates), else recomputes them;
+ * the geometry is then differentiated in reverse mode, the inverse maps
+ * through the implicit-function derivative, each clip vertex through the
+ * two lines it lies on.  Errors: MT_ESTATE,
  * MT_EINVAL, MT_EUNSUPPORTED (dual basis). */
 int mt_backward(mt_ctx* ctx, const double* W_D, const double* W_M, const double* w_g,
                 double* gXs, double* gXm, void* stream);
@@ -211,7 +219,8 @@ int mt_get_stats(mt_ctx* ctx, mt_stats* st);
 #define MT_T_ASSEMBLE 7    /* CSR assembly of D, M, gap (one kernel) */
 #define MT_T_PAIR_BWD 8    /* backward of all pairs (one kernel) */
 #define MT_T_GRAD_REDUCE 9 /* per-node gradient sums */
-#define MT_T_COUNT 10
+#define MT_T_PAIR_POLY 10  /* clip polygons of all pairs (one kernel) */
+#define MT_T_COUNT 11
 
 typedef struct mt_timings {
   double ms[MT_T_COUNT];        /* summed event time per phase */

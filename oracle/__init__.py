@@ -199,11 +199,12 @@ def count_flops(slave, master, prm, cs, cm, detail=False):
     """(flops of the candidate pass over all candidates, flops of the full
     evaluation over the candidates that are pairs).  With detail=True also
     (reverse-mode adjoint flops of those pairs outside the inverse maps,
-    number of inverse maps evaluated)."""
+    number of inverse maps evaluated, reverse-mode adjoint flops of the
+    candidate pass of those pairs)."""
     args, keep = _mesh_args(slave, master)
     cs = np.ascontiguousarray(cs, np.int32)
     cm = np.ascontiguousarray(cm, np.int32)
-    out = np.zeros(4, np.uint64)
+    out = np.zeros(5, np.uint64)
     _lib().or_count_flops(*args, ctypes.byref(prm), cs.size, _p(cs), _p(cm), _p(out))
     if detail:
         return tuple(int(x) for x in out)

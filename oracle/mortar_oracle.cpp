@@ -856,22 +856,25 @@ int or_pair_grads(int64_t ns_nodes, const double* Xs, int64_t ns_el, const int32
 // flops, multiply: 4, divide: 4, square root: 3) over every operation outside
 // the inverse bilinear maps, flops[3] = number of inverse bilinear maps
 // evaluated (each differentiated by the implicit-function theorem instead of
-// through its iterations).
+// through its iterations), flops[4] = the cost model applied to the
+// candidate pass (frame, projection, clip, cleanup) of those pairs alone.
 void or_count_flops(int64_t ns_nodes, const double* Xs, int64_t ns_el, const int32_t* Cs,
                     int64_t nm_nodes, const double* Xm, int64_t nm_el, const int32_t* Cm,
                     const OrParams* op, int64_t n, const int32_t* cs, const int32_t* cm, uint64_t* flops) {
   MeshView S{ns_nodes, Xs, ns_el, Cs}, M{nm_nodes, Xm, nm_el, Cm};
   const Params prm = to_params(op);
   const Rule rule = make_rule(prm.rule);
-  flops[0] = 0; flops[1] = 0; flops[2] = 0; flops[3] = 0;
+  for (int k = 0; k < 5; ++k) flops[k] = 0;
   for (int64_t i = 0; i < n; ++i) {
     Cnt xs[4][3], xm[4][3];
     load_pair(S, M, cs[i], cm[i], xs, xm);
     PairOut<Cnt> o;
     g_flops = 0;
+    for (int k = 0; k < 4; ++k) g_kind[k] = 0;
     eval_pair(xs, xm, prm, rule, false, o);
     flops[0] += g_flops;
     if (o.nv >= 3) {
+      flops[4] += 2 * g_kind[0] + 4 * g_kind[1] + 4 * g_kind[2] + 3 * g_kind[3];
       g_flops = 0;
       for (int k = 0; k < 4; ++k) g_kind[k] = 0;
       g_inverse_maps = 0;

@@ -34,7 +34,7 @@ class mt_stats(ctypes.Structure):
 
 
 MT_T_NAMES = ["prep", "bin_sort", "cand", "clip", "compact", "pattern", "pair_fwd", "assemble", "pair_bwd",
-              "grad_reduce"]
+              "grad_reduce", "pair_poly"]
 MT_T_COUNT = len(MT_T_NAMES)
 
 

@@ -166,7 +166,7 @@ int mt_destroy(mt_ctx* c) {
                  &c->pair_nv, &c->pair_off, &c->inc_cnt, &c->inc_off, &c->inc_cur, &c->inc_list, &c->minc_cnt,
                  &c->minc_off, &c->minc_cur, &c->minc_list, &c->rawD_cnt, &c->rawD_off, &c->rawD, &c->rawM_cnt,
                  &c->rawM_off, &c->rawM, &c->pat_keep, &c->D_cnt, &c->D_rowptr, &c->D_col, &c->M_cnt, &c->M_rowptr,
-                 &c->M_col, &c->posD, &c->posM, &c->blk, &c->gpair, &c->mp_keys, &c->mp_vals, &c->mp_off,
+                 &c->M_col, &c->posD, &c->posM, &c->poly_u, &c->poly_v, &c->poly_lab, &c->poly_nf, &c->blk, &c->gpair, &c->mp_keys, &c->mp_vals, &c->mp_off,
                  &c->scan_tmp, &c->sort_hist, &c->host_tmp};
   for (Buf* b : bufs) release(*b);
   for (auto& iv : c->intervals) {
@@ -188,6 +188,7 @@ int mt_set_params(mt_ctx* c, const mt_params* p) {
     return fail(MT_EINVAL, "mt_set_params: negative or invalid tolerance");
   c->params = *p;
   c->have_pairs = c->have_pattern = c->have_master_index = false;
+  ++c->coord_gen;
   return MT_OK;
 }
 
@@ -207,6 +208,7 @@ int mt_upload(mt_ctx* c, int side, int64_t n_nodes, const double* x, const doubl
   m.n_el = (int32_t)n_el;
   m.set = true;
   c->have_pairs = c->have_pattern = c->have_master_index = false;
+  ++c->coord_gen;
   return MT_OK;
 }
 
@@ -218,6 +220,7 @@ int mt_update_coordinates(mt_ctx* c, int side, const double* x, const double* y,
   if (!m.set) return fail(MT_ESTATE, "mt_update_coordinates: side not uploaded");
   if (m.n_nodes > 0 && (!x || !y || !z)) return fail(MT_EINVAL, "mt_update_coordinates: null array");
   m.x = x; m.y = y; m.z = z;
+  ++c->coord_gen;
   return MT_OK;
 }
 
@@ -229,6 +232,7 @@ int mt_build_pairs(mt_ctx* c, int64_t* n_cand_out, int64_t* n_pairs_out, void* s
   hipStream_t st = (hipStream_t)stream;
   c->last_stream = st;
   c->have_pairs = c->have_pattern = c->have_master_index = false;
+  ++c->coord_gen;
   const DeviceMesh& S = c->side[0];
   const DeviceMesh& M = c->side[1];
   const int32_t ns = S.n_el, nm = M.n_el;
@@ -477,8 +481,18 @@ int mt_integrate(mt_ctx* c, double* D_val, double* M_val, double* gap, void* str
   const int64_t np = c->n_pairs;
   MT_HIP(ensure(c->blk, sizeof(double) * 36 * (size_t)std::max<int64_t>(np, 1)));
   {
+    int rc = ensure_poly(c);
+    if (rc) return rc;
+  }
+  const PolyBuf poly = poly_buf(c);
+  {
+    PhaseTimer t(c, MT_T_PAIR_POLY, st);
+    MT_HIP(launch_pair_poly(S, M, kparams(c->params), c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), np, poly, st));
+    c->poly_gen = c->coord_gen;
+  }
+  {
     PhaseTimer t(c, MT_T_PAIR_FWD, st);
-    MT_HIP(launch_pair_fwd(S, M, kparams(c->params), c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), np,
+    MT_HIP(launch_pair_fwd(S, M, kparams(c->params), c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), np, poly,
                            c->blk.as<double>(), np, c->counters.as<Counters>(), st));
   }
   PhaseTimer t(c, MT_T_ASSEMBLE, st);
@@ -496,6 +510,20 @@ __global__ void k_iota(uint32_t* v, int64_t n) {
 }  // namespace
 
 }  // extern "C"
+
+int mt::ensure_poly(mt_ctx* c) {
+  const size_t np = (size_t)std::max<int64_t>(c->n_pairs, 1);
+  MT_HIP(ensure(c->poly_u, sizeof(double) * CAP0 * np));
+  MT_HIP(ensure(c->poly_v, sizeof(double) * CAP0 * np));
+  MT_HIP(ensure(c->poly_lab, CAP0 * np));
+  MT_HIP(ensure(c->poly_nf, np));
+  return MT_OK;
+}
+
+mt::PolyBuf mt::poly_buf(mt_ctx* c) {
+  return PolyBuf{c->poly_u.as<double>(), c->poly_v.as<double>(), c->poly_lab.as<uint8_t>(), c->poly_nf.as<uint8_t>(),
+                 std::max<int64_t>(c->n_pairs, 1)};
+}
 
 int mt::ensure_master_index(mt_ctx* c, hipStream_t st) {
   if (c->have_master_index) return MT_OK;
@@ -544,8 +572,18 @@ int mt_backward(mt_ctx* c, const double* W_D, const double* W_M, const double* w
   const int64_t np = c->n_pairs;
   MT_HIP(ensure(c->gpair, sizeof(double) * 24 * (size_t)std::max<int64_t>(np, 1)));
   {
+    int rc = ensure_poly(c);
+    if (rc) return rc;
+  }
+  const PolyBuf poly = poly_buf(c);
+  if (c->poly_gen != c->coord_gen) {
+    PhaseTimer t(c, MT_T_PAIR_POLY, st);
+    MT_HIP(launch_pair_poly(S, M, kparams(c->params), c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), np, poly, st));
+    c->poly_gen = c->coord_gen;
+  }
+  {
     PhaseTimer t(c, MT_T_PAIR_BWD, st);
-    MT_HIP(launch_pair_bwd(S, M, kparams(c->params), c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), np,
+    MT_HIP(launch_pair_bwd(S, M, kparams(c->params), c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), np, poly,
                            c->posD.as<int32_t>(), S.n_el, c->posM.as<int32_t>(), W_D, W_M, w_g,
                            c->gpair.as<double>(), np, c->counters.as<Counters>(), st));
   }

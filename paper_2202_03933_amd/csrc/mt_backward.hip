@@ -12,6 +12,12 @@ namespace {
 
 constexpr int BSC = 64;
 
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+  return x;
+}
+
 // Upstream weights of pair p gathered through the position maps.
 __device__ __forceinline__ void gather_weights(int s, int64_t p, int4 csn, const int32_t* __restrict__ posD,
                                                int32_t n_s, const int32_t* __restrict__ posM, int64_t stride,
@@ -29,53 +35,49 @@ __device__ __forceinline__ void gather_weights(int s, int64_t p, int4 csn, const
 }
 
 template <int NQ>
-__global__ __launch_bounds__(BSC) void k_pair_bwd(MeshPtrs S, int32_t n_s, MeshPtrs M, KParams kp,
+__global__ __launch_bounds__(BSC) __attribute__((amdgpu_waves_per_eu(2))) void k_pair_bwd(MeshPtrs S, int32_t n_s, MeshPtrs M, KParams kp,
                                                    const int32_t* __restrict__ pair_s,
-                                                   const int32_t* __restrict__ pair_m, int64_t n_pairs,
+                                                   const int32_t* __restrict__ pair_m, int64_t n_pairs, PolyBuf poly,
                                                    const int32_t* __restrict__ posD, const int32_t* __restrict__ posM,
                                                    const double* __restrict__ W_D, const double* __restrict__ W_M,
                                                    const double* __restrict__ w_g, double* __restrict__ gpair,
                                                    int64_t stride, Counters* cnt) {
-  __shared__ double su[CAPT * BSC], sv[CAPT * BSC];
-  __shared__ uint8_t sl[CAPT * BSC], se[CAPT * BSC];
-  __shared__ double sau[CAP0 * BSC], sav[CAP0 * BSC];
   const int64_t p = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * BSC + threadIdx.x;
-  if (p >= n_pairs) return;
-  const int s = pair_s[p];
-  const int4 csn = load_conn(S.conn, s);
-  double Xs[4][3], Xm[4][3];
-  load_nodes(S.x, S.y, S.z, csn, Xs);
-  load_nodes(M.x, M.y, M.z, load_conn(M.conn, pair_m[p]), Xm);
-  double WD[16], WM[16], wg[4];
-  gather_weights(s, p, csn, posD, n_s, posM, stride, W_D, W_M, w_g, WD, WM, wg);
-  LdsPoly<true> P{su + threadIdx.x, sv + threadIdx.x, sl + threadIdx.x, se + threadIdx.x, BSC};
-  double Xsb[4][3], Xmb[4][3];
   unsigned noconv = 0;
-  pair_backward<NQ>(Xs, Xm, kp, P, sau + threadIdx.x, sav + threadIdx.x, WD, WM, wg, Xsb, Xmb, noconv);
+  if (p < n_pairs) {
+    const int s = pair_s[p];
+    const int4 csn = load_conn(S.conn, s);
+    double WD[16], WM[16], wg[4];
+    gather_weights(s, p, csn, posD, n_s, posM, stride, W_D, W_M, w_g, WD, WM, wg);
+    double Xsb[4][3], Xmb[4][3];
+    pair_backward<NQ>(S, csn, M, load_conn(M.conn, pair_m[p]), gpoly(poly, p), poly.nf[p], kp, WD, WM, wg, Xsb, Xmb,
+                      noconv);
 #pragma unroll
-  for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < 4; ++k)
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      gpair[(int64_t)(3 * k + d) * stride + p] = Xsb[k][d];
-      gpair[(int64_t)(12 + 3 * k + d) * stride + p] = Xmb[k][d];
-    }
-  if (noconv) atomicAdd(&cnt->noconv, (unsigned long long)noconv);
+      for (int d = 0; d < 3; ++d) {
+        gpair[(int64_t)(3 * k + d) * stride + p] = Xsb[k][d];
+        gpair[(int64_t)(12 + 3 * k + d) * stride + p] = Xmb[k][d];
+      }
+  }
+  const unsigned long long nc = wave_sum_u64(noconv);
+  if (threadIdx.x == 0 && nc) atomicAdd(&cnt->noconv, nc);
 }
 
 }  // namespace
 
 hipError_t launch_pair_bwd(const DeviceMesh& S, const DeviceMesh& M, const KParams& kp, const int32_t* pair_s,
-                           const int32_t* pair_m, int64_t n_pairs, const int32_t* posD, int32_t n_s_el,
+                           const int32_t* pair_m, int64_t n_pairs, const PolyBuf& poly, const int32_t* posD, int32_t n_s_el,
                            const int32_t* posM, const double* W_D, const double* W_M, const double* w_g,
                            double* gpair, int64_t stride, Counters* cnt, hipStream_t s) {
   if (n_pairs == 0) return hipSuccess;
   const unsigned nb = xcd_grid((unsigned)((n_pairs + BSC - 1) / BSC));
   const MeshPtrs ms{S.x, S.y, S.z, S.conn}, mm{M.x, M.y, M.z, M.conn};
   if (kp.rule == 3)
-    k_pair_bwd<3><<<nb, BSC, 0, s>>>(ms, n_s_el, mm, kp, pair_s, pair_m, n_pairs, posD, posM, W_D, W_M, w_g, gpair,
+    k_pair_bwd<3><<<nb, BSC, 0, s>>>(ms, n_s_el, mm, kp, pair_s, pair_m, n_pairs, poly, posD, posM, W_D, W_M, w_g, gpair,
                                      stride, cnt);
   else
-    k_pair_bwd<7><<<nb, BSC, 0, s>>>(ms, n_s_el, mm, kp, pair_s, pair_m, n_pairs, posD, posM, W_D, W_M, w_g, gpair,
+    k_pair_bwd<7><<<nb, BSC, 0, s>>>(ms, n_s_el, mm, kp, pair_s, pair_m, n_pairs, poly, posD, posM, W_D, W_M, w_g, gpair,
                                      stride, cnt);
   return hipGetLastError();
 }

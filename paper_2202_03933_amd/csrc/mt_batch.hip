@@ -44,6 +44,7 @@ struct BatchInst {
   const uint32_t* mpairs;
   double* blk;
   double* gpair;
+  PolyBuf poly;
   // per call
   double* D_val;
   double* M_val;
@@ -92,15 +93,16 @@ __device__ __forceinline__ int next_item(const int32_t* __restrict__ qbeg, int32
   return -1;
 }
 
-template <int BSZ, int NQ, bool DUAL>
-__global__ __launch_bounds__(BSZ) void k_batch_fwd(const BatchInst* __restrict__ inst,
-                                                    const WorkItem* __restrict__ items,
-                                                    const int32_t* __restrict__ qbeg, int32_t* qnext, Counters* cnt) {
+// Clip polygons of every pair of every instance (LDS clip buffers).
+template <int BSZ>
+__global__ __launch_bounds__(BSZ) void k_batch_poly(const BatchInst* __restrict__ inst,
+                                                     const WorkItem* __restrict__ items,
+                                                     const int32_t* __restrict__ qbeg, int32_t* qnext) {
   __shared__ double su[CAPT * BSZ], sv[CAPT * BSZ];
+  __shared__ uint8_t sl[CAPT * BSZ], se[CAPT * BSZ];
   __shared__ int s_item;
-  unsigned noconv = 0;
   int qi = 0;
-  LdsPoly<false> P{su + threadIdx.x, sv + threadIdx.x, nullptr, nullptr, BSZ};
+  const LdsPoly<true> P{su + threadIdx.x, sv + threadIdx.x, sl + threadIdx.x, se + threadIdx.x, BSZ};
   for (int it = next_item(qbeg, qnext, qi, &s_item); it >= 0; it = next_item(qbeg, qnext, qi, &s_item)) {
     const WorkItem w = items[it];
     const BatchInst& I = inst[w.inst];
@@ -108,8 +110,25 @@ __global__ __launch_bounds__(BSZ) void k_batch_fwd(const BatchInst* __restrict__
       double Xs[4][3], Xm[4][3];
       load_nodes(I.S.x, I.S.y, I.S.z, load_conn(I.S.conn, I.pair_s[p]), Xs);
       load_nodes(I.M.x, I.M.y, I.M.z, load_conn(I.M.conn, I.pair_m[p]), Xm);
+      store_pair_polygon(Xs, Xm, I.kp, P, I.poly, p);
+    }
+  }
+}
+
+template <int BSZ, int NQ, bool DUAL>
+__global__ __launch_bounds__(BSZ) __attribute__((amdgpu_waves_per_eu(3))) void k_batch_fwd(const BatchInst* __restrict__ inst,
+                                                    const WorkItem* __restrict__ items,
+                                                    const int32_t* __restrict__ qbeg, int32_t* qnext, Counters* cnt) {
+  __shared__ int s_item;
+  unsigned noconv = 0;
+  int qi = 0;
+  for (int it = next_item(qbeg, qnext, qi, &s_item); it >= 0; it = next_item(qbeg, qnext, qi, &s_item)) {
+    const WorkItem w = items[it];
+    const BatchInst& I = inst[w.inst];
+    for (int64_t p = w.begin + (int)threadIdx.x; p < w.end; p += BSZ) {
       double D[16], Mv[16], g[4];
-      pair_forward<NQ, DUAL, false>(Xs, Xm, I.kp, P, D, Mv, g, noconv);
+      pair_forward<NQ, DUAL>(I.S, load_conn(I.S.conn, I.pair_s[p]), I.M, load_conn(I.M.conn, I.pair_m[p]),
+                             gpoly(I.poly, p), I.poly.nf[p], I.kp, D, Mv, g, noconv);
       const int64_t st = I.n_pairs;
 #pragma unroll
       for (int k = 0; k < 16; ++k) I.blk[(int64_t)k * st + p] = D[k];
@@ -124,16 +143,12 @@ __global__ __launch_bounds__(BSZ) void k_batch_fwd(const BatchInst* __restrict__
 }
 
 template <int BSZ, int NQ>
-__global__ __launch_bounds__(BSZ) void k_batch_bwd(const BatchInst* __restrict__ inst,
+__global__ __launch_bounds__(BSZ) __attribute__((amdgpu_waves_per_eu(2))) void k_batch_bwd(const BatchInst* __restrict__ inst,
                                                     const WorkItem* __restrict__ items,
                                                     const int32_t* __restrict__ qbeg, int32_t* qnext, Counters* cnt) {
-  __shared__ double su[CAPT * BSZ], sv[CAPT * BSZ];
-  __shared__ uint8_t sl[CAPT * BSZ], se[CAPT * BSZ];
-  __shared__ double sau[CAP0 * BSZ], sav[CAP0 * BSZ];
   __shared__ int s_item;
   unsigned noconv = 0;
   int qi = 0;
-  LdsPoly<true> P{su + threadIdx.x, sv + threadIdx.x, sl + threadIdx.x, se + threadIdx.x, BSZ};
   for (int it = next_item(qbeg, qnext, qi, &s_item); it >= 0; it = next_item(qbeg, qnext, qi, &s_item)) {
     const WorkItem w = items[it];
     const BatchInst& I = inst[w.inst];
@@ -141,9 +156,6 @@ __global__ __launch_bounds__(BSZ) void k_batch_bwd(const BatchInst* __restrict__
     for (int64_t p = w.begin + (int)threadIdx.x; p < w.end; p += BSZ) {
       const int s = I.pair_s[p];
       const int4 csn = load_conn(I.S.conn, s);
-      double Xs[4][3], Xm[4][3];
-      load_nodes(I.S.x, I.S.y, I.S.z, csn, Xs);
-      load_nodes(I.M.x, I.M.y, I.M.z, load_conn(I.M.conn, I.pair_m[p]), Xm);
       double WD[16], WM[16], wg[4];
 #pragma unroll
       for (int k = 0; k < 16; ++k) WD[k] = I.W_D[I.posD[(int64_t)k * I.n_s_el + s]];
@@ -154,7 +166,8 @@ __global__ __launch_bounds__(BSZ) void k_batch_bwd(const BatchInst* __restrict__
       wg[2] = I.w_g[csn.z];
       wg[3] = I.w_g[csn.w];
       double Xsb[4][3], Xmb[4][3];
-      pair_backward<NQ>(Xs, Xm, I.kp, P, sau + threadIdx.x, sav + threadIdx.x, WD, WM, wg, Xsb, Xmb, noconv);
+      pair_backward<NQ>(I.S, csn, I.M, load_conn(I.M.conn, I.pair_m[p]), gpoly(I.poly, p), I.poly.nf[p], I.kp, WD,
+                        WM, wg, Xsb, Xmb, noconv);
 #pragma unroll
       for (int k = 0; k < 4; ++k)
 #pragma unroll
@@ -194,6 +207,7 @@ __global__ __launch_bounds__(ROWS_PER_ITEM) void k_batch_grad_rows(const BatchIn
     grad_master_row(a, I.n_m_nodes, I.minc_off, I.minc_list, I.mstart, I.mend, I.mpairs, I.gpair, I.n_pairs, I.gXm);
 }
 
+using PolyFn = void (*)(const BatchInst*, const WorkItem*, const int32_t*, int32_t*);
 using FwdFn = void (*)(const BatchInst*, const WorkItem*, const int32_t*, int32_t*, Counters*);
 using BwdFn = void (*)(const BatchInst*, const WorkItem*, const int32_t*, int32_t*, Counters*);
 
@@ -207,6 +221,11 @@ BwdFn bwd_kernel(int nq) {
   return nq == 3 ? k_batch_bwd<BSZ, 3> : k_batch_bwd<BSZ, 7>;
 }
 
+PolyFn pick_poly(int bsz) {
+  if (bsz == 256) return k_batch_poly<256>;
+  if (bsz == 128) return k_batch_poly<128>;
+  return k_batch_poly<64>;
+}
 FwdFn pick_fwd(int bsz, int nq, bool dual) {
   if (bsz == 256) return fwd_kernel<256>(nq, dual);
   if (bsz == 128) return fwd_kernel<128>(nq, dual);
@@ -218,11 +237,12 @@ BwdFn pick_bwd(int bsz, int nq) {
   return bwd_kernel<64>(nq);
 }
 
-// LDS of one block (bytes): forward uses CAPT vertices x 16 B per lane,
-// backward adds two label bytes per vertex slot and CAP0 adjoint slots.
-int max_blocks_per_cu(int bsz, bool backward) {
-  const int per_block = bsz * (CAPT * 16 + (backward ? CAPT * 2 + CAP0 * 16 : 0)) + 64;
-  return std::max(1, (160 * 1024) / per_block);
+// Blocks of kernel fn (block size bsz) resident on one compute unit, from
+// its register and LDS footprint.
+int resident_blocks(const void* fn, int bsz) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, bsz, 0) != hipSuccess || nb < 1) nb = 1;
+  return nb;
 }
 
 }  // namespace
@@ -309,12 +329,27 @@ int upload_inst(mt_batch* b, hipStream_t st) {
   return MT_OK;
 }
 
-int launch_fwd(mt_batch* b, hipStream_t st) {
+int launch_poly(mt_batch* b, hipStream_t st) {
   const int bsz = b->tune.block;
-  const int grid = b->num_cu * std::max(1, b->tune.blocks_per_cu);
+  PolyFn f = pick_poly(bsz);
+  const int grid = b->num_cu * resident_blocks(reinterpret_cast<const void*>(f), bsz);
   k_reset_queues<<<1, 64, 0, st>>>(b->d_qnext.as<int32_t>());
   B_HIP(hipGetLastError());
+  hipLaunchKernelGGL(f, dim3(grid), dim3(bsz), 0, st, b->d_inst.as<BatchInst>(), b->d_pitems.as<WorkItem>(),
+                     b->d_qbeg.as<int32_t>(), b->d_qnext.as<int32_t>());
+  B_HIP(hipGetLastError());
+  return MT_OK;
+}
+
+int launch_fwd(mt_batch* b, hipStream_t st) {
+  int rc = launch_poly(b, st);
+  if (rc) return rc;
+  const int bsz = b->tune.block;
   FwdFn f = pick_fwd(bsz, b->nq, b->dual);
+  const int grid = b->num_cu * std::min(std::max(1, b->tune.blocks_per_cu),
+                                        resident_blocks(reinterpret_cast<const void*>(f), bsz));
+  k_reset_queues<<<1, 64, 0, st>>>(b->d_qnext.as<int32_t>());
+  B_HIP(hipGetLastError());
   hipLaunchKernelGGL(f, dim3(grid), dim3(bsz), 0, st, b->d_inst.as<BatchInst>(), b->d_pitems.as<WorkItem>(),
                      b->d_qbeg.as<int32_t>(), b->d_qnext.as<int32_t>(), b->counters.as<Counters>());
   B_HIP(hipGetLastError());
@@ -333,10 +368,10 @@ int launch_fwd_all(mt_batch* b, hipStream_t st) {
 
 int launch_bwd_all(mt_batch* b, hipStream_t st) {
   const int bsz = b->tune.block;
-  const int grid = b->num_cu * std::min(std::max(1, b->tune.blocks_per_cu), max_blocks_per_cu(bsz, true));
+  BwdFn f = pick_bwd(bsz, b->nq);
+  const int grid = b->num_cu * resident_blocks(reinterpret_cast<const void*>(f), bsz);
   k_reset_queues<<<1, 64, 0, st>>>(b->d_qnext.as<int32_t>());
   B_HIP(hipGetLastError());
-  BwdFn f = pick_bwd(bsz, b->nq);
   hipLaunchKernelGGL(f, dim3(grid), dim3(bsz), 0, st, b->d_inst.as<BatchInst>(), b->d_pitems.as<WorkItem>(),
                      b->d_qbeg.as<int32_t>(), b->d_qnext.as<int32_t>(), b->counters.as<Counters>());
   B_HIP(hipGetLastError());
@@ -435,8 +470,9 @@ int mt_batch_build(mt_batch* b, const mt_batch_tuning* tuning, void* stream) {
   mt_batch_tuning t{};
   if (tuning) t = *tuning;
   if (t.block != 64 && t.block != 128 && t.block != 256) t.block = 64;
-  if (t.blocks_per_cu <= 0) t.blocks_per_cu = max_blocks_per_cu(t.block, false);
-  t.blocks_per_cu = std::min(t.blocks_per_cu, max_blocks_per_cu(t.block, false));
+  const int resident = resident_blocks(reinterpret_cast<const void*>(pick_fwd(t.block, p0.rule, p0.lm_basis == MT_BASIS_DUAL)), t.block);
+  if (t.blocks_per_cu <= 0) t.blocks_per_cu = resident;
+  t.blocks_per_cu = std::min(t.blocks_per_cu, resident);
   if (t.bucket <= 0) t.bucket = 4 * t.block;
   b->tune = t;
 
@@ -478,6 +514,11 @@ int mt_batch_build(mt_batch* b, const mt_batch_tuning* tuning, void* stream) {
     I.mpairs = c->mp_vals.as<uint32_t>();
     I.blk = c->blk.as<double>();
     I.gpair = c->gpair.as<double>();
+    {
+      int rc = ensure_poly(c);
+      if (rc) return rc;
+    }
+    I.poly = poly_buf(c);
     I.kp = kparams(c->params);
     for (int r = 0; r < S.n_nodes; r += ROWS_PER_ITEM) {
       const WorkItem w{(int32_t)i, r, std::min(S.n_nodes, r + ROWS_PER_ITEM), 0};
@@ -525,8 +566,11 @@ int mt_batch_forward(mt_batch* b, double* const* D_val, double* const* M_val, do
   }
   int rc = upload_inst(b, st);
   if (rc) return rc;
-  if (use_graph) return run_graph(&b->g_fwd, &b->g_fwd_stream, st, [&]() { return launch_fwd_all(b, st); });
-  return launch_fwd_all(b, st);
+  if (use_graph) rc = run_graph(&b->g_fwd, &b->g_fwd_stream, st, [&]() { return launch_fwd_all(b, st); });
+  else rc = launch_fwd_all(b, st);
+  if (rc) return rc;
+  for (mt_ctx* c : b->ctxs) c->poly_gen = c->coord_gen;
+  return MT_OK;
 }
 
 int mt_batch_backward(mt_batch* b, const double* const* W_D, const double* const* W_M, const double* const* w_g,
@@ -547,6 +591,13 @@ int mt_batch_backward(mt_batch* b, const double* const* W_D, const double* const
   }
   int rc = upload_inst(b, st);
   if (rc) return rc;
+  bool stale = false;
+  for (mt_ctx* c : b->ctxs) stale = stale || c->poly_gen != c->coord_gen;
+  if (stale) {
+    rc = launch_poly(b, st);
+    if (rc) return rc;
+    for (mt_ctx* c : b->ctxs) c->poly_gen = c->coord_gen;
+  }
   if (use_graph) return run_graph(&b->g_bwd, &b->g_bwd_stream, st, [&]() { return launch_bwd_all(b, st); });
   return launch_bwd_all(b, st);
 }
@@ -561,7 +612,8 @@ int mt_batch_autotune(mt_batch* b, mt_batch_tuning* out, void* stream) {
   for (int block : {64, 128, 256})
     for (int bpc : {1, 2, 4, 6, 8})
       for (int mul : {1, 4, 16})
-        if (bpc <= max_blocks_per_cu(block, false)) cands.push_back({block, bpc, mul});
+        if (bpc <= resident_blocks(reinterpret_cast<const void*>(pick_fwd(block, b->nq, b->dual)), block))
+          cands.push_back({block, bpc, mul});
   hipEvent_t e0, e1;
   B_HIP(hipEventCreate(&e0));
   B_HIP(hipEventCreate(&e1));

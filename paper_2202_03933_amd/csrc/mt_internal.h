@@ -60,6 +60,20 @@ struct Counters {
   unsigned long long degen_master;
 };
 
+// Clip polygons of the pairs, structure-of-arrays over the pair index p:
+// vertex i at u[i * stride + p], v[...], provenance lab[...] (slave node k:
+// 0x80 | k; else (la << 4) | lb, the two lines the vertex lies on: 0..3 slave
+// edges k -> k+1, 4..7 master clip edges); nf[p] = vertex count | flip << 7
+// (flip: the projected master polygon is clockwise and is clipped as
+// (M0, M3, M2, M1)).
+struct PolyBuf {
+  double* u;
+  double* v;
+  uint8_t* lab;
+  uint8_t* nf;
+  int64_t stride;
+};
+
 struct KParams {
   double delta;
   double eps_d;
@@ -123,6 +137,12 @@ struct mt_ctx {
   mt::Buf M_cnt, M_rowptr, M_col;
   mt::Buf posD;            // [16][n_s_el]
   mt::Buf posM;            // [16][n_pairs]
+  // clip polygons of the pairs (mt::PolyBuf); valid for the coordinates of
+  // generation poly_gen (coord_gen counts coordinate and pair-list changes)
+  mt::Buf poly_u, poly_v;  // [CAP0][n_pairs]
+  mt::Buf poly_lab;        // uint8 [CAP0][n_pairs]
+  mt::Buf poly_nf;         // uint8 [n_pairs]
+  int64_t coord_gen = 0, poly_gen = -1;
   // forward / backward staging
   mt::Buf blk;             // [36][n_pairs]
   mt::Buf gpair;           // [24][n_pairs]
@@ -168,9 +188,11 @@ hipError_t launch_compact(const int32_t* cand_s, const int32_t* cand_m, const ui
                           uint8_t* pair_nv, hipStream_t s);
 hipError_t launch_pair_off(const int32_t* cand_off, const int32_t* scan, int32_t n_s, int32_t* pair_off,
                            hipStream_t s);
+hipError_t launch_pair_poly(const DeviceMesh& S, const DeviceMesh& M, const KParams& kp, const int32_t* pair_s,
+                            const int32_t* pair_m, int64_t n_pairs, const PolyBuf& poly, hipStream_t s);
 hipError_t launch_pair_fwd(const DeviceMesh& S, const DeviceMesh& M, const KParams& kp, const int32_t* pair_s,
-                           const int32_t* pair_m, int64_t n_pairs, double* blk, int64_t blk_stride,
-                           Counters* cnt, hipStream_t s);
+                           const int32_t* pair_m, int64_t n_pairs, const PolyBuf& poly, double* blk,
+                           int64_t blk_stride, Counters* cnt, hipStream_t s);
 
 // ---- assembly (mt_assemble.hip) ----------------------------------------------
 hipError_t launch_inc_count(const int32_t* conn, int32_t n_el, int32_t* cnt, hipStream_t s);
@@ -206,7 +228,7 @@ hipError_t launch_grad_master(const int32_t* inc_off, const int32_t* inc_list, i
 
 // ---- backward (mt_backward.hip) ----------------------------------------------
 hipError_t launch_pair_bwd(const DeviceMesh& S, const DeviceMesh& M, const KParams& kp, const int32_t* pair_s, const int32_t* pair_m,
-                           int64_t n_pairs, const int32_t* posD, int32_t n_s_el, const int32_t* posM,
+                           int64_t n_pairs, const PolyBuf& poly, const int32_t* posD, int32_t n_s_el, const int32_t* posM,
                            const double* W_D, const double* W_M, const double* w_g, double* gpair,
                            int64_t stride, Counters* cnt, hipStream_t s);
 
@@ -214,6 +236,9 @@ KParams kparams(const mt_params& p);
 // Node incidence of the master side and the pairs-by-master permutation
 // (needed by the backward's master-node reduction); built once per pattern.
 int ensure_master_index(mt_ctx* c, hipStream_t st);
+// Polygon buffers sized for the current pair list, and their view.
+int ensure_poly(mt_ctx* c);
+PolyBuf poly_buf(mt_ctx* c);
 void set_error(const std::string& msg);
 
 }  // namespace mt

@@ -98,26 +98,40 @@ __global__ __launch_bounds__(BS) void k_pair_off(const int32_t* __restrict__ can
   pair_off[s] = scan[cand_off[s]];
 }
 
-// Segment-based integration of every pair; local blocks staged
-// structure-of-arrays.  Blocks are mapped XCD-major: consecutive blocks are
-// dispatched to different XCDs, so block b works on tile
-// (b % 8) * ceil(nb / 8) + b / 8 and each XCD's L2 sees one contiguous eighth
-// of the pair list (neighbouring pairs share slave nodes).
+// Clip polygon of every pair (projection, clip and cleanup in LDS), stored
+// with its provenance for the integration and its reverse mode.
+__global__ __launch_bounds__(BSC) void k_pair_poly(MeshPtrs S, MeshPtrs M, KParams kp,
+                                                    const int32_t* __restrict__ pair_s,
+                                                    const int32_t* __restrict__ pair_m, int64_t n_pairs,
+                                                    PolyBuf out) {
+  __shared__ double su[CAPT * BSC], sv[CAPT * BSC];
+  __shared__ uint8_t sl[CAPT * BSC], se[CAPT * BSC];
+  const int64_t p = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * BSC + threadIdx.x;
+  if (p >= n_pairs) return;
+  double Xs[4][3], Xm[4][3];
+  load_nodes(S.x, S.y, S.z, load_conn(S.conn, pair_s[p]), Xs);
+  load_nodes(M.x, M.y, M.z, load_conn(M.conn, pair_m[p]), Xm);
+  const LdsPoly<true> P{su + threadIdx.x, sv + threadIdx.x, sl + threadIdx.x, se + threadIdx.x, BSC};
+  store_pair_polygon(Xs, Xm, kp, P, out, p);
+}
+
+// Segment-based integration of every pair from its stored polygon; local
+// blocks staged structure-of-arrays.  Blocks are mapped XCD-major:
+// consecutive blocks are dispatched to different XCDs, so block b works on
+// tile (b % 8) * ceil(nb / 8) + b / 8 and each XCD's L2 sees one contiguous
+// eighth of the pair list (neighbouring pairs share slave nodes).
 template <int NQ, bool DUAL>
-__global__ __launch_bounds__(BSC) void k_pair_fwd(MeshPtrs S, MeshPtrs M, KParams kp,
+__global__ __launch_bounds__(BSC) __attribute__((amdgpu_waves_per_eu(3))) void k_pair_fwd(MeshPtrs S, MeshPtrs M, KParams kp,
                                                    const int32_t* __restrict__ pair_s,
                                                    const int32_t* __restrict__ pair_m, int64_t n_pairs,
-                                                   double* __restrict__ blk, int64_t stride, Counters* cnt) {
-  __shared__ double su[CAPT * BSC], sv[CAPT * BSC];
+                                                   PolyBuf poly, double* __restrict__ blk, int64_t stride,
+                                                   Counters* cnt) {
   const int64_t p = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * BSC + threadIdx.x;
   unsigned noconv = 0;
   if (p < n_pairs) {
-    double Xs[4][3], Xm[4][3];
-    load_nodes(S.x, S.y, S.z, load_conn(S.conn, pair_s[p]), Xs);
-    load_nodes(M.x, M.y, M.z, load_conn(M.conn, pair_m[p]), Xm);
-    LdsPoly<false> P{su + threadIdx.x, sv + threadIdx.x, nullptr, nullptr, BSC};
     double D[16], Mv[16], g[4];
-    pair_forward<NQ, DUAL, false>(Xs, Xm, kp, P, D, Mv, g, noconv);
+    pair_forward<NQ, DUAL>(S, load_conn(S.conn, pair_s[p]), M, load_conn(M.conn, pair_m[p]), gpoly(poly, p),
+                           poly.nf[p], kp, D, Mv, g, noconv);
 #pragma unroll
     for (int k = 0; k < 16; ++k) blk[(int64_t)k * stride + p] = D[k];
 #pragma unroll
@@ -155,18 +169,27 @@ hipError_t launch_pair_off(const int32_t* cand_off, const int32_t* scan, int32_t
   return hipGetLastError();
 }
 
+hipError_t launch_pair_poly(const DeviceMesh& S, const DeviceMesh& M, const KParams& kp, const int32_t* pair_s,
+                            const int32_t* pair_m, int64_t n_pairs, const PolyBuf& poly, hipStream_t s) {
+  if (n_pairs == 0) return hipSuccess;
+  const unsigned nb = xcd_grid((unsigned)((n_pairs + BSC - 1) / BSC));
+  const MeshPtrs ms{S.x, S.y, S.z, S.conn}, mm{M.x, M.y, M.z, M.conn};
+  k_pair_poly<<<nb, BSC, 0, s>>>(ms, mm, kp, pair_s, pair_m, n_pairs, poly);
+  return hipGetLastError();
+}
+
 hipError_t launch_pair_fwd(const DeviceMesh& S, const DeviceMesh& M, const KParams& kp, const int32_t* pair_s,
-                           const int32_t* pair_m, int64_t n_pairs, double* blk, int64_t stride, Counters* cnt,
-                           hipStream_t s) {
+                           const int32_t* pair_m, int64_t n_pairs, const PolyBuf& poly, double* blk, int64_t stride,
+                           Counters* cnt, hipStream_t s) {
   if (n_pairs == 0) return hipSuccess;
   const unsigned nb = xcd_grid((unsigned)((n_pairs + BSC - 1) / BSC));
   const MeshPtrs ms{S.x, S.y, S.z, S.conn}, mm{M.x, M.y, M.z, M.conn};
   if (kp.rule == 3) {
-    if (kp.dual) k_pair_fwd<3, true><<<nb, BSC, 0, s>>>(ms, mm, kp, pair_s, pair_m, n_pairs, blk, stride, cnt);
-    else k_pair_fwd<3, false><<<nb, BSC, 0, s>>>(ms, mm, kp, pair_s, pair_m, n_pairs, blk, stride, cnt);
+    if (kp.dual) k_pair_fwd<3, true><<<nb, BSC, 0, s>>>(ms, mm, kp, pair_s, pair_m, n_pairs, poly, blk, stride, cnt);
+    else k_pair_fwd<3, false><<<nb, BSC, 0, s>>>(ms, mm, kp, pair_s, pair_m, n_pairs, poly, blk, stride, cnt);
   } else {
-    if (kp.dual) k_pair_fwd<7, true><<<nb, BSC, 0, s>>>(ms, mm, kp, pair_s, pair_m, n_pairs, blk, stride, cnt);
-    else k_pair_fwd<7, false><<<nb, BSC, 0, s>>>(ms, mm, kp, pair_s, pair_m, n_pairs, blk, stride, cnt);
+    if (kp.dual) k_pair_fwd<7, true><<<nb, BSC, 0, s>>>(ms, mm, kp, pair_s, pair_m, n_pairs, poly, blk, stride, cnt);
+    else k_pair_fwd<7, false><<<nb, BSC, 0, s>>>(ms, mm, kp, pair_s, pair_m, n_pairs, poly, blk, stride, cnt);
   }
   return hipGetLastError();
 }
