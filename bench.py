@@ -32,7 +32,6 @@ IFT_FLOPS = 38
 # Library phase timer of a single-kernel phase -> (kernel, source files whose
 # hash identifies the kernel version, committed traffic summary).
 KERNELS = {
-    "clip": ("k_clip_count", ["mt_pairs.hip", "mt_geometry.h"], "profiles/k_clip_count_wavy1024_traffic.md"),
     "pair_poly": ("k_pair_poly", ["mt_pairs.hip", "mt_pair_eval.h", "mt_geometry.h"],
                   "profiles/k_pair_poly_wavy1024_traffic.md"),
     "pair_fwd": ("k_pair_fwd", ["mt_pairs.hip", "mt_pair_eval.h", "mt_geometry.h"],
@@ -102,19 +101,15 @@ def cpu_baseline(itf, n_slave_el_sample, seed=3000):
     t_all = time.perf_counter() - t0
     # algorithmic flops (oracle's flop-counting scalar on every 16th pair and
     # every 16th candidate of the sample).  Per kernel:
-    #   k_clip_count: the candidate pass (frame, projection, clip, cleanup) of
-    #     every candidate;
     #   k_pair_poly:  the candidate pass of every pair;
     #   k_pair_fwd:   the pair evaluation minus its candidate pass;
     #   k_pair_bwd:   that forward recompute + the reverse-mode adjoint of the
     #     pair evaluation minus that of its candidate pass (cost model: adjoint
     #     of add/sub 2, mul 4, div 4, sqrt 3) + IFT_FLOPS per inverse map.
     f_cp, f_pair, f_adj, n_inv, f_cadj = oracle.count_flops(sub, itf.master, prm, ps[::16], pm[::16], detail=True)
-    f_cand, _ = oracle.count_flops(sub, itf.master, prm, cs[::16], cm[::16])
     npp = max(1, ps[::16].size)
     return {"pairs": int(ps.size), "t_fwd": t_fwd, "t_all": t_all,
-            "flops_per_unit": {"clip": f_cand / max(1, cs[::16].size),
-                               "pair_poly": f_cp / npp,
+            "flops_per_unit": {"pair_poly": f_cp / npp,
                                "pair_fwd": (f_pair - f_cp) / npp,
                                "pair_bwd": (f_pair - f_cp + f_adj - f_cadj + IFT_FLOPS * n_inv) / npp},
             "sample": f"slave elements 0..{n_slave_el_sample - 1} of the workload (the first "
@@ -246,8 +241,8 @@ def main():
     ms_step = (t1 - t0) * 1e3 / args.steps
     per_step = {k: v[0] / args.steps for k, v in tim.items()}
     per_launch = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in tim.items()}
-    fwd_ms = sum(per_step[k] for k in ("prep", "bin_sort", "cand", "clip", "compact", "pattern", "pair_poly",
-                                        "pair_fwd", "assemble"))
+    fwd_ms = sum(per_step[k] for k in ("prep", "bin_sort", "cand", "clip", "compact", "pattern",
+                                        "pair_poly", "pair_fwd", "assemble"))
 
     if args.calib_copy:
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
@@ -260,11 +255,12 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(itf, args.cpu_sample)
 
-    # roofline of the dominant single-kernel phase (all are FP64-VALU or
-    # latency bound): achieved = oracle-counted algorithmic flops per unit x
+    # roofline of the longest of the pair kernels (FP64-VALU bound; the search
+    # and pattern kernels are shorter, latency bound, and are reported by their
+    # phase times): achieved = oracle-counted algorithmic flops per unit x
     # units per launch / average launch time from the library's event timers
     # over the timed steps
-    units = {"clip": n_cand, "pair_poly": n_pairs, "pair_fwd": n_pairs, "pair_bwd": n_pairs}
+    units = {"pair_poly": n_pairs, "pair_fwd": n_pairs, "pair_bwd": n_pairs}
 
     def roofline(k):
         fp = cpu["flops_per_unit"][k] if cpu else None
@@ -276,12 +272,12 @@ def main():
         return {"bound": "alu", "kernel": KERNELS[k][0], "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
                 "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
                 "traffic": traffic, "traffic_unit": "bytes per launch" if traffic else None,
-                "flops_per_unit": fp, "unit_kind": "candidate" if k == "clip" else "pair",
+                "flops_per_unit": fp, "unit_kind": "pair",
                 "units_per_launch": units[k], "launch_ms": per_launch[k]}
 
     dominant = max(units, key=lambda k: per_launch.get(k, 0.0))
     roof = roofline(dominant)
-    others = {KERNELS[k][0]: roofline(k) for k in units if k != dominant}
+    others = {KERNELS[k][0]: roofline(k) for k in units if k != dominant and per_launch.get(k)}
     out = {
         "metric": "mortar element pairs integrated/sec (D,M,gap) fwd and fwd+bwd, 1 MI355X",
         "value": n_pairs / (ms_step * 1e-3),

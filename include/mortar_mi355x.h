@@ -122,8 +122,8 @@ int mt_upload(mt_ctx* ctx, int side, int64_t n_nodes, const double* x, const dou
  * fixed-topology evaluation a Newton iteration or a gradient check needs.
  * mt_integrate / mt_backward then use the new coordinates; mt_build_pairs
  * recomputes the pairs.  Coordinates changed in place (same pointers) must
- * also be announced with this call before mt_backward, which otherwise
- * reuses the clip polygons of the last mt_integrate.  Errors: MT_ESTATE
+ * also be announced with this call before mt_integrate / mt_backward, which
+ * otherwise reuse the clip polygons computed at the old ones.  Errors: MT_ESTATE
  * (side not uploaded), MT_EINVAL. */
 int mt_update_coordinates(mt_ctx* ctx, int side, const double* x, const double* y, const double* z,
                           void* stream);
@@ -140,10 +140,12 @@ int mt_update_coordinates(mt_ctx* ctx, int side, const double* x, const double* 
  *     with a radix sort, bin ranges by segmented scan;
  *  3. candidates: (s, m) whose boxes overlap after enlarging the slave box by
  *     delta, found in the 27 bins around s, sorted by (s, m);
- *  4. each candidate is projected onto the slave auxiliary plane and the
- *     slave polygon is clipped by the master polygon (Sutherland-Hodgman,
- *     then cleanup); a candidate whose cleaned polygon has >= 3 vertices and
- *     area > eps_a * slave area is a pair.
+ *  4. each candidate is projected onto the slave auxiliary plane and
+ *     screened (degenerate elements, a separating edge line); the rest are
+ *     clipped, slave polygon by master polygon (Sutherland-Hodgman, then
+ *     cleanup); a candidate whose cleaned polygon has >= 3 vertices and
+ *     area > eps_a * slave area is a pair.  The pairs' clip polygons are kept
+ *     for mt_integrate / mt_backward at these coordinates.
  * Writes the counts to *n_cand and *n_pairs (host).  Synchronises `stream`.
  * Errors: MT_ESTATE (a side not uploaded), MT_EINVAL (connectivity out of
  * range), MT_EDEGENERATE (a slave element with non-positive projected area
@@ -174,10 +176,10 @@ int mt_get_csr(mt_ctx* ctx, int32_t* D_rowptr, int32_t* D_col, int32_t* M_rowptr
                void* stream);
 
 /* Segment-based integration (Alg. 1, triangulation and quadrature steps)
- * and assembly: for every pair, the clip polygon is recomputed at the
- * current coordinates (and kept with each vertex's provenance for
- * mt_backward), split into a fan of triangles from its vertex 0 and
- * integrated with the triangle rule; local
+ * and assembly: for every pair, the clip polygon (that of mt_build_pairs,
+ * recomputed first if the coordinates were replaced since, and kept with
+ * each vertex's provenance for mt_backward) is split into a fan of
+ * triangles from its vertex 0 and integrated with the triangle rule; local
  * blocks D_e[j][k] = int Phi_j N_k, M_e[j][l] = int Phi_j (N_l o chi),
  * g_e[j] = int Phi_j (h_master - h_slave) (heights along n0) are summed into
  * D_val[nnz_D], M_val[nnz_M] (CSR order of mt_csr_pattern) and gap[n_s_nodes]
@@ -192,8 +194,8 @@ int mt_integrate(mt_ctx* ctx, double* D_val, double* M_val, double* gap, void* s
  * pattern (the pair list is held fixed).  W_D[nnz_D], W_M[nnz_M],
  * w_g[n_s_nodes] in; gXs[3 * n_s_nodes], gXm[3 * n_m_nodes] out, laid out
  * structure-of-arrays (x block, then y, then z), overwritten.  Uses the clip
- * polygons of the last mt_integrate when the coordinates have not been
- * replaced since (mt_upload / mt_update_coordinates), else recomputes them;
+ * polygons of the last mt_build_pairs / mt_integrate when the coordinates
+ * have not been replaced since (mt_update_coordinates), else recomputes them;
  * the geometry is then differentiated in reverse mode, the inverse maps
  * through the implicit-function derivative, each clip vertex through the
  * two lines it lies on.  Errors: MT_ESTATE,
@@ -209,17 +211,17 @@ int mt_get_stats(mt_ctx* ctx, mt_stats* st);
  * The per-process phase timings of the paper (contact evaluation, assembly,
  * Sec. "Numerical experiments") as per-launch HIP events: when enabled, every
  * phase below is bracketed by two events recorded on the call's stream. */
-#define MT_T_PREP 0        /* element bounding boxes and grid reductions */
+#define MT_T_PREP 0        /* element bounding boxes, grid reductions, per-element data */
 #define MT_T_BIN_SORT 1    /* master bin keys, radix sort, bin ranges */
-#define MT_T_CAND 2        /* candidate count, scan and fill */
-#define MT_T_CLIP 3        /* projection + clip of every candidate (one kernel) */
-#define MT_T_COMPACT 4     /* pair-list compaction */
+#define MT_T_CAND 2        /* candidate count, scan, fill with screening (projection, separating line) */
+#define MT_T_CLIP 3        /* clip and cleanup of the screened candidates (one kernel) */
+#define MT_T_COMPACT 4     /* scans, screened-candidate list, pair-list and polygon compaction */
 #define MT_T_PATTERN 5     /* CSR pattern and position maps */
-#define MT_T_PAIR_FWD 6    /* segment integration of all pairs (one kernel) */
-#define MT_T_ASSEMBLE 7    /* CSR assembly of D, M, gap (one kernel) */
-#define MT_T_PAIR_BWD 8    /* backward of all pairs (one kernel) */
-#define MT_T_GRAD_REDUCE 9 /* per-node gradient sums */
-#define MT_T_PAIR_POLY 10  /* clip polygons of all pairs (one kernel) */
+#define MT_T_PAIR_POLY 6   /* clip polygons of all pairs after a coordinate change (one kernel) */
+#define MT_T_PAIR_FWD 7    /* segment integration of all pairs (one kernel) */
+#define MT_T_ASSEMBLE 8    /* CSR assembly of D, M, gap (one kernel) */
+#define MT_T_PAIR_BWD 9    /* backward of all pairs (one kernel) */
+#define MT_T_GRAD_REDUCE 10 /* per-node gradient sums */
 #define MT_T_COUNT 11
 
 typedef struct mt_timings {

@@ -33,8 +33,8 @@ class mt_stats(ctypes.Structure):
                 ("n_bins", ctypes.c_int64 * 3), ("bin_size", ctypes.c_double * 3)]
 
 
-MT_T_NAMES = ["prep", "bin_sort", "cand", "clip", "compact", "pattern", "pair_fwd", "assemble", "pair_bwd",
-              "grad_reduce", "pair_poly"]
+MT_T_NAMES = ["prep", "bin_sort", "cand", "clip", "compact", "pattern", "pair_poly", "pair_fwd", "assemble",
+              "pair_bwd", "grad_reduce"]
 MT_T_COUNT = len(MT_T_NAMES)
 
 

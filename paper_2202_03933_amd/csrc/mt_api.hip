@@ -160,13 +160,14 @@ int mt_destroy(mt_ctx* c) {
   if (!c) return MT_OK;
   DeviceScope ds(c->device);
   (void)hipDeviceSynchronize();
-  Buf* bufs[] = {&c->box_s, &c->box_m, &c->sdata, &c->reduce, &c->counters, &c->keys, &c->vals,
-                 &c->keys_tmp, &c->vals_tmp, &c->cell_start, &c->cell_end, &c->cand_cnt, &c->cand_tmp, &c->cand_off,
+  Buf* bufs[] = {&c->box_s, &c->box_m, &c->sdata, &c->mdata, &c->reduce, &c->counters, &c->keys, &c->vals,
+                 &c->keys_tmp, &c->vals_tmp, &c->cell_range, &c->sbox, &c->cand_cnt, &c->cand_tmp, &c->cand_off,
                  &c->cand_s, &c->cand_m, &c->cand_nv, &c->cand_flag, &c->cand_scan, &c->pair_s, &c->pair_m,
                  &c->pair_nv, &c->pair_off, &c->inc_cnt, &c->inc_off, &c->inc_cur, &c->inc_list, &c->minc_cnt,
                  &c->minc_off, &c->minc_cur, &c->minc_list, &c->rawD_cnt, &c->rawD_off, &c->rawD, &c->rawM_cnt,
                  &c->rawM_off, &c->rawM, &c->pat_keep, &c->D_cnt, &c->D_rowptr, &c->D_col, &c->M_cnt, &c->M_rowptr,
-                 &c->M_col, &c->posD, &c->posM, &c->poly_u, &c->poly_v, &c->poly_lab, &c->poly_nf, &c->blk, &c->gpair, &c->mp_keys, &c->mp_vals, &c->mp_off,
+                 &c->M_col, &c->posD, &c->posM, &c->poly_u, &c->poly_v, &c->poly_lab, &c->poly_nf, &c->maybe_list,
+                 &c->maybe_flag, &c->maybe_scan, &c->mpoly_u, &c->mpoly_v, &c->mpoly_lab, &c->mpoly_nf, &c->blk, &c->gpair, &c->mp_keys, &c->mp_vals, &c->mp_off,
                  &c->scan_tmp, &c->sort_hist, &c->host_tmp};
   for (Buf* b : bufs) release(*b);
   for (auto& iv : c->intervals) {
@@ -243,13 +244,14 @@ int mt_build_pairs(mt_ctx* c, int64_t* n_cand_out, int64_t* n_pairs_out, void* s
   MT_HIP(ensure(c->box_s, sizeof(double) * 6 * (size_t)ns));
   MT_HIP(ensure(c->box_m, sizeof(double) * 6 * (size_t)nm));
   MT_HIP(ensure(c->sdata, sizeof(double) * SD_N * (size_t)ns));
+  MT_HIP(ensure(c->mdata, sizeof(double) * 12 * (size_t)std::max(nm, 1)));
   PrepReduce* red = c->reduce.as<PrepReduce>();
   {
     PhaseTimer t(c, MT_T_PREP, st);
     MT_HIP(launch_init_reduce(red, st));
     MT_HIP(hipMemsetAsync(c->counters.p, 0, sizeof(Counters), st));
-    MT_HIP(launch_prep(S, true, c->box_s.as<double>(), c->sdata.as<double>(), red, st));
-    MT_HIP(launch_prep(M, false, c->box_m.as<double>(), nullptr, red, st));
+    MT_HIP(launch_prep(S, true, c->box_s.as<double>(), c->sdata.as<double>(), nullptr, red, st));
+    MT_HIP(launch_prep(M, false, c->box_m.as<double>(), nullptr, c->mdata.as<double>(), red, st));
   }
   PrepReduce hr;
   MT_HIP(hipMemcpyAsync(&hr, red, sizeof(hr), hipMemcpyDeviceToHost, st));
@@ -263,8 +265,8 @@ int mt_build_pairs(mt_ctx* c, int64_t* n_cand_out, int64_t* n_pairs_out, void* s
   MT_HIP(ensure(c->vals, sizeof(uint32_t) * (size_t)nm));
   MT_HIP(ensure(c->keys_tmp, sizeof(uint32_t) * (size_t)nm));
   MT_HIP(ensure(c->vals_tmp, sizeof(uint32_t) * (size_t)nm));
-  MT_HIP(ensure(c->cell_start, sizeof(int32_t) * (size_t)g.ncells));
-  MT_HIP(ensure(c->cell_end, sizeof(int32_t) * (size_t)g.ncells));
+  MT_HIP(ensure(c->cell_range, sizeof(int2) * (size_t)g.ncells));
+  MT_HIP(ensure(c->sbox, sizeof(double) * 6 * (size_t)std::max(nm, 1)));
   MT_HIP(ensure(c->sort_hist, sizeof(int32_t) * (size_t)(2 * 256 * ((nm + 2047) / 2048 + 1) + 1)));
   MT_HIP(ensure(c->scan_tmp, 1 << 20));
   {
@@ -272,10 +274,9 @@ int mt_build_pairs(mt_ctx* c, int64_t* n_cand_out, int64_t* n_pairs_out, void* s
     MT_HIP(launch_master_keys(c->box_m.as<double>(), nm, g, c->keys.as<uint32_t>(), c->vals.as<uint32_t>(), st));
     MT_HIP(radix_sort_pairs(c->keys.as<uint32_t>(), c->vals.as<uint32_t>(), c->keys_tmp.as<uint32_t>(),
                             c->vals_tmp.as<uint32_t>(), nm, bits_for(g.ncells), c->sort_hist, c->scan_tmp, st));
-    MT_HIP(hipMemsetAsync(c->cell_start.p, 0, sizeof(int32_t) * (size_t)g.ncells, st));
-    MT_HIP(hipMemsetAsync(c->cell_end.p, 0, sizeof(int32_t) * (size_t)g.ncells, st));
-    MT_HIP(launch_cell_ranges(c->keys.as<uint32_t>(), nm, c->cell_start.as<int32_t>(), c->cell_end.as<int32_t>(),
-                              st));
+    MT_HIP(hipMemsetAsync(c->cell_range.p, 0, sizeof(int2) * (size_t)g.ncells, st));
+    MT_HIP(launch_cell_ranges(c->keys.as<uint32_t>(), c->vals.as<uint32_t>(), nm, c->box_m.as<double>(),
+                              c->cell_range.as<int2>(), c->sbox.as<double>(), st));
   }
 
   // candidates: count, scan, fill (sorted by master within each slave)
@@ -284,9 +285,9 @@ int mt_build_pairs(mt_ctx* c, int64_t* n_cand_out, int64_t* n_pairs_out, void* s
   MT_HIP(ensure(c->cand_tmp, sizeof(int32_t) * (size_t)cand_tmp_per_slave() * (size_t)std::max(ns, 1)));
   {
     PhaseTimer t(c, MT_T_CAND, st);
-    MT_HIP(launch_cand_count(c->box_s.as<double>(), ns, c->box_m.as<double>(), nm, c->vals.as<uint32_t>(),
-                             c->cell_start.as<int32_t>(), c->cell_end.as<int32_t>(), g, c->params.delta,
-                             c->cand_cnt.as<int32_t>(), c->cand_tmp.as<int32_t>(), st));
+    MT_HIP(launch_cand_count(c->box_s.as<double>(), ns, c->sbox.as<double>(), c->vals.as<uint32_t>(),
+                             c->cell_range.as<int2>(), g, c->params.delta, c->cand_cnt.as<int32_t>(),
+                             c->cand_tmp.as<int32_t>(), st));
     MT_HIP(scan_exclusive(c->cand_cnt.as<int32_t>(), c->cand_off.as<int32_t>(), ns, c->scan_tmp, st));
   }
   int32_t ncand32 = 0;
@@ -299,29 +300,55 @@ int mt_build_pairs(mt_ctx* c, int64_t* n_cand_out, int64_t* n_pairs_out, void* s
   MT_HIP(ensure(c->cand_nv, (size_t)n_cand));
   MT_HIP(ensure(c->cand_flag, sizeof(int32_t) * ((size_t)n_cand + 1)));
   MT_HIP(ensure(c->cand_scan, sizeof(int32_t) * ((size_t)n_cand + 1)));
-  {
-    PhaseTimer t(c, MT_T_CAND, st);
-    MT_HIP(launch_cand_fill(c->box_s.as<double>(), ns, c->box_m.as<double>(), nm, c->vals.as<uint32_t>(),
-                            c->cell_start.as<int32_t>(), c->cell_end.as<int32_t>(), g, c->params.delta,
-                            c->cand_tmp.as<int32_t>(), c->cand_off.as<int32_t>(), c->cand_s.as<int32_t>(),
-                            c->cand_m.as<int32_t>(), st));
-  }
-
-  // clip every candidate; compact the pairs
+  // candidates, each screened as it is written (projection onto the slave
+  // plane, degeneracy checks, separating-line test)
   const KParams kp = kparams(c->params);
   Counters* cnt = c->counters.as<Counters>();
   {
-    PhaseTimer t(c, MT_T_CLIP, st);
-    MT_HIP(launch_clip_count(S, M, c->sdata.as<double>(), kp, c->cand_s.as<int32_t>(), c->cand_m.as<int32_t>(), n_cand,
-                             c->cand_nv.as<uint8_t>(), c->cand_flag.as<int32_t>(), cnt, st));
+    PhaseTimer t(c, MT_T_CAND, st);
+    MT_HIP(launch_cand_fill(c->box_s.as<double>(), ns, c->sbox.as<double>(), c->vals.as<uint32_t>(),
+                            c->cell_range.as<int2>(), g, c->params.delta, c->cand_tmp.as<int32_t>(), c->cand_off.as<int32_t>(), c->cand_s.as<int32_t>(),
+                            c->cand_m.as<int32_t>(), c->sdata.as<double>(), c->mdata.as<double>(), kp.eps_a,
+                            c->cand_nv.as<uint8_t>(), c->cand_flag.as<int32_t>(), cnt, st));
   }
+
+  // clip the screened candidates, compact the pairs
   {
     PhaseTimer t(c, MT_T_COMPACT, st);
     MT_HIP(scan_exclusive(c->cand_flag.as<int32_t>(), c->cand_scan.as<int32_t>(), n_cand, c->scan_tmp, st));
   }
+  int32_t nmaybe32 = 0;
+  MT_HIP(hipMemcpyAsync(&nmaybe32, c->cand_scan.as<int32_t>() + n_cand, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  MT_HIP(hipStreamSynchronize(st));
+  const int64_t n_maybe = nmaybe32;
+  const size_t nmb = (size_t)std::max<int64_t>(n_maybe, 1);
+  MT_HIP(ensure(c->maybe_list, sizeof(int32_t) * nmb));
+  MT_HIP(ensure(c->maybe_flag, sizeof(int32_t) * (nmb + 1)));
+  MT_HIP(ensure(c->maybe_scan, sizeof(int32_t) * (nmb + 1)));
+  MT_HIP(ensure(c->mpoly_u, sizeof(double) * CAP0 * nmb));
+  MT_HIP(ensure(c->mpoly_v, sizeof(double) * CAP0 * nmb));
+  MT_HIP(ensure(c->mpoly_lab, CAP0 * nmb));
+  MT_HIP(ensure(c->mpoly_nf, nmb));
+  const PolyBuf mpoly{c->mpoly_u.as<double>(), c->mpoly_v.as<double>(), c->mpoly_lab.as<uint8_t>(),
+                      c->mpoly_nf.as<uint8_t>(), (int64_t)nmb};
+  {
+    PhaseTimer t(c, MT_T_COMPACT, st);
+    MT_HIP(launch_maybe_list(c->cand_flag.as<int32_t>(), c->cand_scan.as<int32_t>(), n_cand,
+                             c->maybe_list.as<int32_t>(), st));
+  }
+  {
+    PhaseTimer t(c, MT_T_CLIP, st);
+    MT_HIP(launch_clip_screened(c->mdata.as<double>(), c->sdata.as<double>(), ns, kp, c->cand_s.as<int32_t>(), c->cand_m.as<int32_t>(),
+                                c->maybe_list.as<int32_t>(), n_maybe, c->cand_nv.as<uint8_t>(),
+                                c->maybe_flag.as<int32_t>(), mpoly, cnt, st));
+  }
+  {
+    PhaseTimer t(c, MT_T_COMPACT, st);
+    MT_HIP(scan_exclusive(c->maybe_flag.as<int32_t>(), c->maybe_scan.as<int32_t>(), n_maybe, c->scan_tmp, st));
+  }
   int32_t np32 = 0;
   Counters hc;
-  MT_HIP(hipMemcpyAsync(&np32, c->cand_scan.as<int32_t>() + n_cand, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  MT_HIP(hipMemcpyAsync(&np32, c->maybe_scan.as<int32_t>() + n_maybe, sizeof(int32_t), hipMemcpyDeviceToHost, st));
   MT_HIP(hipMemcpyAsync(&hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, st));
   MT_HIP(hipStreamSynchronize(st));
   const int64_t n_pairs = np32;
@@ -329,16 +356,23 @@ int mt_build_pairs(mt_ctx* c, int64_t* n_cand_out, int64_t* n_pairs_out, void* s
   MT_HIP(ensure(c->pair_m, sizeof(int32_t) * (size_t)n_pairs));
   MT_HIP(ensure(c->pair_nv, (size_t)n_pairs));
   MT_HIP(ensure(c->pair_off, sizeof(int32_t) * ((size_t)ns + 1)));
+  c->n_cand = n_cand;
+  c->n_maybe = n_maybe;
+  c->n_pairs = n_pairs;
+  {
+    int rc = ensure_poly(c);
+    if (rc) return rc;
+  }
   {
     PhaseTimer t(c, MT_T_COMPACT, st);
-    MT_HIP(launch_compact(c->cand_s.as<int32_t>(), c->cand_m.as<int32_t>(), c->cand_nv.as<uint8_t>(),
-                          c->cand_scan.as<int32_t>(), n_cand, c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(),
-                          c->pair_nv.as<uint8_t>(), st));
-    MT_HIP(launch_pair_off(c->cand_off.as<int32_t>(), c->cand_scan.as<int32_t>(), ns, c->pair_off.as<int32_t>(),
-                           st));
+    MT_HIP(launch_compact_pairs(c->cand_s.as<int32_t>(), c->cand_m.as<int32_t>(), c->maybe_list.as<int32_t>(),
+                                c->maybe_flag.as<int32_t>(), c->maybe_scan.as<int32_t>(), n_maybe, mpoly,
+                                c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), c->pair_nv.as<uint8_t>(),
+                                poly_buf(c), st));
+    MT_HIP(launch_pair_off(c->cand_off.as<int32_t>(), c->cand_scan.as<int32_t>(), c->maybe_scan.as<int32_t>(), ns,
+                           c->pair_off.as<int32_t>(), st));
   }
-  c->n_cand = n_cand;
-  c->n_pairs = n_pairs;
+  c->poly_gen = c->coord_gen;
   c->have_pairs = true;
   if (n_cand_out) *n_cand_out = n_cand;
   if (n_pairs_out) *n_pairs_out = n_pairs;
@@ -485,7 +519,7 @@ int mt_integrate(mt_ctx* c, double* D_val, double* M_val, double* gap, void* str
     if (rc) return rc;
   }
   const PolyBuf poly = poly_buf(c);
-  {
+  if (c->poly_gen != c->coord_gen) {
     PhaseTimer t(c, MT_T_PAIR_POLY, st);
     MT_HIP(launch_pair_poly(S, M, kparams(c->params), c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), np, poly, st));
     c->poly_gen = c->coord_gen;

@@ -342,8 +342,6 @@ int launch_poly(mt_batch* b, hipStream_t st) {
 }
 
 int launch_fwd(mt_batch* b, hipStream_t st) {
-  int rc = launch_poly(b, st);
-  if (rc) return rc;
   const int bsz = b->tune.block;
   FwdFn f = pick_fwd(bsz, b->nq, b->dual);
   const int grid = b->num_cu * std::min(std::max(1, b->tune.blocks_per_cu),
@@ -380,6 +378,19 @@ int launch_bwd_all(mt_batch* b, hipStream_t st) {
                                                                  b->d_ritems_sm.as<WorkItem>());
     B_HIP(hipGetLastError());
   }
+  return MT_OK;
+}
+
+// Recomputes the clip polygons of every instance (one persistent launch,
+// outside any graph) when some instance's coordinates changed since its
+// polygons were computed.
+int refresh_polygons(mt_batch* b, hipStream_t st) {
+  bool stale = false;
+  for (mt_ctx* c : b->ctxs) stale = stale || c->poly_gen != c->coord_gen;
+  if (!stale) return MT_OK;
+  int rc = launch_poly(b, st);
+  if (rc) return rc;
+  for (mt_ctx* c : b->ctxs) c->poly_gen = c->coord_gen;
   return MT_OK;
 }
 
@@ -566,11 +577,10 @@ int mt_batch_forward(mt_batch* b, double* const* D_val, double* const* M_val, do
   }
   int rc = upload_inst(b, st);
   if (rc) return rc;
-  if (use_graph) rc = run_graph(&b->g_fwd, &b->g_fwd_stream, st, [&]() { return launch_fwd_all(b, st); });
-  else rc = launch_fwd_all(b, st);
+  rc = refresh_polygons(b, st);
   if (rc) return rc;
-  for (mt_ctx* c : b->ctxs) c->poly_gen = c->coord_gen;
-  return MT_OK;
+  if (use_graph) return run_graph(&b->g_fwd, &b->g_fwd_stream, st, [&]() { return launch_fwd_all(b, st); });
+  return launch_fwd_all(b, st);
 }
 
 int mt_batch_backward(mt_batch* b, const double* const* W_D, const double* const* W_M, const double* const* w_g,
@@ -591,13 +601,8 @@ int mt_batch_backward(mt_batch* b, const double* const* W_D, const double* const
   }
   int rc = upload_inst(b, st);
   if (rc) return rc;
-  bool stale = false;
-  for (mt_ctx* c : b->ctxs) stale = stale || c->poly_gen != c->coord_gen;
-  if (stale) {
-    rc = launch_poly(b, st);
-    if (rc) return rc;
-    for (mt_ctx* c : b->ctxs) c->poly_gen = c->coord_gen;
-  }
+  rc = refresh_polygons(b, st);
+  if (rc) return rc;
   if (use_graph) return run_graph(&b->g_bwd, &b->g_bwd_stream, st, [&]() { return launch_bwd_all(b, st); });
   return launch_bwd_all(b, st);
 }

@@ -290,24 +290,21 @@ __device__ __forceinline__ void slave_setup(const double Xs[4][3], const double 
   }
 }
 
-// Master part: projection of the master nodes onto the slave plane,
-// orientation, clip and cleanup, given the slave setup.
-template <bool LAB>
-__device__ __forceinline__ int pair_clip(const V2 S[4], double As, double hmax, const double Xm[4][3],
-                                         const double f[12], double eps_d, double eps_a, V2 Mn[4], double hm[4],
-                                         bool& flip, const LdsPoly<LAB>& P, int& res, int& status) {
+// Screening part of the master side: projection of the master nodes onto
+// the slave plane, degeneracy checks, orientation and the separating-line
+// quick exit.  Returns true when the candidate has to be clipped.
+__device__ __forceinline__ bool pair_screen(const V2 S[4], double As, const double Xm[4][3], const double f[12],
+                                            double eps_a, V2 Mn[4], double hm[4], bool& flip, int& status) {
   status = 0;
-  res = 0;
   flip = false;
 #pragma unroll
   for (int k = 0; k < 4; ++k) project(Xm[k], f, Mn[k], hm[k]);
-  if (!(As > 0.0)) { status = PS_DEGEN_SLAVE; return 0; }
-  const double tol_d = eps_d * hmax;
+  if (!(As > 0.0)) { status = PS_DEGEN_SLAVE; return false; }
   const double tol_a = eps_a * As;
   const double Am = quad_fan_area(Mn);
-  if (fabs(Am) <= tol_a) { status = PS_DEGEN_MASTER; return 0; }
+  if (fabs(Am) <= tol_a) { status = PS_DEGEN_MASTER; return false; }
   flip = Am < 0.0;
-  V2 Mo[4] = {Mn[0], flip ? Mn[3] : Mn[1], Mn[2], flip ? Mn[1] : Mn[3]};
+  const V2 Mo[4] = {Mn[0], flip ? Mn[3] : Mn[1], Mn[2], flip ? Mn[1] : Mn[3]};
   // Separating-line quick exit (exact): every slave vertex strictly outside
   // one master edge line, or every master vertex strictly outside one slave
   // edge line, means no overlap.  Same side test as the clip.
@@ -325,17 +322,39 @@ __device__ __forceinline__ int pair_clip(const V2 S[4], double As, double hmax, 
         const double c = dbu * (q.v - a.v) - dbv * (q.u - a.u);
         all_out = all_out && !(c >= 0.0);
       }
-      if (all_out) return 0;
+      if (all_out) return false;
     }
   }
+  return true;
+}
+
+// Clip and cleanup of a screened candidate; the polygon ends in buffer
+// `res` with the returned vertex count (0: not a pair).
+template <bool LAB>
+__device__ __forceinline__ int pair_clip_screened(const V2 S[4], double As, double hmax, const V2 Mn[4], bool flip,
+                                                  double eps_d, double eps_a, const LdsPoly<LAB>& P, int& res,
+                                                  int& status) {
+  const V2 Mo[4] = {Mn[0], flip ? Mn[3] : Mn[1], Mn[2], flip ? Mn[1] : Mn[3]};
   bool ovf;
+  res = 0;
   int n = clip_polygon<LAB>(S, Mo, P, res, ovf);
   if (ovf) { status = PS_OVERFLOW; return 0; }
-  n = cleanup<LAB>(P, res, n, tol_d);
+  n = cleanup<LAB>(P, res, n, eps_d * hmax);
   if (n < 3) return 0;
   const double Ap = poly_fan_area<LAB>(P, res, n);
-  if (!(Ap > tol_a)) return 0;
+  if (!(Ap > eps_a * As)) return 0;
   return n;
+}
+
+// Master part: projection of the master nodes onto the slave plane,
+// orientation, clip and cleanup, given the slave setup.
+template <bool LAB>
+__device__ __forceinline__ int pair_clip(const V2 S[4], double As, double hmax, const double Xm[4][3],
+                                         const double f[12], double eps_d, double eps_a, V2 Mn[4], double hm[4],
+                                         bool& flip, const LdsPoly<LAB>& P, int& res, int& status) {
+  res = 0;
+  if (!pair_screen(S, As, Xm, f, eps_a, Mn, hm, flip, status)) return 0;
+  return pair_clip_screened<LAB>(S, As, hmax, Mn, flip, eps_d, eps_a, P, res, status);
 }
 
 template <bool LAB>

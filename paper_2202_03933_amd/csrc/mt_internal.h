@@ -110,19 +110,27 @@ struct mt_ctx {
   // element preparation
   mt::Buf box_s, box_m;    // [6][n_el] lo xyz, hi xyz
   mt::Buf sdata;           // [SD_N][n_s_el] precomputed slave frame and polygon
+  mt::Buf mdata;           // [n_m_el][12] master element node coordinates
   mt::Buf reduce;          // PrepReduce
   mt::Buf counters;        // Counters
   // binning
   mt::Buf keys, vals, keys_tmp, vals_tmp;
-  mt::Buf cell_start, cell_end;
+  mt::Buf cell_range;      // int2 [ncells]: sorted-master range of each cell
+  mt::Buf sbox;            // [n_m_el][6] master boxes in cell order
   // candidates
   mt::Buf cand_cnt;        // [n_s_el + 1]
   mt::Buf cand_tmp;        // [CTMP][n_s_el] candidates kept by the count pass
   mt::Buf cand_off;        // [n_s_el + 1]
   mt::Buf cand_s, cand_m;  // [n_cand]
   mt::Buf cand_nv;         // uint8 [n_cand]
-  mt::Buf cand_flag;       // int32 [n_cand + 1]
-  mt::Buf cand_scan;       // int32 [n_cand + 1]
+  mt::Buf cand_flag;       // int32 [n_cand + 1] 1 = screened in (to be clipped)
+  mt::Buf cand_scan;       // int32 [n_cand + 1] exclusive scan of cand_flag
+  // screened candidates (index i < n_maybe)
+  int64_t n_maybe = 0;
+  mt::Buf maybe_list;      // int32 [n_maybe] candidate index
+  mt::Buf maybe_flag;      // int32 [n_maybe + 1] 1 = pair
+  mt::Buf maybe_scan;      // int32 [n_maybe + 1] exclusive scan of maybe_flag
+  mt::Buf mpoly_u, mpoly_v, mpoly_lab, mpoly_nf;  // their clip polygons (PolyBuf layout)
   // pairs
   mt::Buf pair_s, pair_m;  // [n_pairs]
   mt::Buf pair_nv;         // uint8 [n_pairs]
@@ -164,30 +172,34 @@ hipError_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 hipError_t fill_f64(double* p, double v, int64_t n, hipStream_t s);
 
 // ---- search (mt_search.hip) ------------------------------------------------
-hipError_t launch_prep(const DeviceMesh& m, bool slave, double* box, double* sd, PrepReduce* red, hipStream_t s);
+hipError_t launch_prep(const DeviceMesh& m, bool slave, double* box, double* sd, double* md, PrepReduce* red,
+                       hipStream_t s);
 hipError_t launch_init_reduce(PrepReduce* red, hipStream_t s);
 void grid_from_reduce(const PrepReduce& r, double delta, double bin_size, Grid& g);
 hipError_t launch_master_keys(const double* box_m, int32_t n_m, Grid g, uint32_t* keys, uint32_t* vals,
                               hipStream_t s);
-hipError_t launch_cell_ranges(const uint32_t* keys, int32_t n, int32_t* start, int32_t* end,
-                              hipStream_t s);
-hipError_t launch_cand_count(const double* box_s, int32_t n_s, const double* box_m, int32_t n_m,
-                             const uint32_t* mvals, const int32_t* start, const int32_t* end, Grid g,
-                             double delta, int32_t* count, int32_t* tmp, hipStream_t s);
-hipError_t launch_cand_fill(const double* box_s, int32_t n_s, const double* box_m, int32_t n_m,
-                            const uint32_t* mvals, const int32_t* start, const int32_t* end, Grid g,
-                            double delta, const int32_t* tmp, const int32_t* off, int32_t* cand_s, int32_t* cand_m,
-                            hipStream_t s);
+hipError_t launch_cell_ranges(const uint32_t* keys, const uint32_t* vals, int32_t n, const double* box_m,
+                              int2* range, double* sbox, hipStream_t s);
+hipError_t launch_cand_count(const double* box_s, int32_t n_s, const double* sbox, const uint32_t* mvals,
+                             const int2* range, Grid g, double delta, int32_t* count, int32_t* tmp, hipStream_t s);
+hipError_t launch_cand_fill(const double* box_s, int32_t n_s, const double* sbox, const uint32_t* mvals,
+                            const int2* range, Grid g, double delta, const int32_t* tmp, const int32_t* off,
+                            int32_t* cand_s, int32_t* cand_m, const double* sd, const double* md, double eps_a,
+                            uint8_t* nv, int32_t* flag, Counters* cnt, hipStream_t s);
 int cand_tmp_per_slave();
 
 // ---- pairs (mt_pairs.hip) ----------------------------------------------------
-hipError_t launch_clip_count(const DeviceMesh& S, const DeviceMesh& M, const double* sdata, const KParams& kp, const int32_t* cand_s, const int32_t* cand_m,
-                             int64_t n_cand, uint8_t* nv, int32_t* flag, Counters* cnt, hipStream_t s);
-hipError_t launch_compact(const int32_t* cand_s, const int32_t* cand_m, const uint8_t* cand_nv,
-                          const int32_t* scan, int64_t n_cand, int32_t* pair_s, int32_t* pair_m,
-                          uint8_t* pair_nv, hipStream_t s);
-hipError_t launch_pair_off(const int32_t* cand_off, const int32_t* scan, int32_t n_s, int32_t* pair_off,
-                           hipStream_t s);
+hipError_t launch_maybe_list(const int32_t* flag, const int32_t* mscan, int64_t n_cand, int32_t* mlist,
+                             hipStream_t s);
+hipError_t launch_clip_screened(const double* mdata, const double* sdata, int32_t n_s, const KParams& kp,
+                                const int32_t* cand_s, const int32_t* cand_m, const int32_t* mlist, int64_t n_maybe,
+                                uint8_t* nv, int32_t* flag2, const PolyBuf& out, Counters* cnt, hipStream_t s);
+hipError_t launch_compact_pairs(const int32_t* cand_s, const int32_t* cand_m, const int32_t* mlist,
+                                const int32_t* flag2, const int32_t* scan2, int64_t n_maybe, const PolyBuf& src,
+                                int32_t* pair_s, int32_t* pair_m, uint8_t* pair_nv, const PolyBuf& dst,
+                                hipStream_t s);
+hipError_t launch_pair_off(const int32_t* cand_off, const int32_t* mscan, const int32_t* scan2, int32_t n_s,
+                           int32_t* pair_off, hipStream_t s);
 hipError_t launch_pair_poly(const DeviceMesh& S, const DeviceMesh& M, const KParams& kp, const int32_t* pair_s,
                             const int32_t* pair_m, int64_t n_pairs, const PolyBuf& poly, hipStream_t s);
 hipError_t launch_pair_fwd(const DeviceMesh& S, const DeviceMesh& M, const KParams& kp, const int32_t* pair_s,

@@ -57,6 +57,18 @@ struct GPoly {
 
 __device__ __forceinline__ GPoly gpoly(const PolyBuf& b, int64_t p) { return GPoly{b.u, b.v, b.lab, b.stride, p}; }
 
+// Copies a clip polygon (n vertices in LDS buffer res) and its provenance to
+// entry idx of a polygon buffer.
+__device__ __forceinline__ void poly_store(const LdsPoly<true>& P, int res, int n, bool flip, const PolyBuf& out,
+                                           int64_t idx) {
+  out.nf[idx] = (uint8_t)(n | (flip ? 0x80 : 0));
+  for (int i = 0; i < n; ++i) {
+    out.u[(int64_t)i * out.stride + idx] = P.u[P.at(res, i)];
+    out.v[(int64_t)i * out.stride + idx] = P.v[P.at(res, i)];
+    out.lab[(int64_t)i * out.stride + idx] = P.vl[P.at(res, i)];
+  }
+}
+
 // Frame, projection, orientation, clip and cleanup of pair p; stores the
 // polygon and its provenance.
 __device__ __forceinline__ void store_pair_polygon(const double Xs[4][3], const double Xm[4][3], const KParams& kp,
@@ -68,12 +80,7 @@ __device__ __forceinline__ void store_pair_polygon(const double Xs[4][3], const 
   int res, st;
   bool flip;
   const int n = pair_geometry<true>(Xs, Xm, f, kp.eps_d, kp.eps_a, S, Mn, hs, hm, flip, P, res, st);
-  out.nf[p] = (uint8_t)(n | (flip ? 0x80 : 0));
-  for (int i = 0; i < n; ++i) {
-    out.u[(int64_t)i * out.stride + p] = P.u[P.at(res, i)];
-    out.v[(int64_t)i * out.stride + p] = P.v[P.at(res, i)];
-    out.lab[(int64_t)i * out.stride + p] = P.vl[P.at(res, i)];
-  }
+  poly_store(P, res, n, flip, out, p);
 }
 
 // Projected nodes and heights of both elements on the slave plane f.

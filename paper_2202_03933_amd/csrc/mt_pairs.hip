@@ -13,7 +13,6 @@ namespace mt {
 namespace {
 
 constexpr int BSC = 64;   // clip / integrate block: one wavefront
-constexpr int CPT = 4;    // candidates per thread in the candidate pass
 constexpr int BS = 256;
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x) {
@@ -22,80 +21,113 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x)
   return x;
 }
 
-// Candidate pass: projection of the master element onto the precomputed
-// slave plane, clip and cleanup; writes the vertex count (0: not a pair).
-__global__ __launch_bounds__(BSC) void k_clip_count(const double* __restrict__ sd, int32_t n_s,
-                                                     const double* __restrict__ xm, const double* __restrict__ ym,
-                                                     const double* __restrict__ zm, const int32_t* __restrict__ cm,
-                                                     KParams kp, const int32_t* __restrict__ cand_s,
-                                                     const int32_t* __restrict__ cand_m, int64_t n_cand,
-                                                     uint8_t* __restrict__ nv_out, int32_t* __restrict__ flag,
-                                                     Counters* cnt) {
+// Slave data of candidate pass kernels: frame, projected slave polygon,
+// its area and longest edge, precomputed per slave element.
+__device__ __forceinline__ void load_slave_data(const double* __restrict__ sd, int32_t n_s, int s, double f[12],
+                                                V2 S[4], double& As, double& hmax) {
+#pragma unroll
+  for (int k = 0; k < 12; ++k) f[k] = sd[(int64_t)k * n_s + s];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    S[k].u = sd[(int64_t)(12 + k) * n_s + s];
+    S[k].v = sd[(int64_t)(16 + k) * n_s + s];
+  }
+  As = sd[(int64_t)20 * n_s + s];
+  hmax = sd[(int64_t)21 * n_s + s];
+}
+
+// Screened candidates in candidate order: mlist[mscan[c]] = c.
+__global__ __launch_bounds__(BS) void k_maybe_list(const int32_t* __restrict__ flag, const int32_t* __restrict__ mscan,
+                                                    int64_t n_cand, int32_t* __restrict__ mlist) {
+  const int64_t c = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (c < n_cand && flag[c]) mlist[mscan[c]] = (int32_t)c;
+}
+
+// Clip and cleanup of every screened candidate (LDS clip buffers with
+// provenance): vertex count to nv[c], pair flag to flag2[i], polygon to
+// entry i of the screened-candidate polygon buffer.
+__global__ __launch_bounds__(BSC) void k_clip_screened(const double* __restrict__ sd, int32_t n_s,
+                                                        const double* __restrict__ md, KParams kp, const int32_t* __restrict__ cand_s,
+                                                        const int32_t* __restrict__ cand_m,
+                                                        const int32_t* __restrict__ mlist, int64_t n_maybe,
+                                                        uint8_t* __restrict__ nv_out, int32_t* __restrict__ flag2,
+                                                        PolyBuf out, Counters* cnt) {
   __shared__ double su[CAPT * BSC], sv[CAPT * BSC];
-  __shared__ unsigned int hist[20];
-  if (threadIdx.x < 20) hist[threadIdx.x] = 0;
+  __shared__ uint8_t sl[CAPT * BSC], se[CAPT * BSC];
+  __shared__ unsigned int hist[18];
+  if (threadIdx.x < 18) hist[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t tile = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * (BSC * CPT);
-#pragma unroll 1
-  for (int it = 0; it < CPT; ++it) {
-  const int64_t c = tile + it * BSC + threadIdx.x;
-  if (c < n_cand) {
+  const int64_t i = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * BSC + threadIdx.x;
+  if (i < n_maybe) {
+    const int c = mlist[i];
     const int s = cand_s[c], m = cand_m[c];
-    double f[12], Xm[4][3];
-#pragma unroll
-    for (int k = 0; k < 12; ++k) f[k] = sd[(int64_t)k * n_s + s];
+    double f[12], Xm[4][3], As, hmax;
     V2 S[4];
+    load_slave_data(sd, n_s, s, f, S, As, hmax);
+    {
+      const double2* src = reinterpret_cast<const double2*>(md + (int64_t)12 * m);
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      S[k].u = sd[(int64_t)(12 + k) * n_s + s];
-      S[k].v = sd[(int64_t)(16 + k) * n_s + s];
+      for (int k = 0; k < 6; ++k) {
+        const double2 t = src[k];
+        Xm[(2 * k) / 3][(2 * k) % 3] = t.x;
+        Xm[(2 * k + 1) / 3][(2 * k + 1) % 3] = t.y;
+      }
     }
-    const double As = sd[(int64_t)20 * n_s + s], hmax = sd[(int64_t)21 * n_s + s];
-    load_nodes(xm, ym, zm, load_conn(cm, m), Xm);
-    LdsPoly<false> P{su + threadIdx.x, sv + threadIdx.x, nullptr, nullptr, BSC};
     V2 Mn[4];
     double hm[4];
-    int res, st;
+    int st, res;
     bool flip;
-    const int n = pair_clip<false>(S, As, hmax, Xm, f, kp.eps_d, kp.eps_a, Mn, hm, flip, P, res, st);
+    pair_screen(S, As, Xm, f, kp.eps_a, Mn, hm, flip, st);
+    const LdsPoly<true> P{su + threadIdx.x, sv + threadIdx.x, sl + threadIdx.x, se + threadIdx.x, BSC};
+    const int n = pair_clip_screened<true>(S, As, hmax, Mn, flip, kp.eps_d, kp.eps_a, P, res, st);
     nv_out[c] = (uint8_t)n;
-    flag[c] = n >= 3 ? 1 : 0;
+    flag2[i] = n >= 3 ? 1 : 0;
+    poly_store(P, res, n, flip, out, i);
     atomicAdd(&hist[n], 1u);
-    if (st & PS_DEGEN_SLAVE) atomicAdd(&hist[17], 1u);
-    if (st & PS_DEGEN_MASTER) atomicAdd(&hist[18], 1u);
-    if (st & PS_OVERFLOW) atomicAdd(&hist[19], 1u);
-  }
+    if (st & PS_OVERFLOW) atomicAdd(&hist[17], 1u);
   }
   __syncthreads();
-  if (threadIdx.x < 20 && hist[threadIdx.x]) {
+  if (threadIdx.x < 18 && hist[threadIdx.x]) {
     const unsigned long long v = hist[threadIdx.x];
     if (threadIdx.x < 17) atomicAdd(&cnt->hist[threadIdx.x], v);
-    else if (threadIdx.x == 17) atomicAdd(&cnt->degen_slave, v);
-    else if (threadIdx.x == 18) atomicAdd(&cnt->degen_master, v);
     else atomicAdd(&cnt->overflow, v);
   }
 }
 
-__global__ __launch_bounds__(BS) void k_compact(const int32_t* __restrict__ cand_s, const int32_t* __restrict__ cand_m,
-                                                 const uint8_t* __restrict__ nv, const int32_t* __restrict__ scan,
-                                                 int64_t n_cand, int32_t* __restrict__ ps, int32_t* __restrict__ pm,
-                                                 uint8_t* __restrict__ pnv) {
-  const int64_t c = (int64_t)blockIdx.x * BS + threadIdx.x;
-  if (c >= n_cand) return;
-  const uint8_t n = nv[c];
-  if (n >= 3) {
-    const int p = scan[c];
-    ps[p] = cand_s[c];
-    pm[p] = cand_m[c];
-    pnv[p] = n;
+// Pair list and pair polygons from the screened candidates that are pairs.
+__global__ __launch_bounds__(BS) void k_compact_pairs(const int32_t* __restrict__ cand_s,
+                                                       const int32_t* __restrict__ cand_m,
+                                                       const int32_t* __restrict__ mlist,
+                                                       const int32_t* __restrict__ flag2,
+                                                       const int32_t* __restrict__ scan2, int64_t n_maybe,
+                                                       PolyBuf src, int32_t* __restrict__ ps,
+                                                       int32_t* __restrict__ pm, uint8_t* __restrict__ pnv,
+                                                       PolyBuf dst) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i >= n_maybe || !flag2[i]) return;
+  const int64_t p = scan2[i];
+  const int c = mlist[i];
+  ps[p] = cand_s[c];
+  pm[p] = cand_m[c];
+  const uint8_t nf = src.nf[i];
+  const int n = nf & 0x7f;
+  pnv[p] = (uint8_t)n;
+  dst.nf[p] = nf;
+  for (int k = 0; k < n; ++k) {
+    dst.u[(int64_t)k * dst.stride + p] = src.u[(int64_t)k * src.stride + i];
+    dst.v[(int64_t)k * dst.stride + p] = src.v[(int64_t)k * src.stride + i];
+    dst.lab[(int64_t)k * dst.stride + p] = src.lab[(int64_t)k * src.stride + i];
   }
 }
 
-__global__ __launch_bounds__(BS) void k_pair_off(const int32_t* __restrict__ cand_off, const int32_t* __restrict__ scan,
-                                                  int32_t n_s, int32_t* __restrict__ pair_off) {
+// First pair of each slave element: pairs before its first candidate.
+__global__ __launch_bounds__(BS) void k_pair_off(const int32_t* __restrict__ cand_off,
+                                                  const int32_t* __restrict__ mscan,
+                                                  const int32_t* __restrict__ scan2, int32_t n_s,
+                                                  int32_t* __restrict__ pair_off) {
   const int s = blockIdx.x * BS + threadIdx.x;
   if (s > n_s) return;
-  pair_off[s] = scan[cand_off[s]];
+  pair_off[s] = scan2[mscan[cand_off[s]]];
 }
 
 // Clip polygon of every pair (projection, clip and cleanup in LDS), stored
@@ -145,27 +177,35 @@ __global__ __launch_bounds__(BSC) __attribute__((amdgpu_waves_per_eu(3))) void k
 
 }  // namespace
 
-hipError_t launch_clip_count(const DeviceMesh& S, const DeviceMesh& M, const double* sdata, const KParams& kp,
-                             const int32_t* cand_s, const int32_t* cand_m, int64_t n_cand, uint8_t* nv,
-                             int32_t* flag, Counters* cnt, hipStream_t s) {
+hipError_t launch_maybe_list(const int32_t* flag, const int32_t* mscan, int64_t n_cand, int32_t* mlist,
+                             hipStream_t s) {
   if (n_cand == 0) return hipSuccess;
-  k_clip_count<<<xcd_grid((unsigned)((n_cand + BSC * CPT - 1) / (BSC * CPT))), BSC, 0, s>>>(sdata, S.n_el, M.x, M.y, M.z, M.conn,
-                                                                              kp, cand_s, cand_m, n_cand, nv, flag,
-                                                                              cnt);
+  k_maybe_list<<<(unsigned)((n_cand + BS - 1) / BS), BS, 0, s>>>(flag, mscan, n_cand, mlist);
   return hipGetLastError();
 }
 
-hipError_t launch_compact(const int32_t* cand_s, const int32_t* cand_m, const uint8_t* cand_nv, const int32_t* scan,
-                          int64_t n_cand, int32_t* pair_s, int32_t* pair_m, uint8_t* pair_nv, hipStream_t s) {
-  if (n_cand == 0) return hipSuccess;
-  k_compact<<<(unsigned)((n_cand + BS - 1) / BS), BS, 0, s>>>(cand_s, cand_m, cand_nv, scan, n_cand, pair_s, pair_m,
-                                                              pair_nv);
+hipError_t launch_clip_screened(const double* mdata, const double* sdata, int32_t n_s, const KParams& kp,
+                                const int32_t* cand_s, const int32_t* cand_m, const int32_t* mlist, int64_t n_maybe,
+                                uint8_t* nv, int32_t* flag2, const PolyBuf& out, Counters* cnt, hipStream_t s) {
+  if (n_maybe == 0) return hipSuccess;
+  k_clip_screened<<<xcd_grid((unsigned)((n_maybe + BSC - 1) / BSC)), BSC, 0, s>>>(
+      sdata, n_s, mdata, kp, cand_s, cand_m, mlist, n_maybe, nv, flag2, out, cnt);
   return hipGetLastError();
 }
 
-hipError_t launch_pair_off(const int32_t* cand_off, const int32_t* scan, int32_t n_s, int32_t* pair_off,
-                           hipStream_t s) {
-  k_pair_off<<<(n_s + 1 + BS - 1) / BS, BS, 0, s>>>(cand_off, scan, n_s, pair_off);
+hipError_t launch_compact_pairs(const int32_t* cand_s, const int32_t* cand_m, const int32_t* mlist,
+                                const int32_t* flag2, const int32_t* scan2, int64_t n_maybe, const PolyBuf& src,
+                                int32_t* pair_s, int32_t* pair_m, uint8_t* pair_nv, const PolyBuf& dst,
+                                hipStream_t s) {
+  if (n_maybe == 0) return hipSuccess;
+  k_compact_pairs<<<(unsigned)((n_maybe + BS - 1) / BS), BS, 0, s>>>(cand_s, cand_m, mlist, flag2, scan2, n_maybe,
+                                                                     src, pair_s, pair_m, pair_nv, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_off(const int32_t* cand_off, const int32_t* mscan, const int32_t* scan2, int32_t n_s,
+                           int32_t* pair_off, hipStream_t s) {
+  k_pair_off<<<(n_s + 1 + BS - 1) / BS, BS, 0, s>>>(cand_off, mscan, scan2, n_s, pair_off);
   return hipGetLastError();
 }
 

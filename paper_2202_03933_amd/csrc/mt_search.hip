@@ -48,13 +48,16 @@ __device__ __forceinline__ T wave_min(T x) {
 }
 
 // Element preparation: bounding boxes, the grid reductions (largest box
-// extent, longest slave edge, bounding box of all element boxes) and, for
-// slave elements, the precomputed frame and projected polygon of the
-// candidate pass.  Grid-stride loop; one atomic per block and quantity.
+// extent, longest slave edge, bounding box of all element boxes), for slave
+// elements the precomputed frame and projected polygon of the candidate
+// pass, for master elements their node coordinates gathered element by
+// element (md[12 e + 3 k + d], read with 16-byte loads by the candidate
+// pass).  Grid-stride loop; one atomic per block and quantity.
 __global__ __launch_bounds__(BS) void k_prep(const double* __restrict__ x, const double* __restrict__ y,
                                               const double* __restrict__ z, const int32_t* __restrict__ conn,
                                               int32_t n_el, int32_t n_nodes, int slave,
-                                              double* __restrict__ box, double* __restrict__ sd, PrepReduce* red) {
+                                              double* __restrict__ box, double* __restrict__ sd,
+                                              double* __restrict__ md, PrepReduce* red) {
   __shared__ double sh[BS / 64][8];
   __shared__ int bad;
   if (threadIdx.x == 0) bad = 0;
@@ -101,6 +104,10 @@ __global__ __launch_bounds__(BS) void k_prep(const double* __restrict__ x, const
       }
       sd[(int64_t)20 * n_el + e] = As;
       sd[(int64_t)21 * n_el + e] = hmax;
+    } else {
+      double2* dst = reinterpret_cast<double2*>(md + (int64_t)12 * e);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) dst[k] = make_double2(X[(2 * k) / 3][(2 * k) % 3], X[(2 * k + 1) / 3][(2 * k + 1) % 3]);
     }
   }
   double v[8] = {ext, edge, -lo[0], -lo[1], -lo[2], hi[0], hi[1], hi[2]};
@@ -154,13 +161,23 @@ __global__ __launch_bounds__(BS) void k_master_keys(const double* __restrict__ b
   vals[m] = (uint32_t)m;
 }
 
-__global__ __launch_bounds__(BS) void k_cell_ranges(const uint32_t* __restrict__ keys, int32_t n,
-                                                     int32_t* __restrict__ start, int32_t* __restrict__ end) {
+// Cell ranges [x, y) of the cell-sorted master list from segment heads, and
+// the master boxes copied into cell order (sbox[i] = lo xyz, hi xyz of the
+// i-th sorted master) so that the candidate walks read them contiguously.
+__global__ __launch_bounds__(BS) void k_cell_ranges(const uint32_t* __restrict__ keys,
+                                                     const uint32_t* __restrict__ vals, int32_t n,
+                                                     const double* __restrict__ box_m, int2* __restrict__ range,
+                                                     double* __restrict__ sbox) {
   const int i = blockIdx.x * BS + threadIdx.x;
   if (i >= n) return;
   const uint32_t k = keys[i];
-  if (i == 0 || keys[i - 1] != k) start[k] = i;
-  if (i == n - 1 || keys[i + 1] != k) end[k] = i + 1;
+  if (i == 0 || keys[i - 1] != k) range[k].x = i;
+  if (i == n - 1 || keys[i + 1] != k) range[k].y = i + 1;
+  const int m = (int)vals[i];
+  double2* dst = reinterpret_cast<double2*>(sbox + (int64_t)6 * i);
+  dst[0] = make_double2(box_m[m], box_m[(int64_t)n + m]);
+  dst[1] = make_double2(box_m[(int64_t)2 * n + m], box_m[(int64_t)3 * n + m]);
+  dst[2] = make_double2(box_m[(int64_t)4 * n + m], box_m[(int64_t)5 * n + m]);
 }
 
 struct SlaveBox {
@@ -178,16 +195,15 @@ __device__ __forceinline__ SlaveBox load_box(const double* __restrict__ box, int
 }
 
 // Candidate test: closed overlap of the delta-enlarged slave box and the
-// master box on all three axes.
-__device__ __forceinline__ bool touch(const SlaveBox& s, const double* __restrict__ box_m, int32_t n_m, int m,
-                                      double delta) {
+// i-th master box in cell order on all three axes.
+__device__ __forceinline__ bool touch(const SlaveBox& s, const double* __restrict__ sbox, int i, double delta) {
+  const double2* b = reinterpret_cast<const double2*>(sbox + (int64_t)6 * i);
+  const double2 b0 = b[0], b1 = b[1], b2 = b[2];
+  const double mlo[3] = {b0.x, b0.y, b1.x}, mhi[3] = {b1.y, b2.x, b2.y};
+  bool t = true;
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const double mlo = box_m[(int64_t)d * n_m + m];
-    const double mhi = box_m[(int64_t)(3 + d) * n_m + m];
-    if (!((s.lo[d] - delta) <= mhi && mlo <= (s.hi[d] + delta))) return false;
-  }
-  return true;
+  for (int d = 0; d < 3; ++d) t = t && (s.lo[d] - delta) <= mhi[d] && mlo[d] <= (s.hi[d] + delta);
+  return t;
 }
 
 constexpr int CCAP = 48;  // per-thread LDS segment of the candidate fill (masters)
@@ -201,10 +217,9 @@ constexpr int CTMP = 32;  // candidates per slave kept by the count pass
 // lane-interleaved LDS segment (in place when longer than CCAP) and writes
 // them out.
 template <bool FILL>
-__device__ __forceinline__ int walk_cells(const SlaveBox& b, const double* __restrict__ box_m, int32_t n_m,
-                                          const uint32_t* __restrict__ mvals, const int32_t* __restrict__ start,
-                                          const int32_t* __restrict__ end, const Grid& g, double delta, int32_t* v,
-                                          int64_t vs, int vcap) {
+__device__ __forceinline__ int walk_cells(const SlaveBox& b, const double* __restrict__ sbox,
+                                          const uint32_t* __restrict__ mvals, const int2* __restrict__ range,
+                                          const Grid& g, double delta, int32_t* v, int64_t vs, int vcap) {
   int ix[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) ix[d] = cell_coord(0.5 * (b.lo[d] + b.hi[d]), g.lo[d], g.inv_beta[d], g.n[d]);
@@ -219,11 +234,10 @@ __device__ __forceinline__ int walk_cells(const SlaveBox& b, const double* __res
         const int xx = ix[0] + dx;
         if (xx < 0 || xx >= g.n[0]) continue;
         const int64_t cell = xx + (int64_t)g.n[0] * (yy + (int64_t)g.n[1] * zz);
-        const int i1 = end[cell];
-        for (int i = start[cell]; i < i1; ++i) {
-          const int m = (int)mvals[i];
-          if (touch(b, box_m, n_m, m, delta)) {
-            if (c < vcap) v[c * vs] = m;
+        const int2 r = range[cell];
+        for (int i = r.x; i < r.y; ++i) {
+          if (touch(b, sbox, i, delta)) {
+            if (c < vcap) v[c * vs] = (int)mvals[i];
             ++c;
           }
         }
@@ -234,49 +248,106 @@ __device__ __forceinline__ int walk_cells(const SlaveBox& b, const double* __res
 }
 
 __global__ __launch_bounds__(BS) void k_cand_count(const double* __restrict__ box_s, int32_t n_s,
-                                                    const double* __restrict__ box_m, int32_t n_m,
+                                                    const double* __restrict__ sbox,
                                                     const uint32_t* __restrict__ mvals,
-                                                    const int32_t* __restrict__ start, const int32_t* __restrict__ end,
-                                                    Grid g, double delta, int32_t* __restrict__ count,
-                                                    int32_t* __restrict__ tmp) {
+                                                    const int2* __restrict__ range, Grid g, double delta,
+                                                    int32_t* __restrict__ count, int32_t* __restrict__ tmp) {
   const int s = blockIdx.x * BS + threadIdx.x;
   if (s >= n_s) return;
   const SlaveBox b = load_box(box_s, n_s, s);
-  count[s] = walk_cells<false>(b, box_m, n_m, mvals, start, end, g, delta, tmp + s, n_s, CTMP);
+  count[s] = walk_cells<false>(b, sbox, mvals, range, g, delta, tmp + s, n_s, CTMP);
 }
 
+__device__ __forceinline__ void load_master_data(const double* __restrict__ md, int m, double X[4][3]) {
+  const double2* src = reinterpret_cast<const double2*>(md + (int64_t)12 * m);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const double2 t = src[k];
+    X[(2 * k) / 3][(2 * k) % 3] = t.x;
+    X[(2 * k + 1) / 3][(2 * k + 1) % 3] = t.y;
+  }
+}
+
+// Fill pass, fused with the screening of each candidate: the slave plane
+// data are loaded once per slave element (one lane per slave), each master
+// element's nodes with six 16-byte loads; the projection onto the slave
+// plane, degeneracy checks and the separating-line quick exit decide
+// flag[c] (1: to be clipped; otherwise the vertex count is 0).
 __global__ __launch_bounds__(BS) void k_cand_fill(const double* __restrict__ box_s, int32_t n_s,
-                                                   const double* __restrict__ box_m, int32_t n_m,
+                                                   const double* __restrict__ sbox,
                                                    const uint32_t* __restrict__ mvals,
-                                                   const int32_t* __restrict__ start, const int32_t* __restrict__ end,
-                                                   Grid g, double delta, const int32_t* __restrict__ tmp,
+                                                   const int2* __restrict__ range, Grid g, double delta, const int32_t* __restrict__ tmp,
                                                    const int32_t* __restrict__ off, int32_t* __restrict__ cand_s,
-                                                   int32_t* __restrict__ cand_m) {
+                                                   int32_t* __restrict__ cand_m, const double* __restrict__ sd,
+                                                   const double* __restrict__ md, double eps_a,
+                                                   uint8_t* __restrict__ nv_out, int32_t* __restrict__ flag,
+                                                   Counters* cnt) {
   __shared__ int32_t lds[CCAP * BS];
+  __shared__ unsigned int hist[3];
+  if (threadIdx.x < 3) hist[threadIdx.x] = 0;
+  __syncthreads();
   const int s = blockIdx.x * BS + threadIdx.x;
-  if (s >= n_s) return;
-  const int base = off[s];
-  const int c = off[s + 1] - base;
-  const bool in_lds = c <= CCAP;
-  int32_t* v = in_lds ? lds + threadIdx.x : cand_m + base;
-  const int vs = in_lds ? BS : 1;
-  if (c <= CTMP) {
-    for (int i = 0; i < c; ++i) v[i * vs] = tmp[(int64_t)i * n_s + s];
-  } else {
-    walk_cells<true>(load_box(box_s, n_s, s), box_m, n_m, mvals, start, end, g, delta, v, vs, c);
-  }
-  for (int i = 1; i < c; ++i) {
-    const int x = v[i * vs];
-    int j = i - 1;
-    while (j >= 0 && v[j * vs] > x) {
-      v[(j + 1) * vs] = v[j * vs];
-      --j;
+  if (s < n_s) {
+    const int base = off[s];
+    const int c = off[s + 1] - base;
+    const bool in_lds = c <= CCAP;
+    int32_t* v = in_lds ? lds + threadIdx.x : cand_m + base;
+    const int vs = in_lds ? BS : 1;
+    if (c <= CTMP) {
+      for (int i = 0; i < c; ++i) v[i * vs] = tmp[(int64_t)i * n_s + s];
+    } else {
+      walk_cells<true>(load_box(box_s, n_s, s), sbox, mvals, range, g, delta, v, vs, c);
     }
-    v[(j + 1) * vs] = x;
+    for (int i = 1; i < c; ++i) {
+      const int x = v[i * vs];
+      int j = i - 1;
+      while (j >= 0 && v[j * vs] > x) {
+        v[(j + 1) * vs] = v[j * vs];
+        --j;
+      }
+      v[(j + 1) * vs] = x;
+    }
+    double f[12], As;
+    V2 S[4];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) f[k] = sd[(int64_t)k * n_s + s];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      S[k].u = sd[(int64_t)(12 + k) * n_s + s];
+      S[k].v = sd[(int64_t)(16 + k) * n_s + s];
+    }
+    As = sd[(int64_t)20 * n_s + s];
+    unsigned rejected = 0, degen_s = 0, degen_m = 0;
+    for (int i = 0; i < c; ++i) {
+      const int m = v[i * vs];
+      double Xm[4][3];
+      load_master_data(md, m, Xm);
+      V2 Mn[4];
+      double hm[4];
+      int st;
+      bool flip;
+      const bool clip = pair_screen(S, As, Xm, f, eps_a, Mn, hm, flip, st);
+      const int64_t ci = (int64_t)base + i;
+      flag[ci] = clip ? 1 : 0;
+      if (!clip) {
+        nv_out[ci] = 0;
+        ++rejected;
+      }
+      degen_s += (st & PS_DEGEN_SLAVE) ? 1u : 0u;
+      degen_m += (st & PS_DEGEN_MASTER) ? 1u : 0u;
+      if (in_lds) cand_m[ci] = m;
+      cand_s[ci] = s;
+    }
+    if (rejected) atomicAdd(&hist[0], rejected);
+    if (degen_s) atomicAdd(&hist[1], degen_s);
+    if (degen_m) atomicAdd(&hist[2], degen_m);
   }
-  for (int i = 0; i < c; ++i) {
-    if (in_lds) cand_m[base + i] = v[i * vs];
-    cand_s[base + i] = s;
+  __syncthreads();
+  if (threadIdx.x < 3 && hist[threadIdx.x]) {
+    const unsigned long long val = hist[threadIdx.x];
+    if (threadIdx.x == 0) atomicAdd(&cnt->hist[0], val);
+    else if (threadIdx.x == 1) atomicAdd(&cnt->degen_slave, val);
+    else atomicAdd(&cnt->degen_master, val);
   }
 }
 
@@ -287,10 +358,11 @@ hipError_t launch_init_reduce(PrepReduce* red, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_prep(const DeviceMesh& m, bool slave, double* box, double* sd, PrepReduce* red, hipStream_t s) {
+hipError_t launch_prep(const DeviceMesh& m, bool slave, double* box, double* sd, double* md, PrepReduce* red,
+                       hipStream_t s) {
   if (m.n_el == 0) return hipSuccess;
   const int grid = std::min(2048, (m.n_el + BS - 1) / BS);
-  k_prep<<<grid, BS, 0, s>>>(m.x, m.y, m.z, m.conn, m.n_el, m.n_nodes, slave ? 1 : 0, box, sd, red);
+  k_prep<<<grid, BS, 0, s>>>(m.x, m.y, m.z, m.conn, m.n_el, m.n_nodes, slave ? 1 : 0, box, sd, md, red);
   return hipGetLastError();
 }
 
@@ -331,27 +403,27 @@ hipError_t launch_master_keys(const double* box_m, int32_t n_m, Grid g, uint32_t
   return hipGetLastError();
 }
 
-hipError_t launch_cell_ranges(const uint32_t* keys, int32_t n, int32_t* start, int32_t* end, hipStream_t s) {
+hipError_t launch_cell_ranges(const uint32_t* keys, const uint32_t* vals, int32_t n, const double* box_m,
+                              int2* range, double* sbox, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  k_cell_ranges<<<(n + BS - 1) / BS, BS, 0, s>>>(keys, n, start, end);
+  k_cell_ranges<<<(n + BS - 1) / BS, BS, 0, s>>>(keys, vals, n, box_m, range, sbox);
   return hipGetLastError();
 }
 
-hipError_t launch_cand_count(const double* box_s, int32_t n_s, const double* box_m, int32_t n_m,
-                             const uint32_t* mvals, const int32_t* start, const int32_t* end, Grid g,
-                             double delta, int32_t* count, int32_t* tmp, hipStream_t s) {
+hipError_t launch_cand_count(const double* box_s, int32_t n_s, const double* sbox, const uint32_t* mvals,
+                             const int2* range, Grid g, double delta, int32_t* count, int32_t* tmp, hipStream_t s) {
   if (n_s == 0) return hipSuccess;
-  k_cand_count<<<(n_s + BS - 1) / BS, BS, 0, s>>>(box_s, n_s, box_m, n_m, mvals, start, end, g, delta, count, tmp);
+  k_cand_count<<<(n_s + BS - 1) / BS, BS, 0, s>>>(box_s, n_s, sbox, mvals, range, g, delta, count, tmp);
   return hipGetLastError();
 }
 
-hipError_t launch_cand_fill(const double* box_s, int32_t n_s, const double* box_m, int32_t n_m,
-                            const uint32_t* mvals, const int32_t* start, const int32_t* end, Grid g,
-                            double delta, const int32_t* tmp, const int32_t* off, int32_t* cand_s, int32_t* cand_m,
-                            hipStream_t s) {
+hipError_t launch_cand_fill(const double* box_s, int32_t n_s, const double* sbox, const uint32_t* mvals,
+                            const int2* range, Grid g, double delta, const int32_t* tmp, const int32_t* off,
+                            int32_t* cand_s, int32_t* cand_m, const double* sd, const double* md, double eps_a,
+                            uint8_t* nv, int32_t* flag, Counters* cnt, hipStream_t s) {
   if (n_s == 0) return hipSuccess;
-  k_cand_fill<<<(n_s + BS - 1) / BS, BS, 0, s>>>(box_s, n_s, box_m, n_m, mvals, start, end, g, delta, tmp, off,
-                                                 cand_s, cand_m);
+  k_cand_fill<<<(n_s + BS - 1) / BS, BS, 0, s>>>(box_s, n_s, sbox, mvals, range, g, delta, tmp, off, cand_s, cand_m,
+                                                 sd, md, eps_a, nv, flag, cnt);
   return hipGetLastError();
 }
 
