@@ -75,55 +75,78 @@ __global__ __launch_bounds__(BS) void k_raw_count(const int32_t* __restrict__ in
   rawM_big[a] = m > PCAP ? m : 0;
 }
 
-// Sort a strided segment ascending and drop duplicates; returns the count.
-__device__ int sort_unique(int32_t* v, int n, int stride) {
-  for (int i = 1; i < n; ++i) {
-    const int x = v[i * stride];
-    int j = i - 1;
-    while (j >= 0 && v[j * stride] > x) {
-      v[(j + 1) * stride] = v[j * stride];
-      --j;
-    }
-    v[(j + 1) * stride] = x;
-  }
-  int u = 0;
-  for (int i = 0; i < n; ++i)
-    if (u == 0 || v[(u - 1) * stride] != v[i * stride]) v[(u++) * stride] = v[i * stride];
-  return u;
+// Inserts x into the ascending, duplicate-free strided list v[0..u) unless
+// it is already there; returns the new length.
+__device__ __forceinline__ int insert_unique(int32_t* v, int u, int x, int stride) {
+  int j = u - 1;
+  while (j >= 0 && v[j * stride] > x) --j;
+  if (j >= 0 && v[j * stride] == x) return u;
+  for (int k = u - 1; k > j; --k) v[(k + 1) * stride] = v[k * stride];
+  v[(j + 1) * stride] = x;
+  return u + 1;
 }
 
-// Column candidates of row a: for D the nodes of every incident slave element
-// that has pairs, for M the master nodes of every pair of those elements.
+// Sorted, duplicate-free columns of row a: for D the nodes of every incident
+// slave element that has pairs, for M the master nodes of every pair of
+// those elements.
 template <bool MCOLS>
-__device__ int gather_row(int a, const int32_t* __restrict__ inc_off, const int32_t* __restrict__ inc_list,
-                          const int32_t* __restrict__ pair_off, const int32_t* __restrict__ pair_m,
-                          const int32_t* __restrict__ conn_s, const int32_t* __restrict__ conn_m, int32_t* v,
-                          int stride) {
-  int c = 0;
+__device__ __forceinline__ int row_columns(int a, const int32_t* __restrict__ inc_off,
+                                           const int32_t* __restrict__ inc_list,
+                                           const int32_t* __restrict__ pair_off,
+                                           const int32_t* __restrict__ pair_m, const int32_t* __restrict__ conn_s,
+                                           const int32_t* __restrict__ conn_m, int32_t* v, int stride) {
+  int u = 0;
   for (int i = inc_off[a]; i < inc_off[a + 1]; ++i) {
     const int e = inc_list[i] >> 2;
     const int p0 = pair_off[e], p1 = pair_off[e + 1];
     if (p1 == p0) continue;
     if (!MCOLS) {
       const int4 q = reinterpret_cast<const int4*>(conn_s)[e];
-      v[(c++) * stride] = q.x; v[(c++) * stride] = q.y; v[(c++) * stride] = q.z; v[(c++) * stride] = q.w;
+      u = insert_unique(v, u, q.x, stride);
+      u = insert_unique(v, u, q.y, stride);
+      u = insert_unique(v, u, q.z, stride);
+      u = insert_unique(v, u, q.w, stride);
     } else {
       for (int p = p0; p < p1; ++p) {
         const int4 q = reinterpret_cast<const int4*>(conn_m)[pair_m[p]];
-        v[(c++) * stride] = q.x; v[(c++) * stride] = q.y; v[(c++) * stride] = q.z; v[(c++) * stride] = q.w;
+        u = insert_unique(v, u, q.x, stride);
+        u = insert_unique(v, u, q.y, stride);
+        u = insert_unique(v, u, q.z, stride);
+        u = insert_unique(v, u, q.w, stride);
       }
     }
   }
-  return c;
+  return u;
 }
 
-// Row patterns of D and M.  Each thread gathers its row's candidates into a
-// lane-interleaved LDS segment (or a global scratch segment when longer than
-// PCAP), sorts and deduplicates them.  The count pass writes the row lengths
+// Row patterns of D and M.  Each thread builds its row's sorted column list
+// in a lane-interleaved LDS segment (or a global scratch segment when the
+// raw candidate count exceeds PCAP).  The count pass writes the row lengths
 // and keeps rows of at most KD (D) / KM (M) columns in lane-interleaved
 // scratch keep[i * n + a]; the fill pass copies those and recomputes the rest.
 constexpr int KD = 16;
 constexpr int KM = 32;
+
+template <bool FILL, bool MCOLS>
+__device__ __forceinline__ void pattern_row(int a, int32_t n, int32_t* v, int stride,
+                                            const int32_t* __restrict__ inc_off,
+                                            const int32_t* __restrict__ inc_list,
+                                            const int32_t* __restrict__ pair_off,
+                                            const int32_t* __restrict__ pair_m,
+                                            const int32_t* __restrict__ conn_s,
+                                            const int32_t* __restrict__ conn_m, int32_t* cnt,
+                                            const int32_t* __restrict__ rowptr, int32_t* colv, int32_t* keep,
+                                            int kcap) {
+  const int u = row_columns<MCOLS>(a, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m, v, stride);
+  if (!FILL) {
+    cnt[a] = u;
+    if (u <= kcap)
+      for (int i = 0; i < u; ++i) keep[(int64_t)i * n] = v[i * stride];
+  } else {
+    int32_t* col = colv + rowptr[a];
+    for (int i = 0; i < u; ++i) col[i] = v[i * stride];
+  }
+}
 
 template <bool FILL>
 __global__ __launch_bounds__(PB) void k_pattern_rows(const int32_t* __restrict__ inc_off,
@@ -141,32 +164,42 @@ __global__ __launch_bounds__(PB) void k_pattern_rows(const int32_t* __restrict__
   __shared__ int32_t lds[PCAP * PB];
   const int a = blockIdx.x * PB + threadIdx.x;
   if (a >= n) return;
-  for (int mode = 0; mode < 2; ++mode) {
-    const int kcap = mode ? KM : KD;
-    int32_t* keep = (mode ? keepM : keepD) + a;
+  // D row
+  {
+    bool done = false;
     if (FILL) {
-      const int32_t* rp = mode ? M_rowptr : D_rowptr;
-      const int u = rp[a + 1] - rp[a];
-      if (u <= kcap) {
-        int32_t* col = (mode ? M_col : D_col) + rp[a];
-        for (int i = 0; i < u; ++i) col[i] = keep[(int64_t)i * n];
-        continue;
+      const int u = D_rowptr[a + 1] - D_rowptr[a];
+      if (u <= KD) {
+        for (int i = 0; i < u; ++i) D_col[D_rowptr[a] + i] = keepD[(int64_t)i * n + a];
+        done = true;
       }
     }
-    const int32_t* boff = mode ? bigM_off : bigD_off;
-    const bool big = boff[a + 1] > boff[a];
-    int32_t* v = big ? (mode ? bigM : bigD) + boff[a] : lds + threadIdx.x;
-    const int stride = big ? 1 : PB;
-    const int c = mode ? gather_row<true>(a, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m, v, stride)
-                       : gather_row<false>(a, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m, v, stride);
-    const int u = sort_unique(v, c, stride);
-    if (!FILL) {
-      (mode ? M_cnt : D_cnt)[a] = u;
-      if (u <= kcap)
-        for (int i = 0; i < u; ++i) keep[(int64_t)i * n] = v[i * stride];
-    } else {
-      int32_t* col = (mode ? M_col : D_col) + (mode ? M_rowptr : D_rowptr)[a];
-      for (int i = 0; i < u; ++i) col[i] = v[i * stride];
+    if (!done) {
+      if (bigD_off[a + 1] == bigD_off[a])
+        pattern_row<FILL, false>(a, n, lds + threadIdx.x, PB, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m,
+                                 D_cnt, D_rowptr, D_col, keepD + a, KD);
+      else
+        pattern_row<FILL, false>(a, n, bigD + bigD_off[a], 1, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m,
+                                 D_cnt, D_rowptr, D_col, keepD + a, KD);
+    }
+  }
+  // M row
+  {
+    bool done = false;
+    if (FILL) {
+      const int u = M_rowptr[a + 1] - M_rowptr[a];
+      if (u <= KM) {
+        for (int i = 0; i < u; ++i) M_col[M_rowptr[a] + i] = keepM[(int64_t)i * n + a];
+        done = true;
+      }
+    }
+    if (!done) {
+      if (bigM_off[a + 1] == bigM_off[a])
+        pattern_row<FILL, true>(a, n, lds + threadIdx.x, PB, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m,
+                                M_cnt, M_rowptr, M_col, keepM + a, KM);
+      else
+        pattern_row<FILL, true>(a, n, bigM + bigM_off[a], 1, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m,
+                                M_cnt, M_rowptr, M_col, keepM + a, KM);
     }
   }
 }

@@ -272,11 +272,74 @@ __device__ __forceinline__ void load_master_data(const double* __restrict__ md, 
 // data are loaded once per slave element (one lane per slave), each master
 // element's nodes with six 16-byte loads; the projection onto the slave
 // plane, degeneracy checks and the separating-line quick exit decide
-// flag[c] (1: to be clipped; otherwise the vertex count is 0).
+// flag[c] (1: to be clipped; otherwise the vertex count is 0).  The
+// candidates are sorted in a lane-interleaved LDS segment, or in place in
+// the output when longer than CCAP (two call sites, so that each pointer
+// has a known address space).
+struct ScreenOut {
+  unsigned rejected, degen_s, degen_m;
+};
+
+__device__ __forceinline__ void fill_and_screen(int s, int32_t n_s, int base, int c, int32_t* v, int vs,
+                                                bool copy_out, const double* __restrict__ box_s,
+                                                const double* __restrict__ sbox, const uint32_t* __restrict__ mvals,
+                                                const int2* __restrict__ range, const Grid& g, double delta,
+                                                const int32_t* __restrict__ tmp, int32_t* __restrict__ cand_s,
+                                                int32_t* __restrict__ cand_m, const double* __restrict__ sd,
+                                                const double* __restrict__ md, double eps_a,
+                                                uint8_t* __restrict__ nv_out, int32_t* __restrict__ flag,
+                                                ScreenOut& so) {
+  if (c <= CTMP) {
+    for (int i = 0; i < c; ++i) v[i * vs] = tmp[(int64_t)i * n_s + s];
+  } else {
+    walk_cells<true>(load_box(box_s, n_s, s), sbox, mvals, range, g, delta, v, vs, c);
+  }
+  for (int i = 1; i < c; ++i) {
+    const int x = v[i * vs];
+    int j = i - 1;
+    while (j >= 0 && v[j * vs] > x) {
+      v[(j + 1) * vs] = v[j * vs];
+      --j;
+    }
+    v[(j + 1) * vs] = x;
+  }
+  double f[12], As;
+  V2 S[4];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) f[k] = sd[(int64_t)k * n_s + s];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    S[k].u = sd[(int64_t)(12 + k) * n_s + s];
+    S[k].v = sd[(int64_t)(16 + k) * n_s + s];
+  }
+  As = sd[(int64_t)20 * n_s + s];
+  for (int i = 0; i < c; ++i) {
+    const int m = v[i * vs];
+    double Xm[4][3];
+    load_master_data(md, m, Xm);
+    V2 Mn[4];
+    double hm[4];
+    int st;
+    bool flip;
+    const bool clip = pair_screen(S, As, Xm, f, eps_a, Mn, hm, flip, st);
+    const int64_t ci = (int64_t)base + i;
+    flag[ci] = clip ? 1 : 0;
+    if (!clip) {
+      nv_out[ci] = 0;
+      ++so.rejected;
+    }
+    so.degen_s += (st & PS_DEGEN_SLAVE) ? 1u : 0u;
+    so.degen_m += (st & PS_DEGEN_MASTER) ? 1u : 0u;
+    if (copy_out) cand_m[ci] = m;
+    cand_s[ci] = s;
+  }
+}
+
 __global__ __launch_bounds__(BS) void k_cand_fill(const double* __restrict__ box_s, int32_t n_s,
                                                    const double* __restrict__ sbox,
                                                    const uint32_t* __restrict__ mvals,
-                                                   const int2* __restrict__ range, Grid g, double delta, const int32_t* __restrict__ tmp,
+                                                   const int2* __restrict__ range, Grid g,
+                                                   double delta, const int32_t* __restrict__ tmp,
                                                    const int32_t* __restrict__ off, int32_t* __restrict__ cand_s,
                                                    int32_t* __restrict__ cand_m, const double* __restrict__ sd,
                                                    const double* __restrict__ md, double eps_a,
@@ -290,57 +353,16 @@ __global__ __launch_bounds__(BS) void k_cand_fill(const double* __restrict__ box
   if (s < n_s) {
     const int base = off[s];
     const int c = off[s + 1] - base;
-    const bool in_lds = c <= CCAP;
-    int32_t* v = in_lds ? lds + threadIdx.x : cand_m + base;
-    const int vs = in_lds ? BS : 1;
-    if (c <= CTMP) {
-      for (int i = 0; i < c; ++i) v[i * vs] = tmp[(int64_t)i * n_s + s];
-    } else {
-      walk_cells<true>(load_box(box_s, n_s, s), sbox, mvals, range, g, delta, v, vs, c);
-    }
-    for (int i = 1; i < c; ++i) {
-      const int x = v[i * vs];
-      int j = i - 1;
-      while (j >= 0 && v[j * vs] > x) {
-        v[(j + 1) * vs] = v[j * vs];
-        --j;
-      }
-      v[(j + 1) * vs] = x;
-    }
-    double f[12], As;
-    V2 S[4];
-#pragma unroll
-    for (int k = 0; k < 12; ++k) f[k] = sd[(int64_t)k * n_s + s];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      S[k].u = sd[(int64_t)(12 + k) * n_s + s];
-      S[k].v = sd[(int64_t)(16 + k) * n_s + s];
-    }
-    As = sd[(int64_t)20 * n_s + s];
-    unsigned rejected = 0, degen_s = 0, degen_m = 0;
-    for (int i = 0; i < c; ++i) {
-      const int m = v[i * vs];
-      double Xm[4][3];
-      load_master_data(md, m, Xm);
-      V2 Mn[4];
-      double hm[4];
-      int st;
-      bool flip;
-      const bool clip = pair_screen(S, As, Xm, f, eps_a, Mn, hm, flip, st);
-      const int64_t ci = (int64_t)base + i;
-      flag[ci] = clip ? 1 : 0;
-      if (!clip) {
-        nv_out[ci] = 0;
-        ++rejected;
-      }
-      degen_s += (st & PS_DEGEN_SLAVE) ? 1u : 0u;
-      degen_m += (st & PS_DEGEN_MASTER) ? 1u : 0u;
-      if (in_lds) cand_m[ci] = m;
-      cand_s[ci] = s;
-    }
-    if (rejected) atomicAdd(&hist[0], rejected);
-    if (degen_s) atomicAdd(&hist[1], degen_s);
-    if (degen_m) atomicAdd(&hist[2], degen_m);
+    ScreenOut so{0u, 0u, 0u};
+    if (c <= CCAP)
+      fill_and_screen(s, n_s, base, c, lds + threadIdx.x, BS, true, box_s, sbox, mvals, range, g, delta, tmp, cand_s,
+                      cand_m, sd, md, eps_a, nv_out, flag, so);
+    else
+      fill_and_screen(s, n_s, base, c, cand_m + base, 1, false, box_s, sbox, mvals, range, g, delta, tmp, cand_s,
+                      cand_m, sd, md, eps_a, nv_out, flag, so);
+    if (so.rejected) atomicAdd(&hist[0], so.rejected);
+    if (so.degen_s) atomicAdd(&hist[1], so.degen_s);
+    if (so.degen_m) atomicAdd(&hist[2], so.degen_m);
   }
   __syncthreads();
   if (threadIdx.x < 3 && hist[threadIdx.x]) {
