@@ -246,12 +246,15 @@ int mt_build_pairs(mt_ctx* c, int64_t* n_cand_out, int64_t* n_pairs_out, void* s
   MT_HIP(ensure(c->sdata, sizeof(double) * SD_N * (size_t)ns));
   MT_HIP(ensure(c->mdata, sizeof(double) * 12 * (size_t)std::max(nm, 1)));
   PrepReduce* red = c->reduce.as<PrepReduce>();
+  const int nb_s = prep_blocks(ns), nb_m = prep_blocks(nm);
+  MT_HIP(ensure(c->prep_part, sizeof(double) * 9 * (size_t)std::max(nb_s + nb_m, 1)));
   {
     PhaseTimer t(c, MT_T_PREP, st);
-    MT_HIP(launch_init_reduce(red, st));
     MT_HIP(hipMemsetAsync(c->counters.p, 0, sizeof(Counters), st));
-    MT_HIP(launch_prep(S, true, c->box_s.as<double>(), c->sdata.as<double>(), nullptr, red, st));
-    MT_HIP(launch_prep(M, false, c->box_m.as<double>(), nullptr, c->mdata.as<double>(), red, st));
+    double* part = c->prep_part.as<double>();
+    MT_HIP(launch_prep(S, true, c->box_s.as<double>(), c->sdata.as<double>(), nullptr, part, st));
+    MT_HIP(launch_prep(M, false, c->box_m.as<double>(), nullptr, c->mdata.as<double>(), part + 9 * (size_t)nb_s, st));
+    MT_HIP(launch_prep_reduce(part, nb_s, nb_m, red, st));
   }
   PrepReduce hr;
   MT_HIP(hipMemcpyAsync(&hr, red, sizeof(hr), hipMemcpyDeviceToHost, st));
@@ -672,6 +675,10 @@ int mt_get_stats(mt_ctx* c, mt_stats* out) {
   }
   if (!c->counters.p) return MT_OK;
   DeviceScope ds(c->device);
+  Counters* dc = c->counters.as<Counters>();
+  MT_HIP(hipMemsetAsync(dc->hist, 0, sizeof(dc->hist), c->last_stream));
+  if (c->have_pairs)
+    MT_HIP(launch_nv_hist(c->cand_nv.as<uint8_t>(), c->n_cand, dc->hist, c->last_stream));
   Counters hc;
   MT_HIP(hipMemcpyAsync(&hc, c->counters.p, sizeof(hc), hipMemcpyDeviceToHost, c->last_stream));
   MT_HIP(hipStreamSynchronize(c->last_stream));

@@ -133,68 +133,110 @@ struct LdsPoly {
 // emitting P when inside and then the crossing when the sides differ.
 // Returns the vertex count; the polygon is in buffer `res`.  Sets *ovf on
 // capacity overflow (then returns 0).
+//
+// The first stage reads the slave polygon from registers and writes buffer
+// 1; the later stages alternate between the LDS buffers, reading each next
+// vertex one edge ahead so that the loads are issued before the stores of
+// the current edge.
+
+// Side value of point (u, v) for the line a -> b (>= 0: inside).
+__device__ __forceinline__ double side_of(V2 a, double dbu, double dbv, double u, double v) {
+  return dbu * (v - a.v) - dbv * (u - a.u);
+}
+
+template <bool LAB>
+__device__ __forceinline__ void emit_vertex(const LdsPoly<LAB>& P, int b, int k, double u, double v, uint8_t vl,
+                                            uint8_t el) {
+  P.u[P.at(b, k)] = u;
+  P.v[P.at(b, k)] = v;
+  if (LAB) {
+    P.vl[P.at(b, k)] = vl;
+    P.el[P.at(b, k)] = el;
+  }
+}
+
 template <bool LAB>
 __device__ __forceinline__ int clip_polygon(const V2 S[4], const V2 Mo[4], const LdsPoly<LAB>& P, int& res,
                                             bool& ovf) {
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    P.u[P.at(0, k)] = S[k].u;
-    P.v[P.at(0, k)] = S[k].v;
-    if (LAB) {
-      P.vl[P.at(0, k)] = (uint8_t)(0x80 | k);
-      P.el[P.at(0, k)] = (uint8_t)k;
-    }
-  }
-  int n = 4, cur = 0;
   ovf = false;
-  for (int l = 0; l < 4; ++l) {
+  int n;
+  // stage 1: slave polygon (registers) against master edge 0, into buffer 1
+  {
+    const V2 a = Mo[0], b = Mo[1];
+    const double dbu = b.u - a.u, dbv = b.v - a.v;
+    double c[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) c[k] = side_of(a, dbu, dbv, S[k].u, S[k].v);
+    int k = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int e = (j + 1) & 3;
+      const bool pin = c[j] >= 0.0, ein = c[e] >= 0.0;
+      if (pin) {
+        emit_vertex<LAB>(P, 1, k, S[j].u, S[j].v, (uint8_t)(0x80 | j), (uint8_t)j);
+        ++k;
+      }
+      if (pin != ein) {
+        const double t = c[j] / (c[j] - c[e]);
+        emit_vertex<LAB>(P, 1, k, S[j].u + t * (S[e].u - S[j].u), S[j].v + t * (S[e].v - S[j].v),
+                         (uint8_t)((j << 4) | 4), pin ? (uint8_t)4 : (uint8_t)j);
+        ++k;
+      }
+    }
+    n = k;
+  }
+  int cur = 1;
+  for (int l = 1; l < 4; ++l) {
     if (n == 0) break;
     const V2 a = Mo[l];
     const V2 b = Mo[(l + 1) & 3];
     const double dbu = b.u - a.u, dbv = b.v - a.v;
     const int nxt = cur ^ 1;
     const int cap = nxt ? CAP1 : CAP0;
-    double Pu = P.u[P.at(cur, 0)], Pv = P.v[P.at(cur, 0)];
-    uint8_t Pl = 0, Pe = 0;
-    if (LAB) { Pl = P.vl[P.at(cur, 0)]; Pe = P.el[P.at(cur, 0)]; }
-    double cP = dbu * (Pv - a.v) - dbv * (Pu - a.u);
-    const double u0 = Pu, v0 = Pv, c0 = cP;
-    const uint8_t l0 = Pl, e0 = Pe;
+    // vertex 0 and the first edge end, read before any store of this stage
+    const double u0 = P.u[P.at(cur, 0)], v0 = P.v[P.at(cur, 0)];
+    uint8_t l0 = 0, e0 = 0;
+    if (LAB) { l0 = P.vl[P.at(cur, 0)]; e0 = P.el[P.at(cur, 0)]; }
+    double Eu = u0, Ev = v0;
+    uint8_t El = l0, Ee = e0;
+    if (n > 1) {
+      Eu = P.u[P.at(cur, 1)];
+      Ev = P.v[P.at(cur, 1)];
+      if (LAB) { El = P.vl[P.at(cur, 1)]; Ee = P.el[P.at(cur, 1)]; }
+    }
+    double Pu = u0, Pv = v0;
+    uint8_t Pl = l0, Pe = e0;
+    const double c0 = side_of(a, dbu, dbv, u0, v0);
+    double cP = c0;
     int k = 0;
     for (int j = 0; j < n; ++j) {
-      double Eu, Ev, cE;
-      uint8_t El = 0, Ee = 0;
-      if (j + 1 < n) {
-        Eu = P.u[P.at(cur, j + 1)];
-        Ev = P.v[P.at(cur, j + 1)];
-        if (LAB) { El = P.vl[P.at(cur, j + 1)]; Ee = P.el[P.at(cur, j + 1)]; }
-        cE = dbu * (Ev - a.v) - dbv * (Eu - a.u);
-      } else {
-        Eu = u0; Ev = v0; cE = c0;
-        if (LAB) { El = l0; Ee = e0; }
+      // next edge end (vertex j + 2), loaded ahead of this edge's stores
+      double Nu = u0, Nv = v0;
+      uint8_t Nl = l0, Ne = e0;
+      if (j + 2 < n) {
+        Nu = P.u[P.at(cur, j + 2)];
+        Nv = P.v[P.at(cur, j + 2)];
+        if (LAB) { Nl = P.vl[P.at(cur, j + 2)]; Ne = P.el[P.at(cur, j + 2)]; }
       }
+      const double cE = j + 1 < n ? side_of(a, dbu, dbv, Eu, Ev) : c0;
       const bool pin = cP >= 0.0;
       const bool ein = cE >= 0.0;
       if (pin) {
         if (k == cap) { ovf = true; return 0; }
-        P.u[P.at(nxt, k)] = Pu;
-        P.v[P.at(nxt, k)] = Pv;
-        if (LAB) { P.vl[P.at(nxt, k)] = Pl; P.el[P.at(nxt, k)] = Pe; }
+        emit_vertex<LAB>(P, nxt, k, Pu, Pv, Pl, Pe);
         ++k;
       }
       if (pin != ein) {
         if (k == cap) { ovf = true; return 0; }
         const double t = cP / (cP - cE);
-        P.u[P.at(nxt, k)] = Pu + t * (Eu - Pu);
-        P.v[P.at(nxt, k)] = Pv + t * (Ev - Pv);
-        if (LAB) {
-          P.vl[P.at(nxt, k)] = (uint8_t)((Pe << 4) | (4 + l));
-          P.el[P.at(nxt, k)] = pin ? (uint8_t)(4 + l) : Pe;
-        }
+        emit_vertex<LAB>(P, nxt, k, Pu + t * (Eu - Pu), Pv + t * (Ev - Pv), (uint8_t)((Pe << 4) | (4 + l)),
+                         pin ? (uint8_t)(4 + l) : Pe);
         ++k;
       }
       Pu = Eu; Pv = Ev; cP = cE;
       if (LAB) { Pl = El; Pe = Ee; }
+      Eu = Nu; Ev = Nv;
+      if (LAB) { El = Nl; Ee = Ne; }
     }
     n = k;
     cur = nxt;

@@ -51,7 +51,8 @@ struct PrepReduce {
   int32_t pad;
 };
 
-// Device counters of the pair pipeline.
+// Device counters of the pair pipeline (hist: filled on demand from the
+// candidates' vertex counts by mt_get_stats).
 struct Counters {
   unsigned long long hist[17];
   unsigned long long noconv;
@@ -112,6 +113,7 @@ struct mt_ctx {
   mt::Buf sdata;           // [SD_N][n_s_el] precomputed slave frame and polygon
   mt::Buf mdata;           // [n_m_el][12] master element node coordinates
   mt::Buf reduce;          // PrepReduce
+  mt::Buf prep_part;       // per-block partials of the element preparation
   mt::Buf counters;        // Counters
   // binning
   mt::Buf keys, vals, keys_tmp, vals_tmp;
@@ -172,9 +174,12 @@ hipError_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 hipError_t fill_f64(double* p, double v, int64_t n, hipStream_t s);
 
 // ---- search (mt_search.hip) ------------------------------------------------
-hipError_t launch_prep(const DeviceMesh& m, bool slave, double* box, double* sd, double* md, PrepReduce* red,
+// Element preparation of one side; per-block partial reductions go to
+// part[prep_blocks(n_el)][9], reduced for both sides by launch_prep_reduce.
+int prep_blocks(int32_t n_el);
+hipError_t launch_prep(const DeviceMesh& m, bool slave, double* box, double* sd, double* md, double* part,
                        hipStream_t s);
-hipError_t launch_init_reduce(PrepReduce* red, hipStream_t s);
+hipError_t launch_prep_reduce(const double* part, int nb_s, int nb_m, PrepReduce* red, hipStream_t s);
 void grid_from_reduce(const PrepReduce& r, double delta, double bin_size, Grid& g);
 hipError_t launch_master_keys(const double* box_m, int32_t n_m, Grid g, uint32_t* keys, uint32_t* vals,
                               hipStream_t s);
@@ -189,6 +194,8 @@ hipError_t launch_cand_fill(const double* box_s, int32_t n_s, const double* sbox
 int cand_tmp_per_slave();
 
 // ---- pairs (mt_pairs.hip) ----------------------------------------------------
+// Histogram of clip vertex counts nv[0..n) added to hist[17].
+hipError_t launch_nv_hist(const uint8_t* nv, int64_t n, unsigned long long* hist, hipStream_t s);
 hipError_t launch_maybe_list(const int32_t* flag, const int32_t* mscan, int64_t n_cand, int32_t* mlist,
                              hipStream_t s);
 hipError_t launch_clip_screened(const double* mdata, const double* sdata, int32_t n_s, const KParams& kp,

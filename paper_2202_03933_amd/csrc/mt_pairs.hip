@@ -6,6 +6,8 @@
 // lane-interleaved.  Local blocks are staged structure-of-arrays,
 // blk[c * stride + p] for the 36 components c = [D 4x4 | M 4x4 | g 4], so
 // the stores of a wavefront are coalesced.
+#include <algorithm>
+
 #include "mt_pair_eval.h"
 
 namespace mt {
@@ -54,9 +56,6 @@ __global__ __launch_bounds__(BSC) void k_clip_screened(const double* __restrict_
                                                         PolyBuf out, Counters* cnt) {
   __shared__ double su[CAPT * BSC], sv[CAPT * BSC];
   __shared__ uint8_t sl[CAPT * BSC], se[CAPT * BSC];
-  __shared__ unsigned int hist[18];
-  if (threadIdx.x < 18) hist[threadIdx.x] = 0;
-  __syncthreads();
   const int64_t i = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * BSC + threadIdx.x;
   if (i < n_maybe) {
     const int c = mlist[i];
@@ -83,15 +82,23 @@ __global__ __launch_bounds__(BSC) void k_clip_screened(const double* __restrict_
     nv_out[c] = (uint8_t)n;
     flag2[i] = n >= 3 ? 1 : 0;
     poly_store(P, res, n, flip, out, i);
-    atomicAdd(&hist[n], 1u);
-    if (st & PS_OVERFLOW) atomicAdd(&hist[17], 1u);
+    if (st & PS_OVERFLOW) atomicAdd(&cnt->overflow, 1ull);
+  }
+}
+
+// Histogram of the candidates' clip vertex counts (computed on demand for
+// the statistics): grid-stride over the counts, per-block LDS histogram.
+__global__ __launch_bounds__(BS) void k_nv_hist(const uint8_t* __restrict__ nv, int64_t n,
+                                                 unsigned long long* __restrict__ hist) {
+  __shared__ unsigned int h[17];
+  if (threadIdx.x < 17) h[threadIdx.x] = 0;
+  __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < n; i += (int64_t)gridDim.x * BS) {
+    const unsigned v = nv[i];
+    atomicAdd(&h[v < 17 ? v : 16], 1u);
   }
   __syncthreads();
-  if (threadIdx.x < 18 && hist[threadIdx.x]) {
-    const unsigned long long v = hist[threadIdx.x];
-    if (threadIdx.x < 17) atomicAdd(&cnt->hist[threadIdx.x], v);
-    else atomicAdd(&cnt->overflow, v);
-  }
+  if (threadIdx.x < 17 && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], (unsigned long long)h[threadIdx.x]);
 }
 
 // Pair list and pair polygons from the screened candidates that are pairs.
@@ -176,6 +183,13 @@ __global__ __launch_bounds__(BSC) __attribute__((amdgpu_waves_per_eu(3))) void k
 }
 
 }  // namespace
+
+hipError_t launch_nv_hist(const uint8_t* nv, int64_t n, unsigned long long* hist, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const unsigned nb = (unsigned)std::min<int64_t>(1024, (n + BS - 1) / BS);
+  k_nv_hist<<<nb, BS, 0, s>>>(nv, n, hist);
+  return hipGetLastError();
+}
 
 hipError_t launch_maybe_list(const int32_t* flag, const int32_t* mscan, int64_t n_cand, int32_t* mlist,
                              hipStream_t s) {

@@ -15,6 +15,7 @@ namespace mt {
 namespace {
 
 constexpr int BS = 256;
+constexpr int PREP_PART = 9;  // per-block partials: ext, edge, -lo xyz, hi xyz, bad
 
 __device__ __forceinline__ unsigned long long order_key(double x) {
   const unsigned long long b = (unsigned long long)__double_as_longlong(x);
@@ -57,7 +58,7 @@ __global__ __launch_bounds__(BS) void k_prep(const double* __restrict__ x, const
                                               const double* __restrict__ z, const int32_t* __restrict__ conn,
                                               int32_t n_el, int32_t n_nodes, int slave,
                                               double* __restrict__ box, double* __restrict__ sd,
-                                              double* __restrict__ md, PrepReduce* red) {
+                                              double* __restrict__ md, double* __restrict__ part) {
   __shared__ double sh[BS / 64][8];
   __shared__ int bad;
   if (threadIdx.x == 0) bad = 0;
@@ -122,24 +123,50 @@ __global__ __launch_bounds__(BS) void k_prep(const double* __restrict__ x, const
     double m = sh[0][threadIdx.x];
 #pragma unroll
     for (int i = 1; i < BS / 64; ++i) m = fmax(m, sh[i][threadIdx.x]);
-    const int k = threadIdx.x;
-    if (k == 0) atomicMax(&red->emax_bits, (unsigned long long)__double_as_longlong(m));
-    else if (k == 1) { if (slave) atomicMax(&red->edge_bits, (unsigned long long)__double_as_longlong(m)); }
-    else if (k < 5) { if (-m <= INFINITY && m > -INFINITY) atomicMin(&red->lo_key[k - 2], order_key(-m)); }
-    else { if (m > -INFINITY) atomicMax(&red->hi_key[k - 5], order_key(m)); }
+    part[(int64_t)blockIdx.x * PREP_PART + threadIdx.x] = m;
   }
-  if (threadIdx.x == 0 && bad) atomicOr(&red->bad_index, 1);
+  if (threadIdx.x == 8) part[(int64_t)blockIdx.x * PREP_PART + 8] = bad ? 1.0 : 0.0;
 }
 
-__global__ void k_init_reduce(PrepReduce* r) {
-  r->emax_bits = 0;
-  r->edge_bits = 0;
-  for (int d = 0; d < 3; ++d) {
-    r->lo_key[d] = ~0ull;
-    r->hi_key[d] = 0ull;
+// Final reduction of the per-block partials of both sides (nb_s slave
+// blocks first, then nb_m master blocks) into the grid quantities.
+__global__ __launch_bounds__(BS) void k_prep_reduce(const double* __restrict__ part, int nb_s, int nb_m,
+                                                     PrepReduce* red) {
+  __shared__ double sh[BS / 64][PREP_PART];
+  double v[PREP_PART];
+#pragma unroll
+  for (int k = 0; k < PREP_PART; ++k) v[k] = k == 0 || k == 1 || k == 8 ? 0.0 : -INFINITY;
+  for (int b = threadIdx.x; b < nb_s + nb_m; b += BS) {
+#pragma unroll
+    for (int k = 0; k < PREP_PART; ++k) {
+      const double x = part[(int64_t)b * PREP_PART + k];
+      if (k != 1 || b < nb_s) v[k] = fmax(v[k], x);
+    }
   }
-  r->bad_index = 0;
-  r->pad = 0;
+#pragma unroll
+  for (int k = 0; k < PREP_PART; ++k) v[k] = wave_max(v[k]);
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < PREP_PART; ++k) sh[threadIdx.x >> 6][k] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r[PREP_PART];
+#pragma unroll
+    for (int k = 0; k < PREP_PART; ++k) {
+      r[k] = sh[0][k];
+#pragma unroll
+      for (int i = 1; i < BS / 64; ++i) r[k] = fmax(r[k], sh[i][k]);
+    }
+    red->emax_bits = (unsigned long long)__double_as_longlong(r[0]);
+    red->edge_bits = (unsigned long long)__double_as_longlong(r[1]);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      red->lo_key[d] = r[2 + d] > -INFINITY ? order_key(-r[2 + d]) : ~0ull;
+      red->hi_key[d] = r[5 + d] > -INFINITY ? order_key(r[5 + d]) : 0ull;
+    }
+    red->bad_index = r[8] > 0.0 ? 1 : 0;
+    red->pad = 0;
+  }
 }
 
 __device__ __forceinline__ int cell_coord(double c, double lo, double inv_beta, int n) {
@@ -277,7 +304,7 @@ __device__ __forceinline__ void load_master_data(const double* __restrict__ md, 
 // the output when longer than CCAP (two call sites, so that each pointer
 // has a known address space).
 struct ScreenOut {
-  unsigned rejected, degen_s, degen_m;
+  unsigned degen_s, degen_m;
 };
 
 __device__ __forceinline__ void fill_and_screen(int s, int32_t n_s, int base, int c, int32_t* v, int vs,
@@ -324,10 +351,7 @@ __device__ __forceinline__ void fill_and_screen(int s, int32_t n_s, int base, in
     const bool clip = pair_screen(S, As, Xm, f, eps_a, Mn, hm, flip, st);
     const int64_t ci = (int64_t)base + i;
     flag[ci] = clip ? 1 : 0;
-    if (!clip) {
-      nv_out[ci] = 0;
-      ++so.rejected;
-    }
+    if (!clip) nv_out[ci] = 0;
     so.degen_s += (st & PS_DEGEN_SLAVE) ? 1u : 0u;
     so.degen_m += (st & PS_DEGEN_MASTER) ? 1u : 0u;
     if (copy_out) cand_m[ci] = m;
@@ -346,45 +370,37 @@ __global__ __launch_bounds__(BS) void k_cand_fill(const double* __restrict__ box
                                                    uint8_t* __restrict__ nv_out, int32_t* __restrict__ flag,
                                                    Counters* cnt) {
   __shared__ int32_t lds[CCAP * BS];
-  __shared__ unsigned int hist[3];
-  if (threadIdx.x < 3) hist[threadIdx.x] = 0;
-  __syncthreads();
   const int s = blockIdx.x * BS + threadIdx.x;
   if (s < n_s) {
     const int base = off[s];
     const int c = off[s + 1] - base;
-    ScreenOut so{0u, 0u, 0u};
+    ScreenOut so{0u, 0u};
     if (c <= CCAP)
       fill_and_screen(s, n_s, base, c, lds + threadIdx.x, BS, true, box_s, sbox, mvals, range, g, delta, tmp, cand_s,
                       cand_m, sd, md, eps_a, nv_out, flag, so);
     else
       fill_and_screen(s, n_s, base, c, cand_m + base, 1, false, box_s, sbox, mvals, range, g, delta, tmp, cand_s,
                       cand_m, sd, md, eps_a, nv_out, flag, so);
-    if (so.rejected) atomicAdd(&hist[0], so.rejected);
-    if (so.degen_s) atomicAdd(&hist[1], so.degen_s);
-    if (so.degen_m) atomicAdd(&hist[2], so.degen_m);
-  }
-  __syncthreads();
-  if (threadIdx.x < 3 && hist[threadIdx.x]) {
-    const unsigned long long val = hist[threadIdx.x];
-    if (threadIdx.x == 0) atomicAdd(&cnt->hist[0], val);
-    else if (threadIdx.x == 1) atomicAdd(&cnt->degen_slave, val);
-    else atomicAdd(&cnt->degen_master, val);
+    // degenerate elements are rare: count them with global atomics
+    if (so.degen_s) atomicAdd(&cnt->degen_slave, (unsigned long long)so.degen_s);
+    if (so.degen_m) atomicAdd(&cnt->degen_master, (unsigned long long)so.degen_m);
   }
 }
 
 }  // namespace
 
-hipError_t launch_init_reduce(PrepReduce* red, hipStream_t s) {
-  k_init_reduce<<<1, 1, 0, s>>>(red);
+int prep_blocks(int32_t n_el) { return n_el == 0 ? 0 : std::min(2048, (n_el + BS - 1) / BS); }
+
+hipError_t launch_prep(const DeviceMesh& m, bool slave, double* box, double* sd, double* md, double* part,
+                       hipStream_t s) {
+  if (m.n_el == 0) return hipSuccess;
+  k_prep<<<prep_blocks(m.n_el), BS, 0, s>>>(m.x, m.y, m.z, m.conn, m.n_el, m.n_nodes, slave ? 1 : 0, box, sd, md,
+                                             part);
   return hipGetLastError();
 }
 
-hipError_t launch_prep(const DeviceMesh& m, bool slave, double* box, double* sd, double* md, PrepReduce* red,
-                       hipStream_t s) {
-  if (m.n_el == 0) return hipSuccess;
-  const int grid = std::min(2048, (m.n_el + BS - 1) / BS);
-  k_prep<<<grid, BS, 0, s>>>(m.x, m.y, m.z, m.conn, m.n_el, m.n_nodes, slave ? 1 : 0, box, sd, md, red);
+hipError_t launch_prep_reduce(const double* part, int nb_s, int nb_m, PrepReduce* red, hipStream_t s) {
+  k_prep_reduce<<<1, BS, 0, s>>>(part, nb_s, nb_m, red);
   return hipGetLastError();
 }
 
