@@ -22,7 +22,7 @@
 namespace mt {
 
 constexpr int NQUEUE = 8;
-constexpr int ROWS_PER_ITEM = 256;
+constexpr int ROWS_PER_ITEM = 128;
 
 struct BatchInst {
   MeshPtrs S, M;
@@ -182,7 +182,7 @@ __global__ __launch_bounds__(BSZ) __attribute__((amdgpu_waves_per_eu(2))) void k
 }
 
 // Row phases: one block per item of ROWS_PER_ITEM rows of one instance.
-constexpr int BATCH_ACAP = 24;  // per-thread row accumulator of the batched assembly
+constexpr int BATCH_ACAP = 32;  // per-thread row accumulator of the batched assembly
 
 __global__ __launch_bounds__(ROWS_PER_ITEM) void k_batch_assemble(const BatchInst* __restrict__ inst,
                                                                    const WorkItem* __restrict__ items) {
