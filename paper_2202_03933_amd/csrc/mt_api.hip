@@ -208,6 +208,7 @@ int mt_upload(mt_ctx* c, int side, int64_t n_nodes, const double* x, const doubl
   m.n_nodes = (int32_t)n_nodes;
   m.n_el = (int32_t)n_el;
   m.set = true;
+  c->have_inc[side] = false;
   c->have_pairs = c->have_pattern = c->have_master_index = false;
   ++c->coord_gen;
   return MT_OK;
@@ -437,24 +438,27 @@ int mt_csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, void* stream) {
   const DeviceMesh& M = c->side[1];
   const int32_t n = S.n_nodes;
   PhaseTimer timer(c, MT_T_PATTERN, st);
-  int rc = build_incidence(c, S, c->inc_cnt, c->inc_off, c->inc_cur, c->inc_list, st);
-  if (rc) return rc;
-  // rows whose candidate lists exceed the per-thread LDS segment get global scratch
+  if (!c->have_inc[0]) {
+    int rc = build_incidence(c, S, c->inc_cnt, c->inc_off, c->inc_cur, c->inc_list, st);
+    if (rc) return rc;
+    c->have_inc[0] = true;
+  }
+  // rows whose column candidates exceed the per-thread LDS segment get global
+  // scratch, sized by the bounds 4 entries per incident element (D) and per
+  // pair of an incident element (M): at most 16 n_el and 16 n_pairs in total
+  if (16 * (int64_t)S.n_el >= (int64_t(1) << 31) || 16 * c->n_pairs >= (int64_t(1) << 31))
+    return fail(MT_ECAPACITY, "mt_csr_pattern: more than 2^31 block entries");
   MT_HIP(ensure(c->rawD_cnt, sizeof(int32_t) * ((size_t)n + 1)));
   MT_HIP(ensure(c->rawM_cnt, sizeof(int32_t) * ((size_t)n + 1)));
   MT_HIP(ensure(c->rawD_off, sizeof(int32_t) * ((size_t)n + 1)));
   MT_HIP(ensure(c->rawM_off, sizeof(int32_t) * ((size_t)n + 1)));
+  MT_HIP(ensure(c->rawD, sizeof(int32_t) * 16 * (size_t)std::max(S.n_el, 1)));
+  MT_HIP(ensure(c->rawM, sizeof(int32_t) * 16 * (size_t)std::max<int64_t>(c->n_pairs, 1)));
   MT_HIP(launch_raw_count(c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(), n, c->pair_off.as<int32_t>(),
                           c->rawD_cnt.as<int32_t>(), c->rawM_cnt.as<int32_t>(), st));
   MT_HIP(scan_exclusive(c->rawD_cnt.as<int32_t>(), c->rawD_off.as<int32_t>(), n, c->scan_tmp, st));
   MT_HIP(scan_exclusive(c->rawM_cnt.as<int32_t>(), c->rawM_off.as<int32_t>(), n, c->scan_tmp, st));
   int32_t tot[2] = {0, 0};
-  MT_HIP(hipMemcpyAsync(&tot[0], c->rawD_off.as<int32_t>() + n, 4, hipMemcpyDeviceToHost, st));
-  MT_HIP(hipMemcpyAsync(&tot[1], c->rawM_off.as<int32_t>() + n, 4, hipMemcpyDeviceToHost, st));
-  MT_HIP(hipStreamSynchronize(st));
-  if (tot[0] < 0 || tot[1] < 0) return fail(MT_ECAPACITY, "mt_csr_pattern: more than 2^31 block entries");
-  MT_HIP(ensure(c->rawD, sizeof(int32_t) * (size_t)tot[0]));
-  MT_HIP(ensure(c->rawM, sizeof(int32_t) * (size_t)tot[1]));
   MT_HIP(ensure(c->pat_keep, sizeof(int32_t) * (size_t)pattern_keep_per_row() * (size_t)std::max(n, 1)));
   MT_HIP(ensure(c->D_cnt, sizeof(int32_t) * ((size_t)n + 1)));
   MT_HIP(ensure(c->M_cnt, sizeof(int32_t) * ((size_t)n + 1)));
@@ -565,8 +569,11 @@ mt::PolyBuf mt::poly_buf(mt_ctx* c) {
 int mt::ensure_master_index(mt_ctx* c, hipStream_t st) {
   if (c->have_master_index) return MT_OK;
   const DeviceMesh& M = c->side[1];
-  int rc = build_incidence(c, M, c->minc_cnt, c->minc_off, c->minc_cur, c->minc_list, st);
-  if (rc) return rc;
+  if (!c->have_inc[1]) {
+    int rc = build_incidence(c, M, c->minc_cnt, c->minc_off, c->minc_cur, c->minc_list, st);
+    if (rc) return rc;
+    c->have_inc[1] = true;
+  }
   const int64_t np = c->n_pairs;
   MT_HIP(ensure(c->mp_keys, sizeof(uint32_t) * (size_t)np));
   MT_HIP(ensure(c->mp_vals, sizeof(uint32_t) * (size_t)np));
@@ -603,6 +610,7 @@ int mt_backward(mt_ctx* c, const double* W_D, const double* W_M, const double* w
   hipStream_t st = (hipStream_t)stream;
   c->last_stream = st;
   {
+    PhaseTimer t(c, MT_T_GRAD_REDUCE, st);
     int rc = ensure_master_index(c, st);
     if (rc) return rc;
   }

@@ -39,6 +39,8 @@ struct Grid {
   double beta[3];
   int32_t n[3];
   int64_t ncells;
+  double reach;  // delta + half the largest element box extent, padded: a master whose box
+                 // touches the delta-enlarged slave box has its centre within this of the slave box
 };
 
 // Device-side scalar reductions of the element preparation step.
@@ -105,6 +107,7 @@ struct mt_ctx {
   bool have_pairs = false;
   bool have_pattern = false;
   bool have_master_index = false;
+  bool have_inc[2] = {false, false};  // node incidence of each side (depends on connectivity only)
   int64_t n_cand = 0, n_pairs = 0, nnz_D = 0, nnz_M = 0;
   mt::Grid grid{};
 

@@ -233,7 +233,7 @@ __device__ __forceinline__ bool touch(const SlaveBox& s, const double* __restric
   return t;
 }
 
-constexpr int CCAP = 48;  // per-thread LDS segment of the candidate fill (masters)
+constexpr int CCAP = 32;  // per-thread LDS segment of the candidate fill (masters)
 constexpr int CTMP = 32;  // candidates per slave kept by the count pass
 
 // Candidates of one slave element: masters of its own and the 26 neighbouring
@@ -247,19 +247,19 @@ template <bool FILL>
 __device__ __forceinline__ int walk_cells(const SlaveBox& b, const double* __restrict__ sbox,
                                           const uint32_t* __restrict__ mvals, const int2* __restrict__ range,
                                           const Grid& g, double delta, int32_t* v, int64_t vs, int vcap) {
-  int ix[3];
+  // the 27 cells around the slave centre's cell, restricted to those that
+  // can hold the centre of a touching master (within g.reach of the box)
+  int c0[3], c1[3];
 #pragma unroll
-  for (int d = 0; d < 3; ++d) ix[d] = cell_coord(0.5 * (b.lo[d] + b.hi[d]), g.lo[d], g.inv_beta[d], g.n[d]);
+  for (int d = 0; d < 3; ++d) {
+    const int ic = cell_coord(0.5 * (b.lo[d] + b.hi[d]), g.lo[d], g.inv_beta[d], g.n[d]);
+    c0[d] = max(ic - 1, cell_coord(b.lo[d] - g.reach, g.lo[d], g.inv_beta[d], g.n[d]));
+    c1[d] = min(ic + 1, cell_coord(b.hi[d] + g.reach, g.lo[d], g.inv_beta[d], g.n[d]));
+  }
   int c = 0;
-  for (int dz = -1; dz <= 1; ++dz) {
-    const int zz = ix[2] + dz;
-    if (zz < 0 || zz >= g.n[2]) continue;
-    for (int dy = -1; dy <= 1; ++dy) {
-      const int yy = ix[1] + dy;
-      if (yy < 0 || yy >= g.n[1]) continue;
-      for (int dx = -1; dx <= 1; ++dx) {
-        const int xx = ix[0] + dx;
-        if (xx < 0 || xx >= g.n[0]) continue;
+  for (int zz = c0[2]; zz <= c1[2]; ++zz) {
+    for (int yy = c0[1]; yy <= c1[1]; ++yy) {
+      for (int xx = c0[0]; xx <= c1[0]; ++xx) {
         const int64_t cell = xx + (int64_t)g.n[0] * (yy + (int64_t)g.n[1] * zz);
         const int2 r = range[cell];
         for (int i = r.x; i < r.y; ++i) {
@@ -340,10 +340,21 @@ __device__ __forceinline__ void fill_and_screen(int s, int32_t n_s, int base, in
     S[k].v = sd[(int64_t)(16 + k) * n_s + s];
   }
   As = sd[(int64_t)20 * n_s + s];
+  // the next candidate's master nodes are loaded while this one is screened
+  int mn = c > 0 ? v[0] : 0;
+  double Xn[4][3];
+  if (c > 0) load_master_data(md, mn, Xn);
   for (int i = 0; i < c; ++i) {
-    const int m = v[i * vs];
+    const int m = mn;
     double Xm[4][3];
-    load_master_data(md, m, Xm);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) Xm[k][d] = Xn[k][d];
+    if (i + 1 < c) {
+      mn = v[(i + 1) * vs];
+      load_master_data(md, mn, Xn);
+    }
     V2 Mn[4];
     double hm[4];
     int st;
@@ -432,6 +443,8 @@ void grid_from_reduce(const PrepReduce& r, double delta, double bin_size, Grid& 
     g.inv_beta[d] = 1.0 / g.beta[d];
   }
   g.ncells = n[0] * n[1] * n[2];
+  // padded so that rounding in the box centres cannot move a centre across
+  g.reach = (delta + 0.5 * emax) * (1.0 + 1e-9) + 1e-9 * beta_min;
 }
 
 hipError_t launch_master_keys(const double* box_m, int32_t n_m, Grid g, uint32_t* keys, uint32_t* vals,
