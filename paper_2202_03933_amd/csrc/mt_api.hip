@@ -167,7 +167,7 @@ int mt_destroy(mt_ctx* c) {
                  &c->minc_off, &c->minc_cur, &c->minc_list, &c->rawD_cnt, &c->rawD_off, &c->rawD, &c->rawM_cnt,
                  &c->rawM_off, &c->rawM, &c->pat_keep, &c->D_cnt, &c->D_rowptr, &c->D_col, &c->M_cnt, &c->M_rowptr,
                  &c->M_col, &c->posD, &c->posM, &c->poly_u, &c->poly_v, &c->poly_lab, &c->poly_nf, &c->maybe_list,
-                 &c->maybe_flag, &c->maybe_scan, &c->mpoly_u, &c->mpoly_v, &c->mpoly_lab, &c->mpoly_nf, &c->blk, &c->gpair, &c->mp_keys, &c->mp_vals, &c->mp_off,
+                 &c->maybe_flag, &c->maybe_scan, &c->mpoly_u, &c->mpoly_v, &c->mpoly_lab, &c->mpoly_nf, &c->blk, &c->gpair, &c->mp_keys, &c->mp_vals, &c->mp_off, &c->mp_pos,
                  &c->scan_tmp, &c->sort_hist, &c->host_tmp};
   for (Buf* b : bufs) release(*b);
   for (auto& iv : c->intervals) {
@@ -589,7 +589,9 @@ int mt::ensure_master_index(mt_ctx* c, hipStream_t st) {
                           c->vals_tmp.as<uint32_t>(), np, bits_for(std::max<int32_t>(M.n_el, 2)), c->sort_hist,
                           c->scan_tmp, st));
   MT_HIP(hipMemsetAsync(c->mp_off.p, 0, sizeof(int32_t) * 2 * ((size_t)M.n_el + 1), st));
-  MT_HIP(launch_mpair_off(c->mp_keys.as<uint32_t>(), np, M.n_el, c->mp_off.as<int32_t>(), st));
+  MT_HIP(ensure(c->mp_pos, sizeof(int32_t) * (size_t)std::max<int64_t>(np, 1)));
+  MT_HIP(launch_mpair_off(c->mp_keys.as<uint32_t>(), c->mp_vals.as<uint32_t>(), np, M.n_el, c->mp_off.as<int32_t>(),
+                          c->mp_pos.as<int32_t>(), st));
   c->have_master_index = true;
   return MT_OK;
 }
@@ -629,6 +631,7 @@ int mt_backward(mt_ctx* c, const double* W_D, const double* W_M, const double* w
   {
     PhaseTimer t(c, MT_T_PAIR_BWD, st);
     MT_HIP(launch_pair_bwd(S, M, kparams(c->params), c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), np, poly,
+                           c->mp_pos.as<int32_t>(),
                            c->posD.as<int32_t>(), S.n_el, c->posM.as<int32_t>(), W_D, W_M, w_g,
                            c->gpair.as<double>(), np, c->counters.as<Counters>(), st));
   }
@@ -637,7 +640,7 @@ int mt_backward(mt_ctx* c, const double* W_D, const double* W_M, const double* w
                            c->gpair.as<double>(), np, gXs, st));
   const int32_t* mo = c->mp_off.as<int32_t>();
   MT_HIP(launch_grad_master(c->minc_off.as<int32_t>(), c->minc_list.as<int32_t>(), M.n_nodes, mo, mo + M.n_el,
-                            c->mp_vals.as<uint32_t>(), c->gpair.as<double>(), np, gXm, st));
+                            c->gpair.as<double>(), np, gXm, st));
   return MT_OK;
 }
 

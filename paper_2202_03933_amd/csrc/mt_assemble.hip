@@ -290,12 +290,18 @@ __global__ __launch_bounds__(BS) void k_grad_master(const int32_t* __restrict__ 
                                                      const int32_t* __restrict__ inc_list, int32_t n,
                                                      const int32_t* __restrict__ mstart,
                                                      const int32_t* __restrict__ mend,
-                                                     const uint32_t* __restrict__ mpairs,
                                                      const double* __restrict__ gpair, int64_t stride,
                                                      double* __restrict__ gX) {
   const int b = blockIdx.x * BS + threadIdx.x;
   if (b >= n) return;
-  grad_master_row(b, n, inc_off, inc_list, mstart, mend, mpairs, gpair, stride, gX);
+  grad_master_row(b, n, inc_off, inc_list, mstart, mend, gpair, stride, gX);
+}
+
+// Rank of each pair in the pairs-by-master order: mpos[mpairs[k]] = k.
+__global__ __launch_bounds__(BS) void k_mpair_pos(const uint32_t* __restrict__ mpairs, int64_t np,
+                                                   int32_t* __restrict__ mpos) {
+  const int64_t k = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (k < np) mpos[mpairs[k]] = (int32_t)k;
 }
 
 inline unsigned grid_of(int64_t n) { return (unsigned)((n + BS - 1) / BS); }
@@ -383,20 +389,20 @@ hipError_t launch_grad_slave(const int32_t* inc_off, const int32_t* inc_list, in
   return hipGetLastError();
 }
 
-hipError_t launch_mpair_off(const uint32_t* sorted_m, int64_t n_pairs, int32_t n_m_el, int32_t* off,
-                            hipStream_t s) {
+hipError_t launch_mpair_off(const uint32_t* sorted_m, const uint32_t* mpairs, int64_t n_pairs, int32_t n_m_el,
+                            int32_t* off, int32_t* mpos, hipStream_t s) {
   // off holds start[n_m_el] followed by end[n_m_el]; both pre-zeroed.
   if (n_pairs == 0) return hipSuccess;
   k_mpair_ranges<<<grid_of(n_pairs), BS, 0, s>>>(sorted_m, n_pairs, off, off + n_m_el);
+  k_mpair_pos<<<grid_of(n_pairs), BS, 0, s>>>(mpairs, n_pairs, mpos);
   return hipGetLastError();
 }
 
 hipError_t launch_grad_master(const int32_t* inc_off, const int32_t* inc_list, int32_t n_nodes,
-                              const int32_t* mstart, const int32_t* mend, const uint32_t* mp_pairs,
-                              const double* gpair, int64_t stride, double* gX, hipStream_t s) {
+                              const int32_t* mstart, const int32_t* mend, const double* gpair, int64_t stride,
+                              double* gX, hipStream_t s) {
   if (n_nodes == 0) return hipSuccess;
-  k_grad_master<<<grid_of(n_nodes), BS, 0, s>>>(inc_off, inc_list, n_nodes, mstart, mend, mp_pairs, gpair, stride,
-                                                gX);
+  k_grad_master<<<grid_of(n_nodes), BS, 0, s>>>(inc_off, inc_list, n_nodes, mstart, mend, gpair, stride, gX);
   return hipGetLastError();
 }
 

@@ -38,6 +38,7 @@ template <int NQ>
 __global__ __launch_bounds__(BSC) __attribute__((amdgpu_waves_per_eu(2))) void k_pair_bwd(MeshPtrs S, int32_t n_s, MeshPtrs M, KParams kp,
                                                    const int32_t* __restrict__ pair_s,
                                                    const int32_t* __restrict__ pair_m, int64_t n_pairs, PolyBuf poly,
+                                                   const int32_t* __restrict__ mpos,
                                                    const int32_t* __restrict__ posD, const int32_t* __restrict__ posM,
                                                    const double* __restrict__ W_D, const double* __restrict__ W_M,
                                                    const double* __restrict__ w_g, double* __restrict__ gpair,
@@ -52,12 +53,13 @@ __global__ __launch_bounds__(BSC) __attribute__((amdgpu_waves_per_eu(2))) void k
     double Xsb[4][3], Xmb[4][3];
     pair_backward<NQ>(S, csn, M, load_conn(M.conn, pair_m[p]), gpoly(poly, p), poly.nf[p], kp, WD, WM, wg, Xsb, Xmb,
                       noconv);
+    const int64_t q = mpos[p];
 #pragma unroll
     for (int k = 0; k < 4; ++k)
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         gpair[(int64_t)(3 * k + d) * stride + p] = Xsb[k][d];
-        gpair[(int64_t)(12 + 3 * k + d) * stride + p] = Xmb[k][d];
+        gpair[(int64_t)(12 + 3 * k + d) * stride + q] = Xmb[k][d];
       }
   }
   const unsigned long long nc = wave_sum_u64(noconv);
@@ -67,17 +69,18 @@ __global__ __launch_bounds__(BSC) __attribute__((amdgpu_waves_per_eu(2))) void k
 }  // namespace
 
 hipError_t launch_pair_bwd(const DeviceMesh& S, const DeviceMesh& M, const KParams& kp, const int32_t* pair_s,
-                           const int32_t* pair_m, int64_t n_pairs, const PolyBuf& poly, const int32_t* posD, int32_t n_s_el,
+                           const int32_t* pair_m, int64_t n_pairs, const PolyBuf& poly, const int32_t* mpos,
+                           const int32_t* posD, int32_t n_s_el,
                            const int32_t* posM, const double* W_D, const double* W_M, const double* w_g,
                            double* gpair, int64_t stride, Counters* cnt, hipStream_t s) {
   if (n_pairs == 0) return hipSuccess;
   const unsigned nb = xcd_grid((unsigned)((n_pairs + BSC - 1) / BSC));
   const MeshPtrs ms{S.x, S.y, S.z, S.conn}, mm{M.x, M.y, M.z, M.conn};
   if (kp.rule == 3)
-    k_pair_bwd<3><<<nb, BSC, 0, s>>>(ms, n_s_el, mm, kp, pair_s, pair_m, n_pairs, poly, posD, posM, W_D, W_M, w_g, gpair,
+    k_pair_bwd<3><<<nb, BSC, 0, s>>>(ms, n_s_el, mm, kp, pair_s, pair_m, n_pairs, poly, mpos, posD, posM, W_D, W_M, w_g, gpair,
                                      stride, cnt);
   else
-    k_pair_bwd<7><<<nb, BSC, 0, s>>>(ms, n_s_el, mm, kp, pair_s, pair_m, n_pairs, poly, posD, posM, W_D, W_M, w_g, gpair,
+    k_pair_bwd<7><<<nb, BSC, 0, s>>>(ms, n_s_el, mm, kp, pair_s, pair_m, n_pairs, poly, mpos, posD, posM, W_D, W_M, w_g, gpair,
                                      stride, cnt);
   return hipGetLastError();
 }

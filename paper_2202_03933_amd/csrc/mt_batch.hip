@@ -41,7 +41,7 @@ struct BatchInst {
   const int32_t* minc_list;
   const int32_t* mstart;
   const int32_t* mend;
-  const uint32_t* mpairs;
+  const int32_t* mpos;
   double* blk;
   double* gpair;
   PolyBuf poly;
@@ -168,12 +168,13 @@ __global__ __launch_bounds__(BSZ) __attribute__((amdgpu_waves_per_eu(2))) void k
       double Xsb[4][3], Xmb[4][3];
       pair_backward<NQ>(I.S, csn, I.M, load_conn(I.M.conn, I.pair_m[p]), gpoly(I.poly, p), I.poly.nf[p], I.kp, WD,
                         WM, wg, Xsb, Xmb, noconv);
+      const int64_t q = I.mpos[p];
 #pragma unroll
       for (int k = 0; k < 4; ++k)
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
           I.gpair[(int64_t)(3 * k + d) * st + p] = Xsb[k][d];
-          I.gpair[(int64_t)(12 + 3 * k + d) * st + p] = Xmb[k][d];
+          I.gpair[(int64_t)(12 + 3 * k + d) * st + q] = Xmb[k][d];
         }
     }
   }
@@ -204,7 +205,7 @@ __global__ __launch_bounds__(ROWS_PER_ITEM) void k_batch_grad_rows(const BatchIn
   if (w.pad == 0)
     grad_slave_row(a, I.n_s_nodes, I.inc_off, I.inc_list, I.pair_off, I.gpair, I.n_pairs, I.gXs);
   else
-    grad_master_row(a, I.n_m_nodes, I.minc_off, I.minc_list, I.mstart, I.mend, I.mpairs, I.gpair, I.n_pairs, I.gXm);
+    grad_master_row(a, I.n_m_nodes, I.minc_off, I.minc_list, I.mstart, I.mend, I.gpair, I.n_pairs, I.gXm);
 }
 
 using PolyFn = void (*)(const BatchInst*, const WorkItem*, const int32_t*, int32_t*);
@@ -522,7 +523,7 @@ int mt_batch_build(mt_batch* b, const mt_batch_tuning* tuning, void* stream) {
     I.minc_list = c->minc_list.as<int32_t>();
     I.mstart = c->mp_off.as<int32_t>();
     I.mend = c->mp_off.as<int32_t>() ? c->mp_off.as<int32_t>() + M.n_el : nullptr;
-    I.mpairs = c->mp_vals.as<uint32_t>();
+    I.mpos = c->mp_pos.as<int32_t>();
     I.blk = c->blk.as<double>();
     I.gpair = c->gpair.as<double>();
     {

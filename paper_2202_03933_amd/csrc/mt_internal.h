@@ -160,6 +160,7 @@ struct mt_ctx {
   mt::Buf blk;             // [36][n_pairs]
   mt::Buf gpair;           // [24][n_pairs]
   mt::Buf mp_keys, mp_vals, mp_off;  // pairs sorted by master element
+  mt::Buf mp_pos;          // int32 [n_pairs]: rank of each pair in that order
   // scan / sort scratch
   mt::Buf scan_tmp, sort_hist, host_tmp;
 };
@@ -242,15 +243,18 @@ hipError_t launch_assemble(const int32_t* inc_off, const int32_t* inc_list, int3
 hipError_t launch_grad_slave(const int32_t* inc_off, const int32_t* inc_list, int32_t n_nodes,
                              const int32_t* pair_off, const double* gpair, int64_t stride, double* gX,
                              hipStream_t s);
-hipError_t launch_mpair_off(const uint32_t* sorted_m, int64_t n_pairs, int32_t n_m_el, int32_t* off,
-                            hipStream_t s);
+// Master ranges of the pairs-by-master order and each pair's rank in it.
+hipError_t launch_mpair_off(const uint32_t* sorted_m, const uint32_t* mpairs, int64_t n_pairs, int32_t n_m_el,
+                            int32_t* off, int32_t* mpos, hipStream_t s);
 hipError_t launch_grad_master(const int32_t* inc_off, const int32_t* inc_list, int32_t n_nodes,
-                              const int32_t* mstart, const int32_t* mend, const uint32_t* mp_pairs,
-                              const double* gpair, int64_t stride, double* gX, hipStream_t s);
+                              const int32_t* mstart, const int32_t* mend, const double* gpair, int64_t stride,
+                              double* gX, hipStream_t s);
 
 // ---- backward (mt_backward.hip) ----------------------------------------------
+// Backward of every pair: slave gradient components at gpair[c * stride + p],
+// master components at gpair[(12 + c) * stride + mpos[p]].
 hipError_t launch_pair_bwd(const DeviceMesh& S, const DeviceMesh& M, const KParams& kp, const int32_t* pair_s, const int32_t* pair_m,
-                           int64_t n_pairs, const PolyBuf& poly, const int32_t* posD, int32_t n_s_el, const int32_t* posM,
+                           int64_t n_pairs, const PolyBuf& poly, const int32_t* mpos, const int32_t* posD, int32_t n_s_el, const int32_t* posM,
                            const double* W_D, const double* W_M, const double* w_g, double* gpair,
                            int64_t stride, Counters* cnt, hipStream_t s);
 

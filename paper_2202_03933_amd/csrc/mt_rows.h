@@ -114,22 +114,22 @@ __device__ __forceinline__ void grad_slave_row(int a, int32_t n, const int32_t* 
   gX[2 * (int64_t)n + a] = g2;
 }
 
-// Gradient of master node b: pairs of each incident master element through
-// the pairs-by-master permutation mpairs[mstart[m] .. mend[m]).
+// Gradient of master node b: the master components of the pairs are staged
+// in pairs-by-master order (position k of pair p = its rank in that order),
+// so the pairs of master element m are the contiguous range
+// mstart[m] .. mend[m].
 __device__ __forceinline__ void grad_master_row(int b, int32_t n, const int32_t* __restrict__ inc_off,
                                                 const int32_t* __restrict__ inc_list,
                                                 const int32_t* __restrict__ mstart, const int32_t* __restrict__ mend,
-                                                const uint32_t* __restrict__ mpairs,
                                                 const double* __restrict__ gpair, int64_t stride,
                                                 double* __restrict__ gX) {
   double g0 = 0.0, g1 = 0.0, g2 = 0.0;
   for (int i = inc_off[b]; i < inc_off[b + 1]; ++i) {
     const int m = inc_list[i] >> 2, l = inc_list[i] & 3;
     for (int k = mstart[m]; k < mend[m]; ++k) {
-      const int64_t p = mpairs[k];
-      g0 += gpair[(int64_t)(12 + 3 * l + 0) * stride + p];
-      g1 += gpair[(int64_t)(12 + 3 * l + 1) * stride + p];
-      g2 += gpair[(int64_t)(12 + 3 * l + 2) * stride + p];
+      g0 += gpair[(int64_t)(12 + 3 * l + 0) * stride + k];
+      g1 += gpair[(int64_t)(12 + 3 * l + 1) * stride + k];
+      g2 += gpair[(int64_t)(12 + 3 * l + 2) * stride + k];
     }
   }
   gX[b] = g0;
