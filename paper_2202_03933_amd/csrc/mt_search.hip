@@ -233,7 +233,7 @@ __device__ __forceinline__ bool touch(const SlaveBox& s, const double* __restric
   return t;
 }
 
-constexpr int CCAP = 32;  // per-thread LDS segment of the candidate fill (masters)
+constexpr int CCAP = 48;  // per-thread LDS segment of the candidate fill (masters)
 constexpr int CTMP = 32;  // candidates per slave kept by the count pass
 
 // Candidates of one slave element: masters of its own and the 26 neighbouring
@@ -340,21 +340,10 @@ __device__ __forceinline__ void fill_and_screen(int s, int32_t n_s, int base, in
     S[k].v = sd[(int64_t)(16 + k) * n_s + s];
   }
   As = sd[(int64_t)20 * n_s + s];
-  // the next candidate's master nodes are loaded while this one is screened
-  int mn = c > 0 ? v[0] : 0;
-  double Xn[4][3];
-  if (c > 0) load_master_data(md, mn, Xn);
   for (int i = 0; i < c; ++i) {
-    const int m = mn;
+    const int m = v[i * vs];
     double Xm[4][3];
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-#pragma unroll
-      for (int d = 0; d < 3; ++d) Xm[k][d] = Xn[k][d];
-    if (i + 1 < c) {
-      mn = v[(i + 1) * vs];
-      load_master_data(md, mn, Xn);
-    }
+    load_master_data(md, m, Xm);
     V2 Mn[4];
     double hm[4];
     int st;
