@@ -108,7 +108,25 @@ def cpu_baseline(itf, n_slave_el_sample, seed=3000):
     #     of add/sub 2, mul 4, div 4, sqrt 3) + IFT_FLOPS per inverse map.
     f_cp, f_pair, f_adj, n_inv, f_cadj = oracle.count_flops(sub, itf.master, prm, ps[::16], pm[::16], detail=True)
     npp = max(1, ps[::16].size)
-    return {"pairs": int(ps.size), "t_fwd": t_fwd, "t_all": t_all,
+    # the same flop model per geometry of the batched interfaces: the first
+    # 512 slave elements of the largest instance of each geometry
+    geo = {}
+    for b in synth.batched_instances(64):
+        g = b.meta["geometry"]
+        if g not in geo or b.slave.conn.shape[0] > geo[g].slave.conn.shape[0]:
+            geo[g] = b
+    batched_flops = {}
+    for g, b in geo.items():
+        bs = synth.Mesh(b.slave.X, b.slave.conn[:512].copy())
+        bprm = oracle.params(delta=b.delta)
+        bcs, bcm = oracle.search(bs, b.master, b.delta)
+        bnv, _, _ = oracle.eval_candidates(bs, b.master, bprm, bcs, bcm, integrate=False)
+        bk = bnv >= 3
+        q = oracle.count_flops(bs, b.master, bprm, bcs[bk], bcm[bk], detail=True)
+        nb = max(1, int(bk.sum()))
+        batched_flops[g] = {"fwd": (q[1] - q[0]) / nb, "bwd": (q[1] - q[0] + q[2] - q[4] + IFT_FLOPS * q[3]) / nb,
+                            "fwd_full": q[1] / nb}
+    return {"pairs": int(ps.size), "t_fwd": t_fwd, "t_all": t_all, "batched_flops": batched_flops,
             "flops_per_unit": {"pair_poly": f_cp / npp,
                                "pair_fwd": (f_pair - f_cp) / npp,
                                "pair_bwd": (f_pair - f_cp + f_adj - f_cadj + IFT_FLOPS * n_inv) / npp},
@@ -131,7 +149,8 @@ def bench_batched(reps=5):
 
     dev = torch.device("cuda", 0)
     ifaces, W = [], []
-    for itf in synth.batched_instances(64):
+    insts = synth.batched_instances(64)
+    for itf in insts:
         it = MortarInterface(torch.from_numpy(itf.slave.X), torch.from_numpy(itf.slave.conn),
                              torch.from_numpy(itf.master.X), torch.from_numpy(itf.master.conn),
                              params=default_params(delta=itf.delta), device=dev).setup()
@@ -167,6 +186,8 @@ def bench_batched(reps=5):
             it.backward(*w, out=g)
 
     res = {"n_interfaces": len(ifaces), "pairs": pairs, "tuning": tuning,
+           "pairs_by_geometry": {g: sum(it.n_pairs for it, itf in zip(ifaces, insts) if itf.meta["geometry"] == g)
+                                 for g in ("flat", "cylinder", "wavy")},
            "fwd_ms_batched_graph": timed(lambda: b.forward(outs, use_graph=True)),
            "fwd_ms_per_interface": timed(per_fwd),
            "bwd_ms_batched_graph": timed(lambda: b.backward(W, outs=gouts, use_graph=True)),
@@ -300,7 +321,18 @@ def main():
         "roofline_other_kernels": others,
         "batched_64_interfaces": batched,
     }
+    if cpu and batched:
+        # batched vs per-interface as fractions of FP64 peak: algorithmic flops
+        # of every pair (per-geometry oracle counts) over the wall time
+        bf = cpu["batched_flops"]
+        for k in ("fwd", "bwd"):
+            fl = sum(batched["pairs_by_geometry"][g] * bf[g][k] for g in bf)
+            for mode in ("batched_graph", "per_interface"):
+                batched[f"{k}_fp64_frac_{mode}"] = fl / (batched[f"{k}_ms_{mode}"] * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS
     if cpu:
+        # whole step as a fraction of FP64 peak (pair kernels' algorithmic flops over the step time)
+        fpu = cpu["flops_per_unit"]
+        out["step_fp64_frac"] = (fpu["pair_fwd"] + fpu["pair_bwd"]) * n_pairs / (ms_step * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS
         out["cpu_baseline"] = {"value": cpu["pairs"] / cpu["t_all"], "unit": "pairs/s", "cores": 1,
                                "kind": "oracle", "sample": cpu["sample"],
                                "fwd_only_pairs_per_s": cpu["pairs"] / cpu["t_fwd"]}
