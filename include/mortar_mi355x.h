@@ -272,7 +272,11 @@ int mt_batch_build(mt_batch* b, const mt_batch_tuning* tuning, void* stream);
  * output pointers are unchanged. */
 int mt_batch_forward(mt_batch* b, double* const* D_val, double* const* M_val, double* const* gap,
                      int use_graph, void* stream);
-/* Backward for every instance (arguments as for mt_backward, per instance). */
+/* Backward for every instance (arguments as for mt_backward, per instance).
+ * Both calls use each instance's current coordinate arrays (replaced with
+ * mt_update_coordinates since mt_batch_build: their clip polygons are
+ * recomputed first, outside any graph); an instance whose pair list or
+ * pattern was rebuilt since mt_batch_build makes them fail with MT_ESTATE. */
 int mt_batch_backward(mt_batch* b, const double* const* W_D, const double* const* W_M,
                       const double* const* w_g, double* const* gXs, double* const* gXm,
                       int use_graph, void* stream);

@@ -491,6 +491,7 @@ int mt_csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, void* stream) {
                      c->M_rowptr.as<int32_t>(), c->M_col.as<int32_t>(), c->posM.as<int32_t>(), st));
   c->have_pattern = true;
   c->have_master_index = false;
+  ++c->pattern_gen;
   if (nnz_D) *nnz_D = c->nnz_D;
   if (nnz_M) *nnz_M = c->nnz_M;
   return MT_OK;

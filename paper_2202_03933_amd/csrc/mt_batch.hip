@@ -258,6 +258,7 @@ struct mt_batch {
   int nq = 7;
   bool dual = false;
   std::vector<mt::BatchInst> h_inst;
+  std::vector<int64_t> pattern_gen;  // each instance's pattern generation at mt_batch_build
   mt::BatchInst* pinned = nullptr;
   mt::Buf d_inst, d_pitems, d_qbeg, d_qnext, d_ritems_s, d_ritems_sm, counters;
   int n_pitems = 0, n_ritems_s = 0, n_ritems_sm = 0;
@@ -318,6 +319,22 @@ int build_items(mt_batch* b, hipStream_t st) {
     B_HIP(hipMemcpy(b->d_pitems.p, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice));
   B_HIP(hipMemcpy(b->d_qbeg.p, qbeg.data(), sizeof(int32_t) * (NQUEUE + 1), hipMemcpyHostToDevice));
   drop_graphs(b);
+  return MT_OK;
+}
+
+// Current coordinate arrays of every instance (they may have been replaced
+// with mt_update_coordinates since mt_batch_build); an instance whose pair
+// list or pattern was rebuilt needs a new mt_batch_build.
+int sync_instances(mt_batch* b) {
+  for (size_t i = 0; i < b->ctxs.size(); ++i) {
+    mt_ctx* c = b->ctxs[i];
+    if (!c->have_pattern || c->pattern_gen != b->pattern_gen[i])
+      return bfail(MT_ESTATE, "batch: an instance was rebuilt since mt_batch_build; build the batch again");
+    const DeviceMesh& S = c->side[0];
+    const DeviceMesh& M = c->side[1];
+    b->h_inst[i].S = MeshPtrs{S.x, S.y, S.z, S.conn};
+    b->h_inst[i].M = MeshPtrs{M.x, M.y, M.z, M.conn};
+  }
   return MT_OK;
 }
 
@@ -489,6 +506,7 @@ int mt_batch_build(mt_batch* b, const mt_batch_tuning* tuning, void* stream) {
   b->tune = t;
 
   b->h_inst.assign(b->ctxs.size(), BatchInst{});
+  b->pattern_gen.assign(b->ctxs.size(), 0);
   std::vector<WorkItem> rs, rsm;
   for (size_t i = 0; i < b->ctxs.size(); ++i) {
     mt_ctx* c = b->ctxs[i];
@@ -503,6 +521,7 @@ int mt_batch_build(mt_batch* b, const mt_batch_tuning* tuning, void* stream) {
     const DeviceMesh& S = c->side[0];
     const DeviceMesh& M = c->side[1];
     BatchInst& I = b->h_inst[i];
+    b->pattern_gen[i] = c->pattern_gen;
     I.S = MeshPtrs{S.x, S.y, S.z, S.conn};
     I.M = MeshPtrs{M.x, M.y, M.z, M.conn};
     I.n_s_el = S.n_el;
@@ -576,7 +595,9 @@ int mt_batch_forward(mt_batch* b, double* const* D_val, double* const* M_val, do
     b->h_inst[i].M_val = M_val[i];
     b->h_inst[i].gap = gap[i];
   }
-  int rc = upload_inst(b, st);
+  int rc = sync_instances(b);
+  if (rc) return rc;
+  rc = upload_inst(b, st);
   if (rc) return rc;
   rc = refresh_polygons(b, st);
   if (rc) return rc;
@@ -600,7 +621,9 @@ int mt_batch_backward(mt_batch* b, const double* const* W_D, const double* const
     b->h_inst[i].gXs = gXs[i];
     b->h_inst[i].gXm = gXm[i];
   }
-  int rc = upload_inst(b, st);
+  int rc = sync_instances(b);
+  if (rc) return rc;
+  rc = upload_inst(b, st);
   if (rc) return rc;
   rc = refresh_polygons(b, st);
   if (rc) return rc;

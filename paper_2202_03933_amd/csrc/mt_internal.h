@@ -156,6 +156,7 @@ struct mt_ctx {
   mt::Buf poly_lab;        // uint8 [CAP0][n_pairs]
   mt::Buf poly_nf;         // uint8 [n_pairs]
   int64_t coord_gen = 0, poly_gen = -1;
+  int64_t pattern_gen = 0;  // counts completed mt_csr_pattern calls
   // forward / backward staging
   mt::Buf blk;             // [36][n_pairs]
   mt::Buf gpair;           // [24][n_pairs]

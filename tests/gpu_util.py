@@ -88,6 +88,8 @@ def assert_forward_parity(g, o):
     assert np.array_equal(g["cand_nv"], o["cand_nverts"]), "clip vertex counts"
     assert np.array_equal(g["pair_s"], o["pair_s"]) and np.array_equal(g["pair_m"], o["pair_m"]), "pairs"
     assert np.array_equal(g["nverts"], o["nverts"])
+    hist = np.bincount(o["cand_nverts"].astype(np.int64), minlength=17)
+    assert list(hist) == list(g["stats"]["nverts_hist"]), "vertex-count histogram"
     assert_same_pattern(g["D"], o["D"])
     assert_same_pattern(g["M"], o["M"])
     eD = rel_err(g["D"].data, o["D"].data)

@@ -1,0 +1,100 @@
+"""State handling of the HIP path through the C ABI: clip polygons are kept
+from the search and recomputed only after a coordinate update, and both ways
+of obtaining them give bitwise identical results; the batched mode refreshes
+the polygons of instances whose coordinates changed."""
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from tests.gpu_util import csr_weights, gpu_params
+
+pytestmark = pytest.mark.gpu
+
+
+def _iface(X_s, itf, X_m=None):
+    from paper_2202_03933_amd import MortarInterface
+    dev = torch.device("cuda", 0)
+    X_m = itf.master.X if X_m is None else X_m
+    return MortarInterface(torch.from_numpy(X_s), torch.from_numpy(itf.slave.conn), torch.from_numpy(X_m),
+                           torch.from_numpy(itf.master.conn), params=gpu_params(itf), device=dev).setup()
+
+
+def _weights(it, seed):
+    import scipy.sparse as sp
+    ns, nm = it.n_slave_nodes, it.n_master_nodes
+    D = sp.csr_matrix((np.zeros(it.nnz_D), it.D_col.cpu().numpy(), it.D_rowptr.cpu().numpy()), shape=(ns, ns))
+    M = sp.csr_matrix((np.zeros(it.nnz_M), it.M_col.cpu().numpy(), it.M_rowptr.cpu().numpy()), shape=(ns, nm))
+    return tuple(torch.from_numpy(a).to(it.device) for a in csr_weights(D, M, ns, seed))
+
+
+def _run(it, W):
+    f = tuple(t.clone() for t in it.integrate())
+    g = tuple(t.clone() for t in it.backward(*W))
+    torch.cuda.synchronize()
+    return f + g
+
+
+def test_polygons_recomputed_after_update_are_bitwise_equal():
+    itf = synth.interface_config(2, scale=60)
+    print(f"[gpu] {itf.name}: search polygons vs recomputed polygons", flush=True)
+    it = _iface(itf.slave.X, itf)
+    W = _weights(it, 11)
+    a = _run(it, W)
+    it.set_coordinates(itf.slave.X, itf.master.X)  # same values, new arrays: polygons recomputed
+    b = _run(it, W)
+    assert all(torch.equal(x, y) for x, y in zip(a, b))
+    assert it.stats()["n_noconv"] == 0
+
+
+def test_updated_coordinates_match_a_fresh_search():
+    itf = synth.interface_config(1, scale=48)
+    print(f"[gpu] {itf.name}: update versus fresh build", flush=True)
+    rng = np.random.default_rng(5)
+    Xm2 = itf.master.X + 1e-9 * rng.standard_normal(itf.master.X.shape)
+    it = _iface(itf.slave.X, itf)
+    pairs0 = [t.cpu().numpy() for t in it.pairs()]
+    W = _weights(it, 12)
+    it.set_coordinates(itf.slave.X, Xm2)
+    a = _run(it, W)
+    fresh = _iface(itf.slave.X, itf, Xm2)
+    pairs1 = [t.cpu().numpy() for t in fresh.pairs()]
+    assert all(np.array_equal(x, y) for x, y in zip(pairs0, pairs1))  # the move keeps every pair
+    b = _run(fresh, W)
+    assert all(torch.equal(x, y) for x, y in zip(a, b))
+
+
+def test_batch_refreshes_moved_instances():
+    from paper_2202_03933_amd import MortarBatch
+    instances = synth.batched_instances(n_inst=6, max_side=32)
+    print(f"[gpu] batch of {len(instances)} with one instance moved", flush=True)
+    ifaces = [_iface(itf.slave.X, itf) for itf in instances]
+    W = [_weights(it, 20 + k) for k, it in enumerate(ifaces)]
+    b = MortarBatch(ifaces)
+    b.forward()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(9)
+    moved = 4
+    itf = instances[moved]
+    ifaces[moved].set_coordinates(itf.slave.X, itf.master.X + 1e-4 * rng.standard_normal(itf.master.X.shape))
+    outs = b.forward()
+    grads = b.backward(W)
+    torch.cuda.synchronize()
+    for k, it in enumerate(ifaces):
+        ref = _run(it, W[k])
+        got = tuple(outs[k]) + tuple(grads[k])
+        assert all(torch.equal(x, y) for x, y in zip(got, ref)), k
+
+
+def test_batch_rejects_rebuilt_instance():
+    from paper_2202_03933_amd import MortarBatch, MortarError
+    from paper_2202_03933_amd import _capi as C
+    instances = synth.batched_instances(n_inst=3, max_side=20)
+    ifaces = [_iface(itf.slave.X, itf) for itf in instances]
+    b = MortarBatch(ifaces)
+    b.forward()
+    ifaces[1].setup()  # new pair list and pattern behind the batch's back
+    with pytest.raises(MortarError) as e:
+        b.forward()
+    assert e.value.code == C.MT_ESTATE
