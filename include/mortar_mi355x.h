@@ -198,8 +198,11 @@ int mt_integrate(mt_ctx* ctx, double* D_val, double* M_val, double* gap, void* s
  * have not been replaced since (mt_update_coordinates), else recomputes them;
  * the geometry is then differentiated in reverse mode, the inverse maps
  * through the implicit-function derivative, each clip vertex through the
- * two lines it lies on.  Errors: MT_ESTATE,
- * MT_EINVAL, MT_EUNSUPPORTED (dual basis). */
+ * two lines it lies on.  With the dual basis (Sec. 2, A_e = D_e M_e^-1 of
+ * the slave element) the gradient also runs through A_e: the standard-basis
+ * blocks of every pair are recomputed, and the adjoint of A_e is taken
+ * through the inverse of the element's M_e and the Gauss points of D_e and
+ * M_e back to the slave nodes.  Errors: MT_ESTATE, MT_EINVAL. */
 int mt_backward(mt_ctx* ctx, const double* W_D, const double* W_M, const double* w_g,
                 double* gXs, double* gXm, void* stream);
 
@@ -276,7 +279,9 @@ int mt_batch_forward(mt_batch* b, double* const* D_val, double* const* M_val, do
  * Both calls use each instance's current coordinate arrays (replaced with
  * mt_update_coordinates since mt_batch_build: their clip polygons are
  * recomputed first, outside any graph); an instance whose pair list or
- * pattern was rebuilt since mt_batch_build makes them fail with MT_ESTATE. */
+ * pattern was rebuilt since mt_batch_build makes them fail with MT_ESTATE.
+ * mt_batch_backward takes the standard basis only (MT_EUNSUPPORTED for a
+ * batch built with the dual basis; mt_backward takes either). */
 int mt_batch_backward(mt_batch* b, const double* const* W_D, const double* const* W_M,
                       const double* const* w_g, double* const* gXs, double* const* gXm,
                       int use_graph, void* stream);

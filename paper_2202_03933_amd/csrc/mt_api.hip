@@ -602,8 +602,6 @@ extern "C" {
 int mt_backward(mt_ctx* c, const double* W_D, const double* W_M, const double* w_g, double* gXs, double* gXm,
                 void* stream) {
   if (!c) return fail(MT_EINVAL, "mt_backward: null ctx");
-  if (c->params.lm_basis == MT_BASIS_DUAL)
-    return fail(MT_EUNSUPPORTED, "mt_backward: the dual basis has no backward pass");
   if (!c->have_pattern) return fail(MT_ESTATE, "mt_backward: build pairs and pattern first");
   const DeviceMesh& S = c->side[0];
   const DeviceMesh& M = c->side[1];
@@ -631,10 +629,23 @@ int mt_backward(mt_ctx* c, const double* W_D, const double* W_M, const double* w
   }
   {
     PhaseTimer t(c, MT_T_PAIR_BWD, st);
-    MT_HIP(launch_pair_bwd(S, M, kparams(c->params), c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), np, poly,
+    const KParams kp = kparams(c->params);
+    if (kp.dual) {
+      // The dual adjoint needs each pair's standard-basis blocks; the
+      // forward's staging buffer is free again once the values are assembled.
+      KParams ks = kp;
+      ks.dual = 0;
+      MT_HIP(ensure(c->blk, sizeof(double) * 36 * (size_t)std::max<int64_t>(np, 1)));
+      MT_HIP(launch_pair_fwd(S, M, ks, c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), np, poly,
+                             c->blk.as<double>(), np, c->counters.as<Counters>(), st));
+    }
+    MT_HIP(launch_pair_bwd(S, M, kp, c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), np, poly,
                            c->mp_pos.as<int32_t>(),
                            c->posD.as<int32_t>(), S.n_el, c->posM.as<int32_t>(), W_D, W_M, w_g,
                            c->gpair.as<double>(), np, c->counters.as<Counters>(), st));
+    if (kp.dual)
+      MT_HIP(launch_dual_adjoint(S, c->pair_s.as<int32_t>(), np, c->posD.as<int32_t>(), c->posM.as<int32_t>(), W_D,
+                                 W_M, w_g, c->blk.as<double>(), c->gpair.as<double>(), np, st));
   }
   PhaseTimer t(c, MT_T_GRAD_REDUCE, st);
   MT_HIP(launch_grad_slave(c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(), S.n_nodes, c->pair_off.as<int32_t>(),

@@ -34,7 +34,7 @@ __device__ __forceinline__ void gather_weights(int s, int64_t p, int4 csn, const
   wg[3] = w_g[csn.w];
 }
 
-template <int NQ>
+template <int NQ, bool DUAL>
 __global__ __launch_bounds__(BSC) __attribute__((amdgpu_waves_per_eu(2))) void k_pair_bwd(MeshPtrs S, int32_t n_s, MeshPtrs M, KParams kp,
                                                    const int32_t* __restrict__ pair_s,
                                                    const int32_t* __restrict__ pair_m, int64_t n_pairs, PolyBuf poly,
@@ -51,7 +51,7 @@ __global__ __launch_bounds__(BSC) __attribute__((amdgpu_waves_per_eu(2))) void k
     double WD[16], WM[16], wg[4];
     gather_weights(s, p, csn, posD, n_s, posM, stride, W_D, W_M, w_g, WD, WM, wg);
     double Xsb[4][3], Xmb[4][3];
-    pair_backward<NQ>(S, csn, M, load_conn(M.conn, pair_m[p]), gpoly(poly, p), poly.nf[p], kp, WD, WM, wg, Xsb, Xmb,
+    pair_backward<NQ, DUAL>(S, csn, M, load_conn(M.conn, pair_m[p]), gpoly(poly, p), poly.nf[p], kp, WD, WM, wg, Xsb, Xmb,
                       noconv);
     const int64_t q = mpos[p];
 #pragma unroll
@@ -66,7 +66,56 @@ __global__ __launch_bounds__(BSC) __attribute__((amdgpu_waves_per_eu(2))) void k
   if (threadIdx.x == 0 && nc) atomicAdd(&cnt->noconv, nc);
 }
 
+// Dual basis: gradient through the dual coefficients of each pair's slave
+// element, from the pair's standard-basis blocks blk_std[c * stride + p];
+// added to the slave components of gpair.
+__global__ __launch_bounds__(BSC) void k_dual_adjoint(MeshPtrs S, int32_t n_s, const int32_t* __restrict__ pair_s,
+                                                       int64_t n_pairs, const int32_t* __restrict__ posD,
+                                                       const int32_t* __restrict__ posM,
+                                                       const double* __restrict__ W_D, const double* __restrict__ W_M,
+                                                       const double* __restrict__ w_g,
+                                                       const double* __restrict__ blk_std, double* __restrict__ gpair,
+                                                       int64_t stride) {
+  const int64_t p = (int64_t)blockIdx.x * BSC + threadIdx.x;
+  if (p >= n_pairs) return;
+  const int s = pair_s[p];
+  const int4 csn = load_conn(S.conn, s);
+  double WD[16], WM[16], wg[4];
+  gather_weights(s, p, csn, posD, n_s, posM, stride, W_D, W_M, w_g, WD, WM, wg);
+  double Ds[16], Ms[16], gs[4];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    Ds[k] = blk_std[(int64_t)k * stride + p];
+    Ms[k] = blk_std[(int64_t)(16 + k) * stride + p];
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) gs[k] = blk_std[(int64_t)(32 + k) * stride + p];
+  double Xs[4][3];
+  load_nodes(S.x, S.y, S.z, csn, Xs);
+  double Xsb[4][3];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) Xsb[k][d] = gpair[(int64_t)(3 * k + d) * stride + p];
+  dual_adjoint(Xs, WD, WM, wg, Ds, Ms, gs, Xsb);
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) gpair[(int64_t)(3 * k + d) * stride + p] = Xsb[k][d];
+}
+
 }  // namespace
+
+hipError_t launch_dual_adjoint(const DeviceMesh& S, const int32_t* pair_s, int64_t n_pairs, const int32_t* posD,
+                               const int32_t* posM, const double* W_D,
+                               const double* W_M, const double* w_g, const double* blk_std, double* gpair,
+                               int64_t stride, hipStream_t s) {
+  if (n_pairs == 0) return hipSuccess;
+  const MeshPtrs ms{S.x, S.y, S.z, S.conn};
+  k_dual_adjoint<<<(unsigned)((n_pairs + BSC - 1) / BSC), BSC, 0, s>>>(ms, S.n_el, pair_s, n_pairs, posD, posM, W_D,
+                                                                        W_M, w_g, blk_std, gpair, stride);
+  return hipGetLastError();
+}
 
 hipError_t launch_pair_bwd(const DeviceMesh& S, const DeviceMesh& M, const KParams& kp, const int32_t* pair_s,
                            const int32_t* pair_m, int64_t n_pairs, const PolyBuf& poly, const int32_t* mpos,
@@ -76,12 +125,10 @@ hipError_t launch_pair_bwd(const DeviceMesh& S, const DeviceMesh& M, const KPara
   if (n_pairs == 0) return hipSuccess;
   const unsigned nb = xcd_grid((unsigned)((n_pairs + BSC - 1) / BSC));
   const MeshPtrs ms{S.x, S.y, S.z, S.conn}, mm{M.x, M.y, M.z, M.conn};
-  if (kp.rule == 3)
-    k_pair_bwd<3><<<nb, BSC, 0, s>>>(ms, n_s_el, mm, kp, pair_s, pair_m, n_pairs, poly, mpos, posD, posM, W_D, W_M, w_g, gpair,
-                                     stride, cnt);
-  else
-    k_pair_bwd<7><<<nb, BSC, 0, s>>>(ms, n_s_el, mm, kp, pair_s, pair_m, n_pairs, poly, mpos, posD, posM, W_D, W_M, w_g, gpair,
-                                     stride, cnt);
+  auto* k = kp.rule == 3 ? (kp.dual ? k_pair_bwd<3, true> : k_pair_bwd<3, false>)
+                         : (kp.dual ? k_pair_bwd<7, true> : k_pair_bwd<7, false>);
+  hipLaunchKernelGGL(k, dim3(nb), dim3(BSC), 0, s, ms, n_s_el, mm, kp, pair_s, pair_m, n_pairs, poly, mpos, posD, posM,
+                     W_D, W_M, w_g, gpair, stride, cnt);
   return hipGetLastError();
 }
 

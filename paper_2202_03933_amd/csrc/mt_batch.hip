@@ -166,7 +166,7 @@ __global__ __launch_bounds__(BSZ) __attribute__((amdgpu_waves_per_eu(2))) void k
       wg[2] = I.w_g[csn.z];
       wg[3] = I.w_g[csn.w];
       double Xsb[4][3], Xmb[4][3];
-      pair_backward<NQ>(I.S, csn, I.M, load_conn(I.M.conn, I.pair_m[p]), gpoly(I.poly, p), I.poly.nf[p], I.kp, WD,
+      pair_backward<NQ, false>(I.S, csn, I.M, load_conn(I.M.conn, I.pair_m[p]), gpoly(I.poly, p), I.poly.nf[p], I.kp, WD,
                         WM, wg, Xsb, Xmb, noconv);
       const int64_t q = I.mpos[p];
 #pragma unroll

@@ -259,6 +259,13 @@ hipError_t launch_pair_bwd(const DeviceMesh& S, const DeviceMesh& M, const KPara
                            const double* W_D, const double* W_M, const double* w_g, double* gpair,
                            int64_t stride, Counters* cnt, hipStream_t s);
 
+// Dual basis: adds the gradient through each pair's dual coefficients (a
+// function of its slave element) to the slave components of gpair, from the
+// pair's standard-basis blocks blk_std[c * stride + p].
+hipError_t launch_dual_adjoint(const DeviceMesh& S, const int32_t* pair_s, int64_t n_pairs, const int32_t* posD,
+                               const int32_t* posM, const double* W_D, const double* W_M, const double* w_g,
+                               const double* blk_std, double* gpair, int64_t stride, hipStream_t s);
+
 KParams kparams(const mt_params& p);
 // Node incidence of the master side and the pairs-by-master permutation
 // (needed by the backward's master-node reduction); built once per pattern.

@@ -429,7 +429,77 @@ __device__ __forceinline__ void vertex_adjoint(uint8_t lab, double xu, double xv
   add_node_adj(cbm, ib1, b2.u, b2.v);
 }
 
-// Backward of one pair (standard basis): gradient of
+// Adjoint of the projection (u, v, h) = ((X - x0).t1, (X - x0).t2,
+// (X - x0).n0) of the 8 nodes (slave 0..3, master 4..7) and of the slave
+// frame (x0, n0 = g1 x g2 / |g1 x g2|, t1 = g1 / |g1|, t2 = n0 x t1):
+// given nb[k] = (ubar, vbar, hbar) of node k, writes the coordinate
+// gradients Xsb (slave) and Xmb (master).
+__device__ __forceinline__ void projection_adjoint(const double Xs[4][3], const double Xm[4][3],
+                                                   const double nb[8][3], double Xsb[4][3], double Xmb[4][3]) {
+#pragma clang fp contract(fast)
+  double f[12];
+  slave_frame(Xs, f);
+  double x0b[3] = {0, 0, 0}, t1b[3] = {0, 0, 0}, t2b[3] = {0, 0, 0}, n0b[3] = {0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const double* X = k < 4 ? Xs[k] : Xm[k - 4];
+    const double ub = nb[k][0], vbb = nb[k][1], hb = nb[k][2];
+    double* Xb = k < 4 ? Xsb[k] : Xmb[k - 4];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double dd = X[d] - f[d];
+      const double gg = ub * f[6 + d] + vbb * f[9 + d] + hb * f[3 + d];
+      Xb[d] = gg;
+      x0b[d] -= gg;
+      t1b[d] += ub * dd;
+      t2b[d] += vbb * dd;
+      n0b[d] += hb * dd;
+    }
+  }
+  // t2 = n0 x t1
+  const double* n0 = f + 3;
+  const double* t1 = f + 6;
+  n0b[0] += t1[1] * t2b[2] - t1[2] * t2b[1];
+  n0b[1] += t1[2] * t2b[0] - t1[0] * t2b[2];
+  n0b[2] += t1[0] * t2b[1] - t1[1] * t2b[0];
+  t1b[0] += t2b[1] * n0[2] - t2b[2] * n0[1];
+  t1b[1] += t2b[2] * n0[0] - t2b[0] * n0[2];
+  t1b[2] += t2b[0] * n0[1] - t2b[1] * n0[0];
+  // frame from the slave nodes: g1, g2, n = g1 x g2, n0 = n/|n|, t1 = g1/|g1|
+  double g1[3], g2[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    g1[d] = 0.25 * (((Xs[1][d] - Xs[0][d]) + Xs[2][d]) - Xs[3][d]);
+    g2[d] = 0.25 * (((Xs[2][d] + Xs[3][d]) - Xs[0][d]) - Xs[1][d]);
+  }
+  const double nn[3] = {g1[1] * g2[2] - g1[2] * g2[1], g1[2] * g2[0] - g1[0] * g2[2], g1[0] * g2[1] - g1[1] * g2[0]};
+  const double rln = 1.0 / sqrt(nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2]);
+  const double rlg = 1.0 / sqrt(g1[0] * g1[0] + g1[1] * g1[1] + g1[2] * g1[2]);
+  const double tt = t1[0] * t1b[0] + t1[1] * t1b[1] + t1[2] * t1b[2];
+  const double nt = n0[0] * n0b[0] + n0[1] * n0b[1] + n0[2] * n0b[2];
+  double g1b[3], g2b[3], nbv[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    g1b[d] = (t1b[d] - t1[d] * tt) * rlg;
+    nbv[d] = (n0b[d] - n0[d] * nt) * rln;
+  }
+  g1b[0] += g2[1] * nbv[2] - g2[2] * nbv[1];
+  g1b[1] += g2[2] * nbv[0] - g2[0] * nbv[2];
+  g1b[2] += g2[0] * nbv[1] - g2[1] * nbv[0];
+  g2b[0] = nbv[1] * g1[2] - nbv[2] * g1[1];
+  g2b[1] = nbv[2] * g1[0] - nbv[0] * g1[2];
+  g2b[2] = nbv[0] * g1[1] - nbv[1] * g1[0];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const double c0 = 0.25 * x0b[d], c1 = 0.25 * g1b[d], c2 = 0.25 * g2b[d];
+    Xsb[0][d] += c0 - c1 - c2;
+    Xsb[1][d] += c0 + c1 - c2;
+    Xsb[2][d] += c0 + c1 + c2;
+    Xsb[3][d] += c0 - c1 + c2;
+  }
+}
+
+// Backward of one pair: gradient of
 // L = sum WD[j][k] D[j][k] + sum WM[j][l] M[j][l] + sum wg[j] g[j]
 // with respect to the slave (Xsb) and master (Xmb) nodal coordinates, from
 // the stored polygon (nf = count | flip << 7).  Per rule point the
@@ -439,10 +509,10 @@ __device__ __forceinline__ void vertex_adjoint(uint8_t lab, double xu, double xv
 // inverse maps (implicit-function derivative), the clip vertices (line
 // intersections, each vertex once: the fan's pending vertex is carried to the
 // next triangle), the projection and the slave frame.
-template <int NQ>
+template <int NQ, bool DUAL>
 __device__ __forceinline__ void pair_backward(const MeshPtrs& SM, int4 cs, const MeshPtrs& MM, int4 cm,
-                                              const GPoly& P, int nf, const KParams& kp, const double WD[16],
-                                              const double WM[16], const double wg[4], double Xsb[4][3],
+                                              const GPoly& P, int nf, const KParams& kp, const double WD_in[16],
+                                              const double WM_in[16], const double wg_in[4], double Xsb[4][3],
                                               double Xmb[4][3], unsigned& noconv) {
   const int n = nf & 0x7f;
   const bool flip = (nf & 0x80) != 0;
@@ -459,6 +529,31 @@ __device__ __forceinline__ void pair_backward(const MeshPtrs& SM, int4 cs, const
     pair_project(Xs, Xm, f, S, Mn, hs, hm);
     ms = qmap(S);
     mm = qmap(Mn);
+    // dual basis: the blocks are A times the standard ones, so the standard
+    // sweep runs on the weights A^T W (the dependence of A on the slave
+    // nodes is added by dual_adjoint)
+    double WD[16], WM[16], wg[4];
+    if (DUAL) {
+      double A[16];
+      dual_coefficients(S, A);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          WD[4 * m + k] = A[m] * WD_in[k] + A[4 + m] * WD_in[4 + k] + A[8 + m] * WD_in[8 + k] + A[12 + m] * WD_in[12 + k];
+          WM[4 * m + k] = A[m] * WM_in[k] + A[4 + m] * WM_in[4 + k] + A[8 + m] * WM_in[8 + k] + A[12 + m] * WM_in[12 + k];
+        }
+        wg[m] = A[m] * wg_in[0] + A[4 + m] * wg_in[1] + A[8 + m] * wg_in[2] + A[12 + m] * wg_in[3];
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        WD[k] = WD_in[k];
+        WM[k] = WM_in[k];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) wg[k] = wg_in[k];
+    }
     double hts[4], htm[4];
     ht_apply(hs, hts);
     ht_apply(hm, htm);
@@ -598,97 +693,191 @@ __device__ __forceinline__ void pair_backward(const MeshPtrs& SM, int4 cs, const
     vertex_adjoint(P.L(0), x0bu, x0bv, ms, mm, flip, cbs, cbm);
   }
 
-  // node adjoints: Xbar = C (coefficient adjoint), hbar = C htbar
+  // node adjoints: Xbar = C (coefficient adjoint), hbar = C htbar (the 1/4
+  // of C is applied in projection_adjoint)
   {
-#pragma clang fp contract(fast)
-    double Sbu[4], Sbv[4], Mbu[4], Mbv[4], hsb[4], hmb[4];
+    double nb[8][3];
     {
       const double cu[4] = {cbs[0], cbs[2], cbs[4], cbs[6]}, cv[4] = {cbs[1], cbs[3], cbs[5], cbs[7]};
-      h_apply(cu, Sbu);
-      h_apply(cv, Sbv);
+      double u[4], v[4], h[4];
+      h_apply(cu, u);
+      h_apply(cv, v);
+      h_apply(htsb, h);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        nb[k][0] = 0.25 * u[k];
+        nb[k][1] = 0.25 * v[k];
+        nb[k][2] = 0.25 * h[k];
+      }
     }
     {
       const double cu[4] = {cbm[0], cbm[2], cbm[4], cbm[6]}, cv[4] = {cbm[1], cbm[3], cbm[5], cbm[7]};
-      h_apply(cu, Mbu);
-      h_apply(cv, Mbv);
-    }
-    h_apply(htsb, hsb);
-    h_apply(htmb, hmb);
-    // projection (u, v, h) = ((X - x0).t1, (X - x0).t2, (X - x0).n0), on
-    // reloaded nodes and a recomputed frame
-    const int4 cs2{launder(cs.x), launder(cs.y), launder(cs.z), launder(cs.w)};
-    const int4 cm2{launder(cm.x), launder(cm.y), launder(cm.z), launder(cm.w)};
-    double Xs[4][3], Xm[4][3], f[12];
-    load_nodes(SM.x, SM.y, SM.z, cs2, Xs);
-    load_nodes(MM.x, MM.y, MM.z, cm2, Xm);
-    slave_frame(Xs, f);
-    double x0b[3] = {0, 0, 0}, t1b[3] = {0, 0, 0}, t2b[3] = {0, 0, 0}, n0b[3] = {0, 0, 0};
+      double u[4], v[4], h[4];
+      h_apply(cu, u);
+      h_apply(cv, v);
+      h_apply(htmb, h);
 #pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const double* X = k < 4 ? Xs[k] : Xm[k - 4];
-      const double ub = 0.25 * (k < 4 ? Sbu[k] : Mbu[k - 4]);
-      const double vbb = 0.25 * (k < 4 ? Sbv[k] : Mbv[k - 4]);
-      const double hb = 0.25 * (k < 4 ? hsb[k] : hmb[k - 4]);
-      double* Xb = k < 4 ? Xsb[k] : Xmb[k - 4];
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        const double dd = X[d] - f[d];
-        const double gg = ub * f[6 + d] + vbb * f[9 + d] + hb * f[3 + d];
-        Xb[d] = gg;
-        x0b[d] -= gg;
-        t1b[d] += ub * dd;
-        t2b[d] += vbb * dd;
-        n0b[d] += hb * dd;
+      for (int k = 0; k < 4; ++k) {
+        nb[4 + k][0] = 0.25 * u[k];
+        nb[4 + k][1] = 0.25 * v[k];
+        nb[4 + k][2] = 0.25 * h[k];
       }
     }
-    // t2 = n0 x t1
-    const double* n0 = f + 3;
-    const double* t1 = f + 6;
-    n0b[0] += t1[1] * t2b[2] - t1[2] * t2b[1];
-    n0b[1] += t1[2] * t2b[0] - t1[0] * t2b[2];
-    n0b[2] += t1[0] * t2b[1] - t1[1] * t2b[0];
-    t1b[0] += t2b[1] * n0[2] - t2b[2] * n0[1];
-    t1b[1] += t2b[2] * n0[0] - t2b[0] * n0[2];
-    t1b[2] += t2b[0] * n0[1] - t2b[1] * n0[0];
-    // frame from the slave nodes: g1, g2, n = g1 x g2, n0 = n/|n|, t1 = g1/|g1|
-    double g1[3], g2[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      g1[d] = 0.25 * (((Xs[1][d] - Xs[0][d]) + Xs[2][d]) - Xs[3][d]);
-      g2[d] = 0.25 * (((Xs[2][d] + Xs[3][d]) - Xs[0][d]) - Xs[1][d]);
-    }
-    const double nn[3] = {g1[1] * g2[2] - g1[2] * g2[1], g1[2] * g2[0] - g1[0] * g2[2],
-                          g1[0] * g2[1] - g1[1] * g2[0]};
-    const double rln = 1.0 / sqrt(nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2]);
-    const double rlg = 1.0 / sqrt(g1[0] * g1[0] + g1[1] * g1[1] + g1[2] * g1[2]);
-    const double tt = t1[0] * t1b[0] + t1[1] * t1b[1] + t1[2] * t1b[2];
-    const double nt = n0[0] * n0b[0] + n0[1] * n0b[1] + n0[2] * n0b[2];
-    double g1b[3], g2b[3], nb[3];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      g1b[d] = (t1b[d] - t1[d] * tt) * rlg;
-      nb[d] = (n0b[d] - n0[d] * nt) * rln;
-    }
-    g1b[0] += g2[1] * nb[2] - g2[2] * nb[1];
-    g1b[1] += g2[2] * nb[0] - g2[0] * nb[2];
-    g1b[2] += g2[0] * nb[1] - g2[1] * nb[0];
-    g2b[0] = nb[1] * g1[2] - nb[2] * g1[1];
-    g2b[1] = nb[2] * g1[0] - nb[0] * g1[2];
-    g2b[2] = nb[0] * g1[1] - nb[1] * g1[0];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const double c0 = 0.25 * x0b[d], c1 = 0.25 * g1b[d], c2 = 0.25 * g2b[d];
-      Xsb[0][d] += c0 - c1 - c2;
-      Xsb[1][d] += c0 + c1 - c2;
-      Xsb[2][d] += c0 + c1 + c2;
-      Xsb[3][d] += c0 - c1 + c2;
-    }
+    // on reloaded nodes and a recomputed frame
+    const int4 cs2{launder(cs.x), launder(cs.y), launder(cs.z), launder(cs.w)};
+    const int4 cm2{launder(cm.x), launder(cm.y), launder(cm.z), launder(cm.w)};
+    double Xs[4][3], Xm[4][3];
+    load_nodes(SM.x, SM.y, SM.z, cs2, Xs);
+    load_nodes(MM.x, MM.y, MM.z, cm2, Xm);
+    projection_adjoint(Xs, Xm, nb, Xsb, Xmb);
   }
 }
 
 }  // namespace mt
 
 namespace mt {
+
+// Dependence of the dual coefficients on the slave nodes, for one pair:
+// with the pair's standard-basis blocks Ds, Ms, gs and its weights, the
+// loss is L = <WD, A Ds> + <WM, A Ms> + <wg, A gs>, so
+// Abar = WD Ds^T + WM Ms^T + wg gs^T; A = diag(De) Me^-1 (2x2 Gauss on the
+// projected slave quad) gives Debar_j = (Abar Me^-1)_jj and
+// Mebar = -A^T Abar Me^-1, then through the Jacobian determinants at the
+// Gauss points to the projected slave nodes, and through the projection and
+// the frame to the slave coordinates (added to Xsb).
+__device__ __forceinline__ void dual_adjoint(const double Xs[4][3], const double WD[16], const double WM[16],
+                                             const double wg[4], const double Ds[16], const double Ms[16],
+                                             const double gs[4], double Xsb[4][3]) {
+#pragma clang fp contract(fast)
+  double f[12];
+  slave_frame(Xs, f);
+  V2 S[4];
+  double hs[4], As, hmax;
+  slave_setup(Xs, f, S, hs, As, hmax);
+  double Ab[16];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      double a = wg[j] * gs[m];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) a += WD[4 * j + k] * Ds[4 * m + k] + WM[4 * j + k] * Ms[4 * m + k];
+      Ab[4 * j + m] = a;
+    }
+  // forward of the coefficients
+  const double gp = 0.5773502691896257;
+  double Me[16], De[4];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) Me[i] = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) De[i] = 0.0;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const double x1 = a ? gp : -gp, x2 = b ? gp : -gp;
+      double N[4];
+      shape4(x1, x2, N);
+      const double d1[4] = {-0.25 * (1.0 - x2), 0.25 * (1.0 - x2), 0.25 * (1.0 + x2), -0.25 * (1.0 + x2)};
+      const double d2[4] = {-0.25 * (1.0 - x1), -0.25 * (1.0 + x1), 0.25 * (1.0 + x1), 0.25 * (1.0 - x1)};
+      double j00 = 0, j01 = 0, j10 = 0, j11 = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        j00 += d1[k] * S[k].u; j01 += d2[k] * S[k].u;
+        j10 += d1[k] * S[k].v; j11 += d2[k] * S[k].v;
+      }
+      const double det = j00 * j11 - j01 * j10;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        De[j] += N[j] * det;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) Me[j * 4 + k] += N[j] * N[k] * det;
+      }
+    }
+  double inv[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) inv[i] = (i % 5 == 0) ? 1.0 : 0.0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const double r = 1.0 / Me[c * 4 + c];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { Me[c * 4 + k] *= r; inv[c * 4 + k] *= r; }
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      if (rr == c) continue;
+      const double fct = Me[rr * 4 + c];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        Me[rr * 4 + k] -= fct * Me[c * 4 + k];
+        inv[rr * 4 + k] -= fct * inv[c * 4 + k];
+      }
+    }
+  }
+  // B = Abar Me^-1, Debar_j = B_jj, Mebar = -A^T B with A = diag(De) Me^-1
+  double B[16], Mb[16], Db[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      B[4 * j + k] = Ab[4 * j] * inv[k] + Ab[4 * j + 1] * inv[4 + k] + Ab[4 * j + 2] * inv[8 + k] + Ab[4 * j + 3] * inv[12 + k];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) Db[j] = B[5 * j];
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      double a = 0.0;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) a += De[m] * inv[4 * m + j] * B[4 * m + k];
+      Mb[4 * j + k] = -a;
+    }
+  // to the projected slave nodes through det J at the Gauss points
+  double ub[4] = {0, 0, 0, 0}, vb[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const double x1 = a ? gp : -gp, x2 = b ? gp : -gp;
+      double N[4];
+      shape4(x1, x2, N);
+      const double d1[4] = {-0.25 * (1.0 - x2), 0.25 * (1.0 - x2), 0.25 * (1.0 + x2), -0.25 * (1.0 + x2)};
+      const double d2[4] = {-0.25 * (1.0 - x1), -0.25 * (1.0 + x1), 0.25 * (1.0 + x1), 0.25 * (1.0 - x1)};
+      double j00 = 0, j01 = 0, j10 = 0, j11 = 0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        j00 += d1[k] * S[k].u; j01 += d2[k] * S[k].u;
+        j10 += d1[k] * S[k].v; j11 += d2[k] * S[k].v;
+      }
+      double detb = 0.0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        double t = Db[j];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) t += Mb[4 * j + k] * N[k];
+        detb += N[j] * t;
+      }
+      const double jb00 = detb * j11, jb11 = detb * j00, jb01 = -detb * j10, jb10 = -detb * j01;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        ub[k] += jb00 * d1[k] + jb01 * d2[k];
+        vb[k] += jb10 * d1[k] + jb11 * d2[k];
+      }
+    }
+  double nb[8][3];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    nb[k][0] = ub[k];
+    nb[k][1] = vb[k];
+    nb[k][2] = 0.0;
+    nb[4 + k][0] = nb[4 + k][1] = nb[4 + k][2] = 0.0;
+  }
+  double gsb[4][3], gmb[4][3];
+  projection_adjoint(Xs, Xs, nb, gsb, gmb);
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) Xsb[k][d] += gsb[k][d];
+}
 
 // Forward of pair p from its stored polygon: nodes, slave frame, projection,
 // then the quadrature of pair_integrate.  The heights are recomputed after

@@ -38,6 +38,38 @@ def test_gradient_parity_reduced(k, scale):
     assert es <= TOL and em <= TOL
 
 
+# Dual basis (Sec. 2): the gradient also runs through A_e = D_e M_e^-1 of
+# every slave element.
+@pytest.mark.parametrize("k,scale,rule", [(2, 41, 7), (1, 37, 7), (2, 52, 3)])
+def test_dual_gradient_parity_reduced(k, scale, rule):
+    itf = synth.interface_config(k, scale=scale)
+    prm = oracle_params(itf, dual=True, rule=rule)
+    g = gpu_run(itf, dual=True, rule=rule, backward_seed=3100)
+    o = oracle.evaluate(itf, prm)
+    assert np.array_equal(g["pair_s"], o["pair_s"]) and np.array_equal(g["pair_m"], o["pair_m"])
+    gs, gm = oracle_grad(itf, prm, o["pair_s"], o["pair_m"], 3100)
+    es, em = rel_err(g["gXs"], gs), rel_err(g["gXm"], gm)
+    print(f"dual grad rel err slave {es:.2e} master {em:.2e}")
+    assert es <= TOL and em <= TOL
+
+
+def test_dual_gradient_parity_full_wavy_sampled():
+    itf = synth.interface_config(2)
+    prm = oracle_params(itf, dual=True)
+    g = gpu_run(itf, dual=True, backward_seed=3100)
+    o = oracle.evaluate(itf, prm)
+    assert np.array_equal(g["pair_s"], o["pair_s"]) and np.array_equal(g["pair_m"], o["pair_m"])
+    rng = np.random.default_rng(3102)
+    sn = rng.choice(itf.slave.n_nodes, 200, replace=False)
+    mn = rng.choice(itf.master.n_nodes, 200, replace=False)
+    ps, pm = o["pair_s"], o["pair_m"]
+    sel = np.isin(itf.slave.conn[ps], sn).any(1) | np.isin(itf.master.conn[pm], mn).any(1)
+    gs, gm = oracle_grad(itf, prm, ps[sel], pm[sel], 3100)
+    es, em = rel_err(g["gXs"][sn], gs[sn]), rel_err(g["gXm"][mn], gm[mn])
+    print(f"sampled dual grad rel err slave {es:.2e} master {em:.2e} over {sel.sum()} pairs")
+    assert es <= TOL and em <= TOL
+
+
 def test_gradient_parity_full_wavy_sampled():
     itf = synth.interface_config(2)
     prm = oracle_params(itf)
@@ -55,14 +87,14 @@ def test_gradient_parity_full_wavy_sampled():
     assert es <= TOL and em <= TOL
 
 
-def _fd_check(itf, seed=3000, n_coords=200, interior=0.35):
+def _fd_check(itf, seed=3000, n_coords=200, interior=0.35, dual=False):
     from paper_2202_03933_amd import MortarInterface
     from tests.gpu_util import csr_weights, gpu_params
     dev = torch.device("cuda", 0)
     Xs = torch.from_numpy(itf.slave.X).to(dev)
     Xm = torch.from_numpy(itf.master.X).to(dev)
     iface = MortarInterface(Xs, torch.from_numpy(itf.slave.conn), Xm, torch.from_numpy(itf.master.conn),
-                            params=gpu_params(itf), device=dev).setup()
+                            params=gpu_params(itf, dual=dual), device=dev).setup()
     import scipy.sparse as sp
     D, M, gp = iface.integrate()
     Dc = sp.csr_matrix((D.cpu().numpy(), iface.D_col.cpu().numpy(), iface.D_rowptr.cpu().numpy()),
@@ -118,6 +150,10 @@ def test_finite_differences_cylinder():
     _fd_check(synth.interface_config(1), n_coords=60, interior=0.6)
 
 
+def test_finite_differences_dual_cylinder():
+    _fd_check(synth.interface_config(1, scale=48), n_coords=60, interior=0.6, dual=True)
+
+
 def test_autograd_function_matches_backward():
     from paper_2202_03933_amd import MortarFunction, MortarInterface
     from tests.gpu_util import gpu_params
@@ -157,10 +193,14 @@ def test_error_codes():
         iface.integrate(out=(torch.empty(1, dtype=torch.float64, device=dev),) * 3)
     assert e.value.code == C.MT_ESTATE
     iface.setup()
-    z = torch.zeros(max(iface.nnz_M, 1), dtype=torch.float64, device=dev)
+    # the batched backward takes the standard basis only
+    from paper_2202_03933_amd import MortarBatch
+    b = MortarBatch([iface])
+    z = torch.zeros(max(iface.nnz_D, iface.nnz_M, iface.n_slave_nodes), dtype=torch.float64, device=dev)
     with pytest.raises(MortarError) as e:
-        iface.backward(z, z, z)
+        b.backward([(z[:iface.nnz_D], z[:iface.nnz_M], z[:iface.n_slave_nodes])])
     assert e.value.code == C.MT_EUNSUPPORTED
+    b.close()
     # connectivity out of range is reported, not read
     bad = itf.slave.conn.copy()
     bad[3, 2] = itf.slave.n_nodes + 5
