@@ -199,6 +199,46 @@ def bench_batched(reps=5):
     return res
 
 
+def bench_dual(itf, weights, steps, warmup):
+    """The same step with the dual Lagrange multiplier basis (dual-basis
+    forward and backward: the backward adds the recomputed standard blocks
+    and the adjoint of the dual coefficients)."""
+    import torch
+    from paper_2202_03933_amd import MortarInterface, default_params
+    dev = torch.device("cuda", 0)
+    it = MortarInterface(torch.from_numpy(itf.slave.X), torch.from_numpy(itf.slave.conn),
+                         torch.from_numpy(itf.master.X), torch.from_numpy(itf.master.conn),
+                         params=default_params(delta=itf.delta, dual=True), device=dev)
+    it.setup()
+    outs = it.alloc_outputs()
+    grads = (torch.empty(3, itf.slave.n_nodes, dtype=torch.float64, device=dev),
+             torch.empty(3, itf.master.n_nodes, dtype=torch.float64, device=dev))
+
+    def step():
+        it.build_pairs()
+        it.csr_pattern()
+        it.integrate(outs)
+        it.backward(*weights, grads)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    it.timings(reset=True)
+    it.set_timing(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    it.set_timing(False)
+    tim = it.timings(reset=True)
+    n_pairs = it.n_pairs
+    it.close()
+    ms = (t1 - t0) * 1e3 / steps
+    return {"ms_per_step": ms, "pairs_per_s": n_pairs / (ms * 1e-3), "n_pairs": n_pairs,
+            "phase_ms_per_step": {k: v[0] / steps for k, v in tim.items()}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -206,6 +246,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-dual", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (calibrates HBM traffic counters)")
     ap.add_argument("--cpu-sample", type=int, default=16384, help="slave elements in the CPU oracle sample")
@@ -271,6 +312,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    dual = None if args.no_dual else bench_dual(itf, (wD, wM, wg), args.steps, args.warmup)
     batched = None if args.no_batched else bench_batched()
     cpu = None
     if not args.no_cpu_baseline:
@@ -319,6 +361,7 @@ def main():
         "phase_ms_per_step": per_step,
         "roofline": roof,
         "roofline_other_kernels": others,
+        "dual_basis": dual,
         "batched_64_interfaces": batched,
     }
     if cpu and batched:

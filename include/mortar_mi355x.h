@@ -199,8 +199,9 @@ int mt_integrate(mt_ctx* ctx, double* D_val, double* M_val, double* gap, void* s
  * the geometry is then differentiated in reverse mode, the inverse maps
  * through the implicit-function derivative, each clip vertex through the
  * two lines it lies on.  With the dual basis (Sec. 2, A_e = D_e M_e^-1 of
- * the slave element) the gradient also runs through A_e: the standard-basis
- * blocks of every pair are recomputed, and the adjoint of A_e is taken
+ * the slave element) the gradient also runs through A_e, once per slave
+ * element, from the dual blocks of its pairs (those of the last
+ * mt_integrate, recomputed when the coordinates or pairs changed since),
  * through the inverse of the element's M_e and the Gauss points of D_e and
  * M_e back to the slave nodes.  Errors: MT_ESTATE, MT_EINVAL. */
 int mt_backward(mt_ctx* ctx, const double* W_D, const double* W_M, const double* w_g,

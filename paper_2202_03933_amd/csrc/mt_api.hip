@@ -536,6 +536,7 @@ int mt_integrate(mt_ctx* c, double* D_val, double* M_val, double* gap, void* str
     PhaseTimer t(c, MT_T_PAIR_FWD, st);
     MT_HIP(launch_pair_fwd(S, M, kparams(c->params), c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), np, poly,
                            c->blk.as<double>(), np, c->counters.as<Counters>(), st));
+    c->blk_gen = c->coord_gen;
   }
   PhaseTimer t(c, MT_T_ASSEMBLE, st);
   MT_HIP(launch_assemble(c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(), S.n_nodes, c->pair_off.as<int32_t>(),
@@ -630,22 +631,19 @@ int mt_backward(mt_ctx* c, const double* W_D, const double* W_M, const double* w
   {
     PhaseTimer t(c, MT_T_PAIR_BWD, st);
     const KParams kp = kparams(c->params);
-    if (kp.dual) {
-      // The dual adjoint needs each pair's standard-basis blocks; the
-      // forward's staging buffer is free again once the values are assembled.
-      KParams ks = kp;
-      ks.dual = 0;
+    if (kp.dual && c->blk_gen != c->coord_gen) {
+      // the dual adjoint reads each pair's dual blocks: those staged by the
+      // last mt_integrate unless the coordinates or pairs changed since
       MT_HIP(ensure(c->blk, sizeof(double) * 36 * (size_t)std::max<int64_t>(np, 1)));
-      MT_HIP(launch_pair_fwd(S, M, ks, c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), np, poly,
+      MT_HIP(launch_pair_fwd(S, M, kp, c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), np, poly,
                              c->blk.as<double>(), np, c->counters.as<Counters>(), st));
+      c->blk_gen = c->coord_gen;
     }
     MT_HIP(launch_pair_bwd(S, M, kp, c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), np, poly,
                            c->mp_pos.as<int32_t>(),
                            c->posD.as<int32_t>(), S.n_el, c->posM.as<int32_t>(), W_D, W_M, w_g,
-                           c->gpair.as<double>(), np, c->counters.as<Counters>(), st));
-    if (kp.dual)
-      MT_HIP(launch_dual_adjoint(S, c->pair_s.as<int32_t>(), np, c->posD.as<int32_t>(), c->posM.as<int32_t>(), W_D,
-                                 W_M, w_g, c->blk.as<double>(), c->gpair.as<double>(), np, st));
+                           kp.dual ? c->blk.as<double>() : nullptr, c->gpair.as<double>(), np,
+                           c->counters.as<Counters>(), st));
   }
   PhaseTimer t(c, MT_T_GRAD_REDUCE, st);
   MT_HIP(launch_grad_slave(c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(), S.n_nodes, c->pair_off.as<int32_t>(),

@@ -601,6 +601,9 @@ int mt_batch_forward(mt_batch* b, double* const* D_val, double* const* M_val, do
   if (rc) return rc;
   rc = refresh_polygons(b, st);
   if (rc) return rc;
+  // the instances' block staging buffers are overwritten with the batch's
+  // parameters: no longer those of their last mt_integrate
+  for (mt_ctx* c : b->ctxs) c->blk_gen = -1;
   if (use_graph) return run_graph(&b->g_fwd, &b->g_fwd_stream, st, [&]() { return launch_fwd_all(b, st); });
   return launch_fwd_all(b, st);
 }

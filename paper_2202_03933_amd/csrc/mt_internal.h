@@ -159,6 +159,7 @@ struct mt_ctx {
   int64_t pattern_gen = 0;  // counts completed mt_csr_pattern calls
   // forward / backward staging
   mt::Buf blk;             // [36][n_pairs]
+  int64_t blk_gen = -1;    // coord_gen of the blocks in blk (mt_integrate)
   mt::Buf gpair;           // [24][n_pairs]
   mt::Buf mp_keys, mp_vals, mp_off;  // pairs sorted by master element
   mt::Buf mp_pos;          // int32 [n_pairs]: rank of each pair in that order
@@ -253,18 +254,13 @@ hipError_t launch_grad_master(const int32_t* inc_off, const int32_t* inc_list, i
 
 // ---- backward (mt_backward.hip) ----------------------------------------------
 // Backward of every pair: slave gradient components at gpair[c * stride + p],
-// master components at gpair[(12 + c) * stride + mpos[p]].
+// master components at gpair[(12 + c) * stride + mpos[p]].  With the dual
+// basis, blk holds the pairs' dual blocks [36][stride] (the gradient through
+// the dual coefficients needs them); unused otherwise.
 hipError_t launch_pair_bwd(const DeviceMesh& S, const DeviceMesh& M, const KParams& kp, const int32_t* pair_s, const int32_t* pair_m,
                            int64_t n_pairs, const PolyBuf& poly, const int32_t* mpos, const int32_t* posD, int32_t n_s_el, const int32_t* posM,
-                           const double* W_D, const double* W_M, const double* w_g, double* gpair,
-                           int64_t stride, Counters* cnt, hipStream_t s);
-
-// Dual basis: adds the gradient through each pair's dual coefficients (a
-// function of its slave element) to the slave components of gpair, from the
-// pair's standard-basis blocks blk_std[c * stride + p].
-hipError_t launch_dual_adjoint(const DeviceMesh& S, const int32_t* pair_s, int64_t n_pairs, const int32_t* posD,
-                               const int32_t* posM, const double* W_D, const double* W_M, const double* w_g,
-                               const double* blk_std, double* gpair, int64_t stride, hipStream_t s);
+                           const double* W_D, const double* W_M, const double* w_g, const double* blk,
+                           double* gpair, int64_t stride, Counters* cnt, hipStream_t s);
 
 KParams kparams(const mt_params& p);
 // Node incidence of the master side and the pairs-by-master permutation

@@ -737,148 +737,6 @@ __device__ __forceinline__ void pair_backward(const MeshPtrs& SM, int4 cs, const
 
 namespace mt {
 
-// Dependence of the dual coefficients on the slave nodes, for one pair:
-// with the pair's standard-basis blocks Ds, Ms, gs and its weights, the
-// loss is L = <WD, A Ds> + <WM, A Ms> + <wg, A gs>, so
-// Abar = WD Ds^T + WM Ms^T + wg gs^T; A = diag(De) Me^-1 (2x2 Gauss on the
-// projected slave quad) gives Debar_j = (Abar Me^-1)_jj and
-// Mebar = -A^T Abar Me^-1, then through the Jacobian determinants at the
-// Gauss points to the projected slave nodes, and through the projection and
-// the frame to the slave coordinates (added to Xsb).
-__device__ __forceinline__ void dual_adjoint(const double Xs[4][3], const double WD[16], const double WM[16],
-                                             const double wg[4], const double Ds[16], const double Ms[16],
-                                             const double gs[4], double Xsb[4][3]) {
-#pragma clang fp contract(fast)
-  double f[12];
-  slave_frame(Xs, f);
-  V2 S[4];
-  double hs[4], As, hmax;
-  slave_setup(Xs, f, S, hs, As, hmax);
-  double Ab[16];
-#pragma unroll
-  for (int j = 0; j < 4; ++j)
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      double a = wg[j] * gs[m];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) a += WD[4 * j + k] * Ds[4 * m + k] + WM[4 * j + k] * Ms[4 * m + k];
-      Ab[4 * j + m] = a;
-    }
-  // forward of the coefficients
-  const double gp = 0.5773502691896257;
-  double Me[16], De[4];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) Me[i] = 0.0;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) De[i] = 0.0;
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const double x1 = a ? gp : -gp, x2 = b ? gp : -gp;
-      double N[4];
-      shape4(x1, x2, N);
-      const double d1[4] = {-0.25 * (1.0 - x2), 0.25 * (1.0 - x2), 0.25 * (1.0 + x2), -0.25 * (1.0 + x2)};
-      const double d2[4] = {-0.25 * (1.0 - x1), -0.25 * (1.0 + x1), 0.25 * (1.0 + x1), 0.25 * (1.0 - x1)};
-      double j00 = 0, j01 = 0, j10 = 0, j11 = 0;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        j00 += d1[k] * S[k].u; j01 += d2[k] * S[k].u;
-        j10 += d1[k] * S[k].v; j11 += d2[k] * S[k].v;
-      }
-      const double det = j00 * j11 - j01 * j10;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        De[j] += N[j] * det;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) Me[j * 4 + k] += N[j] * N[k] * det;
-      }
-    }
-  double inv[16];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) inv[i] = (i % 5 == 0) ? 1.0 : 0.0;
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    const double r = 1.0 / Me[c * 4 + c];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) { Me[c * 4 + k] *= r; inv[c * 4 + k] *= r; }
-#pragma unroll
-    for (int rr = 0; rr < 4; ++rr) {
-      if (rr == c) continue;
-      const double fct = Me[rr * 4 + c];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        Me[rr * 4 + k] -= fct * Me[c * 4 + k];
-        inv[rr * 4 + k] -= fct * inv[c * 4 + k];
-      }
-    }
-  }
-  // B = Abar Me^-1, Debar_j = B_jj, Mebar = -A^T B with A = diag(De) Me^-1
-  double B[16], Mb[16], Db[4];
-#pragma unroll
-  for (int j = 0; j < 4; ++j)
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      B[4 * j + k] = Ab[4 * j] * inv[k] + Ab[4 * j + 1] * inv[4 + k] + Ab[4 * j + 2] * inv[8 + k] + Ab[4 * j + 3] * inv[12 + k];
-#pragma unroll
-  for (int j = 0; j < 4; ++j) Db[j] = B[5 * j];
-#pragma unroll
-  for (int j = 0; j < 4; ++j)
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      double a = 0.0;
-#pragma unroll
-      for (int m = 0; m < 4; ++m) a += De[m] * inv[4 * m + j] * B[4 * m + k];
-      Mb[4 * j + k] = -a;
-    }
-  // to the projected slave nodes through det J at the Gauss points
-  double ub[4] = {0, 0, 0, 0}, vb[4] = {0, 0, 0, 0};
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const double x1 = a ? gp : -gp, x2 = b ? gp : -gp;
-      double N[4];
-      shape4(x1, x2, N);
-      const double d1[4] = {-0.25 * (1.0 - x2), 0.25 * (1.0 - x2), 0.25 * (1.0 + x2), -0.25 * (1.0 + x2)};
-      const double d2[4] = {-0.25 * (1.0 - x1), -0.25 * (1.0 + x1), 0.25 * (1.0 + x1), 0.25 * (1.0 - x1)};
-      double j00 = 0, j01 = 0, j10 = 0, j11 = 0;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        j00 += d1[k] * S[k].u; j01 += d2[k] * S[k].u;
-        j10 += d1[k] * S[k].v; j11 += d2[k] * S[k].v;
-      }
-      double detb = 0.0;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        double t = Db[j];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) t += Mb[4 * j + k] * N[k];
-        detb += N[j] * t;
-      }
-      const double jb00 = detb * j11, jb11 = detb * j00, jb01 = -detb * j10, jb10 = -detb * j01;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        ub[k] += jb00 * d1[k] + jb01 * d2[k];
-        vb[k] += jb10 * d1[k] + jb11 * d2[k];
-      }
-    }
-  double nb[8][3];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    nb[k][0] = ub[k];
-    nb[k][1] = vb[k];
-    nb[k][2] = 0.0;
-    nb[4 + k][0] = nb[4 + k][1] = nb[4 + k][2] = 0.0;
-  }
-  double gsb[4][3], gmb[4][3];
-  projection_adjoint(Xs, Xs, nb, gsb, gmb);
-#pragma unroll
-  for (int k = 0; k < 4; ++k)
-#pragma unroll
-    for (int d = 0; d < 3; ++d) Xsb[k][d] += gsb[k][d];
-}
-
 // Forward of pair p from its stored polygon: nodes, slave frame, projection,
 // then the quadrature of pair_integrate.  The heights are recomputed after
 // the quadrature from reloaded nodes rather than kept in registers.

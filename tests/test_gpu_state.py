@@ -1,7 +1,8 @@
 """State handling of the HIP path through the C ABI: clip polygons are kept
 from the search and recomputed only after a coordinate update, and both ways
-of obtaining them give bitwise identical results; the batched mode refreshes
-the polygons of instances whose coordinates changed."""
+of obtaining them give bitwise identical results (likewise the pair blocks
+that the dual-basis backward reads); the batched mode refreshes the polygons
+of instances whose coordinates changed."""
 
 import numpy as np
 import pytest
@@ -13,12 +14,12 @@ from tests.gpu_util import csr_weights, gpu_params
 pytestmark = pytest.mark.gpu
 
 
-def _iface(X_s, itf, X_m=None):
+def _iface(X_s, itf, X_m=None, dual=False):
     from paper_2202_03933_amd import MortarInterface
     dev = torch.device("cuda", 0)
     X_m = itf.master.X if X_m is None else X_m
     return MortarInterface(torch.from_numpy(X_s), torch.from_numpy(itf.slave.conn), torch.from_numpy(X_m),
-                           torch.from_numpy(itf.master.conn), params=gpu_params(itf), device=dev).setup()
+                           torch.from_numpy(itf.master.conn), params=gpu_params(itf, dual=dual), device=dev).setup()
 
 
 def _weights(it, seed):
@@ -46,6 +47,26 @@ def test_polygons_recomputed_after_update_are_bitwise_equal():
     b = _run(it, W)
     assert all(torch.equal(x, y) for x, y in zip(a, b))
     assert it.stats()["n_noconv"] == 0
+
+
+def test_dual_backward_without_integrate_recomputes_blocks():
+    # the dual backward reads the pair blocks staged by mt_integrate; after a
+    # coordinate update without a new mt_integrate it recomputes them
+    itf = synth.interface_config(2, scale=44)
+    print(f"[gpu] {itf.name}: dual backward with stale staged blocks", flush=True)
+    rng = np.random.default_rng(8)
+    Xs2 = itf.slave.X + 1e-9 * rng.standard_normal(itf.slave.X.shape)
+    it = _iface(itf.slave.X, itf, dual=True)
+    W = _weights(it, 13)
+    a = _run(it, W)
+    it.set_coordinates(Xs2, itf.master.X)
+    g_stale = tuple(t.clone() for t in it.backward(*W))
+    b = _run(it, W)
+    assert all(torch.equal(x, y) for x, y in zip(g_stale, b[3:]))
+    assert not torch.equal(a[3], b[3])
+    it.set_coordinates(itf.slave.X, itf.master.X)
+    g_back = tuple(t.clone() for t in it.backward(*W))
+    assert all(torch.equal(x, y) for x, y in zip(g_back, a[3:]))
 
 
 def test_updated_coordinates_match_a_fresh_search():
