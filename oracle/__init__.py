@@ -53,6 +53,11 @@ def _lib():
         lib.or_inverse_bilinear.argtypes = [vp, vp, dbl, dbl, vp, vp, vp]
         lib.or_dual_matrix.argtypes = [vp, vp]
         lib.or_dual_matrix.restype = None
+        lib.or_gauss_legendre.argtypes = [ctypes.c_int, vp, vp]
+        lib.or_gauss_legendre.restype = None
+        lib.or_eval_elements.argtypes = [i64, vp, i64, vp, i64, vp, i64, vp, vp, ctypes.c_int, i64, vp, vp, vp, vp]
+        lib.or_count_flops_elements.argtypes = [i64, vp, i64, vp, i64, vp, i64, vp, vp, ctypes.c_int, i64, vp, vp]
+        lib.or_count_flops_elements.restype = ctypes.c_uint64
         _lib_handle = lib
     return _lib_handle
 
@@ -156,6 +161,52 @@ def evaluate(itf, prm=None, method="binned"):
     D, M, g = assemble(itf.slave, itf.master, ps, pm, blocks[keep])
     return {"cand_s": cs, "cand_m": cm, "cand_nverts": nv, "pair_s": ps, "pair_m": pm,
             "nverts": nv[keep], "blocks": blocks[keep], "status": st, "D": D, "M": M, "g": g}
+
+
+def gauss_legendre(n):
+    """Gauss-Legendre points and weights on [-1, 1] (ascending)."""
+    x = np.zeros(n)
+    w = np.zeros(n)
+    _lib().or_gauss_legendre(int(n), _p(x), _p(w))
+    return x, w
+
+
+def eval_elements(slave, master, prm, ps, pm, ng):
+    """Element-based integration: local blocks (n, 36) of the pairs (ps, pm),
+    sorted by slave element, with an ng x ng Gauss rule per slave element;
+    and the status bits per pair (those of its slave element)."""
+    args, keep = _mesh_args(slave, master)
+    ps = np.ascontiguousarray(ps, np.int32)
+    pm = np.ascontiguousarray(pm, np.int32)
+    assert np.all(np.diff(ps) >= 0)
+    blocks = np.zeros((ps.size, 36))
+    st = np.zeros(ps.size, np.int32)
+    rc = _lib().or_eval_elements(*args, ctypes.byref(prm), int(ng), ps.size, _p(ps), _p(pm), _p(blocks), _p(st))
+    if rc < 0:
+        raise ValueError(f"element rule {ng} out of range 1..8")
+    return blocks, st
+
+
+def evaluate_elements(itf, ng, prm=None, pairs=None):
+    """Element-based D, M and gap on the pair list of the segment-based
+    search (the pairs whose clip polygon is a segment)."""
+    if prm is None:
+        prm = params(delta=itf.delta)
+    if pairs is None:
+        r = evaluate(itf, prm)
+        pairs = (r["pair_s"], r["pair_m"])
+    ps, pm = pairs
+    blocks, st = eval_elements(itf.slave, itf.master, prm, ps, pm, ng)
+    D, M, g = assemble(itf.slave, itf.master, ps, pm, blocks)
+    return {"pair_s": ps, "pair_m": pm, "blocks": blocks, "status": st, "D": D, "M": M, "g": g}
+
+
+def count_flops_elements(slave, master, prm, ps, pm, ng):
+    """Counted flops of the element-based integration of the pairs (ps, pm)."""
+    args, keep = _mesh_args(slave, master)
+    ps = np.ascontiguousarray(ps, np.int32)
+    pm = np.ascontiguousarray(pm, np.int32)
+    return int(_lib().or_count_flops_elements(*args, ctypes.byref(prm), int(ng), ps.size, _p(ps), _p(pm)))
 
 
 def pair_grads(slave, master, prm, ps, pm, w36):

@@ -21,6 +21,9 @@
 //    Gauss rule.
 //  * standard or dual (biorthogonal) Lagrange multiplier basis (same section,
 //    after eq. (AnsatzDiscretizationLagrangeMult)).
+//  * element-based integration, the alternative to the segments of Alg. 1
+//    that the same section names (a Gauss product rule on the whole slave
+//    element, each point assigned to the master it projects into).
 //  * exact derivatives by forward-mode dual numbers over the 24 nodal
 //    coordinates of a pair (the linearisation the paper requires in every
 //    nonlinear iteration, Sec. "Introduction" after Fig. 1).
@@ -530,6 +533,138 @@ void eval_pair(const T Xs[4][3], const T Xm[4][3], const Params& prm,
   }
 }
 
+// ------------------------------------------------ element-based integration
+
+// Gauss-Legendre points and weights on [-1, 1] in ascending order, exact for
+// polynomials up to degree 2n - 1.  The points are the roots of the Legendre
+// polynomial P_n: root i of the upper half by Newton's method from
+// cos(pi (i + 3/4) / (n + 1/2)), mirrored for the lower half, 0 in the middle
+// for odd n.  P_n and P_n' come from the recurrence (k + 1) P_{k+1} =
+// (2k + 1) x P_k - k P_{k-1} and P_n' = n (x P_n - P_{n-1}) / (x^2 - 1); the
+// weight is 2 / ((1 - x^2) P_n'(x)^2).
+void legendre(int n, double z, double& pn, double& dpn) {
+  double p0 = 1.0, p1 = z;
+  for (int k = 1; k < n; ++k) {
+    const double p2 = ((2.0 * k + 1.0) * z * p1 - k * p0) / (k + 1.0);
+    p0 = p1;
+    p1 = p2;
+  }
+  pn = p1;
+  dpn = n * (z * p1 - p0) / (z * z - 1.0);
+}
+
+void gauss_legendre(int n, double* x, double* w) {
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    double z = (2 * i + 1 == n) ? 0.0 : std::cos(std::acos(-1.0) * (i + 0.75) / (n + 0.5));
+    double pn, dp;
+    for (int it = 0; it < 100 && z != 0.0; ++it) {
+      legendre(n, z, pn, dp);
+      const double dz = pn / dp;
+      z -= dz;
+      if (std::fabs(dz) <= 1e-16) break;
+    }
+    legendre(n, z, pn, dp);
+    const double wi = 2.0 / ((1.0 - z * z) * dp * dp);
+    x[i] = -z;
+    w[i] = wi;
+    x[n - 1 - i] = z;
+    w[n - 1 - i] = wi;
+  }
+}
+
+// Element-based integration of one slave element (Sec. "Evaluation of mortar
+// integrals": no clipping or triangulation, a higher-order rule over the
+// whole slave element).  The paper gives no formulas for it; our reading:
+//  * the rule is the ng x ng Gauss-Legendre product rule in the parameter
+//    space of the projected slave quad, with the measure det J of that map
+//    (area in the auxiliary plane, the measure of the segment-based
+//    integrals, so that both converge to the same values);
+//  * a point P = sum_k N_k(xi) S_k belongs to the first of the element's
+//    pairs (pair order, i.e. ascending master) whose counter-clockwise
+//    projected master quad contains it, by the clip's side test on the
+//    closed half-planes of its four edges; points in no master are dropped;
+//  * the master coordinates of P come from the inverse bilinear map and the
+//    integrands are those of eval_pair.
+// XmK holds the K masters' nodes (12 per master); blk receives 36 values per
+// pair (layout of eval_pair's D, M, g).  Returns status bits.
+template <class T>
+int eval_element(const T Xs[4][3], int K, const T* XmK, const Params& prm, int ng, const double* gx,
+                 const double* gw, T* blk) {
+  int status = 0;
+  for (int i = 0; i < 36 * K; ++i) blk[i] = 0.0;
+  T x0[3], n0[3], t1[3], t2[3];
+  slave_frame(Xs, x0, n0, t1, t2);
+  P2<T> S[4];
+  T hs[4];
+  for (int k = 0; k < 4; ++k) project(Xs[k], x0, n0, t1, t2, S[k], hs[k]);
+  T A[16];
+  if (prm.dual) dual_coefficients(S, A);
+  std::vector<P2<T>> Mn(4 * K), Mo(4 * K);
+  std::vector<T> hm(4 * K);
+  for (int i = 0; i < K; ++i) {
+    for (int k = 0; k < 4; ++k) {
+      T X[3] = {XmK[12 * i + 3 * k], XmK[12 * i + 3 * k + 1], XmK[12 * i + 3 * k + 2]};
+      project(X, x0, n0, t1, t2, Mn[4 * i + k], hm[4 * i + k]);
+    }
+    const T Am = fan_area(4, &Mn[4 * i]);
+    for (int k = 0; k < 4; ++k) Mo[4 * i + k] = Mn[4 * i + k];
+    if (val(Am) < 0.0) { Mo[4 * i + 1] = Mn[4 * i + 3]; Mo[4 * i + 3] = Mn[4 * i + 1]; }
+  }
+  for (int b = 0; b < ng; ++b)
+    for (int a = 0; a < ng; ++a) {
+      const T x1 = gx[a], x2 = gx[b];
+      T Ns[4], d1[4], d2[4];
+      shape(x1, x2, Ns, d1, d2);
+      P2<T> P;
+      P.u = ((Ns[0] * S[0].u + Ns[1] * S[1].u) + Ns[2] * S[2].u) + Ns[3] * S[3].u;
+      P.v = ((Ns[0] * S[0].v + Ns[1] * S[1].v) + Ns[2] * S[2].v) + Ns[3] * S[3].v;
+      int owner = -1;
+      for (int i = 0; i < K && owner < 0; ++i) {
+        bool inside = true;
+        for (int l = 0; l < 4; ++l) {
+          const P2<T>& ea = Mo[4 * i + l];
+          const P2<T>& eb = Mo[4 * i + (l + 1) % 4];
+          const T c = (eb.u - ea.u) * (P.v - ea.v) - (eb.v - ea.v) * (P.u - ea.u);
+          if (!(val(c) >= 0.0)) inside = false;
+        }
+        if (inside) owner = i;
+      }
+      if (owner < 0) continue;
+      T j00 = 0.0, j01 = 0.0, j10 = 0.0, j11 = 0.0;
+      for (int k = 0; k < 4; ++k) {
+        j00 = j00 + d1[k] * S[k].u; j01 = j01 + d2[k] * S[k].u;
+        j10 = j10 + d1[k] * S[k].v; j11 = j11 + d2[k] * S[k].v;
+      }
+      const T wJ = (gw[a] * gw[b]) * (j00 * j11 - j01 * j10);
+      T xm1, xm2;
+      status |= inverse_bilinear(&Mn[4 * owner], P, prm, xm1, xm2);
+      T Nm[4], e1[4], e2[4];
+      shape(xm1, xm2, Nm, e1, e2);
+      T Phi[4];
+      for (int j = 0; j < 4; ++j) {
+        if (prm.dual) {
+          Phi[j] = 0.0;
+          for (int k = 0; k < 4; ++k) Phi[j] = Phi[j] + A[j * 4 + k] * Ns[k];
+        } else {
+          Phi[j] = Ns[j];
+        }
+      }
+      T gap = 0.0;
+      for (int k = 0; k < 4; ++k) gap = gap + Nm[k] * hm[4 * owner + k];
+      for (int k = 0; k < 4; ++k) gap = gap - Ns[k] * hs[k];
+      T* o = blk + 36 * owner;
+      for (int j = 0; j < 4; ++j) {
+        const T wp = wJ * Phi[j];
+        for (int k = 0; k < 4; ++k) {
+          o[j * 4 + k] = o[j * 4 + k] + wp * Ns[k];
+          o[16 + j * 4 + k] = o[16 + j * 4 + k] + wp * Nm[k];
+        }
+        o[32 + j] = o[32 + j] + wp * gap;
+      }
+    }
+  return status;
+}
+
 // ---------------------------------------------------------------- search
 
 struct Box { double lo[3], hi[3]; };
@@ -846,6 +981,72 @@ int or_pair_grads(int64_t ns_nodes, const double* Xs, int64_t ns_el, const int32
     any |= o.status;
   }
   return any;
+}
+
+// Gauss-Legendre rule on [-1, 1] (for tests).
+void or_gauss_legendre(int n, double* x, double* w) { gauss_legendre(n, x, w); }
+
+// Element-based integration over the pairs (ps, pm), sorted by slave element:
+// the element's pairs are taken together (eval_element) with an ng x ng rule,
+// 1 <= ng <= 8.  Writes 36 values per pair (layout of or_eval_candidates);
+// status (optional) per pair: the status bits of its slave element.
+// Returns the union of the status bits, or -1 for a bad ng.
+int or_eval_elements(int64_t ns_nodes, const double* Xs, int64_t ns_el, const int32_t* Cs,
+                     int64_t nm_nodes, const double* Xm, int64_t nm_el, const int32_t* Cm,
+                     const OrParams* op, int ng, int64_t n, const int32_t* ps, const int32_t* pm,
+                     double* blocks, int32_t* status) {
+  if (ng < 1 || ng > 8) return -1;
+  MeshView S{ns_nodes, Xs, ns_el, Cs}, M{nm_nodes, Xm, nm_el, Cm};
+  const Params prm = to_params(op);
+  double gx[8], gw[8];
+  gauss_legendre(ng, gx, gw);
+  int any = 0;
+  for (int64_t i0 = 0; i0 < n;) {
+    int64_t i1 = i0;
+    while (i1 < n && ps[i1] == ps[i0]) ++i1;
+    const int K = (int)(i1 - i0);
+    double xs[4][3];
+    std::vector<double> xm(12 * K);
+    for (int k = 0; k < 4; ++k)
+      for (int d = 0; d < 3; ++d) xs[k][d] = S.X[3 * S.C[4 * ps[i0] + k] + d];
+    for (int i = 0; i < K; ++i)
+      for (int k = 0; k < 4; ++k)
+        for (int d = 0; d < 3; ++d) xm[12 * i + 3 * k + d] = M.X[3 * M.C[4 * pm[i0 + i] + k] + d];
+    const int st = eval_element(xs, K, xm.data(), prm, ng, gx, gw, blocks + 36 * i0);
+    if (status)
+      for (int64_t i = i0; i < i1; ++i) status[i] = st;
+    any |= st;
+    i0 = i1;
+  }
+  return any;
+}
+
+// Counted floating-point operations of the element-based integration of the
+// pairs (ps, pm), sorted by slave element, with an ng x ng rule.
+uint64_t or_count_flops_elements(int64_t ns_nodes, const double* Xs, int64_t ns_el, const int32_t* Cs,
+                                 int64_t nm_nodes, const double* Xm, int64_t nm_el, const int32_t* Cm,
+                                 const OrParams* op, int ng, int64_t n, const int32_t* ps, const int32_t* pm) {
+  if (ng < 1 || ng > 8) return 0;
+  MeshView S{ns_nodes, Xs, ns_el, Cs}, M{nm_nodes, Xm, nm_el, Cm};
+  const Params prm = to_params(op);
+  double gx[8], gw[8];
+  gauss_legendre(ng, gx, gw);
+  g_flops = 0;
+  for (int64_t i0 = 0; i0 < n;) {
+    int64_t i1 = i0;
+    while (i1 < n && ps[i1] == ps[i0]) ++i1;
+    const int K = (int)(i1 - i0);
+    Cnt xs[4][3];
+    std::vector<Cnt> xm(12 * K), blk(36 * K);
+    for (int k = 0; k < 4; ++k)
+      for (int d = 0; d < 3; ++d) xs[k][d] = S.X[3 * S.C[4 * ps[i0] + k] + d];
+    for (int i = 0; i < K; ++i)
+      for (int k = 0; k < 4; ++k)
+        for (int d = 0; d < 3; ++d) xm[12 * i + 3 * k + d] = M.X[3 * M.C[4 * pm[i0 + i] + k] + d];
+    eval_element(xs, K, xm.data(), prm, ng, gx, gw, blk.data());
+    i0 = i1;
+  }
+  return g_flops;
 }
 
 // Counted floating-point operations of the pair evaluation over a list of
