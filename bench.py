@@ -10,7 +10,10 @@ along the normal by U[-1e-3, 1e-3], delta = 1.25e-3.
 
 Prints one JSON line: value = pairs / (wall time of one step), plus the
 roofline of the dominant kernel (from the library's HIP-event phase timers
-over the timed steps) and the CPU oracle timed on a bounded sample.
+over the timed steps) and the CPU oracle timed on a bounded sample.  Extra
+objects: the same step with the dual basis, element-based integration of the
+same interface (n x n Gauss points per slave element, for several n: time
+and difference from the segment-based values), and 64 batched interfaces.
 """
 
 import argparse
@@ -28,6 +31,8 @@ HBM_PEAK_GBS = 8000.0
 # Jacobian at the solution (8), transposed 2x2 solve (12), node adjoints (16),
 # point adjoint (2).
 IFT_FLOPS = 38
+# Gauss points per direction of the element-based integration variants
+ELEM_RULES = (2, 4, 8)
 
 # Library phase timer of a single-kernel phase -> (kernel, source files whose
 # hash identifies the kernel version, committed traffic summary).
@@ -126,7 +131,14 @@ def cpu_baseline(itf, n_slave_el_sample, seed=3000):
         nb = max(1, int(bk.sum()))
         batched_flops[g] = {"fwd": (q[1] - q[0]) / nb, "bwd": (q[1] - q[0] + q[2] - q[4] + IFT_FLOPS * q[3]) / nb,
                             "fwd_full": q[1] / nb}
+    # element-based integration: flops per slave element (every element with
+    # a pair among the first 2048 of the sample)
+    esel = ps < 2048
+    n_e = max(1, np.unique(ps[esel]).size)
+    elem_flops = {ng: oracle.count_flops_elements(sub, itf.master, prm, ps[esel], pm[esel], ng) / n_e
+                  for ng in ELEM_RULES}
     return {"pairs": int(ps.size), "t_fwd": t_fwd, "t_all": t_all, "batched_flops": batched_flops,
+            "elem_flops_per_element": elem_flops,
             "flops_per_unit": {"pair_poly": f_cp / npp,
                                "pair_fwd": (f_pair - f_cp) / npp,
                                "pair_bwd": (f_pair - f_cp + f_adj - f_cadj + IFT_FLOPS * n_inv) / npp},
@@ -199,6 +211,49 @@ def bench_batched(reps=5):
     return res
 
 
+def bench_elements(itf, seg_outs, steps, warmup):
+    """Element-based integration (an n x n Gauss rule on each slave element,
+    no clipping) on the same interface for the rules in ELEM_RULES: time of
+    the forward integration and assembly, and the relative Frobenius
+    difference of D, M and the gap from the segment-based values."""
+    import numpy as np
+    import torch
+    from paper_2202_03933_amd import MortarInterface, default_params
+    dev = torch.device("cuda", 0)
+    out = {}
+    for ng in ELEM_RULES:
+        it = MortarInterface(torch.from_numpy(itf.slave.X), torch.from_numpy(itf.slave.conn),
+                             torch.from_numpy(itf.master.X), torch.from_numpy(itf.master.conn),
+                             params=default_params(delta=itf.delta, element_rule=ng), device=dev)
+        it.setup()
+        outs = it.alloc_outputs()
+        for _ in range(warmup):
+            it.integrate(outs)
+        torch.cuda.synchronize()
+        it.timings(reset=True)
+        it.set_timing(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            it.integrate(outs)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        it.set_timing(False)
+        tim = it.timings(reset=True)
+        n_pairs = it.n_pairs
+        n_el = int(np.unique(it.pairs()[0].cpu().numpy()).size)
+        err = {}
+        for name, a, b in zip(("D", "M", "g"), outs, seg_outs):
+            assert a.shape == b.shape
+            err[name] = (torch.linalg.norm(a - b) / torch.linalg.norm(b)).item()
+        it.close()
+        ms = (t1 - t0) * 1e3 / steps
+        out[str(ng)] = {"integrate_ms": ms, "pairs_per_s": n_pairs / (ms * 1e-3), "slave_elements": n_el,
+                        "k_elem_fwd_ms": tim["pair_fwd"][0] / max(1, tim["pair_fwd"][1]),
+                        "assemble_ms": tim["assemble"][0] / max(1, tim["assemble"][1]),
+                        "rel_diff_vs_segment": err}
+    return out
+
+
 def bench_dual(itf, weights, steps, warmup):
     """The same step with the dual Lagrange multiplier basis (dual-basis
     forward and backward: the backward adds the recomputed standard blocks
@@ -247,6 +302,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-dual", action="store_true")
+    ap.add_argument("--no-elements", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (calibrates HBM traffic counters)")
     ap.add_argument("--cpu-sample", type=int, default=16384, help="slave elements in the CPU oracle sample")
@@ -313,6 +369,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     dual = None if args.no_dual else bench_dual(itf, (wD, wM, wg), args.steps, args.warmup)
+    elements = None if args.no_elements else bench_elements(itf, outs, args.steps, args.warmup)
     batched = None if args.no_batched else bench_batched()
     cpu = None
     if not args.no_cpu_baseline:
@@ -362,6 +419,7 @@ def main():
         "roofline": roof,
         "roofline_other_kernels": others,
         "dual_basis": dual,
+        "element_based": elements,
         "batched_64_interfaces": batched,
     }
     if cpu and batched:
@@ -372,6 +430,18 @@ def main():
             fl = sum(batched["pairs_by_geometry"][g] * bf[g][k] for g in bf)
             for mode in ("batched_graph", "per_interface"):
                 batched[f"{k}_fp64_frac_{mode}"] = fl / (batched[f"{k}_ms_{mode}"] * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS
+    if cpu and elements:
+        # element-based kernel against FP64 peak: oracle-counted flops per
+        # slave element x elements / launch time
+        elements["segment_integrate_ms"] = per_step["pair_fwd"] + per_step["assemble"]
+        for ng in ELEM_RULES:
+            e = elements[str(ng)]
+            fl = cpu["elem_flops_per_element"][ng]
+            ach = fl * e["slave_elements"] / (e["k_elem_fwd_ms"] * 1e-3) / 1e12
+            e["roofline"] = {"bound": "alu", "kernel": "k_elem_fwd", "achieved": ach,
+                             "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                             "frac": ach / FP64_VECTOR_PEAK_TFLOPS, "flops_per_unit": fl,
+                             "unit_kind": "slave element", "units_per_launch": e["slave_elements"]}
     if cpu:
         # whole step as a fraction of FP64 peak (pair kernels' algorithmic flops over the step time)
         fpu = cpu["flops_per_unit"]

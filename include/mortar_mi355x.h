@@ -74,7 +74,8 @@ typedef struct mt_params {
   double eps_a;        /* relative area below which an overlap is not a segment */
   double newton_tol;   /* inverse bilinear map: stop when max |d xi| <= tol */
   int32_t newton_maxit;
-  int32_t reserved;
+  int32_t element_rule; /* 0: segment-based integration (Alg. 1); n = 1..8: element-based,
+                           n x n Gauss-Legendre points per slave element (see mt_integrate) */
 } mt_params;
 
 /* Counters of the last build / integrate / backward on a context. */
@@ -184,6 +185,13 @@ int mt_get_csr(mt_ctx* ctx, int32_t* D_rowptr, int32_t* D_col, int32_t* M_rowptr
  * g_e[j] = int Phi_j (h_master - h_slave) (heights along n0) are summed into
  * D_val[nnz_D], M_val[nnz_M] (CSR order of mt_csr_pattern) and gap[n_s_nodes]
  * (zero where no pair touches a node).  Output arrays are overwritten.
+ * With params.element_rule = n > 0, element-based integration instead (the
+ * cheaper, less accurate alternative the same section names): no clip
+ * polygons; an n x n Gauss-Legendre product rule on each slave element in
+ * the parameter space of its projected quad, each point taken by the first
+ * pair of its element (ascending master) whose projected master quad
+ * contains it (closed edges), points in no master dropped; same blocks,
+ * pattern and assembly.
  * Does not synchronise; quadrature points whose inverse map did not converge
  * are counted in mt_stats.n_noconv.  Errors: MT_ESTATE (no pattern),
  * MT_EINVAL (null outputs). */
@@ -203,7 +211,8 @@ int mt_integrate(mt_ctx* ctx, double* D_val, double* M_val, double* gap, void* s
  * element, from the dual blocks of its pairs (those of the last
  * mt_integrate, recomputed when the coordinates or pairs changed since),
  * through the inverse of the element's M_e and the Gauss points of D_e and
- * M_e back to the slave nodes.  Errors: MT_ESTATE, MT_EINVAL. */
+ * M_e back to the slave nodes.  Errors: MT_ESTATE, MT_EINVAL,
+ * MT_EUNSUPPORTED (element-based integration: forward only). */
 int mt_backward(mt_ctx* ctx, const double* W_D, const double* W_M, const double* w_g,
                 double* gXs, double* gXm, void* stream);
 
@@ -268,7 +277,9 @@ int mt_batch_destroy(mt_batch* b);
 /* Add a context; returns its instance index in *index (host).  The context
  * must outlive the batch.  Errors: MT_EINVAL (other device), MT_ESTATE. */
 int mt_batch_add(mt_batch* b, mt_ctx* ctx, int32_t* index);
-/* Build the work queue and per-instance tables.  `tuning` may be NULL.  Synchronises. */
+/* Build the work queue and per-instance tables.  `tuning` may be NULL.  Synchronises.
+ * Errors: MT_EINVAL (instances differ in rule or basis), MT_EUNSUPPORTED
+ * (an instance set to element-based integration). */
 int mt_batch_build(mt_batch* b, const mt_batch_tuning* tuning, void* stream);
 /* Forward for every instance: D_val[i], M_val[i], gap[i] are host arrays of
  * K device pointers (outputs as for mt_integrate).  use_graph != 0 captures

@@ -579,10 +579,16 @@ void gauss_legendre(int n, double* x, double* w) {
 //    space of the projected slave quad, with the measure det J of that map
 //    (area in the auxiliary plane, the measure of the segment-based
 //    integrals, so that both converge to the same values);
-//  * a point P = sum_k N_k(xi) S_k belongs to the first of the element's
-//    pairs (pair order, i.e. ascending master) whose counter-clockwise
-//    projected master quad contains it, by the clip's side test on the
-//    closed half-planes of its four edges; points in no master are dropped;
+//  * the point of the auxiliary plane at xi is the bilinear map of the
+//    projected slave quad written in monomial form,
+//    P = ((c + e1 xi1) + e2 xi2) + f (xi1 xi2) with c = (S0 + S1 + S2 + S3)/4,
+//    e1 = (S1 - S0 + S2 - S3)/4, e2 = (S2 - S1 + S3 - S0)/4,
+//    f = (S0 - S1 + S2 - S3)/4 (the same map as sum_k N_k(xi) S_k);
+//  * P belongs to the first of the element's pairs (pair order, i.e.
+//    ascending master) whose counter-clockwise projected master quad
+//    contains it: inside the closed bounding box of the quad and on the
+//    closed inner side of its four edges by the clip's side test; points in
+//    no master are dropped;
 //  * the master coordinates of P come from the inverse bilinear map and the
 //    integrands are those of eval_pair.
 // XmK holds the K masters' nodes (12 per master); blk receives 36 values per
@@ -610,17 +616,32 @@ int eval_element(const T Xs[4][3], int K, const T* XmK, const Params& prm, int n
     for (int k = 0; k < 4; ++k) Mo[4 * i + k] = Mn[4 * i + k];
     if (val(Am) < 0.0) { Mo[4 * i + 1] = Mn[4 * i + 3]; Mo[4 * i + 3] = Mn[4 * i + 1]; }
   }
+  P2<T> c, e1, e2, f;
+  c.u = 0.25 * ((S[0].u + S[1].u) + (S[2].u + S[3].u));
+  c.v = 0.25 * ((S[0].v + S[1].v) + (S[2].v + S[3].v));
+  e1.u = 0.25 * ((S[1].u - S[0].u) + (S[2].u - S[3].u));
+  e1.v = 0.25 * ((S[1].v - S[0].v) + (S[2].v - S[3].v));
+  e2.u = 0.25 * ((S[2].u - S[1].u) + (S[3].u - S[0].u));
+  e2.v = 0.25 * ((S[2].v - S[1].v) + (S[3].v - S[0].v));
+  f.u = 0.25 * ((S[0].u - S[1].u) + (S[2].u - S[3].u));
+  f.v = 0.25 * ((S[0].v - S[1].v) + (S[2].v - S[3].v));
   for (int b = 0; b < ng; ++b)
     for (int a = 0; a < ng; ++a) {
       const T x1 = gx[a], x2 = gx[b];
       T Ns[4], d1[4], d2[4];
       shape(x1, x2, Ns, d1, d2);
       P2<T> P;
-      P.u = ((Ns[0] * S[0].u + Ns[1] * S[1].u) + Ns[2] * S[2].u) + Ns[3] * S[3].u;
-      P.v = ((Ns[0] * S[0].v + Ns[1] * S[1].v) + Ns[2] * S[2].v) + Ns[3] * S[3].v;
+      P.u = ((c.u + e1.u * x1) + e2.u * x2) + f.u * (x1 * x2);
+      P.v = ((c.v + e1.v * x1) + e2.v * x2) + f.v * (x1 * x2);
       int owner = -1;
       for (int i = 0; i < K && owner < 0; ++i) {
         bool inside = true;
+        double lo_u = val(Mo[4 * i].u), hi_u = lo_u, lo_v = val(Mo[4 * i].v), hi_v = lo_v;
+        for (int k = 1; k < 4; ++k) {
+          lo_u = std::min(lo_u, val(Mo[4 * i + k].u)); hi_u = std::max(hi_u, val(Mo[4 * i + k].u));
+          lo_v = std::min(lo_v, val(Mo[4 * i + k].v)); hi_v = std::max(hi_v, val(Mo[4 * i + k].v));
+        }
+        if (val(P.u) < lo_u || val(P.u) > hi_u || val(P.v) < lo_v || val(P.v) > hi_v) inside = false;
         for (int l = 0; l < 4; ++l) {
           const P2<T>& ea = Mo[4 * i + l];
           const P2<T>& eb = Mo[4 * i + (l + 1) % 4];

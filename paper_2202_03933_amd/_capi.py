@@ -22,7 +22,7 @@ _NAMES = {0: "MT_OK", 1: "MT_EINVAL", 2: "MT_ECAPACITY", 3: "MT_EHIP", 4: "MT_EN
 class mt_params(ctypes.Structure):
     _fields_ = [("delta", ctypes.c_double), ("bin_size", ctypes.c_double), ("lm_basis", ctypes.c_int32),
                 ("rule", ctypes.c_int32), ("eps_d", ctypes.c_double), ("eps_a", ctypes.c_double),
-                ("newton_tol", ctypes.c_double), ("newton_maxit", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("newton_tol", ctypes.c_double), ("newton_maxit", ctypes.c_int32), ("element_rule", ctypes.c_int32)]
 
 
 class mt_stats(ctypes.Structure):

@@ -117,6 +117,7 @@ KParams kparams(const mt_params& p) {
   k.newton_maxit = p.newton_maxit;
   k.dual = p.lm_basis == MT_BASIS_DUAL ? 1 : 0;
   k.rule = p.rule;
+  k.elem = p.element_rule;
   return k;
 }
 
@@ -184,6 +185,8 @@ int mt_set_params(mt_ctx* c, const mt_params* p) {
   if (p->rule != 3 && p->rule != 7) return fail(MT_EINVAL, "mt_set_params: rule must be 3 or 7");
   if (p->lm_basis != MT_BASIS_STANDARD && p->lm_basis != MT_BASIS_DUAL)
     return fail(MT_EINVAL, "mt_set_params: lm_basis");
+  if (p->element_rule < 0 || p->element_rule > 8)
+    return fail(MT_EINVAL, "mt_set_params: element_rule must be 0 (segments) or 1..8");
   if (!(p->delta >= 0) || !(p->bin_size >= 0) || !(p->eps_d >= 0) || !(p->eps_a >= 0) || !(p->newton_tol > 0) ||
       p->newton_maxit < 1)
     return fail(MT_EINVAL, "mt_set_params: negative or invalid tolerance");
@@ -527,12 +530,19 @@ int mt_integrate(mt_ctx* c, double* D_val, double* M_val, double* gap, void* str
     if (rc) return rc;
   }
   const PolyBuf poly = poly_buf(c);
-  if (c->poly_gen != c->coord_gen) {
-    PhaseTimer t(c, MT_T_PAIR_POLY, st);
-    MT_HIP(launch_pair_poly(S, M, kparams(c->params), c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), np, poly, st));
-    c->poly_gen = c->coord_gen;
-  }
-  {
+  if (c->params.element_rule > 0) {
+    // element-based integration: no clip polygons
+    PhaseTimer t(c, MT_T_PAIR_FWD, st);
+    MT_HIP(launch_elem_fwd(S, M, kparams(c->params), c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(),
+                           c->pair_off.as<int32_t>(), np, c->blk.as<double>(), np, c->counters.as<Counters>(), st));
+    c->blk_gen = -1;
+  } else {
+    if (c->poly_gen != c->coord_gen) {
+      PhaseTimer t(c, MT_T_PAIR_POLY, st);
+      MT_HIP(launch_pair_poly(S, M, kparams(c->params), c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), np, poly,
+                              st));
+      c->poly_gen = c->coord_gen;
+    }
     PhaseTimer t(c, MT_T_PAIR_FWD, st);
     MT_HIP(launch_pair_fwd(S, M, kparams(c->params), c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), np, poly,
                            c->blk.as<double>(), np, c->counters.as<Counters>(), st));
@@ -603,6 +613,8 @@ extern "C" {
 int mt_backward(mt_ctx* c, const double* W_D, const double* W_M, const double* w_g, double* gXs, double* gXm,
                 void* stream) {
   if (!c) return fail(MT_EINVAL, "mt_backward: null ctx");
+  if (c->params.element_rule > 0)
+    return fail(MT_EUNSUPPORTED, "mt_backward: element-based integration has no backward pass");
   if (!c->have_pattern) return fail(MT_ESTATE, "mt_backward: build pairs and pattern first");
   const DeviceMesh& S = c->side[0];
   const DeviceMesh& M = c->side[1];

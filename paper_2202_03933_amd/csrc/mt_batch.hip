@@ -493,6 +493,8 @@ int mt_batch_build(mt_batch* b, const mt_batch_tuning* tuning, void* stream) {
     if (!c->have_pattern) return bfail(MT_ESTATE, "mt_batch_build: an instance has no pattern");
     if (c->params.rule != p0.rule || c->params.lm_basis != p0.lm_basis)
       return bfail(MT_EINVAL, "mt_batch_build: all instances must share the rule and the basis");
+    if (c->params.element_rule != 0)
+      return bfail(MT_EUNSUPPORTED, "mt_batch_build: segment-based integration only");
   }
   b->nq = p0.rule;
   b->dual = p0.lm_basis == MT_BASIS_DUAL;

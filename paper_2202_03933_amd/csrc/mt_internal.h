@@ -85,7 +85,7 @@ struct KParams {
   int32_t newton_maxit;
   int32_t dual;
   int32_t rule;
-  int32_t pad;
+  int32_t elem;  // 0: segment-based integration; n: element-based, n x n Gauss points
 };
 
 }  // namespace mt
@@ -218,6 +218,14 @@ hipError_t launch_pair_poly(const DeviceMesh& S, const DeviceMesh& M, const KPar
 hipError_t launch_pair_fwd(const DeviceMesh& S, const DeviceMesh& M, const KParams& kp, const int32_t* pair_s,
                            const int32_t* pair_m, int64_t n_pairs, const PolyBuf& poly, double* blk,
                            int64_t blk_stride, Counters* cnt, hipStream_t s);
+
+// ---- element-based integration (mt_elements.hip) -----------------------------
+// Blocks of every pair by the kp.elem x kp.elem Gauss rule on each slave
+// element (pairs sorted by slave; those of element e: pair_off[e] ..
+// pair_off[e + 1]).
+hipError_t launch_elem_fwd(const DeviceMesh& S, const DeviceMesh& M, const KParams& kp, const int32_t* pair_s,
+                           const int32_t* pair_m, const int32_t* pair_off, int64_t n_pairs, double* blk,
+                           int64_t stride, Counters* cnt, hipStream_t s);
 
 // ---- assembly (mt_assemble.hip) ----------------------------------------------
 hipError_t launch_inc_count(const int32_t* conn, int32_t n_el, int32_t* cnt, hipStream_t s);

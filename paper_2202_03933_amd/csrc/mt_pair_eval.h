@@ -240,6 +240,57 @@ __device__ __forceinline__ void inverse2(const QMap& A, const QMap& B, double pu
 }
 
 // ---- forward -------------------------------------------------------------------
+// Blocks from the monomial moments of a quadrature: mu_ij = sum w xi1^i
+// xi2^j (i, j <= 2) and Mm[p][r] = sum w m_p(xi) m_r(eta), with the nodal
+// heights: D = C Dm C^T (Dm[p][r] the moment of m_p m_r), M = C Mm C^T,
+// g = C (Mm ht_m - Dm ht_s), ht = C^T h; for the dual basis Phi = A N:
+// D, M, g <- A D, A M, A g.
+template <bool DUAL>
+__device__ __forceinline__ void moments_to_blocks(const QMap& ms, const double mu[9], const double Mm[16],
+                                                  const double hs[4], const double hm[4], double D[16],
+                                                  double M[16], double g[4]) {
+#pragma clang fp contract(fast)
+  // Dm[p][r]: monomial exponents (0,0), (1,0), (0,1), (1,1) added
+  const double Dm[16] = {mu[0], mu[1], mu[2], mu[3], mu[1], mu[4], mu[3], mu[6],
+                         mu[2], mu[3], mu[5], mu[7], mu[3], mu[6], mu[7], mu[8]};
+  double hts[4], htm[4];
+  ht_apply(hs, hts);
+  ht_apply(hm, htm);
+  double gm[4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p) {
+    gm[p] = 0.25 * ((Mm[4 * p] * htm[0] + Mm[4 * p + 1] * htm[1] + Mm[4 * p + 2] * htm[2] + Mm[4 * p + 3] * htm[3]) -
+                    (Dm[4 * p] * hts[0] + Dm[4 * p + 1] * hts[1] + Dm[4 * p + 2] * hts[2] + Dm[4 * p + 3] * hts[3]));
+  }
+  double gs[4];
+  h_apply(gm, gs);
+  double Ds[16], Ms[16];
+  h_sandwich(Dm, 0.0625, Ds);
+  h_sandwich(Mm, 0.0625, Ms);
+  if (DUAL) {
+    const V2 S[4] = {qmap_node(ms, 0), qmap_node(ms, 1), qmap_node(ms, 2), qmap_node(ms, 3)};
+    double A[16];
+    dual_coefficients(S, A);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        D[4 * j + k] = A[4 * j] * Ds[k] + A[4 * j + 1] * Ds[4 + k] + A[4 * j + 2] * Ds[8 + k] + A[4 * j + 3] * Ds[12 + k];
+        M[4 * j + k] = A[4 * j] * Ms[k] + A[4 * j + 1] * Ms[4 + k] + A[4 * j + 2] * Ms[8 + k] + A[4 * j + 3] * Ms[12 + k];
+      }
+      g[j] = 0.25 * (A[4 * j] * gs[0] + A[4 * j + 1] * gs[1] + A[4 * j + 2] * gs[2] + A[4 * j + 3] * gs[3]);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      D[k] = Ds[k];
+      M[k] = Ms[k];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) g[j] = 0.25 * gs[j];
+  }
+}
+
 // Local blocks of one pair from its stored polygon (n vertices):
 //   D[j][k] = sum w A_t Phi_j N_k(xi),  M[j][l] = sum w A_t Phi_j N_l(eta),
 //   g[j]    = sum w A_t Phi_j (sum_l N_l(eta) hm_l - sum_k N_k(xi) hs_k),
@@ -250,95 +301,54 @@ __device__ __forceinline__ void inverse2(const QMap& A, const QMap& B, double pu
 // ht = C^T h, and for the dual basis Phi = A N: D, M, g <- A D, A M, A g.
 template <int NQ, bool DUAL, class Heights>
 __device__ __forceinline__ void pair_integrate(const QMap& ms, const QMap& mm, const Heights& heights,
-                                               const GPoly& P, int n, const KParams& kp, double D[16], double M[16],
-                                               double g[4], unsigned& noconv) {
-  double mu[9], Mm[16];
+                                             const GPoly& P, int n, const KParams& kp, double D[16], double M[16],
+                                             double g[4], unsigned& noconv) {
+double mu[9], Mm[16];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) mu[k] = 0.0;
+for (int k = 0; k < 9; ++k) mu[k] = 0.0;
 #pragma unroll
-  for (int k = 0; k < 16; ++k) Mm[k] = 0.0;
-  if (n >= 3) {
+for (int k = 0; k < 16; ++k) Mm[k] = 0.0;
+if (n >= 3) {
 #pragma clang fp contract(fast)
-    const double u0 = P.U(0), v0 = P.V(0);
-    double u1 = P.U(1), v1 = P.V(1);
-    for (int i = 1; i + 1 < n; ++i) {
-      const double u2 = P.U(i + 1), v2 = P.V(i + 1);
-      const double At = 0.5 * ((u1 - u0) * (v2 - v0) - (v1 - v0) * (u2 - u0));
+  const double u0 = P.U(0), v0 = P.V(0);
+  double u1 = P.U(1), v1 = P.V(1);
+  for (int i = 1; i + 1 < n; ++i) {
+    const double u2 = P.U(i + 1), v2 = P.V(i + 1);
+    const double At = 0.5 * ((u1 - u0) * (v2 - v0) - (v1 - v0) * (u2 - u0));
 #pragma unroll 1
-      for (int q = 0; q < NQ; ++q) {
-        double l0, l1, l2, w;
-        rule_point<NQ>(q, l0, l1, l2, w);
-        const double pu = l0 * u0 + l1 * u1 + l2 * u2;
-        const double pv = l0 * v0 + l1 * v1 + l2 * v2;
-        double a1, a2, b1, b2;
-        inverse2(ms, mm, pu, pv, kp.newton_tol, kp.newton_maxit, a1, a2, b1, b2, noconv);
-        const double t[4] = {w * At, w * At * a1, w * At * a2, w * At * a1 * a2};
-        mu[0] += t[0];
-        mu[1] += t[1];
-        mu[2] += t[2];
-        mu[3] += t[3];
-        mu[4] += t[1] * a1;
-        mu[5] += t[2] * a2;
-        mu[6] += t[3] * a1;
-        mu[7] += t[3] * a2;
-        mu[8] += t[3] * (a1 * a2);
-        const double b12 = b1 * b2;
+    for (int q = 0; q < NQ; ++q) {
+      double l0, l1, l2, w;
+      rule_point<NQ>(q, l0, l1, l2, w);
+      const double pu = l0 * u0 + l1 * u1 + l2 * u2;
+      const double pv = l0 * v0 + l1 * v1 + l2 * v2;
+      double a1, a2, b1, b2;
+      inverse2(ms, mm, pu, pv, kp.newton_tol, kp.newton_maxit, a1, a2, b1, b2, noconv);
+      const double t[4] = {w * At, w * At * a1, w * At * a2, w * At * a1 * a2};
+      mu[0] += t[0];
+      mu[1] += t[1];
+      mu[2] += t[2];
+      mu[3] += t[3];
+      mu[4] += t[1] * a1;
+      mu[5] += t[2] * a2;
+      mu[6] += t[3] * a1;
+      mu[7] += t[3] * a2;
+      mu[8] += t[3] * (a1 * a2);
+      const double b12 = b1 * b2;
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
-          Mm[4 * p] += t[p];
-          Mm[4 * p + 1] += t[p] * b1;
-          Mm[4 * p + 2] += t[p] * b2;
-          Mm[4 * p + 3] += t[p] * b12;
-        }
+      for (int p = 0; p < 4; ++p) {
+        Mm[4 * p] += t[p];
+        Mm[4 * p + 1] += t[p] * b1;
+        Mm[4 * p + 2] += t[p] * b2;
+        Mm[4 * p + 3] += t[p] * b12;
       }
-      u1 = u2;
-      v1 = v2;
     }
+    u1 = u2;
+    v1 = v2;
   }
-  {
-#pragma clang fp contract(fast)
-    // Dm[p][r]: monomial exponents (0,0), (1,0), (0,1), (1,1) added
-    const double Dm[16] = {mu[0], mu[1], mu[2], mu[3], mu[1], mu[4], mu[3], mu[6],
-                           mu[2], mu[3], mu[5], mu[7], mu[3], mu[6], mu[7], mu[8]};
-    double hs[4], hm[4];
-    heights(hs, hm);
-    double hts[4], htm[4];
-    ht_apply(hs, hts);
-    ht_apply(hm, htm);
-    double gm[4];
-#pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      gm[p] = 0.25 * ((Mm[4 * p] * htm[0] + Mm[4 * p + 1] * htm[1] + Mm[4 * p + 2] * htm[2] + Mm[4 * p + 3] * htm[3]) -
-                      (Dm[4 * p] * hts[0] + Dm[4 * p + 1] * hts[1] + Dm[4 * p + 2] * hts[2] + Dm[4 * p + 3] * hts[3]));
-    }
-    double gs[4];
-    h_apply(gm, gs);
-    double Ds[16], Ms[16];
-    h_sandwich(Dm, 0.0625, Ds);
-    h_sandwich(Mm, 0.0625, Ms);
-    if (DUAL) {
-      const V2 S[4] = {qmap_node(ms, 0), qmap_node(ms, 1), qmap_node(ms, 2), qmap_node(ms, 3)};
-      double A[16];
-      dual_coefficients(S, A);
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          D[4 * j + k] = A[4 * j] * Ds[k] + A[4 * j + 1] * Ds[4 + k] + A[4 * j + 2] * Ds[8 + k] + A[4 * j + 3] * Ds[12 + k];
-          M[4 * j + k] = A[4 * j] * Ms[k] + A[4 * j + 1] * Ms[4 + k] + A[4 * j + 2] * Ms[8 + k] + A[4 * j + 3] * Ms[12 + k];
-        }
-        g[j] = 0.25 * (A[4 * j] * gs[0] + A[4 * j + 1] * gs[1] + A[4 * j + 2] * gs[2] + A[4 * j + 3] * gs[3]);
-      }
-    } else {
-#pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        D[k] = Ds[k];
-        M[k] = Ms[k];
-      }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) g[j] = 0.25 * gs[j];
-    }
-  }
+}
+double hs[4], hm[4];
+heights(hs, hm);
+moments_to_blocks<DUAL>(ms, mu, Mm, hs, hm, D, M, g);
 }
 
 // ---- backward ------------------------------------------------------------------
