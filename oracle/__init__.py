@@ -43,7 +43,10 @@ def _lib():
         i64, i32, dbl, vp = ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p
         lib.or_search.argtypes = [ctypes.c_int, i64, vp, i64, vp, i64, vp, i64, vp, dbl, i64, vp, vp, vp]
         lib.or_eval_candidates.argtypes = [i64, vp, i64, vp, i64, vp, i64, vp, vp, i64, vp, vp, vp, vp, vp]
-        lib.or_pair_grads.argtypes = [i64, vp, i64, vp, i64, vp, i64, vp, vp, i64, vp, vp, vp, vp, vp]
+        lib.or_pair_grads.argtypes = [i64, vp, i64, vp, i64, vp, i64, vp, vp, i64, vp, vp, vp, vp, vp, vp]
+        lib.or_normal_chain.argtypes = [i64, vp, i64, vp, vp, vp]
+        lib.or_nodal_normals.argtypes = [i64, vp, i64, vp, vp, vp]
+        lib.or_nodal_normals.restype = None
         lib.or_count_flops.argtypes = [i64, vp, i64, vp, i64, vp, i64, vp, vp, i64, vp, vp, vp]
         lib.or_count_flops.restype = None
         lib.or_pair_polygon.argtypes = [vp, vp, vp, vp, vp, vp]
@@ -66,13 +69,15 @@ class OrParams(ctypes.Structure):
     _fields_ = [("delta", ctypes.c_double), ("dual", ctypes.c_int32), ("rule", ctypes.c_int32),
                 ("eps_d", ctypes.c_double), ("eps_a", ctypes.c_double),
                 ("newton_tol", ctypes.c_double), ("newton_maxit", ctypes.c_int32),
-                ("pad", ctypes.c_int32)]
+                ("normals", ctypes.c_int32)]
 
 
 def params(delta=0.0, dual=False, rule=7, eps_d=1e-12, eps_a=1e-12, newton_tol=1e-14,
-           newton_maxit=30):
+           newton_maxit=30, nodal_normals=False):
+    """nodal_normals: auxiliary planes from the averaged nodal normal field
+    instead of each element's own normal."""
     return OrParams(float(delta), int(bool(dual)), int(rule), float(eps_d), float(eps_a),
-                    float(newton_tol), int(newton_maxit), 0)
+                    float(newton_tol), int(newton_maxit), int(bool(nodal_normals)))
 
 
 ST_NOCONV, ST_OVERFLOW, ST_DEGEN_SLAVE, ST_DEGEN_MASTER = 1, 2, 4, 8
@@ -209,17 +214,44 @@ def count_flops_elements(slave, master, prm, ps, pm, ng):
     return int(_lib().or_count_flops_elements(*args, ctypes.byref(prm), int(ng), ps.size, _p(ps), _p(pm)))
 
 
-def pair_grads(slave, master, prm, ps, pm, w36):
-    """d(<w, blocks>)/d(24 nodal coordinates) per pair, forward-mode exact."""
+def pair_grads(slave, master, prm, ps, pm, w36, with_n0=False):
+    """d(<w, blocks>)/d(24 nodal coordinates) per pair, forward-mode exact;
+    with_n0 also returns d/d(element normal n0) per pair (n, 3), the input
+    the nodal normal field adds (params(nodal_normals=True))."""
     args, keep = _mesh_args(slave, master)
     ps = np.ascontiguousarray(ps, np.int32)
     pm = np.ascontiguousarray(pm, np.int32)
     w36 = np.ascontiguousarray(w36, np.float64)
     n = ps.size
     out = np.zeros((n, 24))
+    gn0 = np.zeros((n, 3))
     st = np.zeros(n, np.int32)
-    _lib().or_pair_grads(*args, ctypes.byref(prm), n, _p(ps), _p(pm), _p(w36), _p(out), _p(st))
+    _lib().or_pair_grads(*args, ctypes.byref(prm), n, _p(ps), _p(pm), _p(w36), _p(out), _p(gn0), _p(st))
+    if with_n0:
+        return out, gn0, st
     return out, st
+
+
+def nodal_normals(slave):
+    """(nodal normals (n_nodes, 3), element normals (n_el, 3)) of the slave side."""
+    X = np.ascontiguousarray(slave.X, np.float64)
+    C = np.ascontiguousarray(slave.conn, np.int32)
+    nn = np.zeros((X.shape[0], 3))
+    ne = np.zeros((C.shape[0], 3))
+    _lib().or_nodal_normals(X.shape[0], _p(X), C.shape[0], _p(C), _p(nn), _p(ne))
+    return nn, ne
+
+
+def normal_chain(slave, gn0_el):
+    """Gradient (n_nodes, 3) of sum_e <gn0_el[e], n0_e> with respect to the
+    slave coordinates through the nodal normal field."""
+    X = np.ascontiguousarray(slave.X, np.float64)
+    C = np.ascontiguousarray(slave.conn, np.int32)
+    g = np.ascontiguousarray(gn0_el, np.float64)
+    out = np.zeros((X.shape[0], 3))
+    if _lib().or_normal_chain(X.shape[0], _p(X), C.shape[0], _p(C), _p(g), _p(out)) != 0:
+        raise RuntimeError("normal_chain: element patch larger than 24 nodes")
+    return out
 
 
 def pair_weights(slave, master, ps, pm, wD_fn, wM_fn, wg_fn):

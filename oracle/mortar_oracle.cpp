@@ -127,6 +127,7 @@ struct Params {
   double eps_a;       // relative area tolerance
   double newton_tol;  // inverse bilinear map: stop when max |d xi| <= tol
   int newton_maxit;   // ... or fail after this many iterations
+  int normals;        // auxiliary-plane normal: 0 element (g1 x g2), 1 averaged nodal normals
 };
 
 enum {
@@ -171,26 +172,54 @@ void shape(const T& x1, const T& x2, T N[4], T d1[4], T d2[4]) {
 // Auxiliary plane of a slave element: centre x0 (parameter origin), unit
 // normal n0 at the centre, and an orthonormal in-plane basis (t1, t2) with
 // t1 along the first covariant base vector.  Fig. 1 projects along n0 at x0.
+// n0 is the element normal g1 x g2 / |g1 x g2| at the centre, or, when nin is
+// given, that unit vector (the continuous normal field of the slave side at
+// the element centre, see element_normals); t1 is then the part of g1
+// orthogonal to n0, normalised.
 template <class T>
-void slave_frame(const T X[4][3], T x0[3], T n0[3], T t1[3], T t2[3]) {
+void slave_frame(const T X[4][3], const T* nin, T x0[3], T n0[3], T t1[3], T t2[3]) {
   T g1[3], g2[3];
   for (int d = 0; d < 3; ++d) {
     x0[d] = 0.25 * (((X[0][d] + X[1][d]) + X[2][d]) + X[3][d]);
     g1[d] = 0.25 * (((X[1][d] - X[0][d]) + X[2][d]) - X[3][d]);
     g2[d] = 0.25 * (((X[2][d] + X[3][d]) - X[0][d]) - X[1][d]);
   }
-  T n[3] = {g1[1] * g2[2] - g1[2] * g2[1],
-            g1[2] * g2[0] - g1[0] * g2[2],
-            g1[0] * g2[1] - g1[1] * g2[0]};
-  T ln = sqrt((n[0] * n[0] + n[1] * n[1]) + n[2] * n[2]);
-  T lg = sqrt((g1[0] * g1[0] + g1[1] * g1[1]) + g1[2] * g1[2]);
-  for (int d = 0; d < 3; ++d) {
-    n0[d] = n[d] / ln;
-    t1[d] = g1[d] / lg;
+  if (nin) {
+    for (int d = 0; d < 3; ++d) n0[d] = nin[d];
+    const T gn = (g1[0] * n0[0] + g1[1] * n0[1]) + g1[2] * n0[2];
+    T w[3];
+    for (int d = 0; d < 3; ++d) w[d] = g1[d] - gn * n0[d];
+    const T lw = sqrt((w[0] * w[0] + w[1] * w[1]) + w[2] * w[2]);
+    for (int d = 0; d < 3; ++d) t1[d] = w[d] / lw;
+  } else {
+    T n[3] = {g1[1] * g2[2] - g1[2] * g2[1],
+              g1[2] * g2[0] - g1[0] * g2[2],
+              g1[0] * g2[1] - g1[1] * g2[0]};
+    T ln = sqrt((n[0] * n[0] + n[1] * n[1]) + n[2] * n[2]);
+    T lg = sqrt((g1[0] * g1[0] + g1[1] * g1[1]) + g1[2] * g1[2]);
+    for (int d = 0; d < 3; ++d) {
+      n0[d] = n[d] / ln;
+      t1[d] = g1[d] / lg;
+    }
   }
   t2[0] = n0[1] * t1[2] - n0[2] * t1[1];
   t2[1] = n0[2] * t1[0] - n0[0] * t1[2];
   t2[2] = n0[0] * t1[1] - n0[1] * t1[0];
+}
+
+// Unit normal of a quad at its corner k: the cross product of the edges to
+// the next and to the previous node (the normal of the bilinear map there).
+template <class T>
+void corner_normal(const T X[4][3], int k, T v[3]) {
+  const int a = (k + 1) % 4, b = (k + 3) % 4;
+  T e1[3], e2[3];
+  for (int d = 0; d < 3; ++d) {
+    e1[d] = X[a][d] - X[k][d];
+    e2[d] = X[b][d] - X[k][d];
+  }
+  const T c[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+  const T l = sqrt((c[0] * c[0] + c[1] * c[1]) + c[2] * c[2]);
+  for (int d = 0; d < 3; ++d) v[d] = c[d] / l;
 }
 
 // In-plane coordinates (u, v) and signed height h above the plane.
@@ -423,14 +452,14 @@ struct PairOut {
 // when the master lies on the +n0 side of the slave.
 template <class T>
 void eval_pair(const T Xs[4][3], const T Xm[4][3], const Params& prm,
-               const Rule& rule, bool integrate, PairOut<T>& out) {
+               const Rule& rule, bool integrate, PairOut<T>& out, const T* nin = nullptr) {
   out.nv = 0;
   out.status = 0;
   for (int i = 0; i < 16; ++i) { out.D[i] = 0.0; out.M[i] = 0.0; }
   for (int i = 0; i < 4; ++i) out.g[i] = 0.0;
 
   T x0[3], n0[3], t1[3], t2[3];
-  slave_frame(Xs, x0, n0, t1, t2);
+  slave_frame(Xs, nin, x0, n0, t1, t2);
   P2<T> S[4], Mn[4];
   T hs[4], hm[4];
   for (int k = 0; k < 4; ++k) project(Xs[k], x0, n0, t1, t2, S[k], hs[k]);
@@ -595,11 +624,11 @@ void gauss_legendre(int n, double* x, double* w) {
 // pair (layout of eval_pair's D, M, g).  Returns status bits.
 template <class T>
 int eval_element(const T Xs[4][3], int K, const T* XmK, const Params& prm, int ng, const double* gx,
-                 const double* gw, T* blk) {
+                 const double* gw, T* blk, const T* nin = nullptr) {
   int status = 0;
   for (int i = 0; i < 36 * K; ++i) blk[i] = 0.0;
   T x0[3], n0[3], t1[3], t2[3];
-  slave_frame(Xs, x0, n0, t1, t2);
+  slave_frame(Xs, nin, x0, n0, t1, t2);
   P2<T> S[4];
   T hs[4];
   for (int k = 0; k < 4; ++k) project(Xs[k], x0, n0, t1, t2, S[k], hs[k]);
@@ -813,6 +842,56 @@ void load_pair(const MeshView& S, const MeshView& M, int32_t s, int32_t m, T Xs[
     }
 }
 
+// Continuous normal field of the slave side (Sec. "Discretization": the
+// projections between the two sides usually rest on a continuous field of
+// slave normals; the paper does not define it).  Our reading: the nodal
+// normal n_a is the normalised sum of the unit corner normals of the elements
+// around node a, added in ascending element order; an element's
+// auxiliary-plane normal is the normalised sum of its four nodal normals in
+// node order (the interpolated field at the element centre, normalised).
+void nodal_normals(const MeshView& S, std::vector<double>& nn) {
+  nn.assign(3 * S.n_nodes, 0.0);
+  for (int64_t e = 0; e < S.n_el; ++e) {
+    double X[4][3];
+    for (int k = 0; k < 4; ++k)
+      for (int d = 0; d < 3; ++d) X[k][d] = S.X[3 * S.C[4 * e + k] + d];
+    for (int k = 0; k < 4; ++k) {
+      double v[3];
+      corner_normal(X, k, v);
+      const int64_t a = S.C[4 * e + k];
+      for (int d = 0; d < 3; ++d) nn[3 * a + d] = nn[3 * a + d] + v[d];
+    }
+  }
+  for (int64_t a = 0; a < S.n_nodes; ++a) {
+    double* u = &nn[3 * a];
+    const double l = std::sqrt((u[0] * u[0] + u[1] * u[1]) + u[2] * u[2]);
+    if (l > 0.0)
+      for (int d = 0; d < 3; ++d) u[d] = u[d] / l;
+  }
+}
+
+void element_normals(const MeshView& S, const std::vector<double>& nn, std::vector<double>& ne) {
+  ne.assign(3 * S.n_el, 0.0);
+  for (int64_t e = 0; e < S.n_el; ++e) {
+    const int32_t* c = S.C + 4 * e;
+    double v[3];
+    for (int d = 0; d < 3; ++d) v[d] = ((nn[3 * c[0] + d] + nn[3 * c[1] + d]) + nn[3 * c[2] + d]) + nn[3 * c[3] + d];
+    const double l = std::sqrt((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
+    for (int d = 0; d < 3; ++d) ne[3 * e + d] = v[d] / l;
+  }
+}
+
+// Element normals of the slave side when the parameters ask for the nodal
+// field, else empty.
+std::vector<double> frame_normals(const MeshView& S, const Params& prm) {
+  std::vector<double> nn, ne;
+  if (prm.normals) {
+    nodal_normals(S, nn);
+    element_normals(S, nn, ne);
+  }
+  return ne;
+}
+
 }  // namespace
 
 // ================================================================== C API
@@ -827,13 +906,14 @@ struct OrParams {
   double eps_a;
   double newton_tol;
   int32_t newton_maxit;
-  int32_t pad;
+  int32_t normals;
 };
 
 static Params to_params(const OrParams* p) {
   Params q;
   q.delta = p->delta; q.dual = p->dual; q.rule = p->rule; q.eps_d = p->eps_d;
   q.eps_a = p->eps_a; q.newton_tol = p->newton_tol; q.newton_maxit = p->newton_maxit;
+  q.normals = p->normals;
   return q;
 }
 
@@ -866,12 +946,13 @@ int or_eval_candidates(int64_t ns_nodes, const double* Xs, int64_t ns_el, const 
   MeshView S{ns_nodes, Xs, ns_el, Cs}, M{nm_nodes, Xm, nm_el, Cm};
   const Params prm = to_params(op);
   const Rule rule = make_rule(prm.rule);
+  const std::vector<double> ne = frame_normals(S, prm);
   int any = 0;
   for (int64_t i = 0; i < n; ++i) {
     double xs[4][3], xm[4][3];
     load_pair(S, M, cs[i], cm[i], xs, xm);
     PairOut<double> o;
-    eval_pair(xs, xm, prm, rule, blocks != nullptr, o);
+    eval_pair(xs, xm, prm, rule, blocks != nullptr, o, ne.empty() ? nullptr : &ne[3 * cs[i]]);
     nverts[i] = (uint8_t)o.nv;
     if (status) status[i] = o.status;
     any |= o.status;
@@ -960,7 +1041,7 @@ void or_dual_matrix(const double* Xs4, double* A) {
   for (int k = 0; k < 4; ++k)
     for (int d = 0; d < 3; ++d) xs[k][d] = Xs4[3 * k + d];
   double x0[3], n0[3], t1[3], t2[3];
-  slave_frame(xs, x0, n0, t1, t2);
+  slave_frame(xs, (const double*)nullptr, x0, n0, t1, t2);
   P2<double> S[4];
   double h;
   for (int k = 0; k < 4; ++k) project(xs[k], x0, n0, t1, t2, S[k], h);
@@ -972,36 +1053,116 @@ void or_dual_matrix(const double* Xs4, double* A) {
 // [slave node 0..3 (x,y,z) | master node 0..3 (x,y,z)], by forward-mode dual
 // numbers through the whole pair evaluation.  Newton is iterated to
 // convergence, so the tangent is the implicit-function derivative.
+// With the nodal normal field (params.normals), the slave element's
+// auxiliary-plane normal n0 is a further input: grads_n0 (optional) receives
+// dL/dn0 per pair (3 values), to be taken to the coordinates by
+// or_normal_chain.
 int or_pair_grads(int64_t ns_nodes, const double* Xs, int64_t ns_el, const int32_t* Cs,
                   int64_t nm_nodes, const double* Xm, int64_t nm_el, const int32_t* Cm,
                   const OrParams* op, int64_t n, const int32_t* cs, const int32_t* cm,
-                  const double* w, double* grads, int32_t* status) {
-  using D24 = Dual<24>;
+                  const double* w, double* grads, double* grads_n0, int32_t* status) {
+  using D27 = Dual<27>;
   MeshView S{ns_nodes, Xs, ns_el, Cs}, M{nm_nodes, Xm, nm_el, Cm};
   const Params prm = to_params(op);
   const Rule rule = make_rule(prm.rule);
+  const std::vector<double> ne = frame_normals(S, prm);
   int any = 0;
   for (int64_t i = 0; i < n; ++i) {
     double xs[4][3], xm[4][3];
     load_pair(S, M, cs[i], cm[i], xs, xm);
-    D24 Ds[4][3], Dm[4][3];
+    D27 Ds[4][3], Dm[4][3], Dn[3];
     for (int k = 0; k < 4; ++k)
       for (int d = 0; d < 3; ++d) {
-        Ds[k][d] = D24(xs[k][d]); Ds[k][d].d[3 * k + d] = 1.0;
-        Dm[k][d] = D24(xm[k][d]); Dm[k][d].d[12 + 3 * k + d] = 1.0;
+        Ds[k][d] = D27(xs[k][d]); Ds[k][d].d[3 * k + d] = 1.0;
+        Dm[k][d] = D27(xm[k][d]); Dm[k][d].d[12 + 3 * k + d] = 1.0;
       }
-    PairOut<D24> o;
-    eval_pair(Ds, Dm, prm, rule, true, o);
-    D24 L(0.0);
+    if (!ne.empty())
+      for (int d = 0; d < 3; ++d) { Dn[d] = D27(ne[3 * cs[i] + d]); Dn[d].d[24 + d] = 1.0; }
+    PairOut<D27> o;
+    eval_pair(Ds, Dm, prm, rule, true, o, ne.empty() ? nullptr : Dn);
+    D27 L(0.0);
     const double* wi = w + 36 * i;
     for (int k = 0; k < 16; ++k) L = L + wi[k] * o.D[k];
     for (int k = 0; k < 16; ++k) L = L + wi[16 + k] * o.M[k];
     for (int k = 0; k < 4; ++k) L = L + wi[32 + k] * o.g[k];
     for (int k = 0; k < 24; ++k) grads[24 * i + k] = L.d[k];
+    if (grads_n0)
+      for (int d = 0; d < 3; ++d) grads_n0[3 * i + d] = L.d[24 + d];
     if (status) status[i] = o.status;
     any |= o.status;
   }
   return any;
+}
+
+// Gradient with respect to the slave coordinates of sum_e <gn0[e], n0_e>,
+// n0_e the element normals of the nodal normal field (element_normals), by
+// forward-mode dual numbers over the coordinates of each element's patch
+// (the nodes of all elements around its four nodes).  Adds to gX (3 per node).
+// Returns 0, or 1 when a patch exceeds 24 nodes.
+int or_normal_chain(int64_t ns_nodes, const double* Xs, int64_t ns_el, const int32_t* Cs, const double* gn0,
+                    double* gX) {
+  constexpr int PMAX = 24;
+  using DP = Dual<3 * PMAX>;
+  std::vector<std::vector<int32_t>> inc(ns_nodes);
+  for (int64_t e = 0; e < ns_el; ++e)
+    for (int k = 0; k < 4; ++k) inc[Cs[4 * e + k]].push_back((int32_t)e);
+  for (int64_t e = 0; e < ns_el; ++e) {
+    const double* g = gn0 + 3 * e;
+    if (g[0] == 0.0 && g[1] == 0.0 && g[2] == 0.0) continue;
+    std::vector<int32_t> patch;
+    for (int k = 0; k < 4; ++k)
+      for (int32_t f : inc[Cs[4 * e + k]])
+        for (int j = 0; j < 4; ++j)
+          if (std::find(patch.begin(), patch.end(), Cs[4 * f + j]) == patch.end()) patch.push_back(Cs[4 * f + j]);
+    if ((int)patch.size() > PMAX) return 1;
+    auto slot = [&](int32_t node) { return (int)(std::find(patch.begin(), patch.end(), node) - patch.begin()); };
+    auto coords = [&](int32_t f, DP X[4][3]) {
+      for (int j = 0; j < 4; ++j) {
+        const int32_t a = Cs[4 * f + j];
+        const int sl = slot(a);
+        for (int d = 0; d < 3; ++d) {
+          X[j][d] = DP(Xs[3 * a + d]);
+          X[j][d].d[3 * sl + d] = 1.0;
+        }
+      }
+    };
+    DP nrm[4][3];
+    for (int k = 0; k < 4; ++k) {
+      const int32_t a = Cs[4 * e + k];
+      DP u[3] = {DP(0.0), DP(0.0), DP(0.0)};
+      for (int32_t f : inc[a]) {  // ascending element order
+        DP X[4][3];
+        coords(f, X);
+        int kk = 0;
+        while (Cs[4 * f + kk] != a) ++kk;
+        DP v[3];
+        corner_normal(X, kk, v);
+        for (int d = 0; d < 3; ++d) u[d] = u[d] + v[d];
+      }
+      const DP l = sqrt((u[0] * u[0] + u[1] * u[1]) + u[2] * u[2]);
+      for (int d = 0; d < 3; ++d) nrm[k][d] = u[d] / l;
+    }
+    DP v[3];
+    for (int d = 0; d < 3; ++d) v[d] = ((nrm[0][d] + nrm[1][d]) + nrm[2][d]) + nrm[3][d];
+    const DP l = sqrt((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
+    DP L(0.0);
+    for (int d = 0; d < 3; ++d) L = L + g[d] * (v[d] / l);
+    for (size_t j = 0; j < patch.size(); ++j)
+      for (int d = 0; d < 3; ++d) gX[3 * patch[j] + d] += L.d[3 * j + d];
+  }
+  return 0;
+}
+
+// Nodal normals (3 per node) and element normals (3 per element) of a slave
+// surface (for tests).
+void or_nodal_normals(int64_t ns_nodes, const double* Xs, int64_t ns_el, const int32_t* Cs, double* nn_out,
+                      double* ne_out) {
+  MeshView S{ns_nodes, Xs, ns_el, Cs};
+  std::vector<double> nn, ne;
+  nodal_normals(S, nn);
+  element_normals(S, nn, ne);
+  std::copy(nn.begin(), nn.end(), nn_out);
+  std::copy(ne.begin(), ne.end(), ne_out);
 }
 
 // Gauss-Legendre rule on [-1, 1] (for tests).
@@ -1021,6 +1182,7 @@ int or_eval_elements(int64_t ns_nodes, const double* Xs, int64_t ns_el, const in
   const Params prm = to_params(op);
   double gx[8], gw[8];
   gauss_legendre(ng, gx, gw);
+  const std::vector<double> ne = frame_normals(S, prm);
   int any = 0;
   for (int64_t i0 = 0; i0 < n;) {
     int64_t i1 = i0;
@@ -1033,7 +1195,8 @@ int or_eval_elements(int64_t ns_nodes, const double* Xs, int64_t ns_el, const in
     for (int i = 0; i < K; ++i)
       for (int k = 0; k < 4; ++k)
         for (int d = 0; d < 3; ++d) xm[12 * i + 3 * k + d] = M.X[3 * M.C[4 * pm[i0 + i] + k] + d];
-    const int st = eval_element(xs, K, xm.data(), prm, ng, gx, gw, blocks + 36 * i0);
+    const int st = eval_element(xs, K, xm.data(), prm, ng, gx, gw, blocks + 36 * i0,
+                                ne.empty() ? nullptr : &ne[3 * ps[i0]]);
     if (status)
       for (int64_t i = i0; i < i1; ++i) status[i] = st;
     any |= st;
