@@ -76,7 +76,22 @@ typedef struct mt_params {
   int32_t newton_maxit;
   int32_t element_rule; /* 0: segment-based integration (Alg. 1); n = 1..8: element-based,
                            n x n Gauss-Legendre points per slave element (see mt_integrate) */
+  int32_t normals;      /* auxiliary-plane normals: MT_NORMALS_ELEMENT or MT_NORMALS_NODAL */
+  int32_t reserved;
 } mt_params;
+
+/* Auxiliary-plane normal of a slave element (Sec. "Discretization": the
+ * projections rest on a continuous field of slave normals).
+ * MT_NORMALS_ELEMENT: the element's own normal g1 x g2 / |g1 x g2| at its
+ * centre.  MT_NORMALS_NODAL: the continuous field -- the nodal normal is the
+ * normalised sum of the unit corner normals of the elements around the node
+ * (corner normal: cross product of the edges to the next and the previous
+ * node), the element's plane normal the normalised sum of its four nodal
+ * normals; the in-plane axis t1 is then the part of g1 orthogonal to it.
+ * mt_backward differentiates through the field (neighbouring elements'
+ * nodes included). */
+#define MT_NORMALS_ELEMENT 0
+#define MT_NORMALS_NODAL 1
 
 /* Counters of the last build / integrate / backward on a context. */
 typedef struct mt_stats {

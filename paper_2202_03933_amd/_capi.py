@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libmortar_mi355x.so")
 MT_OK, MT_EINVAL, MT_ECAPACITY, MT_EHIP, MT_ENOCONV, MT_EDEGENERATE, MT_ESTATE, MT_EUNSUPPORTED = range(8)
 MT_SIDE_SLAVE, MT_SIDE_MASTER = 0, 1
 MT_BASIS_STANDARD, MT_BASIS_DUAL = 0, 1
+MT_NORMALS_ELEMENT, MT_NORMALS_NODAL = 0, 1
 
 _NAMES = {0: "MT_OK", 1: "MT_EINVAL", 2: "MT_ECAPACITY", 3: "MT_EHIP", 4: "MT_ENOCONV", 5: "MT_EDEGENERATE",
           6: "MT_ESTATE", 7: "MT_EUNSUPPORTED"}
@@ -22,7 +23,8 @@ _NAMES = {0: "MT_OK", 1: "MT_EINVAL", 2: "MT_ECAPACITY", 3: "MT_EHIP", 4: "MT_EN
 class mt_params(ctypes.Structure):
     _fields_ = [("delta", ctypes.c_double), ("bin_size", ctypes.c_double), ("lm_basis", ctypes.c_int32),
                 ("rule", ctypes.c_int32), ("eps_d", ctypes.c_double), ("eps_a", ctypes.c_double),
-                ("newton_tol", ctypes.c_double), ("newton_maxit", ctypes.c_int32), ("element_rule", ctypes.c_int32)]
+                ("newton_tol", ctypes.c_double), ("newton_maxit", ctypes.c_int32), ("element_rule", ctypes.c_int32),
+                ("normals", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class mt_stats(ctypes.Structure):

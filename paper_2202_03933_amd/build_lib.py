@@ -21,7 +21,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libmortar_mi355x.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["mt_prims.hip", "mt_search.hip", "mt_pairs.hip", "mt_assemble.hip", "mt_backward.hip", "mt_elements.hip",
+SOURCES = ["mt_prims.hip", "mt_search.hip", "mt_pairs.hip", "mt_assemble.hip", "mt_backward.hip", "mt_elements.hip", "mt_normals.hip",
            "mt_batch.hip", "mt_api.hip"]
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

@@ -168,7 +168,7 @@ int mt_destroy(mt_ctx* c) {
                  &c->minc_off, &c->minc_cur, &c->minc_list, &c->rawD_cnt, &c->rawD_off, &c->rawD, &c->rawM_cnt,
                  &c->rawM_off, &c->rawM, &c->pat_keep, &c->D_cnt, &c->D_rowptr, &c->D_col, &c->M_cnt, &c->M_rowptr,
                  &c->M_col, &c->posD, &c->posM, &c->poly_u, &c->poly_v, &c->poly_lab, &c->poly_nf, &c->maybe_list,
-                 &c->maybe_flag, &c->maybe_scan, &c->mpoly_u, &c->mpoly_v, &c->mpoly_lab, &c->mpoly_nf, &c->blk, &c->gpair, &c->mp_keys, &c->mp_vals, &c->mp_off, &c->mp_pos,
+                 &c->maybe_flag, &c->maybe_scan, &c->mpoly_u, &c->mpoly_v, &c->mpoly_lab, &c->mpoly_nf, &c->blk, &c->gpair, &c->nrm_node, &c->nrm_el, &c->gn0, &c->nrm_sb, &c->nrm_ub, &c->nrm_cg, &c->mp_keys, &c->mp_vals, &c->mp_off, &c->mp_pos,
                  &c->scan_tmp, &c->sort_hist, &c->host_tmp};
   for (Buf* b : bufs) release(*b);
   for (auto& iv : c->intervals) {
@@ -187,6 +187,8 @@ int mt_set_params(mt_ctx* c, const mt_params* p) {
     return fail(MT_EINVAL, "mt_set_params: lm_basis");
   if (p->element_rule < 0 || p->element_rule > 8)
     return fail(MT_EINVAL, "mt_set_params: element_rule must be 0 (segments) or 1..8");
+  if (p->normals != MT_NORMALS_ELEMENT && p->normals != MT_NORMALS_NODAL)
+    return fail(MT_EINVAL, "mt_set_params: normals");
   if (!(p->delta >= 0) || !(p->bin_size >= 0) || !(p->eps_d >= 0) || !(p->eps_a >= 0) || !(p->newton_tol > 0) ||
       p->newton_maxit < 1)
     return fail(MT_EINVAL, "mt_set_params: negative or invalid tolerance");
@@ -208,6 +210,7 @@ int mt_upload(mt_ctx* c, int side, int64_t n_nodes, const double* x, const doubl
     return fail(MT_EINVAL, "mt_upload: connectivity must be 16-byte aligned");
   DeviceMesh& m = c->side[side];
   m.x = x; m.y = y; m.z = z; m.conn = conn;
+  m.nrm = nullptr;
   m.n_nodes = (int32_t)n_nodes;
   m.n_el = (int32_t)n_el;
   m.set = true;
@@ -229,6 +232,8 @@ int mt_update_coordinates(mt_ctx* c, int side, const double* x, const double* y,
   return MT_OK;
 }
 
+static int ensure_normals(mt_ctx* c, hipStream_t st);
+
 int mt_build_pairs(mt_ctx* c, int64_t* n_cand_out, int64_t* n_pairs_out, void* stream) {
   if (!c) return fail(MT_EINVAL, "mt_build_pairs: null ctx");
   if (!c->side[0].set || !c->side[1].set) return fail(MT_ESTATE, "mt_build_pairs: upload both sides first");
@@ -238,6 +243,7 @@ int mt_build_pairs(mt_ctx* c, int64_t* n_cand_out, int64_t* n_pairs_out, void* s
   c->last_stream = st;
   c->have_pairs = c->have_pattern = c->have_master_index = false;
   ++c->coord_gen;
+  c->side[0].nrm = nullptr;  // element frames until the nodal field is built below
   const DeviceMesh& S = c->side[0];
   const DeviceMesh& M = c->side[1];
   const int32_t ns = S.n_el, nm = M.n_el;
@@ -264,6 +270,14 @@ int mt_build_pairs(mt_ctx* c, int64_t* n_cand_out, int64_t* n_pairs_out, void* s
   MT_HIP(hipMemcpyAsync(&hr, red, sizeof(hr), hipMemcpyDeviceToHost, st));
   MT_HIP(hipStreamSynchronize(st));
   if (hr.bad_index) return fail(MT_EINVAL, "mt_build_pairs: connectivity index out of range");
+  if (c->params.normals == MT_NORMALS_NODAL) {
+    // connectivity checked: the continuous normal field, then the slave
+    // frames of the candidate pass again with its plane normals
+    PhaseTimer t(c, MT_T_PREP, st);
+    int rc = ensure_normals(c, st);
+    if (rc) return rc;
+    MT_HIP(launch_prep(S, true, c->box_s.as<double>(), c->sdata.as<double>(), nullptr, c->prep_part.as<double>(), st));
+  }
   grid_from_reduce(hr, c->params.delta, c->params.bin_size, c->grid);
   const Grid& g = c->grid;
 
@@ -431,6 +445,30 @@ static int build_incidence(mt_ctx* c, const DeviceMesh& mesh, Buf& cntb, Buf& of
   return MT_OK;
 }
 
+// The slave side's continuous normal field for the current coordinates (the
+// element plane normals the frames use), or none for element normals.
+static int ensure_normals(mt_ctx* c, hipStream_t st) {
+  DeviceMesh& S = c->side[0];
+  if (c->params.normals != MT_NORMALS_NODAL) {
+    S.nrm = nullptr;
+    return MT_OK;
+  }
+  if (S.nrm && c->nrm_gen == c->coord_gen) return MT_OK;
+  MT_HIP(ensure(c->scan_tmp, 1 << 20));
+  if (!c->have_inc[0]) {
+    int rc = build_incidence(c, S, c->inc_cnt, c->inc_off, c->inc_cur, c->inc_list, st);
+    if (rc) return rc;
+    c->have_inc[0] = true;
+  }
+  MT_HIP(ensure(c->nrm_node, sizeof(double) * 4 * (size_t)std::max(S.n_nodes, 1)));
+  MT_HIP(ensure(c->nrm_el, sizeof(double) * 4 * (size_t)std::max(S.n_el, 1)));
+  MT_HIP(launch_normals(S, c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(), c->nrm_node.as<double>(),
+                        c->nrm_el.as<double>(), st));
+  S.nrm = c->nrm_el.as<double>();
+  c->nrm_gen = c->coord_gen;
+  return MT_OK;
+}
+
 int mt_csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, void* stream) {
   if (!c) return fail(MT_EINVAL, "mt_csr_pattern: null ctx");
   if (!c->have_pairs) return fail(MT_ESTATE, "mt_csr_pattern: build the pair list first");
@@ -527,6 +565,7 @@ int mt_integrate(mt_ctx* c, double* D_val, double* M_val, double* gap, void* str
   MT_HIP(ensure(c->blk, sizeof(double) * 36 * (size_t)std::max<int64_t>(np, 1)));
   {
     int rc = ensure_poly(c);
+    if (!rc) rc = ensure_normals(c, st);
     if (rc) return rc;
   }
   const PolyBuf poly = poly_buf(c);
@@ -632,8 +671,11 @@ int mt_backward(mt_ctx* c, const double* W_D, const double* W_M, const double* w
   MT_HIP(ensure(c->gpair, sizeof(double) * 24 * (size_t)std::max<int64_t>(np, 1)));
   {
     int rc = ensure_poly(c);
+    if (!rc) rc = ensure_normals(c, st);
     if (rc) return rc;
   }
+  const bool nodal = c->params.normals == MT_NORMALS_NODAL;
+  if (nodal) MT_HIP(ensure(c->gn0, sizeof(double) * 3 * (size_t)std::max<int64_t>(np, 1)));
   const PolyBuf poly = poly_buf(c);
   if (c->poly_gen != c->coord_gen) {
     PhaseTimer t(c, MT_T_PAIR_POLY, st);
@@ -654,8 +696,8 @@ int mt_backward(mt_ctx* c, const double* W_D, const double* W_M, const double* w
     MT_HIP(launch_pair_bwd(S, M, kp, c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), np, poly,
                            c->mp_pos.as<int32_t>(),
                            c->posD.as<int32_t>(), S.n_el, c->posM.as<int32_t>(), W_D, W_M, w_g,
-                           kp.dual ? c->blk.as<double>() : nullptr, c->gpair.as<double>(), np,
-                           c->counters.as<Counters>(), st));
+                           kp.dual ? c->blk.as<double>() : nullptr, c->gpair.as<double>(),
+                           nodal ? c->gn0.as<double>() : nullptr, np, c->counters.as<Counters>(), st));
   }
   PhaseTimer t(c, MT_T_GRAD_REDUCE, st);
   MT_HIP(launch_grad_slave(c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(), S.n_nodes, c->pair_off.as<int32_t>(),
@@ -663,6 +705,16 @@ int mt_backward(mt_ctx* c, const double* W_D, const double* W_M, const double* w
   const int32_t* mo = c->mp_off.as<int32_t>();
   MT_HIP(launch_grad_master(c->minc_off.as<int32_t>(), c->minc_list.as<int32_t>(), M.n_nodes, mo, mo + M.n_el,
                             c->gpair.as<double>(), np, gXm, st));
+  if (nodal) {
+    // through the element plane normals to the nodal normals and the
+    // coordinates of the neighbouring elements
+    MT_HIP(ensure(c->nrm_sb, sizeof(double) * 4 * (size_t)std::max(S.n_el, 1)));
+    MT_HIP(ensure(c->nrm_ub, sizeof(double) * 4 * (size_t)std::max(S.n_nodes, 1)));
+    MT_HIP(ensure(c->nrm_cg, sizeof(double) * 12 * (size_t)std::max(S.n_el, 1)));
+    MT_HIP(launch_normal_chain(S, c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(), c->pair_off.as<int32_t>(),
+                               c->gn0.as<double>(), np, c->nrm_node.as<double>(), c->nrm_el.as<double>(),
+                               c->nrm_sb.as<double>(), c->nrm_ub.as<double>(), c->nrm_cg.as<double>(), gXs, st));
+  }
   return MT_OK;
 }
 

@@ -27,11 +27,13 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x)
 // Debar_j = G_jj / De_j and Mebar_jk = -(sum_m Me^-1_jm De_m G_mk) / De_k,
 // then through the Jacobian determinants at the Gauss points to the projected
 // slave nodes, and through the projection and the frame to the slave
-// coordinates (added to Xsb).
-__device__ __forceinline__ void dual_adjoint(const double Xs[4][3], const double G[16], double Xsb[4][3]) {
+// coordinates (added to Xsb) and, with the continuous normal field (ns), to
+// the element's plane normal (added to n0b).
+__device__ __forceinline__ void dual_adjoint(const double Xs[4][3], const double* ns, const double G[16],
+                                             double Xsb[4][3], double n0b[3]) {
 #pragma clang fp contract(fast)
   double f[12];
-  slave_frame(Xs, f);
+  slave_frame_p(Xs, ns, f);
   V2 S[4];
   double hs[4], As, hmax;
   slave_setup(Xs, f, S, hs, As, hmax);
@@ -139,7 +141,7 @@ __device__ __forceinline__ void dual_adjoint(const double Xs[4][3], const double
     nb[4 + k][0] = nb[4 + k][1] = nb[4 + k][2] = 0.0;
   }
   double gsb[4][3], gmb[4][3];
-  projection_adjoint(Xs, Xs, nb, gsb, gmb);
+  projection_adjoint(Xs, Xs, ns, nb, gsb, gmb, n0b);
 #pragma unroll
   for (int k = 0; k < 4; ++k)
 #pragma unroll
@@ -170,7 +172,8 @@ __global__ __launch_bounds__(BSC) __attribute__((amdgpu_waves_per_eu(2))) void k
                                                    const int32_t* __restrict__ posD, const int32_t* __restrict__ posM,
                                                    const double* __restrict__ W_D, const double* __restrict__ W_M,
                                                    const double* __restrict__ w_g, const double* __restrict__ blk,
-                                                   double* __restrict__ gpair, int64_t stride, Counters* cnt) {
+                                                   double* __restrict__ gpair, double* __restrict__ gn0,
+                                                   int64_t stride, Counters* cnt) {
   const int64_t p = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * BSC + threadIdx.x;
   unsigned noconv = 0;
   if (p < n_pairs) {
@@ -199,11 +202,15 @@ __global__ __launch_bounds__(BSC) __attribute__((amdgpu_waves_per_eu(2))) void k
       load_nodes(S.x, S.y, S.z, csn, Xs);
 #pragma unroll
       for (int k = 0; k < 4; ++k) Xd[k][0] = Xd[k][1] = Xd[k][2] = 0.0;
-      dual_adjoint(Xs, G, Xd);
+      double n0d[3] = {0.0, 0.0, 0.0};
+      dual_adjoint(Xs, elem_nrm(S, s), G, Xd, n0d);
 #pragma unroll
       for (int k = 0; k < 4; ++k)
 #pragma unroll
         for (int d = 0; d < 3; ++d) gpair[(int64_t)(3 * k + d) * stride + p] = Xd[k][d];
+      if (gn0)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) gn0[(int64_t)d * stride + p] = n0d[d];
     }
     double WD[16], WM[16], wg[4];
     {
@@ -211,9 +218,16 @@ __global__ __launch_bounds__(BSC) __attribute__((amdgpu_waves_per_eu(2))) void k
       const int4 c2 = DUAL ? int4{launder(csn.x), launder(csn.y), launder(csn.z), launder(csn.w)} : csn;
       gather_weights(s2, p, c2, posD, n_s, posM, stride, W_D, W_M, w_g, WD, WM, wg);
     }
-    double Xsb[4][3], Xmb[4][3];
-    pair_backward<NQ, DUAL>(S, csn, M, load_conn(M.conn, pair_m[p]), gpoly(poly, p), poly.nf[p], kp, WD, WM, wg, Xsb, Xmb,
-                      noconv);
+    double Xsb[4][3], Xmb[4][3], n0b[3];
+    pair_backward<NQ, DUAL>(S, s, csn, M, load_conn(M.conn, pair_m[p]), gpoly(poly, p), poly.nf[p], kp, WD, WM, wg,
+                            Xsb, Xmb, n0b, noconv);
+    if (gn0)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        double v = n0b[d];
+        if (DUAL) v += gn0[(int64_t)d * stride + p];
+        gn0[(int64_t)d * stride + p] = v;
+      }
     const int64_t q = mpos[p];
 #pragma unroll
     for (int k = 0; k < 4; ++k)
@@ -235,14 +249,15 @@ hipError_t launch_pair_bwd(const DeviceMesh& S, const DeviceMesh& M, const KPara
                            const int32_t* pair_m, int64_t n_pairs, const PolyBuf& poly, const int32_t* mpos,
                            const int32_t* posD, int32_t n_s_el,
                            const int32_t* posM, const double* W_D, const double* W_M, const double* w_g,
-                           const double* blk, double* gpair, int64_t stride, Counters* cnt, hipStream_t s) {
+                           const double* blk, double* gpair, double* gn0, int64_t stride, Counters* cnt,
+                           hipStream_t s) {
   if (n_pairs == 0) return hipSuccess;
   const unsigned nb = xcd_grid((unsigned)((n_pairs + BSC - 1) / BSC));
-  const MeshPtrs ms{S.x, S.y, S.z, S.conn}, mm{M.x, M.y, M.z, M.conn};
+  const MeshPtrs ms{S.x, S.y, S.z, S.conn, S.nrm}, mm{M.x, M.y, M.z, M.conn, nullptr};
   auto* k = kp.rule == 3 ? (kp.dual ? k_pair_bwd<3, true> : k_pair_bwd<3, false>)
                          : (kp.dual ? k_pair_bwd<7, true> : k_pair_bwd<7, false>);
   hipLaunchKernelGGL(k, dim3(nb), dim3(BSC), 0, s, ms, n_s_el, mm, kp, pair_s, pair_m, n_pairs, poly, mpos, posD, posM,
-                     W_D, W_M, w_g, blk, gpair, stride, cnt);
+                     W_D, W_M, w_g, blk, gpair, gn0, stride, cnt);
   return hipGetLastError();
 }
 

@@ -110,7 +110,7 @@ __global__ __launch_bounds__(BSZ) void k_batch_poly(const BatchInst* __restrict_
       double Xs[4][3], Xm[4][3];
       load_nodes(I.S.x, I.S.y, I.S.z, load_conn(I.S.conn, I.pair_s[p]), Xs);
       load_nodes(I.M.x, I.M.y, I.M.z, load_conn(I.M.conn, I.pair_m[p]), Xm);
-      store_pair_polygon(Xs, Xm, I.kp, P, I.poly, p);
+      store_pair_polygon(Xs, Xm, elem_nrm(I.S, I.pair_s[p]), I.kp, P, I.poly, p);
     }
   }
 }
@@ -127,7 +127,8 @@ __global__ __launch_bounds__(BSZ) __attribute__((amdgpu_waves_per_eu(3))) void k
     const BatchInst& I = inst[w.inst];
     for (int64_t p = w.begin + (int)threadIdx.x; p < w.end; p += BSZ) {
       double D[16], Mv[16], g[4];
-      pair_forward<NQ, DUAL>(I.S, load_conn(I.S.conn, I.pair_s[p]), I.M, load_conn(I.M.conn, I.pair_m[p]),
+      const int s = I.pair_s[p];
+      pair_forward<NQ, DUAL>(I.S, s, load_conn(I.S.conn, s), I.M, load_conn(I.M.conn, I.pair_m[p]),
                              gpoly(I.poly, p), I.poly.nf[p], I.kp, D, Mv, g, noconv);
       const int64_t st = I.n_pairs;
 #pragma unroll
@@ -165,9 +166,9 @@ __global__ __launch_bounds__(BSZ) __attribute__((amdgpu_waves_per_eu(2))) void k
       wg[1] = I.w_g[csn.y];
       wg[2] = I.w_g[csn.z];
       wg[3] = I.w_g[csn.w];
-      double Xsb[4][3], Xmb[4][3];
-      pair_backward<NQ, false>(I.S, csn, I.M, load_conn(I.M.conn, I.pair_m[p]), gpoly(I.poly, p), I.poly.nf[p], I.kp, WD,
-                        WM, wg, Xsb, Xmb, noconv);
+      double Xsb[4][3], Xmb[4][3], n0b[3];
+      pair_backward<NQ, false>(I.S, s, csn, I.M, load_conn(I.M.conn, I.pair_m[p]), gpoly(I.poly, p), I.poly.nf[p],
+                               I.kp, WD, WM, wg, Xsb, Xmb, n0b, noconv);
       const int64_t q = I.mpos[p];
 #pragma unroll
       for (int k = 0; k < 4; ++k)
@@ -493,8 +494,8 @@ int mt_batch_build(mt_batch* b, const mt_batch_tuning* tuning, void* stream) {
     if (!c->have_pattern) return bfail(MT_ESTATE, "mt_batch_build: an instance has no pattern");
     if (c->params.rule != p0.rule || c->params.lm_basis != p0.lm_basis)
       return bfail(MT_EINVAL, "mt_batch_build: all instances must share the rule and the basis");
-    if (c->params.element_rule != 0)
-      return bfail(MT_EUNSUPPORTED, "mt_batch_build: segment-based integration only");
+    if (c->params.element_rule != 0 || c->params.normals != MT_NORMALS_ELEMENT)
+      return bfail(MT_EUNSUPPORTED, "mt_batch_build: segment-based integration with element normals only");
   }
   b->nq = p0.rule;
   b->dual = p0.lm_basis == MT_BASIS_DUAL;

@@ -131,7 +131,7 @@ __global__ __launch_bounds__(BSE) __attribute__((amdgpu_waves_per_eu(3))) void k
   if (valid) {
     double Xs[4][3], f[12];
     load_nodes(S.x, S.y, S.z, load_conn(S.conn, s), Xs);
-    slave_frame(Xs, f);
+    slave_frame_p(Xs, elem_nrm(S, s), f);
     V2 Sp[4], Mn[4];
     double hs[4], As, hmax;
     slave_setup(Xs, f, Sp, hs, As, hmax);
@@ -190,8 +190,9 @@ __global__ __launch_bounds__(BSE) __attribute__((amdgpu_waves_per_eu(3))) void k
         } else {
           // earlier pair outside the block: its quad from reloaded nodes
           double Xs2[4][3], f2[12];
-          load_nodes(S.x, S.y, S.z, load_conn(S.conn, launder(s)), Xs2);
-          slave_frame(Xs2, f2);
+          const int s2 = launder(s);
+          load_nodes(S.x, S.y, S.z, load_conn(S.conn, s2), Xs2);
+          slave_frame_p(Xs2, elem_nrm(S, s2), f2);
           V2 En[4];
           master_quad(M, pair_m[pp], f2, Eo, En);
         }
@@ -226,12 +227,13 @@ __global__ __launch_bounds__(BSE) __attribute__((amdgpu_waves_per_eu(3))) void k
     // heights from reloaded nodes rather than kept through the loop
     double D[16], Mv[16], g[4];
     {
-      const int4 cs = load_conn(S.conn, launder(s));
+      const int s2 = launder(s);
+      const int4 cs = load_conn(S.conn, s2);
       const int4 cm = load_conn(M.conn, launder(pair_m[p]));
       double Xs2[4][3], Xm2[4][3], f2[12];
       load_nodes(S.x, S.y, S.z, cs, Xs2);
       load_nodes(M.x, M.y, M.z, cm, Xm2);
-      slave_frame(Xs2, f2);
+      slave_frame_p(Xs2, elem_nrm(S, s2), f2);
       V2 S2[4], M2[4];
       double hs[4], hm[4];
       pair_project(Xs2, Xm2, f2, S2, M2, hs, hm);
@@ -303,7 +305,7 @@ hipError_t launch_elem_fwd(const DeviceMesh& S, const DeviceMesh& M, const KPara
   std::call_once(once, [] {
     for (int n = 1; n <= 8; ++n) gauss_table(n, tabs[n]);
   });
-  const MeshPtrs ms{S.x, S.y, S.z, S.conn}, mm{M.x, M.y, M.z, M.conn};
+  const MeshPtrs ms{S.x, S.y, S.z, S.conn, S.nrm}, mm{M.x, M.y, M.z, M.conn, nullptr};
   const unsigned nb = xcd_grid((unsigned)((n_pairs + BSE - 1) / BSE));
   if (kp.dual)
     k_elem_fwd<true><<<nb, BSE, 0, s>>>(ms, mm, kp, tabs[kp.elem], pair_s, pair_m, pair_off, n_pairs, blk, stride, cnt);

@@ -36,6 +36,9 @@ struct MeshPtrs {
   const double* y;
   const double* z;
   const int32_t* conn;
+  // slave side with the continuous normal field: per element the unit plane
+  // normal and the length it was normalised from, nrm[4 e + 0..3]; else null
+  const double* nrm;
 };
 
 // Blocks of a grid are dispatched round-robin over the 8 XCDs of an MI355X;
@@ -90,6 +93,45 @@ __device__ __forceinline__ void slave_frame(const double X[4][3], double f[12]) 
   f[9] = f[4] * f[8] - f[5] * f[7];
   f[10] = f[5] * f[6] - f[3] * f[8];
   f[11] = f[3] * f[7] - f[4] * f[6];
+}
+
+// Frame with a given unit plane normal n (the continuous normal field at the
+// element centre): centre x0, n0 = n, t1 = the part of g1 orthogonal to n,
+// normalised, t2 = n0 x t1.
+__device__ __forceinline__ void slave_frame_n(const double X[4][3], const double n[3], double f[12]) {
+  double g1[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    f[d] = 0.25 * (((X[0][d] + X[1][d]) + X[2][d]) + X[3][d]);
+    g1[d] = 0.25 * (((X[1][d] - X[0][d]) + X[2][d]) - X[3][d]);
+    f[3 + d] = n[d];
+  }
+  const double gn = (g1[0] * n[0] + g1[1] * n[1]) + g1[2] * n[2];
+  double w[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) w[d] = g1[d] - gn * n[d];
+  const double lw = sqrt((w[0] * w[0] + w[1] * w[1]) + w[2] * w[2]);
+  f[6] = w[0] / lw;
+  f[7] = w[1] / lw;
+  f[8] = w[2] / lw;
+  f[9] = f[4] * f[8] - f[5] * f[7];
+  f[10] = f[5] * f[6] - f[3] * f[8];
+  f[11] = f[3] * f[7] - f[4] * f[6];
+}
+
+// Frame of a slave element: from the continuous normal field when nrm (the
+// element's entry of MeshPtrs::nrm) is given, else from its own geometry.
+__device__ __forceinline__ void slave_frame_p(const double X[4][3], const double* nrm, double f[12]) {
+  if (nrm) {
+    const double n[3] = {nrm[0], nrm[1], nrm[2]};
+    slave_frame_n(X, n, f);
+  } else {
+    slave_frame(X, f);
+  }
+}
+
+__device__ __forceinline__ const double* elem_nrm(const MeshPtrs& S, int s) {
+  return S.nrm ? S.nrm + 4 * (int64_t)s : nullptr;
 }
 
 // In-plane coordinates and height of one node.

@@ -27,6 +27,9 @@ struct DeviceMesh {
   const double* y = nullptr;
   const double* z = nullptr;
   const int32_t* conn = nullptr;  // [n_el][4]
+  // slave side with the continuous normal field: element plane normals
+  // [n_el][4] (unit normal, length of the sum it was normalised from)
+  const double* nrm = nullptr;
   int32_t n_nodes = 0;
   int32_t n_el = 0;
   bool set = false;
@@ -158,6 +161,11 @@ struct mt_ctx {
   int64_t coord_gen = 0, poly_gen = -1;
   int64_t pattern_gen = 0;  // counts completed mt_csr_pattern calls
   // forward / backward staging
+  mt::Buf nrm_node;        // [n_s_nodes][4] nodal normals (continuous normal field)
+  mt::Buf nrm_el;          // [n_s_el][4] element plane normals
+  mt::Buf gn0;             // [3][n_pairs] dL/dn0 per pair
+  mt::Buf nrm_sb, nrm_ub, nrm_cg;
+  int64_t nrm_gen = -1;    // coord_gen of nrm_node / nrm_el
   mt::Buf blk;             // [36][n_pairs]
   int64_t blk_gen = -1;    // coord_gen of the blocks in blk (mt_integrate)
   mt::Buf gpair;           // [24][n_pairs]
@@ -264,11 +272,25 @@ hipError_t launch_grad_master(const int32_t* inc_off, const int32_t* inc_list, i
 // Backward of every pair: slave gradient components at gpair[c * stride + p],
 // master components at gpair[(12 + c) * stride + mpos[p]].  With the dual
 // basis, blk holds the pairs' dual blocks [36][stride] (the gradient through
-// the dual coefficients needs them); unused otherwise.
+// the dual coefficients needs them); unused otherwise.  With the continuous
+// normal field (S.nrm), gn0[d * stride + p] receives the gradient with
+// respect to the slave element's plane normal; else gn0 is null.
 hipError_t launch_pair_bwd(const DeviceMesh& S, const DeviceMesh& M, const KParams& kp, const int32_t* pair_s, const int32_t* pair_m,
                            int64_t n_pairs, const PolyBuf& poly, const int32_t* mpos, const int32_t* posD, int32_t n_s_el, const int32_t* posM,
                            const double* W_D, const double* W_M, const double* w_g, const double* blk,
-                           double* gpair, int64_t stride, Counters* cnt, hipStream_t s);
+                           double* gpair, double* gn0, int64_t stride, Counters* cnt, hipStream_t s);
+
+// ---- continuous normal field (mt_normals.hip) --------------------------------
+// Nodal normals nn[4 a + 0..3] (unit normal, length before normalising) and
+// element plane normals ne[4 e + 0..3] of the slave side.
+hipError_t launch_normals(const DeviceMesh& S, const int32_t* inc_off, const int32_t* inc_list, double* nn,
+                          double* ne, hipStream_t s);
+// Adds to gX (SoA [3][n_nodes]) the gradient through the element plane
+// normals, from dL/dn0 per pair (gn0[d * stride + p]); sb, ub, cg scratch of
+// 4 n_el, 4 n_nodes and 12 n_el doubles.
+hipError_t launch_normal_chain(const DeviceMesh& S, const int32_t* inc_off, const int32_t* inc_list,
+                               const int32_t* pair_off, const double* gn0, int64_t stride, const double* nn,
+                               const double* ne, double* sb, double* ub, double* cg, double* gX, hipStream_t s);
 
 KParams kparams(const mt_params& p);
 // Node incidence of the master side and the pairs-by-master permutation

@@ -71,10 +71,11 @@ __device__ __forceinline__ void poly_store(const LdsPoly<true>& P, int res, int 
 
 // Frame, projection, orientation, clip and cleanup of pair p; stores the
 // polygon and its provenance.
-__device__ __forceinline__ void store_pair_polygon(const double Xs[4][3], const double Xm[4][3], const KParams& kp,
-                                                   const LdsPoly<true>& P, const PolyBuf& out, int64_t p) {
+__device__ __forceinline__ void store_pair_polygon(const double Xs[4][3], const double Xm[4][3], const double* ns,
+                                                   const KParams& kp, const LdsPoly<true>& P, const PolyBuf& out,
+                                                   int64_t p) {
   double f[12];
-  slave_frame(Xs, f);
+  slave_frame_p(Xs, ns, f);
   V2 S[4], Mn[4];
   double hs[4], hm[4];
   int res, st;
@@ -443,12 +444,15 @@ __device__ __forceinline__ void vertex_adjoint(uint8_t lab, double xu, double xv
 // (X - x0).n0) of the 8 nodes (slave 0..3, master 4..7) and of the slave
 // frame (x0, n0 = g1 x g2 / |g1 x g2|, t1 = g1 / |g1|, t2 = n0 x t1):
 // given nb[k] = (ubar, vbar, hbar) of node k, writes the coordinate
-// gradients Xsb (slave) and Xmb (master).
-__device__ __forceinline__ void projection_adjoint(const double Xs[4][3], const double Xm[4][3],
-                                                   const double nb[8][3], double Xsb[4][3], double Xmb[4][3]) {
+// gradients Xsb (slave) and Xmb (master).  With the continuous normal field
+// (ns, the element's plane normal: n0 = ns, t1 = the part of g1 orthogonal to
+// n0, normalised) the gradient with respect to n0 is added to n0b instead.
+__device__ __forceinline__ void projection_adjoint(const double Xs[4][3], const double Xm[4][3], const double* ns,
+                                                   const double nb[8][3], double Xsb[4][3], double Xmb[4][3],
+                                                   double n0b_out[3]) {
 #pragma clang fp contract(fast)
   double f[12];
-  slave_frame(Xs, f);
+  slave_frame_p(Xs, ns, f);
   double x0b[3] = {0, 0, 0}, t1b[3] = {0, 0, 0}, t2b[3] = {0, 0, 0}, n0b[3] = {0, 0, 0};
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
@@ -475,13 +479,41 @@ __device__ __forceinline__ void projection_adjoint(const double Xs[4][3], const 
   t1b[0] += t2b[1] * n0[2] - t2b[2] * n0[1];
   t1b[1] += t2b[2] * n0[0] - t2b[0] * n0[2];
   t1b[2] += t2b[0] * n0[1] - t2b[1] * n0[0];
-  // frame from the slave nodes: g1, g2, n = g1 x g2, n0 = n/|n|, t1 = g1/|g1|
   double g1[3], g2[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     g1[d] = 0.25 * (((Xs[1][d] - Xs[0][d]) + Xs[2][d]) - Xs[3][d]);
     g2[d] = 0.25 * (((Xs[2][d] + Xs[3][d]) - Xs[0][d]) - Xs[1][d]);
   }
+  if (ns) {
+    // t1 = w / |w|, w = g1 - (g1.n0) n0; n0 is an input
+    const double gn = g1[0] * n0[0] + g1[1] * n0[1] + g1[2] * n0[2];
+    double w[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) w[d] = g1[d] - gn * n0[d];
+    const double rlw = 1.0 / sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    const double tt = t1[0] * t1b[0] + t1[1] * t1b[1] + t1[2] * t1b[2];
+    double wb[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) wb[d] = (t1b[d] - t1[d] * tt) * rlw;
+    const double nw = n0[0] * wb[0] + n0[1] * wb[1] + n0[2] * wb[2];
+    double g1b[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      g1b[d] = wb[d] - n0[d] * nw;
+      n0b_out[d] += n0b[d] - g1[d] * nw - gn * wb[d];
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double c0 = 0.25 * x0b[d], c1 = 0.25 * g1b[d];
+      Xsb[0][d] += c0 - c1;
+      Xsb[1][d] += c0 + c1;
+      Xsb[2][d] += c0 + c1;
+      Xsb[3][d] += c0 - c1;
+    }
+    return;
+  }
+  // frame from the slave nodes: g1, g2, n = g1 x g2, n0 = n/|n|, t1 = g1/|g1|
   const double nn[3] = {g1[1] * g2[2] - g1[2] * g2[1], g1[2] * g2[0] - g1[0] * g2[2], g1[0] * g2[1] - g1[1] * g2[0]};
   const double rln = 1.0 / sqrt(nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2]);
   const double rlg = 1.0 / sqrt(g1[0] * g1[0] + g1[1] * g1[1] + g1[2] * g1[2]);
@@ -520,10 +552,10 @@ __device__ __forceinline__ void projection_adjoint(const double Xs[4][3], const 
 // intersections, each vertex once: the fan's pending vertex is carried to the
 // next triangle), the projection and the slave frame.
 template <int NQ, bool DUAL>
-__device__ __forceinline__ void pair_backward(const MeshPtrs& SM, int4 cs, const MeshPtrs& MM, int4 cm,
+__device__ __forceinline__ void pair_backward(const MeshPtrs& SM, int s, int4 cs, const MeshPtrs& MM, int4 cm,
                                               const GPoly& P, int nf, const KParams& kp, const double WD_in[16],
                                               const double WM_in[16], const double wg_in[4], double Xsb[4][3],
-                                              double Xmb[4][3], unsigned& noconv) {
+                                              double Xmb[4][3], double n0b[3], unsigned& noconv) {
   const int n = nf & 0x7f;
   const bool flip = (nf & 0x80) != 0;
   QMap ms, mm;
@@ -533,7 +565,7 @@ __device__ __forceinline__ void pair_backward(const MeshPtrs& SM, int4 cs, const
     double Xs[4][3], Xm[4][3], f[12];
     load_nodes(SM.x, SM.y, SM.z, cs, Xs);
     load_nodes(MM.x, MM.y, MM.z, cm, Xm);
-    slave_frame(Xs, f);
+    slave_frame_p(Xs, elem_nrm(SM, s), f);
     V2 S[4], Mn[4];
     double hs[4], hm[4];
     pair_project(Xs, Xm, f, S, Mn, hs, hm);
@@ -739,7 +771,8 @@ __device__ __forceinline__ void pair_backward(const MeshPtrs& SM, int4 cs, const
     double Xs[4][3], Xm[4][3];
     load_nodes(SM.x, SM.y, SM.z, cs2, Xs);
     load_nodes(MM.x, MM.y, MM.z, cm2, Xm);
-    projection_adjoint(Xs, Xm, nb, Xsb, Xmb);
+    n0b[0] = n0b[1] = n0b[2] = 0.0;
+    projection_adjoint(Xs, Xm, elem_nrm(SM, launder(s)), nb, Xsb, Xmb, n0b);
   }
 }
 
@@ -751,7 +784,7 @@ namespace mt {
 // then the quadrature of pair_integrate.  The heights are recomputed after
 // the quadrature from reloaded nodes rather than kept in registers.
 template <int NQ, bool DUAL>
-__device__ __forceinline__ void pair_forward(const MeshPtrs& SM, int4 cs, const MeshPtrs& MM, int4 cm,
+__device__ __forceinline__ void pair_forward(const MeshPtrs& SM, int s, int4 cs, const MeshPtrs& MM, int4 cm,
                                              const GPoly& P, int nf, const KParams& kp, double D[16], double M[16],
                                              double g[4], unsigned& noconv) {
   QMap ms, mm;
@@ -759,7 +792,7 @@ __device__ __forceinline__ void pair_forward(const MeshPtrs& SM, int4 cs, const 
     double Xs[4][3], Xm[4][3], f[12];
     load_nodes(SM.x, SM.y, SM.z, cs, Xs);
     load_nodes(MM.x, MM.y, MM.z, cm, Xm);
-    slave_frame(Xs, f);
+    slave_frame_p(Xs, elem_nrm(SM, s), f);
     V2 S[4], Mn[4];
     double hs[4], hm[4];
     pair_project(Xs, Xm, f, S, Mn, hs, hm);
@@ -772,7 +805,7 @@ __device__ __forceinline__ void pair_forward(const MeshPtrs& SM, int4 cs, const 
     double Xs[4][3], Xm[4][3], f[12];
     load_nodes(SM.x, SM.y, SM.z, cs2, Xs);
     load_nodes(MM.x, MM.y, MM.z, cm2, Xm);
-    slave_frame(Xs, f);
+    slave_frame_p(Xs, elem_nrm(SM, launder(s)), f);
     V2 S[4], Mn[4];
     pair_project(Xs, Xm, f, S, Mn, hs, hm);
   };

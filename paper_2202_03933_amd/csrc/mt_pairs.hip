@@ -148,10 +148,11 @@ __global__ __launch_bounds__(BSC) void k_pair_poly(MeshPtrs S, MeshPtrs M, KPara
   const int64_t p = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * BSC + threadIdx.x;
   if (p >= n_pairs) return;
   double Xs[4][3], Xm[4][3];
-  load_nodes(S.x, S.y, S.z, load_conn(S.conn, pair_s[p]), Xs);
+  const int s = pair_s[p];
+  load_nodes(S.x, S.y, S.z, load_conn(S.conn, s), Xs);
   load_nodes(M.x, M.y, M.z, load_conn(M.conn, pair_m[p]), Xm);
   const LdsPoly<true> P{su + threadIdx.x, sv + threadIdx.x, sl + threadIdx.x, se + threadIdx.x, BSC};
-  store_pair_polygon(Xs, Xm, kp, P, out, p);
+  store_pair_polygon(Xs, Xm, elem_nrm(S, s), kp, P, out, p);
 }
 
 // Segment-based integration of every pair from its stored polygon; local
@@ -169,7 +170,8 @@ __global__ __launch_bounds__(BSC) __attribute__((amdgpu_waves_per_eu(3))) void k
   unsigned noconv = 0;
   if (p < n_pairs) {
     double D[16], Mv[16], g[4];
-    pair_forward<NQ, DUAL>(S, load_conn(S.conn, pair_s[p]), M, load_conn(M.conn, pair_m[p]), gpoly(poly, p),
+    const int s = pair_s[p];
+    pair_forward<NQ, DUAL>(S, s, load_conn(S.conn, s), M, load_conn(M.conn, pair_m[p]), gpoly(poly, p),
                            poly.nf[p], kp, D, Mv, g, noconv);
 #pragma unroll
     for (int k = 0; k < 16; ++k) blk[(int64_t)k * stride + p] = D[k];
@@ -227,7 +229,7 @@ hipError_t launch_pair_poly(const DeviceMesh& S, const DeviceMesh& M, const KPar
                             const int32_t* pair_m, int64_t n_pairs, const PolyBuf& poly, hipStream_t s) {
   if (n_pairs == 0) return hipSuccess;
   const unsigned nb = xcd_grid((unsigned)((n_pairs + BSC - 1) / BSC));
-  const MeshPtrs ms{S.x, S.y, S.z, S.conn}, mm{M.x, M.y, M.z, M.conn};
+  const MeshPtrs ms{S.x, S.y, S.z, S.conn, S.nrm}, mm{M.x, M.y, M.z, M.conn, nullptr};
   k_pair_poly<<<nb, BSC, 0, s>>>(ms, mm, kp, pair_s, pair_m, n_pairs, poly);
   return hipGetLastError();
 }
@@ -237,7 +239,7 @@ hipError_t launch_pair_fwd(const DeviceMesh& S, const DeviceMesh& M, const KPara
                            Counters* cnt, hipStream_t s) {
   if (n_pairs == 0) return hipSuccess;
   const unsigned nb = xcd_grid((unsigned)((n_pairs + BSC - 1) / BSC));
-  const MeshPtrs ms{S.x, S.y, S.z, S.conn}, mm{M.x, M.y, M.z, M.conn};
+  const MeshPtrs ms{S.x, S.y, S.z, S.conn, S.nrm}, mm{M.x, M.y, M.z, M.conn, nullptr};
   if (kp.rule == 3) {
     if (kp.dual) k_pair_fwd<3, true><<<nb, BSC, 0, s>>>(ms, mm, kp, pair_s, pair_m, n_pairs, poly, blk, stride, cnt);
     else k_pair_fwd<3, false><<<nb, BSC, 0, s>>>(ms, mm, kp, pair_s, pair_m, n_pairs, poly, blk, stride, cnt);

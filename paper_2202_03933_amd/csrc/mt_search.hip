@@ -57,6 +57,7 @@ __device__ __forceinline__ T wave_min(T x) {
 __global__ __launch_bounds__(BS) void k_prep(const double* __restrict__ x, const double* __restrict__ y,
                                               const double* __restrict__ z, const int32_t* __restrict__ conn,
                                               int32_t n_el, int32_t n_nodes, int slave,
+                                              const double* __restrict__ nrm,
                                               double* __restrict__ box, double* __restrict__ sd,
                                               double* __restrict__ md, double* __restrict__ part) {
   __shared__ double sh[BS / 64][8];
@@ -94,7 +95,7 @@ __global__ __launch_bounds__(BS) void k_prep(const double* __restrict__ x, const
       }
       double f[12], hs[4], As, hmax;
       V2 S[4];
-      slave_frame(X, f);
+      slave_frame_p(X, nrm ? nrm + 4 * (int64_t)e : nullptr, f);
       slave_setup(X, f, S, hs, As, hmax);
 #pragma unroll
       for (int k = 0; k < 12; ++k) sd[(int64_t)k * n_el + e] = f[k];
@@ -394,8 +395,8 @@ int prep_blocks(int32_t n_el) { return n_el == 0 ? 0 : std::min(2048, (n_el + BS
 hipError_t launch_prep(const DeviceMesh& m, bool slave, double* box, double* sd, double* md, double* part,
                        hipStream_t s) {
   if (m.n_el == 0) return hipSuccess;
-  k_prep<<<prep_blocks(m.n_el), BS, 0, s>>>(m.x, m.y, m.z, m.conn, m.n_el, m.n_nodes, slave ? 1 : 0, box, sd, md,
-                                             part);
+  k_prep<<<prep_blocks(m.n_el), BS, 0, s>>>(m.x, m.y, m.z, m.conn, m.n_el, m.n_nodes, slave ? 1 : 0,
+                                             slave ? m.nrm : nullptr, box, sd, md, part);
   return hipGetLastError();
 }
 

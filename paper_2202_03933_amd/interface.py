@@ -27,6 +27,8 @@ def default_params(**kw):
     for k, v in kw.items():
         if k == "dual":
             p.lm_basis = C.MT_BASIS_DUAL if v else C.MT_BASIS_STANDARD
+        elif k == "nodal_normals":
+            p.normals = C.MT_NORMALS_NODAL if v else C.MT_NORMALS_ELEMENT
         else:
             setattr(p, k, v)
     return p

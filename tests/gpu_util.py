@@ -11,23 +11,24 @@ from synth.weights import keyed_normal, TAG_D, TAG_M, TAG_G
 TOL = 1e-10  # relative Frobenius error bar for D, M, gap and gradients
 
 
-def gpu_params(itf, dual=False, rule=7, element_rule=0):
+def gpu_params(itf, dual=False, rule=7, element_rule=0, nodal=False):
     from paper_2202_03933_amd import default_params
-    return default_params(delta=float(itf.delta), dual=dual, rule=rule, element_rule=element_rule)
+    return default_params(delta=float(itf.delta), dual=dual, rule=rule, element_rule=element_rule,
+                          nodal_normals=nodal)
 
 
-def oracle_params(itf, dual=False, rule=7):
-    return oracle.params(delta=itf.delta, dual=dual, rule=rule)
+def oracle_params(itf, dual=False, rule=7, nodal=False):
+    return oracle.params(delta=itf.delta, dual=dual, rule=rule, nodal_normals=nodal)
 
 
-def gpu_run(itf, dual=False, rule=7, backward_seed=None, element_rule=0):
+def gpu_run(itf, dual=False, rule=7, backward_seed=None, element_rule=0, nodal=False):
     """Full HIP path; returns numpy results."""
     from paper_2202_03933_amd import MortarInterface
-    print(f"[gpu] {itf.name} dual={dual} rule={rule} element_rule={element_rule}", flush=True)
+    print(f"[gpu] {itf.name} dual={dual} rule={rule} element_rule={element_rule} nodal={nodal}", flush=True)
     dev = torch.device("cuda", 0)
     iface = MortarInterface(torch.from_numpy(itf.slave.X), torch.from_numpy(itf.slave.conn),
                             torch.from_numpy(itf.master.X), torch.from_numpy(itf.master.conn),
-                            params=gpu_params(itf, dual, rule, element_rule), device=dev)
+                            params=gpu_params(itf, dual, rule, element_rule, nodal), device=dev)
     iface.build_pairs()
     cs, cm, cnv = (t.cpu().numpy() for t in iface.candidates())
     ps, pm, pnv = (t.cpu().numpy() for t in iface.pairs())

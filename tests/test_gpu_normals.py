@@ -1,0 +1,112 @@
+"""GPU parity of the continuous slave normal field (auxiliary planes from
+averaged nodal normals) with the oracle, through the C ABI: candidates, pairs,
+clip vertex counts and patterns bit-exact (the planes are built in the same
+order on both sides); D, M, gap and gradients (through the normal field into
+neighbouring elements) within 1e-10."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.gpu_util import (TOL, assert_forward_parity, gpu_params, gpu_run, oracle_params, rel_err,
+                            weight_fns)
+
+pytestmark = pytest.mark.gpu
+
+
+def oracle_total_grad(itf, prm, ps, pm, seed):
+    w = oracle.pair_weights(itf.slave, itf.master, ps, pm, *weight_fns(seed))
+    g24, gn0, st = oracle.pair_grads(itf.slave, itf.master, prm, ps, pm, w, with_n0=True)
+    gs, gm = oracle.scatter_grads(itf.slave, itf.master, ps, pm, g24)
+    ge = np.zeros((itf.slave.n_el, 3))
+    np.add.at(ge, ps, gn0)
+    return gs + oracle.normal_chain(itf.slave, ge), gm
+
+
+@pytest.mark.parametrize("k,scale", [(0, None), (1, 37), (2, 53), (2, 130)])
+def test_forward_parity(k, scale):
+    itf = synth.interface_config(k, scale=scale) if scale else synth.interface_config(k)
+    g = gpu_run(itf, nodal=True)
+    o = oracle.evaluate(itf, oracle_params(itf, nodal=True))
+    assert_forward_parity(g, o)
+
+
+def test_flat_equals_element_normals_bitwise():
+    itf = synth.interface_config(0)
+    a = gpu_run(itf)
+    b = gpu_run(itf, nodal=True)
+    for key in ("D", "M"):
+        assert np.array_equal(a[key].data, b[key].data)
+    assert np.array_equal(a["g"], b["g"])
+
+
+def test_full_wavy_forward_parity():
+    itf = synth.interface_config(2)
+    g = gpu_run(itf, nodal=True)
+    o = oracle.evaluate(itf, oracle_params(itf, nodal=True))
+    assert_forward_parity(g, o)
+
+
+@pytest.mark.parametrize("k,scale,dual", [(2, 41, False), (1, 37, False), (2, 44, True)])
+def test_gradient_parity(k, scale, dual):
+    itf = synth.interface_config(k, scale=scale)
+    prm = oracle_params(itf, dual=dual, nodal=True)
+    g = gpu_run(itf, dual=dual, nodal=True, backward_seed=3200)
+    o = oracle.evaluate(itf, prm)
+    assert np.array_equal(g["pair_s"], o["pair_s"]) and np.array_equal(g["pair_m"], o["pair_m"])
+    gs, gm = oracle_total_grad(itf, prm, o["pair_s"], o["pair_m"], 3200)
+    es, em = rel_err(g["gXs"], gs), rel_err(g["gXm"], gm)
+    print(f"nodal-normal grad rel err slave {es:.2e} master {em:.2e}")
+    assert es <= TOL and em <= TOL
+
+
+def test_element_based_with_nodal_normals():
+    itf = synth.interface_config(2, scale=53)
+    prm = oracle_params(itf, nodal=True)
+    g = gpu_run(itf, nodal=True, element_rule=4)
+    o = oracle.evaluate_elements(itf, 4, prm)
+    assert rel_err(g["D"].data, o["D"].data) <= TOL
+    assert rel_err(g["M"].data, o["M"].data) <= TOL
+    assert rel_err(g["g"], o["g"]) <= TOL
+
+
+def test_coordinate_update_recomputes_the_field():
+    # set_coordinates with moved slave nodes: the normals, planes and polygons
+    # are rebuilt; the result equals a fresh interface on the moved geometry
+    from paper_2202_03933_amd import MortarInterface
+    from tests.gpu_util import csr_weights
+    itf = synth.interface_config(2, scale=40)
+    dev = torch.device("cuda", 0)
+    rng = np.random.default_rng(9)
+    Xs2 = itf.slave.X + 1e-9 * rng.standard_normal(itf.slave.X.shape)
+    args = (torch.from_numpy(itf.slave.conn), torch.from_numpy(itf.master.X), torch.from_numpy(itf.master.conn))
+    a = MortarInterface(torch.from_numpy(itf.slave.X), *args, params=gpu_params(itf, nodal=True), device=dev).setup()
+    pairs0 = [t.cpu().numpy() for t in a.pairs()]
+    a.integrate()
+    a.set_coordinates(torch.from_numpy(Xs2), torch.from_numpy(itf.master.X))
+    b = MortarInterface(torch.from_numpy(Xs2), *args, params=gpu_params(itf, nodal=True), device=dev).setup()
+    assert all(np.array_equal(x, y.cpu().numpy()) for x, y in zip(pairs0, b.pairs()))
+    ra, rb = a.integrate(), b.integrate()
+    assert all(torch.equal(x, y) for x, y in zip(ra, rb))
+    import scipy.sparse as sp
+    ns, nm = itf.slave.n_nodes, itf.master.n_nodes
+    D = sp.csr_matrix((np.zeros(b.nnz_D), b.D_col.cpu().numpy(), b.D_rowptr.cpu().numpy()), shape=(ns, ns))
+    M = sp.csr_matrix((np.zeros(b.nnz_M), b.M_col.cpu().numpy(), b.M_rowptr.cpu().numpy()), shape=(ns, nm))
+    W = [torch.from_numpy(x).to(dev) for x in csr_weights(D, M, ns, 5)]
+    ga, gb = a.backward(*W), b.backward(*W)
+    assert all(torch.equal(x, y) for x, y in zip(ga, gb))
+
+
+def test_batch_rejects_nodal_normals():
+    from paper_2202_03933_amd import MortarBatch, MortarError, MortarInterface
+    from paper_2202_03933_amd import _capi as C
+    itf = synth.interface_config(0)
+    dev = torch.device("cuda", 0)
+    it = MortarInterface(torch.from_numpy(itf.slave.X), torch.from_numpy(itf.slave.conn),
+                         torch.from_numpy(itf.master.X), torch.from_numpy(itf.master.conn),
+                         params=gpu_params(itf, nodal=True), device=dev).setup()
+    with pytest.raises(MortarError) as e:
+        MortarBatch([it])
+    assert e.value.code == C.MT_EUNSUPPORTED
