@@ -13,7 +13,8 @@ roofline of the dominant kernel (from the library's HIP-event phase timers
 over the timed steps) and the CPU oracle timed on a bounded sample.  Extra
 objects: the same step with the dual basis, element-based integration of the
 same interface (n x n Gauss points per slave element, for several n: time
-and difference from the segment-based values), and 64 batched interfaces.
+and difference from the segment-based values), the same step with auxiliary
+planes from the continuous nodal normal field, and 64 batched interfaces.
 """
 
 import argparse
@@ -254,16 +255,18 @@ def bench_elements(itf, seg_outs, steps, warmup):
     return out
 
 
-def bench_dual(itf, weights, steps, warmup):
-    """The same step with the dual Lagrange multiplier basis (dual-basis
-    forward and backward: the backward adds the recomputed standard blocks
-    and the adjoint of the dual coefficients)."""
+def bench_variant(itf, weights, steps, warmup, **params):
+    """The same step with other parameters: the dual Lagrange multiplier basis
+    (dual-basis forward and backward, the backward including the adjoint of
+    the dual coefficients), or auxiliary planes from the continuous nodal
+    normal field (its normals computed in every search, its gradient chain in
+    every backward)."""
     import torch
     from paper_2202_03933_amd import MortarInterface, default_params
     dev = torch.device("cuda", 0)
     it = MortarInterface(torch.from_numpy(itf.slave.X), torch.from_numpy(itf.slave.conn),
                          torch.from_numpy(itf.master.X), torch.from_numpy(itf.master.conn),
-                         params=default_params(delta=itf.delta, dual=True), device=dev)
+                         params=default_params(delta=itf.delta, **params), device=dev)
     it.setup()
     outs = it.alloc_outputs()
     grads = (torch.empty(3, itf.slave.n_nodes, dtype=torch.float64, device=dev),
@@ -302,6 +305,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-dual", action="store_true")
+    ap.add_argument("--no-nodal", action="store_true")
     ap.add_argument("--no-elements", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (calibrates HBM traffic counters)")
@@ -368,7 +372,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    dual = None if args.no_dual else bench_dual(itf, (wD, wM, wg), args.steps, args.warmup)
+    dual = None if args.no_dual else bench_variant(itf, (wD, wM, wg), args.steps, args.warmup, dual=True)
+    nodal = None if args.no_nodal else bench_variant(itf, (wD, wM, wg), args.steps, args.warmup, nodal_normals=True)
     elements = None if args.no_elements else bench_elements(itf, outs, args.steps, args.warmup)
     batched = None if args.no_batched else bench_batched()
     cpu = None
@@ -419,6 +424,7 @@ def main():
         "roofline": roof,
         "roofline_other_kernels": others,
         "dual_basis": dual,
+        "nodal_normals": nodal,
         "element_based": elements,
         "batched_64_interfaces": batched,
     }

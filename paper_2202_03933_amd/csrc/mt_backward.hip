@@ -164,7 +164,7 @@ __device__ __forceinline__ void gather_weights(int s, int64_t p, int4 csn, const
   wg[3] = w_g[csn.w];
 }
 
-template <int NQ, bool DUAL>
+template <int NQ, bool DUAL, bool NODAL>
 __global__ __launch_bounds__(BSC) __attribute__((amdgpu_waves_per_eu(2))) void k_pair_bwd(MeshPtrs S, int32_t n_s, MeshPtrs M, KParams kp,
                                                    const int32_t* __restrict__ pair_s,
                                                    const int32_t* __restrict__ pair_m, int64_t n_pairs, PolyBuf poly,
@@ -203,12 +203,12 @@ __global__ __launch_bounds__(BSC) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
       for (int k = 0; k < 4; ++k) Xd[k][0] = Xd[k][1] = Xd[k][2] = 0.0;
       double n0d[3] = {0.0, 0.0, 0.0};
-      dual_adjoint(Xs, elem_nrm(S, s), G, Xd, n0d);
+      dual_adjoint(Xs, NODAL ? elem_nrm(S, s) : nullptr, G, Xd, n0d);
 #pragma unroll
       for (int k = 0; k < 4; ++k)
 #pragma unroll
         for (int d = 0; d < 3; ++d) gpair[(int64_t)(3 * k + d) * stride + p] = Xd[k][d];
-      if (gn0)
+      if (NODAL)
 #pragma unroll
         for (int d = 0; d < 3; ++d) gn0[(int64_t)d * stride + p] = n0d[d];
     }
@@ -219,9 +219,9 @@ __global__ __launch_bounds__(BSC) __attribute__((amdgpu_waves_per_eu(2))) void k
       gather_weights(s2, p, c2, posD, n_s, posM, stride, W_D, W_M, w_g, WD, WM, wg);
     }
     double Xsb[4][3], Xmb[4][3], n0b[3];
-    pair_backward<NQ, DUAL>(S, s, csn, M, load_conn(M.conn, pair_m[p]), gpoly(poly, p), poly.nf[p], kp, WD, WM, wg,
+    pair_backward<NQ, DUAL, NODAL>(S, s, csn, M, load_conn(M.conn, pair_m[p]), gpoly(poly, p), poly.nf[p], kp, WD, WM, wg,
                             Xsb, Xmb, n0b, noconv);
-    if (gn0)
+    if (NODAL)
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
         double v = n0b[d];
@@ -254,8 +254,12 @@ hipError_t launch_pair_bwd(const DeviceMesh& S, const DeviceMesh& M, const KPara
   if (n_pairs == 0) return hipSuccess;
   const unsigned nb = xcd_grid((unsigned)((n_pairs + BSC - 1) / BSC));
   const MeshPtrs ms{S.x, S.y, S.z, S.conn, S.nrm}, mm{M.x, M.y, M.z, M.conn, nullptr};
-  auto* k = kp.rule == 3 ? (kp.dual ? k_pair_bwd<3, true> : k_pair_bwd<3, false>)
-                         : (kp.dual ? k_pair_bwd<7, true> : k_pair_bwd<7, false>);
+  const bool nodal = S.nrm != nullptr;
+  auto* k = kp.rule == 3
+                ? (kp.dual ? (nodal ? k_pair_bwd<3, true, true> : k_pair_bwd<3, true, false>)
+                           : (nodal ? k_pair_bwd<3, false, true> : k_pair_bwd<3, false, false>))
+                : (kp.dual ? (nodal ? k_pair_bwd<7, true, true> : k_pair_bwd<7, true, false>)
+                           : (nodal ? k_pair_bwd<7, false, true> : k_pair_bwd<7, false, false>));
   hipLaunchKernelGGL(k, dim3(nb), dim3(BSC), 0, s, ms, n_s_el, mm, kp, pair_s, pair_m, n_pairs, poly, mpos, posD, posM,
                      W_D, W_M, w_g, blk, gpair, gn0, stride, cnt);
   return hipGetLastError();

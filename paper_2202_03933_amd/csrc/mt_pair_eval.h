@@ -551,7 +551,7 @@ __device__ __forceinline__ void projection_adjoint(const double Xs[4][3], const 
 // inverse maps (implicit-function derivative), the clip vertices (line
 // intersections, each vertex once: the fan's pending vertex is carried to the
 // next triangle), the projection and the slave frame.
-template <int NQ, bool DUAL>
+template <int NQ, bool DUAL, bool NODAL = false>
 __device__ __forceinline__ void pair_backward(const MeshPtrs& SM, int s, int4 cs, const MeshPtrs& MM, int4 cm,
                                               const GPoly& P, int nf, const KParams& kp, const double WD_in[16],
                                               const double WM_in[16], const double wg_in[4], double Xsb[4][3],
@@ -565,7 +565,7 @@ __device__ __forceinline__ void pair_backward(const MeshPtrs& SM, int s, int4 cs
     double Xs[4][3], Xm[4][3], f[12];
     load_nodes(SM.x, SM.y, SM.z, cs, Xs);
     load_nodes(MM.x, MM.y, MM.z, cm, Xm);
-    slave_frame_p(Xs, elem_nrm(SM, s), f);
+    slave_frame_p(Xs, NODAL ? elem_nrm(SM, s) : nullptr, f);
     V2 S[4], Mn[4];
     double hs[4], hm[4];
     pair_project(Xs, Xm, f, S, Mn, hs, hm);
@@ -772,7 +772,7 @@ __device__ __forceinline__ void pair_backward(const MeshPtrs& SM, int s, int4 cs
     load_nodes(SM.x, SM.y, SM.z, cs2, Xs);
     load_nodes(MM.x, MM.y, MM.z, cm2, Xm);
     n0b[0] = n0b[1] = n0b[2] = 0.0;
-    projection_adjoint(Xs, Xm, elem_nrm(SM, launder(s)), nb, Xsb, Xmb, n0b);
+    projection_adjoint(Xs, Xm, NODAL ? elem_nrm(SM, launder(s)) : nullptr, nb, Xsb, Xmb, n0b);
   }
 }
 

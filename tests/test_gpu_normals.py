@@ -62,6 +62,49 @@ def test_gradient_parity(k, scale, dual):
     assert es <= TOL and em <= TOL
 
 
+def test_finite_differences_through_the_field():
+    # central differences of the GPU's own forward values, at slave nodes too
+    from paper_2202_03933_amd import MortarInterface
+    from tests.gpu_util import csr_weights
+    import scipy.sparse as sp
+    itf = synth.interface_config(2, scale=48)
+    dev = torch.device("cuda", 0)
+    Xs = torch.from_numpy(itf.slave.X).to(dev)
+    Xm = torch.from_numpy(itf.master.X).to(dev)
+    it = MortarInterface(Xs, torch.from_numpy(itf.slave.conn), Xm, torch.from_numpy(itf.master.conn),
+                         params=gpu_params(itf, nodal=True), device=dev).setup()
+    ns, nm = itf.slave.n_nodes, itf.master.n_nodes
+    D = sp.csr_matrix((np.zeros(it.nnz_D), it.D_col.cpu().numpy(), it.D_rowptr.cpu().numpy()), shape=(ns, ns))
+    M = sp.csr_matrix((np.zeros(it.nnz_M), it.M_col.cpu().numpy(), it.M_rowptr.cpu().numpy()), shape=(ns, nm))
+    W = [torch.from_numpy(x).to(dev) for x in csr_weights(D, M, ns, 21)]
+    it.integrate()
+    gs, gm = (t.cpu().numpy() for t in it.backward(*W))
+
+    def dL(side, node, d, h):
+        out = []
+        for sg in (1.0, -1.0):
+            A, B = Xs.clone(), Xm.clone()
+            (A if side == 0 else B)[node, d] += sg * h
+            it.set_coordinates(A, B)
+            out.append(it.integrate())
+        return sum(torch.dot(w, p - q).item() for w, p, q in zip(W, out[0], out[1])) / (2 * h)
+
+    rng = np.random.default_rng(4)
+    refined = 0
+    cases = [(0, int(a)) for a in rng.choice(ns, 30, replace=False)] + [(1, int(a)) for a in rng.choice(nm, 10, replace=False)]
+    for side, node in cases:
+        d = int(rng.integers(0, 3))
+        an = (gs if side == 0 else gm)[d, node]
+        fd = dL(side, node, d, 1e-6)
+        if abs(fd - an) > 1e-4 * abs(an) + 1e-10:
+            refined += 1
+            fd = dL(side, node, d, 1e-7)
+            assert abs(fd - an) <= 1e-4 * abs(an) + 1e-9, (side, node, d, fd, an)
+    it.set_coordinates(Xs, Xm)
+    print(f"nodal-normal FD: {len(cases)} coordinates, {refined} re-checked with h=1e-7")
+    assert refined <= 0.15 * len(cases)
+
+
 def test_element_based_with_nodal_normals():
     itf = synth.interface_config(2, scale=53)
     prm = oracle_params(itf, nodal=True)
