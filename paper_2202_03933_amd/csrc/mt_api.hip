@@ -168,9 +168,14 @@ int mt_destroy(mt_ctx* c) {
                  &c->minc_off, &c->minc_cur, &c->minc_list, &c->rawD_cnt, &c->rawD_off, &c->rawD, &c->rawM_cnt,
                  &c->rawM_off, &c->rawM, &c->pat_keep, &c->D_cnt, &c->D_rowptr, &c->D_col, &c->M_cnt, &c->M_rowptr,
                  &c->M_col, &c->posD, &c->posM, &c->poly_u, &c->poly_v, &c->poly_lab, &c->poly_nf, &c->maybe_list,
-                 &c->maybe_flag, &c->maybe_scan, &c->mpoly_u, &c->mpoly_v, &c->mpoly_lab, &c->mpoly_nf, &c->blk, &c->gpair, &c->nrm_node, &c->nrm_el, &c->gn0, &c->nrm_sb, &c->nrm_ub, &c->nrm_cg, &c->mp_keys, &c->mp_vals, &c->mp_off, &c->mp_pos,
+                 &c->maybe_flag, &c->maybe_scan, &c->mpoly_u, &c->mpoly_v, &c->mpoly_lab, &c->mpoly_nf, &c->blk, &c->gpair, &c->nrm_node, &c->nrm_el, &c->gn0, &c->nrm_sb, &c->nrm_ub, &c->nrm_cg, &c->aux_hist, &c->aux_scan, &c->mp_keys, &c->mp_vals, &c->mp_off, &c->mp_pos,
                  &c->scan_tmp, &c->sort_hist, &c->host_tmp};
   for (Buf* b : bufs) release(*b);
+  if (c->aux) {
+    (void)hipEventDestroy(c->aux_fork);
+    (void)hipEventDestroy(c->aux_join);
+    (void)hipStreamDestroy(c->aux);
+  }
   for (auto& iv : c->intervals) {
     (void)hipEventDestroy(iv.a);
     (void)hipEventDestroy(iv.b);
@@ -484,6 +489,41 @@ int mt_csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, void* stream) {
     if (rc) return rc;
     c->have_inc[0] = true;
   }
+  c->have_master_index = false;
+  // The pair blocks of segment-based integration and the pairs-by-master
+  // index of the backward depend on the pair list alone: they run on an
+  // internal stream (the FP64-bound quadrature beside the latency-bound
+  // pattern kernels) and are joined back into the caller's stream before
+  // this call returns.  mt_integrate then only assembles.
+  const bool aux = c->params.element_rule == 0 && c->n_pairs > 0 && c->poly_gen == c->coord_gen;
+  if (aux) {
+    if (!c->have_inc[1]) {
+      int rc = build_incidence(c, M, c->minc_cnt, c->minc_off, c->minc_cur, c->minc_list, st);
+      if (rc) return rc;
+      c->have_inc[1] = true;
+    }
+    const int64_t np = c->n_pairs;
+    MT_HIP(ensure(c->blk, sizeof(double) * 36 * (size_t)np));
+    if (!c->aux) {
+      MT_HIP(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+      MT_HIP(hipEventCreateWithFlags(&c->aux_fork, hipEventDisableTiming));
+      MT_HIP(hipEventCreateWithFlags(&c->aux_join, hipEventDisableTiming));
+    }
+    MT_HIP(hipEventRecord(c->aux_fork, st));
+    MT_HIP(hipStreamWaitEvent(c->aux, c->aux_fork, 0));
+    {
+      PhaseTimer t(c, MT_T_PAIR_FWD, c->aux);
+      MT_HIP(launch_pair_fwd(S, M, kparams(c->params), c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), np,
+                             poly_buf(c), c->blk.as<double>(), np, c->counters.as<Counters>(), c->aux));
+    }
+    {
+      PhaseTimer t(c, MT_T_GRAD_REDUCE, c->aux);
+      int rc = build_master_index(c, c->aux, c->aux_hist, c->aux_scan);
+      if (rc) return rc;
+    }
+    MT_HIP(hipEventRecord(c->aux_join, c->aux));
+    c->blk_gen = c->coord_gen;
+  }
   // rows whose column candidates exceed the per-thread LDS segment get global
   // scratch, sized by the bounds 4 entries per incident element (D) and per
   // pair of an incident element (M): at most 16 n_el and 16 n_pairs in total
@@ -530,8 +570,8 @@ int mt_csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, void* stream) {
                      c->posD.as<int32_t>(), st));
   MT_HIP(launch_posM(S.conn, M.conn, c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), c->n_pairs,
                      c->M_rowptr.as<int32_t>(), c->M_col.as<int32_t>(), c->posM.as<int32_t>(), st));
+  if (aux) MT_HIP(hipStreamWaitEvent(st, c->aux_join, 0));
   c->have_pattern = true;
-  c->have_master_index = false;
   ++c->pattern_gen;
   if (nnz_D) *nnz_D = c->nnz_D;
   if (nnz_M) *nnz_M = c->nnz_M;
@@ -582,10 +622,12 @@ int mt_integrate(mt_ctx* c, double* D_val, double* M_val, double* gap, void* str
                               st));
       c->poly_gen = c->coord_gen;
     }
-    PhaseTimer t(c, MT_T_PAIR_FWD, st);
-    MT_HIP(launch_pair_fwd(S, M, kparams(c->params), c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), np, poly,
-                           c->blk.as<double>(), np, c->counters.as<Counters>(), st));
-    c->blk_gen = c->coord_gen;
+    if (c->blk_gen != c->coord_gen) {  // else computed by mt_csr_pattern for these coordinates
+      PhaseTimer t(c, MT_T_PAIR_FWD, st);
+      MT_HIP(launch_pair_fwd(S, M, kparams(c->params), c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), np, poly,
+                             c->blk.as<double>(), np, c->counters.as<Counters>(), st));
+      c->blk_gen = c->coord_gen;
+    }
   }
   PhaseTimer t(c, MT_T_ASSEMBLE, st);
   MT_HIP(launch_assemble(c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(), S.n_nodes, c->pair_off.as<int32_t>(),
@@ -625,6 +667,11 @@ int mt::ensure_master_index(mt_ctx* c, hipStream_t st) {
     if (rc) return rc;
     c->have_inc[1] = true;
   }
+  return build_master_index(c, st, c->sort_hist, c->scan_tmp);
+}
+
+int mt::build_master_index(mt_ctx* c, hipStream_t st, Buf& hist, Buf& scan_tmp) {
+  const DeviceMesh& M = c->side[1];
   const int64_t np = c->n_pairs;
   MT_HIP(ensure(c->mp_keys, sizeof(uint32_t) * (size_t)np));
   MT_HIP(ensure(c->mp_vals, sizeof(uint32_t) * (size_t)np));
@@ -637,8 +684,8 @@ int mt::ensure_master_index(mt_ctx* c, hipStream_t st) {
     MT_HIP(hipGetLastError());
   }
   MT_HIP(radix_sort_pairs(c->mp_keys.as<uint32_t>(), c->mp_vals.as<uint32_t>(), c->keys_tmp.as<uint32_t>(),
-                          c->vals_tmp.as<uint32_t>(), np, bits_for(std::max<int32_t>(M.n_el, 2)), c->sort_hist,
-                          c->scan_tmp, st));
+                          c->vals_tmp.as<uint32_t>(), np, bits_for(std::max<int32_t>(M.n_el, 2)), hist,
+                          scan_tmp, st));
   MT_HIP(hipMemsetAsync(c->mp_off.p, 0, sizeof(int32_t) * 2 * ((size_t)M.n_el + 1), st));
   MT_HIP(ensure(c->mp_pos, sizeof(int32_t) * (size_t)std::max<int64_t>(np, 1)));
   MT_HIP(launch_mpair_off(c->mp_keys.as<uint32_t>(), c->mp_vals.as<uint32_t>(), np, M.n_el, c->mp_off.as<int32_t>(),

@@ -166,6 +166,11 @@ struct mt_ctx {
   mt::Buf gn0;             // [3][n_pairs] dL/dn0 per pair
   mt::Buf nrm_sb, nrm_ub, nrm_cg;
   int64_t nrm_gen = -1;    // coord_gen of nrm_node / nrm_el
+  // internal stream on which mt_csr_pattern computes the pair blocks and the
+  // pairs-by-master index while the pattern is built on the caller's stream
+  hipStream_t aux = nullptr;
+  hipEvent_t aux_fork = nullptr, aux_join = nullptr;
+  mt::Buf aux_hist, aux_scan;
   mt::Buf blk;             // [36][n_pairs]
   int64_t blk_gen = -1;    // coord_gen of the blocks in blk (mt_integrate)
   mt::Buf gpair;           // [24][n_pairs]
@@ -296,6 +301,9 @@ KParams kparams(const mt_params& p);
 // Node incidence of the master side and the pairs-by-master permutation
 // (needed by the backward's master-node reduction); built once per pattern.
 int ensure_master_index(mt_ctx* c, hipStream_t st);
+// The same on a given stream with its own sort scratch (the master incidence
+// must exist already).
+int build_master_index(mt_ctx* c, hipStream_t st, Buf& hist, Buf& scan_tmp);
 // Polygon buffers sized for the current pair list, and their view.
 int ensure_poly(mt_ctx* c);
 PolyBuf poly_buf(mt_ctx* c);
