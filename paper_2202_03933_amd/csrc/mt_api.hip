@@ -512,14 +512,14 @@ int mt_csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, void* stream) {
     MT_HIP(hipEventRecord(c->aux_fork, st));
     MT_HIP(hipStreamWaitEvent(c->aux, c->aux_fork, 0));
     {
-      PhaseTimer t(c, MT_T_PAIR_FWD, c->aux);
-      MT_HIP(launch_pair_fwd(S, M, kparams(c->params), c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), np,
-                             poly_buf(c), c->blk.as<double>(), np, c->counters.as<Counters>(), c->aux));
-    }
-    {
       PhaseTimer t(c, MT_T_GRAD_REDUCE, c->aux);
       int rc = build_master_index(c, c->aux, c->aux_hist, c->aux_scan);
       if (rc) return rc;
+    }
+    {
+      PhaseTimer t(c, MT_T_PAIR_FWD, c->aux);
+      MT_HIP(launch_pair_fwd(S, M, kparams(c->params), c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), np,
+                             poly_buf(c), c->blk.as<double>(), np, c->counters.as<Counters>(), c->aux));
     }
     MT_HIP(hipEventRecord(c->aux_join, c->aux));
     c->blk_gen = c->coord_gen;
