@@ -42,7 +42,7 @@ KERNELS = {
                   "profiles/k_pair_poly_wavy1024_traffic.md"),
     "pair_fwd": ("k_pair_fwd", ["mt_pairs.hip", "mt_pair_eval.h", "mt_geometry.h"],
                  "profiles/k_pair_fwd_wavy1024_traffic.md"),
-    "pair_bwd": ("k_pair_bwd", ["mt_backward.hip", "mt_pair_eval.h", "mt_geometry.h"],
+    "pair_bwd": ("k_pair_bwd", ["mt_backward.hip", "mt_dual.h", "mt_pair_eval.h", "mt_geometry.h"],
                  "profiles/k_pair_bwd_wavy1024_traffic.md"),
 }
 

@@ -313,8 +313,9 @@ int mt_batch_forward(mt_batch* b, double* const* D_val, double* const* M_val, do
  * mt_update_coordinates since mt_batch_build: their clip polygons are
  * recomputed first, outside any graph); an instance whose pair list or
  * pattern was rebuilt since mt_batch_build makes them fail with MT_ESTATE.
- * mt_batch_backward takes the standard basis only (MT_EUNSUPPORTED for a
- * batch built with the dual basis; mt_backward takes either). */
+ * With the dual basis mt_batch_backward first recomputes every pair's dual
+ * blocks (one more persistent launch), which the dual-coefficient adjoint
+ * reads. */
 int mt_batch_backward(mt_batch* b, const double* const* W_D, const double* const* W_M,
                       const double* const* w_g, double* const* gXs, double* const* gXm,
                       int use_graph, void* stream);

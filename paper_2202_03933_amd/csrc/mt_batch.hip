@@ -16,7 +16,7 @@
 #include <cstring>
 #include <vector>
 
-#include "mt_pair_eval.h"
+#include "mt_dual.h"
 #include "mt_rows.h"
 
 namespace mt {
@@ -143,7 +143,7 @@ __global__ __launch_bounds__(BSZ) __attribute__((amdgpu_waves_per_eu(3))) void k
   if ((threadIdx.x & 63) == 0 && nc) atomicAdd(&cnt->noconv, nc);
 }
 
-template <int BSZ, int NQ>
+template <int BSZ, int NQ, bool DUAL>
 __global__ __launch_bounds__(BSZ) __attribute__((amdgpu_waves_per_eu(2))) void k_batch_bwd(const BatchInst* __restrict__ inst,
                                                     const WorkItem* __restrict__ items,
                                                     const int32_t* __restrict__ qbeg, int32_t* qnext, Counters* cnt) {
@@ -157,24 +157,50 @@ __global__ __launch_bounds__(BSZ) __attribute__((amdgpu_waves_per_eu(2))) void k
     for (int64_t p = w.begin + (int)threadIdx.x; p < w.end; p += BSZ) {
       const int s = I.pair_s[p];
       const int4 csn = load_conn(I.S.conn, s);
+      auto gather = [&](int se, int4 c, double WD[16], double WM[16], double wg[4]) {
+#pragma unroll
+        for (int k = 0; k < 16; ++k) WD[k] = I.W_D[I.posD[(int64_t)k * I.n_s_el + se]];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) WM[k] = I.W_M[I.posM[(int64_t)k * st + p]];
+        wg[0] = I.w_g[c.x];
+        wg[1] = I.w_g[c.y];
+        wg[2] = I.w_g[c.z];
+        wg[3] = I.w_g[c.w];
+      };
+      if (DUAL) {
+        // gradient through the dual coefficients, from the pair's dual
+        // blocks (computed by the forward launch that precedes this one);
+        // parked in the slave slots of gpair during the sweep
+        double WD[16], WM[16], wg[4], G[16];
+        gather(s, csn, WD, WM, wg);
+        dual_gram(WD, WM, wg, I.blk, st, p, G);
+        double Xs[4][3], Xd[4][3], n0d[3] = {0.0, 0.0, 0.0};
+        load_nodes(I.S.x, I.S.y, I.S.z, csn, Xs);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) Xd[k][0] = Xd[k][1] = Xd[k][2] = 0.0;
+        dual_adjoint(Xs, nullptr, G, Xd, n0d);
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+          for (int d = 0; d < 3; ++d) I.gpair[(int64_t)(3 * k + d) * st + p] = Xd[k][d];
+      }
       double WD[16], WM[16], wg[4];
-#pragma unroll
-      for (int k = 0; k < 16; ++k) WD[k] = I.W_D[I.posD[(int64_t)k * I.n_s_el + s]];
-#pragma unroll
-      for (int k = 0; k < 16; ++k) WM[k] = I.W_M[I.posM[(int64_t)k * st + p]];
-      wg[0] = I.w_g[csn.x];
-      wg[1] = I.w_g[csn.y];
-      wg[2] = I.w_g[csn.z];
-      wg[3] = I.w_g[csn.w];
+      {
+        const int s2 = DUAL ? launder(s) : s;
+        const int4 c2 = DUAL ? int4{launder(csn.x), launder(csn.y), launder(csn.z), launder(csn.w)} : csn;
+        gather(s2, c2, WD, WM, wg);
+      }
       double Xsb[4][3], Xmb[4][3], n0b[3];
-      pair_backward<NQ, false>(I.S, s, csn, I.M, load_conn(I.M.conn, I.pair_m[p]), gpoly(I.poly, p), I.poly.nf[p],
-                               I.kp, WD, WM, wg, Xsb, Xmb, n0b, noconv);
+      pair_backward<NQ, DUAL>(I.S, s, csn, I.M, load_conn(I.M.conn, I.pair_m[p]), gpoly(I.poly, p), I.poly.nf[p],
+                              I.kp, WD, WM, wg, Xsb, Xmb, n0b, noconv);
       const int64_t q = I.mpos[p];
 #pragma unroll
       for (int k = 0; k < 4; ++k)
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-          I.gpair[(int64_t)(3 * k + d) * st + p] = Xsb[k][d];
+          double v = Xsb[k][d];
+          if (DUAL) v += I.gpair[(int64_t)(3 * k + d) * st + p];
+          I.gpair[(int64_t)(3 * k + d) * st + p] = v;
           I.gpair[(int64_t)(12 + 3 * k + d) * st + q] = Xmb[k][d];
         }
     }
@@ -219,8 +245,9 @@ FwdFn fwd_kernel(int nq, bool dual) {
   return dual ? k_batch_fwd<BSZ, 7, true> : k_batch_fwd<BSZ, 7, false>;
 }
 template <int BSZ>
-BwdFn bwd_kernel(int nq) {
-  return nq == 3 ? k_batch_bwd<BSZ, 3> : k_batch_bwd<BSZ, 7>;
+BwdFn bwd_kernel(int nq, bool dual) {
+  if (nq == 3) return dual ? k_batch_bwd<BSZ, 3, true> : k_batch_bwd<BSZ, 3, false>;
+  return dual ? k_batch_bwd<BSZ, 7, true> : k_batch_bwd<BSZ, 7, false>;
 }
 
 PolyFn pick_poly(int bsz) {
@@ -233,10 +260,10 @@ FwdFn pick_fwd(int bsz, int nq, bool dual) {
   if (bsz == 128) return fwd_kernel<128>(nq, dual);
   return fwd_kernel<64>(nq, dual);
 }
-BwdFn pick_bwd(int bsz, int nq) {
-  if (bsz == 256) return bwd_kernel<256>(nq);
-  if (bsz == 128) return bwd_kernel<128>(nq);
-  return bwd_kernel<64>(nq);
+BwdFn pick_bwd(int bsz, int nq, bool dual) {
+  if (bsz == 256) return bwd_kernel<256>(nq, dual);
+  if (bsz == 128) return bwd_kernel<128>(nq, dual);
+  return bwd_kernel<64>(nq, dual);
 }
 
 // Blocks of kernel fn (block size bsz) resident on one compute unit, from
@@ -384,8 +411,13 @@ int launch_fwd_all(mt_batch* b, hipStream_t st) {
 }
 
 int launch_bwd_all(mt_batch* b, hipStream_t st) {
+  if (b->dual) {
+    // the dual adjoint reads every pair's dual blocks
+    int rc = launch_fwd(b, st);
+    if (rc) return rc;
+  }
   const int bsz = b->tune.block;
-  BwdFn f = pick_bwd(bsz, b->nq);
+  BwdFn f = pick_bwd(bsz, b->nq, b->dual);
   const int grid = b->num_cu * resident_blocks(reinterpret_cast<const void*>(f), bsz);
   k_reset_queues<<<1, 64, 0, st>>>(b->d_qnext.as<int32_t>());
   B_HIP(hipGetLastError());
@@ -615,7 +647,6 @@ int mt_batch_backward(mt_batch* b, const double* const* W_D, const double* const
                       double* const* gXs, double* const* gXm, int use_graph, void* stream) {
   if (!b) return bfail(MT_EINVAL, "mt_batch_backward: null");
   if (!b->built) return bfail(MT_ESTATE, "mt_batch_backward: mt_batch_build first");
-  if (b->dual) return bfail(MT_EUNSUPPORTED, "mt_batch_backward: the dual basis has no backward pass");
   if (!W_D || !W_M || !w_g || !gXs || !gXm) return bfail(MT_EINVAL, "mt_batch_backward: null table");
   hipStream_t st = (hipStream_t)stream;
   if (use_graph && st == nullptr) return bfail(MT_EINVAL, "mt_batch_backward: graph capture needs a created stream");
@@ -633,6 +664,8 @@ int mt_batch_backward(mt_batch* b, const double* const* W_D, const double* const
   if (rc) return rc;
   rc = refresh_polygons(b, st);
   if (rc) return rc;
+  if (b->dual)  // the launch recomputes the dual blocks into the staging buffers
+    for (mt_ctx* c : b->ctxs) c->blk_gen = -1;
   if (use_graph) return run_graph(&b->g_bwd, &b->g_bwd_stream, st, [&]() { return launch_bwd_all(b, st); });
   return launch_bwd_all(b, st);
 }

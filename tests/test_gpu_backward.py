@@ -193,14 +193,6 @@ def test_error_codes():
         iface.integrate(out=(torch.empty(1, dtype=torch.float64, device=dev),) * 3)
     assert e.value.code == C.MT_ESTATE
     iface.setup()
-    # the batched backward takes the standard basis only
-    from paper_2202_03933_amd import MortarBatch
-    b = MortarBatch([iface])
-    z = torch.zeros(max(iface.nnz_D, iface.nnz_M, iface.n_slave_nodes), dtype=torch.float64, device=dev)
-    with pytest.raises(MortarError) as e:
-        b.backward([(z[:iface.nnz_D], z[:iface.nnz_M], z[:iface.n_slave_nodes])])
-    assert e.value.code == C.MT_EUNSUPPORTED
-    b.close()
     # connectivity out of range is reported, not read
     bad = itf.slave.conn.copy()
     bad[3, 2] = itf.slave.n_nodes + 5

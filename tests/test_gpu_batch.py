@@ -13,14 +13,14 @@ from tests.gpu_util import TOL, csr_weights, gpu_params, oracle_params, rel_err,
 pytestmark = pytest.mark.gpu
 
 
-def make_ifaces(instances):
+def make_ifaces(instances, dual=False):
     from paper_2202_03933_amd import MortarInterface
     dev = torch.device("cuda", 0)
     out = []
     for itf in instances:
         it = MortarInterface(torch.from_numpy(itf.slave.X), torch.from_numpy(itf.slave.conn),
                              torch.from_numpy(itf.master.X), torch.from_numpy(itf.master.conn),
-                             params=gpu_params(itf), device=dev).setup()
+                             params=gpu_params(itf, dual=dual), device=dev).setup()
         out.append(it)
     return out
 
@@ -37,9 +37,9 @@ def equal_outs(a, b):
     return all(torch.equal(x, y) for x, y in zip(a, b))
 
 
-def run_batch_checks(instances, autotune=True):
+def run_batch_checks(instances, autotune=True, dual=False):
     from paper_2202_03933_amd import MortarBatch
-    ifaces = make_ifaces(instances)
+    ifaces = make_ifaces(instances, dual=dual)
     print(f"[gpu] batch of {len(ifaces)} interfaces, {sum(i.n_pairs for i in ifaces)} pairs", flush=True)
     ref = [tuple(t.clone() for t in it.integrate()) for it in ifaces]
     W = [weights_for(it, 4000 + k) for k, it in enumerate(ifaces)]
@@ -97,6 +97,23 @@ def test_batch_small_instances_bitwise_and_oracle():
             assert rel_err(gv.cpu().numpy(), o["g"]) <= TOL
         if itf.meta["geometry"] == "flat":
             continue  # tied flat boundaries: not differentiable (see test_gpu_backward)
+        w = oracle.pair_weights(itf.slave, itf.master, o["pair_s"], o["pair_m"],
+                                *weight_fns(4000 + itf.meta["instance"]))
+        g24, _ = oracle.pair_grads(itf.slave, itf.master, prm, o["pair_s"], o["pair_m"], w)
+        ogs, ogm = oracle.scatter_grads(itf.slave, itf.master, o["pair_s"], o["pair_m"], g24)
+        assert rel_err(gs.cpu().numpy().T, ogs) <= TOL and rel_err(gm.cpu().numpy().T, ogm) <= TOL
+
+
+def test_batch_dual_basis_bitwise_and_oracle():
+    # dual basis: the batched backward recomputes the dual blocks and takes
+    # the dual-coefficient adjoint; bitwise equal to one call per interface
+    instances = synth.batched_instances(n_inst=9, max_side=40)
+    ifaces, outs, grads = run_batch_checks(instances, autotune=False, dual=True)
+    for itf, it, (gs, gm) in zip(instances, ifaces, grads):
+        if itf.meta["geometry"] == "flat":
+            continue
+        prm = oracle_params(itf, dual=True)
+        o = oracle.evaluate(itf, prm)
         w = oracle.pair_weights(itf.slave, itf.master, o["pair_s"], o["pair_m"],
                                 *weight_fns(4000 + itf.meta["instance"]))
         g24, _ = oracle.pair_grads(itf.slave, itf.master, prm, o["pair_s"], o["pair_m"], w)
