@@ -188,8 +188,9 @@ int mt_get_candidates(mt_ctx* ctx, int32_t* slave_el, int32_t* master_el, uint8_
  * mt_integrate, which depends on the pair list only) and the pairs-by-master
  * index of mt_backward on an internal stream of the context, concurrently
  * with the pattern, and joins that stream back into `stream` before
- * returning; mt_integrate then assembles them unless the coordinates or
- * parameters changed since.  Errors: MT_ESTATE. */
+ * returning; the first mt_integrate after it then only assembles them
+ * (unless the coordinates or parameters changed in between).
+ * Errors: MT_ESTATE. */
 int mt_csr_pattern(mt_ctx* ctx, int64_t* nnz_D, int64_t* nnz_M, void* stream);
 
 /* Copy the CSR arrays: D_rowptr[n_s_nodes+1], D_col[nnz_D],

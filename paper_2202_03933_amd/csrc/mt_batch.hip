@@ -638,7 +638,10 @@ int mt_batch_forward(mt_batch* b, double* const* D_val, double* const* M_val, do
   if (rc) return rc;
   // the instances' block staging buffers are overwritten with the batch's
   // parameters: no longer those of their last mt_integrate
-  for (mt_ctx* c : b->ctxs) c->blk_gen = -1;
+  for (mt_ctx* c : b->ctxs) {
+    c->blk_gen = -1;
+    c->blk_pending = false;
+  }
   if (use_graph) return run_graph(&b->g_fwd, &b->g_fwd_stream, st, [&]() { return launch_fwd_all(b, st); });
   return launch_fwd_all(b, st);
 }
@@ -665,7 +668,10 @@ int mt_batch_backward(mt_batch* b, const double* const* W_D, const double* const
   rc = refresh_polygons(b, st);
   if (rc) return rc;
   if (b->dual)  // the launch recomputes the dual blocks into the staging buffers
-    for (mt_ctx* c : b->ctxs) c->blk_gen = -1;
+    for (mt_ctx* c : b->ctxs) {
+      c->blk_gen = -1;
+      c->blk_pending = false;
+    }
   if (use_graph) return run_graph(&b->g_bwd, &b->g_bwd_stream, st, [&]() { return launch_bwd_all(b, st); });
   return launch_bwd_all(b, st);
 }

@@ -173,6 +173,7 @@ struct mt_ctx {
   mt::Buf aux_hist, aux_scan;
   mt::Buf blk;             // [36][n_pairs]
   int64_t blk_gen = -1;    // coord_gen of the blocks in blk (mt_integrate)
+  bool blk_pending = false;  // blocks computed by mt_csr_pattern, not yet assembled
   mt::Buf gpair;           // [24][n_pairs]
   mt::Buf mp_keys, mp_vals, mp_off;  // pairs sorted by master element
   mt::Buf mp_pos;          // int32 [n_pairs]: rank of each pair in that order
