@@ -300,8 +300,8 @@ int mt_batch_destroy(mt_batch* b);
  * must outlive the batch.  Errors: MT_EINVAL (other device), MT_ESTATE. */
 int mt_batch_add(mt_batch* b, mt_ctx* ctx, int32_t* index);
 /* Build the work queue and per-instance tables.  `tuning` may be NULL.  Synchronises.
- * Errors: MT_EINVAL (instances differ in rule or basis), MT_EUNSUPPORTED
- * (an instance set to element-based integration). */
+ * Errors: MT_EINVAL (instances differ in rule, basis or normal field),
+ * MT_EUNSUPPORTED (an instance set to element-based integration). */
 int mt_batch_build(mt_batch* b, const mt_batch_tuning* tuning, void* stream);
 /* Forward for every instance: D_val[i], M_val[i], gap[i] are host arrays of
  * K device pointers (outputs as for mt_integrate).  use_graph != 0 captures

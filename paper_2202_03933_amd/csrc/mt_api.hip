@@ -237,7 +237,7 @@ int mt_update_coordinates(mt_ctx* c, int side, const double* x, const double* y,
   return MT_OK;
 }
 
-static int ensure_normals(mt_ctx* c, hipStream_t st);
+static int normals_for_coords(mt_ctx* c, hipStream_t st);
 
 int mt_build_pairs(mt_ctx* c, int64_t* n_cand_out, int64_t* n_pairs_out, void* stream) {
   if (!c) return fail(MT_EINVAL, "mt_build_pairs: null ctx");
@@ -279,7 +279,7 @@ int mt_build_pairs(mt_ctx* c, int64_t* n_cand_out, int64_t* n_pairs_out, void* s
     // connectivity checked: the continuous normal field, then the slave
     // frames of the candidate pass again with its plane normals
     PhaseTimer t(c, MT_T_PREP, st);
-    int rc = ensure_normals(c, st);
+    int rc = normals_for_coords(c, st);
     if (rc) return rc;
     MT_HIP(launch_prep(S, true, c->box_s.as<double>(), c->sdata.as<double>(), nullptr, c->prep_part.as<double>(), st));
   }
@@ -452,7 +452,7 @@ static int build_incidence(mt_ctx* c, const DeviceMesh& mesh, Buf& cntb, Buf& of
 
 // The slave side's continuous normal field for the current coordinates (the
 // element plane normals the frames use), or none for element normals.
-static int ensure_normals(mt_ctx* c, hipStream_t st) {
+static int normals_for_coords(mt_ctx* c, hipStream_t st) {
   DeviceMesh& S = c->side[0];
   if (c->params.normals != MT_NORMALS_NODAL) {
     S.nrm = nullptr;
@@ -606,7 +606,7 @@ int mt_integrate(mt_ctx* c, double* D_val, double* M_val, double* gap, void* str
   MT_HIP(ensure(c->blk, sizeof(double) * 36 * (size_t)std::max<int64_t>(np, 1)));
   {
     int rc = ensure_poly(c);
-    if (!rc) rc = ensure_normals(c, st);
+    if (!rc) rc = normals_for_coords(c, st);
     if (rc) return rc;
   }
   const PolyBuf poly = poly_buf(c);
@@ -722,7 +722,7 @@ int mt_backward(mt_ctx* c, const double* W_D, const double* W_M, const double* w
   MT_HIP(ensure(c->gpair, sizeof(double) * 24 * (size_t)std::max<int64_t>(np, 1)));
   {
     int rc = ensure_poly(c);
-    if (!rc) rc = ensure_normals(c, st);
+    if (!rc) rc = normals_for_coords(c, st);
     if (rc) return rc;
   }
   const bool nodal = c->params.normals == MT_NORMALS_NODAL;
@@ -764,7 +764,8 @@ int mt_backward(mt_ctx* c, const double* W_D, const double* W_M, const double* w
     MT_HIP(ensure(c->nrm_cg, sizeof(double) * 12 * (size_t)std::max(S.n_el, 1)));
     MT_HIP(launch_normal_chain(S, c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(), c->pair_off.as<int32_t>(),
                                c->gn0.as<double>(), np, c->nrm_node.as<double>(), c->nrm_el.as<double>(),
-                               c->nrm_sb.as<double>(), c->nrm_ub.as<double>(), c->nrm_cg.as<double>(), gXs, st));
+                               c->nrm_sb.as<double>(), c->nrm_ub.as<double>(), c->nrm_cg.as<double>(), gXs, nullptr,
+                               nullptr, st));
   }
   return MT_OK;
 }
@@ -827,3 +828,5 @@ int mt_get_stats(mt_ctx* c, mt_stats* out) {
 }
 
 }  // extern "C"
+
+int mt::ensure_normals(mt_ctx* c, hipStream_t st) { return normals_for_coords(c, st); }

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cstring>
 #include <vector>
 
@@ -44,6 +45,7 @@ struct BatchInst {
   const int32_t* mpos;
   double* blk;
   double* gpair;
+  double* gn0;  // [3][n_pairs] dL/dn0 per pair (continuous normal field), else null
   PolyBuf poly;
   // per call
   double* D_val;
@@ -143,7 +145,7 @@ __global__ __launch_bounds__(BSZ) __attribute__((amdgpu_waves_per_eu(3))) void k
   if ((threadIdx.x & 63) == 0 && nc) atomicAdd(&cnt->noconv, nc);
 }
 
-template <int BSZ, int NQ, bool DUAL>
+template <int BSZ, int NQ, bool DUAL, bool NODAL>
 __global__ __launch_bounds__(BSZ) __attribute__((amdgpu_waves_per_eu(2))) void k_batch_bwd(const BatchInst* __restrict__ inst,
                                                     const WorkItem* __restrict__ items,
                                                     const int32_t* __restrict__ qbeg, int32_t* qnext, Counters* cnt) {
@@ -178,11 +180,14 @@ __global__ __launch_bounds__(BSZ) __attribute__((amdgpu_waves_per_eu(2))) void k
         load_nodes(I.S.x, I.S.y, I.S.z, csn, Xs);
 #pragma unroll
         for (int k = 0; k < 4; ++k) Xd[k][0] = Xd[k][1] = Xd[k][2] = 0.0;
-        dual_adjoint(Xs, nullptr, G, Xd, n0d);
+        dual_adjoint(Xs, NODAL ? elem_nrm(I.S, s) : nullptr, G, Xd, n0d);
 #pragma unroll
         for (int k = 0; k < 4; ++k)
 #pragma unroll
           for (int d = 0; d < 3; ++d) I.gpair[(int64_t)(3 * k + d) * st + p] = Xd[k][d];
+        if (NODAL)
+#pragma unroll
+          for (int d = 0; d < 3; ++d) I.gn0[(int64_t)d * st + p] = n0d[d];
       }
       double WD[16], WM[16], wg[4];
       {
@@ -191,8 +196,15 @@ __global__ __launch_bounds__(BSZ) __attribute__((amdgpu_waves_per_eu(2))) void k
         gather(s2, c2, WD, WM, wg);
       }
       double Xsb[4][3], Xmb[4][3], n0b[3];
-      pair_backward<NQ, DUAL>(I.S, s, csn, I.M, load_conn(I.M.conn, I.pair_m[p]), gpoly(I.poly, p), I.poly.nf[p],
-                              I.kp, WD, WM, wg, Xsb, Xmb, n0b, noconv);
+      pair_backward<NQ, DUAL, NODAL>(I.S, s, csn, I.M, load_conn(I.M.conn, I.pair_m[p]), gpoly(I.poly, p),
+                                     I.poly.nf[p], I.kp, WD, WM, wg, Xsb, Xmb, n0b, noconv);
+      if (NODAL)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          double v = n0b[d];
+          if (DUAL) v += I.gn0[(int64_t)d * st + p];
+          I.gn0[(int64_t)d * st + p] = v;
+        }
       const int64_t q = I.mpos[p];
 #pragma unroll
       for (int k = 0; k < 4; ++k)
@@ -244,10 +256,10 @@ FwdFn fwd_kernel(int nq, bool dual) {
   if (nq == 3) return dual ? k_batch_fwd<BSZ, 3, true> : k_batch_fwd<BSZ, 3, false>;
   return dual ? k_batch_fwd<BSZ, 7, true> : k_batch_fwd<BSZ, 7, false>;
 }
-template <int BSZ>
+template <int BSZ, bool NODAL>
 BwdFn bwd_kernel(int nq, bool dual) {
-  if (nq == 3) return dual ? k_batch_bwd<BSZ, 3, true> : k_batch_bwd<BSZ, 3, false>;
-  return dual ? k_batch_bwd<BSZ, 7, true> : k_batch_bwd<BSZ, 7, false>;
+  if (nq == 3) return dual ? k_batch_bwd<BSZ, 3, true, NODAL> : k_batch_bwd<BSZ, 3, false, NODAL>;
+  return dual ? k_batch_bwd<BSZ, 7, true, NODAL> : k_batch_bwd<BSZ, 7, false, NODAL>;
 }
 
 PolyFn pick_poly(int bsz) {
@@ -260,10 +272,15 @@ FwdFn pick_fwd(int bsz, int nq, bool dual) {
   if (bsz == 128) return fwd_kernel<128>(nq, dual);
   return fwd_kernel<64>(nq, dual);
 }
-BwdFn pick_bwd(int bsz, int nq, bool dual) {
-  if (bsz == 256) return bwd_kernel<256>(nq, dual);
-  if (bsz == 128) return bwd_kernel<128>(nq, dual);
-  return bwd_kernel<64>(nq, dual);
+BwdFn pick_bwd(int bsz, int nq, bool dual, bool nodal) {
+  if (nodal) {
+    if (bsz == 256) return bwd_kernel<256, true>(nq, dual);
+    if (bsz == 128) return bwd_kernel<128, true>(nq, dual);
+    return bwd_kernel<64, true>(nq, dual);
+  }
+  if (bsz == 256) return bwd_kernel<256, false>(nq, dual);
+  if (bsz == 128) return bwd_kernel<128, false>(nq, dual);
+  return bwd_kernel<64, false>(nq, dual);
 }
 
 // Blocks of kernel fn (block size bsz) resident on one compute unit, from
@@ -285,6 +302,7 @@ struct mt_batch {
   mt_batch_tuning tune{};
   int nq = 7;
   bool dual = false;
+  bool nodal = false;
   std::vector<mt::BatchInst> h_inst;
   std::vector<int64_t> pattern_gen;  // each instance's pattern generation at mt_batch_build
   mt::BatchInst* pinned = nullptr;
@@ -353,15 +371,20 @@ int build_items(mt_batch* b, hipStream_t st) {
 // Current coordinate arrays of every instance (they may have been replaced
 // with mt_update_coordinates since mt_batch_build); an instance whose pair
 // list or pattern was rebuilt needs a new mt_batch_build.
-int sync_instances(mt_batch* b) {
+int sync_instances(mt_batch* b, hipStream_t st) {
   for (size_t i = 0; i < b->ctxs.size(); ++i) {
     mt_ctx* c = b->ctxs[i];
     if (!c->have_pattern || c->pattern_gen != b->pattern_gen[i])
       return bfail(MT_ESTATE, "batch: an instance was rebuilt since mt_batch_build; build the batch again");
+    if (b->nodal) {
+      // the normal field of the current coordinates, before any polygon refresh
+      int rc = ensure_normals(c, st);
+      if (rc) return rc;
+    }
     const DeviceMesh& S = c->side[0];
     const DeviceMesh& M = c->side[1];
-    b->h_inst[i].S = MeshPtrs{S.x, S.y, S.z, S.conn};
-    b->h_inst[i].M = MeshPtrs{M.x, M.y, M.z, M.conn};
+    b->h_inst[i].S = MeshPtrs{S.x, S.y, S.z, S.conn, S.nrm};
+    b->h_inst[i].M = MeshPtrs{M.x, M.y, M.z, M.conn, nullptr};
   }
   return MT_OK;
 }
@@ -417,7 +440,7 @@ int launch_bwd_all(mt_batch* b, hipStream_t st) {
     if (rc) return rc;
   }
   const int bsz = b->tune.block;
-  BwdFn f = pick_bwd(bsz, b->nq, b->dual);
+  BwdFn f = pick_bwd(bsz, b->nq, b->dual, b->nodal);
   const int grid = b->num_cu * resident_blocks(reinterpret_cast<const void*>(f), bsz);
   k_reset_queues<<<1, 64, 0, st>>>(b->d_qnext.as<int32_t>());
   B_HIP(hipGetLastError());
@@ -429,6 +452,20 @@ int launch_bwd_all(mt_batch* b, hipStream_t st) {
                                                                  b->d_ritems_sm.as<WorkItem>());
     B_HIP(hipGetLastError());
   }
+  if (b->nodal)
+    // the chain through each instance's normal field (small kernels per
+    // instance); the output pointer is read from the device instance table,
+    // which is updated per call also when the launches replay from a graph
+    for (size_t i = 0; i < b->ctxs.size(); ++i) {
+      mt_ctx* c = b->ctxs[i];
+      const char* rec = reinterpret_cast<const char*>(b->d_inst.p) + i * sizeof(BatchInst);
+      double* const* gx_at = reinterpret_cast<double* const*>(rec + offsetof(BatchInst, gXs));
+      const MeshPtrs* s_at = reinterpret_cast<const MeshPtrs*>(rec + offsetof(BatchInst, S));
+      B_HIP(launch_normal_chain(c->side[0], c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(),
+                                c->pair_off.as<int32_t>(), c->gn0.as<double>(), std::max<int64_t>(c->n_pairs, 1),
+                                c->nrm_node.as<double>(), c->nrm_el.as<double>(), c->nrm_sb.as<double>(),
+                                c->nrm_ub.as<double>(), c->nrm_cg.as<double>(), nullptr, gx_at, s_at, st));
+    }
   return MT_OK;
 }
 
@@ -526,11 +563,14 @@ int mt_batch_build(mt_batch* b, const mt_batch_tuning* tuning, void* stream) {
     if (!c->have_pattern) return bfail(MT_ESTATE, "mt_batch_build: an instance has no pattern");
     if (c->params.rule != p0.rule || c->params.lm_basis != p0.lm_basis)
       return bfail(MT_EINVAL, "mt_batch_build: all instances must share the rule and the basis");
-    if (c->params.element_rule != 0 || c->params.normals != MT_NORMALS_ELEMENT)
-      return bfail(MT_EUNSUPPORTED, "mt_batch_build: segment-based integration with element normals only");
+    if (c->params.normals != p0.normals)
+      return bfail(MT_EINVAL, "mt_batch_build: all instances must share the normal field");
+    if (c->params.element_rule != 0)
+      return bfail(MT_EUNSUPPORTED, "mt_batch_build: segment-based integration only");
   }
   b->nq = p0.rule;
   b->dual = p0.lm_basis == MT_BASIS_DUAL;
+  b->nodal = p0.normals == MT_NORMALS_NODAL;
   mt_batch_tuning t{};
   if (tuning) t = *tuning;
   if (t.block != 64 && t.block != 128 && t.block != 256) t.block = 64;
@@ -545,19 +585,27 @@ int mt_batch_build(mt_batch* b, const mt_batch_tuning* tuning, void* stream) {
   std::vector<WorkItem> rs, rsm;
   for (size_t i = 0; i < b->ctxs.size(); ++i) {
     mt_ctx* c = b->ctxs[i];
-    if (!c->params.lm_basis) {
+    {
       int rc = ensure_master_index(c, st);
+      if (!rc && b->nodal) rc = ensure_normals(c, st);
       if (rc) return rc;
     }
     const int64_t np = std::max<int64_t>(c->n_pairs, 1);
     B_HIP(ensure(c->blk, sizeof(double) * 36 * (size_t)np));
     B_HIP(ensure(c->gpair, sizeof(double) * 24 * (size_t)np));
+    if (b->nodal) {
+      const DeviceMesh& Sn = c->side[0];
+      B_HIP(ensure(c->gn0, sizeof(double) * 3 * (size_t)np));
+      B_HIP(ensure(c->nrm_sb, sizeof(double) * 4 * (size_t)std::max(Sn.n_el, 1)));
+      B_HIP(ensure(c->nrm_ub, sizeof(double) * 4 * (size_t)std::max(Sn.n_nodes, 1)));
+      B_HIP(ensure(c->nrm_cg, sizeof(double) * 12 * (size_t)std::max(Sn.n_el, 1)));
+    }
     B_HIP(ensure(c->counters, sizeof(Counters)));
     const DeviceMesh& S = c->side[0];
     const DeviceMesh& M = c->side[1];
     BatchInst& I = b->h_inst[i];
     b->pattern_gen[i] = c->pattern_gen;
-    I.S = MeshPtrs{S.x, S.y, S.z, S.conn};
+    I.S = MeshPtrs{S.x, S.y, S.z, S.conn, S.nrm};
     I.M = MeshPtrs{M.x, M.y, M.z, M.conn};
     I.n_s_el = S.n_el;
     I.n_s_nodes = S.n_nodes;
@@ -580,6 +628,7 @@ int mt_batch_build(mt_batch* b, const mt_batch_tuning* tuning, void* stream) {
     I.mpos = c->mp_pos.as<int32_t>();
     I.blk = c->blk.as<double>();
     I.gpair = c->gpair.as<double>();
+    I.gn0 = b->nodal ? c->gn0.as<double>() : nullptr;
     {
       int rc = ensure_poly(c);
       if (rc) return rc;
@@ -630,7 +679,7 @@ int mt_batch_forward(mt_batch* b, double* const* D_val, double* const* M_val, do
     b->h_inst[i].M_val = M_val[i];
     b->h_inst[i].gap = gap[i];
   }
-  int rc = sync_instances(b);
+  int rc = sync_instances(b, st);
   if (rc) return rc;
   rc = upload_inst(b, st);
   if (rc) return rc;
@@ -661,7 +710,7 @@ int mt_batch_backward(mt_batch* b, const double* const* W_D, const double* const
     b->h_inst[i].gXs = gXs[i];
     b->h_inst[i].gXm = gXm[i];
   }
-  int rc = sync_instances(b);
+  int rc = sync_instances(b, st);
   if (rc) return rc;
   rc = upload_inst(b, st);
   if (rc) return rc;

@@ -287,16 +287,24 @@ hipError_t launch_pair_bwd(const DeviceMesh& S, const DeviceMesh& M, const KPara
                            double* gpair, double* gn0, int64_t stride, Counters* cnt, hipStream_t s);
 
 // ---- continuous normal field (mt_normals.hip) --------------------------------
+struct MeshPtrs;
+// The slave side's normal field for the current coordinates (S.nrm set), or
+// S.nrm = null with element normals.
+int ensure_normals(mt_ctx* c, hipStream_t st);
 // Nodal normals nn[4 a + 0..3] (unit normal, length before normalising) and
 // element plane normals ne[4 e + 0..3] of the slave side.
 hipError_t launch_normals(const DeviceMesh& S, const int32_t* inc_off, const int32_t* inc_list, double* nn,
                           double* ne, hipStream_t s);
 // Adds to gX (SoA [3][n_nodes]) the gradient through the element plane
 // normals, from dL/dn0 per pair (gn0[d * stride + p]); sb, ub, cg scratch of
-// 4 n_el, 4 n_nodes and 12 n_el doubles.
+// 4 n_el, 4 n_nodes and 12 n_el doubles.  With gX_at / S_at (device memory
+// holding the output pointer / the slave coordinate pointers) those are read
+// there when the kernels run, so that launches recorded in a graph follow a
+// table updated per call.
 hipError_t launch_normal_chain(const DeviceMesh& S, const int32_t* inc_off, const int32_t* inc_list,
                                const int32_t* pair_off, const double* gn0, int64_t stride, const double* nn,
-                               const double* ne, double* sb, double* ub, double* cg, double* gX, hipStream_t s);
+                               const double* ne, double* sb, double* ub, double* cg, double* gX,
+                               double* const* gX_at, const MeshPtrs* S_at, hipStream_t s);
 
 KParams kparams(const mt_params& p);
 // Node incidence of the master side and the pairs-by-master permutation

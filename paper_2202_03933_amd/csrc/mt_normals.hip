@@ -125,13 +125,19 @@ __global__ __launch_bounds__(BSN) void k_node_normal_adj(int32_t n_nodes, const 
 
 // Per element: the coordinate gradient of its four corner normals, given
 // dL/du of the nodes they were added to; cg[(3 j + d) * n_el + e] for local
-// node j.
-__global__ __launch_bounds__(BSN) void k_corner_adj(const double* __restrict__ x, const double* __restrict__ y,
-                                                    const double* __restrict__ z, const int32_t* __restrict__ conn,
-                                                    int32_t n_el, const double* __restrict__ ub,
-                                                    double* __restrict__ cg) {
+// node j.  With S_at the coordinate arrays are read from device memory (see
+// k_corner_gather).
+__global__ __launch_bounds__(BSN) void k_corner_adj(const double* x, const double* y, const double* z,
+                                                    const int32_t* __restrict__ conn, int32_t n_el,
+                                                    const double* __restrict__ ub, double* __restrict__ cg,
+                                                    const MeshPtrs* S_at) {
   const int e = blockIdx.x * BSN + threadIdx.x;
   if (e >= n_el) return;
+  if (S_at) {
+    x = S_at->x;
+    y = S_at->y;
+    z = S_at->z;
+  }
   const int4 c = load_conn(conn, e);
   const int nd[4] = {c.x, c.y, c.z, c.w};
   double G[4][3];
@@ -162,12 +168,15 @@ __global__ __launch_bounds__(BSN) void k_corner_adj(const double* __restrict__ x
 }
 
 // gX[d * n + a] += sum over the elements around node a of their corner
-// gradients at a.
+// gradients at a.  With gX_at, the output pointer is read from device
+// memory (a launch recorded in a graph then follows a table updated per call).
 __global__ __launch_bounds__(BSN) void k_corner_gather(int32_t n_nodes, const int32_t* __restrict__ inc_off,
                                                        const int32_t* __restrict__ inc_list, int32_t n_el,
-                                                       const double* __restrict__ cg, double* __restrict__ gX) {
+                                                       const double* __restrict__ cg, double* gX,
+                                                       double* const* gX_at) {
   const int a = blockIdx.x * BSN + threadIdx.x;
   if (a >= n_nodes) return;
+  if (gX_at) gX = *gX_at;
   double g[3] = {0.0, 0.0, 0.0};
   for (int i = inc_off[a]; i < inc_off[a + 1]; ++i) {
     const int e = inc_list[i] >> 2, j = inc_list[i] & 3;
@@ -192,12 +201,13 @@ hipError_t launch_normals(const DeviceMesh& S, const int32_t* inc_off, const int
 
 hipError_t launch_normal_chain(const DeviceMesh& S, const int32_t* inc_off, const int32_t* inc_list,
                                const int32_t* pair_off, const double* gn0, int64_t stride, const double* nn,
-                               const double* ne, double* sb, double* ub, double* cg, double* gX, hipStream_t s) {
+                               const double* ne, double* sb, double* ub, double* cg, double* gX,
+                               double* const* gX_at, const MeshPtrs* S_at, hipStream_t s) {
   if (S.n_el == 0) return hipSuccess;
   k_elem_normal_adj<<<blocks(S.n_el), BSN, 0, s>>>(S.n_el, pair_off, gn0, stride, ne, sb);
   k_node_normal_adj<<<blocks(S.n_nodes), BSN, 0, s>>>(S.n_nodes, inc_off, inc_list, sb, nn, ub);
-  k_corner_adj<<<blocks(S.n_el), BSN, 0, s>>>(S.x, S.y, S.z, S.conn, S.n_el, ub, cg);
-  k_corner_gather<<<blocks(S.n_nodes), BSN, 0, s>>>(S.n_nodes, inc_off, inc_list, S.n_el, cg, gX);
+  k_corner_adj<<<blocks(S.n_el), BSN, 0, s>>>(S.x, S.y, S.z, S.conn, S.n_el, ub, cg, S_at);
+  k_corner_gather<<<blocks(S.n_nodes), BSN, 0, s>>>(S.n_nodes, inc_off, inc_list, S.n_el, cg, gX, gX_at);
   return hipGetLastError();
 }
 

@@ -142,14 +142,33 @@ def test_coordinate_update_recomputes_the_field():
     assert all(torch.equal(x, y) for x, y in zip(ga, gb))
 
 
-def test_batch_rejects_nodal_normals():
-    from paper_2202_03933_amd import MortarBatch, MortarError, MortarInterface
-    from paper_2202_03933_amd import _capi as C
-    itf = synth.interface_config(0)
+@pytest.mark.parametrize("dual", [False, True])
+def test_batch_bitwise_equal_to_single_interfaces(dual):
+    # batched forward and backward with the normal field (the chain runs per
+    # instance after the persistent launch), eager and over graph replays,
+    # also after moving one instance's coordinates
+    from paper_2202_03933_amd import MortarBatch, MortarInterface
+    from tests.test_gpu_batch import weights_for
     dev = torch.device("cuda", 0)
-    it = MortarInterface(torch.from_numpy(itf.slave.X), torch.from_numpy(itf.slave.conn),
-                         torch.from_numpy(itf.master.X), torch.from_numpy(itf.master.conn),
-                         params=gpu_params(itf, nodal=True), device=dev).setup()
-    with pytest.raises(MortarError) as e:
-        MortarBatch([it])
-    assert e.value.code == C.MT_EUNSUPPORTED
+    insts = synth.batched_instances(n_inst=6, max_side=36)
+    its = [MortarInterface(torch.from_numpy(i.slave.X), torch.from_numpy(i.slave.conn),
+                           torch.from_numpy(i.master.X), torch.from_numpy(i.master.conn),
+                           params=gpu_params(i, dual=dual, nodal=True), device=dev).setup() for i in insts]
+    W = [weights_for(it, 4100 + k) for k, it in enumerate(its)]
+    b = MortarBatch(its)
+    for step in range(2):
+        if step == 1:
+            X = insts[2].slave.X + 1e-9 * np.random.default_rng(1).standard_normal(insts[2].slave.X.shape)
+            its[2].set_coordinates(torch.from_numpy(X), torch.from_numpy(insts[2].master.X))
+        ref = [tuple(t.clone() for t in it.integrate()) for it in its]
+        ref_g = [tuple(t.clone() for t in it.backward(*w)) for it, w in zip(its, W)]
+        for use_graph in (False, True, True):
+            outs = b.forward(use_graph=use_graph)
+            g = b.backward(W, use_graph=use_graph)
+            torch.cuda.synchronize()
+            assert all(all(torch.equal(x, y) for x, y in zip(o, r)) for o, r in zip(outs, ref))
+            diff = [[(x - y).abs().max().item() for x, y in zip(o, r)] for o, r in zip(g, ref_g)]
+            print(f"step {step} graph {use_graph}: max |batch - single| per instance (slave, master) {diff}",
+                  flush=True)
+            assert all(all(torch.equal(x, y) for x, y in zip(o, r)) for o, r in zip(g, ref_g))
+    b.close()
