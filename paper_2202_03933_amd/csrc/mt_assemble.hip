@@ -213,6 +213,24 @@ __device__ __forceinline__ int find_col(const int32_t* __restrict__ col, int lo,
   return lo;
 }
 
+// Positions of four keys that all occur in the sorted row segment
+// col[lo..hi): one pass of independent loads over short rows (no dependent
+// chain of a binary search), a binary search per key over long ones.
+__device__ __forceinline__ void find_cols4(const int32_t* __restrict__ col, int lo, int hi, const int key[4],
+                                           int pos[4]) {
+  if (hi - lo <= 32) {
+    pos[0] = pos[1] = pos[2] = pos[3] = lo;
+    for (int i = lo; i < hi; ++i) {
+      const int c = col[i];
+#pragma unroll
+      for (int l = 0; l < 4; ++l) pos[l] = c == key[l] ? i : pos[l];
+    }
+  } else {
+#pragma unroll
+    for (int l = 0; l < 4; ++l) pos[l] = find_col(col, lo, hi, key[l]);
+  }
+}
+
 __global__ __launch_bounds__(BS) void k_posD(const int32_t* __restrict__ conn_s, int32_t n_el,
                                               const int32_t* __restrict__ pair_off, const int32_t* __restrict__ rowptr,
                                               const int32_t* __restrict__ col, int32_t* __restrict__ posD) {
@@ -222,10 +240,12 @@ __global__ __launch_bounds__(BS) void k_posD(const int32_t* __restrict__ conn_s,
   const int4 c = reinterpret_cast<const int4*>(conn_s)[e];
   const int id[4] = {c.x, c.y, c.z, c.w};
 #pragma unroll
-  for (int j = 0; j < 4; ++j)
+  for (int j = 0; j < 4; ++j) {
+    int pos[4] = {-1, -1, -1, -1};
+    if (has) find_cols4(col, rowptr[id[j]], rowptr[id[j] + 1], id, pos);
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-      posD[(int64_t)(j * 4 + k) * n_el + e] = has ? find_col(col, rowptr[id[j]], rowptr[id[j] + 1], id[k]) : -1;
+    for (int k = 0; k < 4; ++k) posD[(int64_t)(j * 4 + k) * n_el + e] = pos[k];
+  }
 }
 
 __global__ __launch_bounds__(BS) void k_posM(const int32_t* __restrict__ conn_s, const int32_t* __restrict__ conn_m,
@@ -240,9 +260,10 @@ __global__ __launch_bounds__(BS) void k_posM(const int32_t* __restrict__ conn_s,
   const int cm[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const int lo = rowptr[rs[j]], hi = rowptr[rs[j] + 1];
+    int pos[4];
+    find_cols4(col, rowptr[rs[j]], rowptr[rs[j] + 1], cm, pos);
 #pragma unroll
-    for (int l = 0; l < 4; ++l) posM[(int64_t)(j * 4 + l) * np + p] = find_col(col, lo, hi, cm[l]);
+    for (int l = 0; l < 4; ++l) posM[(int64_t)(j * 4 + l) * np + p] = pos[l];
   }
 }
 
