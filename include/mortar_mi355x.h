@@ -266,6 +266,9 @@ typedef struct mt_timings {
 
 /* Enable (1) or disable (0) the phase timers of a context. */
 int mt_set_timing(mt_ctx* ctx, int enable);
+/* Enable the timers of the phases whose bit (1 << MT_T_...) is set in mask
+ * only (0 disables all): fewer events in a timed loop. */
+int mt_set_timing_phases(mt_ctx* ctx, uint32_t mask);
 
 /* Sum the recorded intervals into *t (host); reset != 0 clears them.
  * Synchronises on the recorded events. */

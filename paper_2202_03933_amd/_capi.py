@@ -70,6 +70,7 @@ SIGNATURES = {
     "mt_get_stats": (_int, [_vp, ctypes.POINTER(mt_stats)]),
     "mt_last_error": (ctypes.c_char_p, []),
     "mt_set_timing": (_int, [_vp, _int]),
+    "mt_set_timing_phases": (_int, [_vp, ctypes.c_uint32]),
     "mt_get_timings": (_int, [_vp, ctypes.POINTER(mt_timings), _int]),
     "mt_batch_create": (_int, [ctypes.POINTER(_vp), _int]),
     "mt_batch_destroy": (_int, [_vp]),

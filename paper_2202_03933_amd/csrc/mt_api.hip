@@ -66,7 +66,7 @@ struct PhaseTimer {
   hipStream_t st;
   hipEvent_t a = nullptr;
   PhaseTimer(mt_ctx* c_, int ph, hipStream_t s) : c(c_), phase(ph), st(s) {
-    if (c->timing && (a = take_event(c)) != nullptr) (void)hipEventRecord(a, st);
+    if (c->timing && ((c->timing_mask >> ph) & 1u) && (a = take_event(c)) != nullptr) (void)hipEventRecord(a, st);
   }
   ~PhaseTimer() {
     if (!a) return;
@@ -770,9 +770,17 @@ int mt_backward(mt_ctx* c, const double* W_D, const double* W_M, const double* w
   return MT_OK;
 }
 
+int mt_set_timing_phases(mt_ctx* c, uint32_t mask) {
+  if (!c) return fail(MT_EINVAL, "mt_set_timing_phases: null ctx");
+  c->timing = mask != 0;
+  c->timing_mask = mask;
+  return MT_OK;
+}
+
 int mt_set_timing(mt_ctx* c, int enable) {
   if (!c) return fail(MT_EINVAL, "mt_set_timing: null ctx");
   c->timing = enable != 0;
+  c->timing_mask = ~0u;
   return MT_OK;
 }
 

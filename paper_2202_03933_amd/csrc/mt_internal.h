@@ -97,6 +97,7 @@ struct mt_ctx {
   int device = 0;
   // phase timers
   bool timing = false;
+  uint32_t timing_mask = ~0u;  // phases recorded while timing is on
   struct Interval { int phase; hipEvent_t a, b; };
   std::vector<Interval> intervals;
   std::vector<hipEvent_t> event_pool;

@@ -167,8 +167,16 @@ class MortarInterface:
                 "n_degenerate_slave": st.n_degenerate_slave, "n_degenerate_master": st.n_degenerate_master,
                 "nnz_D": st.nnz_D, "nnz_M": st.nnz_M, "n_bins": list(st.n_bins), "bin_size": list(st.bin_size)}
 
-    def set_timing(self, enable=True):
-        C.check(C.lib().mt_set_timing(self.h, 1 if enable else 0))
+    def set_timing(self, enable=True, phases=None):
+        """Phase timers on or off; with phases (names from _capi.MT_T_NAMES)
+        only those phases are recorded."""
+        if phases is None:
+            C.check(C.lib().mt_set_timing(self.h, 1 if enable else 0))
+        else:
+            mask = 0
+            for name in phases:
+                mask |= 1 << C.MT_T_NAMES.index(name)
+            C.check(C.lib().mt_set_timing_phases(self.h, mask if enable else 0))
 
     def timings(self, reset=False):
         """{phase: (summed ms, intervals)} of the library's phase timers."""
