@@ -10,6 +10,61 @@
 
 namespace mt {
 
+// The pairs that one node's row gathers, as one flat sequence k = 0 .. n-1:
+// the pairs of its incident elements (ascending), each element's pairs in
+// their order.  Up to four incident elements are held in registers, so the
+// loads of several consecutive pairs can be issued before any of them is
+// added; the additions still run in the sequence order, so the sums are the
+// same bit for bit as those of the plain nested loops (used for nodes with
+// more than four elements).
+constexpr int ROW_RUNS = 4;
+
+struct RowRuns {
+  int e[ROW_RUNS];   // incident element
+  int j[ROW_RUNS];   // local index of the node in it
+  int p0[ROW_RUNS];  // first pair (or pair position) of the element
+  int c1, c2, c3;    // flat index at which elements 1, 2, 3 start
+  int n;             // number of pairs in all
+};
+
+// Runs of the ni <= ROW_RUNS incidences inc_list[i0 ..]; element e's pairs
+// are lo[e] .. hi[e] - 1.
+__device__ __forceinline__ void load_runs(int i0, int ni, const int32_t* __restrict__ inc_list,
+                                          const int32_t* __restrict__ lo, const int32_t* __restrict__ hi,
+                                          RowRuns& R) {
+  int l[ROW_RUNS], h[ROW_RUNS];
+#pragma unroll
+  for (int t = 0; t < ROW_RUNS; ++t) {
+    const int v = t < ni ? inc_list[i0 + t] : 0;
+    R.e[t] = v >> 2;
+    R.j[t] = v & 3;
+  }
+#pragma unroll
+  for (int t = 0; t < ROW_RUNS; ++t) {
+    l[t] = t < ni ? lo[R.e[t]] : 0;
+    h[t] = t < ni ? hi[R.e[t]] : 0;
+    R.p0[t] = l[t];
+  }
+  R.c1 = h[0] - l[0];
+  R.c2 = R.c1 + (h[1] - l[1]);
+  R.c3 = R.c2 + (h[2] - l[2]);
+  R.n = R.c3 + (h[3] - l[3]);
+}
+
+// Local index j and pair p of flat position k (0 <= k < n); empty elements
+// are skipped because their start equals the next one's.
+__device__ __forceinline__ int run_at(const RowRuns& R, int k, int& j) {
+  int base = 0, p0 = R.p0[0];
+  j = R.j[0];
+  if (k >= R.c1) { base = R.c1; p0 = R.p0[1]; j = R.j[1]; }
+  if (k >= R.c2) { base = R.c2; p0 = R.p0[2]; j = R.j[2]; }
+  if (k >= R.c3) { base = R.c3; p0 = R.p0[3]; j = R.j[3]; }
+  return p0 + (k - base);
+}
+
+// pairs whose loads the gradient gathers issue together
+constexpr int ROW_BATCH = 8;
+
 // Row a of D, M and the gap from the staged local blocks blk[c * stride + p].
 __device__ __forceinline__ void assemble_row(int a, const int32_t* __restrict__ inc_off,
                                              const int32_t* __restrict__ inc_list,
@@ -42,9 +97,53 @@ __device__ __forceinline__ void assemble_row(int a, const int32_t* __restrict__ 
   gap[a] = g;
 }
 
+// Row a accumulated in the per-thread scratch segment acc[i * astride] (D
+// entries first, then M) by plain nested loops over the incident elements
+// and their pairs; for nodes with more than ROW_RUNS incident elements.
+__device__ __forceinline__ void assemble_row_acc_loops(int a, const int32_t* __restrict__ inc_off,
+                                                       const int32_t* __restrict__ inc_list,
+                                                       const int32_t* __restrict__ pair_off, int d0, int nd, int m0,
+                                                       int nm, const int32_t* __restrict__ posD, int32_t n_s_el,
+                                                       const int32_t* __restrict__ posM,
+                                                       const double* __restrict__ blk, int64_t stride,
+                                                       double* __restrict__ D_val, double* __restrict__ M_val,
+                                                       double* __restrict__ gap, double* acc, int astride) {
+  for (int i = 0; i < nd + nm; ++i) acc[i * astride] = 0.0;
+  double g = 0.0;
+  const int moff = nd - m0;
+  for (int i = inc_off[a]; i < inc_off[a + 1]; ++i) {
+    const int e = inc_list[i] >> 2, j = inc_list[i] & 3;
+    const int p0 = pair_off[e], p1 = pair_off[e + 1];
+    if (p0 == p1) continue;
+    int pd[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pd[k] = posD[(int64_t)(j * 4 + k) * n_s_el + e] - d0;
+    for (int p = p0; p < p1; ++p) {
+      double vd[4], vm[4];
+      int pm[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        vd[k] = blk[(int64_t)(j * 4 + k) * stride + p];
+        vm[k] = blk[(int64_t)(16 + j * 4 + k) * stride + p];
+        pm[k] = posM[(int64_t)(j * 4 + k) * stride + p] + moff;
+      }
+      g += blk[(int64_t)(32 + j) * stride + p];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc[pd[k] * astride] += vd[k];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) acc[pm[k] * astride] += vm[k];
+    }
+  }
+  for (int i = 0; i < nd; ++i) D_val[d0 + i] = acc[i * astride];
+  for (int i = 0; i < nm; ++i) M_val[m0 + i] = acc[(nd + i) * astride];
+  gap[a] = g;
+}
+
 // Same as assemble_row, accumulating the row in a per-thread scratch segment
-// acc[i * stride] (D entries first, then M) and writing it once; rows longer
-// than cap entries fall back to assemble_row.
+// acc[i * astride] (D entries first, then M) and writing it once; rows longer
+// than cap entries fall back to assemble_row.  (Issuing the loads of several
+// pairs together, as the gradient gathers below do, measured slower here:
+// the row's LDS updates, not its loads, set the pace.)
 __device__ __forceinline__ void assemble_row_acc(int a, const int32_t* __restrict__ inc_off,
                                                  const int32_t* __restrict__ inc_list,
                                                  const int32_t* __restrict__ pair_off,
@@ -94,6 +193,32 @@ __device__ __forceinline__ void assemble_row_acc(int a, const int32_t* __restric
   gap[a] = g;
 }
 
+// Sum over the flat pair sequence of R of the three components
+// gpair[(c0 + 3 j + d) * stride + p], d = 0, 1, 2, in sequence order.
+__device__ __forceinline__ void gather3(const RowRuns& R, int c0, const double* __restrict__ gpair, int64_t stride,
+                                        double& g0, double& g1, double& g2) {
+  constexpr int U = ROW_BATCH;
+  for (int k0 = 0; k0 < R.n; k0 += U) {
+    double v[U][3];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      // positions past the end reload the last pair and are not added
+      int j;
+      const int p = run_at(R, min(k0 + u, R.n - 1), j);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) v[u][d] = gpair[(int64_t)(c0 + 3 * j + d) * stride + p];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (k0 + u < R.n) {
+        g0 += v[u][0];
+        g1 += v[u][1];
+        g2 += v[u][2];
+      }
+    }
+  }
+}
+
 // Gradient of slave node a (structure-of-arrays gX[3 * n]).
 __device__ __forceinline__ void grad_slave_row(int a, int32_t n, const int32_t* __restrict__ inc_off,
                                                const int32_t* __restrict__ inc_list,
@@ -101,12 +226,19 @@ __device__ __forceinline__ void grad_slave_row(int a, int32_t n, const int32_t* 
                                                const double* __restrict__ gpair, int64_t stride,
                                                double* __restrict__ gX) {
   double g0 = 0.0, g1 = 0.0, g2 = 0.0;
-  for (int i = inc_off[a]; i < inc_off[a + 1]; ++i) {
-    const int e = inc_list[i] >> 2, j = inc_list[i] & 3;
-    for (int p = pair_off[e]; p < pair_off[e + 1]; ++p) {
-      g0 += gpair[(int64_t)(3 * j + 0) * stride + p];
-      g1 += gpair[(int64_t)(3 * j + 1) * stride + p];
-      g2 += gpair[(int64_t)(3 * j + 2) * stride + p];
+  const int i0 = inc_off[a], ni = inc_off[a + 1] - i0;
+  if (ni <= ROW_RUNS) {
+    RowRuns R;
+    load_runs(i0, ni, inc_list, pair_off, pair_off + 1, R);
+    gather3(R, 0, gpair, stride, g0, g1, g2);
+  } else {
+    for (int i = i0; i < i0 + ni; ++i) {
+      const int e = inc_list[i] >> 2, j = inc_list[i] & 3;
+      for (int p = pair_off[e]; p < pair_off[e + 1]; ++p) {
+        g0 += gpair[(int64_t)(3 * j + 0) * stride + p];
+        g1 += gpair[(int64_t)(3 * j + 1) * stride + p];
+        g2 += gpair[(int64_t)(3 * j + 2) * stride + p];
+      }
     }
   }
   gX[a] = g0;
@@ -124,12 +256,19 @@ __device__ __forceinline__ void grad_master_row(int b, int32_t n, const int32_t*
                                                 const double* __restrict__ gpair, int64_t stride,
                                                 double* __restrict__ gX) {
   double g0 = 0.0, g1 = 0.0, g2 = 0.0;
-  for (int i = inc_off[b]; i < inc_off[b + 1]; ++i) {
-    const int m = inc_list[i] >> 2, l = inc_list[i] & 3;
-    for (int k = mstart[m]; k < mend[m]; ++k) {
-      g0 += gpair[(int64_t)(12 + 3 * l + 0) * stride + k];
-      g1 += gpair[(int64_t)(12 + 3 * l + 1) * stride + k];
-      g2 += gpair[(int64_t)(12 + 3 * l + 2) * stride + k];
+  const int i0 = inc_off[b], ni = inc_off[b + 1] - i0;
+  if (ni <= ROW_RUNS) {
+    RowRuns R;
+    load_runs(i0, ni, inc_list, mstart, mend, R);
+    gather3(R, 12, gpair, stride, g0, g1, g2);
+  } else {
+    for (int i = i0; i < i0 + ni; ++i) {
+      const int m = inc_list[i] >> 2, l = inc_list[i] & 3;
+      for (int k = mstart[m]; k < mend[m]; ++k) {
+        g0 += gpair[(int64_t)(12 + 3 * l + 0) * stride + k];
+        g1 += gpair[(int64_t)(12 + 3 * l + 1) * stride + k];
+        g2 += gpair[(int64_t)(12 + 3 * l + 2) * stride + k];
+      }
     }
   }
   gX[b] = g0;

@@ -234,40 +234,56 @@ __device__ __forceinline__ bool touch(const SlaveBox& s, const double* __restric
   return t;
 }
 
-constexpr int CCAP = 48;  // per-thread LDS segment of the candidate fill (masters)
+constexpr int CCAP = 48;  // per-thread LDS segment of the long-list fill (masters)
 constexpr int CTMP = 32;  // candidates per slave kept by the count pass
+constexpr int G = 4;      // lanes per slave element in the count and fill passes
+static_assert(64 % G == 0 && BS % G == 0, "groups must not straddle a wave");
+constexpr int OWN = CTMP / G;  // candidates per lane in the grouped fill
 
-// Candidates of one slave element: masters of its own and the 26 neighbouring
-// cells whose boxes touch its delta-enlarged box.  The count pass writes the
-// number and keeps the first CTMP in a lane-interleaved scratch array
-// tmp[k * n_s + s]; the fill pass collects them from there (or walks the
-// cells again when there were more), sorts them by master index in a
-// lane-interleaved LDS segment (in place when longer than CCAP) and writes
-// them out.
-template <bool FILL>
-__device__ __forceinline__ int walk_cells(const SlaveBox& b, const double* __restrict__ sbox,
-                                          const uint32_t* __restrict__ mvals, const int2* __restrict__ range,
-                                          const Grid& g, double delta, int32_t* v, int64_t vs, int vcap) {
-  // the 27 cells around the slave centre's cell, restricted to those that
-  // can hold the centre of a touching master (within g.reach of the box)
-  int c0[3], c1[3];
+// The 27 cells around the slave centre's cell, restricted to those that can
+// hold the centre of a touching master (within g.reach of the box).
+__device__ __forceinline__ void cell_window(const SlaveBox& b, const Grid& g, int c0[3], int c1[3]) {
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const int ic = cell_coord(0.5 * (b.lo[d] + b.hi[d]), g.lo[d], g.inv_beta[d], g.n[d]);
     c0[d] = max(ic - 1, cell_coord(b.lo[d] - g.reach, g.lo[d], g.inv_beta[d], g.n[d]));
     c1[d] = min(ic + 1, cell_coord(b.hi[d] + g.reach, g.lo[d], g.inv_beta[d], g.n[d]));
   }
+}
+
+// The cells c0[0] .. c1[0] of one (y, z) row have consecutive keys, so their
+// masters form one run [lo, hi) of the cell-sorted list (empty cells hold the
+// range (0, 0)); walking it visits them in the same order as cell by cell.
+__device__ __forceinline__ void row_run(const int2* __restrict__ range, int64_t row, int x0, int x1, int& lo,
+                                        int& hi) {
+  lo = 0x7fffffff;
+  hi = 0;
+  for (int xx = x0; xx <= x1; ++xx) {
+    const int2 r = range[row + xx];
+    if (r.y > r.x) {
+      lo = min(lo, r.x);
+      hi = max(hi, r.y);
+    }
+  }
+}
+
+// Candidates of one slave element: masters of its own and the 26 neighbouring
+// cells whose boxes touch its delta-enlarged box, in walk order; the first
+// vcap go to v[k * vs].  One lane per slave.
+__device__ __forceinline__ int walk_cells(const SlaveBox& b, const double* __restrict__ sbox,
+                                          const uint32_t* __restrict__ mvals, const int2* __restrict__ range,
+                                          const Grid& g, double delta, int32_t* v, int64_t vs, int vcap) {
+  int c0[3], c1[3];
+  cell_window(b, g, c0, c1);
   int c = 0;
   for (int zz = c0[2]; zz <= c1[2]; ++zz) {
     for (int yy = c0[1]; yy <= c1[1]; ++yy) {
-      for (int xx = c0[0]; xx <= c1[0]; ++xx) {
-        const int64_t cell = xx + (int64_t)g.n[0] * (yy + (int64_t)g.n[1] * zz);
-        const int2 r = range[cell];
-        for (int i = r.x; i < r.y; ++i) {
-          if (touch(b, sbox, i, delta)) {
-            if (c < vcap) v[c * vs] = (int)mvals[i];
-            ++c;
-          }
+      int lo, hi;
+      row_run(range, (int64_t)g.n[0] * (yy + (int64_t)g.n[1] * zz), c0[0], c1[0], lo, hi);
+      for (int i = lo; i < hi; ++i) {
+        if (touch(b, sbox, i, delta)) {
+          if (c < vcap) v[c * vs] = (int)mvals[i];
+          ++c;
         }
       }
     }
@@ -275,15 +291,50 @@ __device__ __forceinline__ int walk_cells(const SlaveBox& b, const double* __res
   return c;
 }
 
+// Same walk by a group of G lanes of one wave (lane r of the group tests
+// masters lo + r, lo + r + G, ...): the group's hits of one step are ranked
+// by a wave ballot, so v receives the same candidates in the same order as
+// the one-lane walk, and the boxes a group reads in one step are adjacent.
+__device__ __forceinline__ int walk_cells_group(const SlaveBox& b, const double* __restrict__ sbox,
+                                                const uint32_t* __restrict__ mvals, const int2* __restrict__ range,
+                                                const Grid& g, double delta, int32_t* v, int64_t vs, int vcap, int r,
+                                                int gshift) {
+  int c0[3], c1[3];
+  cell_window(b, g, c0, c1);
+  const unsigned below = (1u << r) - 1u;
+  int c = 0;
+  for (int zz = c0[2]; zz <= c1[2]; ++zz) {
+    for (int yy = c0[1]; yy <= c1[1]; ++yy) {
+      int lo, hi;
+      row_run(range, (int64_t)g.n[0] * (yy + (int64_t)g.n[1] * zz), c0[0], c1[0], lo, hi);
+      for (int i0 = lo; i0 < hi; i0 += G) {
+        const int i = i0 + r;
+        const bool hit = i < hi && touch(b, sbox, i, delta);
+        const unsigned m = (unsigned)(__ballot(hit) >> gshift) & ((1u << G) - 1u);
+        if (hit) {
+          const int k = c + __popc(m & below);
+          if (k < vcap) v[k * vs] = (int)mvals[i];
+        }
+        c += __popc(m);
+      }
+    }
+  }
+  return c;
+}
+
+// Count pass, G lanes per slave: the number of candidates, and the first
+// CTMP of them (walk order) in the lane-interleaved scratch tmp[k * n_s + s].
 __global__ __launch_bounds__(BS) void k_cand_count(const double* __restrict__ box_s, int32_t n_s,
                                                     const double* __restrict__ sbox,
                                                     const uint32_t* __restrict__ mvals,
                                                     const int2* __restrict__ range, Grid g, double delta,
                                                     int32_t* __restrict__ count, int32_t* __restrict__ tmp) {
-  const int s = blockIdx.x * BS + threadIdx.x;
-  if (s >= n_s) return;
+  const int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x;
+  const int s = (int)(t / G), r = (int)(t % G);
+  if (s >= n_s) return;  // whole groups leave together
   const SlaveBox b = load_box(box_s, n_s, s);
-  count[s] = walk_cells<false>(b, sbox, mvals, range, g, delta, tmp + s, n_s, CTMP);
+  const int c = walk_cells_group(b, sbox, mvals, range, g, delta, tmp + s, n_s, CTMP, r, (int)(__lane_id() & ~(G - 1)));
+  if (r == 0) count[s] = c;
 }
 
 __device__ __forceinline__ void load_master_data(const double* __restrict__ md, int m, double X[4][3]) {
@@ -296,32 +347,105 @@ __device__ __forceinline__ void load_master_data(const double* __restrict__ md, 
   }
 }
 
-// Fill pass, fused with the screening of each candidate: the slave plane
-// data are loaded once per slave element (one lane per slave), each master
-// element's nodes with six 16-byte loads; the projection onto the slave
-// plane, degeneracy checks and the separating-line quick exit decide
-// flag[c] (1: to be clipped; otherwise the vertex count is 0).  The
-// candidates are sorted in a lane-interleaved LDS segment, or in place in
-// the output when longer than CCAP (two call sites, so that each pointer
-// has a known address space).
+// Screening of one candidate (master m of slave s, output slot ci) against
+// the slave plane data: projection of the master nodes, degeneracy checks and
+// the separating-line quick exit decide flag[ci] (1: to be clipped;
+// otherwise the vertex count is 0).
+struct SlavePlane {
+  double f[12], As;
+  V2 S[4];
+};
+
+__device__ __forceinline__ void load_plane(const double* __restrict__ sd, int32_t n_s, int s, SlavePlane& P) {
+#pragma unroll
+  for (int k = 0; k < 12; ++k) P.f[k] = sd[(int64_t)k * n_s + s];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    P.S[k].u = sd[(int64_t)(12 + k) * n_s + s];
+    P.S[k].v = sd[(int64_t)(16 + k) * n_s + s];
+  }
+  P.As = sd[(int64_t)20 * n_s + s];
+}
+
 struct ScreenOut {
   unsigned degen_s, degen_m;
 };
 
-__device__ __forceinline__ void fill_and_screen(int s, int32_t n_s, int base, int c, int32_t* v, int vs,
-                                                bool copy_out, const double* __restrict__ box_s,
-                                                const double* __restrict__ sbox, const uint32_t* __restrict__ mvals,
-                                                const int2* __restrict__ range, const Grid& g, double delta,
-                                                const int32_t* __restrict__ tmp, int32_t* __restrict__ cand_s,
-                                                int32_t* __restrict__ cand_m, const double* __restrict__ sd,
-                                                const double* __restrict__ md, double eps_a,
-                                                uint8_t* __restrict__ nv_out, int32_t* __restrict__ flag,
-                                                ScreenOut& so) {
-  if (c <= CTMP) {
-    for (int i = 0; i < c; ++i) v[i * vs] = tmp[(int64_t)i * n_s + s];
-  } else {
-    walk_cells<true>(load_box(box_s, n_s, s), sbox, mvals, range, g, delta, v, vs, c);
+__device__ __forceinline__ void screen_one(const SlavePlane& P, int s, int m, int64_t ci,
+                                           const double* __restrict__ md, double eps_a, int32_t* __restrict__ cand_s,
+                                           int32_t* __restrict__ cand_m, uint8_t* __restrict__ nv_out,
+                                           int32_t* __restrict__ flag, ScreenOut& so) {
+  double Xm[4][3];
+  load_master_data(md, m, Xm);
+  V2 Mn[4];
+  double hm[4];
+  int st;
+  bool flip;
+  const bool clip = pair_screen(P.S, P.As, Xm, P.f, eps_a, Mn, hm, flip, st);
+  flag[ci] = clip ? 1 : 0;
+  if (!clip) nv_out[ci] = 0;
+  so.degen_s += (st & PS_DEGEN_SLAVE) ? 1u : 0u;
+  so.degen_m += (st & PS_DEGEN_MASTER) ? 1u : 0u;
+  cand_m[ci] = m;
+  cand_s[ci] = s;
+}
+
+__device__ __forceinline__ void count_degenerate(const ScreenOut& so, Counters* cnt) {
+  // degenerate elements are rare: count them with global atomics
+  if (so.degen_s) atomicAdd(&cnt->degen_slave, (unsigned long long)so.degen_s);
+  if (so.degen_m) atomicAdd(&cnt->degen_master, (unsigned long long)so.degen_m);
+}
+
+// Fill pass for slaves with at most CTMP candidates, G lanes per slave: lane
+// r takes the candidates r, r + G, ... of the count pass's list, finds the
+// place of each in the master-sorted order by counting the smaller masters
+// of the list (the masters of one slave are distinct), screens it and writes
+// it there.  No lane reads what another lane wrote.
+__global__ __launch_bounds__(BS) void k_cand_fill(int32_t n_s, const int32_t* __restrict__ tmp,
+                                                   const int32_t* __restrict__ off, int32_t* __restrict__ cand_s,
+                                                   int32_t* __restrict__ cand_m, const double* __restrict__ sd,
+                                                   const double* __restrict__ md, double eps_a,
+                                                   uint8_t* __restrict__ nv_out, int32_t* __restrict__ flag,
+                                                   Counters* cnt) {
+  const int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x;
+  const int s = (int)(t / G), r = (int)(t % G);
+  if (s >= n_s) return;
+  const int base = off[s];
+  const int c = off[s + 1] - base;
+  if (c > CTMP || r >= c) return;
+  int own[OWN], rank[OWN];
+#pragma unroll
+  for (int q = 0; q < OWN; ++q) {
+    const int k = r + q * G;
+    own[q] = k < c ? tmp[(int64_t)k * n_s + s] : 0x7fffffff;
+    rank[q] = 0;
   }
+  for (int k = 0; k < c; ++k) {
+    const int x = tmp[(int64_t)k * n_s + s];
+#pragma unroll
+    for (int q = 0; q < OWN; ++q) rank[q] += x < own[q] ? 1 : 0;
+  }
+  SlavePlane P;
+  load_plane(sd, n_s, s, P);
+  ScreenOut so{0u, 0u};
+  for (int q = 0; q < OWN && r + q * G < c; ++q)
+    screen_one(P, s, own[q], (int64_t)base + rank[q], md, eps_a, cand_s, cand_m, nv_out, flag, so);
+  count_degenerate(so, cnt);
+}
+
+// Fill pass for slaves with more than CTMP candidates (rare), one lane per
+// slave: the walk again, an insertion sort by master index in a
+// lane-interleaved LDS segment (in place in the output when longer than
+// CCAP; two call sites, so that each pointer has a known address space),
+// then the screening.
+__device__ __forceinline__ void fill_long(int s, int32_t n_s, int base, int c, int32_t* v, int vs,
+                                          const double* __restrict__ box_s, const double* __restrict__ sbox,
+                                          const uint32_t* __restrict__ mvals, const int2* __restrict__ range,
+                                          const Grid& g, double delta, int32_t* __restrict__ cand_s,
+                                          int32_t* __restrict__ cand_m, const double* __restrict__ sd,
+                                          const double* __restrict__ md, double eps_a, uint8_t* __restrict__ nv_out,
+                                          int32_t* __restrict__ flag, ScreenOut& so) {
+  walk_cells(load_box(box_s, n_s, s), sbox, mvals, range, g, delta, v, vs, c);
   for (int i = 1; i < c; ++i) {
     const int x = v[i * vs];
     int j = i - 1;
@@ -331,61 +455,35 @@ __device__ __forceinline__ void fill_and_screen(int s, int32_t n_s, int base, in
     }
     v[(j + 1) * vs] = x;
   }
-  double f[12], As;
-  V2 S[4];
-#pragma unroll
-  for (int k = 0; k < 12; ++k) f[k] = sd[(int64_t)k * n_s + s];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    S[k].u = sd[(int64_t)(12 + k) * n_s + s];
-    S[k].v = sd[(int64_t)(16 + k) * n_s + s];
-  }
-  As = sd[(int64_t)20 * n_s + s];
-  for (int i = 0; i < c; ++i) {
-    const int m = v[i * vs];
-    double Xm[4][3];
-    load_master_data(md, m, Xm);
-    V2 Mn[4];
-    double hm[4];
-    int st;
-    bool flip;
-    const bool clip = pair_screen(S, As, Xm, f, eps_a, Mn, hm, flip, st);
-    const int64_t ci = (int64_t)base + i;
-    flag[ci] = clip ? 1 : 0;
-    if (!clip) nv_out[ci] = 0;
-    so.degen_s += (st & PS_DEGEN_SLAVE) ? 1u : 0u;
-    so.degen_m += (st & PS_DEGEN_MASTER) ? 1u : 0u;
-    if (copy_out) cand_m[ci] = m;
-    cand_s[ci] = s;
-  }
+  SlavePlane P;
+  load_plane(sd, n_s, s, P);
+  for (int i = 0; i < c; ++i)
+    screen_one(P, s, v[i * vs], (int64_t)base + i, md, eps_a, cand_s, cand_m, nv_out, flag, so);
 }
 
-__global__ __launch_bounds__(BS) void k_cand_fill(const double* __restrict__ box_s, int32_t n_s,
-                                                   const double* __restrict__ sbox,
-                                                   const uint32_t* __restrict__ mvals,
-                                                   const int2* __restrict__ range, Grid g,
-                                                   double delta, const int32_t* __restrict__ tmp,
-                                                   const int32_t* __restrict__ off, int32_t* __restrict__ cand_s,
-                                                   int32_t* __restrict__ cand_m, const double* __restrict__ sd,
-                                                   const double* __restrict__ md, double eps_a,
-                                                   uint8_t* __restrict__ nv_out, int32_t* __restrict__ flag,
-                                                   Counters* cnt) {
+__global__ __launch_bounds__(BS) void k_cand_fill_long(const double* __restrict__ box_s, int32_t n_s,
+                                                        const double* __restrict__ sbox,
+                                                        const uint32_t* __restrict__ mvals,
+                                                        const int2* __restrict__ range, Grid g, double delta,
+                                                        const int32_t* __restrict__ off, int32_t* __restrict__ cand_s,
+                                                        int32_t* __restrict__ cand_m, const double* __restrict__ sd,
+                                                        const double* __restrict__ md, double eps_a,
+                                                        uint8_t* __restrict__ nv_out, int32_t* __restrict__ flag,
+                                                        Counters* cnt) {
   __shared__ int32_t lds[CCAP * BS];
   const int s = blockIdx.x * BS + threadIdx.x;
-  if (s < n_s) {
-    const int base = off[s];
-    const int c = off[s + 1] - base;
-    ScreenOut so{0u, 0u};
-    if (c <= CCAP)
-      fill_and_screen(s, n_s, base, c, lds + threadIdx.x, BS, true, box_s, sbox, mvals, range, g, delta, tmp, cand_s,
-                      cand_m, sd, md, eps_a, nv_out, flag, so);
-    else
-      fill_and_screen(s, n_s, base, c, cand_m + base, 1, false, box_s, sbox, mvals, range, g, delta, tmp, cand_s,
-                      cand_m, sd, md, eps_a, nv_out, flag, so);
-    // degenerate elements are rare: count them with global atomics
-    if (so.degen_s) atomicAdd(&cnt->degen_slave, (unsigned long long)so.degen_s);
-    if (so.degen_m) atomicAdd(&cnt->degen_master, (unsigned long long)so.degen_m);
-  }
+  if (s >= n_s) return;
+  const int base = off[s];
+  const int c = off[s + 1] - base;
+  if (c <= CTMP) return;
+  ScreenOut so{0u, 0u};
+  if (c <= CCAP)
+    fill_long(s, n_s, base, c, lds + threadIdx.x, BS, box_s, sbox, mvals, range, g, delta, cand_s, cand_m, sd,
+              md, eps_a, nv_out, flag, so);
+  else
+    fill_long(s, n_s, base, c, cand_m + base, 1, box_s, sbox, mvals, range, g, delta, cand_s, cand_m, sd, md,
+              eps_a, nv_out, flag, so);
+  count_degenerate(so, cnt);
 }
 
 }  // namespace
@@ -451,10 +549,12 @@ hipError_t launch_cell_ranges(const uint32_t* keys, const uint32_t* vals, int32_
   return hipGetLastError();
 }
 
+unsigned group_blocks(int32_t n_s) { return (unsigned)(((int64_t)n_s * G + BS - 1) / BS); }
+
 hipError_t launch_cand_count(const double* box_s, int32_t n_s, const double* sbox, const uint32_t* mvals,
                              const int2* range, Grid g, double delta, int32_t* count, int32_t* tmp, hipStream_t s) {
   if (n_s == 0) return hipSuccess;
-  k_cand_count<<<(n_s + BS - 1) / BS, BS, 0, s>>>(box_s, n_s, sbox, mvals, range, g, delta, count, tmp);
+  k_cand_count<<<group_blocks(n_s), BS, 0, s>>>(box_s, n_s, sbox, mvals, range, g, delta, count, tmp);
   return hipGetLastError();
 }
 
@@ -463,8 +563,9 @@ hipError_t launch_cand_fill(const double* box_s, int32_t n_s, const double* sbox
                             int32_t* cand_s, int32_t* cand_m, const double* sd, const double* md, double eps_a,
                             uint8_t* nv, int32_t* flag, Counters* cnt, hipStream_t s) {
   if (n_s == 0) return hipSuccess;
-  k_cand_fill<<<(n_s + BS - 1) / BS, BS, 0, s>>>(box_s, n_s, sbox, mvals, range, g, delta, tmp, off, cand_s, cand_m,
-                                                 sd, md, eps_a, nv, flag, cnt);
+  k_cand_fill<<<group_blocks(n_s), BS, 0, s>>>(n_s, tmp, off, cand_s, cand_m, sd, md, eps_a, nv, flag, cnt);
+  k_cand_fill_long<<<(n_s + BS - 1) / BS, BS, 0, s>>>(box_s, n_s, sbox, mvals, range, g, delta, off, cand_s, cand_m,
+                                                      sd, md, eps_a, nv, flag, cnt);
   return hipGetLastError();
 }
 

@@ -13,6 +13,8 @@ from .meshes import (  # noqa: F401
     flat_tied,
     cylinder,
     wavy,
+    kite_fan,
+    graded_flat,
     interface_config,
     batched_instances,
     CONFIG_NAMES,

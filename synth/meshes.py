@@ -141,6 +141,51 @@ def wavy(ns=1024, nm=777, seed=1002, amp=0.05, normal_offset=1e-3, delta=1.25e-3
                      meta={"geometry": "wavy", "ns": ns, "nm": nm, "seed": seed})
 
 
+def graded_flat(ns=6, nm=40, power=3.0, delta=0.0):
+    """Flat unit square, slave grid graded in x (x = s**power), master uniform.
+
+    The slave elements range from much narrower to much wider than the
+    master elements, so the number of candidates per slave element spans
+    from a few to several dozen within one interface.
+    """
+    s, t, conn, _ = tensor_grid(ns, ns)
+    Xs = np.stack([s ** power, t, np.zeros_like(s)], axis=1)
+    s, t, connm, _ = tensor_grid(nm, nm)
+    Xm = np.stack([s, t, np.zeros_like(s)], axis=1)
+    return Interface(Mesh(Xs, conn), Mesh(Xm, connm), delta, name=f"graded flat {ns}x{ns}/{nm}x{nm}",
+                     meta={"geometry": "graded flat", "ns": ns, "nm": nm, "power": power})
+
+
+def kite_fan(n_slave=6, n_master=7, seed=1003, curvature=0.05, normal_offset=1e-3, delta=1.25e-3):
+    """Each side a fan of n convex kites around one centre node (valence n).
+
+    Kite k has nodes (centre, r_k, q_k, r_{k+1}) with r_k on the unit circle
+    at angle 2 pi k / n and q_k at radius 1.15 halfway between; the surface
+    is the paraboloid z = curvature (x^2 + y^2).  The master fan is rotated by
+    a tenth of a sector, its centre moved by (0.03, -0.02), it is scaled by
+    1.05 and its nodes are moved up by U[0, normal_offset].  Unlike the
+    tensor grids (at most four elements per node) the two centres have n
+    incident elements.
+    """
+    rng = np.random.default_rng(seed)
+
+    def fan(n, rot, centre, scale):
+        a = 2 * math.pi * np.arange(n) / n + rot
+        b = a + math.pi / n
+        xy = np.concatenate([[[0.0, 0.0]], np.stack([np.cos(a), np.sin(a)], 1),
+                             1.15 * np.stack([np.cos(b), np.sin(b)], 1)]) * scale + np.asarray(centre)
+        X = np.concatenate([xy, curvature * (xy ** 2).sum(1, keepdims=True)], 1)
+        k = np.arange(n)
+        conn = np.stack([np.zeros(n, dtype=np.int64), 1 + k, 1 + n + k, 1 + (k + 1) % n], 1).astype(np.int32)
+        return X, conn
+
+    Xs, cs = fan(n_slave, 0.0, (0.0, 0.0), 1.0)
+    Xm, cm = fan(n_master, 0.2 * math.pi / n_master, (0.03, -0.02), 1.05)
+    Xm[:, 2] += rng.uniform(0.0, normal_offset, size=Xm.shape[0])
+    return Interface(Mesh(Xs, cs), Mesh(Xm, cm), delta, name=f"kite fans {n_slave}/{n_master}",
+                     meta={"geometry": "kite fan", "ns": n_slave, "nm": n_master, "seed": seed})
+
+
 def interface_config(k, scale=None):
     """The workload of configuration k (0 flat, 1 cylinder, 2 wavy).
 

@@ -93,3 +93,25 @@ def test_bitwise_deterministic():
     assert np.array_equal(a["D"].data, b["D"].data)
     assert np.array_equal(a["M"].data, b["M"].data)
     assert np.array_equal(a["g"], b["g"])
+
+
+@pytest.mark.parametrize("ns,nm", [(4, 20), (3, 20)])
+def test_many_candidates_per_slave(ns, nm):
+    # coarse slave on a fine master: 33-42 (ns=4) and 49-64 (ns=3)
+    # candidates per slave element, beyond what the count pass keeps
+    itf = synth.flat_tied(ns, nm, seed=5)
+    g = gpu_run(itf)
+    o = oracle.evaluate(itf, oracle_params(itf))
+    assert_forward_parity(g, o)
+    assert np.bincount(o["cand_s"]).min() > 32
+
+
+def test_mixed_candidate_counts():
+    # one interface whose slave elements have from a few to several dozen
+    # candidates, so every fill path runs in the same launch
+    itf = synth.graded_flat(6, 40, 3.0)
+    g = gpu_run(itf)
+    o = oracle.evaluate(itf, oracle_params(itf))
+    assert_forward_parity(g, o)
+    c = np.bincount(o["cand_s"], minlength=itf.slave.n_el)
+    assert (c <= 32).any() and ((c > 32) & (c <= 48)).any() and (c > 48).any()

@@ -65,3 +65,29 @@ def test_ragged_gradients(mode):
         np.add.at(ge, ps, gn0)
         gs = gs + oracle.normal_chain(itf.slave, ge)
     assert rel_err(g["gXs"], gs) <= TOL and rel_err(g["gXm"], gm) <= TOL
+
+
+@pytest.mark.parametrize("mode", MODES, ids=lambda m: "-".join(f"{k}{v}" for k, v in m.items()))
+def test_nodes_with_more_than_four_elements(mode):
+    # fans of kites: the slave centre has 6 incident elements, the master
+    # centre 7, so the row gathers take their general loops
+    itf = synth.kite_fan()
+    seed = None if mode.get("element_rule") else 79
+    g = gpu_run(itf, backward_seed=seed, **mode)
+    o, prm = oracle_for(itf, mode)
+    assert np.array_equal(g["pair_s"], o["pair_s"]) and np.array_equal(g["pair_m"], o["pair_m"])
+    for key in ("D", "M"):
+        assert rel_err(g[key].data, o[key].data) <= TOL
+    assert rel_err(g["g"], o["g"]) <= TOL
+    if seed is None:
+        return
+    ps, pm = o["pair_s"], o["pair_m"]
+    w = oracle.pair_weights(itf.slave, itf.master, ps, pm, *weight_fns(seed))
+    g24, gn0, st = oracle.pair_grads(itf.slave, itf.master, prm, ps, pm, w, with_n0=True)
+    gs, gm = oracle.scatter_grads(itf.slave, itf.master, ps, pm, g24)
+    if mode.get("nodal"):
+        ge = np.zeros((itf.slave.n_el, 3))
+        np.add.at(ge, ps, gn0)
+        gs = gs + oracle.normal_chain(itf.slave, ge)
+    assert abs(gs[0]).max() > 0 and abs(gm[0]).max() > 0
+    assert rel_err(g["gXs"], gs) <= TOL and rel_err(g["gXm"], gm) <= TOL
