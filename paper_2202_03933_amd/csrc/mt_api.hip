@@ -163,7 +163,7 @@ int mt_destroy(mt_ctx* c) {
   (void)hipDeviceSynchronize();
   Buf* bufs[] = {&c->box_s, &c->box_m, &c->sdata, &c->mdata, &c->reduce, &c->counters, &c->keys, &c->vals,
                  &c->keys_tmp, &c->vals_tmp, &c->cell_range, &c->sbox, &c->cand_cnt, &c->cand_tmp, &c->cand_off,
-                 &c->cand_s, &c->cand_m, &c->cand_nv, &c->cand_flag, &c->cand_scan, &c->pair_s, &c->pair_m,
+                 &c->cand_s, &c->cand_m, &c->cand_nv, &c->cand_flag, &c->scr_cnt, &c->scr_off, &c->pair_s, &c->pair_m,
                  &c->pair_nv, &c->pair_off, &c->inc_cnt, &c->inc_off, &c->inc_cur, &c->inc_list, &c->minc_cnt,
                  &c->minc_off, &c->minc_cur, &c->minc_list, &c->rawD_cnt, &c->rawD_off, &c->rawD, &c->rawM_cnt,
                  &c->rawM_off, &c->rawM, &c->pat_keep, &c->D_cnt, &c->D_rowptr, &c->D_col, &c->M_cnt, &c->M_rowptr,
@@ -324,8 +324,9 @@ int mt_build_pairs(mt_ctx* c, int64_t* n_cand_out, int64_t* n_pairs_out, void* s
   MT_HIP(ensure(c->cand_s, sizeof(int32_t) * (size_t)n_cand));
   MT_HIP(ensure(c->cand_m, sizeof(int32_t) * (size_t)n_cand));
   MT_HIP(ensure(c->cand_nv, (size_t)n_cand));
-  MT_HIP(ensure(c->cand_flag, sizeof(int32_t) * ((size_t)n_cand + 1)));
-  MT_HIP(ensure(c->cand_scan, sizeof(int32_t) * ((size_t)n_cand + 1)));
+  MT_HIP(ensure(c->cand_flag, sizeof(int32_t) * (size_t)std::max<int64_t>(n_cand, 1)));
+  MT_HIP(ensure(c->scr_cnt, sizeof(int32_t) * ((size_t)ns + 1)));
+  MT_HIP(ensure(c->scr_off, sizeof(int32_t) * ((size_t)ns + 1)));
   // candidates, each screened as it is written (projection onto the slave
   // plane, degeneracy checks, separating-line test)
   const KParams kp = kparams(c->params);
@@ -335,16 +336,17 @@ int mt_build_pairs(mt_ctx* c, int64_t* n_cand_out, int64_t* n_pairs_out, void* s
     MT_HIP(launch_cand_fill(c->box_s.as<double>(), ns, c->sbox.as<double>(), c->vals.as<uint32_t>(),
                             c->cell_range.as<int2>(), g, c->params.delta, c->cand_tmp.as<int32_t>(), c->cand_off.as<int32_t>(), c->cand_s.as<int32_t>(),
                             c->cand_m.as<int32_t>(), c->sdata.as<double>(), c->mdata.as<double>(), kp.eps_a,
-                            c->cand_nv.as<uint8_t>(), c->cand_flag.as<int32_t>(), cnt, st));
+                            c->cand_nv.as<uint8_t>(), c->cand_flag.as<int32_t>(), c->scr_cnt.as<int32_t>(), cnt,
+                            st));
   }
 
   // clip the screened candidates, compact the pairs
   {
     PhaseTimer t(c, MT_T_COMPACT, st);
-    MT_HIP(scan_exclusive(c->cand_flag.as<int32_t>(), c->cand_scan.as<int32_t>(), n_cand, c->scan_tmp, st));
+    MT_HIP(scan_exclusive(c->scr_cnt.as<int32_t>(), c->scr_off.as<int32_t>(), ns, c->scan_tmp, st));
   }
   int32_t nmaybe32 = 0;
-  MT_HIP(hipMemcpyAsync(&nmaybe32, c->cand_scan.as<int32_t>() + n_cand, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  MT_HIP(hipMemcpyAsync(&nmaybe32, c->scr_off.as<int32_t>() + ns, sizeof(int32_t), hipMemcpyDeviceToHost, st));
   MT_HIP(hipStreamSynchronize(st));
   const int64_t n_maybe = nmaybe32;
   const size_t nmb = (size_t)std::max<int64_t>(n_maybe, 1);
@@ -359,7 +361,7 @@ int mt_build_pairs(mt_ctx* c, int64_t* n_cand_out, int64_t* n_pairs_out, void* s
                       c->mpoly_nf.as<uint8_t>(), (int64_t)nmb};
   {
     PhaseTimer t(c, MT_T_COMPACT, st);
-    MT_HIP(launch_maybe_list(c->cand_flag.as<int32_t>(), c->cand_scan.as<int32_t>(), n_cand,
+    MT_HIP(launch_maybe_list(c->cand_flag.as<int32_t>(), c->cand_off.as<int32_t>(), c->scr_off.as<int32_t>(), ns,
                              c->maybe_list.as<int32_t>(), st));
   }
   {
@@ -395,8 +397,7 @@ int mt_build_pairs(mt_ctx* c, int64_t* n_cand_out, int64_t* n_pairs_out, void* s
                                 c->maybe_flag.as<int32_t>(), c->maybe_scan.as<int32_t>(), n_maybe, mpoly,
                                 c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), c->pair_nv.as<uint8_t>(),
                                 poly_buf(c), st));
-    MT_HIP(launch_pair_off(c->cand_off.as<int32_t>(), c->cand_scan.as<int32_t>(), c->maybe_scan.as<int32_t>(), ns,
-                           c->pair_off.as<int32_t>(), st));
+    MT_HIP(launch_pair_off(c->scr_off.as<int32_t>(), c->maybe_scan.as<int32_t>(), ns, c->pair_off.as<int32_t>(), st));
   }
   c->poly_gen = c->coord_gen;
   c->have_pairs = true;

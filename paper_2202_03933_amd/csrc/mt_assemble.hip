@@ -59,7 +59,7 @@ __global__ __launch_bounds__(BS) void k_raw_count(const int32_t* __restrict__ in
                                                    const int32_t* __restrict__ inc_list, int32_t n,
                                                    const int32_t* __restrict__ pair_off, int32_t* rawD_big,
                                                    int32_t* rawM_big) {
-  const int a = blockIdx.x * BS + threadIdx.x;
+  const int a = xcd_tile(blockIdx.x, gridDim.x) * BS + threadIdx.x;
   if (a >= n) return;
   int d = 0, m = 0;
   for (int i = inc_off[a]; i < inc_off[a + 1]; ++i) {
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(PB) void k_pattern_rows(const int32_t* __restrict__
                                                       const int32_t* __restrict__ M_rowptr, int32_t* D_col,
                                                       int32_t* M_col, int32_t* keepD, int32_t* keepM) {
   __shared__ int32_t lds[PCAP * PB];
-  const int a = blockIdx.x * PB + threadIdx.x;
+  const int a = xcd_tile(blockIdx.x, gridDim.x) * PB + threadIdx.x;
   if (a >= n) return;
   // D row
   {
@@ -234,7 +234,7 @@ __device__ __forceinline__ void find_cols4(const int32_t* __restrict__ col, int 
 __global__ __launch_bounds__(BS) void k_posD(const int32_t* __restrict__ conn_s, int32_t n_el,
                                               const int32_t* __restrict__ pair_off, const int32_t* __restrict__ rowptr,
                                               const int32_t* __restrict__ col, int32_t* __restrict__ posD) {
-  const int e = blockIdx.x * BS + threadIdx.x;
+  const int e = xcd_tile(blockIdx.x, gridDim.x) * BS + threadIdx.x;
   if (e >= n_el) return;
   const bool has = pair_off[e + 1] > pair_off[e];
   const int4 c = reinterpret_cast<const int4*>(conn_s)[e];
@@ -252,7 +252,7 @@ __global__ __launch_bounds__(BS) void k_posM(const int32_t* __restrict__ conn_s,
                                               const int32_t* __restrict__ pair_s, const int32_t* __restrict__ pair_m,
                                               int64_t np, const int32_t* __restrict__ rowptr,
                                               const int32_t* __restrict__ col, int32_t* __restrict__ posM) {
-  const int64_t p = (int64_t)blockIdx.x * BS + threadIdx.x;
+  const int64_t p = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * BS + threadIdx.x;
   if (p >= np) return;
   const int4 c = reinterpret_cast<const int4*>(conn_s)[pair_s[p]];
   const int4 q = reinterpret_cast<const int4*>(conn_m)[pair_m[p]];
@@ -293,7 +293,7 @@ __global__ __launch_bounds__(BS) void k_grad_slave(const int32_t* __restrict__ i
                                                     const int32_t* __restrict__ pair_off,
                                                     const double* __restrict__ gpair, int64_t stride,
                                                     double* __restrict__ gX) {
-  const int a = blockIdx.x * BS + threadIdx.x;
+  const int a = xcd_tile(blockIdx.x, gridDim.x) * BS + threadIdx.x;
   if (a >= n) return;
   grad_slave_row(a, n, inc_off, inc_list, pair_off, gpair, stride, gX);
 }
@@ -313,7 +313,7 @@ __global__ __launch_bounds__(BS) void k_grad_master(const int32_t* __restrict__ 
                                                      const int32_t* __restrict__ mend,
                                                      const double* __restrict__ gpair, int64_t stride,
                                                      double* __restrict__ gX) {
-  const int b = blockIdx.x * BS + threadIdx.x;
+  const int b = xcd_tile(blockIdx.x, gridDim.x) * BS + threadIdx.x;
   if (b >= n) return;
   grad_master_row(b, n, inc_off, inc_list, mstart, mend, gpair, stride, gX);
 }
@@ -351,7 +351,7 @@ hipError_t launch_inc_sort(const int32_t* off, int32_t n_nodes, int32_t* list, h
 hipError_t launch_raw_count(const int32_t* inc_off, const int32_t* inc_list, int32_t n_nodes,
                             const int32_t* pair_off, int32_t* rawD_big, int32_t* rawM_big, hipStream_t s) {
   if (n_nodes == 0) return hipSuccess;
-  k_raw_count<<<grid_of(n_nodes), BS, 0, s>>>(inc_off, inc_list, n_nodes, pair_off, rawD_big, rawM_big);
+  k_raw_count<<<xcd_grid(grid_of(n_nodes)), BS, 0, s>>>(inc_off, inc_list, n_nodes, pair_off, rawD_big, rawM_big);
   return hipGetLastError();
 }
 
@@ -362,7 +362,7 @@ hipError_t launch_pattern_rows(bool fill, const int32_t* inc_off, const int32_t*
                                const int32_t* M_rowptr, int32_t* D_col, int32_t* M_col, int32_t* keep,
                                hipStream_t s) {
   if (n_nodes == 0) return hipSuccess;
-  const unsigned g = (unsigned)((n_nodes + PB - 1) / PB);
+  const unsigned g = xcd_grid((unsigned)((n_nodes + PB - 1) / PB));
   int32_t* keepD = keep;
   int32_t* keepM = keep + (int64_t)KD * n_nodes;
   if (fill)
@@ -381,14 +381,14 @@ int pattern_keep_per_row() { return KD + KM; }
 hipError_t launch_posD(const int32_t* conn_s, int32_t n_s_el, const int32_t* pair_off, const int32_t* rowptr,
                        const int32_t* col, int32_t* posD, hipStream_t s) {
   if (n_s_el == 0) return hipSuccess;
-  k_posD<<<grid_of(n_s_el), BS, 0, s>>>(conn_s, n_s_el, pair_off, rowptr, col, posD);
+  k_posD<<<xcd_grid(grid_of(n_s_el)), BS, 0, s>>>(conn_s, n_s_el, pair_off, rowptr, col, posD);
   return hipGetLastError();
 }
 
 hipError_t launch_posM(const int32_t* conn_s, const int32_t* conn_m, const int32_t* pair_s, const int32_t* pair_m,
                        int64_t n_pairs, const int32_t* rowptr, const int32_t* col, int32_t* posM, hipStream_t s) {
   if (n_pairs == 0) return hipSuccess;
-  k_posM<<<grid_of(n_pairs), BS, 0, s>>>(conn_s, conn_m, pair_s, pair_m, n_pairs, rowptr, col, posM);
+  k_posM<<<xcd_grid(grid_of(n_pairs)), BS, 0, s>>>(conn_s, conn_m, pair_s, pair_m, n_pairs, rowptr, col, posM);
   return hipGetLastError();
 }
 
@@ -406,7 +406,7 @@ hipError_t launch_grad_slave(const int32_t* inc_off, const int32_t* inc_list, in
                              const int32_t* pair_off, const double* gpair, int64_t stride, double* gX,
                              hipStream_t s) {
   if (n_nodes == 0) return hipSuccess;
-  k_grad_slave<<<grid_of(n_nodes), BS, 0, s>>>(inc_off, inc_list, n_nodes, pair_off, gpair, stride, gX);
+  k_grad_slave<<<xcd_grid(grid_of(n_nodes)), BS, 0, s>>>(inc_off, inc_list, n_nodes, pair_off, gpair, stride, gX);
   return hipGetLastError();
 }
 
@@ -423,7 +423,7 @@ hipError_t launch_grad_master(const int32_t* inc_off, const int32_t* inc_list, i
                               const int32_t* mstart, const int32_t* mend, const double* gpair, int64_t stride,
                               double* gX, hipStream_t s) {
   if (n_nodes == 0) return hipSuccess;
-  k_grad_master<<<grid_of(n_nodes), BS, 0, s>>>(inc_off, inc_list, n_nodes, mstart, mend, gpair, stride, gX);
+  k_grad_master<<<xcd_grid(grid_of(n_nodes)), BS, 0, s>>>(inc_off, inc_list, n_nodes, mstart, mend, gpair, stride, gX);
   return hipGetLastError();
 }
 

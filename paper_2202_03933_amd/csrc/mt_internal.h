@@ -132,8 +132,9 @@ struct mt_ctx {
   mt::Buf cand_off;        // [n_s_el + 1]
   mt::Buf cand_s, cand_m;  // [n_cand]
   mt::Buf cand_nv;         // uint8 [n_cand]
-  mt::Buf cand_flag;       // int32 [n_cand + 1] 1 = screened in (to be clipped)
-  mt::Buf cand_scan;       // int32 [n_cand + 1] exclusive scan of cand_flag
+  mt::Buf cand_flag;       // int32 [n_cand] 1 = screened in (to be clipped)
+  mt::Buf scr_cnt;         // int32 [n_s + 1] screened-in candidates per slave element
+  mt::Buf scr_off;         // int32 [n_s + 1] exclusive scan of scr_cnt
   // screened candidates (index i < n_maybe)
   int64_t n_maybe = 0;
   mt::Buf maybe_list;      // int32 [n_maybe] candidate index
@@ -211,14 +212,14 @@ hipError_t launch_cand_count(const double* box_s, int32_t n_s, const double* sbo
 hipError_t launch_cand_fill(const double* box_s, int32_t n_s, const double* sbox, const uint32_t* mvals,
                             const int2* range, Grid g, double delta, const int32_t* tmp, const int32_t* off,
                             int32_t* cand_s, int32_t* cand_m, const double* sd, const double* md, double eps_a,
-                            uint8_t* nv, int32_t* flag, Counters* cnt, hipStream_t s);
+                            uint8_t* nv, int32_t* flag, int32_t* scr_cnt, Counters* cnt, hipStream_t s);
 int cand_tmp_per_slave();
 
 // ---- pairs (mt_pairs.hip) ----------------------------------------------------
 // Histogram of clip vertex counts nv[0..n) added to hist[17].
 hipError_t launch_nv_hist(const uint8_t* nv, int64_t n, unsigned long long* hist, hipStream_t s);
-hipError_t launch_maybe_list(const int32_t* flag, const int32_t* mscan, int64_t n_cand, int32_t* mlist,
-                             hipStream_t s);
+hipError_t launch_maybe_list(const int32_t* flag, const int32_t* cand_off, const int32_t* scr_off, int32_t n_s,
+                             int32_t* mlist, hipStream_t s);
 hipError_t launch_clip_screened(const double* mdata, const double* sdata, int32_t n_s, const KParams& kp,
                                 const int32_t* cand_s, const int32_t* cand_m, const int32_t* mlist, int64_t n_maybe,
                                 uint8_t* nv, int32_t* flag2, const PolyBuf& out, Counters* cnt, hipStream_t s);
@@ -226,8 +227,8 @@ hipError_t launch_compact_pairs(const int32_t* cand_s, const int32_t* cand_m, co
                                 const int32_t* flag2, const int32_t* scan2, int64_t n_maybe, const PolyBuf& src,
                                 int32_t* pair_s, int32_t* pair_m, uint8_t* pair_nv, const PolyBuf& dst,
                                 hipStream_t s);
-hipError_t launch_pair_off(const int32_t* cand_off, const int32_t* mscan, const int32_t* scan2, int32_t n_s,
-                           int32_t* pair_off, hipStream_t s);
+hipError_t launch_pair_off(const int32_t* scr_off, const int32_t* scan2, int32_t n_s, int32_t* pair_off,
+                           hipStream_t s);
 hipError_t launch_pair_poly(const DeviceMesh& S, const DeviceMesh& M, const KParams& kp, const int32_t* pair_s,
                             const int32_t* pair_m, int64_t n_pairs, const PolyBuf& poly, hipStream_t s);
 hipError_t launch_pair_fwd(const DeviceMesh& S, const DeviceMesh& M, const KParams& kp, const int32_t* pair_s,

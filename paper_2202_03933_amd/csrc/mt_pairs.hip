@@ -38,11 +38,16 @@ __device__ __forceinline__ void load_slave_data(const double* __restrict__ sd, i
   hmax = sd[(int64_t)21 * n_s + s];
 }
 
-// Screened candidates in candidate order: mlist[mscan[c]] = c.
-__global__ __launch_bounds__(BS) void k_maybe_list(const int32_t* __restrict__ flag, const int32_t* __restrict__ mscan,
-                                                    int64_t n_cand, int32_t* __restrict__ mlist) {
-  const int64_t c = (int64_t)blockIdx.x * BS + threadIdx.x;
-  if (c < n_cand && flag[c]) mlist[mscan[c]] = (int32_t)c;
+// Screened candidates in candidate order: slave s writes its screened
+// candidates from mlist[scr_off[s]] on, in order.
+__global__ __launch_bounds__(BS) void k_maybe_list(const int32_t* __restrict__ flag, const int32_t* __restrict__ cand_off,
+                                                    const int32_t* __restrict__ scr_off, int32_t n_s,
+                                                    int32_t* __restrict__ mlist) {
+  const int s = blockIdx.x * BS + threadIdx.x;
+  if (s >= n_s) return;
+  int o = scr_off[s];
+  for (int c = cand_off[s]; c < cand_off[s + 1]; ++c)
+    if (flag[c]) mlist[o++] = c;
 }
 
 // Clip and cleanup of every screened candidate (LDS clip buffers with
@@ -127,14 +132,14 @@ __global__ __launch_bounds__(BS) void k_compact_pairs(const int32_t* __restrict_
   }
 }
 
-// First pair of each slave element: pairs before its first candidate.
-__global__ __launch_bounds__(BS) void k_pair_off(const int32_t* __restrict__ cand_off,
-                                                  const int32_t* __restrict__ mscan,
+// First pair of each slave element: pairs among the screened candidates
+// before its first one.
+__global__ __launch_bounds__(BS) void k_pair_off(const int32_t* __restrict__ scr_off,
                                                   const int32_t* __restrict__ scan2, int32_t n_s,
                                                   int32_t* __restrict__ pair_off) {
   const int s = blockIdx.x * BS + threadIdx.x;
   if (s > n_s) return;
-  pair_off[s] = scan2[mscan[cand_off[s]]];
+  pair_off[s] = scan2[scr_off[s]];
 }
 
 // Clip polygon of every pair (projection, clip and cleanup in LDS), stored
@@ -193,10 +198,10 @@ hipError_t launch_nv_hist(const uint8_t* nv, int64_t n, unsigned long long* hist
   return hipGetLastError();
 }
 
-hipError_t launch_maybe_list(const int32_t* flag, const int32_t* mscan, int64_t n_cand, int32_t* mlist,
-                             hipStream_t s) {
-  if (n_cand == 0) return hipSuccess;
-  k_maybe_list<<<(unsigned)((n_cand + BS - 1) / BS), BS, 0, s>>>(flag, mscan, n_cand, mlist);
+hipError_t launch_maybe_list(const int32_t* flag, const int32_t* cand_off, const int32_t* scr_off, int32_t n_s,
+                             int32_t* mlist, hipStream_t s) {
+  if (n_s == 0) return hipSuccess;
+  k_maybe_list<<<(unsigned)((n_s + BS - 1) / BS), BS, 0, s>>>(flag, cand_off, scr_off, n_s, mlist);
   return hipGetLastError();
 }
 
@@ -219,9 +224,9 @@ hipError_t launch_compact_pairs(const int32_t* cand_s, const int32_t* cand_m, co
   return hipGetLastError();
 }
 
-hipError_t launch_pair_off(const int32_t* cand_off, const int32_t* mscan, const int32_t* scan2, int32_t n_s,
-                           int32_t* pair_off, hipStream_t s) {
-  k_pair_off<<<(n_s + 1 + BS - 1) / BS, BS, 0, s>>>(cand_off, mscan, scan2, n_s, pair_off);
+hipError_t launch_pair_off(const int32_t* scr_off, const int32_t* scan2, int32_t n_s, int32_t* pair_off,
+                           hipStream_t s) {
+  k_pair_off<<<(n_s + 1 + BS - 1) / BS, BS, 0, s>>>(scr_off, scan2, n_s, pair_off);
   return hipGetLastError();
 }
 

@@ -236,7 +236,7 @@ __device__ __forceinline__ bool touch(const SlaveBox& s, const double* __restric
 
 constexpr int CCAP = 48;  // per-thread LDS segment of the long-list fill (masters)
 constexpr int CTMP = 32;  // candidates per slave kept by the count pass
-constexpr int G = 4;      // lanes per slave element in the count and fill passes
+constexpr int G = 2;      // lanes per slave element in the count and fill passes
 static_assert(64 % G == 0 && BS % G == 0, "groups must not straddle a wave");
 constexpr int OWN = CTMP / G;  // candidates per lane in the grouped fill
 
@@ -329,7 +329,7 @@ __global__ __launch_bounds__(BS) void k_cand_count(const double* __restrict__ bo
                                                     const uint32_t* __restrict__ mvals,
                                                     const int2* __restrict__ range, Grid g, double delta,
                                                     int32_t* __restrict__ count, int32_t* __restrict__ tmp) {
-  const int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x;
+  const int64_t t = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * BS + threadIdx.x;
   const int s = (int)(t / G), r = (int)(t % G);
   if (s >= n_s) return;  // whole groups leave together
   const SlaveBox b = load_box(box_s, n_s, s);
@@ -371,7 +371,7 @@ struct ScreenOut {
   unsigned degen_s, degen_m;
 };
 
-__device__ __forceinline__ void screen_one(const SlavePlane& P, int s, int m, int64_t ci,
+__device__ __forceinline__ bool screen_one(const SlavePlane& P, int s, int m, int64_t ci,
                                            const double* __restrict__ md, double eps_a, int32_t* __restrict__ cand_s,
                                            int32_t* __restrict__ cand_m, uint8_t* __restrict__ nv_out,
                                            int32_t* __restrict__ flag, ScreenOut& so) {
@@ -388,6 +388,7 @@ __device__ __forceinline__ void screen_one(const SlavePlane& P, int s, int m, in
   so.degen_m += (st & PS_DEGEN_MASTER) ? 1u : 0u;
   cand_m[ci] = m;
   cand_s[ci] = s;
+  return clip;
 }
 
 __device__ __forceinline__ void count_degenerate(const ScreenOut& so, Counters* cnt) {
@@ -400,37 +401,45 @@ __device__ __forceinline__ void count_degenerate(const ScreenOut& so, Counters* 
 // r takes the candidates r, r + G, ... of the count pass's list, finds the
 // place of each in the master-sorted order by counting the smaller masters
 // of the list (the masters of one slave are distinct), screens it and writes
-// it there.  No lane reads what another lane wrote.
+// it there.  No lane reads what another lane wrote; the group's number of
+// screened-in candidates (to scr_cnt[s]) is summed by lane shuffles.
 __global__ __launch_bounds__(BS) void k_cand_fill(int32_t n_s, const int32_t* __restrict__ tmp,
                                                    const int32_t* __restrict__ off, int32_t* __restrict__ cand_s,
                                                    int32_t* __restrict__ cand_m, const double* __restrict__ sd,
                                                    const double* __restrict__ md, double eps_a,
                                                    uint8_t* __restrict__ nv_out, int32_t* __restrict__ flag,
-                                                   Counters* cnt) {
-  const int64_t t = (int64_t)blockIdx.x * BS + threadIdx.x;
+                                                   int32_t* __restrict__ scr_cnt, Counters* cnt) {
+  const int64_t t = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * BS + threadIdx.x;
   const int s = (int)(t / G), r = (int)(t % G);
-  if (s >= n_s) return;
+  if (s >= n_s) return;  // whole groups leave together
   const int base = off[s];
   const int c = off[s + 1] - base;
-  if (c > CTMP || r >= c) return;
-  int own[OWN], rank[OWN];
+  if (c > CTMP) return;  // k_cand_fill_long
+  int nscr = 0;
+  if (r < c) {
+    int own[OWN], rank[OWN];
 #pragma unroll
-  for (int q = 0; q < OWN; ++q) {
-    const int k = r + q * G;
-    own[q] = k < c ? tmp[(int64_t)k * n_s + s] : 0x7fffffff;
-    rank[q] = 0;
-  }
-  for (int k = 0; k < c; ++k) {
-    const int x = tmp[(int64_t)k * n_s + s];
+    for (int q = 0; q < OWN; ++q) {
+      const int k = r + q * G;
+      own[q] = k < c ? tmp[(int64_t)k * n_s + s] : 0x7fffffff;
+      rank[q] = 0;
+    }
+    for (int k = 0; k < c; ++k) {
+      const int x = tmp[(int64_t)k * n_s + s];
 #pragma unroll
-    for (int q = 0; q < OWN; ++q) rank[q] += x < own[q] ? 1 : 0;
+      for (int q = 0; q < OWN; ++q) rank[q] += x < own[q] ? 1 : 0;
+    }
+    SlavePlane P;
+    load_plane(sd, n_s, s, P);
+    ScreenOut so{0u, 0u};
+    for (int q = 0; q < OWN && r + q * G < c; ++q)
+      nscr += screen_one(P, s, own[q], (int64_t)base + rank[q], md, eps_a, cand_s, cand_m, nv_out, flag, so) ? 1 : 0;
+    count_degenerate(so, cnt);
   }
-  SlavePlane P;
-  load_plane(sd, n_s, s, P);
-  ScreenOut so{0u, 0u};
-  for (int q = 0; q < OWN && r + q * G < c; ++q)
-    screen_one(P, s, own[q], (int64_t)base + rank[q], md, eps_a, cand_s, cand_m, nv_out, flag, so);
-  count_degenerate(so, cnt);
+  // all G lanes of the group are active here
+#pragma unroll
+  for (int d = 1; d < G; d <<= 1) nscr += __shfl_xor(nscr, d, 64);
+  if (r == 0) scr_cnt[s] = nscr;
 }
 
 // Fill pass for slaves with more than CTMP candidates (rare), one lane per
@@ -444,7 +453,7 @@ __device__ __forceinline__ void fill_long(int s, int32_t n_s, int base, int c, i
                                           const Grid& g, double delta, int32_t* __restrict__ cand_s,
                                           int32_t* __restrict__ cand_m, const double* __restrict__ sd,
                                           const double* __restrict__ md, double eps_a, uint8_t* __restrict__ nv_out,
-                                          int32_t* __restrict__ flag, ScreenOut& so) {
+                                          int32_t* __restrict__ flag, ScreenOut& so, int& nscr) {
   walk_cells(load_box(box_s, n_s, s), sbox, mvals, range, g, delta, v, vs, c);
   for (int i = 1; i < c; ++i) {
     const int x = v[i * vs];
@@ -458,7 +467,7 @@ __device__ __forceinline__ void fill_long(int s, int32_t n_s, int base, int c, i
   SlavePlane P;
   load_plane(sd, n_s, s, P);
   for (int i = 0; i < c; ++i)
-    screen_one(P, s, v[i * vs], (int64_t)base + i, md, eps_a, cand_s, cand_m, nv_out, flag, so);
+    nscr += screen_one(P, s, v[i * vs], (int64_t)base + i, md, eps_a, cand_s, cand_m, nv_out, flag, so) ? 1 : 0;
 }
 
 __global__ __launch_bounds__(BS) void k_cand_fill_long(const double* __restrict__ box_s, int32_t n_s,
@@ -469,21 +478,23 @@ __global__ __launch_bounds__(BS) void k_cand_fill_long(const double* __restrict_
                                                         int32_t* __restrict__ cand_m, const double* __restrict__ sd,
                                                         const double* __restrict__ md, double eps_a,
                                                         uint8_t* __restrict__ nv_out, int32_t* __restrict__ flag,
-                                                        Counters* cnt) {
+                                                        int32_t* __restrict__ scr_cnt, Counters* cnt) {
   __shared__ int32_t lds[CCAP * BS];
-  const int s = blockIdx.x * BS + threadIdx.x;
+  const int s = xcd_tile(blockIdx.x, gridDim.x) * BS + threadIdx.x;
   if (s >= n_s) return;
   const int base = off[s];
   const int c = off[s + 1] - base;
   if (c <= CTMP) return;
   ScreenOut so{0u, 0u};
+  int nscr = 0;
   if (c <= CCAP)
     fill_long(s, n_s, base, c, lds + threadIdx.x, BS, box_s, sbox, mvals, range, g, delta, cand_s, cand_m, sd,
-              md, eps_a, nv_out, flag, so);
+              md, eps_a, nv_out, flag, so, nscr);
   else
     fill_long(s, n_s, base, c, cand_m + base, 1, box_s, sbox, mvals, range, g, delta, cand_s, cand_m, sd, md,
-              eps_a, nv_out, flag, so);
+              eps_a, nv_out, flag, so, nscr);
   count_degenerate(so, cnt);
+  scr_cnt[s] = nscr;
 }
 
 }  // namespace
@@ -549,7 +560,9 @@ hipError_t launch_cell_ranges(const uint32_t* keys, const uint32_t* vals, int32_
   return hipGetLastError();
 }
 
-unsigned group_blocks(int32_t n_s) { return (unsigned)(((int64_t)n_s * G + BS - 1) / BS); }
+// Grids of the candidate passes: XCD-aware (each XCD's L2 serves a
+// contiguous eighth of the slave elements, whose masters are neighbours).
+unsigned group_blocks(int32_t n_s) { return xcd_grid((unsigned)(((int64_t)n_s * G + BS - 1) / BS)); }
 
 hipError_t launch_cand_count(const double* box_s, int32_t n_s, const double* sbox, const uint32_t* mvals,
                              const int2* range, Grid g, double delta, int32_t* count, int32_t* tmp, hipStream_t s) {
@@ -561,11 +574,12 @@ hipError_t launch_cand_count(const double* box_s, int32_t n_s, const double* sbo
 hipError_t launch_cand_fill(const double* box_s, int32_t n_s, const double* sbox, const uint32_t* mvals,
                             const int2* range, Grid g, double delta, const int32_t* tmp, const int32_t* off,
                             int32_t* cand_s, int32_t* cand_m, const double* sd, const double* md, double eps_a,
-                            uint8_t* nv, int32_t* flag, Counters* cnt, hipStream_t s) {
+                            uint8_t* nv, int32_t* flag, int32_t* scr_cnt, Counters* cnt, hipStream_t s) {
   if (n_s == 0) return hipSuccess;
-  k_cand_fill<<<group_blocks(n_s), BS, 0, s>>>(n_s, tmp, off, cand_s, cand_m, sd, md, eps_a, nv, flag, cnt);
-  k_cand_fill_long<<<(n_s + BS - 1) / BS, BS, 0, s>>>(box_s, n_s, sbox, mvals, range, g, delta, off, cand_s, cand_m,
-                                                      sd, md, eps_a, nv, flag, cnt);
+  k_cand_fill<<<group_blocks(n_s), BS, 0, s>>>(n_s, tmp, off, cand_s, cand_m, sd, md, eps_a, nv, flag, scr_cnt, cnt);
+  k_cand_fill_long<<<xcd_grid((unsigned)((n_s + BS - 1) / BS)), BS, 0, s>>>(box_s, n_s, sbox, mvals, range, g, delta,
+                                                                            off, cand_s, cand_m, sd, md, eps_a, nv,
+                                                                            flag, scr_cnt, cnt);
   return hipGetLastError();
 }
 
