@@ -14,7 +14,7 @@ namespace {
 
 constexpr int BS = 256;
 constexpr int PB = 128;   // block of the pattern kernels
-constexpr int PCAP = 64;  // per-thread LDS segment of the pattern kernels (ints)
+constexpr int PCAP = 32;  // per-thread LDS segment of the pattern kernels (ints)
 
 __global__ __launch_bounds__(BS) void k_inc_count(const int32_t* __restrict__ conn, int32_t n_el, int32_t* cnt) {
   const int e = blockIdx.x * BS + threadIdx.x;
@@ -70,17 +70,20 @@ __global__ __launch_bounds__(BS) void k_raw_count(const int32_t* __restrict__ in
       m += 4 * np;
     }
   }
-  // candidate lists longer than the per-thread LDS segment go to global scratch
+  // rows whose raw candidates exceed the per-thread LDS segment get global
+  // scratch in case their column list does not fit there
   rawD_big[a] = d > PCAP ? d : 0;
   rawM_big[a] = m > PCAP ? m : 0;
 }
 
 // Inserts x into the ascending, duplicate-free strided list v[0..u) unless
-// it is already there; returns the new length.
-__device__ __forceinline__ int insert_unique(int32_t* v, int u, int x, int stride) {
+// it is already there; returns the new length, or -1 when the list holds cap
+// entries and x is new.
+__device__ __forceinline__ int insert_unique(int32_t* v, int u, int x, int stride, int cap) {
   int j = u - 1;
   while (j >= 0 && v[j * stride] > x) --j;
   if (j >= 0 && v[j * stride] == x) return u;
+  if (u == cap) return -1;
   for (int k = u - 1; k > j; --k) v[(k + 1) * stride] = v[k * stride];
   v[(j + 1) * stride] = x;
   return u + 1;
@@ -94,50 +97,38 @@ __device__ __forceinline__ int row_columns(int a, const int32_t* __restrict__ in
                                            const int32_t* __restrict__ inc_list,
                                            const int32_t* __restrict__ pair_off,
                                            const int32_t* __restrict__ pair_m, const int32_t* __restrict__ conn_s,
-                                           const int32_t* __restrict__ conn_m, int32_t* v, int stride) {
+                                           const int32_t* __restrict__ conn_m, int32_t* v, int stride, int cap) {
   int u = 0;
   for (int i = inc_off[a]; i < inc_off[a + 1]; ++i) {
     const int e = inc_list[i] >> 2;
     const int p0 = pair_off[e], p1 = pair_off[e + 1];
     if (p1 == p0) continue;
-    if (!MCOLS) {
-      const int4 q = reinterpret_cast<const int4*>(conn_s)[e];
-      u = insert_unique(v, u, q.x, stride);
-      u = insert_unique(v, u, q.y, stride);
-      u = insert_unique(v, u, q.z, stride);
-      u = insert_unique(v, u, q.w, stride);
-    } else {
-      for (int p = p0; p < p1; ++p) {
-        const int4 q = reinterpret_cast<const int4*>(conn_m)[pair_m[p]];
-        u = insert_unique(v, u, q.x, stride);
-        u = insert_unique(v, u, q.y, stride);
-        u = insert_unique(v, u, q.z, stride);
-        u = insert_unique(v, u, q.w, stride);
-      }
+    for (int p = MCOLS ? p0 : 0; p < (MCOLS ? p1 : 1); ++p) {
+      const int4 q = reinterpret_cast<const int4*>(MCOLS ? conn_m : conn_s)[MCOLS ? pair_m[p] : e];
+      u = insert_unique(v, u, q.x, stride, cap);
+      if (u >= 0) u = insert_unique(v, u, q.y, stride, cap);
+      if (u >= 0) u = insert_unique(v, u, q.z, stride, cap);
+      if (u >= 0) u = insert_unique(v, u, q.w, stride, cap);
+      if (u < 0) return -1;
     }
   }
   return u;
 }
 
 // Row patterns of D and M.  Each thread builds its row's sorted column list
-// in a lane-interleaved LDS segment (or a global scratch segment when the
-// raw candidate count exceeds PCAP).  The count pass writes the row lengths
-// and keeps rows of at most KD (D) / KM (M) columns in lane-interleaved
-// scratch keep[i * n + a]; the fill pass copies those and recomputes the rest.
+// in a lane-interleaved LDS segment of PCAP entries, or, when that fills up
+// (possible only for rows with more than PCAP raw candidates), again in a
+// global scratch segment sized by the raw count.  The count pass writes the
+// row lengths and keeps rows of at most KD (D) / KM (M) columns in
+// lane-interleaved scratch keep[i * n + a]; the fill pass copies those and
+// recomputes the rest.
 constexpr int KD = 16;
 constexpr int KM = 32;
 
-template <bool FILL, bool MCOLS>
-__device__ __forceinline__ void pattern_row(int a, int32_t n, int32_t* v, int stride,
-                                            const int32_t* __restrict__ inc_off,
-                                            const int32_t* __restrict__ inc_list,
-                                            const int32_t* __restrict__ pair_off,
-                                            const int32_t* __restrict__ pair_m,
-                                            const int32_t* __restrict__ conn_s,
-                                            const int32_t* __restrict__ conn_m, int32_t* cnt,
-                                            const int32_t* __restrict__ rowptr, int32_t* colv, int32_t* keep,
-                                            int kcap) {
-  const int u = row_columns<MCOLS>(a, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m, v, stride);
+template <bool FILL>
+__device__ __forceinline__ void finish_row(int a, int32_t n, int u, const int32_t* v, int stride, int32_t* cnt,
+                                           const int32_t* __restrict__ rowptr, int32_t* colv, int32_t* keep,
+                                           int kcap) {
   if (!FILL) {
     cnt[a] = u;
     if (u <= kcap)
@@ -145,6 +136,26 @@ __device__ __forceinline__ void pattern_row(int a, int32_t n, int32_t* v, int st
   } else {
     int32_t* col = colv + rowptr[a];
     for (int i = 0; i < u; ++i) col[i] = v[i * stride];
+  }
+}
+
+template <bool FILL, bool MCOLS>
+__device__ __forceinline__ void pattern_row(int a, int32_t n, int32_t* lds, const int32_t* __restrict__ big_off,
+                                            int32_t* big, const int32_t* __restrict__ inc_off,
+                                            const int32_t* __restrict__ inc_list,
+                                            const int32_t* __restrict__ pair_off,
+                                            const int32_t* __restrict__ pair_m,
+                                            const int32_t* __restrict__ conn_s,
+                                            const int32_t* __restrict__ conn_m, int32_t* cnt,
+                                            const int32_t* __restrict__ rowptr, int32_t* colv, int32_t* keep,
+                                            int kcap) {
+  int u = row_columns<MCOLS>(a, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m, lds, PB, PCAP);
+  if (u >= 0) {
+    finish_row<FILL>(a, n, u, lds, PB, cnt, rowptr, colv, keep, kcap);
+  } else {
+    int32_t* v = big + big_off[a];
+    u = row_columns<MCOLS>(a, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m, v, 1, big_off[a + 1] - big_off[a]);
+    finish_row<FILL>(a, n, u, v, 1, cnt, rowptr, colv, keep, kcap);
   }
 }
 
@@ -165,42 +176,20 @@ __global__ __launch_bounds__(PB) void k_pattern_rows(const int32_t* __restrict__
   const int a = xcd_tile(blockIdx.x, gridDim.x) * PB + threadIdx.x;
   if (a >= n) return;
   // D row
-  {
-    bool done = false;
-    if (FILL) {
-      const int u = D_rowptr[a + 1] - D_rowptr[a];
-      if (u <= KD) {
-        for (int i = 0; i < u; ++i) D_col[D_rowptr[a] + i] = keepD[(int64_t)i * n + a];
-        done = true;
-      }
-    }
-    if (!done) {
-      if (bigD_off[a + 1] == bigD_off[a])
-        pattern_row<FILL, false>(a, n, lds + threadIdx.x, PB, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m,
-                                 D_cnt, D_rowptr, D_col, keepD + a, KD);
-      else
-        pattern_row<FILL, false>(a, n, bigD + bigD_off[a], 1, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m,
-                                 D_cnt, D_rowptr, D_col, keepD + a, KD);
-    }
+  if (FILL && D_rowptr[a + 1] - D_rowptr[a] <= KD) {
+    const int u = D_rowptr[a + 1] - D_rowptr[a];
+    for (int i = 0; i < u; ++i) D_col[D_rowptr[a] + i] = keepD[(int64_t)i * n + a];
+  } else {
+    pattern_row<FILL, false>(a, n, lds + threadIdx.x, bigD_off, bigD, inc_off, inc_list, pair_off, pair_m, conn_s,
+                             conn_m, D_cnt, D_rowptr, D_col, keepD + a, KD);
   }
   // M row
-  {
-    bool done = false;
-    if (FILL) {
-      const int u = M_rowptr[a + 1] - M_rowptr[a];
-      if (u <= KM) {
-        for (int i = 0; i < u; ++i) M_col[M_rowptr[a] + i] = keepM[(int64_t)i * n + a];
-        done = true;
-      }
-    }
-    if (!done) {
-      if (bigM_off[a + 1] == bigM_off[a])
-        pattern_row<FILL, true>(a, n, lds + threadIdx.x, PB, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m,
-                                M_cnt, M_rowptr, M_col, keepM + a, KM);
-      else
-        pattern_row<FILL, true>(a, n, bigM + bigM_off[a], 1, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m,
-                                M_cnt, M_rowptr, M_col, keepM + a, KM);
-    }
+  if (FILL && M_rowptr[a + 1] - M_rowptr[a] <= KM) {
+    const int u = M_rowptr[a + 1] - M_rowptr[a];
+    for (int i = 0; i < u; ++i) M_col[M_rowptr[a] + i] = keepM[(int64_t)i * n + a];
+  } else {
+    pattern_row<FILL, true>(a, n, lds + threadIdx.x, bigM_off, bigM, inc_off, inc_list, pair_off, pair_m, conn_s,
+                            conn_m, M_cnt, M_rowptr, M_col, keepM + a, KM);
   }
 }
 
