@@ -551,7 +551,7 @@ int mt_csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, void* stream) {
                              c->pair_m.as<int32_t>(), S.conn, M.conn, c->rawD_off.as<int32_t>(), c->rawD.as<int32_t>(),
                              c->rawM_off.as<int32_t>(), c->rawM.as<int32_t>(), c->D_cnt.as<int32_t>(),
                              c->M_cnt.as<int32_t>(), nullptr, nullptr, nullptr, nullptr, c->pat_keep.as<int32_t>(),
-                             st));
+                             nullptr, S.n_el, nullptr, c->n_pairs, st));
   MT_HIP(scan_exclusive(c->D_cnt.as<int32_t>(), c->D_rowptr.as<int32_t>(), n, c->scan_tmp, st));
   MT_HIP(scan_exclusive(c->M_cnt.as<int32_t>(), c->M_rowptr.as<int32_t>(), n, c->scan_tmp, st));
   MT_HIP(hipMemcpyAsync(&tot[0], c->D_rowptr.as<int32_t>() + n, 4, hipMemcpyDeviceToHost, st));
@@ -561,17 +561,15 @@ int mt_csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, void* stream) {
   c->nnz_M = tot[1];
   MT_HIP(ensure(c->D_col, sizeof(int32_t) * (size_t)c->nnz_D));
   MT_HIP(ensure(c->M_col, sizeof(int32_t) * (size_t)c->nnz_M));
+  // the fill pass also writes the CSR positions of every local block entry
+  MT_HIP(ensure(c->posD, sizeof(int32_t) * 16 * (size_t)std::max(S.n_el, 1)));
+  MT_HIP(ensure(c->posM, sizeof(int32_t) * 16 * (size_t)std::max<int64_t>(c->n_pairs, 1)));
   MT_HIP(launch_pattern_rows(true, c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(), n, c->pair_off.as<int32_t>(),
                              c->pair_m.as<int32_t>(), S.conn, M.conn, c->rawD_off.as<int32_t>(), c->rawD.as<int32_t>(),
                              c->rawM_off.as<int32_t>(), c->rawM.as<int32_t>(), nullptr, nullptr,
                              c->D_rowptr.as<int32_t>(), c->M_rowptr.as<int32_t>(), c->D_col.as<int32_t>(),
-                             c->M_col.as<int32_t>(), c->pat_keep.as<int32_t>(), st));
-  MT_HIP(ensure(c->posD, sizeof(int32_t) * 16 * (size_t)S.n_el));
-  MT_HIP(ensure(c->posM, sizeof(int32_t) * 16 * (size_t)c->n_pairs));
-  MT_HIP(launch_posD(S.conn, S.n_el, c->pair_off.as<int32_t>(), c->D_rowptr.as<int32_t>(), c->D_col.as<int32_t>(),
-                     c->posD.as<int32_t>(), st));
-  MT_HIP(launch_posM(S.conn, M.conn, c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), c->n_pairs,
-                     c->M_rowptr.as<int32_t>(), c->M_col.as<int32_t>(), c->posM.as<int32_t>(), st));
+                             c->M_col.as<int32_t>(), c->pat_keep.as<int32_t>(), c->posD.as<int32_t>(), S.n_el,
+                             c->posM.as<int32_t>(), c->n_pairs, st));
   if (aux) MT_HIP(hipStreamWaitEvent(st, c->aux_join, 0));
   c->have_pattern = true;
   ++c->pattern_gen;

@@ -124,18 +124,81 @@ __device__ __forceinline__ int row_columns(int a, const int32_t* __restrict__ in
 // recomputes the rest.
 constexpr int KD = 16;
 constexpr int KM = 32;
+static_assert(KD <= PCAP && KM <= PCAP, "kept rows are looked up in the LDS segment");
 
-template <bool FILL>
+// Positions of four keys that all occur in the sorted row v[0..u) (stride
+// vs): one pass over short rows (no dependent chain of a binary search), a
+// binary search per key over long ones.
+__device__ __forceinline__ void find4(const int32_t* v, int vs, int u, const int key[4], int pos[4]) {
+  if (u <= PCAP) {
+    pos[0] = pos[1] = pos[2] = pos[3] = 0;
+    for (int i = 0; i < u; ++i) {
+      const int c = v[i * vs];
+#pragma unroll
+      for (int l = 0; l < 4; ++l) pos[l] = c == key[l] ? i : pos[l];
+    }
+  } else {
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      int lo = 0, hi = u;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (v[mid * vs] < key[l]) lo = mid + 1;
+        else hi = mid;
+      }
+      pos[l] = lo;
+    }
+  }
+}
+
+// CSR positions of the local blocks that row a receives: for D, of the four
+// nodes of each incident element with pairs (posD[(4 j + k) * n_el + e]);
+// for M, of the four master nodes of each pair of those elements
+// (posM[(4 j + l) * n_pairs + p]); j = local index of node a.  Entries of
+// elements without pairs are not written (nothing reads them).
+template <bool MCOLS>
+__device__ __forceinline__ void row_positions(int a, const int32_t* v, int vs, int u, int base,
+                                              const int32_t* __restrict__ inc_off,
+                                              const int32_t* __restrict__ inc_list,
+                                              const int32_t* __restrict__ pair_off,
+                                              const int32_t* __restrict__ pair_m,
+                                              const int32_t* __restrict__ conn_s,
+                                              const int32_t* __restrict__ conn_m, int32_t* __restrict__ pos,
+                                              int64_t pstride) {
+  for (int i = inc_off[a]; i < inc_off[a + 1]; ++i) {
+    const int e = inc_list[i] >> 2, j = inc_list[i] & 3;
+    const int p0 = pair_off[e], p1 = pair_off[e + 1];
+    if (p1 == p0) continue;
+    for (int p = MCOLS ? p0 : 0; p < (MCOLS ? p1 : 1); ++p) {
+      const int4 q = reinterpret_cast<const int4*>(MCOLS ? conn_m : conn_s)[MCOLS ? pair_m[p] : e];
+      const int key[4] = {q.x, q.y, q.z, q.w};
+      int ix[4];
+      find4(v, vs, u, key, ix);
+      const int64_t at = MCOLS ? p : e;
+#pragma unroll
+      for (int l = 0; l < 4; ++l) pos[(int64_t)(j * 4 + l) * pstride + at] = base + ix[l];
+    }
+  }
+}
+
+template <bool FILL, bool MCOLS>
 __device__ __forceinline__ void finish_row(int a, int32_t n, int u, const int32_t* v, int stride, int32_t* cnt,
                                            const int32_t* __restrict__ rowptr, int32_t* colv, int32_t* keep,
-                                           int kcap) {
+                                           int kcap, const int32_t* __restrict__ inc_off,
+                                           const int32_t* __restrict__ inc_list,
+                                           const int32_t* __restrict__ pair_off,
+                                           const int32_t* __restrict__ pair_m,
+                                           const int32_t* __restrict__ conn_s,
+                                           const int32_t* __restrict__ conn_m, int32_t* pos, int64_t pstride) {
   if (!FILL) {
     cnt[a] = u;
     if (u <= kcap)
       for (int i = 0; i < u; ++i) keep[(int64_t)i * n] = v[i * stride];
   } else {
-    int32_t* col = colv + rowptr[a];
+    const int base = rowptr[a];
+    int32_t* col = colv + base;
     for (int i = 0; i < u; ++i) col[i] = v[i * stride];
+    row_positions<MCOLS>(a, v, stride, u, base, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m, pos, pstride);
   }
 }
 
@@ -148,15 +211,36 @@ __device__ __forceinline__ void pattern_row(int a, int32_t n, int32_t* lds, cons
                                             const int32_t* __restrict__ conn_s,
                                             const int32_t* __restrict__ conn_m, int32_t* cnt,
                                             const int32_t* __restrict__ rowptr, int32_t* colv, int32_t* keep,
-                                            int kcap) {
+                                            int kcap, int32_t* pos, int64_t pstride) {
   int u = row_columns<MCOLS>(a, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m, lds, PB, PCAP);
   if (u >= 0) {
-    finish_row<FILL>(a, n, u, lds, PB, cnt, rowptr, colv, keep, kcap);
+    finish_row<FILL, MCOLS>(a, n, u, lds, PB, cnt, rowptr, colv, keep, kcap, inc_off, inc_list, pair_off, pair_m,
+                            conn_s, conn_m, pos, pstride);
   } else {
     int32_t* v = big + big_off[a];
     u = row_columns<MCOLS>(a, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m, v, 1, big_off[a + 1] - big_off[a]);
-    finish_row<FILL>(a, n, u, v, 1, cnt, rowptr, colv, keep, kcap);
+    finish_row<FILL, MCOLS>(a, n, u, v, 1, cnt, rowptr, colv, keep, kcap, inc_off, inc_list, pair_off, pair_m,
+                            conn_s, conn_m, pos, pstride);
   }
+}
+
+// Kept rows of the fill pass: copied from the lane-interleaved scratch to
+// the column array and to the thread's LDS segment, where the block
+// positions are looked up.
+template <bool MCOLS>
+__device__ __forceinline__ void kept_row(int a, int32_t n, int u, const int32_t* keep, int32_t* lds,
+                                         const int32_t* __restrict__ rowptr, int32_t* colv,
+                                         const int32_t* __restrict__ inc_off, const int32_t* __restrict__ inc_list,
+                                         const int32_t* __restrict__ pair_off, const int32_t* __restrict__ pair_m,
+                                         const int32_t* __restrict__ conn_s, const int32_t* __restrict__ conn_m,
+                                         int32_t* pos, int64_t pstride) {
+  const int base = rowptr[a];
+  for (int i = 0; i < u; ++i) {
+    const int c = keep[(int64_t)i * n + a];
+    colv[base + i] = c;
+    lds[i * PB] = c;
+  }
+  row_positions<MCOLS>(a, lds, PB, u, base, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m, pos, pstride);
 }
 
 template <bool FILL>
@@ -171,89 +255,26 @@ __global__ __launch_bounds__(PB) void k_pattern_rows(const int32_t* __restrict__
                                                       int32_t* D_cnt, int32_t* M_cnt,
                                                       const int32_t* __restrict__ D_rowptr,
                                                       const int32_t* __restrict__ M_rowptr, int32_t* D_col,
-                                                      int32_t* M_col, int32_t* keepD, int32_t* keepM) {
+                                                      int32_t* M_col, int32_t* keepD, int32_t* keepM,
+                                                      int32_t* posD, int32_t n_el, int32_t* posM, int64_t np) {
   __shared__ int32_t lds[PCAP * PB];
   const int a = xcd_tile(blockIdx.x, gridDim.x) * PB + threadIdx.x;
   if (a >= n) return;
+  int32_t* seg = lds + threadIdx.x;
   // D row
-  if (FILL && D_rowptr[a + 1] - D_rowptr[a] <= KD) {
-    const int u = D_rowptr[a + 1] - D_rowptr[a];
-    for (int i = 0; i < u; ++i) D_col[D_rowptr[a] + i] = keepD[(int64_t)i * n + a];
-  } else {
-    pattern_row<FILL, false>(a, n, lds + threadIdx.x, bigD_off, bigD, inc_off, inc_list, pair_off, pair_m, conn_s,
-                             conn_m, D_cnt, D_rowptr, D_col, keepD + a, KD);
-  }
+  if (FILL && D_rowptr[a + 1] - D_rowptr[a] <= KD)
+    kept_row<false>(a, n, D_rowptr[a + 1] - D_rowptr[a], keepD, seg, D_rowptr, D_col, inc_off, inc_list, pair_off,
+                    pair_m, conn_s, conn_m, posD, n_el);
+  else
+    pattern_row<FILL, false>(a, n, seg, bigD_off, bigD, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m, D_cnt,
+                             D_rowptr, D_col, keepD + a, KD, posD, n_el);
   // M row
-  if (FILL && M_rowptr[a + 1] - M_rowptr[a] <= KM) {
-    const int u = M_rowptr[a + 1] - M_rowptr[a];
-    for (int i = 0; i < u; ++i) M_col[M_rowptr[a] + i] = keepM[(int64_t)i * n + a];
-  } else {
-    pattern_row<FILL, true>(a, n, lds + threadIdx.x, bigM_off, bigM, inc_off, inc_list, pair_off, pair_m, conn_s,
-                            conn_m, M_cnt, M_rowptr, M_col, keepM + a, KM);
-  }
-}
-
-__device__ __forceinline__ int find_col(const int32_t* __restrict__ col, int lo, int hi, int key) {
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (col[mid] < key) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo;
-}
-
-// Positions of four keys that all occur in the sorted row segment
-// col[lo..hi): one pass of independent loads over short rows (no dependent
-// chain of a binary search), a binary search per key over long ones.
-__device__ __forceinline__ void find_cols4(const int32_t* __restrict__ col, int lo, int hi, const int key[4],
-                                           int pos[4]) {
-  if (hi - lo <= 32) {
-    pos[0] = pos[1] = pos[2] = pos[3] = lo;
-    for (int i = lo; i < hi; ++i) {
-      const int c = col[i];
-#pragma unroll
-      for (int l = 0; l < 4; ++l) pos[l] = c == key[l] ? i : pos[l];
-    }
-  } else {
-#pragma unroll
-    for (int l = 0; l < 4; ++l) pos[l] = find_col(col, lo, hi, key[l]);
-  }
-}
-
-__global__ __launch_bounds__(BS) void k_posD(const int32_t* __restrict__ conn_s, int32_t n_el,
-                                              const int32_t* __restrict__ pair_off, const int32_t* __restrict__ rowptr,
-                                              const int32_t* __restrict__ col, int32_t* __restrict__ posD) {
-  const int e = xcd_tile(blockIdx.x, gridDim.x) * BS + threadIdx.x;
-  if (e >= n_el) return;
-  const bool has = pair_off[e + 1] > pair_off[e];
-  const int4 c = reinterpret_cast<const int4*>(conn_s)[e];
-  const int id[4] = {c.x, c.y, c.z, c.w};
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    int pos[4] = {-1, -1, -1, -1};
-    if (has) find_cols4(col, rowptr[id[j]], rowptr[id[j] + 1], id, pos);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) posD[(int64_t)(j * 4 + k) * n_el + e] = pos[k];
-  }
-}
-
-__global__ __launch_bounds__(BS) void k_posM(const int32_t* __restrict__ conn_s, const int32_t* __restrict__ conn_m,
-                                              const int32_t* __restrict__ pair_s, const int32_t* __restrict__ pair_m,
-                                              int64_t np, const int32_t* __restrict__ rowptr,
-                                              const int32_t* __restrict__ col, int32_t* __restrict__ posM) {
-  const int64_t p = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * BS + threadIdx.x;
-  if (p >= np) return;
-  const int4 c = reinterpret_cast<const int4*>(conn_s)[pair_s[p]];
-  const int4 q = reinterpret_cast<const int4*>(conn_m)[pair_m[p]];
-  const int rs[4] = {c.x, c.y, c.z, c.w};
-  const int cm[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    int pos[4];
-    find_cols4(col, rowptr[rs[j]], rowptr[rs[j] + 1], cm, pos);
-#pragma unroll
-    for (int l = 0; l < 4; ++l) posM[(int64_t)(j * 4 + l) * np + p] = pos[l];
-  }
+  if (FILL && M_rowptr[a + 1] - M_rowptr[a] <= KM)
+    kept_row<true>(a, n, M_rowptr[a + 1] - M_rowptr[a], keepM, seg, M_rowptr, M_col, inc_off, inc_list, pair_off,
+                   pair_m, conn_s, conn_m, posM, np);
+  else
+    pattern_row<FILL, true>(a, n, seg, bigM_off, bigM, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m, M_cnt,
+                            M_rowptr, M_col, keepM + a, KM, posM, np);
 }
 
 // One thread per slave node (row): the row is accumulated in a per-thread
@@ -348,8 +369,8 @@ hipError_t launch_pattern_rows(bool fill, const int32_t* inc_off, const int32_t*
                                const int32_t* pair_off, const int32_t* pair_m, const int32_t* conn_s,
                                const int32_t* conn_m, const int32_t* bigD_off, int32_t* bigD, const int32_t* bigM_off,
                                int32_t* bigM, int32_t* D_cnt, int32_t* M_cnt, const int32_t* D_rowptr,
-                               const int32_t* M_rowptr, int32_t* D_col, int32_t* M_col, int32_t* keep,
-                               hipStream_t s) {
+                               const int32_t* M_rowptr, int32_t* D_col, int32_t* M_col, int32_t* keep, int32_t* posD,
+                               int32_t n_s_el, int32_t* posM, int64_t n_pairs, hipStream_t s) {
   if (n_nodes == 0) return hipSuccess;
   const unsigned g = xcd_grid((unsigned)((n_nodes + PB - 1) / PB));
   int32_t* keepD = keep;
@@ -357,29 +378,15 @@ hipError_t launch_pattern_rows(bool fill, const int32_t* inc_off, const int32_t*
   if (fill)
     k_pattern_rows<true><<<g, PB, 0, s>>>(inc_off, inc_list, n_nodes, pair_off, pair_m, conn_s, conn_m, bigD_off,
                                           bigD, bigM_off, bigM, D_cnt, M_cnt, D_rowptr, M_rowptr, D_col, M_col, keepD,
-                                          keepM);
+                                          keepM, posD, n_s_el, posM, n_pairs);
   else
     k_pattern_rows<false><<<g, PB, 0, s>>>(inc_off, inc_list, n_nodes, pair_off, pair_m, conn_s, conn_m, bigD_off,
                                            bigD, bigM_off, bigM, D_cnt, M_cnt, D_rowptr, M_rowptr, D_col, M_col,
-                                           keepD, keepM);
+                                           keepD, keepM, posD, n_s_el, posM, n_pairs);
   return hipGetLastError();
 }
 
 int pattern_keep_per_row() { return KD + KM; }
-
-hipError_t launch_posD(const int32_t* conn_s, int32_t n_s_el, const int32_t* pair_off, const int32_t* rowptr,
-                       const int32_t* col, int32_t* posD, hipStream_t s) {
-  if (n_s_el == 0) return hipSuccess;
-  k_posD<<<xcd_grid(grid_of(n_s_el)), BS, 0, s>>>(conn_s, n_s_el, pair_off, rowptr, col, posD);
-  return hipGetLastError();
-}
-
-hipError_t launch_posM(const int32_t* conn_s, const int32_t* conn_m, const int32_t* pair_s, const int32_t* pair_m,
-                       int64_t n_pairs, const int32_t* rowptr, const int32_t* col, int32_t* posM, hipStream_t s) {
-  if (n_pairs == 0) return hipSuccess;
-  k_posM<<<xcd_grid(grid_of(n_pairs)), BS, 0, s>>>(conn_s, conn_m, pair_s, pair_m, n_pairs, rowptr, col, posM);
-  return hipGetLastError();
-}
 
 hipError_t launch_assemble(const int32_t* inc_off, const int32_t* inc_list, int32_t n_nodes, const int32_t* pair_off,
                            const int32_t* D_rowptr, const int32_t* M_rowptr, const int32_t* posD, int32_t n_s_el,

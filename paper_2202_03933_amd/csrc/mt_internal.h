@@ -254,14 +254,9 @@ hipError_t launch_pattern_rows(bool fill, const int32_t* inc_off, const int32_t*
                                const int32_t* pair_off, const int32_t* pair_m, const int32_t* conn_s,
                                const int32_t* conn_m, const int32_t* bigD_off, int32_t* bigD, const int32_t* bigM_off,
                                int32_t* bigM, int32_t* D_cnt, int32_t* M_cnt, const int32_t* D_rowptr,
-                               const int32_t* M_rowptr, int32_t* D_col, int32_t* M_col, int32_t* keep,
-                               hipStream_t s);
+                               const int32_t* M_rowptr, int32_t* D_col, int32_t* M_col, int32_t* keep, int32_t* posD,
+                               int32_t n_s_el, int32_t* posM, int64_t n_pairs, hipStream_t s);
 int pattern_keep_per_row();
-hipError_t launch_posD(const int32_t* conn_s, int32_t n_s_el, const int32_t* pair_off,
-                       const int32_t* rowptr, const int32_t* col, int32_t* posD, hipStream_t s);
-hipError_t launch_posM(const int32_t* conn_s, const int32_t* conn_m, const int32_t* pair_s,
-                       const int32_t* pair_m, int64_t n_pairs, const int32_t* rowptr, const int32_t* col,
-                       int32_t* posM, hipStream_t s);
 hipError_t launch_assemble(const int32_t* inc_off, const int32_t* inc_list, int32_t n_nodes,
                            const int32_t* pair_off, const int32_t* D_rowptr, const int32_t* M_rowptr,
                            const int32_t* posD, int32_t n_s_el, const int32_t* posM, const double* blk,
