@@ -165,8 +165,7 @@ int mt_destroy(mt_ctx* c) {
                  &c->keys_tmp, &c->vals_tmp, &c->cell_range, &c->sbox, &c->cand_cnt, &c->cand_tmp, &c->cand_off,
                  &c->cand_s, &c->cand_m, &c->cand_nv, &c->cand_flag, &c->scr_cnt, &c->scr_off, &c->pair_s, &c->pair_m,
                  &c->pair_nv, &c->pair_off, &c->inc_cnt, &c->inc_off, &c->inc_cur, &c->inc_list, &c->minc_cnt,
-                 &c->minc_off, &c->minc_cur, &c->minc_list, &c->rawD_cnt, &c->rawD_off, &c->rawD, &c->rawM_cnt,
-                 &c->rawM_off, &c->rawM, &c->pat_keep, &c->D_cnt, &c->D_rowptr, &c->D_col, &c->M_cnt, &c->M_rowptr,
+                 &c->minc_off, &c->minc_cur, &c->minc_list, &c->pat_keep, &c->D_cnt, &c->D_rowptr, &c->D_col, &c->M_cnt, &c->M_rowptr,
                  &c->M_col, &c->posD, &c->posM, &c->poly_u, &c->poly_v, &c->poly_lab, &c->poly_nf, &c->maybe_list,
                  &c->maybe_flag, &c->maybe_scan, &c->mpoly_u, &c->mpoly_v, &c->mpoly_lab, &c->mpoly_nf, &c->blk, &c->gpair, &c->nrm_node, &c->nrm_el, &c->gn0, &c->nrm_sb, &c->nrm_ub, &c->nrm_cg, &c->aux_hist, &c->aux_scan, &c->mp_keys, &c->mp_vals, &c->mp_off, &c->mp_pos,
                  &c->scan_tmp, &c->sort_hist, &c->host_tmp};
@@ -526,21 +525,10 @@ int mt_csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, void* stream) {
     c->blk_gen = c->coord_gen;
     c->blk_pending = true;
   }
-  // rows whose column candidates exceed the per-thread LDS segment get global
-  // scratch, sized by the bounds 4 entries per incident element (D) and per
-  // pair of an incident element (M): at most 16 n_el and 16 n_pairs in total
+  // the local block entries (16 per pair) bound nnz(M), so the int32 row
+  // pointers cannot overflow below this size
   if (16 * (int64_t)S.n_el >= (int64_t(1) << 31) || 16 * c->n_pairs >= (int64_t(1) << 31))
     return fail(MT_ECAPACITY, "mt_csr_pattern: more than 2^31 block entries");
-  MT_HIP(ensure(c->rawD_cnt, sizeof(int32_t) * ((size_t)n + 1)));
-  MT_HIP(ensure(c->rawM_cnt, sizeof(int32_t) * ((size_t)n + 1)));
-  MT_HIP(ensure(c->rawD_off, sizeof(int32_t) * ((size_t)n + 1)));
-  MT_HIP(ensure(c->rawM_off, sizeof(int32_t) * ((size_t)n + 1)));
-  MT_HIP(ensure(c->rawD, sizeof(int32_t) * 16 * (size_t)std::max(S.n_el, 1)));
-  MT_HIP(ensure(c->rawM, sizeof(int32_t) * 16 * (size_t)std::max<int64_t>(c->n_pairs, 1)));
-  MT_HIP(launch_raw_count(c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(), n, c->pair_off.as<int32_t>(),
-                          c->rawD_cnt.as<int32_t>(), c->rawM_cnt.as<int32_t>(), st));
-  MT_HIP(scan_exclusive(c->rawD_cnt.as<int32_t>(), c->rawD_off.as<int32_t>(), n, c->scan_tmp, st));
-  MT_HIP(scan_exclusive(c->rawM_cnt.as<int32_t>(), c->rawM_off.as<int32_t>(), n, c->scan_tmp, st));
   int32_t tot[2] = {0, 0};
   MT_HIP(ensure(c->pat_keep, sizeof(int32_t) * (size_t)pattern_keep_per_row() * (size_t)std::max(n, 1)));
   MT_HIP(ensure(c->D_cnt, sizeof(int32_t) * ((size_t)n + 1)));
@@ -548,10 +536,9 @@ int mt_csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, void* stream) {
   MT_HIP(ensure(c->D_rowptr, sizeof(int32_t) * ((size_t)n + 1)));
   MT_HIP(ensure(c->M_rowptr, sizeof(int32_t) * ((size_t)n + 1)));
   MT_HIP(launch_pattern_rows(false, c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(), n, c->pair_off.as<int32_t>(),
-                             c->pair_m.as<int32_t>(), S.conn, M.conn, c->rawD_off.as<int32_t>(), c->rawD.as<int32_t>(),
-                             c->rawM_off.as<int32_t>(), c->rawM.as<int32_t>(), c->D_cnt.as<int32_t>(),
-                             c->M_cnt.as<int32_t>(), nullptr, nullptr, nullptr, nullptr, c->pat_keep.as<int32_t>(),
-                             nullptr, S.n_el, nullptr, c->n_pairs, st));
+                             c->pair_m.as<int32_t>(), S.conn, M.conn, c->D_cnt.as<int32_t>(), c->M_cnt.as<int32_t>(),
+                             nullptr, nullptr, nullptr, nullptr, c->pat_keep.as<int32_t>(), nullptr, S.n_el, nullptr,
+                             c->n_pairs, st));
   MT_HIP(scan_exclusive(c->D_cnt.as<int32_t>(), c->D_rowptr.as<int32_t>(), n, c->scan_tmp, st));
   MT_HIP(scan_exclusive(c->M_cnt.as<int32_t>(), c->M_rowptr.as<int32_t>(), n, c->scan_tmp, st));
   MT_HIP(hipMemcpyAsync(&tot[0], c->D_rowptr.as<int32_t>() + n, 4, hipMemcpyDeviceToHost, st));
@@ -565,9 +552,7 @@ int mt_csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, void* stream) {
   MT_HIP(ensure(c->posD, sizeof(int32_t) * 16 * (size_t)std::max(S.n_el, 1)));
   MT_HIP(ensure(c->posM, sizeof(int32_t) * 16 * (size_t)std::max<int64_t>(c->n_pairs, 1)));
   MT_HIP(launch_pattern_rows(true, c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(), n, c->pair_off.as<int32_t>(),
-                             c->pair_m.as<int32_t>(), S.conn, M.conn, c->rawD_off.as<int32_t>(), c->rawD.as<int32_t>(),
-                             c->rawM_off.as<int32_t>(), c->rawM.as<int32_t>(), nullptr, nullptr,
-                             c->D_rowptr.as<int32_t>(), c->M_rowptr.as<int32_t>(), c->D_col.as<int32_t>(),
+                             c->pair_m.as<int32_t>(), S.conn, M.conn, nullptr, nullptr, c->D_rowptr.as<int32_t>(), c->M_rowptr.as<int32_t>(), c->D_col.as<int32_t>(),
                              c->M_col.as<int32_t>(), c->pat_keep.as<int32_t>(), c->posD.as<int32_t>(), S.n_el,
                              c->posM.as<int32_t>(), c->n_pairs, st));
   if (aux) MT_HIP(hipStreamWaitEvent(st, c->aux_join, 0));

@@ -55,27 +55,6 @@ __global__ __launch_bounds__(BS) void k_inc_sort(const int32_t* __restrict__ off
   }
 }
 
-__global__ __launch_bounds__(BS) void k_raw_count(const int32_t* __restrict__ inc_off,
-                                                   const int32_t* __restrict__ inc_list, int32_t n,
-                                                   const int32_t* __restrict__ pair_off, int32_t* rawD_big,
-                                                   int32_t* rawM_big) {
-  const int a = xcd_tile(blockIdx.x, gridDim.x) * BS + threadIdx.x;
-  if (a >= n) return;
-  int d = 0, m = 0;
-  for (int i = inc_off[a]; i < inc_off[a + 1]; ++i) {
-    const int e = inc_list[i] >> 2;
-    const int np = pair_off[e + 1] - pair_off[e];
-    if (np > 0) {
-      d += 4;
-      m += 4 * np;
-    }
-  }
-  // rows whose raw candidates exceed the per-thread LDS segment get global
-  // scratch in case their column list does not fit there
-  rawD_big[a] = d > PCAP ? d : 0;
-  rawM_big[a] = m > PCAP ? m : 0;
-}
-
 // Inserts x into the ascending, duplicate-free strided list v[0..u) unless
 // it is already there; returns the new length, or -1 when the list holds cap
 // entries and x is new.
@@ -115,13 +94,44 @@ __device__ __forceinline__ int row_columns(int a, const int32_t* __restrict__ in
   return u;
 }
 
+// The same columns without any scratch, for rows that outgrow the LDS
+// segment: the u-th column is the smallest candidate above the (u-1)-th, found
+// by a pass over all candidates (raw x unique work, for rare long rows).  With
+// col the columns are written there.
+template <bool MCOLS>
+__device__ __forceinline__ int row_columns_scan(int a, const int32_t* __restrict__ inc_off,
+                                                const int32_t* __restrict__ inc_list,
+                                                const int32_t* __restrict__ pair_off,
+                                                const int32_t* __restrict__ pair_m,
+                                                const int32_t* __restrict__ conn_s,
+                                                const int32_t* __restrict__ conn_m, int32_t* col) {
+  int u = 0, prev = -1;
+  while (true) {
+    int next = 0x7fffffff;
+    for (int i = inc_off[a]; i < inc_off[a + 1]; ++i) {
+      const int e = inc_list[i] >> 2;
+      const int p0 = pair_off[e], p1 = pair_off[e + 1];
+      if (p1 == p0) continue;
+      for (int p = MCOLS ? p0 : 0; p < (MCOLS ? p1 : 1); ++p) {
+        const int4 q = reinterpret_cast<const int4*>(MCOLS ? conn_m : conn_s)[MCOLS ? pair_m[p] : e];
+        const int key[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int l = 0; l < 4; ++l) next = key[l] > prev && key[l] < next ? key[l] : next;
+      }
+    }
+    if (next == 0x7fffffff) return u;
+    if (col) col[u] = next;
+    ++u;
+    prev = next;
+  }
+}
+
 // Row patterns of D and M.  Each thread builds its row's sorted column list
-// in a lane-interleaved LDS segment of PCAP entries, or, when that fills up
-// (possible only for rows with more than PCAP raw candidates), again in a
-// global scratch segment sized by the raw count.  The count pass writes the
-// row lengths and keeps rows of at most KD (D) / KM (M) columns in
-// lane-interleaved scratch keep[i * n + a]; the fill pass copies those and
-// recomputes the rest.
+// in a lane-interleaved LDS segment of PCAP entries; a row that outgrows it
+// is counted, and in the fill pass written, by row_columns_scan.  The count
+// pass writes the row lengths and keeps rows of at most KD (D) / KM (M)
+// columns in lane-interleaved scratch keep[i * n + a]; the fill pass copies
+// those and recomputes the rest.
 constexpr int KD = 16;
 constexpr int KM = 32;
 static_assert(KD <= PCAP && KM <= PCAP, "kept rows are looked up in the LDS segment");
@@ -203,8 +213,7 @@ __device__ __forceinline__ void finish_row(int a, int32_t n, int u, const int32_
 }
 
 template <bool FILL, bool MCOLS>
-__device__ __forceinline__ void pattern_row(int a, int32_t n, int32_t* lds, const int32_t* __restrict__ big_off,
-                                            int32_t* big, const int32_t* __restrict__ inc_off,
+__device__ __forceinline__ void pattern_row(int a, int32_t n, int32_t* lds, const int32_t* __restrict__ inc_off,
                                             const int32_t* __restrict__ inc_list,
                                             const int32_t* __restrict__ pair_off,
                                             const int32_t* __restrict__ pair_m,
@@ -212,15 +221,17 @@ __device__ __forceinline__ void pattern_row(int a, int32_t n, int32_t* lds, cons
                                             const int32_t* __restrict__ conn_m, int32_t* cnt,
                                             const int32_t* __restrict__ rowptr, int32_t* colv, int32_t* keep,
                                             int kcap, int32_t* pos, int64_t pstride) {
-  int u = row_columns<MCOLS>(a, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m, lds, PB, PCAP);
+  const int u = row_columns<MCOLS>(a, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m, lds, PB, PCAP);
   if (u >= 0) {
     finish_row<FILL, MCOLS>(a, n, u, lds, PB, cnt, rowptr, colv, keep, kcap, inc_off, inc_list, pair_off, pair_m,
                             conn_s, conn_m, pos, pstride);
+  } else if (!FILL) {
+    cnt[a] = row_columns_scan<MCOLS>(a, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m, nullptr);
   } else {
-    int32_t* v = big + big_off[a];
-    u = row_columns<MCOLS>(a, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m, v, 1, big_off[a + 1] - big_off[a]);
-    finish_row<FILL, MCOLS>(a, n, u, v, 1, cnt, rowptr, colv, keep, kcap, inc_off, inc_list, pair_off, pair_m,
-                            conn_s, conn_m, pos, pstride);
+    const int base = rowptr[a];
+    const int w = row_columns_scan<MCOLS>(a, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m, colv + base);
+    row_positions<MCOLS>(a, colv + base, 1, w, base, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m, pos,
+                         pstride);
   }
 }
 
@@ -249,10 +260,8 @@ __global__ __launch_bounds__(PB) void k_pattern_rows(const int32_t* __restrict__
                                                       const int32_t* __restrict__ pair_off,
                                                       const int32_t* __restrict__ pair_m,
                                                       const int32_t* __restrict__ conn_s,
-                                                      const int32_t* __restrict__ conn_m,
-                                                      const int32_t* __restrict__ bigD_off, int32_t* bigD,
-                                                      const int32_t* __restrict__ bigM_off, int32_t* bigM,
-                                                      int32_t* D_cnt, int32_t* M_cnt,
+                                                      const int32_t* __restrict__ conn_m, int32_t* D_cnt,
+                                                      int32_t* M_cnt,
                                                       const int32_t* __restrict__ D_rowptr,
                                                       const int32_t* __restrict__ M_rowptr, int32_t* D_col,
                                                       int32_t* M_col, int32_t* keepD, int32_t* keepM,
@@ -266,15 +275,15 @@ __global__ __launch_bounds__(PB) void k_pattern_rows(const int32_t* __restrict__
     kept_row<false>(a, n, D_rowptr[a + 1] - D_rowptr[a], keepD, seg, D_rowptr, D_col, inc_off, inc_list, pair_off,
                     pair_m, conn_s, conn_m, posD, n_el);
   else
-    pattern_row<FILL, false>(a, n, seg, bigD_off, bigD, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m, D_cnt,
-                             D_rowptr, D_col, keepD + a, KD, posD, n_el);
+    pattern_row<FILL, false>(a, n, seg, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m, D_cnt, D_rowptr, D_col,
+                             keepD + a, KD, posD, n_el);
   // M row
   if (FILL && M_rowptr[a + 1] - M_rowptr[a] <= KM)
     kept_row<true>(a, n, M_rowptr[a + 1] - M_rowptr[a], keepM, seg, M_rowptr, M_col, inc_off, inc_list, pair_off,
                    pair_m, conn_s, conn_m, posM, np);
   else
-    pattern_row<FILL, true>(a, n, seg, bigM_off, bigM, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m, M_cnt,
-                            M_rowptr, M_col, keepM + a, KM, posM, np);
+    pattern_row<FILL, true>(a, n, seg, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m, M_cnt, M_rowptr, M_col,
+                            keepM + a, KM, posM, np);
 }
 
 // One thread per slave node (row): the row is accumulated in a per-thread
@@ -358,17 +367,9 @@ hipError_t launch_inc_sort(const int32_t* off, int32_t n_nodes, int32_t* list, h
   return hipGetLastError();
 }
 
-hipError_t launch_raw_count(const int32_t* inc_off, const int32_t* inc_list, int32_t n_nodes,
-                            const int32_t* pair_off, int32_t* rawD_big, int32_t* rawM_big, hipStream_t s) {
-  if (n_nodes == 0) return hipSuccess;
-  k_raw_count<<<xcd_grid(grid_of(n_nodes)), BS, 0, s>>>(inc_off, inc_list, n_nodes, pair_off, rawD_big, rawM_big);
-  return hipGetLastError();
-}
-
 hipError_t launch_pattern_rows(bool fill, const int32_t* inc_off, const int32_t* inc_list, int32_t n_nodes,
                                const int32_t* pair_off, const int32_t* pair_m, const int32_t* conn_s,
-                               const int32_t* conn_m, const int32_t* bigD_off, int32_t* bigD, const int32_t* bigM_off,
-                               int32_t* bigM, int32_t* D_cnt, int32_t* M_cnt, const int32_t* D_rowptr,
+                               const int32_t* conn_m, int32_t* D_cnt, int32_t* M_cnt, const int32_t* D_rowptr,
                                const int32_t* M_rowptr, int32_t* D_col, int32_t* M_col, int32_t* keep, int32_t* posD,
                                int32_t n_s_el, int32_t* posM, int64_t n_pairs, hipStream_t s) {
   if (n_nodes == 0) return hipSuccess;
@@ -376,13 +377,13 @@ hipError_t launch_pattern_rows(bool fill, const int32_t* inc_off, const int32_t*
   int32_t* keepD = keep;
   int32_t* keepM = keep + (int64_t)KD * n_nodes;
   if (fill)
-    k_pattern_rows<true><<<g, PB, 0, s>>>(inc_off, inc_list, n_nodes, pair_off, pair_m, conn_s, conn_m, bigD_off,
-                                          bigD, bigM_off, bigM, D_cnt, M_cnt, D_rowptr, M_rowptr, D_col, M_col, keepD,
-                                          keepM, posD, n_s_el, posM, n_pairs);
+    k_pattern_rows<true><<<g, PB, 0, s>>>(inc_off, inc_list, n_nodes, pair_off, pair_m, conn_s, conn_m, D_cnt, M_cnt,
+                                          D_rowptr, M_rowptr, D_col, M_col, keepD, keepM, posD, n_s_el, posM,
+                                          n_pairs);
   else
-    k_pattern_rows<false><<<g, PB, 0, s>>>(inc_off, inc_list, n_nodes, pair_off, pair_m, conn_s, conn_m, bigD_off,
-                                           bigD, bigM_off, bigM, D_cnt, M_cnt, D_rowptr, M_rowptr, D_col, M_col,
-                                           keepD, keepM, posD, n_s_el, posM, n_pairs);
+    k_pattern_rows<false><<<g, PB, 0, s>>>(inc_off, inc_list, n_nodes, pair_off, pair_m, conn_s, conn_m, D_cnt,
+                                           M_cnt, D_rowptr, M_rowptr, D_col, M_col, keepD, keepM, posD, n_s_el, posM,
+                                           n_pairs);
   return hipGetLastError();
 }
 

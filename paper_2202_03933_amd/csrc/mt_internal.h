@@ -148,8 +148,6 @@ struct mt_ctx {
   // pattern
   mt::Buf inc_cnt, inc_off, inc_cur, inc_list;     // slave node -> (element*4 + local)
   mt::Buf minc_cnt, minc_off, minc_cur, minc_list; // master node -> (element*4 + local)
-  mt::Buf rawD_cnt, rawD_off, rawD;                // per-row raw column lists
-  mt::Buf rawM_cnt, rawM_off, rawM;
   mt::Buf pat_keep;        // per-row column lists kept between the pattern passes
   mt::Buf D_cnt, D_rowptr, D_col;
   mt::Buf M_cnt, M_rowptr, M_col;
@@ -248,12 +246,9 @@ hipError_t launch_inc_count(const int32_t* conn, int32_t n_el, int32_t* cnt, hip
 hipError_t launch_inc_fill(const int32_t* conn, int32_t n_el, const int32_t* off, int32_t* cur,
                            int32_t* list, hipStream_t s);
 hipError_t launch_inc_sort(const int32_t* off, int32_t n_nodes, int32_t* list, hipStream_t s);
-hipError_t launch_raw_count(const int32_t* inc_off, const int32_t* inc_list, int32_t n_nodes,
-                            const int32_t* pair_off, int32_t* rawD_big, int32_t* rawM_big, hipStream_t s);
 hipError_t launch_pattern_rows(bool fill, const int32_t* inc_off, const int32_t* inc_list, int32_t n_nodes,
                                const int32_t* pair_off, const int32_t* pair_m, const int32_t* conn_s,
-                               const int32_t* conn_m, const int32_t* bigD_off, int32_t* bigD, const int32_t* bigM_off,
-                               int32_t* bigM, int32_t* D_cnt, int32_t* M_cnt, const int32_t* D_rowptr,
+                               const int32_t* conn_m, int32_t* D_cnt, int32_t* M_cnt, const int32_t* D_rowptr,
                                const int32_t* M_rowptr, int32_t* D_col, int32_t* M_col, int32_t* keep, int32_t* posD,
                                int32_t n_s_el, int32_t* posM, int64_t n_pairs, hipStream_t s);
 int pattern_keep_per_row();
