@@ -291,7 +291,7 @@ typedef struct mt_batch mt_batch;
 
 /* Tuning knobs of the persistent launch; 0 = autotuned value. */
 typedef struct mt_batch_tuning {
-  int32_t bucket;         /* pairs per work item */
+  int32_t bucket;         /* pairs per work item (one wavefront takes an item) */
   int32_t block;          /* threads per block (multiple of 64) */
   int32_t blocks_per_cu;  /* persistent blocks per compute unit */
   int32_t reserved;

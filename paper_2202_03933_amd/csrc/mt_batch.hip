@@ -4,12 +4,13 @@
 // dynamically evolving interfaces": work is distributed over all compute
 // units regardless of which interface it belongs to).
 //
-// Work items are buckets of consecutive pairs of one instance.  They are
-// split into 8 contiguous queues, one per XCD; a block starts on the queue of
-// its own XCD (blocks are dispatched round-robin over XCDs, so block b runs
-// on XCD b % 8) and then takes items from the other queues, so each XCD's L2
-// first sees one contiguous part of the meshes.  Queue counters are reset by
-// a fill kernel, so the launch sequence can be captured in a HIP graph.
+// Work items are buckets of consecutive pairs of one instance, each taken by
+// one wavefront.  They are split into 8 contiguous queues, one per XCD; the
+// wavefronts of a block start on the queue of the block's XCD (blocks are
+// dispatched round-robin over XCDs, so block b runs on XCD b % 8) and then
+// take items from the other queues, so each XCD's L2 first sees one
+// contiguous part of the meshes.  Queue counters are reset by a fill kernel,
+// so the launch sequence can be captured in a HIP graph.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -75,20 +76,25 @@ __global__ void k_reset_queues(int32_t* qnext) {
   if (threadIdx.x < NQUEUE) qnext[threadIdx.x] = 0;
 }
 
-// Takes the next work item for this block: its own XCD's queue first, then
-// the others in order; returns -1 when every queue is drained.  Uniform
-// across the block.
-__device__ __forceinline__ int next_item(const int32_t* __restrict__ qbeg, int32_t* qnext, int& qi, int* s_item) {
+// Takes the next work item for this wavefront: its block's XCD queue first,
+// then the others in order; returns -1 when every queue is drained.  Each
+// wavefront fetches on its own (lane 0 takes the item, every lane reads it
+// from lane 0), so no wavefront waits at a barrier for another's pairs.
+// Uniform across the wavefront; all its lanes are active here.
+__device__ __forceinline__ int next_item(const int32_t* __restrict__ qbeg, int32_t* qnext, int& qi) {
   const int home = blockIdx.x % NQUEUE;
+  const bool lead = (threadIdx.x & 63) == 0;
   while (qi < NQUEUE) {
     const int q = (home + qi) % NQUEUE;
-    __syncthreads();
-    if (threadIdx.x == 0) {
+    int it = -1;
+    if (lead) {
       const int k = atomicAdd(&qnext[q], 1);
-      *s_item = qbeg[q] + k < qbeg[q + 1] ? qbeg[q] + k : -1;
+      it = qbeg[q] + k < qbeg[q + 1] ? qbeg[q] + k : -1;
     }
-    __syncthreads();
-    const int it = *s_item;
+    // lane 0's value, in a scalar register: the item and instance records
+    // are then read with scalar loads and their pointers stay out of the
+    // vector registers of the pair evaluation
+    it = __builtin_amdgcn_readfirstlane(it);
     if (it >= 0) return it;
     ++qi;
   }
@@ -102,13 +108,12 @@ __global__ __launch_bounds__(BSZ) void k_batch_poly(const BatchInst* __restrict_
                                                      const int32_t* __restrict__ qbeg, int32_t* qnext) {
   __shared__ double su[CAPT * BSZ], sv[CAPT * BSZ];
   __shared__ uint8_t sl[CAPT * BSZ], se[CAPT * BSZ];
-  __shared__ int s_item;
   int qi = 0;
   const LdsPoly<true> P{su + threadIdx.x, sv + threadIdx.x, sl + threadIdx.x, se + threadIdx.x, BSZ};
-  for (int it = next_item(qbeg, qnext, qi, &s_item); it >= 0; it = next_item(qbeg, qnext, qi, &s_item)) {
+  for (int it = next_item(qbeg, qnext, qi); it >= 0; it = next_item(qbeg, qnext, qi)) {
     const WorkItem w = items[it];
     const BatchInst& I = inst[w.inst];
-    for (int64_t p = w.begin + (int)threadIdx.x; p < w.end; p += BSZ) {
+    for (int64_t p = w.begin + (int)(threadIdx.x & 63); p < w.end; p += 64) {
       double Xs[4][3], Xm[4][3];
       load_nodes(I.S.x, I.S.y, I.S.z, load_conn(I.S.conn, I.pair_s[p]), Xs);
       load_nodes(I.M.x, I.M.y, I.M.z, load_conn(I.M.conn, I.pair_m[p]), Xm);
@@ -121,13 +126,12 @@ template <int BSZ, int NQ, bool DUAL>
 __global__ __launch_bounds__(BSZ) __attribute__((amdgpu_waves_per_eu(3))) void k_batch_fwd(const BatchInst* __restrict__ inst,
                                                     const WorkItem* __restrict__ items,
                                                     const int32_t* __restrict__ qbeg, int32_t* qnext, Counters* cnt) {
-  __shared__ int s_item;
   unsigned noconv = 0;
   int qi = 0;
-  for (int it = next_item(qbeg, qnext, qi, &s_item); it >= 0; it = next_item(qbeg, qnext, qi, &s_item)) {
+  for (int it = next_item(qbeg, qnext, qi); it >= 0; it = next_item(qbeg, qnext, qi)) {
     const WorkItem w = items[it];
     const BatchInst& I = inst[w.inst];
-    for (int64_t p = w.begin + (int)threadIdx.x; p < w.end; p += BSZ) {
+    for (int64_t p = w.begin + (int)(threadIdx.x & 63); p < w.end; p += 64) {
       double D[16], Mv[16], g[4];
       const int s = I.pair_s[p];
       pair_forward<NQ, DUAL>(I.S, s, load_conn(I.S.conn, s), I.M, load_conn(I.M.conn, I.pair_m[p]),
@@ -149,14 +153,13 @@ template <int BSZ, int NQ, bool DUAL, bool NODAL>
 __global__ __launch_bounds__(BSZ) __attribute__((amdgpu_waves_per_eu(2))) void k_batch_bwd(const BatchInst* __restrict__ inst,
                                                     const WorkItem* __restrict__ items,
                                                     const int32_t* __restrict__ qbeg, int32_t* qnext, Counters* cnt) {
-  __shared__ int s_item;
   unsigned noconv = 0;
   int qi = 0;
-  for (int it = next_item(qbeg, qnext, qi, &s_item); it >= 0; it = next_item(qbeg, qnext, qi, &s_item)) {
+  for (int it = next_item(qbeg, qnext, qi); it >= 0; it = next_item(qbeg, qnext, qi)) {
     const WorkItem w = items[it];
     const BatchInst& I = inst[w.inst];
     const int64_t st = I.n_pairs;
-    for (int64_t p = w.begin + (int)threadIdx.x; p < w.end; p += BSZ) {
+    for (int64_t p = w.begin + (int)(threadIdx.x & 63); p < w.end; p += 64) {
       const int s = I.pair_s[p];
       const int4 csn = load_conn(I.S.conn, s);
       auto gather = [&](int se, int4 c, double WD[16], double WM[16], double wg[4]) {
@@ -577,7 +580,7 @@ int mt_batch_build(mt_batch* b, const mt_batch_tuning* tuning, void* stream) {
   const int resident = resident_blocks(reinterpret_cast<const void*>(pick_fwd(t.block, p0.rule, p0.lm_basis == MT_BASIS_DUAL)), t.block);
   if (t.blocks_per_cu <= 0) t.blocks_per_cu = resident;
   t.blocks_per_cu = std::min(t.blocks_per_cu, resident);
-  if (t.bucket <= 0) t.bucket = 4 * t.block;
+  if (t.bucket <= 0) t.bucket = 4 * 64;
   b->tune = t;
 
   b->h_inst.assign(b->ctxs.size(), BatchInst{});
@@ -734,7 +737,7 @@ int mt_batch_autotune(mt_batch* b, mt_batch_tuning* out, void* stream) {
   std::vector<Cand> cands;
   for (int block : {64, 128, 256})
     for (int bpc : {1, 2, 4, 6, 8})
-      for (int mul : {1, 4, 16})
+      for (int mul : {1, 2, 4, 8, 16})
         if (bpc <= resident_blocks(reinterpret_cast<const void*>(pick_fwd(block, b->nq, b->dual)), block))
           cands.push_back({block, bpc, mul});
   hipEvent_t e0, e1;
@@ -745,7 +748,7 @@ int mt_batch_autotune(mt_batch* b, mt_batch_tuning* out, void* stream) {
   for (const Cand& c : cands) {
     b->tune.block = c.block;
     b->tune.blocks_per_cu = c.bpc;
-    b->tune.bucket = c.block * c.bucket_mul;
+    b->tune.bucket = 64 * c.bucket_mul;  // pairs per wavefront item
     int rc = build_items(b, st);
     if (rc) return rc;
     rc = launch_fwd(b, st);  // warm-up
