@@ -97,53 +97,59 @@ __device__ __forceinline__ void assemble_row(int a, const int32_t* __restrict__ 
   gap[a] = g;
 }
 
-// Row a accumulated in the per-thread scratch segment acc[i * astride] (D
-// entries first, then M) by plain nested loops over the incident elements
-// and their pairs; for nodes with more than ROW_RUNS incident elements.
-__device__ __forceinline__ void assemble_row_acc_loops(int a, const int32_t* __restrict__ inc_off,
-                                                       const int32_t* __restrict__ inc_list,
-                                                       const int32_t* __restrict__ pair_off, int d0, int nd, int m0,
-                                                       int nm, const int32_t* __restrict__ posD, int32_t n_s_el,
-                                                       const int32_t* __restrict__ posM,
-                                                       const double* __restrict__ blk, int64_t stride,
-                                                       double* __restrict__ D_val, double* __restrict__ M_val,
-                                                       double* __restrict__ gap, double* acc, int astride) {
-  for (int i = 0; i < nd + nm; ++i) acc[i * astride] = 0.0;
+// One sweep over the pairs of row a (incident elements ascending, then their
+// pairs), adding the D part (DP: entry q at acc[(q - d0) * astride], and the
+// gap, returned) and/or the M part (MP: entry q at acc[(q + moff) * astride]).
+template <bool DP, bool MP>
+__device__ __forceinline__ double row_sweep(int a, const int32_t* __restrict__ inc_off,
+                                            const int32_t* __restrict__ inc_list,
+                                            const int32_t* __restrict__ pair_off, int d0, int moff,
+                                            const int32_t* __restrict__ posD, int32_t n_s_el,
+                                            const int32_t* __restrict__ posM, const double* __restrict__ blk,
+                                            int64_t stride, double* acc, int astride) {
   double g = 0.0;
-  const int moff = nd - m0;
   for (int i = inc_off[a]; i < inc_off[a + 1]; ++i) {
     const int e = inc_list[i] >> 2, j = inc_list[i] & 3;
     const int p0 = pair_off[e], p1 = pair_off[e + 1];
     if (p0 == p1) continue;
     int pd[4];
+    if (DP) {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) pd[k] = posD[(int64_t)(j * 4 + k) * n_s_el + e] - d0;
+      for (int k = 0; k < 4; ++k) pd[k] = posD[(int64_t)(j * 4 + k) * n_s_el + e] - d0;
+    }
     for (int p = p0; p < p1; ++p) {
       double vd[4], vm[4];
       int pm[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        vd[k] = blk[(int64_t)(j * 4 + k) * stride + p];
-        vm[k] = blk[(int64_t)(16 + j * 4 + k) * stride + p];
-        pm[k] = posM[(int64_t)(j * 4 + k) * stride + p] + moff;
+        if (DP) vd[k] = blk[(int64_t)(j * 4 + k) * stride + p];
+        if (MP) {
+          vm[k] = blk[(int64_t)(16 + j * 4 + k) * stride + p];
+          pm[k] = posM[(int64_t)(j * 4 + k) * stride + p] + moff;
+        }
       }
-      g += blk[(int64_t)(32 + j) * stride + p];
+      if (DP) g += blk[(int64_t)(32 + j) * stride + p];
+      if (DP) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) acc[pd[k] * astride] += vd[k];
+        for (int k = 0; k < 4; ++k) acc[pd[k] * astride] += vd[k];
+      }
+      if (MP) {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) acc[pm[k] * astride] += vm[k];
+        for (int k = 0; k < 4; ++k) acc[pm[k] * astride] += vm[k];
+      }
     }
   }
-  for (int i = 0; i < nd; ++i) D_val[d0 + i] = acc[i * astride];
-  for (int i = 0; i < nm; ++i) M_val[m0 + i] = acc[(nd + i) * astride];
-  gap[a] = g;
+  return g;
 }
 
 // Same as assemble_row, accumulating the row in a per-thread scratch segment
-// acc[i * astride] (D entries first, then M) and writing it once; rows longer
-// than cap entries fall back to assemble_row.  (Issuing the loads of several
-// pairs together, as the gradient gathers below do, measured slower here:
-// the row's LDS updates, not its loads, set the pace.)
+// of cap entries, acc[i * astride], and writing it once: D and M entries
+// together in one sweep when they fit, else in two sweeps (D with the gap,
+// then M) when each part fits; longer rows fall back to assemble_row.  Every
+// entry receives its contributions in the same order in all three forms.
+// (Issuing the loads of several pairs together, as the gradient gathers
+// below do, measured slower here: the row's LDS updates, not its loads, set
+// the pace.)
 __device__ __forceinline__ void assemble_row_acc(int a, const int32_t* __restrict__ inc_off,
                                                  const int32_t* __restrict__ inc_list,
                                                  const int32_t* __restrict__ pair_off,
@@ -157,39 +163,26 @@ __device__ __forceinline__ void assemble_row_acc(int a, const int32_t* __restric
   const int d0 = D_rowptr[a], d1 = D_rowptr[a + 1];
   const int m0 = M_rowptr[a], m1 = M_rowptr[a + 1];
   const int nd = d1 - d0, nm = m1 - m0;
-  if (nd + nm > cap) {
+  double g;
+  if (nd + nm <= cap) {
+    for (int i = 0; i < nd + nm; ++i) acc[i * astride] = 0.0;
+    g = row_sweep<true, true>(a, inc_off, inc_list, pair_off, d0, nd - m0, posD, n_s_el, posM, blk, stride, acc,
+                              astride);
+    for (int i = 0; i < nd; ++i) D_val[d0 + i] = acc[i * astride];
+    for (int i = 0; i < nm; ++i) M_val[m0 + i] = acc[(nd + i) * astride];
+  } else if (nd <= cap && nm <= cap) {
+    for (int i = 0; i < nd; ++i) acc[i * astride] = 0.0;
+    g = row_sweep<true, false>(a, inc_off, inc_list, pair_off, d0, 0, posD, n_s_el, posM, blk, stride, acc,
+                               astride);
+    for (int i = 0; i < nd; ++i) D_val[d0 + i] = acc[i * astride];
+    for (int i = 0; i < nm; ++i) acc[i * astride] = 0.0;
+    row_sweep<false, true>(a, inc_off, inc_list, pair_off, d0, -m0, posD, n_s_el, posM, blk, stride, acc, astride);
+    for (int i = 0; i < nm; ++i) M_val[m0 + i] = acc[i * astride];
+  } else {
     assemble_row(a, inc_off, inc_list, pair_off, D_rowptr, M_rowptr, posD, n_s_el, posM, blk, stride, D_val, M_val,
                  gap);
     return;
   }
-  for (int i = 0; i < nd + nm; ++i) acc[i * astride] = 0.0;
-  double g = 0.0;
-  const int moff = nd - m0;  // M position q accumulates at acc[(q + moff) * astride]
-  for (int i = inc_off[a]; i < inc_off[a + 1]; ++i) {
-    const int e = inc_list[i] >> 2, j = inc_list[i] & 3;
-    const int p0 = pair_off[e], p1 = pair_off[e + 1];
-    if (p0 == p1) continue;
-    int pd[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) pd[k] = posD[(int64_t)(j * 4 + k) * n_s_el + e] - d0;
-    for (int p = p0; p < p1; ++p) {
-      double vd[4], vm[4];
-      int pm[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        vd[k] = blk[(int64_t)(j * 4 + k) * stride + p];
-        vm[k] = blk[(int64_t)(16 + j * 4 + k) * stride + p];
-        pm[k] = posM[(int64_t)(j * 4 + k) * stride + p] + moff;
-      }
-      g += blk[(int64_t)(32 + j) * stride + p];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) acc[pd[k] * astride] += vd[k];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) acc[pm[k] * astride] += vm[k];
-    }
-  }
-  for (int i = 0; i < nd; ++i) D_val[d0 + i] = acc[i * astride];
-  for (int i = 0; i < nm; ++i) M_val[m0 + i] = acc[(nd + i) * astride];
   gap[a] = g;
 }
 

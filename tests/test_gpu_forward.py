@@ -115,3 +115,15 @@ def test_mixed_candidate_counts():
     assert_forward_parity(g, o)
     c = np.bincount(o["cand_s"], minlength=itf.slave.n_el)
     assert (c <= 32).any() and ((c > 32) & (c <= 48)).any() and (c > 48).any()
+
+
+def test_rows_longer_than_the_accumulator():
+    # master finer than slave (ratio 1.3): many rows of D and M together hold
+    # more than 32 entries (each part fits), and every assembly form of a row
+    # must give the oracle's values; the gradient sums run over the same rows
+    itf = synth.flat_tied(16, 21, seed=4)
+    g = gpu_run(itf, backward_seed=31)
+    o = oracle.evaluate(itf, oracle_params(itf))
+    assert_forward_parity(g, o)
+    nd, nm = np.diff(o["D"].indptr), np.diff(o["M"].indptr)
+    assert ((nd + nm > 32) & (nm <= 32)).sum() > 0
