@@ -34,6 +34,26 @@ __device__ __forceinline__ void gather_weights(int s, int64_t p, int4 csn, const
   wg[3] = w_g[csn.w];
 }
 
+// Dual basis: the dependence of the dual coefficients on the slave nodes
+// (pair_dual_adjoint), before the sweep.  A kernel of its own, so that its
+// registers do not add to those of the sweep.
+template <bool NODAL>
+__global__ __launch_bounds__(BSC) __attribute__((amdgpu_waves_per_eu(2))) void k_pair_dual_adj(MeshPtrs S, int32_t n_s, const int32_t* __restrict__ pair_s,
+                                                        int64_t n_pairs, const int32_t* __restrict__ posD,
+                                                        const int32_t* __restrict__ posM,
+                                                        const double* __restrict__ W_D, const double* __restrict__ W_M,
+                                                        const double* __restrict__ w_g,
+                                                        const double* __restrict__ blk, double* __restrict__ gpair,
+                                                        double* __restrict__ gn0, int64_t stride) {
+  const int64_t p = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * BSC + threadIdx.x;
+  if (p >= n_pairs) return;
+  const int s = pair_s[p];
+  const int4 csn = load_conn(S.conn, s);
+  double WD[16], WM[16], wg[4];
+  gather_weights(s, p, csn, posD, n_s, posM, stride, W_D, W_M, w_g, WD, WM, wg);
+  pair_dual_adjoint<NODAL>(S, s, csn, WD, WM, wg, blk, stride, p, gpair, gn0);
+}
+
 template <int NQ, bool DUAL, bool NODAL>
 __global__ __launch_bounds__(BSC) __attribute__((amdgpu_waves_per_eu(2))) void k_pair_bwd(MeshPtrs S, int32_t n_s, MeshPtrs M, KParams kp,
                                                    const int32_t* __restrict__ pair_s,
@@ -41,43 +61,15 @@ __global__ __launch_bounds__(BSC) __attribute__((amdgpu_waves_per_eu(2))) void k
                                                    const int32_t* __restrict__ mpos,
                                                    const int32_t* __restrict__ posD, const int32_t* __restrict__ posM,
                                                    const double* __restrict__ W_D, const double* __restrict__ W_M,
-                                                   const double* __restrict__ w_g, const double* __restrict__ blk,
-                                                   double* __restrict__ gpair, double* __restrict__ gn0,
-                                                   int64_t stride, Counters* cnt) {
+                                                   const double* __restrict__ w_g, double* __restrict__ gpair,
+                                                   double* __restrict__ gn0, int64_t stride, Counters* cnt) {
   const int64_t p = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * BSC + threadIdx.x;
   unsigned noconv = 0;
   if (p < n_pairs) {
     const int s = pair_s[p];
     const int4 csn = load_conn(S.conn, s);
-    if (DUAL) {
-      // dependence of the dual coefficients on the slave nodes, from the
-      // pair's dual blocks G = WD D^T + WM M^T + wg g^T; parked in the slave
-      // slots of gpair during the sweep (the weights are gathered again for
-      // the sweep rather than kept live through this part)
-      double WD[16], WM[16], wg[4];
-      gather_weights(s, p, csn, posD, n_s, posM, stride, W_D, W_M, w_g, WD, WM, wg);
-      double G[16];
-      dual_gram(WD, WM, wg, blk, stride, p, G);
-      double Xs[4][3], Xd[4][3];
-      load_nodes(S.x, S.y, S.z, csn, Xs);
-#pragma unroll
-      for (int k = 0; k < 4; ++k) Xd[k][0] = Xd[k][1] = Xd[k][2] = 0.0;
-      double n0d[3] = {0.0, 0.0, 0.0};
-      dual_adjoint(Xs, NODAL ? elem_nrm(S, s) : nullptr, G, Xd, n0d);
-#pragma unroll
-      for (int k = 0; k < 4; ++k)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) gpair[(int64_t)(3 * k + d) * stride + p] = Xd[k][d];
-      if (NODAL)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) gn0[(int64_t)d * stride + p] = n0d[d];
-    }
     double WD[16], WM[16], wg[4];
-    {
-      const int s2 = DUAL ? launder(s) : s;
-      const int4 c2 = DUAL ? int4{launder(csn.x), launder(csn.y), launder(csn.z), launder(csn.w)} : csn;
-      gather_weights(s2, p, c2, posD, n_s, posM, stride, W_D, W_M, w_g, WD, WM, wg);
-    }
+    gather_weights(s, p, csn, posD, n_s, posM, stride, W_D, W_M, w_g, WD, WM, wg);
     double Xsb[4][3], Xmb[4][3], n0b[3];
     pair_backward<NQ, DUAL, NODAL>(S, s, csn, M, load_conn(M.conn, pair_m[p]), gpoly(poly, p), poly.nf[p], kp, WD, WM, wg,
                             Xsb, Xmb, n0b, noconv);
@@ -120,8 +112,13 @@ hipError_t launch_pair_bwd(const DeviceMesh& S, const DeviceMesh& M, const KPara
                            : (nodal ? k_pair_bwd<3, false, true> : k_pair_bwd<3, false, false>))
                 : (kp.dual ? (nodal ? k_pair_bwd<7, true, true> : k_pair_bwd<7, true, false>)
                            : (nodal ? k_pair_bwd<7, false, true> : k_pair_bwd<7, false, false>));
+  if (kp.dual) {
+    auto* kd = nodal ? k_pair_dual_adj<true> : k_pair_dual_adj<false>;
+    hipLaunchKernelGGL(kd, dim3(nb), dim3(BSC), 0, s, ms, n_s_el, pair_s, n_pairs, posD, posM, W_D, W_M, w_g, blk,
+                       gpair, gn0, stride);
+  }
   hipLaunchKernelGGL(k, dim3(nb), dim3(BSC), 0, s, ms, n_s_el, mm, kp, pair_s, pair_m, n_pairs, poly, mpos, posD, posM,
-                     W_D, W_M, w_g, blk, gpair, gn0, stride, cnt);
+                     W_D, W_M, w_g, gpair, gn0, stride, cnt);
   return hipGetLastError();
 }
 

@@ -149,6 +149,41 @@ __global__ __launch_bounds__(BSZ) __attribute__((amdgpu_waves_per_eu(3))) void k
   if ((threadIdx.x & 63) == 0 && nc) atomicAdd(&cnt->noconv, nc);
 }
 
+// Upstream weights of pair p of instance I.
+__device__ __forceinline__ void batch_weights(const BatchInst& I, int s, int4 c, int64_t p, double WD[16],
+                                              double WM[16], double wg[4]) {
+#pragma unroll
+  for (int k = 0; k < 16; ++k) WD[k] = I.W_D[I.posD[(int64_t)k * I.n_s_el + s]];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) WM[k] = I.W_M[I.posM[(int64_t)k * I.n_pairs + p]];
+  wg[0] = I.w_g[c.x];
+  wg[1] = I.w_g[c.y];
+  wg[2] = I.w_g[c.z];
+  wg[3] = I.w_g[c.w];
+}
+
+// Dual basis: gradient through the dual coefficients of every pair, from its
+// dual blocks (computed by the forward launch that precedes this one), into
+// the slave slots of gpair before the sweep (a launch of its own, so that its
+// registers do not add to those of the sweep).
+template <int BSZ, bool NODAL>
+__global__ __launch_bounds__(BSZ) __attribute__((amdgpu_waves_per_eu(2))) void k_batch_dual_adj(
+    const BatchInst* __restrict__ inst, const WorkItem* __restrict__ items, const int32_t* __restrict__ qbeg,
+    int32_t* qnext, Counters* cnt) {
+  int qi = 0;
+  for (int it = next_item(qbeg, qnext, qi); it >= 0; it = next_item(qbeg, qnext, qi)) {
+    const WorkItem w = items[it];
+    const BatchInst& I = inst[w.inst];
+    for (int64_t p = w.begin + (int)(threadIdx.x & 63); p < w.end; p += 64) {
+      const int s = I.pair_s[p];
+      const int4 csn = load_conn(I.S.conn, s);
+      double WD[16], WM[16], wg[4];
+      batch_weights(I, s, csn, p, WD, WM, wg);
+      pair_dual_adjoint<NODAL>(I.S, s, csn, WD, WM, wg, I.blk, I.n_pairs, p, I.gpair, I.gn0);
+    }
+  }
+}
+
 template <int BSZ, int NQ, bool DUAL, bool NODAL>
 __global__ __launch_bounds__(BSZ) __attribute__((amdgpu_waves_per_eu(2))) void k_batch_bwd(const BatchInst* __restrict__ inst,
                                                     const WorkItem* __restrict__ items,
@@ -162,42 +197,8 @@ __global__ __launch_bounds__(BSZ) __attribute__((amdgpu_waves_per_eu(2))) void k
     for (int64_t p = w.begin + (int)(threadIdx.x & 63); p < w.end; p += 64) {
       const int s = I.pair_s[p];
       const int4 csn = load_conn(I.S.conn, s);
-      auto gather = [&](int se, int4 c, double WD[16], double WM[16], double wg[4]) {
-#pragma unroll
-        for (int k = 0; k < 16; ++k) WD[k] = I.W_D[I.posD[(int64_t)k * I.n_s_el + se]];
-#pragma unroll
-        for (int k = 0; k < 16; ++k) WM[k] = I.W_M[I.posM[(int64_t)k * st + p]];
-        wg[0] = I.w_g[c.x];
-        wg[1] = I.w_g[c.y];
-        wg[2] = I.w_g[c.z];
-        wg[3] = I.w_g[c.w];
-      };
-      if (DUAL) {
-        // gradient through the dual coefficients, from the pair's dual
-        // blocks (computed by the forward launch that precedes this one);
-        // parked in the slave slots of gpair during the sweep
-        double WD[16], WM[16], wg[4], G[16];
-        gather(s, csn, WD, WM, wg);
-        dual_gram(WD, WM, wg, I.blk, st, p, G);
-        double Xs[4][3], Xd[4][3], n0d[3] = {0.0, 0.0, 0.0};
-        load_nodes(I.S.x, I.S.y, I.S.z, csn, Xs);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) Xd[k][0] = Xd[k][1] = Xd[k][2] = 0.0;
-        dual_adjoint(Xs, NODAL ? elem_nrm(I.S, s) : nullptr, G, Xd, n0d);
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-#pragma unroll
-          for (int d = 0; d < 3; ++d) I.gpair[(int64_t)(3 * k + d) * st + p] = Xd[k][d];
-        if (NODAL)
-#pragma unroll
-          for (int d = 0; d < 3; ++d) I.gn0[(int64_t)d * st + p] = n0d[d];
-      }
       double WD[16], WM[16], wg[4];
-      {
-        const int s2 = DUAL ? launder(s) : s;
-        const int4 c2 = DUAL ? int4{launder(csn.x), launder(csn.y), launder(csn.z), launder(csn.w)} : csn;
-        gather(s2, c2, WD, WM, wg);
-      }
+      batch_weights(I, s, csn, p, WD, WM, wg);
       double Xsb[4][3], Xmb[4][3], n0b[3];
       pair_backward<NQ, DUAL, NODAL>(I.S, s, csn, I.M, load_conn(I.M.conn, I.pair_m[p]), gpoly(I.poly, p),
                                      I.poly.nf[p], I.kp, WD, WM, wg, Xsb, Xmb, n0b, noconv);
@@ -274,6 +275,11 @@ FwdFn pick_fwd(int bsz, int nq, bool dual) {
   if (bsz == 256) return fwd_kernel<256>(nq, dual);
   if (bsz == 128) return fwd_kernel<128>(nq, dual);
   return fwd_kernel<64>(nq, dual);
+}
+BwdFn pick_dual(int bsz, bool nodal) {
+  if (bsz == 256) return nodal ? k_batch_dual_adj<256, true> : k_batch_dual_adj<256, false>;
+  if (bsz == 128) return nodal ? k_batch_dual_adj<128, true> : k_batch_dual_adj<128, false>;
+  return nodal ? k_batch_dual_adj<64, true> : k_batch_dual_adj<64, false>;
 }
 BwdFn pick_bwd(int bsz, int nq, bool dual, bool nodal) {
   if (nodal) {
@@ -443,6 +449,15 @@ int launch_bwd_all(mt_batch* b, hipStream_t st) {
     if (rc) return rc;
   }
   const int bsz = b->tune.block;
+  if (b->dual) {
+    BwdFn fd = pick_dual(bsz, b->nodal);
+    const int gd = b->num_cu * resident_blocks(reinterpret_cast<const void*>(fd), bsz);
+    k_reset_queues<<<1, 64, 0, st>>>(b->d_qnext.as<int32_t>());
+    B_HIP(hipGetLastError());
+    hipLaunchKernelGGL(fd, dim3(gd), dim3(bsz), 0, st, b->d_inst.as<BatchInst>(), b->d_pitems.as<WorkItem>(),
+                       b->d_qbeg.as<int32_t>(), b->d_qnext.as<int32_t>(), b->counters.as<Counters>());
+    B_HIP(hipGetLastError());
+  }
   BwdFn f = pick_bwd(bsz, b->nq, b->dual, b->nodal);
   const int grid = b->num_cu * resident_blocks(reinterpret_cast<const void*>(f), bsz);
   k_reset_queues<<<1, 64, 0, st>>>(b->d_qnext.as<int32_t>());

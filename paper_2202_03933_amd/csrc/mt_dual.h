@@ -152,4 +152,30 @@ __device__ __forceinline__ void dual_gram(const double WD[16], const double WM[1
     }
 }
 
+// The dual-coefficient part of pair p's gradient, written to the slave
+// slots of gpair[c * stride + p] (and, with the continuous normal field, the
+// plane-normal part to gn0[d * stride + p]); the sweep adds its own terms
+// there afterwards.  WD, WM, wg = the pair's upstream weights.
+template <bool NODAL>
+__device__ __forceinline__ void pair_dual_adjoint(const MeshPtrs& S, int s, int4 csn, const double WD[16],
+                                                  const double WM[16], const double wg[4],
+                                                  const double* __restrict__ blk, int64_t stride, int64_t p,
+                                                  double* __restrict__ gpair, double* __restrict__ gn0) {
+  double G[16];
+  dual_gram(WD, WM, wg, blk, stride, p, G);
+  double Xs[4][3], Xd[4][3];
+  load_nodes(S.x, S.y, S.z, csn, Xs);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) Xd[k][0] = Xd[k][1] = Xd[k][2] = 0.0;
+  double n0d[3] = {0.0, 0.0, 0.0};
+  dual_adjoint(Xs, NODAL ? elem_nrm(S, s) : nullptr, G, Xd, n0d);
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) gpair[(int64_t)(3 * k + d) * stride + p] = Xd[k][d];
+  if (NODAL)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) gn0[(int64_t)d * stride + p] = n0d[d];
+}
+
 }  // namespace mt
