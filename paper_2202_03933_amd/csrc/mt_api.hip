@@ -165,7 +165,7 @@ int mt_destroy(mt_ctx* c) {
                  &c->keys_tmp, &c->vals_tmp, &c->cell_range, &c->sbox, &c->cand_cnt, &c->cand_tmp, &c->cand_off,
                  &c->cand_s, &c->cand_m, &c->cand_nv, &c->cand_flag, &c->scr_cnt, &c->scr_off, &c->pair_s, &c->pair_m,
                  &c->pair_nv, &c->pair_off, &c->inc_cnt, &c->inc_off, &c->inc_cur, &c->inc_list, &c->minc_cnt,
-                 &c->minc_off, &c->minc_cur, &c->minc_list, &c->pat_keep, &c->D_cnt, &c->D_rowptr, &c->D_col, &c->M_cnt, &c->M_rowptr,
+                 &c->minc_off, &c->minc_cur, &c->minc_list, &c->pat_keep, &c->pat_ecnt, &c->pat_elist, &c->D_cnt, &c->D_rowptr, &c->D_col, &c->M_cnt, &c->M_rowptr,
                  &c->M_col, &c->posD, &c->posM, &c->poly_u, &c->poly_v, &c->poly_lab, &c->poly_nf, &c->maybe_list,
                  &c->maybe_flag, &c->maybe_scan, &c->mpoly_u, &c->mpoly_v, &c->mpoly_lab, &c->mpoly_nf, &c->blk, &c->gpair, &c->nrm_node, &c->nrm_el, &c->gn0, &c->nrm_sb, &c->nrm_ub, &c->nrm_cg, &c->aux_hist, &c->aux_scan, &c->mp_keys, &c->mp_vals, &c->mp_off, &c->mp_pos,
                  &c->scan_tmp, &c->sort_hist, &c->host_tmp};
@@ -531,6 +531,8 @@ int mt_csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, void* stream) {
     return fail(MT_ECAPACITY, "mt_csr_pattern: more than 2^31 block entries");
   int32_t tot[2] = {0, 0};
   MT_HIP(ensure(c->pat_keep, sizeof(int32_t) * (size_t)pattern_keep_per_row() * (size_t)std::max(n, 1)));
+  MT_HIP(ensure(c->pat_ecnt, sizeof(int32_t) * (size_t)std::max(S.n_el, 1)));
+  MT_HIP(ensure(c->pat_elist, sizeof(int32_t) * (size_t)pattern_elem_list() * (size_t)std::max(S.n_el, 1)));
   MT_HIP(ensure(c->D_cnt, sizeof(int32_t) * ((size_t)n + 1)));
   MT_HIP(ensure(c->M_cnt, sizeof(int32_t) * ((size_t)n + 1)));
   MT_HIP(ensure(c->D_rowptr, sizeof(int32_t) * ((size_t)n + 1)));
@@ -538,7 +540,7 @@ int mt_csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, void* stream) {
   MT_HIP(launch_pattern_rows(false, c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(), n, c->pair_off.as<int32_t>(),
                              c->pair_m.as<int32_t>(), S.conn, M.conn, c->D_cnt.as<int32_t>(), c->M_cnt.as<int32_t>(),
                              nullptr, nullptr, nullptr, nullptr, c->pat_keep.as<int32_t>(), nullptr, S.n_el, nullptr,
-                             c->n_pairs, st));
+                             c->n_pairs, c->pat_ecnt.as<int32_t>(), c->pat_elist.as<int32_t>(), st));
   MT_HIP(scan_exclusive(c->D_cnt.as<int32_t>(), c->D_rowptr.as<int32_t>(), n, c->scan_tmp, st));
   MT_HIP(scan_exclusive(c->M_cnt.as<int32_t>(), c->M_rowptr.as<int32_t>(), n, c->scan_tmp, st));
   MT_HIP(hipMemcpyAsync(&tot[0], c->D_rowptr.as<int32_t>() + n, 4, hipMemcpyDeviceToHost, st));
@@ -554,7 +556,7 @@ int mt_csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, void* stream) {
   MT_HIP(launch_pattern_rows(true, c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(), n, c->pair_off.as<int32_t>(),
                              c->pair_m.as<int32_t>(), S.conn, M.conn, nullptr, nullptr, c->D_rowptr.as<int32_t>(), c->M_rowptr.as<int32_t>(), c->D_col.as<int32_t>(),
                              c->M_col.as<int32_t>(), c->pat_keep.as<int32_t>(), c->posD.as<int32_t>(), S.n_el,
-                             c->posM.as<int32_t>(), c->n_pairs, st));
+                             c->posM.as<int32_t>(), c->n_pairs, nullptr, nullptr, st));
   if (aux) MT_HIP(hipStreamWaitEvent(st, c->aux_join, 0));
   c->have_pattern = true;
   ++c->pattern_gen;

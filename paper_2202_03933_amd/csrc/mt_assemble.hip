@@ -126,6 +126,72 @@ __device__ __forceinline__ int row_columns_scan(int a, const int32_t* __restrict
   }
 }
 
+// Sorted, duplicate-free master nodes of the pairs of each slave element
+// (the element's contribution to the M rows of its four nodes), in the
+// lane-interleaved list elist[k * n_el + e], k < ecnt[e]; ecnt[e] = -1 when
+// there are more than EL of them.
+constexpr int EL = 16;
+
+__global__ __launch_bounds__(BS) void k_elem_mlist(int32_t n_el, const int32_t* __restrict__ pair_off,
+                                                    const int32_t* __restrict__ pair_m,
+                                                    const int32_t* __restrict__ conn_m, int32_t* __restrict__ ecnt,
+                                                    int32_t* __restrict__ elist) {
+  __shared__ int32_t lds[EL * BS];
+  const int e = xcd_tile(blockIdx.x, gridDim.x) * BS + threadIdx.x;
+  if (e >= n_el) return;
+  int32_t* v = lds + threadIdx.x;
+  int u = 0;
+  for (int p = pair_off[e]; p < pair_off[e + 1] && u >= 0; ++p) {
+    const int4 q = reinterpret_cast<const int4*>(conn_m)[pair_m[p]];
+    u = insert_unique(v, u, q.x, BS, EL);
+    if (u >= 0) u = insert_unique(v, u, q.y, BS, EL);
+    if (u >= 0) u = insert_unique(v, u, q.z, BS, EL);
+    if (u >= 0) u = insert_unique(v, u, q.w, BS, EL);
+  }
+  ecnt[e] = u;
+  for (int k = 0; k < u; ++k) elist[(int64_t)k * n_el + e] = v[k * BS];
+}
+
+// M row of node a as the merge of the sorted lists of its (at most ROW_RUNS)
+// incident elements: the row length, with the first kcap columns written to
+// keep[i * n] (lane-interleaved).  Returns -1 (nothing written) when a list
+// is missing (ecnt < 0) or the node has more than ROW_RUNS elements.
+__device__ __forceinline__ int merge_mrow(int a, int32_t n, const int32_t* __restrict__ inc_off,
+                                          const int32_t* __restrict__ inc_list, int32_t n_el,
+                                          const int32_t* __restrict__ ecnt, const int32_t* __restrict__ elist,
+                                          int32_t* keep, int kcap) {
+  constexpr int NONE = 0x7fffffff;
+  const int i0 = inc_off[a], ni = inc_off[a + 1] - i0;
+  if (ni > ROW_RUNS) return -1;
+  int el[ROW_RUNS], len[ROW_RUNS], cur[ROW_RUNS], head[ROW_RUNS];
+#pragma unroll
+  for (int t = 0; t < ROW_RUNS; ++t) {
+    el[t] = t < ni ? inc_list[i0 + t] >> 2 : 0;
+    len[t] = t < ni ? ecnt[el[t]] : 0;
+  }
+#pragma unroll
+  for (int t = 0; t < ROW_RUNS; ++t)
+    if (len[t] < 0) return -1;
+#pragma unroll
+  for (int t = 0; t < ROW_RUNS; ++t) {
+    cur[t] = 0;
+    head[t] = len[t] > 0 ? elist[el[t]] : NONE;
+  }
+  int u = 0;
+  while (true) {
+    const int m = min(min(head[0], head[1]), min(head[2], head[3]));
+    if (m == NONE) return u;
+    if (u < kcap) keep[(int64_t)u * n] = m;
+    ++u;
+#pragma unroll
+    for (int t = 0; t < ROW_RUNS; ++t)
+      if (head[t] == m) {
+        ++cur[t];
+        head[t] = cur[t] < len[t] ? elist[(int64_t)cur[t] * n_el + el[t]] : NONE;
+      }
+  }
+}
+
 // Row patterns of D and M.  Each thread builds its row's sorted column list
 // in a lane-interleaved LDS segment of PCAP entries; a row that outgrows it
 // is counted, and in the fill pass written, by row_columns_scan.  The count
@@ -265,7 +331,9 @@ __global__ __launch_bounds__(PB) void k_pattern_rows(const int32_t* __restrict__
                                                       const int32_t* __restrict__ D_rowptr,
                                                       const int32_t* __restrict__ M_rowptr, int32_t* D_col,
                                                       int32_t* M_col, int32_t* keepD, int32_t* keepM,
-                                                      int32_t* posD, int32_t n_el, int32_t* posM, int64_t np) {
+                                                      int32_t* posD, int32_t n_el, int32_t* posM, int64_t np,
+                                                      const int32_t* __restrict__ ecnt,
+                                                      const int32_t* __restrict__ elist) {
   __shared__ int32_t lds[PCAP * PB];
   const int a = xcd_tile(blockIdx.x, gridDim.x) * PB + threadIdx.x;
   if (a >= n) return;
@@ -277,7 +345,14 @@ __global__ __launch_bounds__(PB) void k_pattern_rows(const int32_t* __restrict__
   else
     pattern_row<FILL, false>(a, n, seg, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m, D_cnt, D_rowptr, D_col,
                              keepD + a, KD, posD, n_el);
-  // M row
+  // M row (count pass: merge of the element lists when they exist)
+  if (!FILL && ecnt) {
+    const int u = merge_mrow(a, n, inc_off, inc_list, n_el, ecnt, elist, keepM + a, KM);
+    if (u >= 0) {
+      M_cnt[a] = u;
+      return;
+    }
+  }
   if (FILL && M_rowptr[a + 1] - M_rowptr[a] <= KM)
     kept_row<true>(a, n, M_rowptr[a + 1] - M_rowptr[a], keepM, seg, M_rowptr, M_col, inc_off, inc_list, pair_off,
                    pair_m, conn_s, conn_m, posM, np);
@@ -371,23 +446,27 @@ hipError_t launch_pattern_rows(bool fill, const int32_t* inc_off, const int32_t*
                                const int32_t* pair_off, const int32_t* pair_m, const int32_t* conn_s,
                                const int32_t* conn_m, int32_t* D_cnt, int32_t* M_cnt, const int32_t* D_rowptr,
                                const int32_t* M_rowptr, int32_t* D_col, int32_t* M_col, int32_t* keep, int32_t* posD,
-                               int32_t n_s_el, int32_t* posM, int64_t n_pairs, hipStream_t s) {
+                               int32_t n_s_el, int32_t* posM, int64_t n_pairs, int32_t* ecnt, int32_t* elist,
+                               hipStream_t s) {
   if (n_nodes == 0) return hipSuccess;
+  if (!fill && n_s_el > 0)
+    k_elem_mlist<<<xcd_grid(grid_of(n_s_el)), BS, 0, s>>>(n_s_el, pair_off, pair_m, conn_m, ecnt, elist);
   const unsigned g = xcd_grid((unsigned)((n_nodes + PB - 1) / PB));
   int32_t* keepD = keep;
   int32_t* keepM = keep + (int64_t)KD * n_nodes;
   if (fill)
     k_pattern_rows<true><<<g, PB, 0, s>>>(inc_off, inc_list, n_nodes, pair_off, pair_m, conn_s, conn_m, D_cnt, M_cnt,
                                           D_rowptr, M_rowptr, D_col, M_col, keepD, keepM, posD, n_s_el, posM,
-                                          n_pairs);
+                                          n_pairs, nullptr, nullptr);
   else
     k_pattern_rows<false><<<g, PB, 0, s>>>(inc_off, inc_list, n_nodes, pair_off, pair_m, conn_s, conn_m, D_cnt,
                                            M_cnt, D_rowptr, M_rowptr, D_col, M_col, keepD, keepM, posD, n_s_el, posM,
-                                           n_pairs);
+                                           n_pairs, ecnt, elist);
   return hipGetLastError();
 }
 
 int pattern_keep_per_row() { return KD + KM; }
+int pattern_elem_list() { return EL; }
 
 hipError_t launch_assemble(const int32_t* inc_off, const int32_t* inc_list, int32_t n_nodes, const int32_t* pair_off,
                            const int32_t* D_rowptr, const int32_t* M_rowptr, const int32_t* posD, int32_t n_s_el,

@@ -149,6 +149,8 @@ struct mt_ctx {
   mt::Buf inc_cnt, inc_off, inc_cur, inc_list;     // slave node -> (element*4 + local)
   mt::Buf minc_cnt, minc_off, minc_cur, minc_list; // master node -> (element*4 + local)
   mt::Buf pat_keep;        // per-row column lists kept between the pattern passes
+  mt::Buf pat_ecnt;        // int32 [n_s_el] master nodes of each slave element's pairs (-1: too many)
+  mt::Buf pat_elist;       // int32 [EL][n_s_el] those master nodes, sorted
   mt::Buf D_cnt, D_rowptr, D_col;
   mt::Buf M_cnt, M_rowptr, M_col;
   mt::Buf posD;            // [16][n_s_el]
@@ -250,8 +252,10 @@ hipError_t launch_pattern_rows(bool fill, const int32_t* inc_off, const int32_t*
                                const int32_t* pair_off, const int32_t* pair_m, const int32_t* conn_s,
                                const int32_t* conn_m, int32_t* D_cnt, int32_t* M_cnt, const int32_t* D_rowptr,
                                const int32_t* M_rowptr, int32_t* D_col, int32_t* M_col, int32_t* keep, int32_t* posD,
-                               int32_t n_s_el, int32_t* posM, int64_t n_pairs, hipStream_t s);
+                               int32_t n_s_el, int32_t* posM, int64_t n_pairs, int32_t* ecnt, int32_t* elist,
+                               hipStream_t s);
 int pattern_keep_per_row();
+int pattern_elem_list();
 hipError_t launch_assemble(const int32_t* inc_off, const int32_t* inc_list, int32_t n_nodes,
                            const int32_t* pair_off, const int32_t* D_rowptr, const int32_t* M_rowptr,
                            const int32_t* posD, int32_t n_s_el, const int32_t* posM, const double* blk,
