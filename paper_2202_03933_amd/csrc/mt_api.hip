@@ -166,7 +166,7 @@ int mt_destroy(mt_ctx* c) {
                  &c->cand_s, &c->cand_m, &c->cand_nv, &c->cand_flag, &c->scr_cnt, &c->scr_off, &c->pair_s, &c->pair_m,
                  &c->pair_nv, &c->pair_off, &c->inc_cnt, &c->inc_off, &c->inc_cur, &c->inc_list, &c->minc_cnt,
                  &c->minc_off, &c->minc_cur, &c->minc_list, &c->pat_keep, &c->pat_ecnt, &c->pat_elist, &c->D_cnt, &c->D_rowptr, &c->D_col, &c->M_cnt, &c->M_rowptr,
-                 &c->M_col, &c->posD, &c->posM, &c->poly_u, &c->poly_v, &c->poly_lab, &c->poly_nf, &c->maybe_list,
+                 &c->M_col, &c->posD, &c->posM, &c->pair_slot, &c->maybe_list,
                  &c->maybe_flag, &c->maybe_scan, &c->mpoly_u, &c->mpoly_v, &c->mpoly_lab, &c->mpoly_nf, &c->blk, &c->gpair, &c->nrm_node, &c->nrm_el, &c->gn0, &c->nrm_sb, &c->nrm_ub, &c->nrm_cg, &c->aux_hist, &c->aux_scan, &c->mp_keys, &c->mp_vals, &c->mp_off, &c->mp_pos,
                  &c->scan_tmp, &c->sort_hist, &c->host_tmp};
   for (Buf* b : bufs) release(*b);
@@ -356,8 +356,9 @@ int mt_build_pairs(mt_ctx* c, int64_t* n_cand_out, int64_t* n_pairs_out, void* s
   MT_HIP(ensure(c->mpoly_v, sizeof(double) * CAP0 * nmb));
   MT_HIP(ensure(c->mpoly_lab, CAP0 * nmb));
   MT_HIP(ensure(c->mpoly_nf, nmb));
+  c->mpoly_stride = (int64_t)nmb;
   const PolyBuf mpoly{c->mpoly_u.as<double>(), c->mpoly_v.as<double>(), c->mpoly_lab.as<uint8_t>(),
-                      c->mpoly_nf.as<uint8_t>(), (int64_t)nmb};
+                      c->mpoly_nf.as<uint8_t>(), (int64_t)nmb, nullptr};
   {
     PhaseTimer t(c, MT_T_COMPACT, st);
     MT_HIP(launch_maybe_list(c->cand_flag.as<int32_t>(), c->cand_off.as<int32_t>(), c->scr_off.as<int32_t>(), ns,
@@ -382,20 +383,17 @@ int mt_build_pairs(mt_ctx* c, int64_t* n_cand_out, int64_t* n_pairs_out, void* s
   MT_HIP(ensure(c->pair_s, sizeof(int32_t) * (size_t)n_pairs));
   MT_HIP(ensure(c->pair_m, sizeof(int32_t) * (size_t)n_pairs));
   MT_HIP(ensure(c->pair_nv, (size_t)n_pairs));
+  MT_HIP(ensure(c->pair_slot, sizeof(int32_t) * (size_t)std::max<int64_t>(n_pairs, 1)));
   MT_HIP(ensure(c->pair_off, sizeof(int32_t) * ((size_t)ns + 1)));
   c->n_cand = n_cand;
   c->n_maybe = n_maybe;
   c->n_pairs = n_pairs;
   {
-    int rc = ensure_poly(c);
-    if (rc) return rc;
-  }
-  {
     PhaseTimer t(c, MT_T_COMPACT, st);
     MT_HIP(launch_compact_pairs(c->cand_s.as<int32_t>(), c->cand_m.as<int32_t>(), c->maybe_list.as<int32_t>(),
-                                c->maybe_flag.as<int32_t>(), c->maybe_scan.as<int32_t>(), n_maybe, mpoly,
-                                c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), c->pair_nv.as<uint8_t>(),
-                                poly_buf(c), st));
+                                c->maybe_flag.as<int32_t>(), c->maybe_scan.as<int32_t>(), n_maybe,
+                                c->mpoly_nf.as<uint8_t>(), c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(),
+                                c->pair_nv.as<uint8_t>(), c->pair_slot.as<int32_t>(), st));
     MT_HIP(launch_pair_off(c->scr_off.as<int32_t>(), c->maybe_scan.as<int32_t>(), ns, c->pair_off.as<int32_t>(), st));
   }
   c->poly_gen = c->coord_gen;
@@ -635,18 +633,18 @@ __global__ void k_iota(uint32_t* v, int64_t n) {
 
 }  // extern "C"
 
+// The pair polygons live in the screened-candidate polygon buffer of the
+// last mt_build_pairs (pair p at entry pair_slot[p]); it holds an entry for
+// every pair, also when the polygons are recomputed for new coordinates.
 int mt::ensure_poly(mt_ctx* c) {
-  const size_t np = (size_t)std::max<int64_t>(c->n_pairs, 1);
-  MT_HIP(ensure(c->poly_u, sizeof(double) * CAP0 * np));
-  MT_HIP(ensure(c->poly_v, sizeof(double) * CAP0 * np));
-  MT_HIP(ensure(c->poly_lab, CAP0 * np));
-  MT_HIP(ensure(c->poly_nf, np));
+  if (c->n_pairs > 0 && (!c->pair_slot.p || !c->mpoly_nf.p))
+    return fail(MT_ESTATE, "pair polygons: build the pair list first");
   return MT_OK;
 }
 
 mt::PolyBuf mt::poly_buf(mt_ctx* c) {
-  return PolyBuf{c->poly_u.as<double>(), c->poly_v.as<double>(), c->poly_lab.as<uint8_t>(), c->poly_nf.as<uint8_t>(),
-                 std::max<int64_t>(c->n_pairs, 1)};
+  return PolyBuf{c->mpoly_u.as<double>(), c->mpoly_v.as<double>(), c->mpoly_lab.as<uint8_t>(),
+                 c->mpoly_nf.as<uint8_t>(), c->mpoly_stride, c->pair_slot.as<int32_t>()};
 }
 
 int mt::ensure_master_index(mt_ctx* c, hipStream_t st) {

@@ -71,7 +71,7 @@ __global__ __launch_bounds__(BSC) __attribute__((amdgpu_waves_per_eu(2))) void k
     double WD[16], WM[16], wg[4];
     gather_weights(s, p, csn, posD, n_s, posM, stride, W_D, W_M, w_g, WD, WM, wg);
     double Xsb[4][3], Xmb[4][3], n0b[3];
-    pair_backward<NQ, DUAL, NODAL>(S, s, csn, M, load_conn(M.conn, pair_m[p]), gpoly(poly, p), poly.nf[p], kp, WD, WM, wg,
+    pair_backward<NQ, DUAL, NODAL>(S, s, csn, M, load_conn(M.conn, pair_m[p]), gpoly(poly, p), gpoly_nf(poly, p), kp, WD, WM, wg,
                             Xsb, Xmb, n0b, noconv);
     if (NODAL)
 #pragma unroll

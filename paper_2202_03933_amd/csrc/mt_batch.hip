@@ -135,7 +135,7 @@ __global__ __launch_bounds__(BSZ) __attribute__((amdgpu_waves_per_eu(3))) void k
       double D[16], Mv[16], g[4];
       const int s = I.pair_s[p];
       pair_forward<NQ, DUAL>(I.S, s, load_conn(I.S.conn, s), I.M, load_conn(I.M.conn, I.pair_m[p]),
-                             gpoly(I.poly, p), I.poly.nf[p], I.kp, D, Mv, g, noconv);
+                             gpoly(I.poly, p), gpoly_nf(I.poly, p), I.kp, D, Mv, g, noconv);
       const int64_t st = I.n_pairs;
 #pragma unroll
       for (int k = 0; k < 16; ++k) I.blk[(int64_t)k * st + p] = D[k];
@@ -201,7 +201,7 @@ __global__ __launch_bounds__(BSZ) __attribute__((amdgpu_waves_per_eu(2))) void k
       batch_weights(I, s, csn, p, WD, WM, wg);
       double Xsb[4][3], Xmb[4][3], n0b[3];
       pair_backward<NQ, DUAL, NODAL>(I.S, s, csn, I.M, load_conn(I.M.conn, I.pair_m[p]), gpoly(I.poly, p),
-                                     I.poly.nf[p], I.kp, WD, WM, wg, Xsb, Xmb, n0b, noconv);
+                                     gpoly_nf(I.poly, p), I.kp, WD, WM, wg, Xsb, Xmb, n0b, noconv);
       if (NODAL)
 #pragma unroll
         for (int d = 0; d < 3; ++d) {

@@ -78,6 +78,8 @@ struct PolyBuf {
   uint8_t* lab;
   uint8_t* nf;
   int64_t stride;
+  const int32_t* slot;  // entry of pair p: slot[p] (nullptr: entry p)
+  __host__ __device__ __forceinline__ int64_t at(int64_t p) const { return slot ? (int64_t)slot[p] : p; }
 };
 
 struct KParams {
@@ -141,6 +143,7 @@ struct mt_ctx {
   mt::Buf maybe_flag;      // int32 [n_maybe + 1] 1 = pair
   mt::Buf maybe_scan;      // int32 [n_maybe + 1] exclusive scan of maybe_flag
   mt::Buf mpoly_u, mpoly_v, mpoly_lab, mpoly_nf;  // their clip polygons (PolyBuf layout)
+  int64_t mpoly_stride = 1;
   // pairs
   mt::Buf pair_s, pair_m;  // [n_pairs]
   mt::Buf pair_nv;         // uint8 [n_pairs]
@@ -157,9 +160,7 @@ struct mt_ctx {
   mt::Buf posM;            // [16][n_pairs]
   // clip polygons of the pairs (mt::PolyBuf); valid for the coordinates of
   // generation poly_gen (coord_gen counts coordinate and pair-list changes)
-  mt::Buf poly_u, poly_v;  // [CAP0][n_pairs]
-  mt::Buf poly_lab;        // uint8 [CAP0][n_pairs]
-  mt::Buf poly_nf;         // uint8 [n_pairs]
+  mt::Buf pair_slot;       // int32 [n_pairs] entry of each pair's polygon in the mpoly buffers
   int64_t coord_gen = 0, poly_gen = -1;
   int64_t pattern_gen = 0;  // counts completed mt_csr_pattern calls
   // forward / backward staging
@@ -224,8 +225,8 @@ hipError_t launch_clip_screened(const double* mdata, const double* sdata, int32_
                                 const int32_t* cand_s, const int32_t* cand_m, const int32_t* mlist, int64_t n_maybe,
                                 uint8_t* nv, int32_t* flag2, const PolyBuf& out, Counters* cnt, hipStream_t s);
 hipError_t launch_compact_pairs(const int32_t* cand_s, const int32_t* cand_m, const int32_t* mlist,
-                                const int32_t* flag2, const int32_t* scan2, int64_t n_maybe, const PolyBuf& src,
-                                int32_t* pair_s, int32_t* pair_m, uint8_t* pair_nv, const PolyBuf& dst,
+                                const int32_t* flag2, const int32_t* scan2, int64_t n_maybe, const uint8_t* nf,
+                                int32_t* pair_s, int32_t* pair_m, uint8_t* pair_nv, int32_t* pair_slot,
                                 hipStream_t s);
 hipError_t launch_pair_off(const int32_t* scr_off, const int32_t* scan2, int32_t n_s, int32_t* pair_off,
                            hipStream_t s);

@@ -55,7 +55,11 @@ struct GPoly {
   __device__ __forceinline__ uint8_t L(int i) const { return l[(int64_t)i * stride + p]; }
 };
 
-__device__ __forceinline__ GPoly gpoly(const PolyBuf& b, int64_t p) { return GPoly{b.u, b.v, b.lab, b.stride, p}; }
+// Polygon of pair p (at its entry of the buffer).
+__device__ __forceinline__ GPoly gpoly(const PolyBuf& b, int64_t p) {
+  return GPoly{b.u, b.v, b.lab, b.stride, b.at(p)};
+}
+__device__ __forceinline__ uint8_t gpoly_nf(const PolyBuf& b, int64_t p) { return b.nf[b.at(p)]; }
 
 // Copies a clip polygon (n vertices in LDS buffer res) and its provenance to
 // entry idx of a polygon buffer.
@@ -81,7 +85,7 @@ __device__ __forceinline__ void store_pair_polygon(const double Xs[4][3], const 
   int res, st;
   bool flip;
   const int n = pair_geometry<true>(Xs, Xm, f, kp.eps_d, kp.eps_a, S, Mn, hs, hm, flip, P, res, st);
-  poly_store(P, res, n, flip, out, p);
+  poly_store(P, res, n, flip, out, out.at(p));
 }
 
 // Projected nodes and heights of both elements on the slave plane f.

@@ -106,30 +106,25 @@ __global__ __launch_bounds__(BS) void k_nv_hist(const uint8_t* __restrict__ nv, 
   if (threadIdx.x < 17 && h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], (unsigned long long)h[threadIdx.x]);
 }
 
-// Pair list and pair polygons from the screened candidates that are pairs.
+// Pair list from the screened candidates that are pairs; each pair's polygon
+// stays where the clip stored it (entry slot[p] of the screened-candidate
+// polygon buffer).
 __global__ __launch_bounds__(BS) void k_compact_pairs(const int32_t* __restrict__ cand_s,
                                                        const int32_t* __restrict__ cand_m,
                                                        const int32_t* __restrict__ mlist,
                                                        const int32_t* __restrict__ flag2,
                                                        const int32_t* __restrict__ scan2, int64_t n_maybe,
-                                                       PolyBuf src, int32_t* __restrict__ ps,
+                                                       const uint8_t* __restrict__ nf, int32_t* __restrict__ ps,
                                                        int32_t* __restrict__ pm, uint8_t* __restrict__ pnv,
-                                                       PolyBuf dst) {
+                                                       int32_t* __restrict__ slot) {
   const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
   if (i >= n_maybe || !flag2[i]) return;
   const int64_t p = scan2[i];
   const int c = mlist[i];
   ps[p] = cand_s[c];
   pm[p] = cand_m[c];
-  const uint8_t nf = src.nf[i];
-  const int n = nf & 0x7f;
-  pnv[p] = (uint8_t)n;
-  dst.nf[p] = nf;
-  for (int k = 0; k < n; ++k) {
-    dst.u[(int64_t)k * dst.stride + p] = src.u[(int64_t)k * src.stride + i];
-    dst.v[(int64_t)k * dst.stride + p] = src.v[(int64_t)k * src.stride + i];
-    dst.lab[(int64_t)k * dst.stride + p] = src.lab[(int64_t)k * src.stride + i];
-  }
+  pnv[p] = (uint8_t)(nf[i] & 0x7f);
+  slot[p] = (int32_t)i;
 }
 
 // First pair of each slave element: pairs among the screened candidates
@@ -177,7 +172,7 @@ __global__ __launch_bounds__(BSC) __attribute__((amdgpu_waves_per_eu(3))) void k
     double D[16], Mv[16], g[4];
     const int s = pair_s[p];
     pair_forward<NQ, DUAL>(S, s, load_conn(S.conn, s), M, load_conn(M.conn, pair_m[p]), gpoly(poly, p),
-                           poly.nf[p], kp, D, Mv, g, noconv);
+                           gpoly_nf(poly, p), kp, D, Mv, g, noconv);
 #pragma unroll
     for (int k = 0; k < 16; ++k) blk[(int64_t)k * stride + p] = D[k];
 #pragma unroll
@@ -215,12 +210,12 @@ hipError_t launch_clip_screened(const double* mdata, const double* sdata, int32_
 }
 
 hipError_t launch_compact_pairs(const int32_t* cand_s, const int32_t* cand_m, const int32_t* mlist,
-                                const int32_t* flag2, const int32_t* scan2, int64_t n_maybe, const PolyBuf& src,
-                                int32_t* pair_s, int32_t* pair_m, uint8_t* pair_nv, const PolyBuf& dst,
+                                const int32_t* flag2, const int32_t* scan2, int64_t n_maybe, const uint8_t* nf,
+                                int32_t* pair_s, int32_t* pair_m, uint8_t* pair_nv, int32_t* pair_slot,
                                 hipStream_t s) {
   if (n_maybe == 0) return hipSuccess;
   k_compact_pairs<<<(unsigned)((n_maybe + BS - 1) / BS), BS, 0, s>>>(cand_s, cand_m, mlist, flag2, scan2, n_maybe,
-                                                                     src, pair_s, pair_m, pair_nv, dst);
+                                                                     nf, pair_s, pair_m, pair_nv, pair_slot);
   return hipGetLastError();
 }
 
