@@ -488,6 +488,12 @@ int mt_csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, void* stream) {
     c->have_inc[0] = true;
   }
   c->have_master_index = false;
+  // per-element master-node lists of the M rows, before the fork: a short
+  // kernel that would otherwise wait behind the forward's blocks
+  MT_HIP(ensure(c->pat_ecnt, sizeof(int32_t) * (size_t)std::max(S.n_el, 1)));
+  MT_HIP(ensure(c->pat_elist, sizeof(int32_t) * (size_t)pattern_elem_list() * (size_t)std::max(S.n_el, 1)));
+  MT_HIP(launch_elem_mlist(S.n_el, c->pair_off.as<int32_t>(), c->pair_m.as<int32_t>(), M.conn,
+                           c->pat_ecnt.as<int32_t>(), c->pat_elist.as<int32_t>(), st));
   // The pair blocks of segment-based integration and the pairs-by-master
   // index of the backward depend on the pair list alone: they run on an
   // internal stream (the FP64-bound quadrature beside the latency-bound
@@ -529,8 +535,6 @@ int mt_csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, void* stream) {
     return fail(MT_ECAPACITY, "mt_csr_pattern: more than 2^31 block entries");
   int32_t tot[2] = {0, 0};
   MT_HIP(ensure(c->pat_keep, sizeof(int32_t) * (size_t)pattern_keep_per_row() * (size_t)std::max(n, 1)));
-  MT_HIP(ensure(c->pat_ecnt, sizeof(int32_t) * (size_t)std::max(S.n_el, 1)));
-  MT_HIP(ensure(c->pat_elist, sizeof(int32_t) * (size_t)pattern_elem_list() * (size_t)std::max(S.n_el, 1)));
   MT_HIP(ensure(c->D_cnt, sizeof(int32_t) * ((size_t)n + 1)));
   MT_HIP(ensure(c->M_cnt, sizeof(int32_t) * ((size_t)n + 1)));
   MT_HIP(ensure(c->D_rowptr, sizeof(int32_t) * ((size_t)n + 1)));

@@ -449,8 +449,6 @@ hipError_t launch_pattern_rows(bool fill, const int32_t* inc_off, const int32_t*
                                int32_t n_s_el, int32_t* posM, int64_t n_pairs, int32_t* ecnt, int32_t* elist,
                                hipStream_t s) {
   if (n_nodes == 0) return hipSuccess;
-  if (!fill && n_s_el > 0)
-    k_elem_mlist<<<xcd_grid(grid_of(n_s_el)), BS, 0, s>>>(n_s_el, pair_off, pair_m, conn_m, ecnt, elist);
   const unsigned g = xcd_grid((unsigned)((n_nodes + PB - 1) / PB));
   int32_t* keepD = keep;
   int32_t* keepM = keep + (int64_t)KD * n_nodes;
@@ -462,6 +460,13 @@ hipError_t launch_pattern_rows(bool fill, const int32_t* inc_off, const int32_t*
     k_pattern_rows<false><<<g, PB, 0, s>>>(inc_off, inc_list, n_nodes, pair_off, pair_m, conn_s, conn_m, D_cnt,
                                            M_cnt, D_rowptr, M_rowptr, D_col, M_col, keepD, keepM, posD, n_s_el, posM,
                                            n_pairs, ecnt, elist);
+  return hipGetLastError();
+}
+
+hipError_t launch_elem_mlist(int32_t n_s_el, const int32_t* pair_off, const int32_t* pair_m, const int32_t* conn_m,
+                             int32_t* ecnt, int32_t* elist, hipStream_t s) {
+  if (n_s_el == 0) return hipSuccess;
+  k_elem_mlist<<<xcd_grid(grid_of(n_s_el)), BS, 0, s>>>(n_s_el, pair_off, pair_m, conn_m, ecnt, elist);
   return hipGetLastError();
 }
 

@@ -255,6 +255,8 @@ hipError_t launch_pattern_rows(bool fill, const int32_t* inc_off, const int32_t*
                                const int32_t* M_rowptr, int32_t* D_col, int32_t* M_col, int32_t* keep, int32_t* posD,
                                int32_t n_s_el, int32_t* posM, int64_t n_pairs, int32_t* ecnt, int32_t* elist,
                                hipStream_t s);
+hipError_t launch_elem_mlist(int32_t n_s_el, const int32_t* pair_off, const int32_t* pair_m, const int32_t* conn_m,
+                             int32_t* ecnt, int32_t* elist, hipStream_t s);
 int pattern_keep_per_row();
 int pattern_elem_list();
 hipError_t launch_assemble(const int32_t* inc_off, const int32_t* inc_list, int32_t n_nodes,
