@@ -333,6 +333,8 @@ def main():
 
     dev = torch.device("cuda", 0)
     itf = synth.interface_config(2)
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info(dev)[0]
     iface = MortarInterface(torch.from_numpy(itf.slave.X), torch.from_numpy(itf.slave.conn),
                             torch.from_numpy(itf.master.X), torch.from_numpy(itf.master.conn),
                             params=default_params(delta=itf.delta), device=dev)
@@ -381,6 +383,9 @@ def main():
     tim = iface.timings(reset=True)
     assert iface.n_pairs == n_pairs and iface.n_cand == n_cand
     ms_step = (t1 - t0) * 1e3 / args.steps
+    # device memory held for the workload: library buffers, torch inputs,
+    # outputs, weights and gradients, and torch's cached blocks
+    mem_gb = (free0 - torch.cuda.mem_get_info(dev)[0]) / 2**30
     if tim[dominant][1]:
         per_launch[dominant] = tim[dominant][0] / tim[dominant][1]
     # forward path alone (search + pattern + forward), wall clock, no timers;
@@ -451,6 +456,7 @@ def main():
         "fwd_ms_per_step": fwd_ms,
         "phase_ms_per_step": per_step,
         "phase_note": "instrumented pass; pair_fwd runs on the internal stream inside the pattern phase",
+        "device_memory_gib": mem_gb,
         "roofline": roof,
         "roofline_other_kernels": others,
         "dual_basis": dual,
