@@ -177,9 +177,9 @@ struct LdsPoly {
 // capacity overflow (then returns 0).
 //
 // The first stage reads the slave polygon from registers and writes buffer
-// 1; the later stages alternate between the LDS buffers, reading each next
-// vertex one edge ahead so that the loads are issued before the stores of
-// the current edge.
+// 1; the later stages alternate between the LDS buffers, each first reading
+// its whole input polygon into registers (one round trip of independent LDS
+// reads instead of one per edge).
 
 // Side value of point (u, v) for the line a -> b (>= 0: inside).
 __device__ __forceinline__ double side_of(V2 a, double dbu, double dbv, double u, double v) {
@@ -228,6 +228,8 @@ __device__ __forceinline__ int clip_polygon(const V2 S[4], const V2 Mo[4], const
     n = k;
   }
   int cur = 1;
+  constexpr int CIN = CAP0 > CAP1 ? CAP0 : CAP1;  // a stage's input fits its buffer
+#pragma unroll
   for (int l = 1; l < 4; ++l) {
     if (n == 0) break;
     const V2 a = Mo[l];
@@ -235,50 +237,48 @@ __device__ __forceinline__ int clip_polygon(const V2 S[4], const V2 Mo[4], const
     const double dbu = b.u - a.u, dbv = b.v - a.v;
     const int nxt = cur ^ 1;
     const int cap = nxt ? CAP1 : CAP0;
-    // vertex 0 and the first edge end, read before any store of this stage
-    const double u0 = P.u[P.at(cur, 0)], v0 = P.v[P.at(cur, 0)];
-    uint8_t l0 = 0, e0 = 0;
-    if (LAB) { l0 = P.vl[P.at(cur, 0)]; e0 = P.el[P.at(cur, 0)]; }
-    double Eu = u0, Ev = v0;
-    uint8_t El = l0, Ee = e0;
-    if (n > 1) {
-      Eu = P.u[P.at(cur, 1)];
-      Ev = P.v[P.at(cur, 1)];
-      if (LAB) { El = P.vl[P.at(cur, 1)]; Ee = P.el[P.at(cur, 1)]; }
+    // the stage's whole input polygon to registers first (independent LDS
+    // reads, one round trip), then the walk with static register indices
+    double qu[CIN], qv[CIN], qc[CIN];
+    uint8_t ql[CIN], qe[CIN];
+#pragma unroll
+    for (int i = 0; i < CIN; ++i) {
+      qu[i] = 0.0;
+      qv[i] = 0.0;
+      ql[i] = 0;
+      qe[i] = 0;
+      if (i < n) {
+        qu[i] = P.u[P.at(cur, i)];
+        qv[i] = P.v[P.at(cur, i)];
+        if (LAB) { ql[i] = P.vl[P.at(cur, i)]; qe[i] = P.el[P.at(cur, i)]; }
+      }
     }
-    double Pu = u0, Pv = v0;
-    uint8_t Pl = l0, Pe = e0;
-    const double c0 = side_of(a, dbu, dbv, u0, v0);
-    double cP = c0;
+#pragma unroll
+    for (int i = 0; i < CIN; ++i) qc[i] = side_of(a, dbu, dbv, qu[i], qv[i]);
     int k = 0;
-    for (int j = 0; j < n; ++j) {
-      // next edge end (vertex j + 2), loaded ahead of this edge's stores
-      double Nu = u0, Nv = v0;
-      uint8_t Nl = l0, Ne = e0;
-      if (j + 2 < n) {
-        Nu = P.u[P.at(cur, j + 2)];
-        Nv = P.v[P.at(cur, j + 2)];
-        if (LAB) { Nl = P.vl[P.at(cur, j + 2)]; Ne = P.el[P.at(cur, j + 2)]; }
+#pragma unroll
+    for (int j = 0; j < CIN; ++j) {
+      if (j < n) {
+        // edge from vertex j to the next one (vertex 0 after the last)
+        const int jn = j + 1 < CIN ? j + 1 : 0;
+        const bool wrap = j + 1 == n;
+        const double Eu = wrap ? qu[0] : qu[jn], Ev = wrap ? qv[0] : qv[jn];
+        const double cP = qc[j], cE = wrap ? qc[0] : qc[jn];
+        const bool pin = cP >= 0.0;
+        const bool ein = cE >= 0.0;
+        if (pin) {
+          if (k == cap) { ovf = true; return 0; }
+          emit_vertex<LAB>(P, nxt, k, qu[j], qv[j], ql[j], qe[j]);
+          ++k;
+        }
+        if (pin != ein) {
+          if (k == cap) { ovf = true; return 0; }
+          const double t = cP / (cP - cE);
+          emit_vertex<LAB>(P, nxt, k, qu[j] + t * (Eu - qu[j]), qv[j] + t * (Ev - qv[j]),
+                           (uint8_t)((qe[j] << 4) | (4 + l)), pin ? (uint8_t)(4 + l) : qe[j]);
+          ++k;
+        }
       }
-      const double cE = j + 1 < n ? side_of(a, dbu, dbv, Eu, Ev) : c0;
-      const bool pin = cP >= 0.0;
-      const bool ein = cE >= 0.0;
-      if (pin) {
-        if (k == cap) { ovf = true; return 0; }
-        emit_vertex<LAB>(P, nxt, k, Pu, Pv, Pl, Pe);
-        ++k;
-      }
-      if (pin != ein) {
-        if (k == cap) { ovf = true; return 0; }
-        const double t = cP / (cP - cE);
-        emit_vertex<LAB>(P, nxt, k, Pu + t * (Eu - Pu), Pv + t * (Ev - Pv), (uint8_t)((Pe << 4) | (4 + l)),
-                         pin ? (uint8_t)(4 + l) : Pe);
-        ++k;
-      }
-      Pu = Eu; Pv = Ev; cP = cE;
-      if (LAB) { Pl = El; Pe = Ee; }
-      Eu = Nu; Ev = Nv;
-      if (LAB) { El = Nl; Ee = Ne; }
     }
     n = k;
     cur = nxt;
