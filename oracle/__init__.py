@@ -250,7 +250,7 @@ def normal_chain(slave, gn0_el):
     g = np.ascontiguousarray(gn0_el, np.float64)
     out = np.zeros((X.shape[0], 3))
     if _lib().or_normal_chain(X.shape[0], _p(X), C.shape[0], _p(C), _p(g), _p(out)) != 0:
-        raise RuntimeError("normal_chain: element patch larger than 24 nodes")
+        raise RuntimeError("normal_chain: element patch larger than 48 nodes")
     return out
 
 

@@ -1098,10 +1098,10 @@ int or_pair_grads(int64_t ns_nodes, const double* Xs, int64_t ns_el, const int32
 // n0_e the element normals of the nodal normal field (element_normals), by
 // forward-mode dual numbers over the coordinates of each element's patch
 // (the nodes of all elements around its four nodes).  Adds to gX (3 per node).
-// Returns 0, or 1 when a patch exceeds 24 nodes.
+// Returns 0, or 1 when a patch exceeds PMAX (48) nodes.
 int or_normal_chain(int64_t ns_nodes, const double* Xs, int64_t ns_el, const int32_t* Cs, const double* gn0,
                     double* gX) {
-  constexpr int PMAX = 24;
+  constexpr int PMAX = 48;
   using DP = Dual<3 * PMAX>;
   std::vector<std::vector<int32_t>> inc(ns_nodes);
   for (int64_t e = 0; e < ns_el; ++e)

@@ -67,11 +67,14 @@ def test_ragged_gradients(mode):
     assert rel_err(g["gXs"], gs) <= TOL and rel_err(g["gXm"], gm) <= TOL
 
 
+@pytest.mark.parametrize("fan", [(6, 7), (16, 18)], ids=["valence6", "valence16"])
 @pytest.mark.parametrize("mode", MODES, ids=lambda m: "-".join(f"{k}{v}" for k, v in m.items()))
-def test_nodes_with_more_than_four_elements(mode):
-    # fans of kites: the slave centre has 6 incident elements, the master
-    # centre 7, so the row gathers take their general loops
-    itf = synth.kite_fan()
+def test_nodes_with_more_than_four_elements(mode, fan):
+    # fans of kites: the slave centre has 6 (16) incident elements, the master
+    # centre 7 (18), so the row gathers take their general loops; with 16 the
+    # centre's D and M rows (33 and 37 columns) outgrow the per-thread
+    # segments of the pattern and assembly kernels
+    itf = synth.kite_fan(*fan)
     seed = None if mode.get("element_rule") else 79
     g = gpu_run(itf, backward_seed=seed, **mode)
     o, prm = oracle_for(itf, mode)
