@@ -250,7 +250,7 @@ int mt_get_stats(mt_ctx* ctx, mt_stats* st);
 #define MT_T_BIN_SORT 1    /* master bin keys, radix sort, bin ranges */
 #define MT_T_CAND 2        /* candidate count, scan, fill with screening (projection, separating line) */
 #define MT_T_CLIP 3        /* clip and cleanup of the screened candidates (one kernel) */
-#define MT_T_COMPACT 4     /* scans, screened-candidate list, pair-list and polygon compaction */
+#define MT_T_COMPACT 4     /* scans, screened-candidate list, pair-list compaction */
 #define MT_T_PATTERN 5     /* CSR pattern and position maps */
 #define MT_T_PAIR_POLY 6   /* clip polygons of all pairs after a coordinate change (one kernel) */
 #define MT_T_PAIR_FWD 7    /* segment integration of all pairs (one kernel) */
