@@ -254,6 +254,7 @@ def bench_elements(itf, seg_outs, steps, warmup):
         it.close()
         ms = (t1 - t0) * 1e3 / steps
         out[str(ng)] = {"integrate_ms": ms, "pairs_per_s": n_pairs / (ms * 1e-3), "slave_elements": n_el,
+                        "n_pairs": n_pairs,
                         "k_elem_fwd_ms": tim["pair_fwd"][0] / max(1, tim["pair_fwd"][1]),
                         "assemble_ms": tim["assemble"][0] / max(1, tim["assemble"][1]),
                         "rel_diff_vs_segment": err}
@@ -484,6 +485,15 @@ def main():
                              "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                              "frac": ach / FP64_VECTOR_PEAK_TFLOPS, "flops_per_unit": fl,
                              "unit_kind": "slave element", "units_per_launch": e["slave_elements"]}
+            # the same launch against HBM: algorithmic bytes = per slave element
+            # its connectivity, nodes and pair range (16 + 96 + 8 B), per pair
+            # its master index, connectivity and nodes (4 + 16 + 96 B) read and
+            # its 36 staged block values (288 B) written
+            by = e["slave_elements"] * 120 + e["n_pairs"] * 404
+            gbs = by / (e["k_elem_fwd_ms"] * 1e-3) / 1e9
+            e["roofline_hbm"] = {"bound": "hbm", "kernel": "k_elem_fwd", "achieved": gbs,
+                                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                                 "bytes_per_launch": by}
     if cpu:
         # whole step as a fraction of FP64 peak (pair kernels' algorithmic flops over the step time)
         fpu = cpu["flops_per_unit"]
