@@ -208,6 +208,7 @@ static_assert(KD <= PCAP && KM <= PCAP, "kept rows are looked up in the LDS segm
 __device__ __forceinline__ void find4(const int32_t* v, int vs, int u, const int key[4], int pos[4]) {
   if (u <= PCAP) {
     pos[0] = pos[1] = pos[2] = pos[3] = 0;
+#pragma unroll 4
     for (int i = 0; i < u; ++i) {
       const int c = v[i * vs];
 #pragma unroll
