@@ -17,7 +17,9 @@
  *    are HOST pointers.
  *  - `stream` is a hipStream_t (NULL = the legacy default stream).  All GPU
  *    work is enqueued on it.  Entry points that must report a data-dependent
- *    size (mt_build_pairs, mt_csr_pattern) synchronise that stream once.
+ *    size (mt_build_pairs, mt_csr_pattern) synchronise that stream: each
+ *    size is read back (through pinned host memory of the context) before
+ *    the host launches the work that it sizes.
  *  - Inputs and outputs are owned by the caller and must stay valid while a
  *    call that reads or writes them runs.  Meshes are registered, not
  *    copied: mt_upload keeps the pointers, and the arrays must stay alive and

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <initializer_list>
 #include <string>
 
 #include "mt_geometry.h"
@@ -168,8 +169,9 @@ int mt_destroy(mt_ctx* c) {
                  &c->minc_off, &c->minc_cur, &c->minc_list, &c->pat_keep, &c->pat_ecnt, &c->pat_elist, &c->D_cnt, &c->D_rowptr, &c->D_col, &c->M_cnt, &c->M_rowptr,
                  &c->M_col, &c->posD, &c->posM, &c->pair_slot, &c->maybe_list,
                  &c->maybe_flag, &c->maybe_scan, &c->mpoly_u, &c->mpoly_v, &c->mpoly_lab, &c->mpoly_nf, &c->blk, &c->gpair, &c->nrm_node, &c->nrm_el, &c->gn0, &c->nrm_sb, &c->nrm_ub, &c->nrm_cg, &c->aux_hist, &c->aux_scan, &c->mp_keys, &c->mp_vals, &c->mp_off, &c->mp_pos,
-                 &c->scan_tmp, &c->sort_hist, &c->host_tmp};
+                 &c->scan_tmp, &c->sort_hist};
   for (Buf* b : bufs) release(*b);
+  if (c->pin) (void)hipHostFree(c->pin);
   if (c->aux) {
     (void)hipEventDestroy(c->aux_fork);
     (void)hipEventDestroy(c->aux_join);
@@ -238,6 +240,44 @@ int mt_update_coordinates(mt_ctx* c, int side, const double* x, const double* y,
 
 static int normals_for_coords(mt_ctx* c, hipStream_t st);
 
+// Small device-to-host reads (totals of a scan, reduction maxima, counters)
+// through a pinned staging buffer of the context: the copies go straight to
+// host memory, one stream synchronisation covers all of them, and the values
+// are then copied to their destinations.
+struct ReadBack {
+  void* dst;
+  const void* src;
+  size_t bytes;
+};
+static constexpr size_t PIN_BYTES = 1024;
+
+static hipError_t read_back(mt_ctx* c, std::initializer_list<ReadBack> items, hipStream_t st) {
+  if (!c->pin) {
+    hipError_t e = hipHostMalloc(&c->pin, PIN_BYTES, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      c->pin = nullptr;
+      return e;
+    }
+  }
+  size_t off = 0;
+  for (const ReadBack& r : items) {
+    off = (off + 15) & ~size_t(15);
+    if (off + r.bytes > PIN_BYTES) return hipErrorInvalidValue;
+    hipError_t e = hipMemcpyAsync(static_cast<char*>(c->pin) + off, r.src, r.bytes, hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return e;
+    off += r.bytes;
+  }
+  hipError_t e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return e;
+  off = 0;
+  for (const ReadBack& r : items) {
+    off = (off + 15) & ~size_t(15);
+    std::memcpy(r.dst, static_cast<const char*>(c->pin) + off, r.bytes);
+    off += r.bytes;
+  }
+  return hipSuccess;
+}
+
 int mt_build_pairs(mt_ctx* c, int64_t* n_cand_out, int64_t* n_pairs_out, void* stream) {
   if (!c) return fail(MT_EINVAL, "mt_build_pairs: null ctx");
   if (!c->side[0].set || !c->side[1].set) return fail(MT_ESTATE, "mt_build_pairs: upload both sides first");
@@ -254,7 +294,6 @@ int mt_build_pairs(mt_ctx* c, int64_t* n_cand_out, int64_t* n_pairs_out, void* s
 
   MT_HIP(ensure(c->reduce, sizeof(PrepReduce)));
   MT_HIP(ensure(c->counters, sizeof(Counters)));
-  MT_HIP(ensure(c->host_tmp, 64));
   MT_HIP(ensure(c->box_s, sizeof(double) * 6 * (size_t)ns));
   MT_HIP(ensure(c->box_m, sizeof(double) * 6 * (size_t)nm));
   MT_HIP(ensure(c->sdata, sizeof(double) * SD_N * (size_t)ns));
@@ -271,8 +310,7 @@ int mt_build_pairs(mt_ctx* c, int64_t* n_cand_out, int64_t* n_pairs_out, void* s
     MT_HIP(launch_prep_reduce(part, nb_s, nb_m, red, st));
   }
   PrepReduce hr;
-  MT_HIP(hipMemcpyAsync(&hr, red, sizeof(hr), hipMemcpyDeviceToHost, st));
-  MT_HIP(hipStreamSynchronize(st));
+  MT_HIP(read_back(c, {{&hr, red, sizeof(hr)}}, st));
   if (hr.bad_index) return fail(MT_EINVAL, "mt_build_pairs: connectivity index out of range");
   if (c->params.normals == MT_NORMALS_NODAL) {
     // connectivity checked: the continuous normal field, then the slave
@@ -315,38 +353,54 @@ int mt_build_pairs(mt_ctx* c, int64_t* n_cand_out, int64_t* n_pairs_out, void* s
                              c->cand_tmp.as<int32_t>(), st));
     MT_HIP(scan_exclusive(c->cand_cnt.as<int32_t>(), c->cand_off.as<int32_t>(), ns, c->scan_tmp, st));
   }
-  int32_t ncand32 = 0;
-  MT_HIP(hipMemcpyAsync(&ncand32, c->cand_off.as<int32_t>() + ns, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  MT_HIP(hipStreamSynchronize(st));
-  const int64_t n_cand = ncand32;
-  if (n_cand < 0) return fail(MT_ECAPACITY, "mt_build_pairs: more than 2^31 candidates");
-  MT_HIP(ensure(c->cand_s, sizeof(int32_t) * (size_t)n_cand));
-  MT_HIP(ensure(c->cand_m, sizeof(int32_t) * (size_t)n_cand));
-  MT_HIP(ensure(c->cand_nv, (size_t)n_cand));
-  MT_HIP(ensure(c->cand_flag, sizeof(int32_t) * (size_t)std::max<int64_t>(n_cand, 1)));
   MT_HIP(ensure(c->scr_cnt, sizeof(int32_t) * ((size_t)ns + 1)));
   MT_HIP(ensure(c->scr_off, sizeof(int32_t) * ((size_t)ns + 1)));
-  // candidates, each screened as it is written (projection onto the slave
-  // plane, degeneracy checks, separating-line test)
+  // Candidates, each screened as it is written (projection onto the slave
+  // plane, degeneracy checks, separating-line test).  The candidate arrays
+  // keep their size from call to call: the fill pass runs against the present
+  // size and the total comes back with the screened count in one read; only
+  // when the total outgrew the arrays are they enlarged and the pass repeated.
+  // The first call reads the total before the fill.
   const KParams kp = kparams(c->params);
   Counters* cnt = c->counters.as<Counters>();
-  {
-    PhaseTimer t(c, MT_T_CAND, st);
-    MT_HIP(launch_cand_fill(c->box_s.as<double>(), ns, c->sbox.as<double>(), c->vals.as<uint32_t>(),
-                            c->cell_range.as<int2>(), g, c->params.delta, c->cand_tmp.as<int32_t>(), c->cand_off.as<int32_t>(), c->cand_s.as<int32_t>(),
-                            c->cand_m.as<int32_t>(), c->sdata.as<double>(), c->mdata.as<double>(), kp.eps_a,
-                            c->cand_nv.as<uint8_t>(), c->cand_flag.as<int32_t>(), c->scr_cnt.as<int32_t>(), cnt,
-                            st));
+  auto size_cand = [c](int64_t n) -> hipError_t {
+    hipError_t e = ensure(c->cand_s, sizeof(int32_t) * (size_t)n);
+    if (e == hipSuccess) e = ensure(c->cand_m, sizeof(int32_t) * (size_t)n);
+    if (e == hipSuccess) e = ensure(c->cand_nv, (size_t)n);
+    if (e == hipSuccess) e = ensure(c->cand_flag, sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1));
+    return e;
+  };
+  int32_t ncand32 = 0, nmaybe32 = 0;
+  if (!c->cand_s.p) {
+    MT_HIP(read_back(c, {{&ncand32, c->cand_off.as<int32_t>() + ns, sizeof(int32_t)}}, st));
+    if (ncand32 < 0) return fail(MT_ECAPACITY, "mt_build_pairs: more than 2^31 candidates");
+    MT_HIP(size_cand(ncand32));
   }
-
-  // clip the screened candidates, compact the pairs
-  {
-    PhaseTimer t(c, MT_T_COMPACT, st);
-    MT_HIP(scan_exclusive(c->scr_cnt.as<int32_t>(), c->scr_off.as<int32_t>(), ns, c->scan_tmp, st));
+  for (int pass = 0;; ++pass) {
+    const int64_t cap = (int64_t)std::min(std::min(c->cand_s.bytes, c->cand_m.bytes) / sizeof(int32_t),
+                                          std::min(c->cand_nv.bytes, c->cand_flag.bytes / sizeof(int32_t)));
+    {
+      PhaseTimer t(c, MT_T_CAND, st);
+      MT_HIP(launch_cand_fill(c->box_s.as<double>(), ns, c->sbox.as<double>(), c->vals.as<uint32_t>(),
+                              c->cell_range.as<int2>(), g, c->params.delta, c->cand_tmp.as<int32_t>(),
+                              c->cand_off.as<int32_t>(), c->cand_s.as<int32_t>(), c->cand_m.as<int32_t>(),
+                              c->sdata.as<double>(), c->mdata.as<double>(), kp.eps_a, c->cand_nv.as<uint8_t>(),
+                              c->cand_flag.as<int32_t>(), c->scr_cnt.as<int32_t>(), cnt, cap, st));
+    }
+    {
+      PhaseTimer t(c, MT_T_COMPACT, st);
+      MT_HIP(scan_exclusive(c->scr_cnt.as<int32_t>(), c->scr_off.as<int32_t>(), ns, c->scan_tmp, st));
+    }
+    MT_HIP(read_back(c, {{&ncand32, c->cand_off.as<int32_t>() + ns, sizeof(int32_t)},
+                         {&nmaybe32, c->scr_off.as<int32_t>() + ns, sizeof(int32_t)}}, st));
+    if (ncand32 < 0) return fail(MT_ECAPACITY, "mt_build_pairs: more than 2^31 candidates");
+    if (ncand32 <= cap) break;
+    if (pass > 0) return fail(MT_ECAPACITY, "mt_build_pairs: candidate arrays not sized");
+    MT_HIP(size_cand(ncand32));
+    // the degenerate-element counts of the partial pass are dropped
+    MT_HIP(hipMemsetAsync(&cnt->degen_slave, 0, 2 * sizeof(unsigned long long), st));
   }
-  int32_t nmaybe32 = 0;
-  MT_HIP(hipMemcpyAsync(&nmaybe32, c->scr_off.as<int32_t>() + ns, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  MT_HIP(hipStreamSynchronize(st));
+  const int64_t n_cand = ncand32;
   const int64_t n_maybe = nmaybe32;
   const size_t nmb = (size_t)std::max<int64_t>(n_maybe, 1);
   MT_HIP(ensure(c->maybe_list, sizeof(int32_t) * nmb));
@@ -376,9 +430,7 @@ int mt_build_pairs(mt_ctx* c, int64_t* n_cand_out, int64_t* n_pairs_out, void* s
   }
   int32_t np32 = 0;
   Counters hc;
-  MT_HIP(hipMemcpyAsync(&np32, c->maybe_scan.as<int32_t>() + n_maybe, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  MT_HIP(hipMemcpyAsync(&hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, st));
-  MT_HIP(hipStreamSynchronize(st));
+  MT_HIP(read_back(c, {{&np32, c->maybe_scan.as<int32_t>() + n_maybe, sizeof(int32_t)}, {&hc, cnt, sizeof(hc)}}, st));
   const int64_t n_pairs = np32;
   MT_HIP(ensure(c->pair_s, sizeof(int32_t) * (size_t)n_pairs));
   MT_HIP(ensure(c->pair_m, sizeof(int32_t) * (size_t)n_pairs));
@@ -545,13 +597,12 @@ int mt_csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, void* stream) {
                              c->n_pairs, c->pat_ecnt.as<int32_t>(), c->pat_elist.as<int32_t>(), st));
   MT_HIP(scan_exclusive(c->D_cnt.as<int32_t>(), c->D_rowptr.as<int32_t>(), n, c->scan_tmp, st));
   MT_HIP(scan_exclusive(c->M_cnt.as<int32_t>(), c->M_rowptr.as<int32_t>(), n, c->scan_tmp, st));
-  MT_HIP(hipMemcpyAsync(&tot[0], c->D_rowptr.as<int32_t>() + n, 4, hipMemcpyDeviceToHost, st));
-  MT_HIP(hipMemcpyAsync(&tot[1], c->M_rowptr.as<int32_t>() + n, 4, hipMemcpyDeviceToHost, st));
-  MT_HIP(hipStreamSynchronize(st));
-  c->nnz_D = tot[0];
-  c->nnz_M = tot[1];
-  MT_HIP(ensure(c->D_col, sizeof(int32_t) * (size_t)c->nnz_D));
-  MT_HIP(ensure(c->M_col, sizeof(int32_t) * (size_t)c->nnz_M));
+  // The fill pass needs the row pointers on the device only: the column arrays
+  // are sized by the local block entries (16 per slave element for D, 16 per
+  // pair for M), so the pass is launched before the totals are read back and
+  // the host waits once, after it.
+  MT_HIP(ensure(c->D_col, sizeof(int32_t) * 16 * (size_t)std::max(S.n_el, 1)));
+  MT_HIP(ensure(c->M_col, sizeof(int32_t) * 16 * (size_t)std::max<int64_t>(c->n_pairs, 1)));
   // the fill pass also writes the CSR positions of every local block entry
   MT_HIP(ensure(c->posD, sizeof(int32_t) * 16 * (size_t)std::max(S.n_el, 1)));
   MT_HIP(ensure(c->posM, sizeof(int32_t) * 16 * (size_t)std::max<int64_t>(c->n_pairs, 1)));
@@ -559,6 +610,9 @@ int mt_csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, void* stream) {
                              c->pair_m.as<int32_t>(), S.conn, M.conn, nullptr, nullptr, c->D_rowptr.as<int32_t>(), c->M_rowptr.as<int32_t>(), c->D_col.as<int32_t>(),
                              c->M_col.as<int32_t>(), c->pat_keep.as<int32_t>(), c->posD.as<int32_t>(), S.n_el,
                              c->posM.as<int32_t>(), c->n_pairs, nullptr, nullptr, st));
+  MT_HIP(read_back(c, {{&tot[0], c->D_rowptr.as<int32_t>() + n, 4}, {&tot[1], c->M_rowptr.as<int32_t>() + n, 4}}, st));
+  c->nnz_D = tot[0];
+  c->nnz_M = tot[1];
   if (aux) MT_HIP(hipStreamWaitEvent(st, c->aux_join, 0));
   c->have_pattern = true;
   ++c->pattern_gen;
@@ -813,8 +867,7 @@ int mt_get_stats(mt_ctx* c, mt_stats* out) {
   if (c->have_pairs)
     MT_HIP(launch_nv_hist(c->cand_nv.as<uint8_t>(), c->n_cand, dc->hist, c->last_stream));
   Counters hc;
-  MT_HIP(hipMemcpyAsync(&hc, c->counters.p, sizeof(hc), hipMemcpyDeviceToHost, c->last_stream));
-  MT_HIP(hipStreamSynchronize(c->last_stream));
+  MT_HIP(read_back(c, {{&hc, c->counters.p, sizeof(hc)}}, c->last_stream));
   for (int i = 0; i < 17; ++i) out->nverts_hist[i] = (int64_t)hc.hist[i];
   out->n_noconv = (int64_t)hc.noconv;
   out->n_overflow = (int64_t)hc.overflow;

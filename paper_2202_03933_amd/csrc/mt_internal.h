@@ -181,7 +181,8 @@ struct mt_ctx {
   mt::Buf mp_keys, mp_vals, mp_off;  // pairs sorted by master element
   mt::Buf mp_pos;          // int32 [n_pairs]: rank of each pair in that order
   // scan / sort scratch
-  mt::Buf scan_tmp, sort_hist, host_tmp;
+  mt::Buf scan_tmp, sort_hist;
+  void* pin = nullptr;     // pinned host staging of the small read-backs (counts, maxima)
 };
 
 namespace mt {
@@ -210,10 +211,14 @@ hipError_t launch_cell_ranges(const uint32_t* keys, const uint32_t* vals, int32_
                               int2* range, double* sbox, hipStream_t s);
 hipError_t launch_cand_count(const double* box_s, int32_t n_s, const double* sbox, const uint32_t* mvals,
                              const int2* range, Grid g, double delta, int32_t* count, int32_t* tmp, hipStream_t s);
+// Candidates of slave s go to [off[s], off[s + 1]) of cand_s / cand_m / nv /
+// flag, whose length is cap: a slave whose range ends beyond cap writes
+// nothing and gets scr_cnt[s] = 0 (the host compares off[n_s] with cap).
 hipError_t launch_cand_fill(const double* box_s, int32_t n_s, const double* sbox, const uint32_t* mvals,
                             const int2* range, Grid g, double delta, const int32_t* tmp, const int32_t* off,
                             int32_t* cand_s, int32_t* cand_m, const double* sd, const double* md, double eps_a,
-                            uint8_t* nv, int32_t* flag, int32_t* scr_cnt, Counters* cnt, hipStream_t s);
+                            uint8_t* nv, int32_t* flag, int32_t* scr_cnt, Counters* cnt, int64_t cap,
+                            hipStream_t s);
 int cand_tmp_per_slave();
 
 // ---- pairs (mt_pairs.hip) ----------------------------------------------------

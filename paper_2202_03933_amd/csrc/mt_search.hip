@@ -408,13 +408,17 @@ __global__ __launch_bounds__(BS) void k_cand_fill(int32_t n_s, const int32_t* __
                                                    int32_t* __restrict__ cand_m, const double* __restrict__ sd,
                                                    const double* __restrict__ md, double eps_a,
                                                    uint8_t* __restrict__ nv_out, int32_t* __restrict__ flag,
-                                                   int32_t* __restrict__ scr_cnt, Counters* cnt) {
+                                                   int32_t* __restrict__ scr_cnt, Counters* cnt, int64_t cap) {
   const int64_t t = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * BS + threadIdx.x;
   const int s = (int)(t / G), r = (int)(t % G);
   if (s >= n_s) return;  // whole groups leave together
   const int base = off[s];
   const int c = off[s + 1] - base;
   if (c > CTMP) return;  // k_cand_fill_long
+  if (base < 0 || (int64_t)base + c > cap) {  // output too short: the host sizes it, runs the pass again
+    if (r == 0) scr_cnt[s] = 0;
+    return;
+  }
   int nscr = 0;
   if (r < c) {
     int own[OWN], rank[OWN];
@@ -478,13 +482,18 @@ __global__ __launch_bounds__(BS) void k_cand_fill_long(const double* __restrict_
                                                         int32_t* __restrict__ cand_m, const double* __restrict__ sd,
                                                         const double* __restrict__ md, double eps_a,
                                                         uint8_t* __restrict__ nv_out, int32_t* __restrict__ flag,
-                                                        int32_t* __restrict__ scr_cnt, Counters* cnt) {
+                                                        int32_t* __restrict__ scr_cnt, Counters* cnt,
+                                                        int64_t cap) {
   __shared__ int32_t lds[CCAP * BS];
   const int s = xcd_tile(blockIdx.x, gridDim.x) * BS + threadIdx.x;
   if (s >= n_s) return;
   const int base = off[s];
   const int c = off[s + 1] - base;
   if (c <= CTMP) return;
+  if (base < 0 || (int64_t)base + c > cap) {
+    scr_cnt[s] = 0;
+    return;
+  }
   ScreenOut so{0u, 0u};
   int nscr = 0;
   if (c <= CCAP)
@@ -574,12 +583,14 @@ hipError_t launch_cand_count(const double* box_s, int32_t n_s, const double* sbo
 hipError_t launch_cand_fill(const double* box_s, int32_t n_s, const double* sbox, const uint32_t* mvals,
                             const int2* range, Grid g, double delta, const int32_t* tmp, const int32_t* off,
                             int32_t* cand_s, int32_t* cand_m, const double* sd, const double* md, double eps_a,
-                            uint8_t* nv, int32_t* flag, int32_t* scr_cnt, Counters* cnt, hipStream_t s) {
+                            uint8_t* nv, int32_t* flag, int32_t* scr_cnt, Counters* cnt, int64_t cap,
+                            hipStream_t s) {
   if (n_s == 0) return hipSuccess;
-  k_cand_fill<<<group_blocks(n_s), BS, 0, s>>>(n_s, tmp, off, cand_s, cand_m, sd, md, eps_a, nv, flag, scr_cnt, cnt);
+  k_cand_fill<<<group_blocks(n_s), BS, 0, s>>>(n_s, tmp, off, cand_s, cand_m, sd, md, eps_a, nv, flag, scr_cnt, cnt,
+                                               cap);
   k_cand_fill_long<<<xcd_grid((unsigned)((n_s + BS - 1) / BS)), BS, 0, s>>>(box_s, n_s, sbox, mvals, range, g, delta,
                                                                             off, cand_s, cand_m, sd, md, eps_a, nv,
-                                                                            flag, scr_cnt, cnt);
+                                                                            flag, scr_cnt, cnt, cap);
   return hipGetLastError();
 }
 

@@ -119,3 +119,41 @@ def test_batch_rejects_rebuilt_instance():
     with pytest.raises(MortarError) as e:
         b.forward()
     assert e.value.code == C.MT_ESTATE
+
+
+def test_rebuild_with_more_candidates_matches_a_fresh_search():
+    # The candidate arrays keep their size between searches of one context
+    # and the fill pass runs against that size: a second search with about
+    # twice the candidates outgrows them, which makes the pass run again on
+    # enlarged arrays; a third with fewer fits.  Every search must equal a
+    # fresh context's, bit for bit, and the oracle's candidate list.
+    import oracle
+    from tests.gpu_util import oracle_params
+    itf = synth.flat_tied(24, 19, seed=21)
+    shifted = itf.master.X + np.array([0.55, 0.0, 0.0])
+    print(f"[gpu] {itf.name}: searches with growing and shrinking candidate counts", flush=True)
+    it = _iface(itf.slave.X, itf, shifted)
+    counts = [it.n_cand]
+    for Xm in (itf.master.X, shifted + np.array([0.2, 0.0, 0.0]), itf.master.X):
+        it.set_coordinates(itf.slave.X, Xm)
+        it.setup()
+        counts.append(it.n_cand)
+        fresh = _iface(itf.slave.X, itf, Xm)
+        assert (it.n_cand, it.n_pairs, it.nnz_D, it.nnz_M) == (fresh.n_cand, fresh.n_pairs, fresh.nnz_D, fresh.nnz_M)
+        for x, y in zip(it.candidates() + it.pairs(), fresh.candidates() + fresh.pairs()):
+            assert torch.equal(x, y)
+        for x, y in zip((it.D_rowptr, it.D_col, it.M_rowptr, it.M_col),
+                        (fresh.D_rowptr, fresh.D_col, fresh.M_rowptr, fresh.M_col)):
+            assert torch.equal(x, y)
+        a = tuple(t.clone() for t in it.integrate())
+        b = tuple(t.clone() for t in fresh.integrate())
+        torch.cuda.synchronize()
+        assert all(torch.equal(x, y) for x, y in zip(a, b))
+        sa, sb = it.stats(), fresh.stats()
+        assert sa == sb
+        moved = synth.Interface(itf.slave, synth.Mesh(Xm, itf.master.conn), itf.delta, name=itf.name,
+                                meta=itf.meta)
+        o = oracle.evaluate(moved, oracle_params(moved))
+        cs, cm, _ = (t.cpu().numpy() for t in it.candidates())
+        assert np.array_equal(cs, o["cand_s"]) and np.array_equal(cm, o["cand_m"])
+    assert counts[1] > 1.25 * counts[0] and counts[2] < counts[1]
