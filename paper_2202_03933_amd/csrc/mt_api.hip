@@ -533,6 +533,10 @@ int mt_csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, void* stream) {
   const DeviceMesh& S = c->side[0];
   const DeviceMesh& M = c->side[1];
   const int32_t n = S.n_nodes;
+  // the local block entries (16 per pair) bound nnz(M), so the int32 row
+  // pointers cannot overflow below this size
+  if (16 * (int64_t)S.n_el >= (int64_t(1) << 31) || 16 * c->n_pairs >= (int64_t(1) << 31))
+    return fail(MT_ECAPACITY, "mt_csr_pattern: more than 2^31 block entries");
   PhaseTimer timer(c, MT_T_PATTERN, st);
   if (!c->have_inc[0]) {
     int rc = build_incidence(c, S, c->inc_cnt, c->inc_off, c->inc_cur, c->inc_list, st);
@@ -544,13 +548,21 @@ int mt_csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, void* stream) {
   // kernel that would otherwise wait behind the forward's blocks
   MT_HIP(ensure(c->pat_ecnt, sizeof(int32_t) * (size_t)std::max(S.n_el, 1)));
   MT_HIP(ensure(c->pat_elist, sizeof(int32_t) * (size_t)pattern_elem_list() * (size_t)std::max(S.n_el, 1)));
+  MT_HIP(ensure(c->pat_keep, sizeof(int32_t) * (size_t)pattern_keep_per_row() * (size_t)std::max(n, 1)));
+  MT_HIP(ensure(c->D_cnt, sizeof(int32_t) * ((size_t)n + 1)));
+  MT_HIP(ensure(c->M_cnt, sizeof(int32_t) * ((size_t)n + 1)));
+  MT_HIP(ensure(c->D_rowptr, sizeof(int32_t) * ((size_t)n + 1)));
+  MT_HIP(ensure(c->M_rowptr, sizeof(int32_t) * ((size_t)n + 1)));
   MT_HIP(launch_elem_mlist(S.n_el, c->pair_off.as<int32_t>(), c->pair_m.as<int32_t>(), M.conn,
                            c->pat_ecnt.as<int32_t>(), c->pat_elist.as<int32_t>(), st));
   // The pair blocks of segment-based integration and the pairs-by-master
   // index of the backward depend on the pair list alone: they run on an
   // internal stream (the FP64-bound quadrature beside the latency-bound
   // pattern kernels) and are joined back into the caller's stream before
-  // this call returns.  mt_integrate then only assembles.
+  // this call returns.  mt_integrate then only assembles.  Enqueue order:
+  // the forward, the pattern passes, then the index (a chain of short sort
+  // kernels, needed by the backward only), so that no pattern kernel waits
+  // for the host to enqueue that chain behind the forward.
   const bool aux = c->params.element_rule == 0 && c->n_pairs > 0 && c->poly_gen == c->coord_gen;
   if (aux) {
     if (!c->have_inc[1]) {
@@ -568,33 +580,16 @@ int mt_csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, void* stream) {
     MT_HIP(hipEventRecord(c->aux_fork, st));
     MT_HIP(hipStreamWaitEvent(c->aux, c->aux_fork, 0));
     {
-      PhaseTimer t(c, MT_T_GRAD_REDUCE, c->aux);
-      int rc = build_master_index(c, c->aux, c->aux_hist, c->aux_scan);
-      if (rc) return rc;
-    }
-    {
       PhaseTimer t(c, MT_T_PAIR_FWD, c->aux);
       MT_HIP(launch_pair_fwd(S, M, kparams(c->params), c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), np,
                              poly_buf(c), c->blk.as<double>(), np, c->counters.as<Counters>(), c->aux));
     }
-    MT_HIP(hipEventRecord(c->aux_join, c->aux));
-    c->blk_gen = c->coord_gen;
-    c->blk_pending = true;
   }
-  // the local block entries (16 per pair) bound nnz(M), so the int32 row
-  // pointers cannot overflow below this size
-  if (16 * (int64_t)S.n_el >= (int64_t(1) << 31) || 16 * c->n_pairs >= (int64_t(1) << 31))
-    return fail(MT_ECAPACITY, "mt_csr_pattern: more than 2^31 block entries");
-  int32_t tot[2] = {0, 0};
-  MT_HIP(ensure(c->pat_keep, sizeof(int32_t) * (size_t)pattern_keep_per_row() * (size_t)std::max(n, 1)));
-  MT_HIP(ensure(c->D_cnt, sizeof(int32_t) * ((size_t)n + 1)));
-  MT_HIP(ensure(c->M_cnt, sizeof(int32_t) * ((size_t)n + 1)));
-  MT_HIP(ensure(c->D_rowptr, sizeof(int32_t) * ((size_t)n + 1)));
-  MT_HIP(ensure(c->M_rowptr, sizeof(int32_t) * ((size_t)n + 1)));
   MT_HIP(launch_pattern_rows(false, c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(), n, c->pair_off.as<int32_t>(),
                              c->pair_m.as<int32_t>(), S.conn, M.conn, c->D_cnt.as<int32_t>(), c->M_cnt.as<int32_t>(),
                              nullptr, nullptr, nullptr, nullptr, c->pat_keep.as<int32_t>(), nullptr, S.n_el, nullptr,
                              c->n_pairs, c->pat_ecnt.as<int32_t>(), c->pat_elist.as<int32_t>(), st));
+  int32_t tot[2] = {0, 0};
   MT_HIP(scan_exclusive(c->D_cnt.as<int32_t>(), c->D_rowptr.as<int32_t>(), n, c->scan_tmp, st));
   MT_HIP(scan_exclusive(c->M_cnt.as<int32_t>(), c->M_rowptr.as<int32_t>(), n, c->scan_tmp, st));
   // The fill pass needs the row pointers on the device only: the column arrays
@@ -610,6 +605,16 @@ int mt_csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, void* stream) {
                              c->pair_m.as<int32_t>(), S.conn, M.conn, nullptr, nullptr, c->D_rowptr.as<int32_t>(), c->M_rowptr.as<int32_t>(), c->D_col.as<int32_t>(),
                              c->M_col.as<int32_t>(), c->pat_keep.as<int32_t>(), c->posD.as<int32_t>(), S.n_el,
                              c->posM.as<int32_t>(), c->n_pairs, nullptr, nullptr, st));
+  if (aux) {
+    {
+      PhaseTimer t(c, MT_T_GRAD_REDUCE, c->aux);
+      int rc = build_master_index(c, c->aux, c->aux_hist, c->aux_scan);
+      if (rc) return rc;
+    }
+    MT_HIP(hipEventRecord(c->aux_join, c->aux));
+    c->blk_gen = c->coord_gen;
+    c->blk_pending = true;
+  }
   MT_HIP(read_back(c, {{&tot[0], c->D_rowptr.as<int32_t>() + n, 4}, {&tot[1], c->M_rowptr.as<int32_t>() + n, 4}}, st));
   c->nnz_D = tot[0];
   c->nnz_M = tot[1];
