@@ -2,6 +2,7 @@
 // checks, device buffers and the launch sequence of each entry point.
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <initializer_list>
 #include <string>
@@ -398,6 +399,8 @@ int mt_build_pairs(mt_ctx* c, int64_t* n_cand_out, int64_t* n_pairs_out, void* s
     if (pass > 0) return fail(MT_ECAPACITY, "mt_build_pairs: candidate arrays not sized");
     MT_HIP(size_cand(ncand32));
     // the degenerate-element counts of the partial pass are dropped
+    static_assert(offsetof(Counters, degen_master) == offsetof(Counters, degen_slave) + sizeof(unsigned long long),
+                  "degen_slave and degen_master are cleared together");
     MT_HIP(hipMemsetAsync(&cnt->degen_slave, 0, 2 * sizeof(unsigned long long), st));
   }
   const int64_t n_cand = ncand32;
