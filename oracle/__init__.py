@@ -84,6 +84,8 @@ ST_NOCONV, ST_OVERFLOW, ST_DEGEN_SLAVE, ST_DEGEN_MASTER = 1, 2, 4, 8
 
 
 def capacity():
+    """Size of the vertex buffers the polygon helpers below pass (the
+    oracle's own clip polygons are growable)."""
     return int(_lib().or_capacity())
 
 
@@ -301,6 +303,8 @@ def pair_polygon(xs4, xm4, prm):
     pv = np.zeros(capacity())
     st = ctypes.c_int32(0)
     n = _lib().or_pair_polygon(_p(xs4), _p(xm4), ctypes.byref(prm), _p(pu), _p(pv), ctypes.byref(st))
+    if n < 0:
+        raise RuntimeError("pair_polygon: more vertices than the output buffer holds")
     return np.stack([pu[:n], pv[:n]], axis=1), st.value
 
 

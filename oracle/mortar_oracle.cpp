@@ -132,23 +132,19 @@ struct Params {
 
 enum {
   ST_NOCONV = 1,        // inverse bilinear map did not converge
-  ST_OVERFLOW = 2,      // a clip stage exceeded the polygon capacity
+  ST_OVERFLOW = 2,      // unused here (clip polygons grow); reserved for the status layout
   ST_DEGEN_SLAVE = 4,   // projected slave polygon has non-positive area
   ST_DEGEN_MASTER = 8,  // projected master polygon has (near) zero area
 };
 
-// Working capacity of the clip polygons.  The clipper alternates between two
-// buffers: buffer 0 holds the slave polygon and the outputs of stages 2 and
-// 4, buffer 1 the outputs of stages 1 and 3.  A convex quad clipped by k half
-// planes has at most 4 + k vertices (5, 6, 7, 8); the capacities leave two
-// vertices of headroom for near-duplicate vertices that rounding can emit
-// next to coincident edges.  A stage that would exceed its buffer makes the
-// candidate degenerate (no pair, overflow status).
-constexpr int CAP0 = 10;
-constexpr int CAP1 = 9;
-constexpr int CAP = CAP0;  // storage per buffer
+// Clip polygons are growable: Alg. 1 clips with plain Sutherland-Hodgman
+// and neither it nor Fig. 1 sets a vertex limit, so no stage can overflow
+// here.  OR_MAX_VERTICES only sizes the output buffers of the test entry
+// points below (a cleaned clip of two quads has at most 8 vertices).
+constexpr int OR_MAX_VERTICES = 64;
 
 template <class T> struct P2 { T u, v; };
+template <class T> using Poly = std::vector<P2<T>>;
 
 // ------------------------------------------------------- shape functions
 
@@ -251,30 +247,26 @@ T fan_area(int n, const P2<T>* p) {
 // master edge 0 as the first clip line, reproduces Fig. 1's clip polygon and
 // vertex order exactly.
 template <class T>
-int clip_stage(int n, const P2<T>* in, const P2<T>& a, const P2<T>& b,
-               P2<T>* out, int cap, int* status) {
-  if (n == 0) return 0;
-  T c[CAP];
+void clip_stage(const Poly<T>& in, const P2<T>& a, const P2<T>& b, Poly<T>& out) {
+  out.clear();
+  const int n = (int)in.size();
+  if (n == 0) return;
+  std::vector<T> c(n);
   for (int j = 0; j < n; ++j)
     c[j] = (b.u - a.u) * (in[j].v - a.v) - (b.v - a.v) * (in[j].u - a.u);
-  int k = 0;
   for (int j = 0; j < n; ++j) {
     const int e = (j + 1) % n;
     const bool pin = val(c[j]) >= 0.0;
     const bool ein = val(c[e]) >= 0.0;
-    if (pin) {
-      if (k == cap) { *status |= ST_OVERFLOW; return 0; }
-      out[k++] = in[j];
-    }
+    if (pin) out.push_back(in[j]);
     if (pin != ein) {
-      if (k == cap) { *status |= ST_OVERFLOW; return 0; }
       T t = c[j] / (c[j] - c[e]);
-      out[k].u = in[j].u + t * (in[e].u - in[j].u);
-      out[k].v = in[j].v + t * (in[e].v - in[j].v);
-      ++k;
+      P2<T> x;
+      x.u = in[j].u + t * (in[e].u - in[j].u);
+      x.v = in[j].v + t * (in[e].v - in[j].v);
+      out.push_back(x);
     }
   }
-  return k;
 }
 
 inline double linf(double du, double dv) { return std::max(std::fabs(du), std::fabs(dv)); }
@@ -288,34 +280,34 @@ inline double linf(double du, double dv) { return std::max(std::fabs(du), std::f
 //       as |cross(next-prev, v-prev)| <= tol * maxnorm(next-prev), until a
 //       sweep removes nothing or fewer than 3 vertices remain.
 template <class T>
-int cleanup(int n, P2<T>* p, double tol) {
-  if (n == 0) return 0;
+void cleanup(Poly<T>& p, double tol) {
+  int n = (int)p.size();
+  if (n == 0) return;
   int m = 1;
   for (int i = 1; i < n; ++i) {
     if (linf(val(p[i].u) - val(p[m - 1].u), val(p[i].v) - val(p[m - 1].v)) > tol)
       p[m++] = p[i];
   }
   if (m > 1 && linf(val(p[m - 1].u) - val(p[0].u), val(p[m - 1].v) - val(p[0].v)) <= tol) --m;
-  n = m;
+  p.resize(m);
   bool changed = true;
-  while (changed && n >= 3) {
+  while (changed && p.size() >= 3) {
     changed = false;
-    int i = 0;
-    while (i < n && n >= 3) {
-      const P2<T>& a = p[(i + n - 1) % n];
-      const P2<T>& b = p[(i + 1) % n];
+    size_t i = 0;
+    while (i < p.size() && p.size() >= 3) {
+      const size_t k = p.size();
+      const P2<T>& a = p[(i + k - 1) % k];
+      const P2<T>& b = p[(i + 1) % k];
       const double bu = val(b.u) - val(a.u), bv = val(b.v) - val(a.v);
       const double cr = bu * (val(p[i].v) - val(a.v)) - bv * (val(p[i].u) - val(a.u));
       if (std::fabs(cr) <= tol * linf(bu, bv)) {
-        for (int j = i; j + 1 < n; ++j) p[j] = p[j + 1];
-        --n;
+        p.erase(p.begin() + (std::ptrdiff_t)i);
         changed = true;
       } else {
         ++i;
       }
     }
   }
-  return n;
 }
 
 // ----------------------------------------------------------- quadrature
@@ -438,7 +430,7 @@ template <class T>
 struct PairOut {
   int nv = 0;          // clip polygon vertex count after cleanup (0: no pair)
   int status = 0;
-  P2<T> poly[CAP];
+  Poly<T> poly;        // the cleaned clip polygon of a pair
   T D[16], M[16], g[4];
 };
 
@@ -455,6 +447,7 @@ void eval_pair(const T Xs[4][3], const T Xm[4][3], const Params& prm,
                const Rule& rule, bool integrate, PairOut<T>& out, const T* nin = nullptr) {
   out.nv = 0;
   out.status = 0;
+  out.poly.clear();
   for (int i = 0; i < 16; ++i) { out.D[i] = 0.0; out.M[i] = 0.0; }
   for (int i = 0; i < 4; ++i) out.g[i] = 0.0;
 
@@ -482,46 +475,26 @@ void eval_pair(const T Xs[4][3], const T Xm[4][3], const Params& prm,
   P2<T> Mo[4] = {Mn[0], Mn[1], Mn[2], Mn[3]};
   if (val(Am) < 0.0) { Mo[1] = Mn[3]; Mo[3] = Mn[1]; }
 
-  // Separating-line quick exit (our addition; exact): when every slave vertex
-  // lies strictly outside one master edge line, or every master vertex
-  // strictly outside one slave edge line, the two convex polygons do not
-  // overlap.  The side test is the clip's own expression.
-  for (int side = 0; side < 2; ++side) {
-    const P2<T>* E = side == 0 ? Mo : S;  // polygon supplying the edge lines
-    const P2<T>* V = side == 0 ? S : Mo;  // polygon tested against them
-    for (int l = 0; l < 4; ++l) {
-      const P2<T>& a = E[l];
-      const P2<T>& b = E[(l + 1) % 4];
-      bool all_out = true;
-      for (int k = 0; k < 4; ++k) {
-        const T c = (b.u - a.u) * (V[k].v - a.v) - (b.v - a.v) * (V[k].u - a.u);
-        if (val(c) >= 0.0) all_out = false;
-      }
-      if (all_out) return;
-    }
+  // Sutherland-Hodgman: the slave polygon from node 0 is the subject, the
+  // oriented master edges from edge 0 the clip lines.
+  Poly<T> cur(S, S + 4), nxt;
+  for (int l = 0; l < 4 && !cur.empty(); ++l) {
+    clip_stage(cur, Mo[l], Mo[(l + 1) % 4], nxt);
+    cur.swap(nxt);
   }
-
-  P2<T> buf[2][CAP];
-  int n = 4;
-  for (int k = 0; k < 4; ++k) buf[0][k] = S[k];
-  int cur = 0;
-  for (int l = 0; l < 4 && n > 0; ++l) {
-    n = clip_stage(n, buf[cur], Mo[l], Mo[(l + 1) % 4], buf[1 - cur], cur == 0 ? CAP1 : CAP0, &out.status);
-    cur = 1 - cur;
-  }
-  if (out.status & ST_OVERFLOW) return;
-  n = cleanup(n, buf[cur], tol_d);
+  cleanup(cur, tol_d);
+  const int n = (int)cur.size();
   if (n < 3) return;
-  T Ap = fan_area(n, buf[cur]);
+  T Ap = fan_area(n, cur.data());
   if (!(val(Ap) > tol_a)) return;
   out.nv = n;
-  for (int i = 0; i < n; ++i) out.poly[i] = buf[cur][i];
+  out.poly = cur;
   if (!integrate) return;
 
   T A[16];
   if (prm.dual) dual_coefficients(S, A);
 
-  const P2<T>* P = out.poly;
+  const P2<T>* P = out.poly.data();
   for (int i = 1; i + 1 < n; ++i) {
     const P2<T>& V0 = P[0];
     const P2<T>& V1 = P[i];
@@ -917,7 +890,7 @@ static Params to_params(const OrParams* p) {
   return q;
 }
 
-int or_capacity() { return CAP; }
+int or_capacity() { return OR_MAX_VERTICES; }
 
 // Candidate pairs sorted by (slave, master).  method 0: brute force over all
 // pairs; method 1: binning.  Returns 0, or 1 when `cap` is too small (then
@@ -975,8 +948,9 @@ int or_pair_polygon(const double* Xs4, const double* Xm4, const OrParams* op, do
   const Params prm = to_params(op);
   PairOut<double> o;
   eval_pair(xs, xm, prm, make_rule(prm.rule), false, o);
-  for (int i = 0; i < o.nv; ++i) { pu[i] = o.poly[i].u; pv[i] = o.poly[i].v; }
   *status = o.status;
+  if (o.nv > OR_MAX_VERTICES) return -1;
+  for (int i = 0; i < o.nv; ++i) { pu[i] = o.poly[i].u; pv[i] = o.poly[i].v; }
   return o.nv;
 }
 
@@ -984,21 +958,19 @@ int or_pair_polygon(const double* Xs4, const double* Xm4, const OrParams* op, do
 // Writes the raw Sutherland-Hodgman output and the cleaned polygon.
 int or_clip2d(int ns, const double* su, const double* sv, int nc, const double* cu, const double* cv,
               double tol, double* raw_u, double* raw_v, int32_t* n_raw, double* out_u, double* out_v) {
-  if (ns > CAP || nc > CAP) return -1;
-  P2<double> buf[2][CAP], C[CAP];
-  for (int i = 0; i < ns; ++i) buf[0][i] = {su[i], sv[i]};
-  for (int i = 0; i < nc; ++i) C[i] = {cu[i], cv[i]};
-  int st = 0, n = ns, cur = 0;
-  for (int l = 0; l < nc && n > 0; ++l) {
-    n = clip_stage(n, buf[cur], C[l], C[(l + 1) % nc], buf[1 - cur], cur == 0 ? CAP1 : CAP0, &st);
-    cur = 1 - cur;
+  Poly<double> cur, nxt, C;
+  for (int i = 0; i < ns; ++i) cur.push_back({su[i], sv[i]});
+  for (int i = 0; i < nc; ++i) C.push_back({cu[i], cv[i]});
+  for (int l = 0; l < nc && !cur.empty(); ++l) {
+    clip_stage(cur, C[l], C[(l + 1) % nc], nxt);
+    cur.swap(nxt);
   }
-  if (st) return -2;
-  *n_raw = n;
-  for (int i = 0; i < n; ++i) { raw_u[i] = buf[cur][i].u; raw_v[i] = buf[cur][i].v; }
-  n = cleanup(n, buf[cur], tol);
-  for (int i = 0; i < n; ++i) { out_u[i] = buf[cur][i].u; out_v[i] = buf[cur][i].v; }
-  return n;
+  if ((int)cur.size() > OR_MAX_VERTICES) return -2;
+  *n_raw = (int32_t)cur.size();
+  for (size_t i = 0; i < cur.size(); ++i) { raw_u[i] = cur[i].u; raw_v[i] = cur[i].v; }
+  cleanup(cur, tol);
+  for (size_t i = 0; i < cur.size(); ++i) { out_u[i] = cur[i].u; out_v[i] = cur[i].v; }
+  return (int)cur.size();
 }
 
 // Quadrature points of the fan triangulation of a polygon: for triangle

@@ -16,6 +16,7 @@ from .meshes import (  # noqa: F401
     kite_fan,
     graded_flat,
     interface_config,
+    opposing,
     batched_instances,
     CONFIG_NAMES,
 )

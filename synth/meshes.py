@@ -186,12 +186,27 @@ def kite_fan(n_slave=6, n_master=7, seed=1003, curvature=0.05, normal_offset=1e-
                      meta={"geometry": "kite fan", "ns": n_slave, "nm": n_master, "seed": seed})
 
 
-def interface_config(k, scale=None):
+def opposing(itf):
+    """The same interface with every master element's node order reversed,
+    (0, 1, 2, 3) -> (0, 3, 2, 1): the master normal then points against the
+    slave normal, as for two bodies in contact, and the master's projection
+    onto a slave plane runs clockwise.  Coordinates are shared."""
+    conn = np.ascontiguousarray(itf.master.conn[:, [0, 3, 2, 1]]).astype(np.int32)
+    meta = dict(itf.meta)
+    meta["opposing"] = True
+    return Interface(itf.slave, Mesh(itf.master.X, conn), itf.delta, name=itf.name + ", opposing master",
+                     meta=meta)
+
+
+def interface_config(k, scale=None, opposing_normals=False):
     """The workload of configuration k (0 flat, 1 cylinder, 2 wavy).
 
     `scale` replaces the slave resolution and scales the master resolution
     by the same ratio (used for reduced-size parity cases).
+    `opposing_normals` reverses the master node order (see `opposing`).
     """
+    if opposing_normals:
+        return opposing(interface_config(k, scale))
     if k == 0:
         if scale is None:
             return flat_tied()

@@ -146,9 +146,11 @@ def test_cleanup_merges_near_duplicates():
     np.testing.assert_allclose(p, [[0, 0], [1, 0], [0, 1]], atol=1e-13)
 
 
-def test_capacity_bound_respected_on_degenerate_configs():
+def test_convex_bound_on_degenerate_configs():
     # Coincident boundary lines (tied flat meshes) exercise degenerate clips;
-    # no clip stage may exceed the working capacity.
+    # the cleaned overlap of two convex quads never has more than 8 vertices
+    # (each of the 4 clip lines adds at most one), and the oracle's growable
+    # clip never reports an overflow.
     import synth
     for seed in range(5):
         itf = synth.flat_tied(8, 7, seed=seed)
