@@ -79,18 +79,23 @@ def recorded_traffic(kernel):
         return None
 
 
-def cpu_baseline(itf, n_slave_el_sample, seed=3000):
-    """Oracle (serial C++, one core) on a bounded sample of the workload: the
-    slave elements [0, n) against the whole master side -- search, clip,
-    integration, assembly and gradients.  Returns a dict; also counts the
-    oracle's flops per pair for the forward evaluation."""
+_SHARD_ITF = None  # the workload, inherited by the forked oracle workers
+
+
+def _oracle_shard(rows):
+    """The oracle (serial C++, one core) on the slave elements of grid rows
+    [r0, r1) against the whole master side: search, clip, integration,
+    assembly and forward-mode gradients.  Returns (pairs, fwd s, all s)."""
     import numpy as np
 
     import oracle
     import synth
     from synth.weights import keyed_normal, TAG_D, TAG_M, TAG_G
 
-    sub = synth.Mesh(itf.slave.X, itf.slave.conn[:n_slave_el_sample].copy())
+    r0, r1, seed = rows
+    itf = _SHARD_ITF
+    nx = int(round(itf.slave.n_el ** 0.5))
+    sub = synth.Mesh(itf.slave.X, itf.slave.conn[r0 * nx:r1 * nx].copy())
     prm = oracle.params(delta=itf.delta)
     oracle._lib()  # load outside the timed region
     t0 = time.perf_counter()
@@ -98,7 +103,7 @@ def cpu_baseline(itf, n_slave_el_sample, seed=3000):
     nv, blocks, _ = oracle.eval_candidates(sub, itf.master, prm, cs, cm, integrate=True)
     keep = nv >= 3
     ps, pm = cs[keep], cm[keep]
-    D, M, g = oracle.assemble(sub, itf.master, ps, pm, blocks[keep])
+    oracle.assemble(sub, itf.master, ps, pm, blocks[keep])
     t_fwd = time.perf_counter() - t0
     fD = lambda r, c: keyed_normal(seed, TAG_D, r, c)  # noqa: E731
     fM = lambda r, c: keyed_normal(seed, TAG_M, r, c)  # noqa: E731
@@ -106,9 +111,56 @@ def cpu_baseline(itf, n_slave_el_sample, seed=3000):
     w = oracle.pair_weights(sub, itf.master, ps, pm, fD, fM, fg)
     g24, _ = oracle.pair_grads(sub, itf.master, prm, ps, pm, w)
     oracle.scatter_grads(sub, itf.master, ps, pm, g24)
-    t_all = time.perf_counter() - t0
-    # algorithmic flops (oracle's flop-counting scalar on every 16th pair and
-    # every 16th candidate of the sample).  Per kernel:
+    return int(ps.size), t_fwd, time.perf_counter() - t0
+
+
+def host_cores():
+    """Host threads the oracle legs use: the CPUs this process may run on,
+    at most 16 (the host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline(itf, rows=16, seed=3000):
+    """Oracle timings on the host, run before the GPU is touched: one core
+    on grid rows [0, rows), and all host cores (forked worker processes, one
+    contiguous block of `rows` slave-element rows each, rows [0, cores x
+    rows)) -- the embarrassingly sharded oracle.  Pairs/s over the wall time
+    of each leg."""
+    import multiprocessing as mp
+
+    global _SHARD_ITF
+    _SHARD_ITF = itf
+    p1, f1, a1 = _oracle_shard((0, rows, seed))
+    n = host_cores()
+    with mp.get_context("fork").Pool(n) as pool:
+        t0 = time.perf_counter()
+        res = pool.map(_oracle_shard, [(k * rows, (k + 1) * rows, seed) for k in range(n)], chunksize=1)
+        wall = time.perf_counter() - t0
+    pn = sum(r[0] for r in res)
+    return {"one_core": {"pairs": p1, "t_fwd": f1, "t_all": a1, "rows": rows},
+            "all_cores": {"pairs": pn, "wall": wall, "cores": n, "rows": n * rows,
+                          "worker_fwd_s_max": max(r[1] for r in res), "worker_all_s_max": max(r[2] for r in res)}}
+
+
+def oracle_flop_model(itf, n_slave_el_sample=16384):
+    """The oracle's operation counts per unit (its flop-counting scalar on
+    every 16th pair of the first rows of the workload): the algorithmic-work
+    model, reported beside the executed FP64 instruction counts."""
+    import numpy as np
+
+    import oracle
+    import synth
+
+    sub = synth.Mesh(itf.slave.X, itf.slave.conn[:n_slave_el_sample].copy())
+    prm = oracle.params(delta=itf.delta)
+    cs, cm = oracle.search(sub, itf.master, itf.delta)
+    nv, _, _ = oracle.eval_candidates(sub, itf.master, prm, cs, cm, integrate=False)
+    keep = nv >= 3
+    ps, pm = cs[keep], cm[keep]
     #   k_pair_poly:  the candidate pass of every pair;
     #   k_pair_fwd:   the pair evaluation minus its candidate pass;
     #   k_pair_bwd:   that forward recompute + the reverse-mode adjoint of the
@@ -116,38 +168,13 @@ def cpu_baseline(itf, n_slave_el_sample, seed=3000):
     #     of add/sub 2, mul 4, div 4, sqrt 3) + IFT_FLOPS per inverse map.
     f_cp, f_pair, f_adj, n_inv, f_cadj = oracle.count_flops(sub, itf.master, prm, ps[::16], pm[::16], detail=True)
     npp = max(1, ps[::16].size)
-    # the same flop model per geometry of the batched interfaces: the first
-    # 512 slave elements of the largest instance of each geometry
-    geo = {}
-    for b in synth.batched_instances(64):
-        g = b.meta["geometry"]
-        if g not in geo or b.slave.conn.shape[0] > geo[g].slave.conn.shape[0]:
-            geo[g] = b
-    batched_flops = {}
-    for g, b in geo.items():
-        bs = synth.Mesh(b.slave.X, b.slave.conn[:512].copy())
-        bprm = oracle.params(delta=b.delta)
-        bcs, bcm = oracle.search(bs, b.master, b.delta)
-        bnv, _, _ = oracle.eval_candidates(bs, b.master, bprm, bcs, bcm, integrate=False)
-        bk = bnv >= 3
-        q = oracle.count_flops(bs, b.master, bprm, bcs[bk], bcm[bk], detail=True)
-        nb = max(1, int(bk.sum()))
-        batched_flops[g] = {"fwd": (q[1] - q[0]) / nb, "bwd": (q[1] - q[0] + q[2] - q[4] + IFT_FLOPS * q[3]) / nb,
-                            "fwd_full": q[1] / nb}
-    # element-based integration: flops per slave element (every element with
-    # a pair among the first 2048 of the sample)
     esel = ps < 2048
     n_e = max(1, np.unique(ps[esel]).size)
     elem_flops = {ng: oracle.count_flops_elements(sub, itf.master, prm, ps[esel], pm[esel], ng) / n_e
                   for ng in ELEM_RULES}
-    return {"pairs": int(ps.size), "t_fwd": t_fwd, "t_all": t_all, "batched_flops": batched_flops,
-            "elem_flops_per_element": elem_flops,
-            "flops_per_unit": {"pair_poly": f_cp / npp,
-                               "pair_fwd": (f_pair - f_cp) / npp,
-                               "pair_bwd": (f_pair - f_cp + f_adj - f_cadj + IFT_FLOPS * n_inv) / npp},
-            "sample": f"slave elements 0..{n_slave_el_sample - 1} of the workload (the first "
-                      f"{n_slave_el_sample // 1024} rows of the 1024x1024 slave grid) against the whole master "
-                      f"side: {ps.size} pairs; search + clip + integrate + assemble + gradients"}
+    return {"pair_poly": f_cp / npp, "pair_fwd": (f_pair - f_cp) / npp,
+            "pair_bwd": (f_pair - f_cp + f_adj - f_cadj + IFT_FLOPS * n_inv) / npp,
+            "elem_flops_per_element": elem_flops}
 
 
 def bench_batched(reps=5):
@@ -207,10 +234,25 @@ def bench_batched(reps=5):
            "fwd_ms_per_interface": timed(per_fwd),
            "bwd_ms_batched_graph": timed(lambda: b.backward(W, outs=gouts, use_graph=True)),
            "bwd_ms_per_interface": timed(per_bwd)}
-    for k in ("fwd", "bwd"):
+    ab = {"forward": 0, "backward": 0}
+    for it, itf in zip(ifaces, insts):
+        a = algorithmic_bytes(itf.slave.n_nodes, itf.master.n_nodes, itf.slave.n_el, itf.master.n_el, it.n_cand,
+                              it.n_pairs, it.nnz_D, it.nnz_M)
+        ab["forward"] += a["forward"]
+        ab["backward"] += a["backward"]
+    counters = recorded_counters(FP64_SUMMARY, ALL_SOURCES)
+    res["hbm"] = {}
+    for k, phase, kern in (("fwd", "forward", "k_batch_fwd"), ("bwd", "backward", "k_batch_bwd")):
         res[f"{k}_pairs_per_s_batched"] = pairs / (res[f"{k}_ms_batched_graph"] * 1e-3)
         res[f"{k}_pairs_per_s_per_interface"] = pairs / (res[f"{k}_ms_per_interface"] * 1e-3)
         res[f"{k}_speedup"] = res[f"{k}_ms_per_interface"] / res[f"{k}_ms_batched_graph"]
+        for mode in ("batched_graph", "per_interface"):
+            res["hbm"][f"{k}_{mode}"] = hbm_entry(ab[phase], res[f"{k}_ms_{mode}"])
+            fl = counters.get(f"{kern}.fp64_flops_per_launch") if counters else None
+            # executed FP64 flops of the batched launch (the same pair arithmetic
+            # as the per-interface kernels) over each mode's wall time
+            res[f"{k}_fp64_frac_{mode}"] = (fl / (res[f"{k}_ms_{mode}"] * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS
+                                            if fl else None)
     return res
 
 
@@ -306,6 +348,71 @@ def bench_variant(itf, weights, steps, warmup, **params):
             "phase_ms_per_step": {k: v[0] / steps for k, v in tim.items()}}
 
 
+def recorded_counters(name, files):
+    """Executed-instruction counts per launch recorded by a committed
+    rocprofv3 --pmc summary (profiles/<name>), or None when it is missing or
+    the kernel sources changed since."""
+    full = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(full):
+        return None
+    rec = {}
+    with open(full) as f:
+        for line in f:
+            if line.startswith("- ") and ":" in line:
+                k, v = line[2:].split(":", 1)
+                rec[k.strip()] = v.strip().strip("`")
+    if rec.get("source_hash") != kernel_source_hash(files):
+        return None
+    out = {}
+    for k, v in rec.items():
+        try:
+            out[k] = float(v)
+        except ValueError:
+            pass
+    return out
+
+
+ALL_SOURCES = ["mt_prims.hip", "mt_search.hip", "mt_pairs.hip", "mt_assemble.hip", "mt_backward.hip",
+               "mt_elements.hip", "mt_normals.hip", "mt_batch.hip", "mt_api.hip", "mt_geometry.h",
+               "mt_pair_eval.h", "mt_dual.h", "mt_rows.h", "mt_internal.h"]
+FP64_SUMMARY = "wavy1024_fp64_counters.md"  # executed FP64 VALU instructions of every kernel of the step
+
+
+def algorithmic_bytes(n_sn, n_mn, n_se, n_me, n_cand, n_pairs, nnz_D, nnz_M):
+    """Algorithmic HBM bytes of each phase: what the method must move, not
+    what the kernels' staging adds.
+      search:   nodes once (24 B/node), connectivity once (16 B/element), the
+                master bin sort (4 passes, key+value read and written, 16 B
+                per master per pass), candidate list written and read
+                (2 x 8 B per candidate), pair list written (8 B per pair);
+      pattern:  pair list (8 B) and each pair's master connectivity (16 B)
+                read, slave connectivity (16 B/element) read, CSR column
+                indices (4 B/nonzero) and row pointers (2 x 4 B/row) written;
+      forward:  nodes, connectivity and pair list read, CSR indices read, D, M
+                and gap values written (8 B each);
+      backward: nodes, connectivity, pair list and CSR indices read, the
+                upstream weights read (8 B per value), gradients written
+                (24 B/node)."""
+    nodes = 24 * (n_sn + n_mn)
+    conn = 16 * (n_se + n_me)
+    csr_idx = 4 * (nnz_D + nnz_M) + 8 * (n_sn + 1)
+    vals = 8 * (nnz_D + nnz_M + n_sn)
+    search = nodes + conn + 4 * 16 * n_me + 16 * n_cand + 8 * n_pairs
+    pattern = 8 * n_pairs + 16 * n_pairs + 16 * n_se + csr_idx
+    fwd = nodes + conn + 8 * n_pairs + csr_idx + vals
+    bwd = nodes + conn + 8 * n_pairs + csr_idx + vals + 24 * (n_sn + n_mn)
+    return {"search": search, "pattern": pattern, "forward": fwd, "backward": bwd,
+            "step": search + pattern + fwd + bwd, "forward_path": search + pattern + fwd}
+
+
+def hbm_entry(nbytes, ms):
+    if not ms:
+        return None
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"bytes": int(nbytes), "ms": ms, "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -318,7 +425,8 @@ def main():
     ap.add_argument("--no-elements", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (calibrates HBM traffic counters)")
-    ap.add_argument("--cpu-sample", type=int, default=16384, help="slave elements in the CPU oracle sample")
+    ap.add_argument("--cpu-rows", type=int, default=16,
+                    help="slave-grid rows per oracle worker in the CPU legs (1024 slave elements a row)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs the mortar path on a single MI355X; "
@@ -326,18 +434,26 @@ def main():
         sys.exit(2)
 
     import numpy as np
-    import torch
 
     import synth
+    itf = synth.interface_config(2)
+    # the CPU legs run before anything touches the GPU (their workers are
+    # forked processes)
+    cpu = model = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(itf, args.cpu_rows)
+        model = oracle_flop_model(itf)
+
+    import torch
     from paper_2202_03933_amd import MortarInterface, default_params
     from synth.weights import keyed_normal, TAG_D, TAG_M, TAG_G
 
     dev = torch.device("cuda", 0)
-    itf = synth.interface_config(2)
     torch.cuda.synchronize()
     free0 = torch.cuda.mem_get_info(dev)[0]
-    iface = MortarInterface(torch.from_numpy(itf.slave.X), torch.from_numpy(itf.slave.conn),
-                            torch.from_numpy(itf.master.X), torch.from_numpy(itf.master.conn),
+    Xs = torch.from_numpy(itf.slave.X).to(dev)
+    Xm = torch.from_numpy(itf.master.X).to(dev)
+    iface = MortarInterface(Xs, torch.from_numpy(itf.slave.conn), Xm, torch.from_numpy(itf.master.conn),
                             params=default_params(delta=itf.delta), device=dev)
     iface.setup()
     n_pairs, n_cand = iface.n_pairs, iface.n_cand
@@ -351,11 +467,19 @@ def main():
     grads = (torch.empty(3, itf.slave.n_nodes, dtype=torch.float64, device=dev),
              torch.empty(3, itf.master.n_nodes, dtype=torch.float64, device=dev))
 
-    def step():
-        iface.build_pairs()
-        iface.csr_pattern()
+    def step(sync=True):
+        iface.build_pairs(sync=sync)
+        iface.csr_pattern(sync=sync)
         iface.integrate(outs)
         iface.backward(wD, wM, wg, grads)
+
+    def wall(fn, steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
 
     for _ in range(args.warmup):
         step()
@@ -371,35 +495,39 @@ def main():
     per_step = {k: v[0] / args.steps for k, v in tim_all.items()}
     per_launch = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in tim_all.items()}
     dominant = max(("pair_poly", "pair_fwd", "pair_bwd"), key=lambda k: per_launch.get(k, 0.0))
-    # the timed pass: events only around the dominant pair kernel, whose
-    # launch time the roofline uses
+    # the synchronous step (counts read back by every call), events only
+    # around the dominant pair kernel, whose launch time the roofline uses
     iface.set_timing(True, phases=[dominant])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    ms_sync = wall(step, args.steps)
     iface.set_timing(False)
     tim = iface.timings(reset=True)
     assert iface.n_pairs == n_pairs and iface.n_cand == n_cand
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    # device memory held for the workload: library buffers, torch inputs,
-    # outputs, weights and gradients, and torch's cached blocks
-    mem_gb = (free0 - torch.cuda.mem_get_info(dev)[0]) / 2**30
     if tim[dominant][1]:
         per_launch[dominant] = tim[dominant][0] / tim[dominant][1]
-    # forward path alone (search + pattern + forward), wall clock, no timers;
-    # the phase sums cannot give it: the forward runs beside the pattern
-    # kernels on the library's internal stream, inside the "pattern" phase
+    # the step without host waits (no count read-backs), then captured once
+    # into a HIP graph and replayed: the per-iteration form of a Newton loop
+    # (fixed capacities, coordinates updated in place)
+    ms_async = wall(lambda: step(False), args.steps)
+    iface.check()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step(False)
+    torch.cuda.current_stream().wait_stream(s)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        iface.build_pairs()
-        iface.csr_pattern()
-        iface.integrate(outs)
-    torch.cuda.synchronize()
-    fwd_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        step(False)
+    ms_graph = wall(graph.replay, args.steps)
+    iface.check()
+    # forward path alone (search + pattern + forward), no timers
+    fwd_ms = wall(lambda: (iface.build_pairs(sync=False), iface.csr_pattern(sync=False), iface.integrate(outs)),
+                  args.steps)
+    iface.check()
+    st = iface.stats()
+    assert st["n_pairs"] == n_pairs
+    ms_step = min(ms_graph, ms_async)
+    mem_gb = (free0 - torch.cuda.mem_get_info(dev)[0]) / 2**30
 
     if args.calib_copy:
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
@@ -411,32 +539,49 @@ def main():
     nodal = None if args.no_nodal else bench_variant(itf, (wD, wM, wg), args.steps, args.warmup, nodal_normals=True)
     elements = None if args.no_elements else bench_elements(itf, outs, args.steps, args.warmup)
     batched = None if args.no_batched else bench_batched()
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(itf, args.cpu_sample)
 
-    # roofline of the longest of the pair kernels (FP64-VALU bound; the search
-    # and pattern kernels are shorter, latency bound, and are reported by their
-    # phase times): achieved = oracle-counted algorithmic flops per unit x
-    # units per launch / average launch time from the library's event timers
-    # over the timed steps
-    units = {"pair_poly": n_pairs, "pair_fwd": n_pairs, "pair_bwd": n_pairs}
+    # Roofline of the longest pair kernel (FP64-VALU bound): achieved =
+    # executed FP64 flops per launch (rocprofv3 counters of FP64 VALU
+    # instructions, committed under profiles/, times 64 lanes, FMA 2 flops)
+    # over the launch time measured here; the oracle's operation count per
+    # pair is reported beside it as the algorithmic model.
+    counters = recorded_counters(FP64_SUMMARY, ALL_SOURCES)
 
     def roofline(k):
-        fp = cpu["flops_per_unit"][k] if cpu else None
-        if fp is None or not per_launch.get(k):
+        if not per_launch.get(k):
             return None
         launch_s = per_launch[k] * 1e-3
-        achieved = fp * units[k] / launch_s / 1e12
-        traffic = recorded_traffic(k)
-        return {"bound": "alu", "kernel": KERNELS[k][0], "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-                "traffic": traffic, "traffic_unit": "bytes per launch" if traffic else None,
-                "flops_per_unit": fp, "unit_kind": "pair",
-                "units_per_launch": units[k], "launch_ms": per_launch[k]}
+        kern = KERNELS[k][0]
+        executed = counters.get(f"{kern}.fp64_flops_per_launch") if counters else None
+        valu = counters.get(f"{kern}.valu_insts_per_launch") if counters else None
+        achieved = executed / launch_s / 1e12 if executed else None
+        r = {"bound": "alu", "kernel": kern, "achieved": achieved, "peak": FP64_VECTOR_PEAK_TFLOPS,
+             "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS if achieved else None,
+             "traffic": recorded_traffic(k), "traffic_unit": "bytes per launch",
+             "flops_source": "executed FP64 VALU instructions per launch (rocprofv3 SQ_INSTS_VALU_{FMA,ADD,MUL,TRANS}_F64"
+                             " x 64 lanes, FMA 2 flops)",
+             "units_per_launch": n_pairs, "unit_kind": "pair", "launch_ms": per_launch[k],
+             "executed_flops_per_pair": executed / n_pairs if executed else None}
+        if valu:
+            # VALU issue: a wave64 VALU instruction occupies a 16-lane SIMD 4 cycles
+            r["valu_issue_frac"] = valu * 4 / (launch_s * 2.4e9 * 256 * 4)
+        if model:
+            m = model[k] * n_pairs / launch_s / 1e12
+            r["oracle_model"] = {"flops_per_pair": model[k], "achieved": m, "frac": m / FP64_VECTOR_PEAK_TFLOPS}
+        return r
 
     roof = roofline(dominant)
-    others = {KERNELS[k][0]: roofline(k) for k in units if k != dominant and per_launch.get(k)}
+    others = {KERNELS[k][0]: roofline(k) for k in ("pair_poly", "pair_fwd", "pair_bwd")
+              if k != dominant and per_launch.get(k)}
+    ab = algorithmic_bytes(itf.slave.n_nodes, itf.master.n_nodes, itf.slave.n_el, itf.master.n_el, n_cand, n_pairs,
+                           iface.nnz_D, iface.nnz_M)
+    search_ms = sum(per_step.get(k, 0.0) for k in ("prep", "bin_sort", "cand", "clip", "compact"))
+    hbm = {"search": hbm_entry(ab["search"], search_ms),
+           "assemble": hbm_entry(ab["forward"] - (24 * (itf.slave.n_nodes + itf.master.n_nodes)
+                                                  + 16 * (itf.slave.n_el + itf.master.n_el)), per_step.get("assemble")),
+           "forward_path": hbm_entry(ab["forward_path"], fwd_ms),
+           "step": hbm_entry(ab["step"], ms_step),
+           "definitions": algorithmic_bytes.__doc__.split("\n", 2)[2].strip()}
     out = {
         "metric": "mortar element pairs integrated/sec (D,M,gap) fwd and fwd+bwd, 1 MI355X",
         "value": n_pairs / (ms_step * 1e-3),
@@ -453,54 +598,49 @@ def main():
         "config": {"workload": "wavy z=0.05 sin(2 pi x) sin(2 pi y), slave 1024x1024 / master 777x777 quad4, "
                                "normal offsets U[-1e-3,1e-3], delta 1.25e-3: search + forward + backward per step",
                    "n_pairs": n_pairs, "n_candidates": n_cand, "nnz_D": iface.nnz_D, "nnz_M": iface.nnz_M},
+        "step_modes_ms": {"graph_replay": ms_graph, "async": ms_async, "sync_counts": ms_sync},
+        "step_note": "value: the faster of the graph-replayed and the eager no-wait step (inputs resident, every "
+                     "phase recomputed); sync_counts reads the counts back in every call",
         "fwd_pairs_per_s": n_pairs / (fwd_ms * 1e-3),
         "fwd_ms_per_step": fwd_ms,
         "phase_ms_per_step": per_step,
-        "phase_note": "instrumented pass; pair_fwd runs on the internal stream inside the pattern phase",
+        "phase_note": "instrumented synchronous pass; pair_fwd runs on the internal stream inside the pattern phase",
         "device_memory_gib": mem_gb,
+        "workspace_bytes": iface._ws_bytes,
         "roofline": roof,
         "roofline_other_kernels": others,
+        "hbm": hbm,
         "dual_basis": dual,
         "nodal_normals": nodal,
         "element_based": elements,
         "batched_64_interfaces": batched,
     }
-    if cpu and batched:
-        # batched vs per-interface as fractions of FP64 peak: algorithmic flops
-        # of every pair (per-geometry oracle counts) over the wall time
-        bf = cpu["batched_flops"]
-        for k in ("fwd", "bwd"):
-            fl = sum(batched["pairs_by_geometry"][g] * bf[g][k] for g in bf)
-            for mode in ("batched_graph", "per_interface"):
-                batched[f"{k}_fp64_frac_{mode}"] = fl / (batched[f"{k}_ms_{mode}"] * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS
-    if cpu and elements:
-        # element-based kernel against FP64 peak: oracle-counted flops per
-        # slave element x elements / launch time
+    if counters and counters.get("step.fp64_flops"):
+        out["step_fp64_frac"] = counters["step.fp64_flops"] / (ms_step * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS
+    if model and elements:
         elements["segment_integrate_ms"] = per_step["pair_fwd"] + per_step["assemble"]
         for ng in ELEM_RULES:
             e = elements[str(ng)]
-            fl = cpu["elem_flops_per_element"][ng]
+            fl = model["elem_flops_per_element"][ng]
             ach = fl * e["slave_elements"] / (e["k_elem_fwd_ms"] * 1e-3) / 1e12
-            e["roofline"] = {"bound": "alu", "kernel": "k_elem_fwd", "achieved": ach,
-                             "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
-                             "frac": ach / FP64_VECTOR_PEAK_TFLOPS, "flops_per_unit": fl,
-                             "unit_kind": "slave element", "units_per_launch": e["slave_elements"]}
-            # the same launch against HBM: algorithmic bytes = per slave element
-            # its connectivity, nodes and pair range (16 + 96 + 8 B), per pair
-            # its master index, connectivity and nodes (4 + 16 + 96 B) read and
-            # its 36 staged block values (288 B) written
+            e["oracle_model"] = {"kernel": "k_elem_fwd", "achieved": ach, "unit": "TFLOP/s",
+                                 "frac": ach / FP64_VECTOR_PEAK_TFLOPS, "flops_per_unit": fl,
+                                 "unit_kind": "slave element", "units_per_launch": e["slave_elements"]}
+            # per slave element its connectivity, nodes and pair range
+            # (16 + 96 + 8 B), per pair its master index, connectivity and
+            # nodes (4 + 16 + 96 B) read and its 36 block values (288 B) written
             by = e["slave_elements"] * 120 + e["n_pairs"] * 404
-            gbs = by / (e["k_elem_fwd_ms"] * 1e-3) / 1e9
-            e["roofline_hbm"] = {"bound": "hbm", "kernel": "k_elem_fwd", "achieved": gbs,
-                                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
-                                 "bytes_per_launch": by}
+            e["roofline_hbm"] = dict(hbm_entry(by, e["k_elem_fwd_ms"]), kernel="k_elem_fwd")
     if cpu:
-        # whole step as a fraction of FP64 peak (pair kernels' algorithmic flops over the step time)
-        fpu = cpu["flops_per_unit"]
-        out["step_fp64_frac"] = (fpu["pair_fwd"] + fpu["pair_bwd"]) * n_pairs / (ms_step * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS
-        out["cpu_baseline"] = {"value": cpu["pairs"] / cpu["t_all"], "unit": "pairs/s", "cores": 1,
-                               "kind": "oracle", "sample": cpu["sample"],
-                               "fwd_only_pairs_per_s": cpu["pairs"] / cpu["t_fwd"]}
+        one, alln = cpu["one_core"], cpu["all_cores"]
+        out["cpu_baseline"] = {
+            "value": alln["pairs"] / alln["wall"], "unit": "pairs/s", "cores": alln["cores"], "kind": "oracle",
+            "sample": f"slave-grid rows 0..{alln['rows'] - 1} of the workload ({alln['rows'] * 1024} slave elements, "
+                      f"{alln['pairs']} pairs) against the whole master side, {alln['cores']} forked oracle "
+                      f"processes of {one['rows']} rows each; per process: search + clip + integrate + assemble + "
+                      f"forward-mode gradients",
+            "one_core": {"value": one["pairs"] / one["t_all"], "fwd_only": one["pairs"] / one["t_fwd"],
+                         "pairs": one["pairs"], "rows": one["rows"]}}
     print(json.dumps(out))
 
 

@@ -16,17 +16,28 @@
  *    stated otherwise; scalars returned through int64_t* / struct pointers
  *    are HOST pointers.
  *  - `stream` is a hipStream_t (NULL = the legacy default stream).  All GPU
- *    work is enqueued on it.  Entry points that must report a data-dependent
- *    size (mt_build_pairs, mt_csr_pattern) synchronise that stream: each
- *    size is read back (through pinned host memory of the context) before
- *    the host launches the work that it sizes.
- *  - Inputs and outputs are owned by the caller and must stay valid while a
- *    call that reads or writes them runs.  Meshes are registered, not
- *    copied: mt_upload keeps the pointers, and the arrays must stay alive and
- *    unchanged-in-shape until the next mt_upload of that side or
- *    mt_destroy.  Intermediate data (bins, candidates, pair list, CSR
- *    pattern, per-pair staging) lives in device memory owned by the context;
- *    it grows on demand and is released by mt_destroy.
+ *    work is enqueued on it.
+ *  - The library allocates no device memory.  Inputs and outputs are owned
+ *    by the caller and must stay valid while a call that reads or writes
+ *    them runs.  Meshes are registered, not copied: mt_upload keeps the
+ *    pointers, and the arrays must stay alive, unchanged in shape and (for
+ *    the connectivity) in content until the next mt_upload of that side or
+ *    mt_destroy.  Intermediate data (search grid, candidates, pair list,
+ *    clip polygons, CSR pattern, per-pair staging) lives in a WORKSPACE the
+ *    caller provides: mt_workspace_size gives its size for a set of
+ *    capacities (mt_capacity), mt_build_pairs binds it, and every later call
+ *    on that pair list (mt_csr_pattern, mt_integrate, mt_backward, the
+ *    getters, a batch) uses it; it must stay valid until the next
+ *    mt_build_pairs or mt_destroy.
+ *  - Host synchronisation.  mt_upload synchronises its stream (it checks the
+ *    connectivity).  mt_build_pairs and mt_csr_pattern synchronise only when
+ *    asked for counts (non-NULL count pointers); with NULL count pointers no
+ *    call of the chain mt_build_pairs -> mt_csr_pattern -> mt_integrate ->
+ *    mt_backward waits for the device (data-dependent sizes stay on the
+ *    device, kernels are launched for the capacities), so the chain can be
+ *    captured into a HIP graph and replayed.  Device-side conditions
+ *    (a capacity exceeded, non-finite coordinates, degenerate elements,
+ *    non-converged inverse maps) are then reported by mt_check.
  *  - Indices are 0-based int32; coordinates and values are IEEE double.
  *    Coordinates are structure-of-arrays: x[n], y[n], z[n].  Connectivity is
  *    int32 conn[n_el][4] (16-byte aligned), nodes counter-clockwise around
@@ -49,10 +60,11 @@ extern "C" {
 /* ---- status codes ---------------------------------------------------- */
 #define MT_OK 0
 #define MT_EINVAL 1        /* bad argument: null pointer, size, alignment, index range */
-#define MT_ECAPACITY 2     /* a caller buffer or a fixed capacity is too small */
+#define MT_ECAPACITY 2     /* a capacity or the workspace is too small (mt_required_capacity) */
 #define MT_EHIP 3          /* a HIP runtime call failed */
 #define MT_ENOCONV 4       /* an inverse bilinear map did not converge (values still written) */
-#define MT_EDEGENERATE 5   /* non-positive projected slave area or clip capacity exceeded */
+#define MT_EDEGENERATE 5   /* non-positive projected slave area, clip capacity exceeded, or a
+                              pair no longer a segment after a coordinate update */
 #define MT_ESTATE 6        /* called out of order (e.g. integrate before build_pairs) */
 #define MT_EUNSUPPORTED 7  /* option not supported by this entry point */
 
@@ -104,6 +116,8 @@ typedef struct mt_stats {
   int64_t n_overflow;       /* candidates whose clip exceeded the working capacity */
   int64_t n_degenerate_slave;
   int64_t n_degenerate_master;
+  int64_t n_lost_pairs;     /* pairs whose polygon stopped being a segment after a coordinate
+                               update (they contribute nothing) */
   int64_t nnz_D, nnz_M;
   int64_t n_bins[3];        /* search grid */
   double bin_size[3];
@@ -115,7 +129,8 @@ typedef struct mt_stats {
  * handle.  Errors: MT_EINVAL (null ctx), MT_EHIP (bad device). */
 int mt_create(mt_ctx** ctx, int device);
 
-/* Release the context and all device memory it owns.  NULL is a no-op. */
+/* Release the context (its events, internal stream and pinned host memory;
+ * workspaces stay the caller's).  NULL is a no-op. */
 int mt_destroy(mt_ctx* ctx);
 
 /* Fill *p with the defaults listed at mt_params. */
@@ -129,9 +144,10 @@ int mt_set_params(mt_ctx* ctx, const mt_params* p);
  * n_nodes coordinates x, y, z and n_el quad4 elements conn[n_el][4]
  * (device pointers, kept, not copied; eq. (AnsatzDiscretization) surface
  * meshes).  Invalidates the pair list.  Connectivity indices are checked
- * against n_nodes on the device during mt_build_pairs (MT_EINVAL).  Errors:
- * MT_EINVAL for null pointers with non-zero sizes, conn not 16-byte aligned,
- * sizes >= 2^31. */
+ * against n_nodes on the device here (the call synchronises `stream`).
+ * Errors: MT_EINVAL for null pointers with non-zero sizes, conn not 16-byte
+ * aligned, sizes >= 2^31, a connectivity index out of range (the side is
+ * then not registered). */
 int mt_upload(mt_ctx* ctx, int side, int64_t n_nodes, const double* x, const double* y,
               const double* z, int64_t n_el, const int32_t* conn, void* stream);
 
@@ -146,11 +162,34 @@ int mt_upload(mt_ctx* ctx, int side, int64_t n_nodes, const double* x, const dou
 int mt_update_coordinates(mt_ctx* ctx, int side, const double* x, const double* y, const double* z,
                           void* stream);
 
+/* Capacities of the data-dependent arrays of one build: how many
+ * candidates, screened candidates (those that reach the clip) and pairs the
+ * workspace holds, and the most cells of the search grid (a finer grid is
+ * coarsened to fit; coarser cells keep the search complete).  All <= 2^31 - 1. */
+typedef struct mt_capacity {
+  int64_t candidates;
+  int64_t screened;
+  int64_t pairs;
+  int64_t cells;
+} mt_capacity;
+
+/* Capacities for the uploaded meshes from their sizes (n_s, n_m elements):
+ * candidates 20 (n_s + n_m) + 1024, screened and pairs 2.5 (n_s + n_m) +
+ * 1024 (two nearly coincident surfaces overlap in about n_s + n_m +
+ * 2 sqrt(n_s n_m) pairs), cells min(2^24, max(2^16, 64 (n_s + n_m))).
+ * Errors: MT_ESTATE (a side not uploaded). */
+int mt_default_capacity(mt_ctx* ctx, mt_capacity* cap);
+
+/* Bytes of workspace mt_build_pairs needs for capacities `cap` (NULL: the
+ * defaults) with the current meshes and parameters (the continuous normal
+ * field adds its arrays).  Written to *bytes (host).  Errors: MT_ESTATE,
+ * MT_EINVAL (a capacity out of range). */
+int mt_workspace_size(mt_ctx* ctx, const mt_capacity* cap, size_t* bytes);
+
 /* Contact search and clipping (Alg. 2, then the projection and clipping
  * steps of Alg. 1):
  *  1. per element: bounding box; per slave element: auxiliary plane (centre
- *     x0, normal n0, in-plane basis t1, t2) and, for the dual basis, its
- *     coefficient matrix;
+ *     x0, normal n0, in-plane basis t1, t2);
  *  2. Cartesian bins over the nodes' bounding box expanded by the minimal
  *     bin size beta_min = max(longest slave edge, largest element box extent
  *     + delta, params.bin_size) (the paper's rule without a motion term,
@@ -164,16 +203,44 @@ int mt_update_coordinates(mt_ctx* ctx, int side, const double* x, const double* 
  *     cleanup); a candidate whose cleaned polygon has >= 3 vertices and
  *     area > eps_a * slave area is a pair.  The pairs' clip polygons are kept
  *     for mt_integrate / mt_backward at these coordinates.
- * Writes the counts to *n_cand and *n_pairs (host).  Synchronises `stream`.
- * Errors: MT_ESTATE (a side not uploaded), MT_EINVAL (connectivity out of
- * range), MT_EDEGENERATE (a slave element with non-positive projected area
- * or a clip exceeding capacity; counts still written). */
-int mt_build_pairs(mt_ctx* ctx, int64_t* n_cand, int64_t* n_pairs, void* stream);
+ * `cap` (NULL: mt_default_capacity) sizes the arrays; `ws` is the caller's
+ * device workspace of ws_bytes >= mt_workspace_size(cap) bytes (256-byte
+ * aligned), bound to the context until the next mt_build_pairs.  With
+ * n_cand / n_pairs non-NULL the call synchronises `stream`, writes the
+ * counts (host) and reports the device checks; with both NULL it does not
+ * wait for the device (see the conventions) and mt_check reports them.
+ * Errors: MT_ESTATE (a side not uploaded), MT_EINVAL (null or misaligned
+ * workspace, non-finite coordinates), MT_ECAPACITY (workspace smaller than
+ * mt_workspace_size; or a count beyond its capacity: the pair list is then
+ * incomplete, mt_required_capacity gives the counts), MT_EDEGENERATE (a
+ * slave element with non-positive projected area or a clip exceeding its
+ * working capacity; counts still written). */
+int mt_build_pairs(mt_ctx* ctx, const mt_capacity* cap, void* ws, size_t ws_bytes, int64_t* n_cand,
+                   int64_t* n_pairs, void* stream);
+
+/* Counts the last mt_build_pairs needed (synchronises its stream): the
+ * candidates found; the screened candidates among the candidates it could
+ * store; the pairs among the screened candidates it could store; the grid
+ * cells it used.  A build that exceeded a capacity runs again with
+ * capacities at least these (a stage after an exceeded one may need more
+ * once the earlier stage fits).  Errors: MT_ESTATE (no build). */
+int mt_required_capacity(mt_ctx* ctx, mt_capacity* need);
+
+/* Status of the device-side checks since the last mt_build_pairs
+ * (synchronises the stream of the last call): MT_EINVAL (a coordinate NaN
+ * or infinite), MT_ECAPACITY (a capacity exceeded), MT_EDEGENERATE (a
+ * degenerate slave element, a clip beyond its working capacity, or a pair
+ * lost after a coordinate update), MT_ENOCONV (an inverse bilinear map did
+ * not converge in mt_integrate / mt_backward), else MT_OK; the first that
+ * applies, in that order, with a message in mt_last_error.  Counts in
+ * mt_get_stats. */
+int mt_check(mt_ctx* ctx);
 
 /* Copy the pair list, sorted by (slave element, master element): n_pairs
- * entries each (sizes from mt_build_pairs); nverts = vertex count of the
- * cleaned clip polygon (3..16).  Any pointer may be NULL to skip it.
- * Errors: MT_ESTATE before mt_build_pairs. */
+ * entries each (sizes from mt_build_pairs or mt_get_stats; synchronises the
+ * stream of the build when they have not been read back); nverts = vertex
+ * count of the cleaned clip polygon (3..16).  Any pointer may be NULL to
+ * skip it.  Errors: MT_ESTATE before mt_build_pairs. */
 int mt_get_pairs(mt_ctx* ctx, int32_t* slave_el, int32_t* master_el, uint8_t* nverts, void* stream);
 
 /* Copy the candidate list (n_cand entries, sorted by (s, m)) and each
@@ -184,8 +251,10 @@ int mt_get_candidates(mt_ctx* ctx, int32_t* slave_el, int32_t* master_el, uint8_
 /* Sparsity of D (slave nodes x slave nodes) and M (slave nodes x master
  * nodes): the union of the 4x4 nodal blocks of all pairs (D: of every slave
  * element with at least one pair), columns sorted ascending, structural
- * zeros kept (the assembly of eq. (DiscreteWeakFormInterfaceFlux)).  Writes
- * nnz counts (host).  Synchronises `stream`.  For segment-based integration
+ * zeros kept (the assembly of eq. (DiscreteWeakFormInterfaceFlux)).  With
+ * nnz_D / nnz_M non-NULL it synchronises `stream` and writes the counts
+ * (host); with both NULL it does not wait (nnz(D) <= 16 n_s_el and nnz(M)
+ * <= 16 x the pair capacity bound them).  For segment-based integration
  * it also computes the local blocks of every pair (the quadrature of
  * mt_integrate, which depends on the pair list only) and the pairs-by-master
  * index of mt_backward on an internal stream of the context, concurrently
@@ -208,7 +277,8 @@ int mt_get_csr(mt_ctx* ctx, int32_t* D_rowptr, int32_t* D_col, int32_t* M_rowptr
  * blocks D_e[j][k] = int Phi_j N_k, M_e[j][l] = int Phi_j (N_l o chi),
  * g_e[j] = int Phi_j (h_master - h_slave) (heights along n0) are summed into
  * D_val[nnz_D], M_val[nnz_M] (CSR order of mt_csr_pattern) and gap[n_s_nodes]
- * (zero where no pair touches a node).  Output arrays are overwritten.
+ * (zero where no pair touches a node).  Output arrays are overwritten; the
+ * caller sizes them for the pattern's nnz (or its bounds).
  * With params.element_rule = n > 0, element-based integration instead (the
  * cheaper, less accurate alternative the same section names): no clip
  * polygons; an n x n Gauss-Legendre product rule on each slave element in
@@ -217,8 +287,9 @@ int mt_get_csr(mt_ctx* ctx, int32_t* D_rowptr, int32_t* D_col, int32_t* M_rowptr
  * contains it (closed edges), points in no master dropped; same blocks,
  * pattern and assembly.
  * Does not synchronise; quadrature points whose inverse map did not converge
- * are counted in mt_stats.n_noconv.  Errors: MT_ESTATE (no pattern),
- * MT_EINVAL (null outputs). */
+ * are counted in mt_stats.n_noconv and reported by mt_check (MT_ENOCONV), as
+ * are pairs lost after a coordinate update (MT_EDEGENERATE).  Errors:
+ * MT_ESTATE (no pattern), MT_EINVAL (null outputs). */
 int mt_integrate(mt_ctx* ctx, double* D_val, double* M_val, double* gap, void* stream);
 
 /* Gradient of L = <W_D, D_val> + <W_M, M_val> + <w_g, gap> with respect to
@@ -282,7 +353,9 @@ const char* mt_last_error(void);
 
 /* ---- batched evaluation of many independent interfaces ------------------
  * A batch holds references to K contexts (one interface each), all on one
- * device, each already through mt_build_pairs and mt_csr_pattern.
+ * device, each already through mt_build_pairs and mt_csr_pattern (their
+ * workspaces hold the per-instance data; the batch's own work queues and
+ * instance table live in a workspace of the batch).
  * mt_batch_build concatenates their pair lists into one work queue of
  * (instance, pair bucket) items balanced over the GPU (the single-GPU
  * analogue of the paper's interface load balancing, Sec. "Interface domain
@@ -304,10 +377,17 @@ int mt_batch_destroy(mt_batch* b);
 /* Add a context; returns its instance index in *index (host).  The context
  * must outlive the batch.  Errors: MT_EINVAL (other device), MT_ESTATE. */
 int mt_batch_add(mt_batch* b, mt_ctx* ctx, int32_t* index);
-/* Build the work queue and per-instance tables.  `tuning` may be NULL.  Synchronises.
- * Errors: MT_EINVAL (instances differ in rule, basis or normal field),
+/* Bytes of batch workspace mt_batch_build needs for the current instances
+ * (their pair counts; synchronises them when not read back).  Errors:
+ * MT_ESTATE (no instances). */
+int mt_batch_workspace_size(mt_batch* b, size_t* bytes);
+/* Build the work queue and per-instance tables in the caller's workspace
+ * `ws` of ws_bytes >= mt_batch_workspace_size bytes (256-byte aligned; kept
+ * until the next mt_batch_build or mt_batch_destroy).  `tuning` may be
+ * NULL.  Synchronises.  Errors: MT_EINVAL (instances differ in rule, basis
+ * or normal field; bad workspace), MT_ECAPACITY (workspace too small),
  * MT_EUNSUPPORTED (an instance set to element-based integration). */
-int mt_batch_build(mt_batch* b, const mt_batch_tuning* tuning, void* stream);
+int mt_batch_build(mt_batch* b, const mt_batch_tuning* tuning, void* ws, size_t ws_bytes, void* stream);
 /* Forward for every instance: D_val[i], M_val[i], gap[i] are host arrays of
  * K device pointers (outputs as for mt_integrate).  use_graph != 0 captures
  * the launch sequence into a HIP graph on first use and replays it while the

@@ -31,8 +31,14 @@ class mt_stats(ctypes.Structure):
     _fields_ = [("n_candidates", ctypes.c_int64), ("n_pairs", ctypes.c_int64),
                 ("nverts_hist", ctypes.c_int64 * 17), ("n_noconv", ctypes.c_int64),
                 ("n_overflow", ctypes.c_int64), ("n_degenerate_slave", ctypes.c_int64),
-                ("n_degenerate_master", ctypes.c_int64), ("nnz_D", ctypes.c_int64), ("nnz_M", ctypes.c_int64),
+                ("n_degenerate_master", ctypes.c_int64), ("n_lost_pairs", ctypes.c_int64),
+                ("nnz_D", ctypes.c_int64), ("nnz_M", ctypes.c_int64),
                 ("n_bins", ctypes.c_int64 * 3), ("bin_size", ctypes.c_double * 3)]
+
+
+class mt_capacity(ctypes.Structure):
+    _fields_ = [("candidates", ctypes.c_int64), ("screened", ctypes.c_int64), ("pairs", ctypes.c_int64),
+                ("cells", ctypes.c_int64)]
 
 
 MT_T_NAMES = ["prep", "bin_sort", "cand", "clip", "compact", "pattern", "pair_poly", "pair_fwd", "assemble",
@@ -53,6 +59,8 @@ class mt_batch_tuning(ctypes.Structure):
 _vp, _i32, _i64, _int = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int
 _pi64 = ctypes.POINTER(ctypes.c_int64)
 _pi32 = ctypes.POINTER(ctypes.c_int32)
+_psz = ctypes.POINTER(ctypes.c_size_t)
+_pcap = ctypes.POINTER(mt_capacity)
 SIGNATURES = {
     "mt_create": (_int, [ctypes.POINTER(_vp), _int]),
     "mt_destroy": (_int, [_vp]),
@@ -60,7 +68,11 @@ SIGNATURES = {
     "mt_set_params": (_int, [_vp, ctypes.POINTER(mt_params)]),
     "mt_upload": (_int, [_vp, _int, _i64, _vp, _vp, _vp, _i64, _vp, _vp]),
     "mt_update_coordinates": (_int, [_vp, _int, _vp, _vp, _vp, _vp]),
-    "mt_build_pairs": (_int, [_vp, _pi64, _pi64, _vp]),
+    "mt_default_capacity": (_int, [_vp, _pcap]),
+    "mt_workspace_size": (_int, [_vp, _pcap, _psz]),
+    "mt_build_pairs": (_int, [_vp, _pcap, _vp, ctypes.c_size_t, _pi64, _pi64, _vp]),
+    "mt_required_capacity": (_int, [_vp, _pcap]),
+    "mt_check": (_int, [_vp]),
     "mt_get_pairs": (_int, [_vp, _vp, _vp, _vp, _vp]),
     "mt_get_candidates": (_int, [_vp, _vp, _vp, _vp, _vp]),
     "mt_csr_pattern": (_int, [_vp, _pi64, _pi64, _vp]),
@@ -75,7 +87,8 @@ SIGNATURES = {
     "mt_batch_create": (_int, [ctypes.POINTER(_vp), _int]),
     "mt_batch_destroy": (_int, [_vp]),
     "mt_batch_add": (_int, [_vp, _vp, _pi32]),
-    "mt_batch_build": (_int, [_vp, ctypes.POINTER(mt_batch_tuning), _vp]),
+    "mt_batch_workspace_size": (_int, [_vp, _psz]),
+    "mt_batch_build": (_int, [_vp, ctypes.POINTER(mt_batch_tuning), _vp, ctypes.c_size_t, _vp]),
     "mt_batch_forward": (_int, [_vp, _vp, _vp, _vp, _int, _vp]),
     "mt_batch_backward": (_int, [_vp, _vp, _vp, _vp, _vp, _vp, _int, _vp]),
     "mt_batch_autotune": (_int, [_vp, ctypes.POINTER(mt_batch_tuning), _vp]),

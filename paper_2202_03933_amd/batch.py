@@ -12,7 +12,7 @@ import os
 import torch
 
 from . import _capi as C
-from .interface import _ptr
+from .interface import _ptr, workspace
 
 
 def _ptr_table(tensors):
@@ -45,7 +45,14 @@ class MortarBatch:
             t.block = int(tuning.get("block", 0))
             t.blocks_per_cu = int(tuning.get("blocks_per_cu", 0))
         self.stream.wait_stream(torch.cuda.current_stream(self.device))
-        C.check(C.lib().mt_batch_build(self.h, ctypes.byref(t), self._s()))
+        n = ctypes.c_size_t()
+        C.check(C.lib().mt_batch_workspace_size(self.h, ctypes.byref(n)))
+        if n.value > getattr(self, "_ws_bytes", 0):
+            self._ws = None
+            self._ws, self._ws_ptr = workspace(n.value, self.device)
+            self._ws_bytes = n.value
+        C.check(C.lib().mt_batch_build(self.h, ctypes.byref(t), ctypes.c_void_p(self._ws_ptr), self._ws_bytes,
+                                       self._s()))
 
     def signature(self):
         props = torch.cuda.get_device_properties(self.device)

@@ -393,8 +393,10 @@ __global__ __launch_bounds__(BS) void k_grad_slave(const int32_t* __restrict__ i
   grad_slave_row(a, n, inc_off, inc_list, pair_off, gpair, stride, gX);
 }
 
-__global__ __launch_bounds__(BS) void k_mpair_ranges(const uint32_t* __restrict__ keys, int64_t np,
-                                                      int32_t* __restrict__ start, int32_t* __restrict__ end) {
+__global__ __launch_bounds__(BS) void k_mpair_ranges(const uint32_t* __restrict__ keys,
+                                                      const int32_t* __restrict__ n_dev, int32_t* __restrict__ start,
+                                                      int32_t* __restrict__ end) {
+  const int64_t np = *n_dev;
   const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
   if (i >= np) return;
   const uint32_t k = keys[i];
@@ -414,10 +416,16 @@ __global__ __launch_bounds__(BS) void k_grad_master(const int32_t* __restrict__ 
 }
 
 // Rank of each pair in the pairs-by-master order: mpos[mpairs[k]] = k.
-__global__ __launch_bounds__(BS) void k_mpair_pos(const uint32_t* __restrict__ mpairs, int64_t np,
-                                                   int32_t* __restrict__ mpos) {
+__global__ __launch_bounds__(BS) void k_mpair_pos(const uint32_t* __restrict__ mpairs,
+                                                   const int32_t* __restrict__ n_dev, int32_t* __restrict__ mpos) {
   const int64_t k = (int64_t)blockIdx.x * BS + threadIdx.x;
-  if (k < np) mpos[mpairs[k]] = (int32_t)k;
+  if (k < *n_dev) mpos[mpairs[k]] = (int32_t)k;
+}
+
+// Identity values 0..n-1 (the pair indices sorted by master).
+__global__ __launch_bounds__(BS) void k_iota(uint32_t* __restrict__ v, const int32_t* __restrict__ n_dev) {
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (i < *n_dev) v[i] = (uint32_t)i;
 }
 
 inline unsigned grid_of(int64_t n) { return (unsigned)((n + BS - 1) / BS); }
@@ -447,7 +455,7 @@ hipError_t launch_pattern_rows(bool fill, const int32_t* inc_off, const int32_t*
                                const int32_t* pair_off, const int32_t* pair_m, const int32_t* conn_s,
                                const int32_t* conn_m, int32_t* D_cnt, int32_t* M_cnt, const int32_t* D_rowptr,
                                const int32_t* M_rowptr, int32_t* D_col, int32_t* M_col, int32_t* keep, int32_t* posD,
-                               int32_t n_s_el, int32_t* posM, int64_t n_pairs, int32_t* ecnt, int32_t* elist,
+                               int32_t n_s_el, int32_t* posM, int64_t pstride, int32_t* ecnt, int32_t* elist,
                                hipStream_t s) {
   if (n_nodes == 0) return hipSuccess;
   const unsigned g = xcd_grid((unsigned)((n_nodes + PB - 1) / PB));
@@ -456,11 +464,11 @@ hipError_t launch_pattern_rows(bool fill, const int32_t* inc_off, const int32_t*
   if (fill)
     k_pattern_rows<true><<<g, PB, 0, s>>>(inc_off, inc_list, n_nodes, pair_off, pair_m, conn_s, conn_m, D_cnt, M_cnt,
                                           D_rowptr, M_rowptr, D_col, M_col, keepD, keepM, posD, n_s_el, posM,
-                                          n_pairs, nullptr, nullptr);
+                                          pstride, nullptr, nullptr);
   else
     k_pattern_rows<false><<<g, PB, 0, s>>>(inc_off, inc_list, n_nodes, pair_off, pair_m, conn_s, conn_m, D_cnt,
                                            M_cnt, D_rowptr, M_rowptr, D_col, M_col, keepD, keepM, posD, n_s_el, posM,
-                                           n_pairs, ecnt, elist);
+                                           pstride, ecnt, elist);
   return hipGetLastError();
 }
 
@@ -492,12 +500,18 @@ hipError_t launch_grad_slave(const int32_t* inc_off, const int32_t* inc_list, in
   return hipGetLastError();
 }
 
-hipError_t launch_mpair_off(const uint32_t* sorted_m, const uint32_t* mpairs, int64_t n_pairs, int32_t n_m_el,
-                            int32_t* off, int32_t* mpos, hipStream_t s) {
+hipError_t launch_iota(uint32_t* v, const int32_t* n_dev, int64_t cap, hipStream_t s) {
+  if (cap == 0) return hipSuccess;
+  k_iota<<<grid_of(cap), BS, 0, s>>>(v, n_dev);
+  return hipGetLastError();
+}
+
+hipError_t launch_mpair_off(const uint32_t* sorted_m, const uint32_t* mpairs, const int32_t* n_pairs, int64_t cap,
+                            int32_t n_m_el, int32_t* off, int32_t* mpos, hipStream_t s) {
   // off holds start[n_m_el] followed by end[n_m_el]; both pre-zeroed.
-  if (n_pairs == 0) return hipSuccess;
-  k_mpair_ranges<<<grid_of(n_pairs), BS, 0, s>>>(sorted_m, n_pairs, off, off + n_m_el);
-  k_mpair_pos<<<grid_of(n_pairs), BS, 0, s>>>(mpairs, n_pairs, mpos);
+  if (cap == 0) return hipSuccess;
+  k_mpair_ranges<<<grid_of(cap), BS, 0, s>>>(sorted_m, n_pairs, off, off + n_m_el);
+  k_mpair_pos<<<grid_of(cap), BS, 0, s>>>(mpairs, n_pairs, mpos);
   return hipGetLastError();
 }
 

@@ -39,13 +39,17 @@ __device__ __forceinline__ void gather_weights(int s, int64_t p, int4 csn, const
 // registers do not add to those of the sweep.
 template <bool NODAL>
 __global__ __launch_bounds__(BSC) __attribute__((amdgpu_waves_per_eu(2))) void k_pair_dual_adj(MeshPtrs S, int32_t n_s, const int32_t* __restrict__ pair_s,
-                                                        int64_t n_pairs, const int32_t* __restrict__ posD,
+                                                        const int32_t* __restrict__ n_dev,
+                                                        const int32_t* __restrict__ posD,
                                                         const int32_t* __restrict__ posM,
                                                         const double* __restrict__ W_D, const double* __restrict__ W_M,
                                                         const double* __restrict__ w_g,
                                                         const double* __restrict__ blk, double* __restrict__ gpair,
                                                         double* __restrict__ gn0, int64_t stride) {
-  const int64_t p = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * BSC + threadIdx.x;
+  const int64_t n_pairs = *n_dev;
+  const int64_t tile = dyn_tile(blockIdx.x, n_pairs, BSC);
+  if (tile < 0) return;
+  const int64_t p = tile * BSC + threadIdx.x;
   if (p >= n_pairs) return;
   const int s = pair_s[p];
   const int4 csn = load_conn(S.conn, s);
@@ -57,13 +61,17 @@ __global__ __launch_bounds__(BSC) __attribute__((amdgpu_waves_per_eu(2))) void k
 template <int NQ, bool DUAL, bool NODAL>
 __global__ __launch_bounds__(BSC) __attribute__((amdgpu_waves_per_eu(2))) void k_pair_bwd(MeshPtrs S, int32_t n_s, MeshPtrs M, KParams kp,
                                                    const int32_t* __restrict__ pair_s,
-                                                   const int32_t* __restrict__ pair_m, int64_t n_pairs, PolyBuf poly,
+                                                   const int32_t* __restrict__ pair_m,
+                                                   const int32_t* __restrict__ n_dev, PolyBuf poly,
                                                    const int32_t* __restrict__ mpos,
                                                    const int32_t* __restrict__ posD, const int32_t* __restrict__ posM,
                                                    const double* __restrict__ W_D, const double* __restrict__ W_M,
                                                    const double* __restrict__ w_g, double* __restrict__ gpair,
                                                    double* __restrict__ gn0, int64_t stride, Counters* cnt) {
-  const int64_t p = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * BSC + threadIdx.x;
+  const int64_t n_pairs = *n_dev;
+  const int64_t tile = dyn_tile(blockIdx.x, n_pairs, BSC);
+  if (tile < 0) return;
+  const int64_t p = tile * BSC + threadIdx.x;
   unsigned noconv = 0;
   if (p < n_pairs) {
     const int s = pair_s[p];
@@ -98,13 +106,14 @@ __global__ __launch_bounds__(BSC) __attribute__((amdgpu_waves_per_eu(2))) void k
 }  // namespace
 
 hipError_t launch_pair_bwd(const DeviceMesh& S, const DeviceMesh& M, const KParams& kp, const int32_t* pair_s,
-                           const int32_t* pair_m, int64_t n_pairs, const PolyBuf& poly, const int32_t* mpos,
+                           const int32_t* pair_m, const int32_t* n_pairs, int64_t cap, const PolyBuf& poly,
+                           const int32_t* mpos,
                            const int32_t* posD, int32_t n_s_el,
                            const int32_t* posM, const double* W_D, const double* W_M, const double* w_g,
                            const double* blk, double* gpair, double* gn0, int64_t stride, Counters* cnt,
                            hipStream_t s) {
-  if (n_pairs == 0) return hipSuccess;
-  const unsigned nb = xcd_grid((unsigned)((n_pairs + BSC - 1) / BSC));
+  if (cap == 0) return hipSuccess;
+  const unsigned nb = xcd_grid((unsigned)((cap + BSC - 1) / BSC));
   const MeshPtrs ms{S.x, S.y, S.z, S.conn, S.nrm}, mm{M.x, M.y, M.z, M.conn, nullptr};
   const bool nodal = S.nrm != nullptr;
   auto* k = kp.rule == 3

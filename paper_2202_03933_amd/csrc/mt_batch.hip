@@ -32,6 +32,7 @@ struct BatchInst {
   const int32_t* pair_s;
   const int32_t* pair_m;
   int64_t n_pairs;
+  int64_t stride;  // of the per-pair arrays (the instance's pair capacity)
   const int32_t* pair_off;
   const int32_t* inc_off;
   const int32_t* inc_list;
@@ -46,8 +47,9 @@ struct BatchInst {
   const int32_t* mpos;
   double* blk;
   double* gpair;
-  double* gn0;  // [3][n_pairs] dL/dn0 per pair (continuous normal field), else null
+  double* gn0;  // [3][stride] dL/dn0 per pair (continuous normal field), else null
   PolyBuf poly;
+  Counters* cnt;  // the instance's counters (pairs lost after a coordinate update)
   // per call
   double* D_val;
   double* M_val;
@@ -117,7 +119,8 @@ __global__ __launch_bounds__(BSZ) void k_batch_poly(const BatchInst* __restrict_
       double Xs[4][3], Xm[4][3];
       load_nodes(I.S.x, I.S.y, I.S.z, load_conn(I.S.conn, I.pair_s[p]), Xs);
       load_nodes(I.M.x, I.M.y, I.M.z, load_conn(I.M.conn, I.pair_m[p]), Xm);
-      store_pair_polygon(Xs, Xm, elem_nrm(I.S, I.pair_s[p]), I.kp, P, I.poly, p);
+      if (store_pair_polygon(Xs, Xm, elem_nrm(I.S, I.pair_s[p]), I.kp, P, I.poly, p))
+        atomicAdd(&I.cnt->degen_poly, 1ull);
     }
   }
 }
@@ -136,7 +139,7 @@ __global__ __launch_bounds__(BSZ) __attribute__((amdgpu_waves_per_eu(3))) void k
       const int s = I.pair_s[p];
       pair_forward<NQ, DUAL>(I.S, s, load_conn(I.S.conn, s), I.M, load_conn(I.M.conn, I.pair_m[p]),
                              gpoly(I.poly, p), gpoly_nf(I.poly, p), I.kp, D, Mv, g, noconv);
-      const int64_t st = I.n_pairs;
+      const int64_t st = I.stride;
 #pragma unroll
       for (int k = 0; k < 16; ++k) I.blk[(int64_t)k * st + p] = D[k];
 #pragma unroll
@@ -155,7 +158,7 @@ __device__ __forceinline__ void batch_weights(const BatchInst& I, int s, int4 c,
 #pragma unroll
   for (int k = 0; k < 16; ++k) WD[k] = I.W_D[I.posD[(int64_t)k * I.n_s_el + s]];
 #pragma unroll
-  for (int k = 0; k < 16; ++k) WM[k] = I.W_M[I.posM[(int64_t)k * I.n_pairs + p]];
+  for (int k = 0; k < 16; ++k) WM[k] = I.W_M[I.posM[(int64_t)k * I.stride + p]];
   wg[0] = I.w_g[c.x];
   wg[1] = I.w_g[c.y];
   wg[2] = I.w_g[c.z];
@@ -179,7 +182,7 @@ __global__ __launch_bounds__(BSZ) __attribute__((amdgpu_waves_per_eu(2))) void k
       const int4 csn = load_conn(I.S.conn, s);
       double WD[16], WM[16], wg[4];
       batch_weights(I, s, csn, p, WD, WM, wg);
-      pair_dual_adjoint<NODAL>(I.S, s, csn, WD, WM, wg, I.blk, I.n_pairs, p, I.gpair, I.gn0);
+      pair_dual_adjoint<NODAL>(I.S, s, csn, WD, WM, wg, I.blk, I.stride, p, I.gpair, I.gn0);
     }
   }
 }
@@ -193,7 +196,7 @@ __global__ __launch_bounds__(BSZ) __attribute__((amdgpu_waves_per_eu(2))) void k
   for (int it = next_item(qbeg, qnext, qi); it >= 0; it = next_item(qbeg, qnext, qi)) {
     const WorkItem w = items[it];
     const BatchInst& I = inst[w.inst];
-    const int64_t st = I.n_pairs;
+    const int64_t st = I.stride;
     for (int64_t p = w.begin + (int)(threadIdx.x & 63); p < w.end; p += 64) {
       const int s = I.pair_s[p];
       const int4 csn = load_conn(I.S.conn, s);
@@ -236,7 +239,7 @@ __global__ __launch_bounds__(ROWS_PER_ITEM) void k_batch_assemble(const BatchIns
   if (a >= w.end) return;
   const BatchInst& I = inst[w.inst];
   assemble_row_acc(a, I.inc_off, I.inc_list, I.pair_off, I.D_rowptr, I.M_rowptr, I.posD, I.n_s_el, I.posM, I.blk,
-                   I.n_pairs, I.D_val, I.M_val, I.gap, acc + threadIdx.x, ROWS_PER_ITEM, BATCH_ACAP);
+                   I.stride, I.D_val, I.M_val, I.gap, acc + threadIdx.x, ROWS_PER_ITEM, BATCH_ACAP);
 }
 
 __global__ __launch_bounds__(ROWS_PER_ITEM) void k_batch_grad_rows(const BatchInst* __restrict__ inst,
@@ -246,9 +249,9 @@ __global__ __launch_bounds__(ROWS_PER_ITEM) void k_batch_grad_rows(const BatchIn
   if (a >= w.end) return;
   const BatchInst& I = inst[w.inst];
   if (w.pad == 0)
-    grad_slave_row(a, I.n_s_nodes, I.inc_off, I.inc_list, I.pair_off, I.gpair, I.n_pairs, I.gXs);
+    grad_slave_row(a, I.n_s_nodes, I.inc_off, I.inc_list, I.pair_off, I.gpair, I.stride, I.gXs);
   else
-    grad_master_row(a, I.n_m_nodes, I.minc_off, I.minc_list, I.mstart, I.mend, I.gpair, I.n_pairs, I.gXm);
+    grad_master_row(a, I.n_m_nodes, I.minc_off, I.minc_list, I.mstart, I.mend, I.gpair, I.stride, I.gXm);
 }
 
 using PolyFn = void (*)(const BatchInst*, const WorkItem*, const int32_t*, int32_t*);
@@ -315,8 +318,10 @@ struct mt_batch {
   std::vector<mt::BatchInst> h_inst;
   std::vector<int64_t> pattern_gen;  // each instance's pattern generation at mt_batch_build
   mt::BatchInst* pinned = nullptr;
+  // regions of the caller's batch workspace
   mt::Buf d_inst, d_pitems, d_qbeg, d_qnext, d_ritems_s, d_ritems_sm, counters;
   int n_pitems = 0, n_ritems_s = 0, n_ritems_sm = 0;
+  int64_t max_pitems = 0;  // pair items the workspace holds (buckets of at least MIN_BUCKET pairs)
   hipGraphExec_t g_fwd = nullptr, g_bwd = nullptr;
   hipStream_t g_fwd_stream = nullptr, g_bwd_stream = nullptr;
 };
@@ -366,9 +371,7 @@ int build_items(mt_batch* b, hipStream_t st) {
     acc += items[k].end - items[k].begin;
   }
   b->n_pitems = (int)items.size();
-  B_HIP(ensure(b->d_pitems, sizeof(WorkItem) * std::max<size_t>(1, items.size())));
-  B_HIP(ensure(b->d_qbeg, sizeof(int32_t) * (NQUEUE + 1)));
-  B_HIP(ensure(b->d_qnext, sizeof(int32_t) * NQUEUE));
+  if ((int64_t)items.size() > b->max_pitems) return bfail(MT_ECAPACITY, "batch: more work items than the workspace holds");
   B_HIP(hipStreamSynchronize(st));
   if (!items.empty())
     B_HIP(hipMemcpy(b->d_pitems.p, items.data(), sizeof(WorkItem) * items.size(), hipMemcpyHostToDevice));
@@ -480,7 +483,7 @@ int launch_bwd_all(mt_batch* b, hipStream_t st) {
       double* const* gx_at = reinterpret_cast<double* const*>(rec + offsetof(BatchInst, gXs));
       const MeshPtrs* s_at = reinterpret_cast<const MeshPtrs*>(rec + offsetof(BatchInst, S));
       B_HIP(launch_normal_chain(c->side[0], c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(),
-                                c->pair_off.as<int32_t>(), c->gn0.as<double>(), std::max<int64_t>(c->n_pairs, 1),
+                                c->pair_off.as<int32_t>(), c->gn0.as<double>(), c->cap.pairs,
                                 c->nrm_node.as<double>(), c->nrm_el.as<double>(), c->nrm_sb.as<double>(),
                                 c->nrm_ub.as<double>(), c->nrm_cg.as<double>(), nullptr, gx_at, s_at, st));
     }
@@ -554,8 +557,6 @@ int mt_batch_destroy(mt_batch* b) {
   (void)hipDeviceSynchronize();
   drop_graphs(b);
   if (b->pinned) (void)hipHostFree(b->pinned);
-  Buf* bufs[] = {&b->d_inst, &b->d_pitems, &b->d_qbeg, &b->d_qnext, &b->d_ritems_s, &b->d_ritems_sm, &b->counters};
-  for (Buf* x : bufs) release(*x);
   delete b;
   return MT_OK;
 }
@@ -571,21 +572,77 @@ int mt_batch_add(mt_batch* b, mt_ctx* c, int32_t* index) {
   return MT_OK;
 }
 
-int mt_batch_build(mt_batch* b, const mt_batch_tuning* tuning, void* stream) {
-  if (!b) return bfail(MT_EINVAL, "mt_batch_build: null");
-  if (b->ctxs.empty()) return bfail(MT_ESTATE, "mt_batch_build: no instances");
+// Checks shared by the size query and the build.
+static int batch_check(mt_batch* b, const char* who) {
+  if (!b) return bfail(MT_EINVAL, who);
+  if (b->ctxs.empty()) return bfail(MT_ESTATE, "batch: no instances");
+  const mt_params& p0 = b->ctxs[0]->params;
+  for (mt_ctx* c : b->ctxs) {
+    if (!c->have_pattern) return bfail(MT_ESTATE, "batch: an instance has no pattern");
+    if (c->params.rule != p0.rule || c->params.lm_basis != p0.lm_basis)
+      return bfail(MT_EINVAL, "batch: all instances must share the rule and the basis");
+    if (c->params.normals != p0.normals)
+      return bfail(MT_EINVAL, "batch: all instances must share the normal field");
+    if (c->params.element_rule != 0) return bfail(MT_EUNSUPPORTED, "batch: segment-based integration only");
+    int rc = host_counts(c);
+    if (rc) return rc;
+  }
+  return MT_OK;
+}
+
+constexpr int MIN_BUCKET = 64;  // smallest pair bucket (the autotuner's)
+
+// Layout of the batch workspace for the current instances.
+static void batch_layout(mt_batch* b, Arena& A, int64_t& max_pitems, int64_t& n_rs, int64_t& n_rsm) {
+  max_pitems = 0;
+  n_rs = n_rsm = 0;
+  for (mt_ctx* c : b->ctxs) {
+    max_pitems += (c->n_pairs + MIN_BUCKET - 1) / MIN_BUCKET;
+    const int64_t rs = (c->side[0].n_nodes + ROWS_PER_ITEM - 1) / ROWS_PER_ITEM;
+    n_rs += rs;
+    n_rsm += rs + (c->side[1].n_nodes + ROWS_PER_ITEM - 1) / ROWS_PER_ITEM;
+  }
+  A.take(b->d_inst, sizeof(BatchInst) * b->ctxs.size());
+  A.take(b->d_pitems, sizeof(WorkItem) * (size_t)std::max<int64_t>(1, max_pitems));
+  A.take(b->d_qbeg, sizeof(int32_t) * (NQUEUE + 1));
+  A.take(b->d_qnext, sizeof(int32_t) * NQUEUE);
+  A.take(b->d_ritems_s, sizeof(WorkItem) * (size_t)std::max<int64_t>(1, n_rs));
+  A.take(b->d_ritems_sm, sizeof(WorkItem) * (size_t)std::max<int64_t>(1, n_rsm));
+  A.take(b->counters, sizeof(Counters));
+}
+
+int mt_batch_workspace_size(mt_batch* b, size_t* bytes) {
+  if (!bytes) return bfail(MT_EINVAL, "mt_batch_workspace_size: null");
+  int rc = batch_check(b, "mt_batch_workspace_size: null");
+  if (rc) return rc;
+  mt_batch probe;
+  probe.ctxs = b->ctxs;
+  Arena A;
+  int64_t a, r1, r2;
+  batch_layout(&probe, A, a, r1, r2);
+  *bytes = A.off;
+  return MT_OK;
+}
+
+int mt_batch_build(mt_batch* b, const mt_batch_tuning* tuning, void* ws, size_t ws_bytes, void* stream) {
+  int rc = batch_check(b, "mt_batch_build: null");
+  if (rc) return rc;
+  if (!ws || (reinterpret_cast<uintptr_t>(ws) & 255))
+    return bfail(MT_EINVAL, "mt_batch_build: workspace null or not 256-byte aligned");
   (void)hipSetDevice(b->device);
   hipStream_t st = (hipStream_t)stream;
   const mt_params& p0 = b->ctxs[0]->params;
-  for (mt_ctx* c : b->ctxs) {
-    if (!c->have_pattern) return bfail(MT_ESTATE, "mt_batch_build: an instance has no pattern");
-    if (c->params.rule != p0.rule || c->params.lm_basis != p0.lm_basis)
-      return bfail(MT_EINVAL, "mt_batch_build: all instances must share the rule and the basis");
-    if (c->params.normals != p0.normals)
-      return bfail(MT_EINVAL, "mt_batch_build: all instances must share the normal field");
-    if (c->params.element_rule != 0)
-      return bfail(MT_EUNSUPPORTED, "mt_batch_build: segment-based integration only");
+  {
+    Arena A;
+    A.base = static_cast<char*>(ws);
+    int64_t r1, r2;
+    batch_layout(b, A, b->max_pitems, r1, r2);
+    if (A.off > ws_bytes) {
+      b->built = false;
+      return bfail(MT_ECAPACITY, "mt_batch_build: workspace smaller than mt_batch_workspace_size");
+    }
   }
+  drop_graphs(b);
   b->nq = p0.rule;
   b->dual = p0.lm_basis == MT_BASIS_DUAL;
   b->nodal = p0.normals == MT_NORMALS_NODAL;
@@ -596,6 +653,7 @@ int mt_batch_build(mt_batch* b, const mt_batch_tuning* tuning, void* stream) {
   if (t.blocks_per_cu <= 0) t.blocks_per_cu = resident;
   t.blocks_per_cu = std::min(t.blocks_per_cu, resident);
   if (t.bucket <= 0) t.bucket = 4 * 64;
+  t.bucket = std::max(t.bucket, MIN_BUCKET);
   b->tune = t;
 
   b->h_inst.assign(b->ctxs.size(), BatchInst{});
@@ -604,21 +662,10 @@ int mt_batch_build(mt_batch* b, const mt_batch_tuning* tuning, void* stream) {
   for (size_t i = 0; i < b->ctxs.size(); ++i) {
     mt_ctx* c = b->ctxs[i];
     {
-      int rc = ensure_master_index(c, st);
-      if (!rc && b->nodal) rc = ensure_normals(c, st);
-      if (rc) return rc;
+      int rc2 = ensure_master_index(c, st);
+      if (!rc2 && b->nodal) rc2 = ensure_normals(c, st);
+      if (rc2) return rc2;
     }
-    const int64_t np = std::max<int64_t>(c->n_pairs, 1);
-    B_HIP(ensure(c->blk, sizeof(double) * 36 * (size_t)np));
-    B_HIP(ensure(c->gpair, sizeof(double) * 24 * (size_t)np));
-    if (b->nodal) {
-      const DeviceMesh& Sn = c->side[0];
-      B_HIP(ensure(c->gn0, sizeof(double) * 3 * (size_t)np));
-      B_HIP(ensure(c->nrm_sb, sizeof(double) * 4 * (size_t)std::max(Sn.n_el, 1)));
-      B_HIP(ensure(c->nrm_ub, sizeof(double) * 4 * (size_t)std::max(Sn.n_nodes, 1)));
-      B_HIP(ensure(c->nrm_cg, sizeof(double) * 12 * (size_t)std::max(Sn.n_el, 1)));
-    }
-    B_HIP(ensure(c->counters, sizeof(Counters)));
     const DeviceMesh& S = c->side[0];
     const DeviceMesh& M = c->side[1];
     BatchInst& I = b->h_inst[i];
@@ -632,6 +679,7 @@ int mt_batch_build(mt_batch* b, const mt_batch_tuning* tuning, void* stream) {
     I.pair_s = c->pair_s.as<int32_t>();
     I.pair_m = c->pair_m.as<int32_t>();
     I.n_pairs = c->n_pairs;
+    I.stride = c->cap.pairs;
     I.pair_off = c->pair_off.as<int32_t>();
     I.inc_off = c->inc_off.as<int32_t>();
     I.inc_list = c->inc_list.as<int32_t>();
@@ -648,10 +696,11 @@ int mt_batch_build(mt_batch* b, const mt_batch_tuning* tuning, void* stream) {
     I.gpair = c->gpair.as<double>();
     I.gn0 = b->nodal ? c->gn0.as<double>() : nullptr;
     {
-      int rc = ensure_poly(c);
-      if (rc) return rc;
+      int rc2 = ensure_poly(c);
+      if (rc2) return rc2;
     }
     I.poly = poly_buf(c);
+    I.cnt = c->counters.as<Counters>();
     I.kp = kparams(c->params);
     for (int r = 0; r < S.n_nodes; r += ROWS_PER_ITEM) {
       const WorkItem w{(int32_t)i, r, std::min(S.n_nodes, r + ROWS_PER_ITEM), 0};
@@ -664,21 +713,17 @@ int mt_batch_build(mt_batch* b, const mt_batch_tuning* tuning, void* stream) {
   b->n_ritems_s = (int)rs.size();
   b->n_ritems_sm = (int)rsm.size();
   B_HIP(hipStreamSynchronize(st));
-  B_HIP(ensure(b->d_ritems_s, sizeof(WorkItem) * std::max<size_t>(1, rs.size())));
-  B_HIP(ensure(b->d_ritems_sm, sizeof(WorkItem) * std::max<size_t>(1, rsm.size())));
   if (!rs.empty()) B_HIP(hipMemcpy(b->d_ritems_s.p, rs.data(), sizeof(WorkItem) * rs.size(), hipMemcpyHostToDevice));
   if (!rsm.empty())
     B_HIP(hipMemcpy(b->d_ritems_sm.p, rsm.data(), sizeof(WorkItem) * rsm.size(), hipMemcpyHostToDevice));
   const size_t ib = sizeof(BatchInst) * b->h_inst.size();
-  B_HIP(ensure(b->d_inst, ib));
-  B_HIP(ensure(b->counters, sizeof(Counters)));
-  B_HIP(hipMemset(b->counters.p, 0, sizeof(Counters)));
+  B_HIP(fill_i32(b->counters.as<int32_t>(), 0, sizeof(Counters) / 4, st));
   if (b->pinned) (void)hipHostFree(b->pinned);
   b->pinned = nullptr;
   B_HIP(hipHostMalloc((void**)&b->pinned, ib, hipHostMallocDefault));
   std::memcpy(b->pinned, b->h_inst.data(), ib);
   B_HIP(hipMemcpy(b->d_inst.p, b->pinned, ib, hipMemcpyHostToDevice));
-  int rc = build_items(b, st);
+  rc = build_items(b, st);
   if (rc) return rc;
   b->built = true;
   return MT_OK;

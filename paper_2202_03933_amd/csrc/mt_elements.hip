@@ -114,15 +114,18 @@ __device__ __forceinline__ void master_quad(const MeshPtrs& M, int m, const doub
 template <bool DUAL>
 __global__ __launch_bounds__(BSE) __attribute__((amdgpu_waves_per_eu(3))) void k_elem_fwd(
     MeshPtrs S, MeshPtrs M, KParams kp, GaussTab gt, const int32_t* __restrict__ pair_s,
-    const int32_t* __restrict__ pair_m, const int32_t* __restrict__ pair_off, int64_t n_pairs,
+    const int32_t* __restrict__ pair_m, const int32_t* __restrict__ pair_off, const int32_t* __restrict__ n_dev,
     double* __restrict__ blk, int64_t stride, Counters* cnt) {
   __shared__ double sq[8][BSE];
   __shared__ double sg[8], sw[8];
+  const int64_t n_pairs = *n_dev;
+  const int64_t tile = dyn_tile(blockIdx.x, n_pairs, BSE);
+  if (tile < 0) return;  // the whole block
   if (threadIdx.x < 8) {
     sg[threadIdx.x] = gt.x[threadIdx.x];
     sw[threadIdx.x] = gt.w[threadIdx.x];
   }
-  const int64_t base = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * BSE;
+  const int64_t base = tile * BSE;
   const int64_t p = base + threadIdx.x;
   const bool valid = p < n_pairs;
   const int s = valid ? pair_s[p] : 0;
@@ -296,9 +299,9 @@ void gauss_table(int n, GaussTab& t) {
 }  // namespace
 
 hipError_t launch_elem_fwd(const DeviceMesh& S, const DeviceMesh& M, const KParams& kp, const int32_t* pair_s,
-                           const int32_t* pair_m, const int32_t* pair_off, int64_t n_pairs, double* blk,
-                           int64_t stride, Counters* cnt, hipStream_t s) {
-  if (n_pairs == 0) return hipSuccess;
+                           const int32_t* pair_m, const int32_t* pair_off, const int32_t* n_pairs, int64_t cap,
+                           double* blk, int64_t stride, Counters* cnt, hipStream_t s) {
+  if (cap == 0) return hipSuccess;
   if (kp.elem < 1 || kp.elem > 8) return hipErrorInvalidValue;
   static GaussTab tabs[9];
   static std::once_flag once;
@@ -306,7 +309,7 @@ hipError_t launch_elem_fwd(const DeviceMesh& S, const DeviceMesh& M, const KPara
     for (int n = 1; n <= 8; ++n) gauss_table(n, tabs[n]);
   });
   const MeshPtrs ms{S.x, S.y, S.z, S.conn, S.nrm}, mm{M.x, M.y, M.z, M.conn, nullptr};
-  const unsigned nb = xcd_grid((unsigned)((n_pairs + BSE - 1) / BSE));
+  const unsigned nb = xcd_grid((unsigned)((cap + BSE - 1) / BSE));
   if (kp.dual)
     k_elem_fwd<true><<<nb, BSE, 0, s>>>(ms, mm, kp, tabs[kp.elem], pair_s, pair_m, pair_off, n_pairs, blk, stride, cnt);
   else

@@ -53,6 +53,14 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned grid) {
   return (b % 8) * per + b / 8;
 }
 
+// Launches over a count the device holds (the grid sized for a capacity):
+// block b takes tile xcd_tile(b, g) of the g = xcd_grid(tiles of n) blocks a
+// launch over exactly n items would have; blocks past g have no tile (-1).
+__device__ __forceinline__ int64_t dyn_tile(unsigned b, int64_t n, int bs) {
+  const unsigned g = xcd_grid((unsigned)((n + bs - 1) / bs));
+  return b < g ? (int64_t)xcd_tile(b, g) : int64_t(-1);
+}
+
 __device__ __forceinline__ int4 load_conn(const int32_t* conn, int e) {
   return reinterpret_cast<const int4*>(conn)[e];
 }
@@ -352,7 +360,7 @@ __device__ __forceinline__ double poly_fan_area(const LdsPoly<LAB>& P, int b, in
 }
 
 // Status bits of one pair evaluation.
-enum : int { PS_DEGEN_SLAVE = 1, PS_DEGEN_MASTER = 2, PS_OVERFLOW = 4 };
+enum : int { PS_DEGEN_SLAVE = 1, PS_DEGEN_MASTER = 2, PS_OVERFLOW = 4, PS_LOST = 8 };
 
 // Projection, orientation, clip and cleanup of one candidate.  On return:
 // S, Mn = projected slave / master nodes (node order), hs, hm = heights,

@@ -13,15 +13,28 @@
 
 namespace mt {
 
-// Grow-only device allocation owned by a context.
+// A region of the caller's workspace.  The library allocates no device
+// memory: every buffer is carved from the workspace bound by mt_build_pairs
+// (or mt_batch_build) at a fixed offset, so its size is known up front.
 struct Buf {
   void* p = nullptr;
   size_t bytes = 0;
   template <class T> T* as() const { return static_cast<T*>(p); }
 };
-hipError_t ensure(Buf& b, size_t bytes);
-void release(Buf& b);
 
+// Carves buffers from a base pointer in a fixed order (256-byte aligned);
+// with a null base it only sums their sizes.
+struct Arena {
+  char* base = nullptr;
+  size_t off = 0;
+  void take(Buf& b, size_t bytes) {
+    off = (off + 255) & ~size_t(255);
+    if (bytes == 0) bytes = 16;
+    b.p = base ? base + off : nullptr;
+    b.bytes = bytes;
+    off += bytes;
+  }
+};
 struct DeviceMesh {
   const double* x = nullptr;
   const double* y = nullptr;
@@ -64,6 +77,28 @@ struct Counters {
   unsigned long long overflow;
   unsigned long long degen_slave;
   unsigned long long degen_master;
+  unsigned long long degen_poly;  // pair polygons lost after a coordinate update
+};
+
+// Device-side state of a build: the search grid and the data-dependent
+// counts, which the kernels read so that the host need not (no read-back
+// between the launches of a build).  Counts are clamped to the capacities;
+// the flags say which capacity was exceeded.
+enum : uint32_t {
+  DS_CAP_CAND = 1u,      // more candidates than their capacity
+  DS_CAP_SCREENED = 2u,  // more screened candidates than their capacity
+  DS_CAP_PAIRS = 4u,     // more pairs than their capacity
+  DS_NONFINITE = 8u,     // a coordinate is NaN or infinite
+};
+struct DevState {
+  Grid grid;
+  int32_t n_cand;         // candidates found (may exceed the capacity: DS_CAP_CAND)
+  int32_t n_screened;     // screened candidates kept, <= capacity
+  int32_t n_pairs;        // pairs kept, <= capacity
+  int32_t need_screened;  // screened candidates among the kept candidates
+  int32_t need_pairs;     // pairs among the kept screened candidates
+  uint32_t flags;         // DS_* bits
+  int32_t pad[2];
 };
 
 // Clip polygons of the pairs, structure-of-arrays over the pair index p:
@@ -109,12 +144,21 @@ struct mt_ctx {
   mt::DeviceMesh side[2];
   hipStream_t last_stream = nullptr;
 
+  // the caller's workspace bound by the last mt_build_pairs and its layout
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  mt_capacity cap{};
+  int32_t lay_n[4] = {-1, -1, -1, -1};  // slave/master nodes and elements the layout was made for
+  int32_t lay_nodal = -1;
+  uint64_t static_gen = 0;  // binding of the static scratch (mt_build_pairs_static), 0: none
+
   // state flags
   bool have_pairs = false;
   bool have_pattern = false;
   bool have_master_index = false;
   bool have_inc[2] = {false, false};  // node incidence of each side (depends on connectivity only)
-  int64_t n_cand = 0, n_pairs = 0, nnz_D = 0, nnz_M = 0;
+  bool counts_known = false;  // n_cand .. nnz_M read back since the last build / pattern
+  int64_t n_cand = 0, n_maybe = 0, n_pairs = 0, nnz_D = 0, nnz_M = 0;
   mt::Grid grid{};
 
   // element preparation
@@ -124,29 +168,29 @@ struct mt_ctx {
   mt::Buf reduce;          // PrepReduce
   mt::Buf prep_part;       // per-block partials of the element preparation
   mt::Buf counters;        // Counters
+  mt::Buf state;           // DevState
   // binning
-  mt::Buf keys, vals, keys_tmp, vals_tmp;
-  mt::Buf cell_range;      // int2 [ncells]: sorted-master range of each cell
+  mt::Buf keys, vals, keys_tmp, vals_tmp;  // [max(n_m_el, pair capacity)]
+  mt::Buf cell_range;      // int2 [cell capacity]: sorted-master range of each cell
   mt::Buf sbox;            // [n_m_el][6] master boxes in cell order
   // candidates
   mt::Buf cand_cnt;        // [n_s_el + 1]
   mt::Buf cand_tmp;        // [CTMP][n_s_el] candidates kept by the count pass
   mt::Buf cand_off;        // [n_s_el + 1]
-  mt::Buf cand_s, cand_m;  // [n_cand]
-  mt::Buf cand_nv;         // uint8 [n_cand]
-  mt::Buf cand_flag;       // int32 [n_cand] 1 = screened in (to be clipped)
+  mt::Buf cand_s, cand_m;  // [candidate capacity]
+  mt::Buf cand_nv;         // uint8 [candidate capacity]
+  mt::Buf cand_flag;       // int32 [candidate capacity] 1 = screened in (to be clipped)
   mt::Buf scr_cnt;         // int32 [n_s + 1] screened-in candidates per slave element
   mt::Buf scr_off;         // int32 [n_s + 1] exclusive scan of scr_cnt
-  // screened candidates (index i < n_maybe)
-  int64_t n_maybe = 0;
-  mt::Buf maybe_list;      // int32 [n_maybe] candidate index
-  mt::Buf maybe_flag;      // int32 [n_maybe + 1] 1 = pair
-  mt::Buf maybe_scan;      // int32 [n_maybe + 1] exclusive scan of maybe_flag
+  // screened candidates (index i < DevState::n_screened)
+  mt::Buf maybe_list;      // int32 [screened capacity] candidate index
+  mt::Buf maybe_flag;      // int32 [screened capacity + 1] 1 = pair
+  mt::Buf maybe_scan;      // int32 [screened capacity + 1] exclusive scan of maybe_flag
   mt::Buf mpoly_u, mpoly_v, mpoly_lab, mpoly_nf;  // their clip polygons (PolyBuf layout)
   int64_t mpoly_stride = 1;
-  // pairs
-  mt::Buf pair_s, pair_m;  // [n_pairs]
-  mt::Buf pair_nv;         // uint8 [n_pairs]
+  // pairs (index p < DevState::n_pairs; per-pair arrays have stride cap.pairs)
+  mt::Buf pair_s, pair_m;  // [pair capacity]
+  mt::Buf pair_nv;         // uint8 [pair capacity]
   mt::Buf pair_off;        // [n_s_el + 1] first pair of each slave element
   // pattern
   mt::Buf inc_cnt, inc_off, inc_cur, inc_list;     // slave node -> (element*4 + local)
@@ -154,19 +198,19 @@ struct mt_ctx {
   mt::Buf pat_keep;        // per-row column lists kept between the pattern passes
   mt::Buf pat_ecnt;        // int32 [n_s_el] master nodes of each slave element's pairs (-1: too many)
   mt::Buf pat_elist;       // int32 [EL][n_s_el] those master nodes, sorted
-  mt::Buf D_cnt, D_rowptr, D_col;
-  mt::Buf M_cnt, M_rowptr, M_col;
+  mt::Buf D_cnt, D_rowptr, D_col;  // D_col: [16 n_s_el] (bound of nnz(D))
+  mt::Buf M_cnt, M_rowptr, M_col;  // M_col: [16 pair capacity] (bound of nnz(M))
   mt::Buf posD;            // [16][n_s_el]
-  mt::Buf posM;            // [16][n_pairs]
+  mt::Buf posM;            // [16][pair capacity]
   // clip polygons of the pairs (mt::PolyBuf); valid for the coordinates of
   // generation poly_gen (coord_gen counts coordinate and pair-list changes)
-  mt::Buf pair_slot;       // int32 [n_pairs] entry of each pair's polygon in the mpoly buffers
+  mt::Buf pair_slot;       // int32 [pair capacity] entry of each pair's polygon in the mpoly buffers
   int64_t coord_gen = 0, poly_gen = -1;
   int64_t pattern_gen = 0;  // counts completed mt_csr_pattern calls
   // forward / backward staging
   mt::Buf nrm_node;        // [n_s_nodes][4] nodal normals (continuous normal field)
   mt::Buf nrm_el;          // [n_s_el][4] element plane normals
-  mt::Buf gn0;             // [3][n_pairs] dL/dn0 per pair
+  mt::Buf gn0;             // [3][pair capacity] dL/dn0 per pair
   mt::Buf nrm_sb, nrm_ub, nrm_cg;
   int64_t nrm_gen = -1;    // coord_gen of nrm_node / nrm_el
   // internal stream on which mt_csr_pattern computes the pair blocks and the
@@ -174,26 +218,35 @@ struct mt_ctx {
   hipStream_t aux = nullptr;
   hipEvent_t aux_fork = nullptr, aux_join = nullptr;
   mt::Buf aux_hist, aux_scan;
-  mt::Buf blk;             // [36][n_pairs]
+  mt::Buf blk;             // [36][pair capacity]
   int64_t blk_gen = -1;    // coord_gen of the blocks in blk (mt_integrate)
   bool blk_pending = false;  // blocks computed by mt_csr_pattern, not yet assembled
-  mt::Buf gpair;           // [24][n_pairs]
+  mt::Buf gpair;           // [24][pair capacity]
   mt::Buf mp_keys, mp_vals, mp_off;  // pairs sorted by master element
-  mt::Buf mp_pos;          // int32 [n_pairs]: rank of each pair in that order
+  mt::Buf mp_pos;          // int32 [pair capacity]: rank of each pair in that order
   // scan / sort scratch
   mt::Buf scan_tmp, sort_hist;
-  void* pin = nullptr;     // pinned host staging of the small read-backs (counts, maxima)
+  void* pin = nullptr;     // pinned host memory: read-backs and the connectivity check
 };
 
 namespace mt {
 
 // ---- primitives (mt_prims.hip) ------------------------------------------
+// Scratch (int32 elements) of a scan of up to n values.
+int64_t scan_tmp_elems(int64_t n);
 // Exclusive prefix sum of n int32 values into out[0..n]; out[n] = total.
-hipError_t scan_exclusive(const int32_t* in, int32_t* out, int64_t n, Buf& tmp, hipStream_t s);
+hipError_t scan_exclusive(const int32_t* in, int32_t* out, int64_t n, const Buf& tmp, hipStream_t s);
+// The same over a count the device holds (*n_dev <= cap): out[0..cap] with
+// the values from *n_dev on taken as zero, so out[*n_dev] = total.
+hipError_t scan_exclusive_dev(const int32_t* in, int32_t* out, const int32_t* n_dev, int64_t cap, const Buf& tmp,
+                              hipStream_t s);
+// Histogram scratch (int32 elements) of a radix sort of up to n keys.
+int64_t radix_hist_elems(int64_t n);
 // Stable LSD radix sort of (key, value) pairs on key bits [0, bits).
 // Results end in (keys, vals); (keys_tmp, vals_tmp) are scratch of size n.
-hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp,
-                            int64_t n, int bits, Buf& hist, Buf& scan_tmp, hipStream_t s);
+// With n_dev, only the first *n_dev <= n pairs are sorted.
+hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp, int64_t n,
+                            const int32_t* n_dev, int bits, const Buf& hist, const Buf& scan_tmp, hipStream_t s);
 hipError_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 hipError_t fill_f64(double* p, double v, int64_t n, hipStream_t s);
 
@@ -204,50 +257,64 @@ int prep_blocks(int32_t n_el);
 hipError_t launch_prep(const DeviceMesh& m, bool slave, double* box, double* sd, double* md, double* part,
                        hipStream_t s);
 hipError_t launch_prep_reduce(const double* part, int nb_s, int nb_m, PrepReduce* red, hipStream_t s);
-void grid_from_reduce(const PrepReduce& r, double delta, double bin_size, Grid& g);
-hipError_t launch_master_keys(const double* box_m, int32_t n_m, Grid g, uint32_t* keys, uint32_t* vals,
+// The search grid (st->grid) from the reductions, at most max_cells cells;
+// flags non-finite coordinates.
+hipError_t launch_grid(const PrepReduce* red, double delta, double bin_size, int64_t max_cells, DevState* st,
+                       hipStream_t s);
+hipError_t launch_master_keys(const double* box_m, int32_t n_m, const Grid* g, uint32_t* keys, uint32_t* vals,
                               hipStream_t s);
+hipError_t launch_clear_cells(int2* range, const Grid* g, int64_t max_cells, hipStream_t s);
 hipError_t launch_cell_ranges(const uint32_t* keys, const uint32_t* vals, int32_t n, const double* box_m,
                               int2* range, double* sbox, hipStream_t s);
 hipError_t launch_cand_count(const double* box_s, int32_t n_s, const double* sbox, const uint32_t* mvals,
-                             const int2* range, Grid g, double delta, int32_t* count, int32_t* tmp, hipStream_t s);
+                             const int2* range, const Grid* g, double delta, int32_t* count, int32_t* tmp,
+                             hipStream_t s);
 // Candidates of slave s go to [off[s], off[s + 1]) of cand_s / cand_m / nv /
 // flag, whose length is cap: a slave whose range ends beyond cap writes
-// nothing and gets scr_cnt[s] = 0 (the host compares off[n_s] with cap).
+// nothing and gets scr_cnt[s] = 0 (the stage totals flag the excess).
 hipError_t launch_cand_fill(const double* box_s, int32_t n_s, const double* sbox, const uint32_t* mvals,
-                            const int2* range, Grid g, double delta, const int32_t* tmp, const int32_t* off,
+                            const int2* range, const Grid* g, double delta, const int32_t* tmp, const int32_t* off,
                             int32_t* cand_s, int32_t* cand_m, const double* sd, const double* md, double eps_a,
                             uint8_t* nv, int32_t* flag, int32_t* scr_cnt, Counters* cnt, int64_t cap,
                             hipStream_t s);
 int cand_tmp_per_slave();
 
 // ---- pairs (mt_pairs.hip) ----------------------------------------------------
+// Stage totals into the device state: stage 0 candidates (vec[idx]), 1
+// screened candidates (vec[idx]), 2 pairs (vec[st->n_screened]); clamped to
+// cap, the excess flagged.
+hipError_t launch_stage_totals(int stage, const int32_t* vec, int64_t idx, int64_t cap, DevState* st,
+                               hipStream_t s);
 // Histogram of clip vertex counts nv[0..n) added to hist[17].
 hipError_t launch_nv_hist(const uint8_t* nv, int64_t n, unsigned long long* hist, hipStream_t s);
 hipError_t launch_maybe_list(const int32_t* flag, const int32_t* cand_off, const int32_t* scr_off, int32_t n_s,
-                             int32_t* mlist, hipStream_t s);
+                             int64_t cap_cand, int64_t cap, int32_t* mlist, hipStream_t s);
 hipError_t launch_clip_screened(const double* mdata, const double* sdata, int32_t n_s, const KParams& kp,
-                                const int32_t* cand_s, const int32_t* cand_m, const int32_t* mlist, int64_t n_maybe,
-                                uint8_t* nv, int32_t* flag2, const PolyBuf& out, Counters* cnt, hipStream_t s);
+                                const int32_t* cand_s, const int32_t* cand_m, const int32_t* mlist,
+                                const int32_t* n_maybe, int64_t cap, uint8_t* nv, int32_t* flag2, const PolyBuf& out,
+                                Counters* cnt, hipStream_t s);
 hipError_t launch_compact_pairs(const int32_t* cand_s, const int32_t* cand_m, const int32_t* mlist,
-                                const int32_t* flag2, const int32_t* scan2, int64_t n_maybe, const uint8_t* nf,
-                                int32_t* pair_s, int32_t* pair_m, uint8_t* pair_nv, int32_t* pair_slot,
-                                hipStream_t s);
-hipError_t launch_pair_off(const int32_t* scr_off, const int32_t* scan2, int32_t n_s, int32_t* pair_off,
-                           hipStream_t s);
+                                const int32_t* flag2, const int32_t* scan2, const int32_t* n_maybe, int64_t cap_maybe,
+                                const uint8_t* nf, int32_t* pair_s, int32_t* pair_m, uint8_t* pair_nv,
+                                int32_t* pair_slot, int64_t cap_pairs, hipStream_t s);
+hipError_t launch_pair_off(const int32_t* scr_off, const int32_t* scan2, int32_t n_s, const DevState* st,
+                           int32_t* pair_off, hipStream_t s);
+// Kernels over the pairs take the device count n_pairs (<= cap, the stride
+// of the per-pair arrays).
 hipError_t launch_pair_poly(const DeviceMesh& S, const DeviceMesh& M, const KParams& kp, const int32_t* pair_s,
-                            const int32_t* pair_m, int64_t n_pairs, const PolyBuf& poly, hipStream_t s);
+                            const int32_t* pair_m, const int32_t* n_pairs, int64_t cap, const PolyBuf& poly,
+                            Counters* cnt, hipStream_t s);
 hipError_t launch_pair_fwd(const DeviceMesh& S, const DeviceMesh& M, const KParams& kp, const int32_t* pair_s,
-                           const int32_t* pair_m, int64_t n_pairs, const PolyBuf& poly, double* blk,
-                           int64_t blk_stride, Counters* cnt, hipStream_t s);
+                           const int32_t* pair_m, const int32_t* n_pairs, int64_t cap, const PolyBuf& poly,
+                           double* blk, int64_t blk_stride, Counters* cnt, hipStream_t s);
 
 // ---- element-based integration (mt_elements.hip) -----------------------------
 // Blocks of every pair by the kp.elem x kp.elem Gauss rule on each slave
 // element (pairs sorted by slave; those of element e: pair_off[e] ..
 // pair_off[e + 1]).
 hipError_t launch_elem_fwd(const DeviceMesh& S, const DeviceMesh& M, const KParams& kp, const int32_t* pair_s,
-                           const int32_t* pair_m, const int32_t* pair_off, int64_t n_pairs, double* blk,
-                           int64_t stride, Counters* cnt, hipStream_t s);
+                           const int32_t* pair_m, const int32_t* pair_off, const int32_t* n_pairs, int64_t cap,
+                           double* blk, int64_t stride, Counters* cnt, hipStream_t s);
 
 // ---- assembly (mt_assemble.hip) ----------------------------------------------
 hipError_t launch_inc_count(const int32_t* conn, int32_t n_el, int32_t* cnt, hipStream_t s);
@@ -258,7 +325,7 @@ hipError_t launch_pattern_rows(bool fill, const int32_t* inc_off, const int32_t*
                                const int32_t* pair_off, const int32_t* pair_m, const int32_t* conn_s,
                                const int32_t* conn_m, int32_t* D_cnt, int32_t* M_cnt, const int32_t* D_rowptr,
                                const int32_t* M_rowptr, int32_t* D_col, int32_t* M_col, int32_t* keep, int32_t* posD,
-                               int32_t n_s_el, int32_t* posM, int64_t n_pairs, int32_t* ecnt, int32_t* elist,
+                               int32_t n_s_el, int32_t* posM, int64_t pstride, int32_t* ecnt, int32_t* elist,
                                hipStream_t s);
 hipError_t launch_elem_mlist(int32_t n_s_el, const int32_t* pair_off, const int32_t* pair_m, const int32_t* conn_m,
                              int32_t* ecnt, int32_t* elist, hipStream_t s);
@@ -272,8 +339,9 @@ hipError_t launch_grad_slave(const int32_t* inc_off, const int32_t* inc_list, in
                              const int32_t* pair_off, const double* gpair, int64_t stride, double* gX,
                              hipStream_t s);
 // Master ranges of the pairs-by-master order and each pair's rank in it.
-hipError_t launch_mpair_off(const uint32_t* sorted_m, const uint32_t* mpairs, int64_t n_pairs, int32_t n_m_el,
-                            int32_t* off, int32_t* mpos, hipStream_t s);
+hipError_t launch_iota(uint32_t* v, const int32_t* n_dev, int64_t cap, hipStream_t s);
+hipError_t launch_mpair_off(const uint32_t* sorted_m, const uint32_t* mpairs, const int32_t* n_pairs, int64_t cap,
+                            int32_t n_m_el, int32_t* off, int32_t* mpos, hipStream_t s);
 hipError_t launch_grad_master(const int32_t* inc_off, const int32_t* inc_list, int32_t n_nodes,
                               const int32_t* mstart, const int32_t* mend, const double* gpair, int64_t stride,
                               double* gX, hipStream_t s);
@@ -286,7 +354,7 @@ hipError_t launch_grad_master(const int32_t* inc_off, const int32_t* inc_list, i
 // normal field (S.nrm), gn0[d * stride + p] receives the gradient with
 // respect to the slave element's plane normal; else gn0 is null.
 hipError_t launch_pair_bwd(const DeviceMesh& S, const DeviceMesh& M, const KParams& kp, const int32_t* pair_s, const int32_t* pair_m,
-                           int64_t n_pairs, const PolyBuf& poly, const int32_t* mpos, const int32_t* posD, int32_t n_s_el, const int32_t* posM,
+                           const int32_t* n_pairs, int64_t cap, const PolyBuf& poly, const int32_t* mpos, const int32_t* posD, int32_t n_s_el, const int32_t* posM,
                            const double* W_D, const double* W_M, const double* w_g, const double* blk,
                            double* gpair, double* gn0, int64_t stride, Counters* cnt, hipStream_t s);
 
@@ -316,10 +384,18 @@ KParams kparams(const mt_params& p);
 int ensure_master_index(mt_ctx* c, hipStream_t st);
 // The same on a given stream with its own sort scratch (the master incidence
 // must exist already).
-int build_master_index(mt_ctx* c, hipStream_t st, Buf& hist, Buf& scan_tmp);
-// Polygon buffers sized for the current pair list, and their view.
+int build_master_index(mt_ctx* c, hipStream_t st, const Buf& hist, const Buf& scan_tmp);
+// Polygon buffers of the current pair list, and their view.
 int ensure_poly(mt_ctx* c);
 PolyBuf poly_buf(mt_ctx* c);
+// Device count of pairs of the current build.
+const int32_t* dev_n_pairs(mt_ctx* c);
+// The counts of the last build / pattern on the host (synchronises the last
+// stream when they have not been read back yet).
+int host_counts(mt_ctx* c);
+// MT_OK while the context's workspace still holds its build (MT_ESTATE once
+// another context bound the static scratch this one was built in).
+int ws_live(mt_ctx* c);
 void set_error(const std::string& msg);
 
 }  // namespace mt

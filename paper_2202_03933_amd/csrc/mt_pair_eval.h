@@ -74,8 +74,10 @@ __device__ __forceinline__ void poly_store(const LdsPoly<true>& P, int res, int 
 }
 
 // Frame, projection, orientation, clip and cleanup of pair p; stores the
-// polygon and its provenance.
-__device__ __forceinline__ void store_pair_polygon(const double Xs[4][3], const double Xm[4][3], const double* ns,
+// polygon and its provenance.  Returns the clip status bits (PS_*), with
+// PS_LOST when the polygon is no longer a segment at these coordinates (the
+// pair then contributes nothing).
+__device__ __forceinline__ int store_pair_polygon(const double Xs[4][3], const double Xm[4][3], const double* ns,
                                                    const KParams& kp, const LdsPoly<true>& P, const PolyBuf& out,
                                                    int64_t p) {
   double f[12];
@@ -86,6 +88,7 @@ __device__ __forceinline__ void store_pair_polygon(const double Xs[4][3], const 
   bool flip;
   const int n = pair_geometry<true>(Xs, Xm, f, kp.eps_d, kp.eps_a, S, Mn, hs, hm, flip, P, res, st);
   poly_store(P, res, n, flip, out, out.at(p));
+  return st | (n >= 3 ? 0 : PS_LOST);
 }
 
 // Projected nodes and heights of both elements on the slave plane f.
@@ -350,6 +353,15 @@ if (n >= 3) {
     u1 = u2;
     v1 = v2;
   }
+}
+if (n < 3) {
+  // no segment (a pair lost after a coordinate update): no contribution, and
+  // no dual coefficients of a possibly degenerate slave element
+#pragma unroll
+  for (int k = 0; k < 16; ++k) D[k] = M[k] = 0.0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) g[k] = 0.0;
+  return;
 }
 double hs[4], hm[4];
 heights(hs, hm);

@@ -43,8 +43,19 @@ __device__ __forceinline__ T block_exclusive(T x, T* total) {
   return off + inc - x;
 }
 
+// n_dev (optional): a count the device holds, at most n; entries from it on
+// count as zero.
 template <class T>
-__global__ __launch_bounds__(SCAN_BS) void k_tile_sums(const T* __restrict__ in, int64_t n, T* __restrict__ sums) {
+__device__ __forceinline__ int64_t live_count(int64_t n, const int32_t* n_dev) {
+  if (!n_dev) return n;
+  const int64_t m = *n_dev;
+  return m < 0 ? 0 : (m < n ? m : n);
+}
+
+template <class T>
+__global__ __launch_bounds__(SCAN_BS) void k_tile_sums(const T* __restrict__ in, int64_t n, const int32_t* n_dev,
+                                                       T* __restrict__ sums) {
+  n = live_count<T>(n, n_dev);
   const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IPT;
   T s = 0;
 #pragma unroll
@@ -58,14 +69,15 @@ __global__ __launch_bounds__(SCAN_BS) void k_tile_sums(const T* __restrict__ in,
 // out[i] = offs[tile] + exclusive prefix of in within the tile; the last
 // tile also writes out[n] = grand total.
 template <class T>
-__global__ __launch_bounds__(SCAN_BS) void k_tile_scan(const T* __restrict__ in, int64_t n,
+__global__ __launch_bounds__(SCAN_BS) void k_tile_scan(const T* __restrict__ in, int64_t n, const int32_t* n_dev,
                                                        const T* __restrict__ offs, T* __restrict__ out) {
+  const int64_t live = live_count<T>(n, n_dev);
   const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IPT;
   T v[SCAN_IPT];
   T s = 0;
 #pragma unroll
   for (int i = 0; i < SCAN_IPT; ++i) {
-    v[i] = (base + i < n) ? in[base + i] : T(0);
+    v[i] = (base + i < live) ? in[base + i] : T(0);
     s += v[i];
   }
   T tot;
@@ -78,25 +90,29 @@ __global__ __launch_bounds__(SCAN_BS) void k_tile_scan(const T* __restrict__ in,
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_BS - 1) out[n] = run;
 }
 
+// Exclusive scan of n values (of the first *n_dev when given; the rest count
+// as zero) into out[0..n].  No memset: the launches can be captured in a
+// graph.
 template <class T>
-hipError_t scan_impl(const T* in, T* out, int64_t n, T* tmp, hipStream_t s) {
-  const int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
-  if (n == 0) return hipMemsetAsync(out, 0, sizeof(T), s);
+hipError_t scan_impl(const T* in, T* out, int64_t n, const int32_t* n_dev, T* tmp, hipStream_t s) {
+  const int64_t tiles = std::max<int64_t>(1, (n + SCAN_TILE - 1) / SCAN_TILE);
   if (tiles == 1) {
-    k_tile_scan<T><<<1, SCAN_BS, 0, s>>>(in, n, nullptr, out);
+    k_tile_scan<T><<<1, SCAN_BS, 0, s>>>(in, n, n_dev, nullptr, out);
     return hipGetLastError();
   }
   T* sums = tmp;
   T* offs = tmp + tiles;  // tiles + 1 entries
   T* rest = offs + tiles + 1;
-  k_tile_sums<T><<<(unsigned)tiles, SCAN_BS, 0, s>>>(in, n, sums);
+  k_tile_sums<T><<<(unsigned)tiles, SCAN_BS, 0, s>>>(in, n, n_dev, sums);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  e = scan_impl<T>(sums, offs, tiles, rest, s);
+  e = scan_impl<T>(sums, offs, tiles, nullptr, rest, s);
   if (e != hipSuccess) return e;
-  k_tile_scan<T><<<(unsigned)tiles, SCAN_BS, 0, s>>>(in, n, offs, out);
+  k_tile_scan<T><<<(unsigned)tiles, SCAN_BS, 0, s>>>(in, n, n_dev, offs, out);
   return hipGetLastError();
 }
+
+}  // namespace
 
 int64_t scan_tmp_elems(int64_t n) {
   int64_t total = 0;
@@ -109,6 +125,8 @@ int64_t scan_tmp_elems(int64_t n) {
   return total + 1;
 }
 
+namespace {
+
 // ---- radix sort ------------------------------------------------------------
 
 constexpr int RS_BS = 256;
@@ -117,8 +135,10 @@ constexpr int RS_TILE = RS_BS * RS_IPT;
 constexpr int RS_RADIX = 256;
 
 // Per tile digit histogram, stored digit-major: hist[d * tiles + tile].
-__global__ __launch_bounds__(RS_BS) void k_rs_hist(const uint32_t* __restrict__ keys, int64_t n, int shift,
-                                                    int32_t* __restrict__ hist, int64_t tiles) {
+__global__ __launch_bounds__(RS_BS) void k_rs_hist(const uint32_t* __restrict__ keys, int64_t n,
+                                                    const int32_t* n_dev, int shift, int32_t* __restrict__ hist,
+                                                    int64_t tiles) {
+  n = live_count<int32_t>(n, n_dev);
   __shared__ int32_t h[RS_RADIX];
   h[threadIdx.x] = 0;
   __syncthreads();
@@ -138,8 +158,9 @@ __global__ __launch_bounds__(RS_BS) void k_rs_hist(const uint32_t* __restrict__ 
 // the round, plus the count of earlier rounds.
 __global__ __launch_bounds__(RS_BS) void k_rs_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                        uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                       int64_t n, int shift, const int32_t* __restrict__ offs,
-                                                       int64_t tiles) {
+                                                       int64_t n, const int32_t* n_dev, int shift,
+                                                       const int32_t* __restrict__ offs, int64_t tiles) {
+  n = live_count<int32_t>(n, n_dev);
   __shared__ int32_t run[RS_RADIX];
   __shared__ int32_t wcnt[RS_BS / 64][RS_RADIX];
   run[threadIdx.x] = offs[(int64_t)threadIdx.x * tiles + blockIdx.x];
@@ -200,38 +221,53 @@ __global__ void k_fill_f64(double* p, double v, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
 }
+__global__ void k_copy_u32(const uint32_t* __restrict__ a, uint32_t* __restrict__ b, int64_t n,
+                           const int32_t* n_dev) {
+  n = live_count<int32_t>(n, n_dev);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
+}
 
 }  // namespace
 
-hipError_t scan_exclusive(const int32_t* in, int32_t* out, int64_t n, Buf& tmp, hipStream_t s) {
-  hipError_t e = ensure(tmp, sizeof(int32_t) * (size_t)scan_tmp_elems(n));
-  if (e != hipSuccess) return e;
-  return scan_impl<int32_t>(in, out, n, tmp.as<int32_t>(), s);
+hipError_t scan_exclusive(const int32_t* in, int32_t* out, int64_t n, const Buf& tmp, hipStream_t s) {
+  if ((int64_t)(tmp.bytes / sizeof(int32_t)) < scan_tmp_elems(n)) return hipErrorInvalidValue;
+  return scan_impl<int32_t>(in, out, n, nullptr, tmp.as<int32_t>(), s);
 }
 
+hipError_t scan_exclusive_dev(const int32_t* in, int32_t* out, const int32_t* n_dev, int64_t cap, const Buf& tmp,
+                              hipStream_t s) {
+  if ((int64_t)(tmp.bytes / sizeof(int32_t)) < scan_tmp_elems(cap)) return hipErrorInvalidValue;
+  return scan_impl<int32_t>(in, out, cap, n_dev, tmp.as<int32_t>(), s);
+}
+
+int64_t radix_hist_elems(int64_t n) { return 2 * ((n + RS_TILE - 1) / RS_TILE) * RS_RADIX + 1; }
+
 hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp, int64_t n,
-                            int bits, Buf& hist, Buf& scan_tmp, hipStream_t s) {
+                            const int32_t* n_dev, int bits, const Buf& hist, const Buf& scan_tmp, hipStream_t s) {
   if (n <= 1 || bits <= 0) return hipSuccess;
   const int64_t tiles = (n + RS_TILE - 1) / RS_TILE;
   const int64_t hn = tiles * RS_RADIX;
-  hipError_t e = ensure(hist, sizeof(int32_t) * (size_t)(2 * hn + 1));
-  if (e != hipSuccess) return e;
+  if ((int64_t)(hist.bytes / sizeof(int32_t)) < radix_hist_elems(n)) return hipErrorInvalidValue;
   int32_t* h = hist.as<int32_t>();
   int32_t* off = h + hn;
+  hipError_t e;
   int passes = (bits + 7) / 8;
   uint32_t *ki = keys, *vi = vals, *ko = keys_tmp, *vo = vals_tmp;
   for (int p = 0; p < passes; ++p) {
-    k_rs_hist<<<(unsigned)tiles, RS_BS, 0, s>>>(ki, n, 8 * p, h, tiles);
+    k_rs_hist<<<(unsigned)tiles, RS_BS, 0, s>>>(ki, n, n_dev, 8 * p, h, tiles);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = scan_exclusive(h, off, hn, scan_tmp, s)) != hipSuccess) return e;
-    k_rs_scatter<<<(unsigned)tiles, RS_BS, 0, s>>>(ki, vi, ko, vo, n, 8 * p, off, tiles);
+    k_rs_scatter<<<(unsigned)tiles, RS_BS, 0, s>>>(ki, vi, ko, vo, n, n_dev, 8 * p, off, tiles);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     std::swap(ki, ko);
     std::swap(vi, vo);
   }
   if (ki != keys) {
-    if ((e = hipMemcpyAsync(keys, ki, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
-    if ((e = hipMemcpyAsync(vals, vi, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s)) != hipSuccess) return e;
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    k_copy_u32<<<nb, 256, 0, s>>>(ki, keys, n, n_dev);
+    k_copy_u32<<<nb, 256, 0, s>>>(vi, vals, n, n_dev);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;
 }

@@ -15,7 +15,7 @@ namespace mt {
 namespace {
 
 constexpr int BS = 256;
-constexpr int PREP_PART = 9;  // per-block partials: ext, edge, -lo xyz, hi xyz, bad
+constexpr int PREP_PART = 9;  // per-block partials: ext, edge, -lo xyz, hi xyz, bad (bits)
 
 __device__ __forceinline__ unsigned long long order_key(double x) {
   const unsigned long long b = (unsigned long long)__double_as_longlong(x);
@@ -61,7 +61,7 @@ __global__ __launch_bounds__(BS) void k_prep(const double* __restrict__ x, const
                                               double* __restrict__ box, double* __restrict__ sd,
                                               double* __restrict__ md, double* __restrict__ part) {
   __shared__ double sh[BS / 64][8];
-  __shared__ int bad;
+  __shared__ int bad;  // 1: connectivity out of range, 2: a coordinate not finite
   if (threadIdx.x == 0) bad = 0;
   __syncthreads();
   double ext = 0.0, edge = 0.0;
@@ -71,11 +71,17 @@ __global__ __launch_bounds__(BS) void k_prep(const double* __restrict__ x, const
     const bool ok = c.x >= 0 && c.y >= 0 && c.z >= 0 && c.w >= 0 && c.x < n_nodes && c.y < n_nodes &&
                     c.z < n_nodes && c.w < n_nodes;
     if (!ok) {
-      bad = 1;
+      atomicOr(&bad, 1);
       continue;
     }
     double X[4][3];
     load_nodes(x, y, z, c, X);
+    bool fin = true;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) fin = fin && isfinite(X[k][d]);
+    if (!fin) atomicOr(&bad, 2);
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const double l = fmin(fmin(X[0][d], X[1][d]), fmin(X[2][d], X[3][d]));
@@ -126,7 +132,7 @@ __global__ __launch_bounds__(BS) void k_prep(const double* __restrict__ x, const
     for (int i = 1; i < BS / 64; ++i) m = fmax(m, sh[i][threadIdx.x]);
     part[(int64_t)blockIdx.x * PREP_PART + threadIdx.x] = m;
   }
-  if (threadIdx.x == 8) part[(int64_t)blockIdx.x * PREP_PART + 8] = bad ? 1.0 : 0.0;
+  if (threadIdx.x == 8) part[(int64_t)blockIdx.x * PREP_PART + 8] = (double)bad;
 }
 
 // Final reduction of the per-block partials of both sides (nb_s slave
@@ -137,13 +143,19 @@ __global__ __launch_bounds__(BS) void k_prep_reduce(const double* __restrict__ p
   double v[PREP_PART];
 #pragma unroll
   for (int k = 0; k < PREP_PART; ++k) v[k] = k == 0 || k == 1 || k == 8 ? 0.0 : -INFINITY;
+  int bits = 0;
   for (int b = threadIdx.x; b < nb_s + nb_m; b += BS) {
 #pragma unroll
-    for (int k = 0; k < PREP_PART; ++k) {
+    for (int k = 0; k < PREP_PART - 1; ++k) {
       const double x = part[(int64_t)b * PREP_PART + k];
       if (k != 1 || b < nb_s) v[k] = fmax(v[k], x);
     }
+    bits |= (int)part[(int64_t)b * PREP_PART + 8];
   }
+  __shared__ int sbits;
+  if (threadIdx.x == 0) sbits = 0;
+  __syncthreads();
+  if (bits) atomicOr(&sbits, bits);
 #pragma unroll
   for (int k = 0; k < PREP_PART; ++k) v[k] = wave_max(v[k]);
   if ((threadIdx.x & 63) == 0)
@@ -165,20 +177,79 @@ __global__ __launch_bounds__(BS) void k_prep_reduce(const double* __restrict__ p
       red->lo_key[d] = r[2 + d] > -INFINITY ? order_key(-r[2 + d]) : ~0ull;
       red->hi_key[d] = r[5 + d] > -INFINITY ? order_key(r[5 + d]) : 0ull;
     }
-    red->bad_index = r[8] > 0.0 ? 1 : 0;
+    red->bad_index = sbits;
     red->pad = 0;
   }
 }
 
+// Cell index along one axis, clamped to [0, n); a NaN position (a
+// non-finite coordinate, reported by the preparation) lands in cell 0.
 __device__ __forceinline__ int cell_coord(double c, double lo, double inv_beta, int n) {
-  int i = (int)floor((c - lo) * inv_beta);
-  return i < 0 ? 0 : (i >= n ? n - 1 : i);
+  double t = floor((c - lo) * inv_beta);
+  t = fmax(t, 0.0);
+  t = fmin(t, (double)(n - 1));
+  return (int)t;
 }
 
-__global__ __launch_bounds__(BS) void k_master_keys(const double* __restrict__ box, int32_t n, Grid g,
-                                                     uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+// Search grid from the element reductions (one thread): the minimal bin size
+// beta_min = max(longest slave edge, largest box extent + delta, bin_size)
+// (the paper's rule without a motion term, raised so that 27 cells are
+// complete), the node bounding box expanded by beta_min, max(1, floor(L /
+// beta_min)) cells per axis, the dense cell table coarsened to at most
+// max_cells cells (coarser cells stay complete).
+__global__ void k_grid(const PrepReduce* __restrict__ red, double delta, double bin_size, int64_t max_cells,
+                       DevState* st) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double emax = __longlong_as_double((long long)red->emax_bits);
+  const double edge = __longlong_as_double((long long)red->edge_bits);
+  double beta_min = fmax(fmax(edge, emax + delta), bin_size) * (1.0 + 0x1p-20);
+  if (!(beta_min > 0.0) || !isfinite(beta_min)) beta_min = 1.0;
+  Grid g;
+  double L[3];
+  int64_t n[3];
+  for (int d = 0; d < 3; ++d) {
+    double lo = from_order_key(red->lo_key[d]);
+    double hi = from_order_key(red->hi_key[d]);
+    if (!(lo <= hi) || !isfinite(lo) || !isfinite(hi)) { lo = 0.0; hi = 0.0; }
+    g.lo[d] = lo - beta_min;
+    L[d] = (hi + beta_min) - g.lo[d];
+    const double q = floor(L[d] / beta_min);
+    n[d] = q >= 1.0 ? (q < (double)max_cells ? (int64_t)q : max_cells) : 1;
+  }
+  // (the product in double: three factors up to max_cells overflow int64)
+  while ((double)n[0] * (double)n[1] * (double)n[2] > (double)max_cells) {
+    const double f = cbrt((double)n[0] * (double)n[1] * (double)n[2] / (double)max_cells) * 1.01;
+    for (int d = 0; d < 3; ++d) {
+      const double q = floor((double)n[d] / f);
+      n[d] = q >= 1.0 ? (int64_t)q : 1;
+    }
+  }
+  for (int d = 0; d < 3; ++d) {
+    g.n[d] = (int32_t)n[d];
+    g.beta[d] = L[d] / (double)n[d];
+    g.inv_beta[d] = 1.0 / g.beta[d];
+  }
+  g.ncells = n[0] * n[1] * n[2];
+  // padded so that rounding in the box centres cannot move a centre across
+  g.reach = (delta + 0.5 * emax) * (1.0 + 1e-9) + 1e-9 * beta_min;
+  st->grid = g;
+  if (red->bad_index & 2) st->flags |= DS_NONFINITE;
+}
+
+// Empty cells hold the range (0, 0): the cell table is cleared over the
+// grid's cells (grid-stride), so no memset node enters a captured graph.
+__global__ __launch_bounds__(BS) void k_clear_cells(int2* __restrict__ range, const Grid* __restrict__ gp) {
+  const int64_t nc = gp->ncells;
+  for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < nc; i += (int64_t)gridDim.x * BS)
+    range[i] = make_int2(0, 0);
+}
+
+__global__ __launch_bounds__(BS) void k_master_keys(const double* __restrict__ box, int32_t n,
+                                                     const Grid* __restrict__ gp, uint32_t* __restrict__ keys,
+                                                     uint32_t* __restrict__ vals) {
   const int m = blockIdx.x * BS + threadIdx.x;
   if (m >= n) return;
+  const Grid g = *gp;
   int ix[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
@@ -327,11 +398,13 @@ __device__ __forceinline__ int walk_cells_group(const SlaveBox& b, const double*
 __global__ __launch_bounds__(BS) void k_cand_count(const double* __restrict__ box_s, int32_t n_s,
                                                     const double* __restrict__ sbox,
                                                     const uint32_t* __restrict__ mvals,
-                                                    const int2* __restrict__ range, Grid g, double delta,
-                                                    int32_t* __restrict__ count, int32_t* __restrict__ tmp) {
+                                                    const int2* __restrict__ range, const Grid* __restrict__ gp,
+                                                    double delta, int32_t* __restrict__ count,
+                                                    int32_t* __restrict__ tmp) {
   const int64_t t = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * BS + threadIdx.x;
   const int s = (int)(t / G), r = (int)(t % G);
   if (s >= n_s) return;  // whole groups leave together
+  const Grid g = *gp;
   const SlaveBox b = load_box(box_s, n_s, s);
   const int c = walk_cells_group(b, sbox, mvals, range, g, delta, tmp + s, n_s, CTMP, r, (int)(__lane_id() & ~(G - 1)));
   if (r == 0) count[s] = c;
@@ -477,7 +550,8 @@ __device__ __forceinline__ void fill_long(int s, int32_t n_s, int base, int c, i
 __global__ __launch_bounds__(BS) void k_cand_fill_long(const double* __restrict__ box_s, int32_t n_s,
                                                         const double* __restrict__ sbox,
                                                         const uint32_t* __restrict__ mvals,
-                                                        const int2* __restrict__ range, Grid g, double delta,
+                                                        const int2* __restrict__ range, const Grid* __restrict__ gp,
+                                                        double delta,
                                                         const int32_t* __restrict__ off, int32_t* __restrict__ cand_s,
                                                         int32_t* __restrict__ cand_m, const double* __restrict__ sd,
                                                         const double* __restrict__ md, double eps_a,
@@ -494,6 +568,7 @@ __global__ __launch_bounds__(BS) void k_cand_fill_long(const double* __restrict_
     scr_cnt[s] = 0;
     return;
   }
+  const Grid g = *gp;
   ScreenOut so{0u, 0u};
   int nscr = 0;
   if (c <= CCAP)
@@ -523,42 +598,22 @@ hipError_t launch_prep_reduce(const double* part, int nb_s, int nb_m, PrepReduce
   return hipGetLastError();
 }
 
-void grid_from_reduce(const PrepReduce& r, double delta, double bin_size, Grid& g) {
-  double emax, edge;
-  std::memcpy(&emax, &r.emax_bits, sizeof(double));
-  std::memcpy(&edge, &r.edge_bits, sizeof(double));
-  double beta_min = std::fmax(std::fmax(edge, emax + delta), bin_size) * (1.0 + std::ldexp(1.0, -20));
-  if (!(beta_min > 0.0) || !std::isfinite(beta_min)) beta_min = 1.0;
-  double L[3];
-  int64_t n[3];
-  for (int d = 0; d < 3; ++d) {
-    double lo = from_order_key(r.lo_key[d]);
-    double hi = from_order_key(r.hi_key[d]);
-    if (!(lo <= hi)) { lo = 0.0; hi = 0.0; }
-    g.lo[d] = lo - beta_min;
-    L[d] = (hi + beta_min) - g.lo[d];
-    n[d] = std::max<int64_t>(1, (int64_t)std::floor(L[d] / beta_min));
-  }
-  // Bound the dense cell table; coarser cells keep the search complete.
-  const int64_t cap = int64_t(1) << 24;
-  while (n[0] * n[1] * n[2] > cap) {
-    const double f = std::cbrt((double)(n[0] * n[1] * n[2]) / (double)cap) * 1.01;
-    for (int d = 0; d < 3; ++d) n[d] = std::max<int64_t>(1, (int64_t)std::floor((double)n[d] / f));
-  }
-  for (int d = 0; d < 3; ++d) {
-    g.n[d] = (int32_t)n[d];
-    g.beta[d] = L[d] / (double)n[d];
-    g.inv_beta[d] = 1.0 / g.beta[d];
-  }
-  g.ncells = n[0] * n[1] * n[2];
-  // padded so that rounding in the box centres cannot move a centre across
-  g.reach = (delta + 0.5 * emax) * (1.0 + 1e-9) + 1e-9 * beta_min;
+hipError_t launch_grid(const PrepReduce* red, double delta, double bin_size, int64_t max_cells, DevState* st,
+                       hipStream_t s) {
+  k_grid<<<1, 64, 0, s>>>(red, delta, bin_size, max_cells, st);
+  return hipGetLastError();
 }
 
-hipError_t launch_master_keys(const double* box_m, int32_t n_m, Grid g, uint32_t* keys, uint32_t* vals,
+hipError_t launch_master_keys(const double* box_m, int32_t n_m, const Grid* g, uint32_t* keys, uint32_t* vals,
                               hipStream_t s) {
   if (n_m == 0) return hipSuccess;
   k_master_keys<<<(n_m + BS - 1) / BS, BS, 0, s>>>(box_m, n_m, g, keys, vals);
+  return hipGetLastError();
+}
+
+hipError_t launch_clear_cells(int2* range, const Grid* g, int64_t max_cells, hipStream_t s) {
+  const unsigned nb = (unsigned)std::min<int64_t>(2048, (max_cells + BS - 1) / BS);
+  k_clear_cells<<<nb, BS, 0, s>>>(range, g);
   return hipGetLastError();
 }
 
@@ -574,14 +629,15 @@ hipError_t launch_cell_ranges(const uint32_t* keys, const uint32_t* vals, int32_
 unsigned group_blocks(int32_t n_s) { return xcd_grid((unsigned)(((int64_t)n_s * G + BS - 1) / BS)); }
 
 hipError_t launch_cand_count(const double* box_s, int32_t n_s, const double* sbox, const uint32_t* mvals,
-                             const int2* range, Grid g, double delta, int32_t* count, int32_t* tmp, hipStream_t s) {
+                             const int2* range, const Grid* g, double delta, int32_t* count, int32_t* tmp,
+                             hipStream_t s) {
   if (n_s == 0) return hipSuccess;
   k_cand_count<<<group_blocks(n_s), BS, 0, s>>>(box_s, n_s, sbox, mvals, range, g, delta, count, tmp);
   return hipGetLastError();
 }
 
 hipError_t launch_cand_fill(const double* box_s, int32_t n_s, const double* sbox, const uint32_t* mvals,
-                            const int2* range, Grid g, double delta, const int32_t* tmp, const int32_t* off,
+                            const int2* range, const Grid* g, double delta, const int32_t* tmp, const int32_t* off,
                             int32_t* cand_s, int32_t* cand_m, const double* sd, const double* md, double eps_a,
                             uint8_t* nv, int32_t* flag, int32_t* scr_cnt, Counters* cnt, int64_t cap,
                             hipStream_t s) {

@@ -34,8 +34,21 @@ def default_params(**kw):
     return p
 
 
+def workspace(nbytes, device):
+    """A device workspace of at least nbytes from torch's allocator (256-byte
+    aligned, as the library requires)."""
+    t = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device)
+    off = (-t.data_ptr()) % 256
+    return t, t.data_ptr() + off
+
+
 class MortarInterface:
-    """One slave/master interface registered with a library context."""
+    """One slave/master interface registered with a library context.
+
+    The library allocates no device memory: the interface keeps a torch
+    workspace sized by mt_workspace_size for its capacities (the library's
+    defaults at first; after a build that exceeded one, the counts it
+    needed, mt_required_capacity) and passes it to mt_build_pairs."""
 
     def __init__(self, Xs, conn_s, Xm, conn_m, params=None, device=None, stream=None):
         if device is None:
@@ -50,6 +63,11 @@ class MortarInterface:
         self._uploaded = False
         self.set_coordinates(Xs, Xm, conn_s, conn_m)
         self.n_cand = self.n_pairs = self.nnz_D = self.nnz_M = None
+        self.capacity = None
+        self._ws = None
+        self._ws_ptr = 0
+        self._ws_bytes = 0
+        self.coord_version = 0  # counts coordinate registrations (MortarFunction checks it)
 
     def set_coordinates(self, Xs, Xm, conn_s=None, conn_m=None):
         """Register coordinates (n, 3) and, optionally, connectivity.  With
@@ -74,6 +92,7 @@ class MortarInterface:
                 C.check(L.mt_update_coordinates(self.h, side, _ptr(X[0]), _ptr(X[1]), _ptr(X[2]),
                                                 _stream(self.stream)))
         self._uploaded = True
+        self.coord_version = getattr(self, "coord_version", 0) + 1
 
     @property
     def n_slave_nodes(self):
@@ -83,13 +102,70 @@ class MortarInterface:
     def n_master_nodes(self):
         return int(self.Xm.shape[1])
 
-    def build_pairs(self):
-        nc, npairs = ctypes.c_int64(), ctypes.c_int64()
-        C.check(C.lib().mt_build_pairs(self.h, ctypes.byref(nc), ctypes.byref(npairs), _stream(self.stream)))
-        self.n_cand, self.n_pairs = nc.value, npairs.value
-        return self.n_cand, self.n_pairs
+    def default_capacity(self):
+        cap = C.mt_capacity()
+        C.check(C.lib().mt_default_capacity(self.h, ctypes.byref(cap)))
+        return cap
+
+    def set_capacity(self, cap=None, candidates=None, screened=None, pairs=None, cells=None):
+        """Capacities of the next builds (mt_capacity or keywords; None keeps
+        the current / default value) and a workspace that holds them."""
+        base = cap if cap is not None else (self.capacity or self.default_capacity())
+        new = C.mt_capacity(base.candidates, base.screened, base.pairs, base.cells)
+        for k, v in (("candidates", candidates), ("screened", screened), ("pairs", pairs), ("cells", cells)):
+            if v is not None:
+                setattr(new, k, int(v))
+        n = ctypes.c_size_t()
+        C.check(C.lib().mt_workspace_size(self.h, ctypes.byref(new), ctypes.byref(n)))
+        if n.value > self._ws_bytes:
+            self._ws = None
+            self._ws, self._ws_ptr = workspace(n.value, self.device)
+            self._ws_bytes = n.value
+        self.capacity = new
+        return new
+
+    def build_pairs(self, sync=True):
+        """mt_build_pairs into the interface's workspace.  sync=True reads the
+        counts back (and, when a capacity was exceeded, enlarges it to the
+        counts the build needed and builds again); sync=False launches the
+        build without waiting for the device (check() reports its status)."""
+        if self.capacity is None:
+            self.set_capacity()
+        L = C.lib()
+        for _ in range(4):
+            if not sync:
+                C.check(L.mt_build_pairs(self.h, ctypes.byref(self.capacity), ctypes.c_void_p(self._ws_ptr),
+                                         self._ws_bytes, None, None, _stream(self.stream)))
+                self.n_cand = self.n_pairs = None
+                return None
+            nc, npairs = ctypes.c_int64(), ctypes.c_int64()
+            rc = L.mt_build_pairs(self.h, ctypes.byref(self.capacity), ctypes.c_void_p(self._ws_ptr), self._ws_bytes,
+                                  ctypes.byref(nc), ctypes.byref(npairs), _stream(self.stream))
+            if rc != C.MT_ECAPACITY:
+                # the counts are written also when a device check failed
+                self.n_cand, self.n_pairs = nc.value, npairs.value
+                C.check(rc)
+                return self.n_cand, self.n_pairs
+            need = C.mt_capacity()
+            C.check(L.mt_required_capacity(self.h, ctypes.byref(need)))
+            cap = self.capacity
+            self.set_capacity(candidates=max(cap.candidates, need.candidates),
+                              screened=max(cap.screened, need.screened), pairs=max(cap.pairs, need.pairs))
+        C.check(rc)
+
+    def check(self):
+        """mt_check: raises MortarError for a device-side condition since the
+        last build (capacity, non-finite coordinates, degenerate elements,
+        non-converged inverse maps)."""
+        C.check(C.lib().mt_check(self.h))
+
+    def _counts(self):
+        if self.n_pairs is None or self.n_cand is None:
+            st = self.stats()
+            self.n_cand, self.n_pairs = st["n_candidates"], st["n_pairs"]
 
     def pairs(self):
+        self._counts()
         n = self.n_pairs
         s = torch.empty(n, dtype=torch.int32, device=self.device)
         m = torch.empty(n, dtype=torch.int32, device=self.device)
@@ -98,6 +174,7 @@ class MortarInterface:
         return s, m, nv
 
     def candidates(self):
+        self._counts()
         n = self.n_cand
         s = torch.empty(n, dtype=torch.int32, device=self.device)
         m = torch.empty(n, dtype=torch.int32, device=self.device)
@@ -105,13 +182,19 @@ class MortarInterface:
         C.check(C.lib().mt_get_candidates(self.h, _ptr(s), _ptr(m), _ptr(nv), _stream(self.stream)))
         return s, m, nv
 
-    def csr_pattern(self):
+    def csr_pattern(self, sync=True):
         """Build the CSR patterns of D and M; the arrays are copied out on
-        first access of D_rowptr / D_col / M_rowptr / M_col."""
+        first access of D_rowptr / D_col / M_rowptr / M_col.  sync=False:
+        no read-back of the nonzero counts."""
+        self._csr = None
+        if not sync:
+            C.check(C.lib().mt_csr_pattern(self.h, None, None, _stream(self.stream)))
+            return None
         a, b = ctypes.c_int64(), ctypes.c_int64()
         C.check(C.lib().mt_csr_pattern(self.h, ctypes.byref(a), ctypes.byref(b), _stream(self.stream)))
         self.nnz_D, self.nnz_M = a.value, b.value
-        self._csr = None
+        st = self.stats()
+        self.n_cand, self.n_pairs = st["n_candidates"], st["n_pairs"]
         return self.nnz_D, self.nnz_M
 
     def _fetch_csr(self):
@@ -165,6 +248,7 @@ class MortarInterface:
         return {"n_candidates": st.n_candidates, "n_pairs": st.n_pairs, "nverts_hist": list(st.nverts_hist),
                 "n_noconv": st.n_noconv, "n_overflow": st.n_overflow,
                 "n_degenerate_slave": st.n_degenerate_slave, "n_degenerate_master": st.n_degenerate_master,
+                "n_lost_pairs": st.n_lost_pairs,
                 "nnz_D": st.nnz_D, "nnz_M": st.nnz_M, "n_bins": list(st.n_bins), "bin_size": list(st.bin_size)}
 
     def set_timing(self, enable=True, phases=None):
@@ -199,18 +283,27 @@ class MortarInterface:
 class MortarFunction(torch.autograd.Function):
     """(Xs (n_s, 3), Xm (n_m, 3)) -> (D_val, M_val, gap) on a fixed pair list
     and CSR pattern; backward returns dL/dXs, dL/dXm from the hand-written
-    reverse-mode kernel."""
+    reverse-mode kernel, at the coordinates of this forward (re-registered
+    when another forward moved the interface since)."""
 
     @staticmethod
     def forward(ctx, Xs, Xm, iface):
-        iface.set_coordinates(Xs.detach(), Xm.detach())
+        Xs_d, Xm_d = Xs.detach(), Xm.detach()
+        iface.set_coordinates(Xs_d, Xm_d)
         D, M, g = iface.integrate()
         ctx.iface = iface
+        ctx.coords = (Xs_d, Xm_d)
+        ctx.version = iface.coord_version
         return D, M, g
 
     @staticmethod
     def backward(ctx, gD, gM, gg):
         iface = ctx.iface
+        if iface.coord_version != ctx.version:
+            # another forward (a second loss, a line-search trial point) moved
+            # the interface: evaluate the gradient at this forward's point
+            iface.set_coordinates(*ctx.coords)
+            ctx.version = iface.coord_version
         dev = iface.device
         gD = gD if gD is not None else torch.zeros(iface.nnz_D, dtype=torch.float64, device=dev)
         gM = gM if gM is not None else torch.zeros(iface.nnz_M, dtype=torch.float64, device=dev)

@@ -20,4 +20,5 @@ from .meshes import (  # noqa: F401
     batched_instances,
     CONFIG_NAMES,
 )
+from .degenerate import collapsed_slave, perpendicular_master  # noqa: F401
 from .weights import keyed_normal, upstream_weights  # noqa: F401

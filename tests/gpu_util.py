@@ -102,3 +102,52 @@ def assert_forward_parity(g, o):
     else:
         assert eg <= TOL, eg
     return eD, eM, eg
+
+
+def window_oracle(itf, els, prm, elements=None):
+    """Oracle on the slave elements `els` only (against the whole master
+    side): returns the oracle results with global slave element indices in
+    'pair_s' and the slave nodes whose rows it computes completely (every
+    incident slave element lies in the window)."""
+    from synth.meshes import Interface, Mesh
+    els = np.asarray(els)
+    sub = Interface(Mesh(itf.slave.X, itf.slave.conn[els]), itf.master, itf.delta)
+    o = oracle.evaluate(sub, prm) if elements is None else oracle.evaluate_elements(sub, elements, prm)
+    o["pair_s"] = els[o["pair_s"]]
+    cnt = np.bincount(itf.slave.conn.ravel(), minlength=itf.slave.n_nodes)
+    cnt_w = np.bincount(itf.slave.conn[els].ravel(), minlength=itf.slave.n_nodes)
+    nodes = np.nonzero((cnt_w == cnt) & (cnt > 0))[0]
+    return o, nodes
+
+
+def assert_rows_parity(D, M, g, o, nodes):
+    """Rows `nodes` of GPU CSR D, M and gap against the oracle's: same
+    pattern, values within TOL."""
+    for A, B in ((D, o["D"]), (M, o["M"])):
+        A, B = A[nodes], B[nodes]
+        assert_same_pattern(A, B)
+        assert rel_err(A.data, B.data) <= TOL
+    if np.linalg.norm(o["g"][nodes]) > 0:
+        assert rel_err(g[nodes], o["g"][nodes]) <= TOL
+
+
+def sampled_oracle(itf, prm, sn, mn, seed=None):
+    """Oracle values at sampled nodes without evaluating every pair: the pair
+    list of the whole interface (search + clip only), then the blocks of the
+    pairs whose slave element holds a node of `sn` (complete rows of D, M and
+    gap for those nodes) and, with `seed`, the keyed-weight gradient of the
+    pairs touching `sn` or `mn` (complete for those nodes)."""
+    cs, cm = oracle.search(itf.slave, itf.master, prm.delta)
+    nv, _, _ = oracle.eval_candidates(itf.slave, itf.master, prm, cs, cm, integrate=False)
+    keep = nv >= 3
+    ps, pm = cs[keep], cm[keep]
+    out = {"pair_s": ps, "pair_m": pm}
+    rows = np.isin(itf.slave.conn[ps], sn).any(1)
+    _, blocks, st = oracle.eval_candidates(itf.slave, itf.master, prm, ps[rows], pm[rows])
+    out["D"], out["M"], out["g"] = oracle.assemble(itf.slave, itf.master, ps[rows], pm[rows], blocks)
+    if seed is not None:
+        sel = rows | np.isin(itf.master.conn[pm], mn).any(1)
+        w = oracle.pair_weights(itf.slave, itf.master, ps[sel], pm[sel], *weight_fns(seed))
+        g24, _ = oracle.pair_grads(itf.slave, itf.master, prm, ps[sel], pm[sel], w)
+        out["gXs"], out["gXm"] = oracle.scatter_grads(itf.slave, itf.master, ps[sel], pm[sel], g24)
+    return out

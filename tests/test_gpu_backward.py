@@ -8,7 +8,8 @@ import torch
 
 import oracle
 import synth
-from tests.gpu_util import TOL, gpu_run, oracle_params, rel_err, weight_fns
+from tests.gpu_util import (TOL, assert_forward_parity, assert_rows_parity, gpu_run, oracle_params, rel_err,
+                            sampled_oracle, weight_fns)
 
 pytestmark = pytest.mark.gpu
 
@@ -58,7 +59,9 @@ def test_dual_gradient_parity_full_wavy_sampled():
     prm = oracle_params(itf, dual=True)
     g = gpu_run(itf, dual=True, backward_seed=3100)
     o = oracle.evaluate(itf, prm)
-    assert np.array_equal(g["pair_s"], o["pair_s"]) and np.array_equal(g["pair_m"], o["pair_m"])
+    # full-size dual forward values, then the sampled gradients
+    eD, eM, eg = assert_forward_parity(g, o)
+    print(f"full wavy dual forward rel err D {eD:.2e} M {eM:.2e} g {eg:.2e}")
     rng = np.random.default_rng(3102)
     sn = rng.choice(itf.slave.n_nodes, 200, replace=False)
     mn = rng.choice(itf.master.n_nodes, 200, replace=False)
@@ -84,6 +87,21 @@ def test_gradient_parity_full_wavy_sampled():
     gs, gm = oracle_grad(itf, prm, ps[sel], pm[sel], 3000)
     es, em = rel_err(g["gXs"][sn], gs[sn]), rel_err(g["gXm"][mn], gm[mn])
     print(f"sampled grad rel err slave {es:.2e} master {em:.2e} over {sel.sum()} pairs")
+    assert es <= TOL and em <= TOL
+
+
+def test_gradient_parity_full_cylinder_sampled():
+    itf = synth.interface_config(1)
+    prm = oracle_params(itf)
+    g = gpu_run(itf, backward_seed=3000)
+    rng = np.random.default_rng(3003)
+    sn = rng.choice(itf.slave.n_nodes, 300, replace=False)
+    mn = rng.choice(itf.master.n_nodes, 300, replace=False)
+    o = sampled_oracle(itf, prm, sn, mn, seed=3000)
+    assert np.array_equal(g["pair_s"], o["pair_s"]) and np.array_equal(g["pair_m"], o["pair_m"])
+    assert_rows_parity(g["D"], g["M"], g["g"], o, sn)
+    es, em = rel_err(g["gXs"][sn], o["gXs"][sn]), rel_err(g["gXm"][mn], o["gXm"][mn])
+    print(f"sampled cylinder grad rel err slave {es:.2e} master {em:.2e}")
     assert es <= TOL and em <= TOL
 
 
@@ -193,11 +211,10 @@ def test_error_codes():
         iface.integrate(out=(torch.empty(1, dtype=torch.float64, device=dev),) * 3)
     assert e.value.code == C.MT_ESTATE
     iface.setup()
-    # connectivity out of range is reported, not read
+    # connectivity out of range is reported by the upload, not read
     bad = itf.slave.conn.copy()
     bad[3, 2] = itf.slave.n_nodes + 5
-    iface2 = MortarInterface(torch.from_numpy(itf.slave.X), torch.from_numpy(bad), torch.from_numpy(itf.master.X),
-                             torch.from_numpy(itf.master.conn), device=dev)
     with pytest.raises(MortarError) as e:
-        iface2.build_pairs()
+        MortarInterface(torch.from_numpy(itf.slave.X), torch.from_numpy(bad), torch.from_numpy(itf.master.X),
+                        torch.from_numpy(itf.master.conn), device=dev)
     assert e.value.code == C.MT_EINVAL

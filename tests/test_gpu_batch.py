@@ -8,7 +8,8 @@ import torch
 
 import oracle
 import synth
-from tests.gpu_util import TOL, csr_weights, gpu_params, oracle_params, rel_err, weight_fns
+from tests.gpu_util import (TOL, assert_rows_parity, csr_weights, gpu_params, oracle_params, rel_err, sampled_oracle,
+                            weight_fns)
 
 pytestmark = pytest.mark.gpu
 
@@ -122,8 +123,27 @@ def test_batch_dual_basis_bitwise_and_oracle():
 
 
 def test_batch_full_64_instances_bitwise():
+    import scipy.sparse as sp
     instances = synth.batched_instances(n_inst=64)
-    run_batch_checks(instances, autotune=False)
+    ifaces, outs, grads = run_batch_checks(instances, autotune=False)
+    # the three largest instances against the oracle at sampled nodes
+    big = sorted(range(len(instances)), key=lambda i: -instances[i].slave.n_el)[:3]
+    for i in big:
+        itf, it, (D, M, gv), (gs, gm) = instances[i], ifaces[i], outs[i], grads[i]
+        print(f"[gpu] batch instance {i}: {itf.name}, {it.n_pairs} pairs", flush=True)
+        prm = oracle_params(itf)
+        rng = np.random.default_rng(5000 + i)
+        sn = rng.choice(itf.slave.n_nodes, 150, replace=False)
+        mn = rng.choice(itf.master.n_nodes, 150, replace=False)
+        flat = itf.meta["geometry"] == "flat"
+        o = sampled_oracle(itf, prm, sn, mn, seed=None if flat else 4000 + i)
+        ns, nm = itf.slave.n_nodes, itf.master.n_nodes
+        Dc = sp.csr_matrix((D.cpu().numpy(), it.D_col.cpu().numpy(), it.D_rowptr.cpu().numpy()), shape=(ns, ns))
+        Mc = sp.csr_matrix((M.cpu().numpy(), it.M_col.cpu().numpy(), it.M_rowptr.cpu().numpy()), shape=(ns, nm))
+        assert_rows_parity(Dc, Mc, gv.cpu().numpy(), o, sn)
+        if not flat:  # tied flat boundaries: not differentiable
+            assert rel_err(gs.cpu().numpy().T[sn], o["gXs"][sn]) <= TOL
+            assert rel_err(gm.cpu().numpy().T[mn], o["gXm"][mn]) <= TOL
 
 
 def test_batch_rejects_mixed_rules_and_graph_on_default_stream():

@@ -1,0 +1,123 @@
+"""Error paths of the HIP path through the C ABI, each against the oracle's
+status bits where the oracle has one: non-finite coordinates (MT_EINVAL), a
+collapsed slave element (MT_EDEGENERATE, counted per candidate), a master
+perpendicular to the slave plane (counted as degenerate master), inverse maps
+cut off after one iteration (MT_ENOCONV from mt_check, every map counted),
+and pairs lost after a coordinate update (MT_EDEGENERATE from mt_check, no
+contribution, no NaN in the dual basis)."""
+
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.gpu_util import TOL, gpu_run, oracle_params, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _iface(itf, **kw):
+    from paper_2202_03933_amd import MortarInterface, default_params
+    dev = torch.device("cuda", 0)
+    print(f"[gpu] {itf.name} {kw}", flush=True)
+    return MortarInterface(torch.from_numpy(itf.slave.X), torch.from_numpy(itf.slave.conn),
+                           torch.from_numpy(itf.master.X), torch.from_numpy(itf.master.conn),
+                           params=default_params(delta=float(itf.delta), **kw), device=dev)
+
+
+def test_nonfinite_coordinates_are_rejected():
+    from paper_2202_03933_amd import MortarError
+    from paper_2202_03933_amd import _capi as C
+    itf = synth.interface_config(2, scale=24)
+    X = itf.slave.X.copy()
+    X[37, 1] = np.nan
+    X[301, 2] = np.inf
+    bad = synth.Interface(synth.Mesh(X, itf.slave.conn), itf.master, itf.delta, name="wavy with NaN")
+    it = _iface(bad)
+    with pytest.raises(MortarError) as e:
+        it.build_pairs()
+    assert e.value.code == C.MT_EINVAL
+    # the same build without waiting: no fault, mt_check reports it
+    it.build_pairs(sync=False)
+    with pytest.raises(MortarError) as e:
+        it.check()
+    assert e.value.code == C.MT_EINVAL
+    # and a clean interface afterwards is unaffected
+    good = _iface(itf).setup()
+    good.check()
+
+
+def test_collapsed_slave_element():
+    from paper_2202_03933_amd import MortarError
+    from paper_2202_03933_amd import _capi as C
+    itf = synth.collapsed_slave()
+    o = oracle.evaluate(itf, oracle_params(itf))
+    it = _iface(itf)
+    with pytest.raises(MortarError) as e:
+        it.build_pairs()
+    assert e.value.code == C.MT_EDEGENERATE
+    st = it.stats()
+    assert st["n_degenerate_slave"] == int(np.count_nonzero(o["status"] & oracle.ST_DEGEN_SLAVE))
+    cs, cm, cnv = (t.cpu().numpy() for t in it.candidates())
+    assert np.array_equal(cs, o["cand_s"]) and np.array_equal(cm, o["cand_m"])
+    assert np.array_equal(cnv, o["cand_nverts"])
+
+
+def test_perpendicular_master_counted():
+    itf = synth.perpendicular_master()
+    o = oracle.evaluate(itf, oracle_params(itf))
+    g = gpu_run(itf)
+    assert g["stats"]["n_degenerate_master"] == int(np.count_nonzero(o["status"] & oracle.ST_DEGEN_MASTER)) == 4
+    assert np.array_equal(g["pair_s"], o["pair_s"]) and np.array_equal(g["pair_m"], o["pair_m"])
+    assert rel_err(g["D"].data, o["D"].data) <= TOL
+
+
+def test_newton_cut_off_reports_noconv():
+    from paper_2202_03933_amd import MortarError
+    from paper_2202_03933_amd import _capi as C
+    itf = synth.interface_config(1, scale=20)
+    it = _iface(itf, newton_maxit=1).setup()
+    o = oracle.evaluate(itf, oracle.params(delta=itf.delta, newton_maxit=1))
+    assert np.all(o["status"][o["cand_nverts"] >= 3] & oracle.ST_NOCONV)
+    it.integrate()
+    with pytest.raises(MortarError) as e:
+        it.check()
+    assert e.value.code == C.MT_ENOCONV
+    # no map converges in one iteration: both maps of every rule point count
+    nv = o["nverts"].astype(np.int64)
+    assert it.stats()["n_noconv"] == 2 * 7 * int((nv - 2).sum())
+
+
+@pytest.mark.parametrize("dual", [False, True])
+def test_pairs_lost_after_update(dual):
+    from paper_2202_03933_amd import MortarError
+    from paper_2202_03933_amd import _capi as C
+    itf = synth.collapsed_slave(collapsed=False)  # every element has its own nodes
+    it = _iface(itf, dual=dual).setup()
+    it.check()
+    ps, pm, _ = (t.cpu().numpy() for t in it.pairs())
+    bad = itf.slave.n_el - 1
+    assert np.count_nonzero(ps == bad) == 1
+    # collapse that element onto a segment: its pair stops being a segment
+    moved = synth.collapsed_slave(collapsed=True)
+    it.set_coordinates(moved.slave.X, moved.master.X)
+    D, M, g = it.integrate()
+    torch.cuda.synchronize()
+    with pytest.raises(MortarError) as e:
+        it.check()
+    assert e.value.code == C.MT_EDEGENERATE
+    assert it.stats()["n_lost_pairs"] == 1
+    for t in (D, M, g):
+        assert torch.isfinite(t).all()
+    # the oracle on the same fixed pair list at the moved coordinates
+    prm = oracle_params(itf, dual=dual)
+    nv, blocks, st = oracle.eval_candidates(moved.slave, moved.master, prm, ps, pm)
+    lost = nv < 3
+    assert np.array_equal(lost, ps == bad)
+    blocks[lost] = 0.0
+    Do, Mo, go = oracle.assemble(moved.slave, moved.master, ps, pm, blocks)
+    assert rel_err(D.cpu().numpy(), Do.data) <= TOL and rel_err(M.cpu().numpy(), Mo.data) <= TOL
+    assert np.abs(g.cpu().numpy()).max() == 0.0 and np.abs(go).max() == 0.0  # all on z = 0

@@ -122,17 +122,19 @@ def test_batch_rejects_rebuilt_instance():
 
 
 def test_rebuild_with_more_candidates_matches_a_fresh_search():
-    # The candidate arrays keep their size between searches of one context
-    # and the fill pass runs against that size: a second search with about
-    # twice the candidates outgrows them, which makes the pass run again on
-    # enlarged arrays; a third with fewer fits.  Every search must equal a
-    # fresh context's, bit for bit, and the oracle's candidate list.
+    # The workspace is sized for the exact counts of the first search: a
+    # second search with about twice the candidates exceeds the capacities
+    # (MT_ECAPACITY), so the interface enlarges them to the counts the build
+    # needed and builds again; a third with fewer fits.  Every search must
+    # equal a fresh context's, bit for bit, and the oracle's candidate list.
     import oracle
     from tests.gpu_util import oracle_params
     itf = synth.flat_tied(24, 19, seed=21)
     shifted = itf.master.X + np.array([0.55, 0.0, 0.0])
     print(f"[gpu] {itf.name}: searches with growing and shrinking candidate counts", flush=True)
     it = _iface(itf.slave.X, itf, shifted)
+    it.set_capacity(candidates=it.n_cand, screened=max(it.n_pairs, 1), pairs=max(it.n_pairs, 1))
+    it.setup()
     counts = [it.n_cand]
     for Xm in (itf.master.X, shifted + np.array([0.2, 0.0, 0.0]), itf.master.X):
         it.set_coordinates(itf.slave.X, Xm)
