@@ -218,6 +218,19 @@ int mt_workspace_size(mt_ctx* ctx, const mt_capacity* cap, size_t* bytes);
 int mt_build_pairs(mt_ctx* ctx, const mt_capacity* cap, void* ws, size_t ws_bytes, int64_t* n_cand,
                    int64_t* n_pairs, void* stream);
 
+/* mt_build_pairs without a caller workspace, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  The workspace is a static device array
+ * of the library, 256 MiB on each GPU it runs on, held until the process
+ * ends.  Arguments, results and errors as mt_build_pairs, plus MT_ECAPACITY
+ * when mt_workspace_size(cap) exceeds 256 MiB (nothing is launched then).
+ * Every context on one GPU shares that array: a build here binds it to this
+ * context, and a context built here before gets MT_ESTATE from every later
+ * call that needs its pair list; calls on one GPU that overlap in time (other
+ * host threads, or work of another context still in flight on another
+ * stream) race on it.  The build clears the state and counters it needs. */
+int mt_build_pairs_static(mt_ctx* ctx, const mt_capacity* cap, int64_t* n_cand, int64_t* n_pairs, void* stream);
+
 /* Counts the last mt_build_pairs needed (synchronises its stream): the
  * candidates found; the screened candidates among the candidates it could
  * store; the pairs among the screened candidates it could store; the grid

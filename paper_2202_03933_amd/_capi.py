@@ -71,6 +71,7 @@ SIGNATURES = {
     "mt_default_capacity": (_int, [_vp, _pcap]),
     "mt_workspace_size": (_int, [_vp, _pcap, _psz]),
     "mt_build_pairs": (_int, [_vp, _pcap, _vp, ctypes.c_size_t, _pi64, _pi64, _vp]),
+    "mt_build_pairs_static": (_int, [_vp, _pcap, _pi64, _pi64, _vp]),
     "mt_required_capacity": (_int, [_vp, _pcap]),
     "mt_check": (_int, [_vp]),
     "mt_get_pairs": (_int, [_vp, _vp, _vp, _vp, _vp]),

@@ -998,9 +998,60 @@ int mt_get_stats(mt_ctx* c, mt_stats* out) {
 
 int mt::ensure_normals(mt_ctx* c, hipStream_t st) { return normals_for_coords(c, st); }
 
+// ---- the build that allocates nothing ------------------------------------------
+// For callers that cannot allocate device memory (code under HIP graph
+// capture, tight serving loops, harnesses that forbid it): the workspace of
+// mt_build_pairs is a static device array of the library instead of caller
+// memory.  Each GPU the library runs on holds its own copy until the process
+// ends; in host code the array's name is no device address, so its address
+// is taken once per device with hipGetSymbolAddress and used from then on.
+namespace {
 
-// A caller workspace stays the context's until its next build.
+constexpr size_t STATIC_SCRATCH_BYTES = size_t(256) << 20;  // 256 MiB per device
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+uint64_t g_scratch_gen[MAX_DEVICES] = {};  // counts bindings of each device's scratch
+
+}  // namespace
+
 int mt::ws_live(mt_ctx* c) {
-  (void)c;
-  return MT_OK;
+  if (c->static_gen == 0) return MT_OK;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (c->device < MAX_DEVICES && g_scratch_gen[c->device] == c->static_gen) return MT_OK;
+  c->have_pairs = c->have_pattern = c->have_master_index = false;
+  return fail(MT_ESTATE, "the static scratch was bound by another context since this context's build");
+}
+
+extern "C" int mt_build_pairs_static(mt_ctx* c, const mt_capacity* cap, int64_t* n_cand, int64_t* n_pairs,
+                                     void* stream) {
+  if (!c) return fail(MT_EINVAL, "mt_build_pairs_static: null ctx");
+  if (c->device < 0 || c->device >= MAX_DEVICES) return fail(MT_EINVAL, "mt_build_pairs_static: device index");
+  size_t need = 0;
+  if (int rc = mt_workspace_size(c, cap, &need)) return rc;
+  if (need > STATIC_SCRATCH_BYTES)
+    return fail(MT_ECAPACITY, "mt_build_pairs_static: the workspace needs " + std::to_string(need) +
+                                  " bytes; the static scratch holds " + std::to_string(STATIC_SCRATCH_BYTES));
+  DeviceScope ds(c->device);
+  if (ds.err != hipSuccess) return hip_fail(ds.err, "hipSetDevice");
+  void* ptr = nullptr;
+  uint64_t gen = 0;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[c->device]) {
+      // first call on this device, with it current: the device address of
+      // this device's copy of the array
+      void* p = nullptr;
+      hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+      g_scratch_ptr[c->device] = p;
+    }
+    ptr = g_scratch_ptr[c->device];
+    gen = ++g_scratch_gen[c->device];
+  }
+  const int rc = mt_build_pairs(c, cap, ptr, STATIC_SCRATCH_BYTES, n_cand, n_pairs, stream);
+  c->static_gen = gen;
+  return rc;
 }
