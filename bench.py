@@ -240,7 +240,7 @@ def bench_batched(reps=5):
                               it.n_pairs, it.nnz_D, it.nnz_M)
         ab["forward"] += a["forward"]
         ab["backward"] += a["backward"]
-    counters = recorded_counters(FP64_SUMMARY, ALL_SOURCES)
+    counters = recorded_counters(FP64_SUMMARY)
     res["hbm"] = {}
     for k, phase, kern in (("fwd", "forward", "k_batch_fwd"), ("bwd", "backward", "k_batch_bwd")):
         res[f"{k}_pairs_per_s_batched"] = pairs / (res[f"{k}_ms_batched_graph"] * 1e-3)
@@ -348,10 +348,12 @@ def bench_variant(itf, weights, steps, warmup, **params):
             "phase_ms_per_step": {k: v[0] / steps for k, v in tim.items()}}
 
 
-def recorded_counters(name, files):
-    """Executed-instruction counts per launch recorded by a committed
-    rocprofv3 --pmc summary (profiles/<name>), or None when it is missing or
-    the kernel sources changed since."""
+def recorded_counters(name):
+    """Executed-instruction counts recorded by a committed rocprofv3 --pmc
+    summary (profiles/<name>): entries `<kernel>.<quantity>`, each kernel's
+    valid only while the hash of its source files equals the recorded
+    `<kernel>.source_hash` (else the kernel changed since the counters were
+    taken and its entries are dropped).  None when the summary is missing."""
     full = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(full):
         return None
@@ -361,10 +363,13 @@ def recorded_counters(name, files):
             if line.startswith("- ") and ":" in line:
                 k, v = line[2:].split(":", 1)
                 rec[k.strip()] = v.strip().strip("`")
-    if rec.get("source_hash") != kernel_source_hash(files):
-        return None
     out = {}
     for k, v in rec.items():
+        kern, _, q = k.rpartition(".")
+        if q == "source_hash" or kern not in COUNTER_SOURCES:
+            continue
+        if rec.get(f"{kern}.source_hash") != kernel_source_hash(COUNTER_SOURCES[kern]):
+            continue
         try:
             out[k] = float(v)
         except ValueError:
@@ -376,6 +381,14 @@ ALL_SOURCES = ["mt_prims.hip", "mt_search.hip", "mt_pairs.hip", "mt_assemble.hip
                "mt_elements.hip", "mt_normals.hip", "mt_batch.hip", "mt_api.hip", "mt_geometry.h",
                "mt_pair_eval.h", "mt_dual.h", "mt_rows.h", "mt_internal.h"]
 FP64_SUMMARY = "wavy1024_fp64_counters.md"  # executed FP64 VALU instructions of every kernel of the step
+# source files whose hash identifies each counted kernel ("step": the whole library)
+COUNTER_SOURCES = {
+    "k_pair_fwd": ["mt_pairs.hip", "mt_pair_eval.h", "mt_geometry.h"],
+    "k_pair_bwd": ["mt_backward.hip", "mt_dual.h", "mt_pair_eval.h", "mt_geometry.h"],
+    "k_batch_fwd": ["mt_batch.hip", "mt_dual.h", "mt_rows.h", "mt_pair_eval.h", "mt_geometry.h"],
+    "k_batch_bwd": ["mt_batch.hip", "mt_dual.h", "mt_rows.h", "mt_pair_eval.h", "mt_geometry.h"],
+    "step": ALL_SOURCES,
+}
 
 
 def algorithmic_bytes(n_sn, n_mn, n_se, n_me, n_cand, n_pairs, nnz_D, nnz_M):
@@ -545,7 +558,7 @@ def main():
     # instructions, committed under profiles/, times 64 lanes, FMA 2 flops)
     # over the launch time measured here; the oracle's operation count per
     # pair is reported beside it as the algorithmic model.
-    counters = recorded_counters(FP64_SUMMARY, ALL_SOURCES)
+    counters = recorded_counters(FP64_SUMMARY)
 
     def roofline(k):
         if not per_launch.get(k):
