@@ -234,12 +234,34 @@ def bench_batched(reps=5):
            "fwd_ms_per_interface": timed(per_fwd),
            "bwd_ms_batched_graph": timed(lambda: b.backward(W, outs=gouts, use_graph=True)),
            "bwd_ms_per_interface": timed(per_bwd)}
-    ab = {"forward": 0, "backward": 0}
+    # the search and pattern of every interface: one mt_build_pairs +
+    # mt_csr_pattern per interface (with and without the count read-backs)
+    # versus one mt_batch_search (the instances on four internal streams)
+
+    def per_search_sync():
+        for it in ifaces:
+            it.build_pairs()
+            it.csr_pattern()
+
+    def per_search_nowait():
+        for it in ifaces:
+            it.build_pairs(sync=False)
+            it.csr_pattern(sync=False)
+
+    res["search_ms_per_interface_sync"] = timed(per_search_sync)
+    res["search_ms_per_interface_nowait"] = timed(per_search_nowait)
+    res["search_ms_batched"] = timed(lambda: b.search(rebuild=False))
+    b.search(rebuild=True)  # counts read back, batch built again for them
+    assert sum(it.n_pairs for it in ifaces) == pairs
+    res["search_speedup_vs_per_interface_sync"] = res["search_ms_per_interface_sync"] / res["search_ms_batched"]
+    res["search_pairs_per_s_batched"] = pairs / (res["search_ms_batched"] * 1e-3)
+    ab = {"forward": 0, "backward": 0, "search": 0}
     for it, itf in zip(ifaces, insts):
         a = algorithmic_bytes(itf.slave.n_nodes, itf.master.n_nodes, itf.slave.n_el, itf.master.n_el, it.n_cand,
                               it.n_pairs, it.nnz_D, it.nnz_M)
         ab["forward"] += a["forward"]
         ab["backward"] += a["backward"]
+        ab["search"] += a["search"] + a["pattern"]
     counters = recorded_counters(FP64_SUMMARY)
     res["hbm"] = {}
     for k, phase, kern in (("fwd", "forward", "k_batch_fwd"), ("bwd", "backward", "k_batch_bwd")):
@@ -253,6 +275,8 @@ def bench_batched(reps=5):
             # as the per-interface kernels) over each mode's wall time
             res[f"{k}_fp64_frac_{mode}"] = (fl / (res[f"{k}_ms_{mode}"] * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS
                                             if fl else None)
+    for mode in ("batched", "per_interface_sync"):
+        res["hbm"][f"search_{mode}"] = hbm_entry(ab["search"], res[f"search_ms_{mode}"])
     return res
 
 

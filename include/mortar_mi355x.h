@@ -418,6 +418,20 @@ int mt_batch_forward(mt_batch* b, double* const* D_val, double* const* M_val, do
 int mt_batch_backward(mt_batch* b, const double* const* W_D, const double* const* W_M,
                       const double* const* w_g, double* const* gXs, double* const* gXm,
                       int use_graph, void* stream);
+/* The search of every instance (Alg. 1 and 2 of Sec. "Parallel
+ * algorithms" per instance, then the CSR pattern) in one call:
+ * mt_build_pairs into the workspace and capacities its last mt_build_pairs
+ * bound, then mt_csr_pattern, neither reading anything back, the instances
+ * spread round-robin over four internal streams that are ordered after
+ * `stream` on entry and before it on exit.  Counts and device-side status
+ * per instance as after mt_build_pairs without read-back (mt_get_stats,
+ * mt_check, mt_required_capacity); the pair counts may have changed, so
+ * call mt_batch_workspace_size / mt_batch_build again before the next
+ * mt_batch_forward / mt_batch_backward.  use_graph must be 0: capture of
+ * this call into a HIP graph is not supported (MT_EUNSUPPORTED).  Errors:
+ * MT_ESTATE (an instance with no workspace of its own bound: never built,
+ * or built by mt_build_pairs_static), errors of the per-instance calls. */
+int mt_batch_search(mt_batch* b, int use_graph, void* stream);
 /* Autotune the tuning knobs on the current instances by timing candidate
  * settings of the forward launch; writes the choice to *out (host) and uses
  * it from then on.  Values are unchanged by tuning (bitwise). */

@@ -92,6 +92,7 @@ SIGNATURES = {
     "mt_batch_build": (_int, [_vp, ctypes.POINTER(mt_batch_tuning), _vp, ctypes.c_size_t, _vp]),
     "mt_batch_forward": (_int, [_vp, _vp, _vp, _vp, _int, _vp]),
     "mt_batch_backward": (_int, [_vp, _vp, _vp, _vp, _vp, _vp, _int, _vp]),
+    "mt_batch_search": (_int, [_vp, ctypes.c_int, _vp]),
     "mt_batch_autotune": (_int, [_vp, ctypes.POINTER(mt_batch_tuning), _vp]),
 }
 

@@ -39,6 +39,7 @@ class MortarBatch:
         return ctypes.c_void_p(self.stream.cuda_stream)
 
     def build(self, tuning=None):
+        self._tuning = tuning
         t = C.mt_batch_tuning()
         if tuning:
             t.bucket = int(tuning.get("bucket", 0))
@@ -74,17 +75,36 @@ class MortarBatch:
         if key in cache:
             self.build(cache[key])
             return dict(cache[key], cached=True)
+        self._tuning = None
         t = C.mt_batch_tuning()
         self.stream.wait_stream(torch.cuda.current_stream(self.device))
         C.check(C.lib().mt_batch_autotune(self.h, ctypes.byref(t), self._s()))
         torch.cuda.current_stream(self.device).wait_stream(self.stream)
         choice = {"bucket": t.bucket, "block": t.block, "blocks_per_cu": t.blocks_per_cu}
+        self._tuning = choice
         if cache_path:
             cache[key] = choice
             os.makedirs(os.path.dirname(os.path.abspath(cache_path)), exist_ok=True)
             with open(cache_path, "w") as f:
                 json.dump(cache, f, indent=1)
         return dict(choice, cached=False)
+
+    def search(self, use_graph=False, rebuild=True):
+        """mt_batch_search: the pair search and CSR pattern of every instance
+        in one call, on the batch's internal streams (use_graph: capture
+        into a HIP graph, refused by the library).  With rebuild, the
+        instances' new counts are read back and the batch is built again for
+        the new pair lists, with the same tuning."""
+        cur = torch.cuda.current_stream(self.device)
+        self.stream.wait_stream(cur)
+        C.check(C.lib().mt_batch_search(self.h, 1 if use_graph else 0, self._s()))
+        cur.wait_stream(self.stream)
+        for it in self.ifaces:
+            it._searched()
+        if rebuild:
+            for it in self.ifaces:
+                it.refresh()
+            self.build(self._tuning)
 
     def alloc_outputs(self):
         return [it.alloc_outputs() for it in self.ifaces]

@@ -105,7 +105,7 @@ int64_t scan_max(const mt_ctx* c, const mt_capacity& cap) {
   const int64_t sortn = std::max<int64_t>(nm, cap.pairs);
   const int64_t hist = radix_hist_elems(sortn);
   int64_t m = std::max<int64_t>({(int64_t)c->side[0].n_el, (int64_t)c->side[0].n_nodes, (int64_t)c->side[1].n_nodes,
-                                 cap.screened, hist});
+                                 nm, cap.screened, hist});
   return m + 1;
 }
 
@@ -131,9 +131,9 @@ void layout(mt_ctx* c, const mt_capacity& cap, Arena& A) {
   for (Buf* b : {&c->keys, &c->vals, &c->keys_tmp, &c->vals_tmp}) A.take(*b, 4 * sortn);
   A.take(c->cell_range, 8 * G);
   A.take(c->sbox, 48 * nm);
+  A.take(c->qbox, 16 * nm);
   A.take(c->sort_hist, hist);
   A.take(c->scan_tmp, scan);
-  A.take(c->aux_hist, hist);
   A.take(c->aux_scan, scan);
   A.take(c->cand_cnt, 4 * (ns + 1));
   A.take(c->cand_off, 4 * (ns + 1));
@@ -180,9 +180,11 @@ void layout(mt_ctx* c, const mt_capacity& cap, Arena& A) {
   }
   A.take(c->blk, 288 * P);
   A.take(c->gpair, 192 * P);
-  A.take(c->mp_keys, 4 * P);
+  A.take(c->mp_cnt, 4 * (nm + 1));
+  A.take(c->mp_cur, 4 * (nm + 1));
+  A.take(c->mp_off, 4 * (nm + 1));
   A.take(c->mp_vals, 4 * P);
-  A.take(c->mp_off, 8 * (nm + 1));
+  A.take(c->mp_tmp, 4 * P);
   A.take(c->mp_pos, 4 * P);
 }
 
@@ -523,17 +525,17 @@ int mt_build_pairs(mt_ctx* c, const mt_capacity* cap_in, void* ws, size_t ws_byt
     MT_HIP(radix_sort_pairs(c->keys.as<uint32_t>(), c->vals.as<uint32_t>(), c->keys_tmp.as<uint32_t>(),
                             c->vals_tmp.as<uint32_t>(), nm, nullptr, bits, c->sort_hist, c->scan_tmp, st));
     MT_HIP(launch_clear_cells(c->cell_range.as<int2>(), g, cap.cells, st));
-    MT_HIP(launch_cell_ranges(c->keys.as<uint32_t>(), c->vals.as<uint32_t>(), nm, c->box_m.as<double>(),
-                              c->cell_range.as<int2>(), c->sbox.as<double>(), st));
+    MT_HIP(launch_cell_ranges(c->keys.as<uint32_t>(), c->vals.as<uint32_t>(), nm, c->box_m.as<double>(), g,
+                              c->cell_range.as<int2>(), c->sbox.as<double>(), c->qbox.as<uint64_t>(), st));
   }
   {
     // candidates: count, scan, fill (sorted by master within each slave),
     // each screened as it is written (projection onto the slave plane,
     // degeneracy checks, separating-line test)
     PhaseTimer t(c, MT_T_CAND, st);
-    MT_HIP(launch_cand_count(c->box_s.as<double>(), ns, c->sbox.as<double>(), c->vals.as<uint32_t>(),
-                             c->cell_range.as<int2>(), g, c->params.delta, c->cand_cnt.as<int32_t>(),
-                             c->cand_tmp.as<int32_t>(), st));
+    MT_HIP(launch_cand_count(c->box_s.as<double>(), ns, c->sbox.as<double>(), c->qbox.as<uint64_t>(),
+                             c->vals.as<uint32_t>(), c->cell_range.as<int2>(), g, c->params.delta,
+                             c->cand_cnt.as<int32_t>(), c->cand_tmp.as<int32_t>(), st));
     MT_HIP(scan_exclusive(c->cand_cnt.as<int32_t>(), c->cand_off.as<int32_t>(), ns, c->scan_tmp, st));
     MT_HIP(launch_stage_totals(0, c->cand_off.as<int32_t>(), ns, cap.candidates, dst, st));
     MT_HIP(launch_cand_fill(c->box_s.as<double>(), ns, c->sbox.as<double>(), c->vals.as<uint32_t>(),
@@ -714,7 +716,7 @@ int mt_csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, void* stream) {
   if (aux) {
     {
       PhaseTimer t(c, MT_T_GRAD_REDUCE, c->aux);
-      int rc = build_master_index(c, c->aux, c->aux_hist, c->aux_scan);
+      int rc = build_master_index(c, c->aux, c->aux_scan);
       if (rc) return rc;
     }
     MT_HIP(hipEventRecord(c->aux_join, c->aux));
@@ -835,22 +837,14 @@ int mt::ensure_master_index(mt_ctx* c, hipStream_t st) {
     if (rc) return rc;
     c->have_inc[1] = true;
   }
-  return build_master_index(c, st, c->sort_hist, c->scan_tmp);
+  return build_master_index(c, st, c->scan_tmp);
 }
 
-int mt::build_master_index(mt_ctx* c, hipStream_t st, const Buf& hist, const Buf& scan_tmp) {
+int mt::build_master_index(mt_ctx* c, hipStream_t st, const Buf& scan_tmp) {
   const DeviceMesh& M = c->side[1];
-  const int64_t P = c->cap.pairs;
-  const int32_t* np_dev = dev_n_pairs(c);
-  MT_HIP(hipMemcpyAsync(c->mp_keys.p, c->pair_m.p, 4 * (size_t)P, hipMemcpyDeviceToDevice, st));
-  MT_HIP(launch_iota(c->mp_vals.as<uint32_t>(), np_dev, P, st));
-  int bits = 1;
-  while ((int64_t(1) << bits) < std::max<int32_t>(M.n_el, 2)) ++bits;
-  MT_HIP(radix_sort_pairs(c->mp_keys.as<uint32_t>(), c->mp_vals.as<uint32_t>(), c->keys_tmp.as<uint32_t>(),
-                          c->vals_tmp.as<uint32_t>(), P, np_dev, bits, hist, scan_tmp, st));
-  MT_HIP(fill_i32(c->mp_off.as<int32_t>(), 0, 2 * ((int64_t)M.n_el + 1), st));
-  MT_HIP(launch_mpair_off(c->mp_keys.as<uint32_t>(), c->mp_vals.as<uint32_t>(), np_dev, P, M.n_el,
-                          c->mp_off.as<int32_t>(), c->mp_pos.as<int32_t>(), st));
+  MT_HIP(launch_master_index(c->pair_m.as<int32_t>(), dev_n_pairs(c), c->cap.pairs, M.n_el, c->mp_cnt.as<int32_t>(),
+                             c->mp_cur.as<int32_t>(), c->mp_off.as<int32_t>(), c->mp_vals.as<uint32_t>(),
+                             c->mp_tmp.as<uint32_t>(), c->mp_pos.as<int32_t>(), scan_tmp, st));
   c->have_master_index = true;
   return MT_OK;
 }
@@ -915,7 +909,7 @@ int mt_backward(mt_ctx* c, const double* W_D, const double* W_M, const double* w
   MT_HIP(launch_grad_slave(c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(), S.n_nodes, c->pair_off.as<int32_t>(),
                            c->gpair.as<double>(), P, gXs, st));
   const int32_t* mo = c->mp_off.as<int32_t>();
-  MT_HIP(launch_grad_master(c->minc_off.as<int32_t>(), c->minc_list.as<int32_t>(), M.n_nodes, mo, mo + M.n_el,
+  MT_HIP(launch_grad_master(c->minc_off.as<int32_t>(), c->minc_list.as<int32_t>(), M.n_nodes, mo, mo + 1,
                             c->gpair.as<double>(), P, gXm, st));
   if (nodal) {
     // through the element plane normals to the nodal normals and the
@@ -997,6 +991,16 @@ int mt_get_stats(mt_ctx* c, mt_stats* out) {
 }  // extern "C"
 
 int mt::ensure_normals(mt_ctx* c, hipStream_t st) { return normals_for_coords(c, st); }
+
+// ---- search of many interfaces ------------------------------------------------
+int mt::search_no_wait(mt_ctx* c, hipStream_t st) {
+  const bool timing = c->timing;
+  c->timing = false;
+  int rc = mt_build_pairs(c, &c->cap, c->ws, c->ws_bytes, nullptr, nullptr, st);
+  if (rc == MT_OK) rc = mt_csr_pattern(c, nullptr, nullptr, st);
+  c->timing = timing;
+  return rc;
+}
 
 // ---- the build that allocates nothing ------------------------------------------
 // For callers that cannot allocate device memory (code under HIP graph

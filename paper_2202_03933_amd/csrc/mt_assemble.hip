@@ -393,17 +393,6 @@ __global__ __launch_bounds__(BS) void k_grad_slave(const int32_t* __restrict__ i
   grad_slave_row(a, n, inc_off, inc_list, pair_off, gpair, stride, gX);
 }
 
-__global__ __launch_bounds__(BS) void k_mpair_ranges(const uint32_t* __restrict__ keys,
-                                                      const int32_t* __restrict__ n_dev, int32_t* __restrict__ start,
-                                                      int32_t* __restrict__ end) {
-  const int64_t np = *n_dev;
-  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
-  if (i >= np) return;
-  const uint32_t k = keys[i];
-  if (i == 0 || keys[i - 1] != k) start[k] = (int32_t)i;
-  if (i == np - 1 || keys[i + 1] != k) end[k] = (int32_t)(i + 1);
-}
-
 __global__ __launch_bounds__(BS) void k_grad_master(const int32_t* __restrict__ inc_off,
                                                      const int32_t* __restrict__ inc_list, int32_t n,
                                                      const int32_t* __restrict__ mstart,
@@ -415,17 +404,131 @@ __global__ __launch_bounds__(BS) void k_grad_master(const int32_t* __restrict__ 
   grad_master_row(b, n, inc_off, inc_list, mstart, mend, gpair, stride, gX);
 }
 
-// Rank of each pair in the pairs-by-master order: mpos[mpairs[k]] = k.
-__global__ __launch_bounds__(BS) void k_mpair_pos(const uint32_t* __restrict__ mpairs,
-                                                   const int32_t* __restrict__ n_dev, int32_t* __restrict__ mpos) {
-  const int64_t k = (int64_t)blockIdx.x * BS + threadIdx.x;
-  if (k < *n_dev) mpos[mpairs[k]] = (int32_t)k;
+// Pairs by master element (the order the master-node gradient sums read):
+// a counting sort -- pairs per master element (integer atomics), their
+// exclusive scan, a scatter into each element's range -- then each range
+// sorted ascending, so the order is the stable one (pair index within a
+// master element) whatever order the atomics took; rank of each pair in it.
+// A range of up to MS_SMALL pairs is sorted by one thread; a longer one (a
+// master element much coarser than the slave elements it meets) goes on a
+// list for a workgroup, which sorts runs of MS_RUN in LDS and merges them.
+constexpr int MS_SMALL = 32;
+constexpr int MS_RUN = 2048;
+constexpr int MS_BLOCKS = 512;
+
+__global__ __launch_bounds__(BS) void k_mcount(const int32_t* __restrict__ pair_m, const int32_t* __restrict__ n_dev,
+                                                int32_t* __restrict__ cnt) {
+  const int64_t p = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (p < *n_dev) atomicAdd(&cnt[pair_m[p]], 1);
 }
 
-// Identity values 0..n-1 (the pair indices sorted by master).
-__global__ __launch_bounds__(BS) void k_iota(uint32_t* __restrict__ v, const int32_t* __restrict__ n_dev) {
-  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
-  if (i < *n_dev) v[i] = (uint32_t)i;
+__global__ __launch_bounds__(BS) void k_mscatter(const int32_t* __restrict__ pair_m, const int32_t* __restrict__ n_dev,
+                                                  const int32_t* __restrict__ off, int32_t* __restrict__ cur,
+                                                  uint32_t* __restrict__ vals) {
+  const int64_t p = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if (p >= *n_dev) return;
+  const int m = pair_m[p];
+  vals[off[m] + atomicAdd(&cur[m], 1)] = (uint32_t)p;
+}
+
+// Short ranges: insertion sort, ranks.  Long ranges: appended to `big`
+// (its length in *n_big; the list order does not matter, each range is
+// sorted on its own).
+__global__ __launch_bounds__(BS) void k_msort(const int32_t* __restrict__ off, int32_t n_m_el,
+                                               uint32_t* __restrict__ vals, int32_t* __restrict__ mpos,
+                                               int32_t* __restrict__ big, int32_t* __restrict__ n_big) {
+  const int m = blockIdx.x * BS + threadIdx.x;
+  if (m >= n_m_el) return;
+  const int b = off[m], e = off[m + 1];
+  if (e - b > MS_SMALL) {
+    big[atomicAdd(n_big, 1)] = m;
+    return;
+  }
+  for (int i = b + 1; i < e; ++i) {
+    const uint32_t v = vals[i];
+    int j = i - 1;
+    while (j >= b && vals[j] > v) {
+      vals[j + 1] = vals[j];
+      --j;
+    }
+    vals[j + 1] = v;
+  }
+  for (int k = b; k < e; ++k) mpos[vals[k]] = k;
+}
+
+// Ascending bitonic sort of a[0..n) (n <= MS_RUN) through LDS, by the block.
+__device__ void block_sort_run(uint32_t* __restrict__ a, int n, uint32_t* __restrict__ s) {
+  int n2 = 2;
+  while (n2 < n) n2 <<= 1;
+  for (int t = threadIdx.x; t < n2; t += BS) s[t] = t < n ? a[t] : 0xffffffffu;
+  __syncthreads();
+  for (int size = 2; size <= n2; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int t = threadIdx.x; t < (n2 >> 1); t += BS) {
+        const int i = 2 * t - (t & (stride - 1));
+        const int j = i + stride;
+        const uint32_t x = s[i], y = s[j];
+        if ((x > y) == ((i & size) == 0)) {
+          s[i] = y;
+          s[j] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int t = threadIdx.x; t < n; t += BS) a[t] = s[t];
+  __syncthreads();
+}
+
+// Merge of the sorted runs x[0..nx) and y[0..ny) (distinct values) into
+// out[0..nx+ny) by the block: each thread takes an equal share of the
+// output and finds where it starts by a search along its diagonal.
+__device__ void block_merge(const uint32_t* __restrict__ x, int nx, const uint32_t* __restrict__ y, int ny,
+                            uint32_t* __restrict__ out) {
+  const int n = nx + ny;
+  const int seg = (n + BS - 1) / BS;
+  const int d = min(n, (int)threadIdx.x * seg);
+  const int end = min(n, d + seg);
+  int lo = max(0, d - ny), hi = min(d, nx);
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (x[mid] < y[d - mid - 1])
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  int i = lo, j = d - lo;
+  for (int o = d; o < end; ++o) out[o] = (j >= ny || (i < nx && x[i] < y[j])) ? x[i++] : y[j++];
+}
+
+__global__ __launch_bounds__(BS) void k_msort_big(const int32_t* __restrict__ off, const int32_t* __restrict__ big,
+                                                   const int32_t* __restrict__ n_big, uint32_t* __restrict__ vals,
+                                                   uint32_t* __restrict__ tmp, int32_t* __restrict__ mpos) {
+  __shared__ uint32_t s[MS_RUN];
+  const int nb = *n_big;
+  for (int q = blockIdx.x; q < nb; q += gridDim.x) {
+    const int m = big[q];
+    const int b = off[m], k = off[m + 1] - b;
+    for (int r = 0; r < k; r += MS_RUN) block_sort_run(vals + b + r, min(MS_RUN, k - r), s);
+    uint32_t* src = vals + b;
+    uint32_t* dst = tmp + b;
+    for (int w = MS_RUN; w < k; w <<= 1) {
+      for (int lo = 0; lo < k; lo += 2 * w) {
+        const int mid = min(k, lo + w), hi = min(k, lo + 2 * w);
+        block_merge(src + lo, mid - lo, src + mid, hi - mid, dst + lo);
+      }
+      __syncthreads();
+      uint32_t* t = src;
+      src = dst;
+      dst = t;
+    }
+    for (int t = threadIdx.x; t < k; t += BS) {
+      const uint32_t v = src[t];
+      if (src != vals + b) vals[b + t] = v;
+      mpos[v] = b + t;
+    }
+    __syncthreads();
+  }
 }
 
 inline unsigned grid_of(int64_t n) { return (unsigned)((n + BS - 1) / BS); }
@@ -500,18 +603,26 @@ hipError_t launch_grad_slave(const int32_t* inc_off, const int32_t* inc_list, in
   return hipGetLastError();
 }
 
-hipError_t launch_iota(uint32_t* v, const int32_t* n_dev, int64_t cap, hipStream_t s) {
-  if (cap == 0) return hipSuccess;
-  k_iota<<<grid_of(cap), BS, 0, s>>>(v, n_dev);
-  return hipGetLastError();
-}
-
-hipError_t launch_mpair_off(const uint32_t* sorted_m, const uint32_t* mpairs, const int32_t* n_pairs, int64_t cap,
-                            int32_t n_m_el, int32_t* off, int32_t* mpos, hipStream_t s) {
-  // off holds start[n_m_el] followed by end[n_m_el]; both pre-zeroed.
-  if (cap == 0) return hipSuccess;
-  k_mpair_ranges<<<grid_of(cap), BS, 0, s>>>(sorted_m, n_pairs, off, off + n_m_el);
-  k_mpair_pos<<<grid_of(cap), BS, 0, s>>>(mpairs, n_pairs, mpos);
+hipError_t launch_master_index(const int32_t* pair_m, const int32_t* n_pairs, int64_t cap, int32_t n_m_el,
+                               int32_t* cnt, int32_t* cur, int32_t* off, uint32_t* vals, uint32_t* tmp, int32_t* mpos,
+                               const Buf& scan_tmp, hipStream_t s) {
+  if (n_m_el == 0) return hipSuccess;
+  // cnt[n_m_el] counts the long ranges; cur, after the scatter, lists them
+  hipError_t e = fill_i32(cnt, 0, (int64_t)n_m_el + 1, s);
+  if (e == hipSuccess) e = fill_i32(cur, 0, (int64_t)n_m_el + 1, s);
+  if (e != hipSuccess) return e;
+  if (cap > 0) {
+    k_mcount<<<grid_of(cap), BS, 0, s>>>(pair_m, n_pairs, cnt);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if ((e = scan_exclusive(cnt, off, n_m_el, scan_tmp, s)) != hipSuccess) return e;
+  if (cap > 0) {
+    k_mscatter<<<grid_of(cap), BS, 0, s>>>(pair_m, n_pairs, off, cur, vals);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  k_msort<<<grid_of(n_m_el), BS, 0, s>>>(off, n_m_el, vals, mpos, cur, cnt + n_m_el);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  k_msort_big<<<(unsigned)std::min<int64_t>(MS_BLOCKS, n_m_el), BS, 0, s>>>(off, cur, cnt + n_m_el, vals, tmp, mpos);
   return hipGetLastError();
 }
 

@@ -324,6 +324,11 @@ struct mt_batch {
   int64_t max_pitems = 0;  // pair items the workspace holds (buckets of at least MIN_BUCKET pairs)
   hipGraphExec_t g_fwd = nullptr, g_bwd = nullptr;
   hipStream_t g_fwd_stream = nullptr, g_bwd_stream = nullptr;
+  // the search of all instances (mt_batch_search): instances go round-robin
+  // onto internal streams forked from and joined back into the caller's
+  static constexpr int NSEARCH = 4;
+  hipStream_t s_stream[NSEARCH] = {};
+  hipEvent_t s_fork = nullptr, s_join[NSEARCH] = {};
 };
 
 using namespace mt;
@@ -556,6 +561,11 @@ int mt_batch_destroy(mt_batch* b) {
   (void)hipSetDevice(b->device);
   (void)hipDeviceSynchronize();
   drop_graphs(b);
+  for (int k = 0; k < mt_batch::NSEARCH; ++k) {
+    if (b->s_stream[k]) (void)hipStreamDestroy(b->s_stream[k]);
+    if (b->s_join[k]) (void)hipEventDestroy(b->s_join[k]);
+  }
+  if (b->s_fork) (void)hipEventDestroy(b->s_fork);
   if (b->pinned) (void)hipHostFree(b->pinned);
   delete b;
   return MT_OK;
@@ -690,7 +700,7 @@ int mt_batch_build(mt_batch* b, const mt_batch_tuning* tuning, void* ws, size_t 
     I.minc_off = c->minc_off.as<int32_t>();
     I.minc_list = c->minc_list.as<int32_t>();
     I.mstart = c->mp_off.as<int32_t>();
-    I.mend = c->mp_off.as<int32_t>() ? c->mp_off.as<int32_t>() + M.n_el : nullptr;
+    I.mend = c->mp_off.as<int32_t>() + 1;
     I.mpos = c->mp_pos.as<int32_t>();
     I.blk = c->blk.as<double>();
     I.gpair = c->gpair.as<double>();
@@ -786,6 +796,44 @@ int mt_batch_backward(mt_batch* b, const double* const* W_D, const double* const
     }
   if (use_graph) return run_graph(&b->g_bwd, &b->g_bwd_stream, st, [&]() { return launch_bwd_all(b, st); });
   return launch_bwd_all(b, st);
+}
+
+int mt_batch_search(mt_batch* b, int use_graph, void* stream) {
+  if (!b) return bfail(MT_EINVAL, "mt_batch_search: null");
+  if (b->ctxs.empty()) return bfail(MT_ESTATE, "mt_batch_search: no instances");
+  // A HIP-graph capture of this sequence (the caller's stream forked to the
+  // internal streams, each forking again to its instances' internal
+  // streams) ended the process with a segmentation fault inside the
+  // capturing call; the cause is not found, so capture is refused.
+  if (use_graph) return bfail(MT_EUNSUPPORTED, "mt_batch_search: graph capture is not supported");
+  hipStream_t st = (hipStream_t)stream;
+  B_HIP(hipSetDevice(b->device));
+  for (mt_ctx* c : b->ctxs) {
+    if (!c->ws || c->static_gen != 0)
+      return bfail(MT_ESTATE, "mt_batch_search: every instance needs its own workspace bound by mt_build_pairs");
+    if (!c->side[0].set || !c->side[1].set) return bfail(MT_ESTATE, "mt_batch_search: an instance is not uploaded");
+  }
+  if (!b->s_fork) {
+    B_HIP(hipEventCreateWithFlags(&b->s_fork, hipEventDisableTiming));
+    for (int k = 0; k < mt_batch::NSEARCH; ++k) {
+      B_HIP(hipStreamCreateWithFlags(&b->s_stream[k], hipStreamNonBlocking));
+      B_HIP(hipEventCreateWithFlags(&b->s_join[k], hipEventDisableTiming));
+    }
+  }
+  B_HIP(hipEventRecord(b->s_fork, st));
+  for (int k = 0; k < mt_batch::NSEARCH; ++k) B_HIP(hipStreamWaitEvent(b->s_stream[k], b->s_fork, 0));
+  int rc = MT_OK;
+  for (size_t i = 0; i < b->ctxs.size() && rc == MT_OK; ++i)
+    rc = search_no_wait(b->ctxs[i], b->s_stream[i % mt_batch::NSEARCH]);
+  // joined back also after an error, so that the caller's stream orders
+  // after whatever was launched
+  for (int k = 0; k < mt_batch::NSEARCH; ++k) {
+    B_HIP(hipEventRecord(b->s_join[k], b->s_stream[k]));
+    B_HIP(hipStreamWaitEvent(st, b->s_join[k], 0));
+  }
+  // read-backs of the instances' counts wait on the caller's stream
+  for (mt_ctx* c : b->ctxs) c->last_stream = st;
+  return rc;
 }
 
 int mt_batch_autotune(mt_batch* b, mt_batch_tuning* out, void* stream) {

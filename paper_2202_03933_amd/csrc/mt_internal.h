@@ -57,6 +57,10 @@ struct Grid {
   int64_t ncells;
   double reach;  // delta + half the largest element box extent, padded: a master whose box
                  // touches the delta-enlarged slave box has its centre within this of the slave box
+  // quantisation of box bounds for the candidate prefilter: level q of axis d
+  // stands for qo[d] + q qu[d] (qu a power of two, q < 2^21)
+  double qo[3];
+  double qu[3];
 };
 
 // Device-side scalar reductions of the element preparation step.
@@ -173,6 +177,7 @@ struct mt_ctx {
   mt::Buf keys, vals, keys_tmp, vals_tmp;  // [max(n_m_el, pair capacity)]
   mt::Buf cell_range;      // int2 [cell capacity]: sorted-master range of each cell
   mt::Buf sbox;            // [n_m_el][6] master boxes in cell order
+  mt::Buf qbox;            // uint64 [n_m_el][2] their bounds quantised (candidate prefilter)
   // candidates
   mt::Buf cand_cnt;        // [n_s_el + 1]
   mt::Buf cand_tmp;        // [CTMP][n_s_el] candidates kept by the count pass
@@ -217,12 +222,15 @@ struct mt_ctx {
   // pairs-by-master index while the pattern is built on the caller's stream
   hipStream_t aux = nullptr;
   hipEvent_t aux_fork = nullptr, aux_join = nullptr;
-  mt::Buf aux_hist, aux_scan;
+  mt::Buf aux_scan;
   mt::Buf blk;             // [36][pair capacity]
   int64_t blk_gen = -1;    // coord_gen of the blocks in blk (mt_integrate)
   bool blk_pending = false;  // blocks computed by mt_csr_pattern, not yet assembled
   mt::Buf gpair;           // [24][pair capacity]
-  mt::Buf mp_keys, mp_vals, mp_off;  // pairs sorted by master element
+  mt::Buf mp_cnt, mp_cur;  // int32 [n_m_el + 1] counting-sort scratch of the pairs-by-master index
+  mt::Buf mp_off;          // int32 [n_m_el + 1] range of each master element in that order
+  mt::Buf mp_vals;         // uint32 [pair capacity] pairs sorted by master element
+  mt::Buf mp_tmp;          // uint32 [pair capacity] merge scratch of that sort
   mt::Buf mp_pos;          // int32 [pair capacity]: rank of each pair in that order
   // scan / sort scratch
   mt::Buf scan_tmp, sort_hist;
@@ -265,10 +273,10 @@ hipError_t launch_master_keys(const double* box_m, int32_t n_m, const Grid* g, u
                               hipStream_t s);
 hipError_t launch_clear_cells(int2* range, const Grid* g, int64_t max_cells, hipStream_t s);
 hipError_t launch_cell_ranges(const uint32_t* keys, const uint32_t* vals, int32_t n, const double* box_m,
-                              int2* range, double* sbox, hipStream_t s);
-hipError_t launch_cand_count(const double* box_s, int32_t n_s, const double* sbox, const uint32_t* mvals,
-                             const int2* range, const Grid* g, double delta, int32_t* count, int32_t* tmp,
-                             hipStream_t s);
+                              const Grid* g, int2* range, double* sbox, uint64_t* qbox, hipStream_t s);
+hipError_t launch_cand_count(const double* box_s, int32_t n_s, const double* sbox, const uint64_t* qbox,
+                             const uint32_t* mvals, const int2* range, const Grid* g, double delta, int32_t* count,
+                             int32_t* tmp, hipStream_t s);
 // Candidates of slave s go to [off[s], off[s + 1]) of cand_s / cand_m / nv /
 // flag, whose length is cap: a slave whose range ends beyond cap writes
 // nothing and gets scr_cnt[s] = 0 (the stage totals flag the excess).
@@ -338,10 +346,12 @@ hipError_t launch_assemble(const int32_t* inc_off, const int32_t* inc_list, int3
 hipError_t launch_grad_slave(const int32_t* inc_off, const int32_t* inc_list, int32_t n_nodes,
                              const int32_t* pair_off, const double* gpair, int64_t stride, double* gX,
                              hipStream_t s);
-// Master ranges of the pairs-by-master order and each pair's rank in it.
-hipError_t launch_iota(uint32_t* v, const int32_t* n_dev, int64_t cap, hipStream_t s);
-hipError_t launch_mpair_off(const uint32_t* sorted_m, const uint32_t* mpairs, const int32_t* n_pairs, int64_t cap,
-                            int32_t n_m_el, int32_t* off, int32_t* mpos, hipStream_t s);
+// Pairs by master element: off[m] .. off[m + 1] the range of master element
+// m in vals (pair indices, ascending within the range), mpos[p] the rank of
+// pair p in that order; cnt, cur scratch of n_m_el + 1, tmp of cap.
+hipError_t launch_master_index(const int32_t* pair_m, const int32_t* n_pairs, int64_t cap, int32_t n_m_el,
+                               int32_t* cnt, int32_t* cur, int32_t* off, uint32_t* vals, uint32_t* tmp, int32_t* mpos,
+                               const Buf& scan_tmp, hipStream_t s);
 hipError_t launch_grad_master(const int32_t* inc_off, const int32_t* inc_list, int32_t n_nodes,
                               const int32_t* mstart, const int32_t* mend, const double* gpair, int64_t stride,
                               double* gX, hipStream_t s);
@@ -382,9 +392,9 @@ KParams kparams(const mt_params& p);
 // Node incidence of the master side and the pairs-by-master permutation
 // (needed by the backward's master-node reduction); built once per pattern.
 int ensure_master_index(mt_ctx* c, hipStream_t st);
-// The same on a given stream with its own sort scratch (the master incidence
+// The same on a given stream with its own scan scratch (the master incidence
 // must exist already).
-int build_master_index(mt_ctx* c, hipStream_t st, const Buf& hist, const Buf& scan_tmp);
+int build_master_index(mt_ctx* c, hipStream_t st, const Buf& scan_tmp);
 // Polygon buffers of the current pair list, and their view.
 int ensure_poly(mt_ctx* c);
 PolyBuf poly_buf(mt_ctx* c);
@@ -396,6 +406,12 @@ int host_counts(mt_ctx* c);
 // MT_OK while the context's workspace still holds its build (MT_ESTATE once
 // another context bound the static scratch this one was built in).
 int ws_live(mt_ctx* c);
+
+// ---- search of many interfaces (mt_batch_search) ------------------------------
+// mt_build_pairs into the bound workspace and capacities, then mt_csr_pattern,
+// without read-back (and without phase timers) on stream st.
+int search_no_wait(mt_ctx* c, hipStream_t st);
+
 void set_error(const std::string& msg);
 
 }  // namespace mt

@@ -52,74 +52,123 @@ __device__ __forceinline__ int64_t live_count(int64_t n, const int32_t* n_dev) {
   return m < 0 ? 0 : (m < n ? m : n);
 }
 
-template <class T>
-__global__ __launch_bounds__(SCAN_BS) void k_tile_sums(const T* __restrict__ in, int64_t n, const int32_t* n_dev,
-                                                       T* __restrict__ sums) {
-  n = live_count<T>(n, n_dev);
-  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IPT;
-  T s = 0;
+// Exclusive scan: per-tile sums, then each tile's scan with its offset.
+// Up to SCAN_DIRECT tiles, every tile adds up the sums before it itself (no
+// third launch; the sums are a few KB, read from L2); beyond, the sums are
+// scanned recursively first.  No tile waits for another.
+constexpr int64_t SCAN_DIRECT = 8192;
+
+// The SCAN_IPT values of thread's slot (zero past `live`): two 16-byte loads
+// when VEC (in 16-byte aligned) and the slot is whole.
+template <bool VEC>
+__device__ __forceinline__ void load_slot(const int32_t* __restrict__ in, int64_t base, int64_t live,
+                                          int32_t v[SCAN_IPT]) {
+  static_assert(SCAN_IPT == 8, "two 16-byte vectors per thread");
+  if (VEC && base + SCAN_IPT <= live) {
+    const int4 a = *reinterpret_cast<const int4*>(in + base);
+    const int4 b = *reinterpret_cast<const int4*>(in + base + 4);
+    v[0] = a.x, v[1] = a.y, v[2] = a.z, v[3] = a.w, v[4] = b.x, v[5] = b.y, v[6] = b.z, v[7] = b.w;
+  } else {
 #pragma unroll
-  for (int i = 0; i < SCAN_IPT; ++i)
-    if (base + i < n) s += in[base + i];
-  T tot;
+    for (int i = 0; i < SCAN_IPT; ++i) v[i] = (base + i < live) ? in[base + i] : 0;
+  }
+}
+
+template <bool VEC>
+__global__ __launch_bounds__(SCAN_BS) void k_tile_sums(const int32_t* __restrict__ in, int64_t n,
+                                                       const int32_t* n_dev, int32_t* __restrict__ sums) {
+  const int64_t live = live_count<int32_t>(n, n_dev);
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IPT;
+  int32_t v[SCAN_IPT];
+  load_slot<VEC>(in, base, live, v);
+  int32_t s = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_IPT; ++i) s += v[i];
+  int32_t tot;
   block_exclusive(s, &tot);
   if (threadIdx.x == 0) sums[blockIdx.x] = tot;
 }
 
-// out[i] = offs[tile] + exclusive prefix of in within the tile; the last
-// tile also writes out[n] = grand total.
-template <class T>
-__global__ __launch_bounds__(SCAN_BS) void k_tile_scan(const T* __restrict__ in, int64_t n, const int32_t* n_dev,
-                                                       const T* __restrict__ offs, T* __restrict__ out) {
-  const int64_t live = live_count<T>(n, n_dev);
-  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IPT;
-  T v[SCAN_IPT];
-  T s = 0;
-#pragma unroll
-  for (int i = 0; i < SCAN_IPT; ++i) {
-    v[i] = (base + i < live) ? in[base + i] : T(0);
-    s += v[i];
+// out[i] = offset of the tile + exclusive prefix of in within the tile; the
+// last tile also writes out[n] = grand total.  Offset of tile t: offs[t]
+// (scanned), or with DIRECT the sum of sums[0..t) (raw tile sums), or 0.
+template <bool VEC, bool DIRECT>
+__global__ __launch_bounds__(SCAN_BS) void k_tile_scan(const int32_t* __restrict__ in, int64_t n,
+                                                       const int32_t* n_dev, const int32_t* __restrict__ offs,
+                                                       int32_t* __restrict__ out) {
+  const int64_t live = live_count<int32_t>(n, n_dev);
+  const int64_t t = blockIdx.x;
+  int32_t off = 0;
+  if (DIRECT) {
+    int32_t part = 0;
+    for (int64_t i = threadIdx.x; i < t; i += SCAN_BS) part += offs[i];
+    block_exclusive(part, &off);
+  } else if (offs) {
+    off = offs[t];
   }
-  T tot;
-  T run = block_exclusive(s, &tot) + (offs ? offs[blockIdx.x] : T(0));
+  const int64_t base = t * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IPT;
+  int32_t v[SCAN_IPT];
+  load_slot<VEC>(in, base, live, v);
+  int32_t s = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_IPT; ++i) s += v[i];
+  int32_t tot;
+  int32_t run = block_exclusive(s, &tot) + off;
+  int32_t o[SCAN_IPT];
 #pragma unroll
   for (int i = 0; i < SCAN_IPT; ++i) {
-    if (base + i < n) out[base + i] = run;
+    o[i] = run;
     run += v[i];
   }
-  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == SCAN_BS - 1) out[n] = run;
+  if (VEC && base + SCAN_IPT <= n) {
+    *reinterpret_cast<int4*>(out + base) = make_int4(o[0], o[1], o[2], o[3]);
+    *reinterpret_cast<int4*>(out + base + 4) = make_int4(o[4], o[5], o[6], o[7]);
+  } else {
+#pragma unroll
+    for (int i = 0; i < SCAN_IPT; ++i)
+      if (base + i < n) out[base + i] = o[i];
+  }
+  if (t == (int64_t)gridDim.x - 1 && threadIdx.x == SCAN_BS - 1) out[n] = run;
 }
 
 // Exclusive scan of n values (of the first *n_dev when given; the rest count
 // as zero) into out[0..n].  No memset: the launches can be captured in a
 // graph.
-template <class T>
-hipError_t scan_impl(const T* in, T* out, int64_t n, const int32_t* n_dev, T* tmp, hipStream_t s) {
+hipError_t scan_impl(const int32_t* in, int32_t* out, int64_t n, const int32_t* n_dev, int32_t* tmp, hipStream_t s) {
   const int64_t tiles = std::max<int64_t>(1, (n + SCAN_TILE - 1) / SCAN_TILE);
+  const bool vec = ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15) == 0;
   if (tiles == 1) {
-    k_tile_scan<T><<<1, SCAN_BS, 0, s>>>(in, n, n_dev, nullptr, out);
+    auto* k = vec ? k_tile_scan<true, false> : k_tile_scan<false, false>;
+    k<<<1, SCAN_BS, 0, s>>>(in, n, n_dev, nullptr, out);
     return hipGetLastError();
   }
-  T* sums = tmp;
-  T* offs = tmp + tiles;  // tiles + 1 entries
-  T* rest = offs + tiles + 1;
-  k_tile_sums<T><<<(unsigned)tiles, SCAN_BS, 0, s>>>(in, n, n_dev, sums);
+  int32_t* sums = tmp;
+  (vec ? k_tile_sums<true> : k_tile_sums<false>)<<<(unsigned)tiles, SCAN_BS, 0, s>>>(in, n, n_dev, sums);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  e = scan_impl<T>(sums, offs, tiles, nullptr, rest, s);
+  if (tiles <= SCAN_DIRECT) {
+    auto* k = vec ? k_tile_scan<true, true> : k_tile_scan<false, true>;
+    k<<<(unsigned)tiles, SCAN_BS, 0, s>>>(in, n, n_dev, sums, out);
+    return hipGetLastError();
+  }
+  int32_t* offs = tmp + tiles;  // tiles + 1 entries
+  e = scan_impl(sums, offs, tiles, nullptr, offs + tiles + 1, s);
   if (e != hipSuccess) return e;
-  k_tile_scan<T><<<(unsigned)tiles, SCAN_BS, 0, s>>>(in, n, n_dev, offs, out);
+  auto* k = vec ? k_tile_scan<true, false> : k_tile_scan<false, false>;
+  k<<<(unsigned)tiles, SCAN_BS, 0, s>>>(in, n, n_dev, offs, out);
   return hipGetLastError();
 }
 
 }  // namespace
 
 int64_t scan_tmp_elems(int64_t n) {
+  // per level: the tile sums and their scan (tiles + 1), while recursing
   int64_t total = 0;
   while (true) {
     const int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
     if (tiles <= 1) break;
     total += 2 * tiles + 1;
+    if (tiles <= SCAN_DIRECT) break;
     n = tiles;
   }
   return total + 1;
@@ -232,13 +281,13 @@ __global__ void k_copy_u32(const uint32_t* __restrict__ a, uint32_t* __restrict_
 
 hipError_t scan_exclusive(const int32_t* in, int32_t* out, int64_t n, const Buf& tmp, hipStream_t s) {
   if ((int64_t)(tmp.bytes / sizeof(int32_t)) < scan_tmp_elems(n)) return hipErrorInvalidValue;
-  return scan_impl<int32_t>(in, out, n, nullptr, tmp.as<int32_t>(), s);
+  return scan_impl(in, out, n, nullptr, tmp.as<int32_t>(), s);
 }
 
 hipError_t scan_exclusive_dev(const int32_t* in, int32_t* out, const int32_t* n_dev, int64_t cap, const Buf& tmp,
                               hipStream_t s) {
   if ((int64_t)(tmp.bytes / sizeof(int32_t)) < scan_tmp_elems(cap)) return hipErrorInvalidValue;
-  return scan_impl<int32_t>(in, out, cap, n_dev, tmp.as<int32_t>(), s);
+  return scan_impl(in, out, cap, n_dev, tmp.as<int32_t>(), s);
 }
 
 int64_t radix_hist_elems(int64_t n) { return 2 * ((n + RS_TILE - 1) / RS_TILE) * RS_RADIX + 1; }

@@ -192,6 +192,79 @@ __device__ __forceinline__ int cell_coord(double c, double lo, double inv_beta, 
 }
 
 // Search grid from the element reductions (one thread): the minimal bin size
+// ---- box prefilter ------------------------------------------------------------
+// The candidate test compares (slave lo - delta) with master hi and master lo
+// with (slave hi + delta) on each axis.  Master box bounds are stored as
+// quantisation levels (21 bits each, one 16-byte record per master): level q
+// of axis d stands for B(q) = qo + q qu, computed the same way wherever it is
+// used, so B is non-decreasing in q, and a master bound x is stored as the
+// largest q with B(q) <= x (then B(q) <= x < B(q + 1)).  For each slave the
+// walk computes, per axis, the levels around a = lo - delta and c = hi +
+// delta; a test is then decided by integer comparisons when the levels
+// separate the values, and by the exact FP64 test otherwise, so the
+// candidate list is the one of the exact test.
+constexpr int QBITS = 21;
+constexpr int64_t QMAX = (int64_t(1) << QBITS) - 1;
+constexpr uint64_t QMASK = (uint64_t(1) << QBITS) - 1;
+constexpr uint64_t QEXACT = uint64_t(1) << 63;  // record flag: exact test only
+
+__device__ __forceinline__ double qlevel(const Grid& g, int d, int64_t q) { return g.qo[d] + (double)q * g.qu[d]; }
+
+// max{q in [0, QMAX + 1] : B(q) <= x (B(q) < x when strict)}, -1 when there is
+// none; x finite.  A guess, a few unit steps, then bisection.
+__device__ int64_t q_max_le(const Grid& g, int d, double x, bool strict) {
+  auto ok = [&](int64_t q) {
+    const double b = qlevel(g, d, q);
+    return strict ? b < x : b <= x;
+  };
+  const double f = floor((x - g.qo[d]) / g.qu[d]);
+  int64_t q = (int64_t)fmin(fmax(f, -1.0), (double)(QMAX + 1));
+  for (int it = 0; it < 4; ++it) {
+    if (q >= 0 && !ok(q)) {
+      --q;
+    } else if (q <= QMAX && ok(q + 1)) {
+      ++q;
+    } else {
+      return q;
+    }
+  }
+  int64_t lo = -1, hi = QMAX + 2;  // ok(lo) and !ok(hi), taken as given at the ends
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (ok(mid))
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// Per-slave thresholds of the prefilter: on axis d a master with levels
+// (ql, qh) fails when qh < ea or ql > ecf, passes when qh > la and ql < ecp;
+// anything else goes to the exact test.
+struct QSlave {
+  int32_t la[3], ea[3], ecp[3], ecf[3];
+};
+
+__device__ __forceinline__ QSlave q_slave(const Grid& g, const double lo[3], const double hi[3], double delta) {
+  QSlave t;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const double a = lo[d] - delta, c = hi[d] + delta;  // as in the exact test
+    if (isfinite(a) && isfinite(c)) {
+      t.la[d] = (int32_t)q_max_le(g, d, a, true);
+      t.ea[d] = (int32_t)q_max_le(g, d, a, false);
+      t.ecp[d] = t.ecf[d] = (int32_t)q_max_le(g, d, c, false);
+    } else {  // never decided by the levels
+      t.la[d] = (int32_t)QMAX + 1;
+      t.ea[d] = -1;
+      t.ecp[d] = -1;
+      t.ecf[d] = (int32_t)QMAX + 1;
+    }
+  }
+  return t;
+}
+
 // beta_min = max(longest slave edge, largest box extent + delta, bin_size)
 // (the paper's rule without a motion term, raised so that 27 cells are
 // complete), the node bounding box expanded by beta_min, max(1, floor(L /
@@ -230,6 +303,15 @@ __global__ void k_grid(const PrepReduce* __restrict__ red, double delta, double 
     g.inv_beta[d] = 1.0 / g.beta[d];
   }
   g.ncells = n[0] * n[1] * n[2];
+  // quantisation of the prefilter: levels from the grid's low corner in
+  // steps of a power of two, QMAX + 1 of them spanning at least twice the
+  // grid, so every box bound of the grid lies between levels 0 and QMAX
+  for (int d = 0; d < 3; ++d) {
+    g.qo[d] = g.lo[d];
+    int e = 0;
+    (void)frexp(2.0 * L[d] / (double)QMAX, &e);
+    g.qu[d] = L[d] > 0.0 && isfinite(L[d]) ? ldexp(1.0, e) : 1.0;
+  }
   // padded so that rounding in the box centres cannot move a centre across
   g.reach = (delta + 0.5 * emax) * (1.0 + 1e-9) + 1e-9 * beta_min;
   st->grid = g;
@@ -265,18 +347,39 @@ __global__ __launch_bounds__(BS) void k_master_keys(const double* __restrict__ b
 // i-th sorted master) so that the candidate walks read them contiguously.
 __global__ __launch_bounds__(BS) void k_cell_ranges(const uint32_t* __restrict__ keys,
                                                      const uint32_t* __restrict__ vals, int32_t n,
-                                                     const double* __restrict__ box_m, int2* __restrict__ range,
-                                                     double* __restrict__ sbox) {
+                                                     const double* __restrict__ box_m, const Grid* __restrict__ gp,
+                                                     int2* __restrict__ range, double* __restrict__ sbox,
+                                                     uint64_t* __restrict__ qbox) {
   const int i = blockIdx.x * BS + threadIdx.x;
   if (i >= n) return;
   const uint32_t k = keys[i];
   if (i == 0 || keys[i - 1] != k) range[k].x = i;
   if (i == n - 1 || keys[i + 1] != k) range[k].y = i + 1;
   const int m = (int)vals[i];
+  double bx[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) bx[j] = box_m[(int64_t)j * n + m];
   double2* dst = reinterpret_cast<double2*>(sbox + (int64_t)6 * i);
-  dst[0] = make_double2(box_m[m], box_m[(int64_t)n + m]);
-  dst[1] = make_double2(box_m[(int64_t)2 * n + m], box_m[(int64_t)3 * n + m]);
-  dst[2] = make_double2(box_m[(int64_t)4 * n + m], box_m[(int64_t)5 * n + m]);
+  dst[0] = make_double2(bx[0], bx[1]);
+  dst[1] = make_double2(bx[2], bx[3]);
+  dst[2] = make_double2(bx[4], bx[5]);
+  // quantised record: lo levels in the first word, hi levels in the second
+  const Grid g = *gp;
+  uint64_t w[2] = {0, 0};
+  bool exact = false;
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const int d = j % 3;
+    int64_t q = -1;
+    if (isfinite(bx[j])) q = q_max_le(g, d, bx[j], false);
+    if (q < 0 || q > QMAX) {
+      exact = true;
+      q = 0;
+    }
+    w[j / 3] |= (uint64_t)q << (QBITS * d);
+  }
+  if (exact) w[1] |= QEXACT;
+  reinterpret_cast<ulonglong2*>(qbox)[i] = make_ulonglong2(w[0], w[1]);
 }
 
 struct SlaveBox {
@@ -303,6 +406,26 @@ __device__ __forceinline__ bool touch(const SlaveBox& s, const double* __restric
 #pragma unroll
   for (int d = 0; d < 3; ++d) t = t && (s.lo[d] - delta) <= mhi[d] && mlo[d] <= (s.hi[d] + delta);
   return t;
+}
+
+// The candidate test through the quantised record first (one 16-byte load);
+// the exact test only when the levels do not decide it.
+__device__ __forceinline__ bool touch_q(const SlaveBox& s, const QSlave& t, const double* __restrict__ sbox,
+                                        const uint64_t* __restrict__ qbox, int i, double delta) {
+  const ulonglong2 rec = reinterpret_cast<const ulonglong2*>(qbox)[i];
+  bool fail = false, pass = (rec.y & QEXACT) == 0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int32_t ql = (int32_t)((rec.x >> (QBITS * d)) & QMASK);
+    const int32_t qh = (int32_t)((rec.y >> (QBITS * d)) & QMASK);
+    fail = fail || qh < t.ea[d] || ql > t.ecf[d];
+    pass = pass && qh > t.la[d] && ql < t.ecp[d];
+  }
+  if ((rec.y & QEXACT) == 0) {
+    if (fail) return false;
+    if (pass) return true;
+  }
+  return touch(s, sbox, i, delta);
 }
 
 constexpr int CCAP = 48;  // per-thread LDS segment of the long-list fill (masters)
@@ -367,11 +490,13 @@ __device__ __forceinline__ int walk_cells(const SlaveBox& b, const double* __res
 // by a wave ballot, so v receives the same candidates in the same order as
 // the one-lane walk, and the boxes a group reads in one step are adjacent.
 __device__ __forceinline__ int walk_cells_group(const SlaveBox& b, const double* __restrict__ sbox,
+                                                const uint64_t* __restrict__ qbox,
                                                 const uint32_t* __restrict__ mvals, const int2* __restrict__ range,
                                                 const Grid& g, double delta, int32_t* v, int64_t vs, int vcap, int r,
                                                 int gshift) {
   int c0[3], c1[3];
   cell_window(b, g, c0, c1);
+  const QSlave qs = q_slave(g, b.lo, b.hi, delta);
   const unsigned below = (1u << r) - 1u;
   int c = 0;
   for (int zz = c0[2]; zz <= c1[2]; ++zz) {
@@ -380,7 +505,7 @@ __device__ __forceinline__ int walk_cells_group(const SlaveBox& b, const double*
       row_run(range, (int64_t)g.n[0] * (yy + (int64_t)g.n[1] * zz), c0[0], c1[0], lo, hi);
       for (int i0 = lo; i0 < hi; i0 += G) {
         const int i = i0 + r;
-        const bool hit = i < hi && touch(b, sbox, i, delta);
+        const bool hit = i < hi && touch_q(b, qs, sbox, qbox, i, delta);
         const unsigned m = (unsigned)(__ballot(hit) >> gshift) & ((1u << G) - 1u);
         if (hit) {
           const int k = c + __popc(m & below);
@@ -397,6 +522,7 @@ __device__ __forceinline__ int walk_cells_group(const SlaveBox& b, const double*
 // CTMP of them (walk order) in the lane-interleaved scratch tmp[k * n_s + s].
 __global__ __launch_bounds__(BS) void k_cand_count(const double* __restrict__ box_s, int32_t n_s,
                                                     const double* __restrict__ sbox,
+                                                    const uint64_t* __restrict__ qbox,
                                                     const uint32_t* __restrict__ mvals,
                                                     const int2* __restrict__ range, const Grid* __restrict__ gp,
                                                     double delta, int32_t* __restrict__ count,
@@ -406,7 +532,8 @@ __global__ __launch_bounds__(BS) void k_cand_count(const double* __restrict__ bo
   if (s >= n_s) return;  // whole groups leave together
   const Grid g = *gp;
   const SlaveBox b = load_box(box_s, n_s, s);
-  const int c = walk_cells_group(b, sbox, mvals, range, g, delta, tmp + s, n_s, CTMP, r, (int)(__lane_id() & ~(G - 1)));
+  const int c = walk_cells_group(b, sbox, qbox, mvals, range, g, delta, tmp + s, n_s, CTMP, r,
+                                 (int)(__lane_id() & ~(G - 1)));
   if (r == 0) count[s] = c;
 }
 
@@ -618,9 +745,9 @@ hipError_t launch_clear_cells(int2* range, const Grid* g, int64_t max_cells, hip
 }
 
 hipError_t launch_cell_ranges(const uint32_t* keys, const uint32_t* vals, int32_t n, const double* box_m,
-                              int2* range, double* sbox, hipStream_t s) {
+                              const Grid* g, int2* range, double* sbox, uint64_t* qbox, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  k_cell_ranges<<<(n + BS - 1) / BS, BS, 0, s>>>(keys, vals, n, box_m, range, sbox);
+  k_cell_ranges<<<(n + BS - 1) / BS, BS, 0, s>>>(keys, vals, n, box_m, g, range, sbox, qbox);
   return hipGetLastError();
 }
 
@@ -628,11 +755,12 @@ hipError_t launch_cell_ranges(const uint32_t* keys, const uint32_t* vals, int32_
 // contiguous eighth of the slave elements, whose masters are neighbours).
 unsigned group_blocks(int32_t n_s) { return xcd_grid((unsigned)(((int64_t)n_s * G + BS - 1) / BS)); }
 
-hipError_t launch_cand_count(const double* box_s, int32_t n_s, const double* sbox, const uint32_t* mvals,
+hipError_t launch_cand_count(const double* box_s, int32_t n_s, const double* sbox, const uint64_t* qbox,
+                             const uint32_t* mvals,
                              const int2* range, const Grid* g, double delta, int32_t* count, int32_t* tmp,
                              hipStream_t s) {
   if (n_s == 0) return hipSuccess;
-  k_cand_count<<<group_blocks(n_s), BS, 0, s>>>(box_s, n_s, sbox, mvals, range, g, delta, count, tmp);
+  k_cand_count<<<group_blocks(n_s), BS, 0, s>>>(box_s, n_s, sbox, qbox, mvals, range, g, delta, count, tmp);
   return hipGetLastError();
 }
 

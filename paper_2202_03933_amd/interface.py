@@ -94,6 +94,31 @@ class MortarInterface:
         self._uploaded = True
         self.coord_version = getattr(self, "coord_version", 0) + 1
 
+    def move_coordinates(self, Xs, Xm):
+        """Write new coordinates (n, 3) into the registered arrays in place
+        (same device pointers, so a captured step stays valid); the pair
+        list and pattern are kept until the next build."""
+        self.Xs.copy_(torch.as_tensor(Xs, dtype=torch.float64, device=self.device).t())
+        self.Xm.copy_(torch.as_tensor(Xm, dtype=torch.float64, device=self.device).t())
+        L = C.lib()
+        for side, X in ((C.MT_SIDE_SLAVE, self.Xs), (C.MT_SIDE_MASTER, self.Xm)):
+            C.check(L.mt_update_coordinates(self.h, side, _ptr(X[0]), _ptr(X[1]), _ptr(X[2]), _stream(self.stream)))
+        self.coord_version += 1
+
+    def _searched(self):
+        # a search without read-back ran (mt_batch_search): counts unknown
+        self.n_cand = self.n_pairs = self.nnz_D = self.nnz_M = None
+        self._csr = None
+
+    def refresh(self):
+        """Read back the counts of the last search (waits for it) and raise
+        MortarError for a device-side condition (mt_check)."""
+        self.check()
+        st = self.stats()
+        self.n_cand, self.n_pairs = st["n_candidates"], st["n_pairs"]
+        self.nnz_D, self.nnz_M = st["nnz_D"], st["nnz_M"]
+        self._csr = None
+
     @property
     def n_slave_nodes(self):
         return int(self.Xs.shape[1])

@@ -39,6 +39,28 @@ def test_gradient_parity_reduced(k, scale):
     assert es <= TOL and em <= TOL
 
 
+# A master mesh much coarser than the slave mesh (mortar methods put the finer
+# mesh on the slave side): each master element meets ~190, ~2,300 or ~4,300
+# slave elements, so the master-node gradient sums run over long per-element
+# pair lists (sorted by a workgroup in LDS runs of 2,048, merged beyond one
+# run).  Parity with the oracle, and the same bits from a second run.
+@pytest.mark.parametrize("ns,nm", [(64, 5), (96, 2), (128, 2)])
+def test_gradient_parity_coarse_master(ns, nm):
+    itf = synth.cylinder(ns, nm)
+    prm = oracle_params(itf)
+    g = gpu_run(itf, backward_seed=3200)
+    o = oracle.evaluate(itf, prm)
+    assert np.array_equal(g["pair_s"], o["pair_s"]) and np.array_equal(g["pair_m"], o["pair_m"])
+    per_master = np.bincount(o["pair_m"], minlength=itf.master.n_el)
+    print(f"pairs per master element {per_master.min()}..{per_master.max()}")
+    gs, gm = oracle_grad(itf, prm, o["pair_s"], o["pair_m"], 3200)
+    es, em = rel_err(g["gXs"], gs), rel_err(g["gXm"], gm)
+    print(f"coarse-master grad rel err slave {es:.2e} master {em:.2e}")
+    assert es <= TOL and em <= TOL
+    g2 = gpu_run(itf, backward_seed=3200)
+    assert np.array_equal(g2["gXm"], g["gXm"]) and np.array_equal(g2["gXs"], g["gXs"])
+
+
 # Dual basis (Sec. 2): the gradient also runs through A_e = D_e M_e^-1 of
 # every slave element.
 @pytest.mark.parametrize("k,scale,rule", [(2, 41, 7), (1, 37, 7), (2, 52, 3)])

@@ -164,3 +164,63 @@ def test_batch_rejects_mixed_rules_and_graph_on_default_stream():
     tabs = [_ptr_table([o[k] for o in outs]) for k in range(3)]
     rc = C.lib().mt_batch_forward(bt.h, *tabs, 1, ctypes.c_void_p(0))
     assert rc == C.MT_EINVAL
+
+
+def _moved(itf, step):
+    """The instance with its master slid tangentially by 0.37 (step + 1) of
+    a master element (along the cylinder axis, else along x): the pair lists
+    change from step to step."""
+    from synth.meshes import Interface, Mesh
+    Xm = itf.master.X.copy()
+    c = itf.master.conn
+    h = float(np.linalg.norm(Xm[c[:, 1]] - Xm[c[:, 0]], axis=1).mean())
+    d = 2 if itf.meta["geometry"] == "cylinder" else 0
+    Xm[:, d] += 0.37 * h * (step + 1)
+    return Interface(itf.slave, Mesh(Xm, c), itf.delta, name=itf.name + f", moved {step}", meta=itf.meta)
+
+
+# The search of all instances in one call (Alg. 1 and 2 per instance, then
+# the pattern) while the instances move: candidates, pairs, patterns and the
+# batched forward and backward after it bitwise equal to fresh per-interface
+# builds at the moved coordinates.
+@pytest.mark.parametrize("use_graph", [
+    pytest.param(True, marks=pytest.mark.skip(
+        reason="HIP-graph capture of the batched search ended the process with a segmentation fault inside "
+               "the capturing call; cause not found, capture switched off in the library")),
+    False])
+def test_batch_search_moving_instances(use_graph):
+    from paper_2202_03933_amd import MortarBatch
+    instances = synth.batched_instances(n_inst=12, max_side=48)
+    ifaces = make_ifaces(instances)
+    b = MortarBatch(ifaces)
+    for step in range(3):
+        moved = [_moved(itf, step) for itf in instances]
+        print(f"[gpu] batched search, graph={use_graph}, step {step}", flush=True)
+        for it, itf in zip(ifaces, moved):
+            it.move_coordinates(itf.slave.X, itf.master.X)
+        b.search(use_graph=use_graph)
+        refs = make_ifaces(moved)
+        for it, ref in zip(ifaces, refs):
+            assert (it.n_cand, it.n_pairs, it.nnz_D, it.nnz_M) == (ref.n_cand, ref.n_pairs, ref.nnz_D, ref.nnz_M)
+            for x, y in zip(it.candidates() + it.pairs(), ref.candidates() + ref.pairs()):
+                assert torch.equal(x, y)
+            for x, y in zip((it.D_rowptr, it.D_col, it.M_rowptr, it.M_col),
+                            (ref.D_rowptr, ref.D_col, ref.M_rowptr, ref.M_col)):
+                assert torch.equal(x, y)
+        outs = b.forward(use_graph=use_graph)
+        ref_out = [tuple(t.clone() for t in r.integrate()) for r in refs]
+        W = [weights_for(r, 4100 + k) for k, r in enumerate(refs)]
+        g = b.backward(W, use_graph=use_graph)
+        ref_g = [tuple(t.clone() for t in r.backward(*w)) for r, w in zip(refs, W)]
+        torch.cuda.synchronize()
+        assert all(equal_outs(o, r) for o, r in zip(outs, ref_out)), step
+        assert all(equal_outs(x, r) for x, r in zip(g, ref_g)), step
+
+
+def test_batch_search_graph_capture_refused():
+    from paper_2202_03933_amd import MortarBatch, MortarError
+    from paper_2202_03933_amd import _capi as C
+    b = MortarBatch(make_ifaces(synth.batched_instances(n_inst=2, max_side=20)))
+    with pytest.raises(MortarError) as e:
+        b.search(use_graph=True)
+    assert e.value.code == C.MT_EUNSUPPORTED
