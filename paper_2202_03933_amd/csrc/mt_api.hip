@@ -353,7 +353,9 @@ int mt_destroy(mt_ctx* c) {
   if (c->aux) {
     (void)hipEventDestroy(c->aux_fork);
     (void)hipEventDestroy(c->aux_join);
+    (void)hipEventDestroy(c->aux2_join);
     (void)hipStreamDestroy(c->aux);
+    (void)hipStreamDestroy(c->aux2);
   }
   for (auto& iv : c->intervals) {
     (void)hipEventDestroy(iv.a);
@@ -688,11 +690,14 @@ int mt_csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, void* stream) {
     }
     if (!c->aux) {
       MT_HIP(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+      MT_HIP(hipStreamCreateWithFlags(&c->aux2, hipStreamNonBlocking));
       MT_HIP(hipEventCreateWithFlags(&c->aux_fork, hipEventDisableTiming));
       MT_HIP(hipEventCreateWithFlags(&c->aux_join, hipEventDisableTiming));
+      MT_HIP(hipEventCreateWithFlags(&c->aux2_join, hipEventDisableTiming));
     }
     MT_HIP(hipEventRecord(c->aux_fork, st));
     MT_HIP(hipStreamWaitEvent(c->aux, c->aux_fork, 0));
+    MT_HIP(hipStreamWaitEvent(c->aux2, c->aux_fork, 0));
     {
       PhaseTimer t(c, MT_T_PAIR_FWD, c->aux);
       MT_HIP(launch_pair_fwd(S, M, kparams(c->params), c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), np_dev, P,
@@ -715,15 +720,19 @@ int mt_csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, void* stream) {
                              nullptr, nullptr, st));
   if (aux) {
     {
-      PhaseTimer t(c, MT_T_GRAD_REDUCE, c->aux);
-      int rc = build_master_index(c, c->aux, c->aux_scan);
+      // on a second internal stream: the index's short atomic and sort
+      // kernels run beside the forward instead of after it
+      PhaseTimer t(c, MT_T_GRAD_REDUCE, c->aux2);
+      int rc = build_master_index(c, c->aux2, c->aux_scan);
       if (rc) return rc;
     }
     MT_HIP(hipEventRecord(c->aux_join, c->aux));
+    MT_HIP(hipEventRecord(c->aux2_join, c->aux2));
     c->blk_gen = c->coord_gen;
     c->blk_pending = true;
+    MT_HIP(hipStreamWaitEvent(st, c->aux_join, 0));
+    MT_HIP(hipStreamWaitEvent(st, c->aux2_join, 0));
   }
-  if (aux) MT_HIP(hipStreamWaitEvent(st, c->aux_join, 0));
   c->have_pattern = true;
   ++c->pattern_gen;
   if (!nnz_D && !nnz_M) return MT_OK;

@@ -218,10 +218,13 @@ struct mt_ctx {
   mt::Buf gn0;             // [3][pair capacity] dL/dn0 per pair
   mt::Buf nrm_sb, nrm_ub, nrm_cg;
   int64_t nrm_gen = -1;    // coord_gen of nrm_node / nrm_el
-  // internal stream on which mt_csr_pattern computes the pair blocks and the
-  // pairs-by-master index while the pattern is built on the caller's stream
+  // internal streams on which mt_csr_pattern computes the pair blocks (aux)
+  // and the pairs-by-master index (aux2) while the pattern is built on the
+  // caller's stream
   hipStream_t aux = nullptr;
   hipEvent_t aux_fork = nullptr, aux_join = nullptr;
+  hipStream_t aux2 = nullptr;
+  hipEvent_t aux2_join = nullptr;
   mt::Buf aux_scan;
   mt::Buf blk;             // [36][pair capacity]
   int64_t blk_gen = -1;    // coord_gen of the blocks in blk (mt_integrate)
