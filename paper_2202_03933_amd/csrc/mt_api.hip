@@ -688,13 +688,7 @@ int mt_csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, void* stream) {
       if (rc) return rc;
       c->have_inc[1] = true;
     }
-    if (!c->aux) {
-      MT_HIP(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
-      MT_HIP(hipStreamCreateWithFlags(&c->aux2, hipStreamNonBlocking));
-      MT_HIP(hipEventCreateWithFlags(&c->aux_fork, hipEventDisableTiming));
-      MT_HIP(hipEventCreateWithFlags(&c->aux_join, hipEventDisableTiming));
-      MT_HIP(hipEventCreateWithFlags(&c->aux2_join, hipEventDisableTiming));
-    }
+    if (int rc = ensure_aux(c)) return rc;
     MT_HIP(hipEventRecord(c->aux_fork, st));
     MT_HIP(hipStreamWaitEvent(c->aux, c->aux_fork, 0));
     MT_HIP(hipStreamWaitEvent(c->aux2, c->aux_fork, 0));
@@ -1000,6 +994,16 @@ int mt_get_stats(mt_ctx* c, mt_stats* out) {
 }  // extern "C"
 
 int mt::ensure_normals(mt_ctx* c, hipStream_t st) { return normals_for_coords(c, st); }
+
+int mt::ensure_aux(mt_ctx* c) {
+  if (c->aux) return MT_OK;
+  MT_HIP(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+  MT_HIP(hipStreamCreateWithFlags(&c->aux2, hipStreamNonBlocking));
+  MT_HIP(hipEventCreateWithFlags(&c->aux_fork, hipEventDisableTiming));
+  MT_HIP(hipEventCreateWithFlags(&c->aux_join, hipEventDisableTiming));
+  MT_HIP(hipEventCreateWithFlags(&c->aux2_join, hipEventDisableTiming));
+  return MT_OK;
+}
 
 // ---- search of many interfaces ------------------------------------------------
 int mt::search_no_wait(mt_ctx* c, hipStream_t st) {

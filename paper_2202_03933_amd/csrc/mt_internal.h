@@ -414,6 +414,8 @@ int ws_live(mt_ctx* c);
 // mt_build_pairs into the bound workspace and capacities, then mt_csr_pattern,
 // without read-back (and without phase timers) on stream st.
 int search_no_wait(mt_ctx* c, hipStream_t st);
+// The context's internal streams and their events, created on first use.
+int ensure_aux(mt_ctx* c);
 
 void set_error(const std::string& msg);
 

@@ -214,6 +214,36 @@ def test_autograd_function_matches_backward():
     assert torch.equal(Xs.grad, gs.t()) and torch.equal(Xm.grad, gm.t())
 
 
+def test_autograd_two_forwards_before_backward():
+    # a second forward at other coordinates (a line-search trial point) runs
+    # before the first loss's backward: that gradient is still the one at the
+    # first forward's coordinates, bitwise equal to a fresh interface there
+    from paper_2202_03933_amd import MortarFunction, MortarInterface
+    from tests.gpu_util import gpu_params
+    itf = synth.interface_config(2, scale=48)
+    dev = torch.device("cuda", 0)
+    cs, cm = torch.from_numpy(itf.slave.conn), torch.from_numpy(itf.master.conn)
+    X1s = torch.from_numpy(itf.slave.X).to(dev).requires_grad_(True)
+    X1m = torch.from_numpy(itf.master.X).to(dev).requires_grad_(True)
+    iface = MortarInterface(X1s.detach(), cs, X1m.detach(), cm, params=gpu_params(itf), device=dev).setup()
+    D1, M1, g1 = MortarFunction.apply(X1s, X1m, iface)
+    shift = torch.tensor([2e-4, -1e-4, 0.0], dtype=torch.float64, device=dev)
+    X2s = X1s.detach().clone().requires_grad_(True)
+    X2m = (X1m.detach() + shift).requires_grad_(True)
+    D2, M2, g2 = MortarFunction.apply(X2s, X2m, iface)
+    assert not torch.equal(M1, M2)
+    gen = torch.Generator(device="cpu").manual_seed(11)
+    wD = torch.randn(D1.shape, generator=gen, dtype=torch.float64).to(dev)
+    wM = torch.randn(M1.shape, generator=gen, dtype=torch.float64).to(dev)
+    wg = torch.randn(g1.shape, generator=gen, dtype=torch.float64).to(dev)
+    ((wD * D1).sum() + (wM * M1).sum() + (wg * g1).sum()).backward()
+    ref = MortarInterface(X1s.detach(), cs, X1m.detach(), cm, params=gpu_params(itf), device=dev).setup()
+    assert ref.n_pairs == iface.n_pairs and ref.nnz_M == iface.nnz_M
+    gs, gm = ref.backward(wD, wM, wg)
+    torch.cuda.synchronize()
+    assert torch.equal(X1s.grad, gs.t()) and torch.equal(X1m.grad, gm.t())
+
+
 def test_backward_bitwise_deterministic():
     itf = synth.interface_config(1, scale=80)
     a = gpu_run(itf, backward_seed=7)
