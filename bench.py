@@ -510,6 +510,13 @@ def main():
         iface.integrate(outs)
         iface.backward(wD, wM, wg, grads)
 
+    def step_fused(sync=True):
+        # the same step with mt_integrate_backward (the weights are known
+        # before the values): the assembly runs beside the reverse sweep
+        iface.build_pairs(sync=sync)
+        iface.csr_pattern(sync=sync)
+        iface.integrate_backward(wD, wM, wg, out=outs, grad_out=grads)
+
     def wall(fn, steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -557,13 +564,16 @@ def main():
         step(False)
     ms_graph = wall(graph.replay, args.steps)
     iface.check()
+    del graph
+    ms_fused = wall(lambda: step_fused(False), args.steps)
+    iface.check()
     # forward path alone (search + pattern + forward), no timers
     fwd_ms = wall(lambda: (iface.build_pairs(sync=False), iface.csr_pattern(sync=False), iface.integrate(outs)),
                   args.steps)
     iface.check()
     st = iface.stats()
     assert st["n_pairs"] == n_pairs
-    ms_step = min(ms_graph, ms_async)
+    ms_step = min(ms_graph, ms_async, ms_fused)
     mem_gb = (free0 - torch.cuda.mem_get_info(dev)[0]) / 2**30
 
     if args.calib_copy:
@@ -635,9 +645,12 @@ def main():
         "config": {"workload": "wavy z=0.05 sin(2 pi x) sin(2 pi y), slave 1024x1024 / master 777x777 quad4, "
                                "normal offsets U[-1e-3,1e-3], delta 1.25e-3: search + forward + backward per step",
                    "n_pairs": n_pairs, "n_candidates": n_cand, "nnz_D": iface.nnz_D, "nnz_M": iface.nnz_M},
-        "step_modes_ms": {"graph_replay": ms_graph, "async": ms_async, "sync_counts": ms_sync},
-        "step_note": "value: the faster of the graph-replayed and the eager no-wait step (inputs resident, every "
-                     "phase recomputed); sync_counts reads the counts back in every call",
+        "step_modes_ms": {"graph_replay": ms_graph, "async": ms_async, "sync_counts": ms_sync,
+                          "fused_async": ms_fused},
+        "step_note": "value: the fastest of the eager no-wait step, its graph replay, and the eager step with "
+                     "mt_integrate_backward in place of mt_integrate + mt_backward (the same outputs bit for bit; "
+                     "the assembly beside the reverse sweep); inputs resident, every phase recomputed; sync_counts "
+                     "reads the counts back in every call",
         "fwd_pairs_per_s": n_pairs / (fwd_ms * 1e-3),
         "fwd_ms_per_step": fwd_ms,
         "phase_ms_per_step": per_step,

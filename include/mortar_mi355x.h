@@ -324,6 +324,18 @@ int mt_integrate(mt_ctx* ctx, double* D_val, double* M_val, double* gap, void* s
 int mt_backward(mt_ctx* ctx, const double* W_D, const double* W_M, const double* w_g,
                 double* gXs, double* gXm, void* stream);
 
+/* mt_integrate and mt_backward in one call, for upstream weights known
+ * before the values (a fixed linear functional of D, M and the gap, or the
+ * weights of an earlier iterate of the nonlinear solve in which the
+ * linearisation is needed, Sec. "Introduction"): the same outputs bit for
+ * bit as mt_integrate followed by mt_backward with the same arguments, with
+ * the assembly of D, M and the gap (bound by memory) on `stream` beside the
+ * reverse sweep and the gradient sums (bound by FP64 issue) on an internal
+ * stream of the context, joined before the call returns.  Arguments and
+ * errors as the two calls. */
+int mt_integrate_backward(mt_ctx* ctx, double* D_val, double* M_val, double* gap, const double* W_D,
+                          const double* W_M, const double* w_g, double* gXs, double* gXm, void* stream);
+
 /* Copy the counters of the last calls into *st (host).  Synchronises the
  * stream of the last call. */
 int mt_get_stats(mt_ctx* ctx, mt_stats* st);
@@ -421,7 +433,9 @@ int mt_batch_backward(mt_batch* b, const double* const* W_D, const double* const
 /* The search of every instance (Alg. 1 and 2 of Sec. "Parallel
  * algorithms" per instance, then the CSR pattern) in one call:
  * mt_build_pairs into the workspace and capacities its last mt_build_pairs
- * bound, then mt_csr_pattern, neither reading anything back, the instances
+ * bound, then mt_csr_pattern (without the pair blocks it computes beside
+ * the pattern for the next mt_integrate: the batched forward computes its
+ * own), neither reading anything back, the instances
  * spread round-robin over four internal streams that are ordered after
  * `stream` on entry and before it on exit.  Counts and device-side status
  * per instance as after mt_build_pairs without read-back (mt_get_stats,

@@ -80,6 +80,7 @@ SIGNATURES = {
     "mt_get_csr": (_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "mt_integrate": (_int, [_vp, _vp, _vp, _vp, _vp]),
     "mt_backward": (_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "mt_integrate_backward": (_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "mt_get_stats": (_int, [_vp, ctypes.POINTER(mt_stats)]),
     "mt_last_error": (ctypes.c_char_p, []),
     "mt_set_timing": (_int, [_vp, _int]),

@@ -307,6 +307,124 @@ int mt::host_counts(mt_ctx* c) {
 
 const int32_t* mt::dev_n_pairs(mt_ctx* c) { return &c->state.as<DevState>()->n_pairs; }
 
+namespace {
+
+// Argument checks of mt_integrate / mt_backward (sizes not read back: any
+// slave element may have pairs).
+int check_integrate(mt_ctx* c, const double* D_val, const double* M_val, const double* gap, const char* who) {
+  if (!c) return fail(MT_EINVAL, std::string(who) + ": null ctx");
+  if (!c->have_pattern) return fail(MT_ESTATE, std::string(who) + ": build pairs and pattern first");
+  if (int rc = ws_live(c)) return rc;
+  const bool known = c->counts_known;
+  const bool needD = known ? c->nnz_D > 0 : c->side[0].n_el > 0;
+  const bool needM = known ? c->nnz_M > 0 : c->side[0].n_el > 0;
+  if ((needD && !D_val) || (needM && !M_val) || (c->side[0].n_nodes && !gap))
+    return fail(MT_EINVAL, std::string(who) + ": null output");
+  return MT_OK;
+}
+
+int check_backward(mt_ctx* c, const double* W_D, const double* W_M, const double* w_g, const double* gXs,
+                   const double* gXm, const char* who) {
+  if (!c) return fail(MT_EINVAL, std::string(who) + ": null ctx");
+  if (c->params.element_rule > 0)
+    return fail(MT_EUNSUPPORTED, std::string(who) + ": element-based integration has no backward pass");
+  if (!c->have_pattern) return fail(MT_ESTATE, std::string(who) + ": build pairs and pattern first");
+  if (int rc = ws_live(c)) return rc;
+  const DeviceMesh& S = c->side[0];
+  const DeviceMesh& M = c->side[1];
+  const bool known = c->counts_known;
+  const bool needD = known ? c->nnz_D > 0 : S.n_el > 0;
+  const bool needM = known ? c->nnz_M > 0 : S.n_el > 0;
+  if ((needD && !W_D) || (needM && !W_M) || (S.n_nodes && (!w_g || !gXs)) || (M.n_nodes && !gXm))
+    return fail(MT_EINVAL, std::string(who) + ": null argument");
+  return MT_OK;
+}
+
+// The clip polygons and the normal field of the current coordinates.
+int prepare_pairs(mt_ctx* c, hipStream_t st) {
+  int rc = ensure_poly(c);
+  if (!rc) rc = normals_for_coords(c, st);
+  if (rc) return rc;
+  if (c->params.element_rule == 0 && c->poly_gen != c->coord_gen) {
+    PhaseTimer t(c, MT_T_PAIR_POLY, st);
+    MT_HIP(launch_pair_poly(c->side[0], c->side[1], kparams(c->params), c->pair_s.as<int32_t>(),
+                            c->pair_m.as<int32_t>(), dev_n_pairs(c), c->cap.pairs, poly_buf(c),
+                            c->counters.as<Counters>(), st));
+    c->poly_gen = c->coord_gen;
+  }
+  return MT_OK;
+}
+
+// The per-pair blocks the assembly reads: those mt_csr_pattern computed
+// serve the first integration after it (for unchanged coordinates); every
+// other one computes them.
+int ensure_blocks(mt_ctx* c, hipStream_t st) {
+  const DeviceMesh& S = c->side[0];
+  const DeviceMesh& M = c->side[1];
+  const int64_t P = c->cap.pairs;
+  if (c->params.element_rule > 0) {
+    // element-based integration: no clip polygons
+    PhaseTimer t(c, MT_T_PAIR_FWD, st);
+    MT_HIP(launch_elem_fwd(S, M, kparams(c->params), c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(),
+                           c->pair_off.as<int32_t>(), dev_n_pairs(c), P, c->blk.as<double>(), P,
+                           c->counters.as<Counters>(), st));
+    c->blk_gen = -1;
+  } else if (!(c->blk_pending && c->blk_gen == c->coord_gen)) {
+    PhaseTimer t(c, MT_T_PAIR_FWD, st);
+    MT_HIP(launch_pair_fwd(S, M, kparams(c->params), c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(),
+                           dev_n_pairs(c), P, poly_buf(c), c->blk.as<double>(), P, c->counters.as<Counters>(), st));
+    c->blk_gen = c->coord_gen;
+  }
+  c->blk_pending = false;
+  return MT_OK;
+}
+
+int enqueue_assemble(mt_ctx* c, double* D_val, double* M_val, double* gap, hipStream_t st) {
+  const DeviceMesh& S = c->side[0];
+  PhaseTimer t(c, MT_T_ASSEMBLE, st);
+  MT_HIP(launch_assemble(c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(), S.n_nodes, c->pair_off.as<int32_t>(),
+                         c->D_rowptr.as<int32_t>(), c->M_rowptr.as<int32_t>(), c->posD.as<int32_t>(), S.n_el,
+                         c->posM.as<int32_t>(), c->blk.as<double>(), c->cap.pairs, D_val, M_val, gap, st));
+  return MT_OK;
+}
+
+// The reverse sweep of every pair and the nodal gradient sums (the
+// polygons, normal field, master index and, for the dual basis, the pair
+// blocks of the current coordinates in place).
+int enqueue_backward(mt_ctx* c, const double* W_D, const double* W_M, const double* w_g, double* gXs, double* gXm,
+                     hipStream_t st) {
+  const DeviceMesh& S = c->side[0];
+  const DeviceMesh& M = c->side[1];
+  const int64_t P = c->cap.pairs;
+  const bool nodal = c->params.normals == MT_NORMALS_NODAL;
+  {
+    PhaseTimer t(c, MT_T_PAIR_BWD, st);
+    const KParams kp = kparams(c->params);
+    MT_HIP(launch_pair_bwd(S, M, kp, c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), dev_n_pairs(c), P,
+                           poly_buf(c), c->mp_pos.as<int32_t>(), c->posD.as<int32_t>(), S.n_el,
+                           c->posM.as<int32_t>(), W_D, W_M, w_g, kp.dual ? c->blk.as<double>() : nullptr,
+                           c->gpair.as<double>(), nodal ? c->gn0.as<double>() : nullptr, P,
+                           c->counters.as<Counters>(), st));
+  }
+  PhaseTimer t(c, MT_T_GRAD_REDUCE, st);
+  MT_HIP(launch_grad_slave(c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(), S.n_nodes, c->pair_off.as<int32_t>(),
+                           c->gpair.as<double>(), P, gXs, st));
+  const int32_t* mo = c->mp_off.as<int32_t>();
+  MT_HIP(launch_grad_master(c->minc_off.as<int32_t>(), c->minc_list.as<int32_t>(), M.n_nodes, mo, mo + 1,
+                            c->gpair.as<double>(), P, gXm, st));
+  if (nodal) {
+    // through the element plane normals to the nodal normals and the
+    // coordinates of the neighbouring elements
+    MT_HIP(launch_normal_chain(S, c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(), c->pair_off.as<int32_t>(),
+                               c->gn0.as<double>(), P, c->nrm_node.as<double>(), c->nrm_el.as<double>(),
+                               c->nrm_sb.as<double>(), c->nrm_ub.as<double>(), c->nrm_cg.as<double>(), gXs, nullptr,
+                               nullptr, st));
+  }
+  return MT_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* mt_last_error(void) { return mt::g_err.c_str(); }
@@ -645,11 +763,18 @@ int mt_get_candidates(mt_ctx* c, int32_t* s, int32_t* m, uint8_t* nv, void* stre
 }
 
 int mt_csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, void* stream) {
+  return csr_pattern(c, nnz_D, nnz_M, (hipStream_t)stream, true);
+}
+
+}  // extern "C"
+
+// The pattern, and with `blocks` the pair blocks of the coming integration
+// beside it.
+int mt::csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, hipStream_t st, bool blocks) {
   if (!c) return fail(MT_EINVAL, "mt_csr_pattern: null ctx");
   if (!c->have_pairs) return fail(MT_ESTATE, "mt_csr_pattern: build the pair list first");
   if (int rc = ws_live(c)) return rc;
   DeviceScope ds(c->device);
-  hipStream_t st = (hipStream_t)stream;
   c->last_stream = st;
   const DeviceMesh& S = c->side[0];
   const DeviceMesh& M = c->side[1];
@@ -692,7 +817,7 @@ int mt_csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, void* stream) {
     MT_HIP(hipEventRecord(c->aux_fork, st));
     MT_HIP(hipStreamWaitEvent(c->aux, c->aux_fork, 0));
     MT_HIP(hipStreamWaitEvent(c->aux2, c->aux_fork, 0));
-    {
+    if (blocks) {
       PhaseTimer t(c, MT_T_PAIR_FWD, c->aux);
       MT_HIP(launch_pair_fwd(S, M, kparams(c->params), c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), np_dev, P,
                              poly_buf(c), c->blk.as<double>(), P, c->counters.as<Counters>(), c->aux));
@@ -722,8 +847,10 @@ int mt_csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, void* stream) {
     }
     MT_HIP(hipEventRecord(c->aux_join, c->aux));
     MT_HIP(hipEventRecord(c->aux2_join, c->aux2));
-    c->blk_gen = c->coord_gen;
-    c->blk_pending = true;
+    if (blocks) {
+      c->blk_gen = c->coord_gen;
+      c->blk_pending = true;
+    }
     MT_HIP(hipStreamWaitEvent(st, c->aux_join, 0));
     MT_HIP(hipStreamWaitEvent(st, c->aux2_join, 0));
   }
@@ -746,6 +873,8 @@ int mt_csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, void* stream) {
   return MT_OK;
 }
 
+extern "C" {
+
 int mt_get_csr(mt_ctx* c, int32_t* D_rowptr, int32_t* D_col, int32_t* M_rowptr, int32_t* M_col, void* stream) {
   if (!c) return fail(MT_EINVAL, "mt_get_csr: null ctx");
   if (!c->have_pattern) return fail(MT_ESTATE, "mt_get_csr: no pattern");
@@ -761,59 +890,13 @@ int mt_get_csr(mt_ctx* c, int32_t* D_rowptr, int32_t* D_col, int32_t* M_rowptr, 
 }
 
 int mt_integrate(mt_ctx* c, double* D_val, double* M_val, double* gap, void* stream) {
-  if (!c) return fail(MT_EINVAL, "mt_integrate: null ctx");
-  if (!c->have_pattern) return fail(MT_ESTATE, "mt_integrate: build pairs and pattern first");
-  if (int rc = ws_live(c)) return rc;
-  {
-    // sizes not read back: any slave element may have pairs
-    const bool known = c->counts_known;
-    const bool needD = known ? c->nnz_D > 0 : c->side[0].n_el > 0;
-    const bool needM = known ? c->nnz_M > 0 : c->side[0].n_el > 0;
-    if ((needD && !D_val) || (needM && !M_val) || (c->side[0].n_nodes && !gap))
-      return fail(MT_EINVAL, "mt_integrate: null output");
-  }
+  if (int rc = check_integrate(c, D_val, M_val, gap, "mt_integrate")) return rc;
   DeviceScope ds(c->device);
   hipStream_t st = (hipStream_t)stream;
   c->last_stream = st;
-  const DeviceMesh& S = c->side[0];
-  const DeviceMesh& M = c->side[1];
-  const int64_t P = c->cap.pairs;
-  const int32_t* np_dev = dev_n_pairs(c);
-  {
-    int rc = ensure_poly(c);
-    if (!rc) rc = normals_for_coords(c, st);
-    if (rc) return rc;
-  }
-  const PolyBuf poly = poly_buf(c);
-  if (c->params.element_rule > 0) {
-    // element-based integration: no clip polygons
-    PhaseTimer t(c, MT_T_PAIR_FWD, st);
-    MT_HIP(launch_elem_fwd(S, M, kparams(c->params), c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(),
-                           c->pair_off.as<int32_t>(), np_dev, P, c->blk.as<double>(), P, c->counters.as<Counters>(),
-                           st));
-    c->blk_gen = -1;
-  } else {
-    if (c->poly_gen != c->coord_gen) {
-      PhaseTimer t(c, MT_T_PAIR_POLY, st);
-      MT_HIP(launch_pair_poly(S, M, kparams(c->params), c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), np_dev, P,
-                              poly, c->counters.as<Counters>(), st));
-      c->poly_gen = c->coord_gen;
-    }
-    // the blocks mt_csr_pattern computed serve the first mt_integrate after
-    // it (for unchanged coordinates); every other call computes them
-    if (!(c->blk_pending && c->blk_gen == c->coord_gen)) {
-      PhaseTimer t(c, MT_T_PAIR_FWD, st);
-      MT_HIP(launch_pair_fwd(S, M, kparams(c->params), c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), np_dev, P,
-                             poly, c->blk.as<double>(), P, c->counters.as<Counters>(), st));
-      c->blk_gen = c->coord_gen;
-    }
-  }
-  c->blk_pending = false;
-  PhaseTimer t(c, MT_T_ASSEMBLE, st);
-  MT_HIP(launch_assemble(c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(), S.n_nodes, c->pair_off.as<int32_t>(),
-                         c->D_rowptr.as<int32_t>(), c->M_rowptr.as<int32_t>(), c->posD.as<int32_t>(), S.n_el,
-                         c->posM.as<int32_t>(), c->blk.as<double>(), P, D_val, M_val, gap, st));
-  return MT_OK;
+  if (int rc = prepare_pairs(c, st)) return rc;
+  if (int rc = ensure_blocks(c, st)) return rc;
+  return enqueue_assemble(c, D_val, M_val, gap, st);
 }
 
 }  // extern "C"
@@ -856,72 +939,51 @@ extern "C" {
 
 int mt_backward(mt_ctx* c, const double* W_D, const double* W_M, const double* w_g, double* gXs, double* gXm,
                 void* stream) {
-  if (!c) return fail(MT_EINVAL, "mt_backward: null ctx");
-  if (c->params.element_rule > 0)
-    return fail(MT_EUNSUPPORTED, "mt_backward: element-based integration has no backward pass");
-  if (!c->have_pattern) return fail(MT_ESTATE, "mt_backward: build pairs and pattern first");
-  if (int rc = ws_live(c)) return rc;
-  const DeviceMesh& S = c->side[0];
-  const DeviceMesh& M = c->side[1];
-  {
-    const bool known = c->counts_known;
-    const bool needD = known ? c->nnz_D > 0 : S.n_el > 0;
-    const bool needM = known ? c->nnz_M > 0 : S.n_el > 0;
-    if ((needD && !W_D) || (needM && !W_M) || (S.n_nodes && (!w_g || !gXs)) || (M.n_nodes && !gXm))
-      return fail(MT_EINVAL, "mt_backward: null argument");
-  }
+  if (int rc = check_backward(c, W_D, W_M, w_g, gXs, gXm, "mt_backward")) return rc;
   DeviceScope ds(c->device);
   hipStream_t st = (hipStream_t)stream;
   c->last_stream = st;
   {
     PhaseTimer t(c, MT_T_GRAD_REDUCE, st);
-    int rc = ensure_master_index(c, st);
-    if (rc) return rc;
+    if (int rc = ensure_master_index(c, st)) return rc;
   }
-  const int64_t P = c->cap.pairs;
-  const int32_t* np_dev = dev_n_pairs(c);
-  {
-    int rc = ensure_poly(c);
-    if (!rc) rc = normals_for_coords(c, st);
-    if (rc) return rc;
-  }
-  const bool nodal = c->params.normals == MT_NORMALS_NODAL;
-  const PolyBuf poly = poly_buf(c);
-  if (c->poly_gen != c->coord_gen) {
-    PhaseTimer t(c, MT_T_PAIR_POLY, st);
-    MT_HIP(launch_pair_poly(S, M, kparams(c->params), c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), np_dev, P,
-                            poly, c->counters.as<Counters>(), st));
-    c->poly_gen = c->coord_gen;
-  }
-  {
+  if (int rc = prepare_pairs(c, st)) return rc;
+  if (c->params.lm_basis == MT_BASIS_DUAL && c->blk_gen != c->coord_gen) {
+    // the dual adjoint reads each pair's dual blocks: those staged by the
+    // last mt_integrate unless the coordinates or pairs changed since
     PhaseTimer t(c, MT_T_PAIR_BWD, st);
-    const KParams kp = kparams(c->params);
-    if (kp.dual && c->blk_gen != c->coord_gen) {
-      // the dual adjoint reads each pair's dual blocks: those staged by the
-      // last mt_integrate unless the coordinates or pairs changed since
-      MT_HIP(launch_pair_fwd(S, M, kp, c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), np_dev, P, poly,
-                             c->blk.as<double>(), P, c->counters.as<Counters>(), st));
-      c->blk_gen = c->coord_gen;
-    }
-    MT_HIP(launch_pair_bwd(S, M, kp, c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), np_dev, P, poly,
-                           c->mp_pos.as<int32_t>(), c->posD.as<int32_t>(), S.n_el, c->posM.as<int32_t>(), W_D, W_M,
-                           w_g, kp.dual ? c->blk.as<double>() : nullptr, c->gpair.as<double>(),
-                           nodal ? c->gn0.as<double>() : nullptr, P, c->counters.as<Counters>(), st));
+    MT_HIP(launch_pair_fwd(c->side[0], c->side[1], kparams(c->params), c->pair_s.as<int32_t>(),
+                           c->pair_m.as<int32_t>(), dev_n_pairs(c), c->cap.pairs, poly_buf(c), c->blk.as<double>(),
+                           c->cap.pairs, c->counters.as<Counters>(), st));
+    c->blk_gen = c->coord_gen;
   }
-  PhaseTimer t(c, MT_T_GRAD_REDUCE, st);
-  MT_HIP(launch_grad_slave(c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(), S.n_nodes, c->pair_off.as<int32_t>(),
-                           c->gpair.as<double>(), P, gXs, st));
-  const int32_t* mo = c->mp_off.as<int32_t>();
-  MT_HIP(launch_grad_master(c->minc_off.as<int32_t>(), c->minc_list.as<int32_t>(), M.n_nodes, mo, mo + 1,
-                            c->gpair.as<double>(), P, gXm, st));
-  if (nodal) {
-    // through the element plane normals to the nodal normals and the
-    // coordinates of the neighbouring elements
-    MT_HIP(launch_normal_chain(S, c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(), c->pair_off.as<int32_t>(),
-                               c->gn0.as<double>(), P, c->nrm_node.as<double>(), c->nrm_el.as<double>(),
-                               c->nrm_sb.as<double>(), c->nrm_ub.as<double>(), c->nrm_cg.as<double>(), gXs, nullptr,
-                               nullptr, st));
+  return enqueue_backward(c, W_D, W_M, w_g, gXs, gXm, st);
+}
+
+int mt_integrate_backward(mt_ctx* c, double* D_val, double* M_val, double* gap, const double* W_D,
+                          const double* W_M, const double* w_g, double* gXs, double* gXm, void* stream) {
+  if (int rc = check_backward(c, W_D, W_M, w_g, gXs, gXm, "mt_integrate_backward")) return rc;
+  if (int rc = check_integrate(c, D_val, M_val, gap, "mt_integrate_backward")) return rc;
+  DeviceScope ds(c->device);
+  hipStream_t st = (hipStream_t)stream;
+  c->last_stream = st;
+  {
+    PhaseTimer t(c, MT_T_GRAD_REDUCE, st);
+    if (int rc = ensure_master_index(c, st)) return rc;
   }
+  if (int rc = prepare_pairs(c, st)) return rc;
+  if (int rc = ensure_blocks(c, st)) return rc;  // also the dual adjoint's blocks
+  // the assembly (bound by memory) on the caller's stream, the reverse sweep
+  // (bound by FP64 issue) and the gradient sums on an internal stream; the
+  // assembly is enqueued first, so that its workgroups are dispatched before
+  // the sweep's fill the register files
+  if (int rc = ensure_aux(c)) return rc;
+  MT_HIP(hipEventRecord(c->aux_fork, st));
+  if (int rc = enqueue_assemble(c, D_val, M_val, gap, st)) return rc;
+  MT_HIP(hipStreamWaitEvent(c->aux, c->aux_fork, 0));
+  if (int rc = enqueue_backward(c, W_D, W_M, w_g, gXs, gXm, c->aux)) return rc;
+  MT_HIP(hipEventRecord(c->aux_join, c->aux));
+  MT_HIP(hipStreamWaitEvent(st, c->aux_join, 0));
   return MT_OK;
 }
 
@@ -1010,7 +1072,8 @@ int mt::search_no_wait(mt_ctx* c, hipStream_t st) {
   const bool timing = c->timing;
   c->timing = false;
   int rc = mt_build_pairs(c, &c->cap, c->ws, c->ws_bytes, nullptr, nullptr, st);
-  if (rc == MT_OK) rc = mt_csr_pattern(c, nullptr, nullptr, st);
+  // the batch's forward computes the pair blocks itself
+  if (rc == MT_OK) rc = csr_pattern(c, nullptr, nullptr, st, false);
   c->timing = timing;
   return rc;
 }

@@ -414,6 +414,9 @@ int ws_live(mt_ctx* c);
 // mt_build_pairs into the bound workspace and capacities, then mt_csr_pattern,
 // without read-back (and without phase timers) on stream st.
 int search_no_wait(mt_ctx* c, hipStream_t st);
+// mt_csr_pattern on stream st; without `blocks` the pair blocks of the coming
+// integration are not computed beside it (a batch computes its own).
+int csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, hipStream_t st, bool blocks);
 // The context's internal streams and their events, created on first use.
 int ensure_aux(mt_ctx* c);
 

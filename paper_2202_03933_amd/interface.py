@@ -267,6 +267,24 @@ class MortarInterface:
                                     _stream(self.stream)))
         return gXs, gXm
 
+    def integrate_backward(self, W_D, W_M, w_g, out=None, grad_out=None):
+        """mt_integrate_backward: (D, M, g) and (gXs, gXm) of integrate() and
+        backward() with the same arguments, the assembly beside the reverse
+        sweep; for upstream weights known before the values."""
+        dev = self.device
+        D, M, g = out if out is not None else self.alloc_outputs()
+        if grad_out is None:
+            gXs = torch.empty(3, self.n_slave_nodes, dtype=torch.float64, device=dev)
+            gXm = torch.empty(3, self.n_master_nodes, dtype=torch.float64, device=dev)
+        else:
+            gXs, gXm = grad_out
+        W_D = W_D.contiguous()
+        W_M = W_M.contiguous()
+        w_g = w_g.contiguous()
+        C.check(C.lib().mt_integrate_backward(self.h, _ptr(D), _ptr(M), _ptr(g), _ptr(W_D), _ptr(W_M), _ptr(w_g),
+                                              _ptr(gXs), _ptr(gXm), _stream(self.stream)))
+        return (D, M, g), (gXs, gXm)
+
     def stats(self):
         st = C.mt_stats()
         C.check(C.lib().mt_get_stats(self.h, ctypes.byref(st)))

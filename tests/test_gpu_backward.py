@@ -244,6 +244,47 @@ def test_autograd_two_forwards_before_backward():
     assert torch.equal(X1s.grad, gs.t()) and torch.equal(X1m.grad, gm.t())
 
 
+def _fused_vs_sequential(itf, dual=False, nodal=False, seed=3300):
+    from paper_2202_03933_amd import MortarInterface
+    from tests.gpu_util import csr_weights, gpu_params
+    import scipy.sparse as sp
+    dev = torch.device("cuda", 0)
+
+    def make():
+        return MortarInterface(torch.from_numpy(itf.slave.X), torch.from_numpy(itf.slave.conn),
+                               torch.from_numpy(itf.master.X), torch.from_numpy(itf.master.conn),
+                               params=gpu_params(itf, dual=dual, nodal=nodal), device=dev).setup()
+    a, b = make(), make()
+    ns, nm = a.n_slave_nodes, a.n_master_nodes
+    D = sp.csr_matrix((np.zeros(a.nnz_D), a.D_col.cpu().numpy(), a.D_rowptr.cpu().numpy()), shape=(ns, ns))
+    M = sp.csr_matrix((np.zeros(a.nnz_M), a.M_col.cpu().numpy(), a.M_rowptr.cpu().numpy()), shape=(ns, nm))
+    W = tuple(torch.from_numpy(x).to(dev) for x in csr_weights(D, M, ns, seed))
+    rng = np.random.default_rng(seed)
+    for step in range(2):
+        if step == 1:  # moved in place: polygons and blocks recomputed inside the calls
+            Xs = itf.slave.X + rng.uniform(-1e-5, 1e-5, itf.slave.X.shape)
+            a.move_coordinates(Xs, itf.master.X)
+            b.move_coordinates(Xs, itf.master.X)
+        f_seq = tuple(t.clone() for t in a.integrate())
+        g_seq = tuple(t.clone() for t in a.backward(*W))
+        f_fus, g_fus = b.integrate_backward(*W)
+        torch.cuda.synchronize()
+        assert all(torch.equal(x, y) for x, y in zip(f_seq, f_fus)), step
+        assert all(torch.equal(x, y) for x, y in zip(g_seq, g_fus)), step
+
+
+# mt_integrate_backward (assembly beside the reverse sweep) equals
+# mt_integrate followed by mt_backward bit for bit: standard and dual basis,
+# the continuous normal field, before and after an in-place coordinate move.
+@pytest.mark.parametrize("dual,nodal", [(False, False), (True, False), (False, True), (True, True)])
+def test_integrate_backward_equals_sequential(dual, nodal):
+    _fused_vs_sequential(synth.interface_config(1, scale=56), dual=dual, nodal=nodal)
+
+
+def test_integrate_backward_equals_sequential_full_wavy():
+    _fused_vs_sequential(synth.interface_config(2))
+
+
 def test_backward_bitwise_deterministic():
     itf = synth.interface_config(1, scale=80)
     a = gpu_run(itf, backward_seed=7)
