@@ -817,42 +817,49 @@ int mt::csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, hipStream_t st, b
     MT_HIP(hipEventRecord(c->aux_fork, st));
     MT_HIP(hipStreamWaitEvent(c->aux, c->aux_fork, 0));
     MT_HIP(hipStreamWaitEvent(c->aux2, c->aux_fork, 0));
-    if (blocks) {
+  }
+  // from the fork on, errors still join the internal streams back, so that
+  // the caller's stream orders after whatever was launched
+  auto body = [&]() -> int {
+    if (aux && blocks) {
       PhaseTimer t(c, MT_T_PAIR_FWD, c->aux);
       MT_HIP(launch_pair_fwd(S, M, kparams(c->params), c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), np_dev, P,
                              poly_buf(c), c->blk.as<double>(), P, c->counters.as<Counters>(), c->aux));
     }
-  }
-  MT_HIP(launch_pattern_rows(false, c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(), n, c->pair_off.as<int32_t>(),
-                             c->pair_m.as<int32_t>(), S.conn, M.conn, c->D_cnt.as<int32_t>(), c->M_cnt.as<int32_t>(),
-                             nullptr, nullptr, nullptr, nullptr, c->pat_keep.as<int32_t>(), nullptr, S.n_el, nullptr,
-                             P, c->pat_ecnt.as<int32_t>(), c->pat_elist.as<int32_t>(), st));
-  MT_HIP(scan_exclusive(c->D_cnt.as<int32_t>(), c->D_rowptr.as<int32_t>(), n, c->scan_tmp, st));
-  MT_HIP(scan_exclusive(c->M_cnt.as<int32_t>(), c->M_rowptr.as<int32_t>(), n, c->scan_tmp, st));
-  // the fill pass also writes the CSR positions of every local block entry;
-  // the column arrays are sized by the local block entries (16 per slave
-  // element for D, 16 per pair for M)
-  MT_HIP(launch_pattern_rows(true, c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(), n, c->pair_off.as<int32_t>(),
-                             c->pair_m.as<int32_t>(), S.conn, M.conn, nullptr, nullptr, c->D_rowptr.as<int32_t>(),
-                             c->M_rowptr.as<int32_t>(), c->D_col.as<int32_t>(), c->M_col.as<int32_t>(),
-                             c->pat_keep.as<int32_t>(), c->posD.as<int32_t>(), S.n_el, c->posM.as<int32_t>(), P,
-                             nullptr, nullptr, st));
-  if (aux) {
-    {
-      // on a second internal stream: the index's short atomic and sort
+    MT_HIP(launch_pattern_rows(false, c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(), n,
+                               c->pair_off.as<int32_t>(), c->pair_m.as<int32_t>(), S.conn, M.conn,
+                               c->D_cnt.as<int32_t>(), c->M_cnt.as<int32_t>(), nullptr, nullptr, nullptr, nullptr,
+                               c->pat_keep.as<int32_t>(), nullptr, S.n_el, nullptr, P, c->pat_ecnt.as<int32_t>(),
+                               c->pat_elist.as<int32_t>(), st));
+    MT_HIP(scan_exclusive(c->D_cnt.as<int32_t>(), c->D_rowptr.as<int32_t>(), n, c->scan_tmp, st));
+    MT_HIP(scan_exclusive(c->M_cnt.as<int32_t>(), c->M_rowptr.as<int32_t>(), n, c->scan_tmp, st));
+    // the fill pass also writes the CSR positions of every local block
+    // entry; the column arrays are sized by the local block entries (16 per
+    // slave element for D, 16 per pair for M)
+    MT_HIP(launch_pattern_rows(true, c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(), n,
+                               c->pair_off.as<int32_t>(), c->pair_m.as<int32_t>(), S.conn, M.conn, nullptr, nullptr,
+                               c->D_rowptr.as<int32_t>(), c->M_rowptr.as<int32_t>(), c->D_col.as<int32_t>(),
+                               c->M_col.as<int32_t>(), c->pat_keep.as<int32_t>(), c->posD.as<int32_t>(), S.n_el,
+                               c->posM.as<int32_t>(), P, nullptr, nullptr, st));
+    if (aux) {
+      // on the second internal stream: the index's short atomic and sort
       // kernels run beside the forward instead of after it
       PhaseTimer t(c, MT_T_GRAD_REDUCE, c->aux2);
-      int rc = build_master_index(c, c->aux2, c->aux_scan);
-      if (rc) return rc;
+      return build_master_index(c, c->aux2, c->aux_scan);
     }
+    return MT_OK;
+  };
+  const int rc = body();
+  if (aux) {
     MT_HIP(hipEventRecord(c->aux_join, c->aux));
     MT_HIP(hipEventRecord(c->aux2_join, c->aux2));
-    if (blocks) {
-      c->blk_gen = c->coord_gen;
-      c->blk_pending = true;
-    }
     MT_HIP(hipStreamWaitEvent(st, c->aux_join, 0));
     MT_HIP(hipStreamWaitEvent(st, c->aux2_join, 0));
+  }
+  if (rc) return rc;
+  if (aux && blocks) {
+    c->blk_gen = c->coord_gen;
+    c->blk_pending = true;
   }
   c->have_pattern = true;
   ++c->pattern_gen;
@@ -979,12 +986,14 @@ int mt_integrate_backward(mt_ctx* c, double* D_val, double* M_val, double* gap, 
   // the sweep's fill the register files
   if (int rc = ensure_aux(c)) return rc;
   MT_HIP(hipEventRecord(c->aux_fork, st));
-  if (int rc = enqueue_assemble(c, D_val, M_val, gap, st)) return rc;
+  int rc = enqueue_assemble(c, D_val, M_val, gap, st);
   MT_HIP(hipStreamWaitEvent(c->aux, c->aux_fork, 0));
-  if (int rc = enqueue_backward(c, W_D, W_M, w_g, gXs, gXm, c->aux)) return rc;
+  if (rc == MT_OK) rc = enqueue_backward(c, W_D, W_M, w_g, gXs, gXm, c->aux);
+  // joined also after an error, so that the caller's stream orders after
+  // whatever was launched
   MT_HIP(hipEventRecord(c->aux_join, c->aux));
   MT_HIP(hipStreamWaitEvent(st, c->aux_join, 0));
-  return MT_OK;
+  return rc;
 }
 
 int mt_set_timing_phases(mt_ctx* c, uint32_t mask) {
