@@ -501,8 +501,22 @@ __device__ __forceinline__ int walk_cells_group(const SlaveBox& b, const double*
   int c = 0;
   for (int zz = c0[2]; zz <= c1[2]; ++zz) {
     for (int yy = c0[1]; yy <= c1[1]; ++yy) {
-      int lo, hi;
-      row_run(range, (int64_t)g.n[0] * (yy + (int64_t)g.n[1] * zz), c0[0], c1[0], lo, hi);
+      // the run of the row's cells: the group's lanes read alternate cells
+      // and combine their bounds (the same run as row_run)
+      const int64_t row = (int64_t)g.n[0] * (yy + (int64_t)g.n[1] * zz);
+      int lo = 0x7fffffff, hi = 0;
+      for (int xx = c0[0] + r; xx <= c1[0]; xx += G) {
+        const int2 cr = range[row + xx];
+        if (cr.y > cr.x) {
+          lo = min(lo, cr.x);
+          hi = max(hi, cr.y);
+        }
+      }
+#pragma unroll
+      for (int d = 1; d < G; d <<= 1) {
+        lo = min(lo, __shfl_xor(lo, d, 64));
+        hi = max(hi, __shfl_xor(hi, d, 64));
+      }
       for (int i0 = lo; i0 < hi; i0 += G) {
         const int i = i0 + r;
         const bool hit = i < hi && touch_q(b, qs, sbox, qbox, i, delta);
