@@ -40,3 +40,35 @@ def test_binding_refuses_missing_library(tmp_path, monkeypatch):
     monkeypatch.setattr(_capi, "_lib", None)
     with pytest.raises(RuntimeError):
         _capi.lib()
+
+
+C_EXAMPLE = os.path.join(ROOT, "tests", "c_abi", "mortar_c_example.c")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+
+
+def build_c_example(outdir):
+    """gcc build of the plain-C example against the header, the library and
+    the HIP runtime (C host API only); returns the executable's path."""
+    import shutil
+    import subprocess
+    from paper_2202_03933_amd import _capi
+    gcc = shutil.which("gcc")
+    if gcc is None or not os.path.exists(os.path.join(ROCM, "include", "hip", "hip_runtime_api.h")):
+        pytest.skip("gcc or the HIP headers are not installed")
+    libdir = os.path.dirname(_capi.LIB_PATH)
+    exe = os.path.join(str(outdir), "mortar_c_example")
+    cmd = [gcc, "-std=c99", "-O2", "-Wall", "-Werror", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROCM, "include"),
+           "-I", os.path.join(ROOT, "include"), C_EXAMPLE, "-L", libdir, "-lmortar_mi355x",
+           "-L", os.path.join(ROCM, "lib"), "-lamdhip64", "-lm", f"-Wl,-rpath,{libdir}:{os.path.join(ROCM, 'lib')}",
+           "-o", exe]
+    subprocess.run(cmd, check=True, capture_output=True, text=True)
+    return exe
+
+
+def test_header_is_c_and_the_example_links(tmp_path):
+    # the header compiles as C99 and every entry point the C example calls
+    # resolves against the built library (nothing is run here)
+    from paper_2202_03933_amd import _capi
+    if not os.path.exists(_capi.LIB_PATH):
+        pytest.fail("HIP library not built (run __graft_entry__.build())")
+    assert os.path.exists(build_c_example(tmp_path))
