@@ -50,11 +50,21 @@ KERNELS = {
 
 
 def kernel_source_hash(files):
+    """Hash of the sources that make a kernel: whole files, or (file, marker)
+    for the part of a file before the line that starts with marker (the
+    device code of a file whose host code follows it)."""
     import hashlib
     h = hashlib.sha256()
     for f in files:
-        with open(os.path.join(ROOT, "paper_2202_03933_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        name, marker = f if isinstance(f, tuple) else (f, None)
+        with open(os.path.join(ROOT, "paper_2202_03933_amd", "csrc", name), "rb") as fh:
+            text = fh.read()
+        if marker is not None:
+            at = text.find(b"\n" + marker.encode())
+            if at < 0:
+                raise RuntimeError(f"{name}: no line starting with {marker!r}")
+            text = text[:at + 1]
+        h.update(text)
     return h.hexdigest()[:16]
 
 
@@ -405,12 +415,15 @@ ALL_SOURCES = ["mt_prims.hip", "mt_search.hip", "mt_pairs.hip", "mt_assemble.hip
                "mt_elements.hip", "mt_normals.hip", "mt_batch.hip", "mt_api.hip", "mt_geometry.h",
                "mt_pair_eval.h", "mt_dual.h", "mt_rows.h", "mt_internal.h"]
 FP64_SUMMARY = "wavy1024_fp64_counters.md"  # executed FP64 VALU instructions of every kernel of the step
+# mt_batch.hip holds its kernels first and the host code that drives them after
+# this line; the batched kernels are identified by the part before it
+BATCH_HOST = "struct mt_batch {"
 # source files whose hash identifies each counted kernel ("step": the whole library)
 COUNTER_SOURCES = {
     "k_pair_fwd": ["mt_pairs.hip", "mt_pair_eval.h", "mt_geometry.h"],
     "k_pair_bwd": ["mt_backward.hip", "mt_dual.h", "mt_pair_eval.h", "mt_geometry.h"],
-    "k_batch_fwd": ["mt_batch.hip", "mt_dual.h", "mt_rows.h", "mt_pair_eval.h", "mt_geometry.h"],
-    "k_batch_bwd": ["mt_batch.hip", "mt_dual.h", "mt_rows.h", "mt_pair_eval.h", "mt_geometry.h"],
+    "k_batch_fwd": [("mt_batch.hip", BATCH_HOST), "mt_dual.h", "mt_rows.h", "mt_pair_eval.h", "mt_geometry.h"],
+    "k_batch_bwd": [("mt_batch.hip", BATCH_HOST), "mt_dual.h", "mt_rows.h", "mt_pair_eval.h", "mt_geometry.h"],
     "step": ALL_SOURCES,
 }
 
