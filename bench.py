@@ -337,12 +337,14 @@ def bench_elements(itf, seg_outs, steps, warmup):
     return out
 
 
-def bench_variant(itf, weights, steps, warmup, **params):
+def bench_variant(itf, weights, steps, warmup, sync=True, **params):
     """The same step with other parameters: the dual Lagrange multiplier basis
     (dual-basis forward and backward, the backward including the adjoint of
-    the dual coefficients), or auxiliary planes from the continuous nodal
+    the dual coefficients), auxiliary planes from the continuous nodal
     normal field (its normals computed in every search, its gradient chain in
-    every backward)."""
+    every backward), or every kernel on the caller's stream (single_stream:
+    no phase runs beside another, so the phase times are those of each phase
+    alone).  sync=False: no count read-backs in the step."""
     import torch
     from paper_2202_03933_amd import MortarInterface, default_params
     dev = torch.device("cuda", 0)
@@ -355,8 +357,8 @@ def bench_variant(itf, weights, steps, warmup, **params):
              torch.empty(3, itf.master.n_nodes, dtype=torch.float64, device=dev))
 
     def step():
-        it.build_pairs()
-        it.csr_pattern()
+        it.build_pairs(sync=sync)
+        it.csr_pattern(sync=sync)
         it.integrate(outs)
         it.backward(*weights, grads)
 
@@ -375,7 +377,7 @@ def bench_variant(itf, weights, steps, warmup, **params):
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    n_pairs = it.n_pairs
+    n_pairs = it.stats()["n_pairs"]  # (read back: the no-wait step leaves the host counts unset)
     it.close()
     ms = (t1 - t0) * 1e3 / steps
     return {"ms_per_step": ms, "pairs_per_s": n_pairs / (ms * 1e-3), "n_pairs": n_pairs,
@@ -473,6 +475,7 @@ def main():
     ap.add_argument("--no-dual", action="store_true")
     ap.add_argument("--no-nodal", action="store_true")
     ap.add_argument("--no-elements", action="store_true")
+    ap.add_argument("--no-single-stream", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain 1 GiB device copy (calibrates HBM traffic counters)")
     ap.add_argument("--cpu-rows", type=int, default=16,
@@ -586,7 +589,13 @@ def main():
     iface.check()
     st = iface.stats()
     assert st["n_pairs"] == n_pairs
-    ms_step = min(ms_graph, ms_async, ms_fused)
+    # the same step on a context that runs every kernel on the caller's
+    # stream (single_stream): what the library's internal concurrency buys,
+    # and each phase's time alone
+    single = None
+    if not args.no_single_stream:
+        single = bench_variant(itf, (wD, wM, wg), args.steps, args.warmup, sync=False, single_stream=1)
+    ms_step = min(ms_graph, ms_async, ms_fused, single["ms_per_step"] if single else float("inf"))
     mem_gb = (free0 - torch.cuda.mem_get_info(dev)[0]) / 2**30
 
     if args.calib_copy:
@@ -659,11 +668,14 @@ def main():
                                "normal offsets U[-1e-3,1e-3], delta 1.25e-3: search + forward + backward per step",
                    "n_pairs": n_pairs, "n_candidates": n_cand, "nnz_D": iface.nnz_D, "nnz_M": iface.nnz_M},
         "step_modes_ms": {"graph_replay": ms_graph, "async": ms_async, "sync_counts": ms_sync,
-                          "fused_async": ms_fused},
-        "step_note": "value: the fastest of the eager no-wait step, its graph replay, and the eager step with "
+                          "fused_async": ms_fused,
+                          "single_stream_async": single["ms_per_step"] if single else None},
+        "single_stream_phase_ms_per_step": single["phase_ms_per_step"] if single else None,
+        "step_note": "value: the fastest of the eager no-wait step, its graph replay, the eager step with "
                      "mt_integrate_backward in place of mt_integrate + mt_backward (the same outputs bit for bit; "
-                     "the assembly beside the reverse sweep); inputs resident, every phase recomputed; sync_counts "
-                     "reads the counts back in every call",
+                     "the assembly beside the reverse sweep), and the eager step on a context with every kernel "
+                     "on the caller's stream (single_stream); inputs resident, every phase recomputed; "
+                     "sync_counts reads the counts back in every call",
         "fwd_pairs_per_s": n_pairs / (fwd_ms * 1e-3),
         "fwd_ms_per_step": fwd_ms,
         "phase_ms_per_step": per_step,

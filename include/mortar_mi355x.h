@@ -78,7 +78,8 @@ typedef struct mt_ctx mt_ctx;
 
 /* Algorithm parameters.  Defaults (mt_default_params): delta 0, automatic
  * bins, standard basis, 7-point rule, eps_d = eps_a = 1e-12,
- * newton_tol = 1e-14, newton_maxit = 30. */
+ * newton_tol = 1e-14, newton_maxit = 30, segment-based integration, element
+ * normals, internal streams allowed (single_stream 0). */
 typedef struct mt_params {
   double delta;        /* search: slave bounding box enlarged by delta per side */
   double bin_size;     /* search: minimal bin edge; 0 = automatic (see mt_build_pairs) */
@@ -91,7 +92,10 @@ typedef struct mt_params {
   int32_t element_rule; /* 0: segment-based integration (Alg. 1); n = 1..8: element-based,
                            n x n Gauss-Legendre points per slave element (see mt_integrate) */
   int32_t normals;      /* auxiliary-plane normals: MT_NORMALS_ELEMENT or MT_NORMALS_NODAL */
-  int32_t reserved;
+  int32_t single_stream; /* 0 (default): mt_csr_pattern and mt_integrate_backward run part of
+                            their kernels on the context's internal streams (forked from and
+                            joined back into the caller's stream); 1: every kernel of the
+                            context's calls on the caller's stream, in call order */
 } mt_params;
 
 /* Auxiliary-plane normal of a slave element (Sec. "Discretization": the
@@ -137,7 +141,8 @@ int mt_destroy(mt_ctx* ctx);
 int mt_default_params(mt_params* p);
 
 /* Set parameters (copied).  Invalidates the pair list.  Errors: MT_EINVAL
- * for rule not in {3, 7}, lm_basis out of range, negative tolerances. */
+ * for rule not in {3, 7}, lm_basis, element_rule, normals or single_stream
+ * out of range, negative tolerances. */
 int mt_set_params(mt_ctx* ctx, const mt_params* p);
 
 /* Register one side of the interface (MT_SIDE_SLAVE or MT_SIDE_MASTER):
@@ -273,7 +278,9 @@ int mt_get_candidates(mt_ctx* ctx, int32_t* slave_el, int32_t* master_el, uint8_
  * index of mt_backward on an internal stream of the context, concurrently
  * with the pattern, and joins that stream back into `stream` before
  * returning; the first mt_integrate after it then only assembles them
- * (unless the coordinates or parameters changed in between).
+ * (unless the coordinates or parameters changed in between).  With
+ * single_stream set, neither is done here: mt_integrate and mt_backward
+ * compute them on `stream`.
  * Errors: MT_ESTATE. */
 int mt_csr_pattern(mt_ctx* ctx, int64_t* nnz_D, int64_t* nnz_M, void* stream);
 
@@ -331,7 +338,8 @@ int mt_backward(mt_ctx* ctx, const double* W_D, const double* W_M, const double*
  * bit as mt_integrate followed by mt_backward with the same arguments, with
  * the assembly of D, M and the gap (bound by memory) on `stream` beside the
  * reverse sweep and the gradient sums (bound by FP64 issue) on an internal
- * stream of the context, joined before the call returns.  Arguments and
+ * stream of the context, joined before the call returns (with single_stream
+ * set, the assembly and then the reverse sweep on `stream`).  Arguments and
  * errors as the two calls. */
 int mt_integrate_backward(mt_ctx* ctx, double* D_val, double* M_val, double* gap, const double* W_D,
                           const double* W_M, const double* w_g, double* gXs, double* gXm, void* stream);

@@ -24,7 +24,7 @@ class mt_params(ctypes.Structure):
     _fields_ = [("delta", ctypes.c_double), ("bin_size", ctypes.c_double), ("lm_basis", ctypes.c_int32),
                 ("rule", ctypes.c_int32), ("eps_d", ctypes.c_double), ("eps_a", ctypes.c_double),
                 ("newton_tol", ctypes.c_double), ("newton_maxit", ctypes.c_int32), ("element_rule", ctypes.c_int32),
-                ("normals", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("normals", ctypes.c_int32), ("single_stream", ctypes.c_int32)]
 
 
 class mt_stats(ctypes.Structure):

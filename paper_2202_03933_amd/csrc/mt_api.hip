@@ -493,6 +493,7 @@ int mt_set_params(mt_ctx* c, const mt_params* p) {
     return fail(MT_EINVAL, "mt_set_params: element_rule must be 0 (segments) or 1..8");
   if (p->normals != MT_NORMALS_ELEMENT && p->normals != MT_NORMALS_NODAL)
     return fail(MT_EINVAL, "mt_set_params: normals");
+  if (p->single_stream != 0 && p->single_stream != 1) return fail(MT_EINVAL, "mt_set_params: single_stream");
   if (!(p->delta >= 0) || !(p->bin_size >= 0) || !(p->eps_d >= 0) || !(p->eps_a >= 0) || !(p->newton_tol > 0) ||
       p->newton_maxit < 1)
     return fail(MT_EINVAL, "mt_set_params: negative or invalid tolerance");
@@ -806,7 +807,7 @@ int mt::csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, hipStream_t st, b
   // the forward, the pattern passes, then the index (a chain of short sort
   // kernels, needed by the backward only), so that no pattern kernel waits
   // for the host to enqueue that chain behind the forward.
-  const bool aux = c->params.element_rule == 0 && c->poly_gen == c->coord_gen;
+  const bool aux = c->params.element_rule == 0 && c->poly_gen == c->coord_gen && !c->params.single_stream;
   if (aux) {
     if (!c->have_inc[1]) {
       int rc = build_incidence(c, M, c->minc_cnt, c->minc_off, c->minc_cur, c->minc_list, st);
@@ -831,8 +832,8 @@ int mt::csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, hipStream_t st, b
                                c->D_cnt.as<int32_t>(), c->M_cnt.as<int32_t>(), nullptr, nullptr, nullptr, nullptr,
                                c->pat_keep.as<int32_t>(), nullptr, S.n_el, nullptr, P, c->pat_ecnt.as<int32_t>(),
                                c->pat_elist.as<int32_t>(), st));
-    MT_HIP(scan_exclusive(c->D_cnt.as<int32_t>(), c->D_rowptr.as<int32_t>(), n, c->scan_tmp, st));
-    MT_HIP(scan_exclusive(c->M_cnt.as<int32_t>(), c->M_rowptr.as<int32_t>(), n, c->scan_tmp, st));
+    MT_HIP(scan_exclusive2(c->D_cnt.as<int32_t>(), c->D_rowptr.as<int32_t>(), c->M_cnt.as<int32_t>(),
+                           c->M_rowptr.as<int32_t>(), n, c->scan_tmp, st, aux ? SCAN_BLOCKS_BESIDE : 0));
     // the fill pass also writes the CSR positions of every local block
     // entry; the column arrays are sized by the local block entries (16 per
     // slave element for D, 16 per pair for M)
@@ -980,6 +981,10 @@ int mt_integrate_backward(mt_ctx* c, double* D_val, double* M_val, double* gap, 
   }
   if (int rc = prepare_pairs(c, st)) return rc;
   if (int rc = ensure_blocks(c, st)) return rc;  // also the dual adjoint's blocks
+  if (c->params.single_stream) {
+    const int rc = enqueue_assemble(c, D_val, M_val, gap, st);
+    return rc ? rc : enqueue_backward(c, W_D, W_M, w_g, gXs, gXm, st);
+  }
   // the assembly (bound by memory) on the caller's stream, the reverse sweep
   // (bound by FP64 issue) and the gradient sums on an internal stream; the
   // assembly is enqueued first, so that its workgroups are dispatched before

@@ -203,16 +203,23 @@ constexpr int KM = 32;
 static_assert(KD <= PCAP && KM <= PCAP, "kept rows are looked up in the LDS segment");
 
 // Positions of four keys that all occur in the sorted row v[0..u) (stride
-// vs): one pass over short rows (no dependent chain of a binary search), a
-// binary search per key over long ones.
+// vs).  Rows of the LDS segment: a branch-free lower bound in steps of 16,
+// 8, 4, 2, 1 (a position below 32 is the number of smaller entries), the
+// four keys' steps interleaved -- 5 reads per key instead of a pass over the
+// row, which matters because the fill pass runs beside the FP64-bound pair
+// quadrature and competes for the same vector ALUs.  Longer rows: a binary
+// search per key.
+static_assert(PCAP <= 32, "the stepped lower bound reaches positions up to 31");
 __device__ __forceinline__ void find4(const int32_t* v, int vs, int u, const int key[4], int pos[4]) {
   if (u <= PCAP) {
     pos[0] = pos[1] = pos[2] = pos[3] = 0;
-#pragma unroll 4
-    for (int i = 0; i < u; ++i) {
-      const int c = v[i * vs];
 #pragma unroll
-      for (int l = 0; l < 4; ++l) pos[l] = c == key[l] ? i : pos[l];
+    for (int st = 16; st > 0; st >>= 1) {
+#pragma unroll
+      for (int l = 0; l < 4; ++l) {
+        const int q = pos[l] + st;
+        if (q <= u && v[(q - 1) * vs] < key[l]) pos[l] = q;
+      }
     }
   } else {
 #pragma unroll
@@ -415,45 +422,72 @@ __global__ __launch_bounds__(BS) void k_grad_master(const int32_t* __restrict__ 
 constexpr int MS_SMALL = 32;
 constexpr int MS_RUN = 2048;
 constexpr int MS_BLOCKS = 512;
+constexpr unsigned MS_GRID = 2048;  // workgroups of the count and scatter passes
 
+// (grid-stride over the live pairs with at most MS_GRID workgroups: these
+// kernels run beside the pair quadrature on another stream)
 __global__ __launch_bounds__(BS) void k_mcount(const int32_t* __restrict__ pair_m, const int32_t* __restrict__ n_dev,
                                                 int32_t* __restrict__ cnt) {
-  const int64_t p = (int64_t)blockIdx.x * BS + threadIdx.x;
-  if (p < *n_dev) atomicAdd(&cnt[pair_m[p]], 1);
+  const int64_t n = *n_dev;
+  for (int64_t p = (int64_t)blockIdx.x * BS + threadIdx.x; p < n; p += (int64_t)gridDim.x * BS)
+    atomicAdd(&cnt[pair_m[p]], 1);
 }
 
 __global__ __launch_bounds__(BS) void k_mscatter(const int32_t* __restrict__ pair_m, const int32_t* __restrict__ n_dev,
                                                   const int32_t* __restrict__ off, int32_t* __restrict__ cur,
                                                   uint32_t* __restrict__ vals) {
-  const int64_t p = (int64_t)blockIdx.x * BS + threadIdx.x;
-  if (p >= *n_dev) return;
-  const int m = pair_m[p];
-  vals[off[m] + atomicAdd(&cur[m], 1)] = (uint32_t)p;
+  const int64_t n = *n_dev;
+  for (int64_t p = (int64_t)blockIdx.x * BS + threadIdx.x; p < n; p += (int64_t)gridDim.x * BS) {
+    const int m = pair_m[p];
+    vals[off[m] + atomicAdd(&cur[m], 1)] = (uint32_t)p;
+  }
 }
 
-// Short ranges: insertion sort, ranks.  Long ranges: appended to `big`
+// Ranges of up to MS_REG values: held in registers (no LDS, so that the
+// kernel finds room beside the LDS-heavy pattern kernels it runs with), each
+// value placed at its rank, the number of smaller values in the range (the
+// values, pair indices, are distinct), with its position recorded.  Up to
+// MS_SMALL: an insertion sort in place.  Longer ranges: appended to `big`
 // (its length in *n_big; the list order does not matter, each range is
 // sorted on its own).
+constexpr int MS_REG = 16;
+
 __global__ __launch_bounds__(BS) void k_msort(const int32_t* __restrict__ off, int32_t n_m_el,
                                                uint32_t* __restrict__ vals, int32_t* __restrict__ mpos,
                                                int32_t* __restrict__ big, int32_t* __restrict__ n_big) {
   const int m = blockIdx.x * BS + threadIdx.x;
   if (m >= n_m_el) return;
-  const int b = off[m], e = off[m + 1];
-  if (e - b > MS_SMALL) {
+  const int b = off[m], n = off[m + 1] - b;
+  if (n > MS_SMALL) {
     big[atomicAdd(n_big, 1)] = m;
     return;
   }
-  for (int i = b + 1; i < e; ++i) {
-    const uint32_t v = vals[i];
+  if (n <= MS_REG) {
+    uint32_t v[MS_REG];
+#pragma unroll
+    for (int k = 0; k < MS_REG; ++k) v[k] = k < n ? vals[b + k] : 0xffffffffu;
+#pragma unroll
+    for (int k = 0; k < MS_REG; ++k) {
+      if (k < n) {
+        int rank = 0;
+#pragma unroll
+        for (int i = 0; i < MS_REG; ++i) rank += v[i] < v[k] ? 1 : 0;
+        vals[b + rank] = v[k];
+        mpos[v[k]] = b + rank;
+      }
+    }
+    return;
+  }
+  for (int i = b + 1; i < b + n; ++i) {
+    const uint32_t x = vals[i];
     int j = i - 1;
-    while (j >= b && vals[j] > v) {
+    while (j >= b && vals[j] > x) {
       vals[j + 1] = vals[j];
       --j;
     }
-    vals[j + 1] = v;
+    vals[j + 1] = x;
   }
-  for (int k = b; k < e; ++k) mpos[vals[k]] = k;
+  for (int k = b; k < b + n; ++k) mpos[vals[k]] = k;
 }
 
 // Ascending bitonic sort of a[0..n) (n <= MS_RUN) through LDS, by the block.
@@ -612,12 +646,12 @@ hipError_t launch_master_index(const int32_t* pair_m, const int32_t* n_pairs, in
   if (e == hipSuccess) e = fill_i32(cur, 0, (int64_t)n_m_el + 1, s);
   if (e != hipSuccess) return e;
   if (cap > 0) {
-    k_mcount<<<grid_of(cap), BS, 0, s>>>(pair_m, n_pairs, cnt);
+    k_mcount<<<std::min<unsigned>(grid_of(cap), MS_GRID), BS, 0, s>>>(pair_m, n_pairs, cnt);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
-  if ((e = scan_exclusive(cnt, off, n_m_el, scan_tmp, s)) != hipSuccess) return e;
+  if ((e = scan_exclusive(cnt, off, n_m_el, scan_tmp, s, SCAN_BLOCKS_BESIDE)) != hipSuccess) return e;
   if (cap > 0) {
-    k_mscatter<<<grid_of(cap), BS, 0, s>>>(pair_m, n_pairs, off, cur, vals);
+    k_mscatter<<<std::min<unsigned>(grid_of(cap), MS_GRID), BS, 0, s>>>(pair_m, n_pairs, off, cur, vals);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   k_msort<<<grid_of(n_m_el), BS, 0, s>>>(off, n_m_el, vals, mpos, cur, cnt + n_m_el);

@@ -246,7 +246,16 @@ namespace mt {
 // Scratch (int32 elements) of a scan of up to n values.
 int64_t scan_tmp_elems(int64_t n);
 // Exclusive prefix sum of n int32 values into out[0..n]; out[n] = total.
-hipError_t scan_exclusive(const int32_t* in, int32_t* out, int64_t n, const Buf& tmp, hipStream_t s);
+// max_blocks > 0 caps the workgroups per launch (for a scan that runs beside
+// a long kernel on another stream).
+hipError_t scan_exclusive(const int32_t* in, int32_t* out, int64_t n, const Buf& tmp, hipStream_t s,
+                          int64_t max_blocks = 0);
+// Two such scans of arrays of the same length (in into out, in2 into out2)
+// in the launches of one; the same scratch.
+hipError_t scan_exclusive2(const int32_t* in, int32_t* out, const int32_t* in2, int32_t* out2, int64_t n,
+                           const Buf& tmp, hipStream_t s, int64_t max_blocks = 0);
+// Workgroup cap of scans that run beside the pair kernels.
+constexpr int64_t SCAN_BLOCKS_BESIDE = 256;
 // The same over a count the device holds (*n_dev <= cap): out[0..cap] with
 // the values from *n_dev on taken as zero, so out[*n_dev] = total.
 hipError_t scan_exclusive_dev(const int32_t* in, int32_t* out, const int32_t* n_dev, int64_t cap, const Buf& tmp,

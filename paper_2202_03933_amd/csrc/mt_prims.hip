@@ -74,88 +74,121 @@ __device__ __forceinline__ void load_slot(const int32_t* __restrict__ in, int64_
   }
 }
 
+// Each workgroup takes `per` consecutive tiles.  A launch with gridDim.y = 2
+// scans a second array of the same length (in2 into out2, its workgroup sums
+// after the first array's) in the same launches.
 template <bool VEC>
-__global__ __launch_bounds__(SCAN_BS) void k_tile_sums(const int32_t* __restrict__ in, int64_t n,
-                                                       const int32_t* n_dev, int32_t* __restrict__ sums) {
+__global__ __launch_bounds__(SCAN_BS) void k_tile_sums(const int32_t* __restrict__ in, const int32_t* __restrict__ in2,
+                                                       int64_t n, const int32_t* n_dev, int32_t* __restrict__ sums,
+                                                       int per) {
+  if (blockIdx.y) {
+    in = in2;
+    sums += gridDim.x;
+  }
   const int64_t live = live_count<int32_t>(n, n_dev);
-  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IPT;
-  int32_t v[SCAN_IPT];
-  load_slot<VEC>(in, base, live, v);
   int32_t s = 0;
+  for (int q = 0; q < per; ++q) {
+    const int64_t base = ((int64_t)blockIdx.x * per + q) * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IPT;
+    int32_t v[SCAN_IPT];
+    load_slot<VEC>(in, base, live, v);
 #pragma unroll
-  for (int i = 0; i < SCAN_IPT; ++i) s += v[i];
+    for (int i = 0; i < SCAN_IPT; ++i) s += v[i];
+  }
   int32_t tot;
   block_exclusive(s, &tot);
   if (threadIdx.x == 0) sums[blockIdx.x] = tot;
 }
 
-// out[i] = offset of the tile + exclusive prefix of in within the tile; the
-// last tile also writes out[n] = grand total.  Offset of tile t: offs[t]
-// (scanned), or with DIRECT the sum of sums[0..t) (raw tile sums), or 0.
+// out[i] = offset of the workgroup + exclusive prefix of in within its
+// tiles; the last workgroup also writes out[n] = grand total.  Offset of
+// workgroup w: offs[w] (scanned), or with DIRECT the sum of sums[0..w) (raw
+// workgroup sums), or 0.
 template <bool VEC, bool DIRECT>
-__global__ __launch_bounds__(SCAN_BS) void k_tile_scan(const int32_t* __restrict__ in, int64_t n,
-                                                       const int32_t* n_dev, const int32_t* __restrict__ offs,
-                                                       int32_t* __restrict__ out) {
+__global__ __launch_bounds__(SCAN_BS) void k_tile_scan(const int32_t* __restrict__ in, const int32_t* __restrict__ in2,
+                                                       int64_t n, const int32_t* n_dev,
+                                                       const int32_t* __restrict__ offs, int32_t* __restrict__ out,
+                                                       int32_t* __restrict__ out2, int per) {
+  if (blockIdx.y) {  // (the raw workgroup sums of the second array follow the first's)
+    in = in2;
+    out = out2;
+    if (DIRECT) offs += gridDim.x;
+  }
   const int64_t live = live_count<int32_t>(n, n_dev);
-  const int64_t t = blockIdx.x;
+  const int64_t w = blockIdx.x;
   int32_t off = 0;
   if (DIRECT) {
     int32_t part = 0;
-    for (int64_t i = threadIdx.x; i < t; i += SCAN_BS) part += offs[i];
+    for (int64_t i = threadIdx.x; i < w; i += SCAN_BS) part += offs[i];
     block_exclusive(part, &off);
   } else if (offs) {
-    off = offs[t];
+    off = offs[w];
   }
-  const int64_t base = t * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IPT;
-  int32_t v[SCAN_IPT];
-  load_slot<VEC>(in, base, live, v);
-  int32_t s = 0;
+  for (int q = 0; q < per; ++q) {
+    const int64_t base = (w * per + q) * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IPT;
+    int32_t v[SCAN_IPT];
+    load_slot<VEC>(in, base, live, v);
+    int32_t s = 0;
 #pragma unroll
-  for (int i = 0; i < SCAN_IPT; ++i) s += v[i];
-  int32_t tot;
-  int32_t run = block_exclusive(s, &tot) + off;
-  int32_t o[SCAN_IPT];
+    for (int i = 0; i < SCAN_IPT; ++i) s += v[i];
+    int32_t tot;
+    int32_t run = block_exclusive(s, &tot) + off;
+    int32_t o[SCAN_IPT];
 #pragma unroll
-  for (int i = 0; i < SCAN_IPT; ++i) {
-    o[i] = run;
-    run += v[i];
+    for (int i = 0; i < SCAN_IPT; ++i) {
+      o[i] = run;
+      run += v[i];
+    }
+    if (VEC && base + SCAN_IPT <= n) {
+      *reinterpret_cast<int4*>(out + base) = make_int4(o[0], o[1], o[2], o[3]);
+      *reinterpret_cast<int4*>(out + base + 4) = make_int4(o[4], o[5], o[6], o[7]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < SCAN_IPT; ++i)
+        if (base + i < n) out[base + i] = o[i];
+    }
+    off += tot;
   }
-  if (VEC && base + SCAN_IPT <= n) {
-    *reinterpret_cast<int4*>(out + base) = make_int4(o[0], o[1], o[2], o[3]);
-    *reinterpret_cast<int4*>(out + base + 4) = make_int4(o[4], o[5], o[6], o[7]);
-  } else {
-#pragma unroll
-    for (int i = 0; i < SCAN_IPT; ++i)
-      if (base + i < n) out[base + i] = o[i];
-  }
-  if (t == (int64_t)gridDim.x - 1 && threadIdx.x == SCAN_BS - 1) out[n] = run;
+  if (w == (int64_t)gridDim.x - 1 && threadIdx.x == 0) out[n] = off;
 }
 
 // Exclusive scan of n values (of the first *n_dev when given; the rest count
-// as zero) into out[0..n].  No memset: the launches can be captured in a
-// graph.
-hipError_t scan_impl(const int32_t* in, int32_t* out, int64_t n, const int32_t* n_dev, int32_t* tmp, hipStream_t s) {
+// as zero) into out[0..n]; with in2, also of in2 into out2 (n_dev null) in
+// the same launches while the workgroup sums of both fit the direct scheme.
+// max_blocks > 0 caps the workgroups of each launch (several tiles each): a
+// scan queued beside a long kernel on another stream then waits for few
+// dispatch slots.  No memset: the launches can be captured in a graph.
+hipError_t scan_impl(const int32_t* in, int32_t* out, int64_t n, const int32_t* n_dev, int32_t* tmp, hipStream_t s,
+                     const int32_t* in2 = nullptr, int32_t* out2 = nullptr, int64_t max_blocks = 0) {
   const int64_t tiles = std::max<int64_t>(1, (n + SCAN_TILE - 1) / SCAN_TILE);
-  const bool vec = ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 15) == 0;
-  if (tiles == 1) {
+  const int per = max_blocks > 0 ? (int)((tiles + max_blocks - 1) / max_blocks) : 1;
+  const int64_t blocks = (tiles + per - 1) / per;
+  uintptr_t addr = reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out);
+  if (in2) addr |= reinterpret_cast<uintptr_t>(in2) | reinterpret_cast<uintptr_t>(out2);
+  const bool vec = (addr & 15) == 0;
+  if (in2 && blocks > SCAN_DIRECT) {
+    hipError_t e = scan_impl(in, out, n, n_dev, tmp, s, nullptr, nullptr, max_blocks);
+    return e != hipSuccess ? e : scan_impl(in2, out2, n, nullptr, tmp, s, nullptr, nullptr, max_blocks);
+  }
+  const dim3 grid((unsigned)blocks, in2 ? 2u : 1u);
+  if (blocks == 1) {
     auto* k = vec ? k_tile_scan<true, false> : k_tile_scan<false, false>;
-    k<<<1, SCAN_BS, 0, s>>>(in, n, n_dev, nullptr, out);
+    k<<<grid, SCAN_BS, 0, s>>>(in, in2, n, n_dev, nullptr, out, out2, per);
     return hipGetLastError();
   }
-  int32_t* sums = tmp;
-  (vec ? k_tile_sums<true> : k_tile_sums<false>)<<<(unsigned)tiles, SCAN_BS, 0, s>>>(in, n, n_dev, sums);
+  int32_t* sums = tmp;  // blocks (2 blocks with in2) entries
+  (vec ? k_tile_sums<true> : k_tile_sums<false>)<<<grid, SCAN_BS, 0, s>>>(in, in2, n, n_dev, sums, per);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (tiles <= SCAN_DIRECT) {
+  if (blocks <= SCAN_DIRECT) {
     auto* k = vec ? k_tile_scan<true, true> : k_tile_scan<false, true>;
-    k<<<(unsigned)tiles, SCAN_BS, 0, s>>>(in, n, n_dev, sums, out);
+    k<<<grid, SCAN_BS, 0, s>>>(in, in2, n, n_dev, sums, out, out2, per);
     return hipGetLastError();
   }
-  int32_t* offs = tmp + tiles;  // tiles + 1 entries
-  e = scan_impl(sums, offs, tiles, nullptr, offs + tiles + 1, s);
+  int32_t* offs = tmp + blocks;  // blocks + 1 entries
+  e = scan_impl(sums, offs, blocks, nullptr, offs + blocks + 1, s);
   if (e != hipSuccess) return e;
   auto* k = vec ? k_tile_scan<true, false> : k_tile_scan<false, false>;
-  k<<<(unsigned)tiles, SCAN_BS, 0, s>>>(in, n, n_dev, offs, out);
+  k<<<(unsigned)blocks, SCAN_BS, 0, s>>>(in, nullptr, n, n_dev, offs, out, nullptr, per);
   return hipGetLastError();
 }
 
@@ -262,9 +295,12 @@ __global__ __launch_bounds__(RS_BS) void k_rs_scatter(const uint32_t* __restrict
   }
 }
 
+// Grid-stride fill: at most FILL_BLOCKS workgroups, so that a fill queued
+// beside a long kernel on another stream waits for few dispatch slots.
+constexpr int64_t FILL_BLOCKS = 1024;
 __global__ void k_fill_i32(int32_t* p, int32_t v, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
 }
 __global__ void k_fill_f64(double* p, double v, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -279,9 +315,16 @@ __global__ void k_copy_u32(const uint32_t* __restrict__ a, uint32_t* __restrict_
 
 }  // namespace
 
-hipError_t scan_exclusive(const int32_t* in, int32_t* out, int64_t n, const Buf& tmp, hipStream_t s) {
+hipError_t scan_exclusive(const int32_t* in, int32_t* out, int64_t n, const Buf& tmp, hipStream_t s,
+                          int64_t max_blocks) {
   if ((int64_t)(tmp.bytes / sizeof(int32_t)) < scan_tmp_elems(n)) return hipErrorInvalidValue;
-  return scan_impl(in, out, n, nullptr, tmp.as<int32_t>(), s);
+  return scan_impl(in, out, n, nullptr, tmp.as<int32_t>(), s, nullptr, nullptr, max_blocks);
+}
+
+hipError_t scan_exclusive2(const int32_t* in, int32_t* out, const int32_t* in2, int32_t* out2, int64_t n,
+                           const Buf& tmp, hipStream_t s, int64_t max_blocks) {
+  if ((int64_t)(tmp.bytes / sizeof(int32_t)) < scan_tmp_elems(n)) return hipErrorInvalidValue;
+  return scan_impl(in, out, n, nullptr, tmp.as<int32_t>(), s, in2, out2, max_blocks);
 }
 
 hipError_t scan_exclusive_dev(const int32_t* in, int32_t* out, const int32_t* n_dev, int64_t cap, const Buf& tmp,
@@ -323,7 +366,7 @@ hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, 
 
 hipError_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  k_fill_i32<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, v, n);
+  k_fill_i32<<<(unsigned)std::min<int64_t>((n + 255) / 256, FILL_BLOCKS), 256, 0, s>>>(p, v, n);
   return hipGetLastError();
 }
 

@@ -2,6 +2,8 @@
 oracle's forward-mode dual-number gradients, central finite differences of
 the GPU's own forward pass, and the torch.autograd.Function wrapper."""
 
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -250,11 +252,13 @@ def _fused_vs_sequential(itf, dual=False, nodal=False, seed=3300):
     import scipy.sparse as sp
     dev = torch.device("cuda", 0)
 
-    def make():
+    def make(single_stream=0):
+        p = gpu_params(itf, dual=dual, nodal=nodal)
+        p.single_stream = single_stream
         return MortarInterface(torch.from_numpy(itf.slave.X), torch.from_numpy(itf.slave.conn),
                                torch.from_numpy(itf.master.X), torch.from_numpy(itf.master.conn),
-                               params=gpu_params(itf, dual=dual, nodal=nodal), device=dev).setup()
-    a, b = make(), make()
+                               params=p, device=dev).setup()
+    a, b, c = make(), make(), make(single_stream=1)
     ns, nm = a.n_slave_nodes, a.n_master_nodes
     D = sp.csr_matrix((np.zeros(a.nnz_D), a.D_col.cpu().numpy(), a.D_rowptr.cpu().numpy()), shape=(ns, ns))
     M = sp.csr_matrix((np.zeros(a.nnz_M), a.M_col.cpu().numpy(), a.M_rowptr.cpu().numpy()), shape=(ns, nm))
@@ -265,16 +269,22 @@ def _fused_vs_sequential(itf, dual=False, nodal=False, seed=3300):
             Xs = itf.slave.X + rng.uniform(-1e-5, 1e-5, itf.slave.X.shape)
             a.move_coordinates(Xs, itf.master.X)
             b.move_coordinates(Xs, itf.master.X)
+            c.move_coordinates(Xs, itf.master.X)
         f_seq = tuple(t.clone() for t in a.integrate())
         g_seq = tuple(t.clone() for t in a.backward(*W))
         f_fus, g_fus = b.integrate_backward(*W)
+        # every kernel on the caller's stream: the same values
+        f_one, g_one = c.integrate_backward(*W)
         torch.cuda.synchronize()
         assert all(torch.equal(x, y) for x, y in zip(f_seq, f_fus)), step
         assert all(torch.equal(x, y) for x, y in zip(g_seq, g_fus)), step
+        assert all(torch.equal(x, y) for x, y in zip(f_seq, f_one)), step
+        assert all(torch.equal(x, y) for x, y in zip(g_seq, g_one)), step
 
 
 # mt_integrate_backward (assembly beside the reverse sweep) equals
-# mt_integrate followed by mt_backward bit for bit: standard and dual basis,
+# mt_integrate followed by mt_backward bit for bit, and so does a context
+# that runs every kernel on the caller's stream: standard and dual basis,
 # the continuous normal field, before and after an in-place coordinate move.
 @pytest.mark.parametrize("dual,nodal", [(False, False), (True, False), (False, True), (True, True)])
 def test_integrate_backward_equals_sequential(dual, nodal):
@@ -303,6 +313,9 @@ def test_error_codes():
     with pytest.raises(MortarError) as e:
         iface.integrate(out=(torch.empty(1, dtype=torch.float64, device=dev),) * 3)
     assert e.value.code == C.MT_ESTATE
+    p = default_params()
+    p.single_stream = 2
+    assert C.lib().mt_set_params(iface.h, ctypes.byref(p)) == C.MT_EINVAL
     iface.setup()
     # connectivity out of range is reported by the upload, not read
     bad = itf.slave.conn.copy()
