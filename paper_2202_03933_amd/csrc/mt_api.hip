@@ -830,18 +830,21 @@ int mt::csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, hipStream_t st, b
     MT_HIP(launch_pattern_rows(false, c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(), n,
                                c->pair_off.as<int32_t>(), c->pair_m.as<int32_t>(), S.conn, M.conn,
                                c->D_cnt.as<int32_t>(), c->M_cnt.as<int32_t>(), nullptr, nullptr, nullptr, nullptr,
-                               c->pat_keep.as<int32_t>(), nullptr, S.n_el, nullptr, P, c->pat_ecnt.as<int32_t>(),
+                               c->pat_keep.as<int32_t>(), S.n_el, c->pat_ecnt.as<int32_t>(),
                                c->pat_elist.as<int32_t>(), st));
     MT_HIP(scan_exclusive2(c->D_cnt.as<int32_t>(), c->D_rowptr.as<int32_t>(), c->M_cnt.as<int32_t>(),
                            c->M_rowptr.as<int32_t>(), n, c->scan_tmp, st, aux ? SCAN_BLOCKS_BESIDE : 0));
-    // the fill pass also writes the CSR positions of every local block
-    // entry; the column arrays are sized by the local block entries (16 per
-    // slave element for D, 16 per pair for M)
+    // the column arrays are sized by the local block entries (16 per slave
+    // element for D, 16 per pair for M); then the CSR position of every
+    // local block entry, pair by pair
     MT_HIP(launch_pattern_rows(true, c->inc_off.as<int32_t>(), c->inc_list.as<int32_t>(), n,
                                c->pair_off.as<int32_t>(), c->pair_m.as<int32_t>(), S.conn, M.conn, nullptr, nullptr,
                                c->D_rowptr.as<int32_t>(), c->M_rowptr.as<int32_t>(), c->D_col.as<int32_t>(),
-                               c->M_col.as<int32_t>(), c->pat_keep.as<int32_t>(), c->posD.as<int32_t>(), S.n_el,
-                               c->posM.as<int32_t>(), P, nullptr, nullptr, st));
+                               c->M_col.as<int32_t>(), c->pat_keep.as<int32_t>(), S.n_el, nullptr, nullptr, st));
+    MT_HIP(launch_pattern_positions(c->pair_s.as<int32_t>(), c->pair_m.as<int32_t>(), np_dev, P, S.conn, M.conn,
+                                    S.n_el, c->pair_off.as<int32_t>(), c->D_rowptr.as<int32_t>(),
+                                    c->D_col.as<int32_t>(), c->M_rowptr.as<int32_t>(), c->M_col.as<int32_t>(),
+                                    c->posD.as<int32_t>(), c->posM.as<int32_t>(), st));
     if (aux) {
       // on the second internal stream: the index's short atomic and sort
       // kernels run beside the forward instead of after it

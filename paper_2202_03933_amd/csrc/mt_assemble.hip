@@ -197,94 +197,11 @@ __device__ __forceinline__ int merge_mrow(int a, int32_t n, const int32_t* __res
 // is counted, and in the fill pass written, by row_columns_scan.  The count
 // pass writes the row lengths and keeps rows of at most KD (D) / KM (M)
 // columns in lane-interleaved scratch keep[i * n + a]; the fill pass copies
-// those and recomputes the rest.
+// those and recomputes the rest.  The CSR positions of the local blocks are
+// found afterwards, pair by pair (k_positions).
 constexpr int KD = 16;
 constexpr int KM = 32;
-static_assert(KD <= PCAP && KM <= PCAP, "kept rows are looked up in the LDS segment");
-
-// Positions of four keys that all occur in the sorted row v[0..u) (stride
-// vs).  Rows of the LDS segment: a branch-free lower bound in steps of 16,
-// 8, 4, 2, 1 (a position below 32 is the number of smaller entries), the
-// four keys' steps interleaved -- 5 reads per key instead of a pass over the
-// row, which matters because the fill pass runs beside the FP64-bound pair
-// quadrature and competes for the same vector ALUs.  Longer rows: a binary
-// search per key.
-static_assert(PCAP <= 32, "the stepped lower bound reaches positions up to 31");
-__device__ __forceinline__ void find4(const int32_t* v, int vs, int u, const int key[4], int pos[4]) {
-  if (u <= PCAP) {
-    pos[0] = pos[1] = pos[2] = pos[3] = 0;
-#pragma unroll
-    for (int st = 16; st > 0; st >>= 1) {
-#pragma unroll
-      for (int l = 0; l < 4; ++l) {
-        const int q = pos[l] + st;
-        if (q <= u && v[(q - 1) * vs] < key[l]) pos[l] = q;
-      }
-    }
-  } else {
-#pragma unroll
-    for (int l = 0; l < 4; ++l) {
-      int lo = 0, hi = u;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (v[mid * vs] < key[l]) lo = mid + 1;
-        else hi = mid;
-      }
-      pos[l] = lo;
-    }
-  }
-}
-
-// CSR positions of the local blocks that row a receives: for D, of the four
-// nodes of each incident element with pairs (posD[(4 j + k) * n_el + e]);
-// for M, of the four master nodes of each pair of those elements
-// (posM[(4 j + l) * n_pairs + p]); j = local index of node a.  Entries of
-// elements without pairs are not written (nothing reads them).
-template <bool MCOLS>
-__device__ __forceinline__ void row_positions(int a, const int32_t* v, int vs, int u, int base,
-                                              const int32_t* __restrict__ inc_off,
-                                              const int32_t* __restrict__ inc_list,
-                                              const int32_t* __restrict__ pair_off,
-                                              const int32_t* __restrict__ pair_m,
-                                              const int32_t* __restrict__ conn_s,
-                                              const int32_t* __restrict__ conn_m, int32_t* __restrict__ pos,
-                                              int64_t pstride) {
-  for (int i = inc_off[a]; i < inc_off[a + 1]; ++i) {
-    const int e = inc_list[i] >> 2, j = inc_list[i] & 3;
-    const int p0 = pair_off[e], p1 = pair_off[e + 1];
-    if (p1 == p0) continue;
-    for (int p = MCOLS ? p0 : 0; p < (MCOLS ? p1 : 1); ++p) {
-      const int4 q = reinterpret_cast<const int4*>(MCOLS ? conn_m : conn_s)[MCOLS ? pair_m[p] : e];
-      const int key[4] = {q.x, q.y, q.z, q.w};
-      int ix[4];
-      find4(v, vs, u, key, ix);
-      const int64_t at = MCOLS ? p : e;
-#pragma unroll
-      for (int l = 0; l < 4; ++l) pos[(int64_t)(j * 4 + l) * pstride + at] = base + ix[l];
-    }
-  }
-}
-
-template <bool FILL, bool MCOLS>
-__device__ __forceinline__ void finish_row(int a, int32_t n, int u, const int32_t* v, int stride, int32_t* cnt,
-                                           const int32_t* __restrict__ rowptr, int32_t* colv, int32_t* keep,
-                                           int kcap, const int32_t* __restrict__ inc_off,
-                                           const int32_t* __restrict__ inc_list,
-                                           const int32_t* __restrict__ pair_off,
-                                           const int32_t* __restrict__ pair_m,
-                                           const int32_t* __restrict__ conn_s,
-                                           const int32_t* __restrict__ conn_m, int32_t* pos, int64_t pstride) {
-  if (!FILL) {
-    cnt[a] = u;
-    if (u <= kcap)
-      for (int i = 0; i < u; ++i) keep[(int64_t)i * n] = v[i * stride];
-  } else {
-    const int base = rowptr[a];
-    int32_t* col = colv + base;
-    for (int i = 0; i < u; ++i) col[i] = v[i * stride];
-    row_positions<MCOLS>(a, v, stride, u, base, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m, pos, pstride);
-  }
-}
+static_assert(KD <= PCAP && KM <= PCAP, "kept rows fit the LDS segment");
 
 template <bool FILL, bool MCOLS>
 __device__ __forceinline__ void pattern_row(int a, int32_t n, int32_t* lds, const int32_t* __restrict__ inc_off,
@@ -294,38 +211,29 @@ __device__ __forceinline__ void pattern_row(int a, int32_t n, int32_t* lds, cons
                                             const int32_t* __restrict__ conn_s,
                                             const int32_t* __restrict__ conn_m, int32_t* cnt,
                                             const int32_t* __restrict__ rowptr, int32_t* colv, int32_t* keep,
-                                            int kcap, int32_t* pos, int64_t pstride) {
+                                            int kcap) {
   const int u = row_columns<MCOLS>(a, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m, lds, PB, PCAP);
   if (u >= 0) {
-    finish_row<FILL, MCOLS>(a, n, u, lds, PB, cnt, rowptr, colv, keep, kcap, inc_off, inc_list, pair_off, pair_m,
-                            conn_s, conn_m, pos, pstride);
+    if (!FILL) {
+      cnt[a] = u;
+      if (u <= kcap)
+        for (int i = 0; i < u; ++i) keep[(int64_t)i * n] = lds[i * PB];
+    } else {
+      int32_t* col = colv + rowptr[a];
+      for (int i = 0; i < u; ++i) col[i] = lds[i * PB];
+    }
   } else if (!FILL) {
     cnt[a] = row_columns_scan<MCOLS>(a, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m, nullptr);
   } else {
-    const int base = rowptr[a];
-    const int w = row_columns_scan<MCOLS>(a, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m, colv + base);
-    row_positions<MCOLS>(a, colv + base, 1, w, base, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m, pos,
-                         pstride);
+    row_columns_scan<MCOLS>(a, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m, colv + rowptr[a]);
   }
 }
 
-// Kept rows of the fill pass: copied from the lane-interleaved scratch to
-// the column array and to the thread's LDS segment, where the block
-// positions are looked up.
-template <bool MCOLS>
-__device__ __forceinline__ void kept_row(int a, int32_t n, int u, const int32_t* keep, int32_t* lds,
-                                         const int32_t* __restrict__ rowptr, int32_t* colv,
-                                         const int32_t* __restrict__ inc_off, const int32_t* __restrict__ inc_list,
-                                         const int32_t* __restrict__ pair_off, const int32_t* __restrict__ pair_m,
-                                         const int32_t* __restrict__ conn_s, const int32_t* __restrict__ conn_m,
-                                         int32_t* pos, int64_t pstride) {
-  const int base = rowptr[a];
-  for (int i = 0; i < u; ++i) {
-    const int c = keep[(int64_t)i * n + a];
-    colv[base + i] = c;
-    lds[i * PB] = c;
-  }
-  row_positions<MCOLS>(a, lds, PB, u, base, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m, pos, pstride);
+// Kept rows of the fill pass: copied from the lane-interleaved scratch.
+__device__ __forceinline__ void kept_row(int a, int32_t n, int u, const int32_t* __restrict__ keep,
+                                         const int32_t* __restrict__ rowptr, int32_t* colv) {
+  int32_t* col = colv + rowptr[a];
+  for (int i = 0; i < u; ++i) col[i] = keep[(int64_t)i * n + a];
 }
 
 template <bool FILL>
@@ -338,8 +246,7 @@ __global__ __launch_bounds__(PB) void k_pattern_rows(const int32_t* __restrict__
                                                       int32_t* M_cnt,
                                                       const int32_t* __restrict__ D_rowptr,
                                                       const int32_t* __restrict__ M_rowptr, int32_t* D_col,
-                                                      int32_t* M_col, int32_t* keepD, int32_t* keepM,
-                                                      int32_t* posD, int32_t n_el, int32_t* posM, int64_t np,
+                                                      int32_t* M_col, int32_t* keepD, int32_t* keepM, int32_t n_el,
                                                       const int32_t* __restrict__ ecnt,
                                                       const int32_t* __restrict__ elist) {
   __shared__ int32_t lds[PCAP * PB];
@@ -348,11 +255,10 @@ __global__ __launch_bounds__(PB) void k_pattern_rows(const int32_t* __restrict__
   int32_t* seg = lds + threadIdx.x;
   // D row
   if (FILL && D_rowptr[a + 1] - D_rowptr[a] <= KD)
-    kept_row<false>(a, n, D_rowptr[a + 1] - D_rowptr[a], keepD, seg, D_rowptr, D_col, inc_off, inc_list, pair_off,
-                    pair_m, conn_s, conn_m, posD, n_el);
+    kept_row(a, n, D_rowptr[a + 1] - D_rowptr[a], keepD, D_rowptr, D_col);
   else
     pattern_row<FILL, false>(a, n, seg, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m, D_cnt, D_rowptr, D_col,
-                             keepD + a, KD, posD, n_el);
+                             keepD + a, KD);
   // M row (count pass: merge of the element lists when they exist)
   if (!FILL && ecnt) {
     const int u = merge_mrow(a, n, inc_off, inc_list, n_el, ecnt, elist, keepM + a, KM);
@@ -362,11 +268,103 @@ __global__ __launch_bounds__(PB) void k_pattern_rows(const int32_t* __restrict__
     }
   }
   if (FILL && M_rowptr[a + 1] - M_rowptr[a] <= KM)
-    kept_row<true>(a, n, M_rowptr[a + 1] - M_rowptr[a], keepM, seg, M_rowptr, M_col, inc_off, inc_list, pair_off,
-                   pair_m, conn_s, conn_m, posM, np);
+    kept_row(a, n, M_rowptr[a + 1] - M_rowptr[a], keepM, M_rowptr, M_col);
   else
     pattern_row<FILL, true>(a, n, seg, inc_off, inc_list, pair_off, pair_m, conn_s, conn_m, M_cnt, M_rowptr, M_col,
-                            keepM + a, KM, posM, np);
+                            keepM + a, KM);
+}
+
+// Positions of four keys that all occur in the sorted row v[0..u): a
+// branch-free lower bound in power-of-two steps from the largest power of
+// two not above u (the position of a key is the number of smaller entries),
+// the four keys' steps interleaved.
+template <class P>
+__device__ __forceinline__ void lower_bound4(P v, int u, const int key[4], int pos[4]) {
+  pos[0] = pos[1] = pos[2] = pos[3] = 0;
+  for (int st = u > 0 ? 1 << (31 - __clz(u)) : 0; st > 0; st >>= 1) {
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+      const int q = pos[l] + st;
+      if (q <= u && v[q - 1] < key[l]) pos[l] = q;
+    }
+  }
+}
+
+// CSR positions of the local blocks, one lane per pair (M) or slave element
+// with pairs (D), for the four local nodes j in turn: for M, of the four
+// master nodes of pair p in the row of slave node j of its element
+// (posM[(4 j + l) * pstride + p]); for D, of the four nodes of element e in
+// the row of its node j (posD[(4 j + k) * n_el + e]; elements without pairs
+// are skipped, nothing reads their entries).  The rows a workgroup's lanes
+// need for one j are neighbours in a mesh numbered row by row, so the
+// workgroup stages the span of the column array from its smallest to its
+// largest row in LDS with coalesced loads and each lane searches its row
+// there; a span longer than POS_SPAN is searched in global memory.  Lanes
+// write consecutive entries.
+constexpr int POS_SPAN = 4096;
+
+template <bool MCOLS>
+__global__ __launch_bounds__(BS) void k_positions(int64_t n_items, const int32_t* __restrict__ n_dev,
+                                                   const int32_t* __restrict__ pair_s,
+                                                   const int32_t* __restrict__ pair_m,
+                                                   const int32_t* __restrict__ pair_off,
+                                                   const int32_t* __restrict__ conn_s,
+                                                   const int32_t* __restrict__ conn_m,
+                                                   const int32_t* __restrict__ rowptr,
+                                                   const int32_t* __restrict__ col, int32_t* __restrict__ pos,
+                                                   int64_t pstride) {
+  __shared__ int32_t span[POS_SPAN];
+  __shared__ int32_t red[2][BS / 64];
+  const int64_t n = MCOLS ? (int64_t)*n_dev : n_items;
+  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
+  if ((int64_t)blockIdx.x * BS >= n) return;  // whole workgroups past the end
+  bool act = i < n;
+  int4 cs = make_int4(0, 0, 0, 0), key4 = make_int4(0, 0, 0, 0);
+  if (act) {
+    const int e = MCOLS ? pair_s[i] : (int)i;
+    if (!MCOLS) act = pair_off[e + 1] > pair_off[e];
+    cs = reinterpret_cast<const int4*>(conn_s)[e];
+    key4 = MCOLS ? reinterpret_cast<const int4*>(conn_m)[pair_m[i]] : cs;
+  }
+  const int key[4] = {key4.x, key4.y, key4.z, key4.w};
+  const int w = threadIdx.x >> 6;
+#pragma unroll 1
+  for (int j = 0; j < 4; ++j) {
+    const int a = j == 0 ? cs.x : j == 1 ? cs.y : j == 2 ? cs.z : cs.w;
+    int lo = act ? a : 0x7fffffff, hi = act ? a : -1;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+      lo = min(lo, __shfl_xor(lo, d, 64));
+      hi = max(hi, __shfl_xor(hi, d, 64));
+    }
+    __syncthreads();  // (the previous j's searches are done with the span)
+    if ((threadIdx.x & 63) == 0) {
+      red[0][w] = lo;
+      red[1][w] = hi;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < BS / 64; ++k) {
+      lo = min(lo, red[0][k]);
+      hi = max(hi, red[1][k]);
+    }
+    if (hi < 0) continue;  // no active lane (uniform across the workgroup)
+    const int c0 = rowptr[lo], c1 = rowptr[hi + 1];
+    const bool staged = c1 - c0 <= POS_SPAN;
+    if (staged)
+      for (int k = threadIdx.x; k < c1 - c0; k += BS) span[k] = col[c0 + k];
+    __syncthreads();
+    if (act) {
+      const int r0 = rowptr[a], u = rowptr[a + 1] - r0;
+      int ix[4];
+      if (staged)
+        lower_bound4(span + (r0 - c0), u, key, ix);
+      else
+        lower_bound4(col + r0, u, key, ix);
+#pragma unroll
+      for (int l = 0; l < 4; ++l) pos[(int64_t)(j * 4 + l) * pstride + i] = r0 + ix[l];
+    }
+  }
 }
 
 // One thread per slave node (row): the row is accumulated in a per-thread
@@ -591,21 +589,36 @@ hipError_t launch_inc_sort(const int32_t* off, int32_t n_nodes, int32_t* list, h
 hipError_t launch_pattern_rows(bool fill, const int32_t* inc_off, const int32_t* inc_list, int32_t n_nodes,
                                const int32_t* pair_off, const int32_t* pair_m, const int32_t* conn_s,
                                const int32_t* conn_m, int32_t* D_cnt, int32_t* M_cnt, const int32_t* D_rowptr,
-                               const int32_t* M_rowptr, int32_t* D_col, int32_t* M_col, int32_t* keep, int32_t* posD,
-                               int32_t n_s_el, int32_t* posM, int64_t pstride, int32_t* ecnt, int32_t* elist,
-                               hipStream_t s) {
+                               const int32_t* M_rowptr, int32_t* D_col, int32_t* M_col, int32_t* keep,
+                               int32_t n_s_el, int32_t* ecnt, int32_t* elist, hipStream_t s) {
   if (n_nodes == 0) return hipSuccess;
   const unsigned g = xcd_grid((unsigned)((n_nodes + PB - 1) / PB));
   int32_t* keepD = keep;
   int32_t* keepM = keep + (int64_t)KD * n_nodes;
   if (fill)
     k_pattern_rows<true><<<g, PB, 0, s>>>(inc_off, inc_list, n_nodes, pair_off, pair_m, conn_s, conn_m, D_cnt, M_cnt,
-                                          D_rowptr, M_rowptr, D_col, M_col, keepD, keepM, posD, n_s_el, posM,
-                                          pstride, nullptr, nullptr);
+                                          D_rowptr, M_rowptr, D_col, M_col, keepD, keepM, n_s_el, nullptr, nullptr);
   else
     k_pattern_rows<false><<<g, PB, 0, s>>>(inc_off, inc_list, n_nodes, pair_off, pair_m, conn_s, conn_m, D_cnt,
-                                           M_cnt, D_rowptr, M_rowptr, D_col, M_col, keepD, keepM, posD, n_s_el, posM,
-                                           pstride, ecnt, elist);
+                                           M_cnt, D_rowptr, M_rowptr, D_col, M_col, keepD, keepM, n_s_el, ecnt,
+                                           elist);
+  return hipGetLastError();
+}
+
+hipError_t launch_pattern_positions(const int32_t* pair_s, const int32_t* pair_m, const int32_t* n_pairs,
+                                    int64_t cap, const int32_t* conn_s, const int32_t* conn_m, int32_t n_s_el,
+                                    const int32_t* pair_off, const int32_t* D_rowptr, const int32_t* D_col,
+                                    const int32_t* M_rowptr, const int32_t* M_col, int32_t* posD, int32_t* posM,
+                                    hipStream_t s) {
+  if (n_s_el > 0) {
+    k_positions<false><<<grid_of(n_s_el), BS, 0, s>>>(n_s_el, nullptr, nullptr, nullptr, pair_off, conn_s, nullptr,
+                                                      D_rowptr, D_col, posD, n_s_el);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (cap > 0)
+    k_positions<true><<<grid_of(cap), BS, 0, s>>>(cap, n_pairs, pair_s, pair_m, nullptr, conn_s, conn_m, M_rowptr,
+                                                  M_col, posM, cap);
   return hipGetLastError();
 }
 

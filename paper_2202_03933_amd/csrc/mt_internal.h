@@ -344,9 +344,15 @@ hipError_t launch_inc_sort(const int32_t* off, int32_t n_nodes, int32_t* list, h
 hipError_t launch_pattern_rows(bool fill, const int32_t* inc_off, const int32_t* inc_list, int32_t n_nodes,
                                const int32_t* pair_off, const int32_t* pair_m, const int32_t* conn_s,
                                const int32_t* conn_m, int32_t* D_cnt, int32_t* M_cnt, const int32_t* D_rowptr,
-                               const int32_t* M_rowptr, int32_t* D_col, int32_t* M_col, int32_t* keep, int32_t* posD,
-                               int32_t n_s_el, int32_t* posM, int64_t pstride, int32_t* ecnt, int32_t* elist,
-                               hipStream_t s);
+                               const int32_t* M_rowptr, int32_t* D_col, int32_t* M_col, int32_t* keep,
+                               int32_t n_s_el, int32_t* ecnt, int32_t* elist, hipStream_t s);
+// CSR positions of every local block entry (posD[(4 j + k) * n_s_el + e],
+// posM[(4 j + l) * cap + p]) from the filled column arrays.
+hipError_t launch_pattern_positions(const int32_t* pair_s, const int32_t* pair_m, const int32_t* n_pairs,
+                                    int64_t cap, const int32_t* conn_s, const int32_t* conn_m, int32_t n_s_el,
+                                    const int32_t* pair_off, const int32_t* D_rowptr, const int32_t* D_col,
+                                    const int32_t* M_rowptr, const int32_t* M_col, int32_t* posD, int32_t* posM,
+                                    hipStream_t s);
 hipError_t launch_elem_mlist(int32_t n_s_el, const int32_t* pair_off, const int32_t* pair_m, const int32_t* conn_m,
                              int32_t* ecnt, int32_t* elist, hipStream_t s);
 int pattern_keep_per_row();

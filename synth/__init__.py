@@ -17,6 +17,7 @@ from .meshes import (  # noqa: F401
     graded_flat,
     interface_config,
     opposing,
+    renumbered,
     batched_instances,
     CONFIG_NAMES,
 )

@@ -198,6 +198,26 @@ def opposing(itf):
                      meta=meta)
 
 
+def renumbered(itf, seed=7):
+    """The same interface with the nodes and elements of both sides in a
+    random order (each element keeps its own node cycle).  meta["new_of_old"]
+    holds, per side, the new index of every old node."""
+    rng = np.random.default_rng(seed)
+
+    def renum(mesh):
+        new_of_old = rng.permutation(mesh.n_nodes)
+        X = np.empty_like(mesh.X)
+        X[new_of_old] = mesh.X
+        conn = new_of_old[mesh.conn[rng.permutation(mesh.n_el)]]
+        return Mesh(X, np.ascontiguousarray(conn, dtype=np.int32)), new_of_old
+
+    s, ps = renum(itf.slave)
+    m, pm = renum(itf.master)
+    meta = dict(itf.meta)
+    meta["new_of_old"] = (ps, pm)
+    return Interface(s, m, itf.delta, name=itf.name + ", renumbered", meta=meta)
+
+
 def interface_config(k, scale=None, opposing_normals=False):
     """The workload of configuration k (0 flat, 1 cylinder, 2 wavy).
 

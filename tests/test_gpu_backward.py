@@ -324,3 +324,43 @@ def test_error_codes():
         MortarInterface(torch.from_numpy(itf.slave.X), torch.from_numpy(bad), torch.from_numpy(itf.master.X),
                         torch.from_numpy(itf.master.conn), device=dev)
     assert e.value.code == C.MT_EINVAL
+
+
+# Meshes numbered in random order (nodes and elements of both sides): the
+# forward matches the oracle on the renumbered meshes, and the gradients, with
+# each upstream weight attached to the same pair of original nodes, are those
+# of the original numbering up to the order of summation.  The rows a
+# workgroup of the CSR-position pass needs are then far apart, so it searches
+# them in global memory instead of a staged span.
+def test_renumbered_meshes_forward_and_gradients():
+    from synth.weights import keyed_normal, TAG_D, TAG_M, TAG_G
+    base = synth.interface_config(2, scale=53)
+    itf = synth.renumbered(base, seed=11)
+    g_new = gpu_run(itf)
+    assert_forward_parity(g_new, oracle.evaluate(itf, oracle_params(itf)))
+    g_old = gpu_run(base)
+    ps, pm = itf.meta["new_of_old"]
+    ident_s, ident_m = np.arange(base.slave.n_nodes), np.arange(base.master.n_nodes)
+    old_s, old_m = np.argsort(ps), np.argsort(pm)  # original index of each new node
+    dev = torch.device("cuda", 0)
+
+    def grads(run, os_, om_):
+        D, M = run["D"], run["M"]
+        Dr = np.repeat(np.arange(D.shape[0]), np.diff(D.indptr))
+        Mr = np.repeat(np.arange(M.shape[0]), np.diff(M.indptr))
+        idx = np.arange(D.shape[0])
+        W = (keyed_normal(5, TAG_D, os_[Dr], os_[D.indices]), keyed_normal(5, TAG_M, os_[Mr], om_[M.indices]),
+             keyed_normal(5, TAG_G, os_[idx], 0 * idx))
+        gs, gm = run["iface"].backward(*(torch.from_numpy(w).to(dev) for w in W))
+        torch.cuda.synchronize()
+        return gs.cpu().numpy(), gm.cpu().numpy()
+
+    gs_old, gm_old = grads(g_old, ident_s, ident_m)
+    gs_new, gm_new = grads(g_new, old_s, old_m)
+    assert np.abs(gs_new[:, ps] - gs_old).max() <= 1e-12 * np.abs(gs_old).max()
+    assert np.abs(gm_new[:, pm] - gm_old).max() <= 1e-12 * np.abs(gm_old).max()
+    # the values themselves, renumbered back
+    Dn, Mn = g_new["D"][ps][:, ps], g_new["M"][ps][:, pm]
+    assert abs(Dn - g_old["D"]).max() <= 1e-13 * abs(g_old["D"]).max()
+    assert abs(Mn - g_old["M"]).max() <= 1e-13 * abs(g_old["M"]).max()
+    np.testing.assert_allclose(g_new["g"][ps], g_old["g"], rtol=0, atol=1e-13 * np.abs(g_old["g"]).max())
