@@ -261,10 +261,16 @@ def bench_batched(reps=5):
     res["search_ms_per_interface_sync"] = timed(per_search_sync)
     res["search_ms_per_interface_nowait"] = timed(per_search_nowait)
     res["search_ms_batched"] = timed(lambda: b.search(rebuild=False))
+    # the same call captured into a HIP graph once (in the warm-up call) and
+    # replayed
+    res["search_ms_batched_graph"] = timed(lambda: b.search(use_graph=True, rebuild=False))
     b.search(rebuild=True)  # counts read back, batch built again for them
     assert sum(it.n_pairs for it in ifaces) == pairs
     res["search_speedup_vs_per_interface_sync"] = res["search_ms_per_interface_sync"] / res["search_ms_batched"]
+    res["search_speedup_graph_vs_per_interface_sync"] = (res["search_ms_per_interface_sync"]
+                                                         / res["search_ms_batched_graph"])
     res["search_pairs_per_s_batched"] = pairs / (res["search_ms_batched"] * 1e-3)
+    res["search_pairs_per_s_batched_graph"] = pairs / (res["search_ms_batched_graph"] * 1e-3)
     ab = {"forward": 0, "backward": 0, "search": 0}
     for it, itf in zip(ifaces, insts):
         a = algorithmic_bytes(itf.slave.n_nodes, itf.master.n_nodes, itf.slave.n_el, itf.master.n_el, it.n_cand,
@@ -285,7 +291,7 @@ def bench_batched(reps=5):
             # as the per-interface kernels) over each mode's wall time
             res[f"{k}_fp64_frac_{mode}"] = (fl / (res[f"{k}_ms_{mode}"] * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS
                                             if fl else None)
-    for mode in ("batched", "per_interface_sync"):
+    for mode in ("batched", "batched_graph", "per_interface_sync"):
         res["hbm"][f"search_{mode}"] = hbm_entry(ab["search"], res[f"search_ms_{mode}"])
     return res
 

@@ -449,10 +449,18 @@ int mt_batch_backward(mt_batch* b, const double* const* W_D, const double* const
  * per instance as after mt_build_pairs without read-back (mt_get_stats,
  * mt_check, mt_required_capacity); the pair counts may have changed, so
  * call mt_batch_workspace_size / mt_batch_build again before the next
- * mt_batch_forward / mt_batch_backward.  use_graph must be 0: capture of
- * this call into a HIP graph is not supported (MT_EUNSUPPORTED).  Errors:
- * MT_ESTATE (an instance with no workspace of its own bound: never built,
- * or built by mt_build_pairs_static), errors of the per-instance calls. */
+ * mt_batch_forward / mt_batch_backward.  With use_graph, the launches are
+ * captured into a HIP graph at the first such call and the graph is replayed
+ * by the next ones while `stream`, and each instance's workspace,
+ * capacities, parameters and mesh arrays (pointers and sizes), are those of
+ * the capture; otherwise it is captured again.  Coordinates moved in place
+ * are read by the replay.  In the graph no instance's pattern uses the
+ * instance's internal streams, so the pairs-by-master index is built by the
+ * first backward after it.  Errors: MT_EINVAL (use_graph on the null
+ * stream), MT_ESTATE (an instance with no workspace of its own bound: never
+ * built, or built by mt_build_pairs_static), MT_EHIP (capture or
+ * instantiation failed; the instances then hold no pair list), errors of the
+ * per-instance calls. */
 int mt_batch_search(mt_batch* b, int use_graph, void* stream);
 /* Autotune the tuning knobs on the current instances by timing candidate
  * settings of the forward launch; writes the choice to *out (host) and uses

@@ -91,8 +91,9 @@ class MortarBatch:
 
     def search(self, use_graph=False, rebuild=True):
         """mt_batch_search: the pair search and CSR pattern of every instance
-        in one call, on the batch's internal streams (use_graph: capture
-        into a HIP graph, refused by the library).  With rebuild, the
+        in one call, on the batch's internal streams (use_graph: captured
+        into a HIP graph once, replayed while the instances' workspaces,
+        capacities and mesh arrays are unchanged).  With rebuild, the
         instances' new counts are read back and the batch is built again for
         the new pair lists, with the same tuning."""
         cur = torch.cuda.current_stream(self.device)

@@ -771,7 +771,7 @@ int mt_csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, void* stream) {
 
 // The pattern, and with `blocks` the pair blocks of the coming integration
 // beside it.
-int mt::csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, hipStream_t st, bool blocks) {
+int mt::csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, hipStream_t st, bool blocks, bool fork) {
   if (!c) return fail(MT_EINVAL, "mt_csr_pattern: null ctx");
   if (!c->have_pairs) return fail(MT_ESTATE, "mt_csr_pattern: build the pair list first");
   if (int rc = ws_live(c)) return rc;
@@ -807,7 +807,8 @@ int mt::csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, hipStream_t st, b
   // the forward, the pattern passes, then the index (a chain of short sort
   // kernels, needed by the backward only), so that no pattern kernel waits
   // for the host to enqueue that chain behind the forward.
-  const bool aux = c->params.element_rule == 0 && c->poly_gen == c->coord_gen && !c->params.single_stream;
+  const bool aux =
+      fork && c->params.element_rule == 0 && c->poly_gen == c->coord_gen && !c->params.single_stream;
   if (aux) {
     if (!c->have_inc[1]) {
       int rc = build_incidence(c, M, c->minc_cnt, c->minc_off, c->minc_cur, c->minc_list, st);
@@ -1085,14 +1086,53 @@ int mt::ensure_aux(mt_ctx* c) {
 }
 
 // ---- search of many interfaces ------------------------------------------------
-int mt::search_no_wait(mt_ctx* c, hipStream_t st) {
+int mt::search_no_wait(mt_ctx* c, hipStream_t st, bool fork) {
   const bool timing = c->timing;
   c->timing = false;
   int rc = mt_build_pairs(c, &c->cap, c->ws, c->ws_bytes, nullptr, nullptr, st);
   // the batch's forward computes the pair blocks itself
-  if (rc == MT_OK) rc = csr_pattern(c, nullptr, nullptr, st, false);
+  if (rc == MT_OK) rc = csr_pattern(c, nullptr, nullptr, st, false, fork);
   c->timing = timing;
   return rc;
+}
+
+void mt::search_replayed(mt_ctx* c, hipStream_t st) {
+  // mt_build_pairs (same workspace binding, no read-back)
+  c->last_stream = st;
+  c->have_master_index = false;
+  c->counts_known = false;
+  ++c->coord_gen;
+  DeviceMesh& S = c->side[0];
+  if (c->params.normals == MT_NORMALS_NODAL) {  // recomputed by the graph
+    S.nrm = c->nrm_el.as<double>();
+    c->nrm_gen = c->coord_gen;
+  } else {
+    S.nrm = nullptr;
+  }
+  c->static_gen = 0;
+  c->mpoly_stride = c->cap.screened;
+  c->poly_gen = c->coord_gen;
+  c->have_pairs = true;
+  // mt_csr_pattern without the internal streams
+  c->have_pattern = true;
+  ++c->pattern_gen;
+}
+
+std::string mt::search_signature(const mt_ctx* c) {
+  std::string s;
+  auto add = [&s](const void* p, size_t n) { s.append(static_cast<const char*>(p), n); };
+  add(&c->device, sizeof(c->device));
+  add(&c->ws, sizeof(c->ws));
+  add(&c->ws_bytes, sizeof(c->ws_bytes));
+  add(&c->cap, sizeof(c->cap));
+  add(&c->params, sizeof(c->params));
+  for (const DeviceMesh& m : c->side) {
+    const void* ptrs[4] = {m.x, m.y, m.z, m.conn};
+    const int32_t n[2] = {m.n_nodes, m.n_el};
+    add(ptrs, sizeof(ptrs));
+    add(n, sizeof(n));
+  }
+  return s;
 }
 
 // ---- the build that allocates nothing ------------------------------------------

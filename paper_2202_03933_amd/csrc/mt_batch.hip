@@ -329,6 +329,11 @@ struct mt_batch {
   static constexpr int NSEARCH = 4;
   hipStream_t s_stream[NSEARCH] = {};
   hipEvent_t s_fork = nullptr, s_join[NSEARCH] = {};
+  // the search captured in a HIP graph: replayed while the capture stream
+  // and every instance's search signature are unchanged
+  hipGraphExec_t g_search = nullptr;
+  hipStream_t g_search_stream = nullptr;
+  std::vector<std::string> g_search_sig;
 };
 
 using namespace mt;
@@ -561,6 +566,7 @@ int mt_batch_destroy(mt_batch* b) {
   (void)hipSetDevice(b->device);
   (void)hipDeviceSynchronize();
   drop_graphs(b);
+  if (b->g_search) (void)hipGraphExecDestroy(b->g_search);
   for (int k = 0; k < mt_batch::NSEARCH; ++k) {
     if (b->s_stream[k]) (void)hipStreamDestroy(b->s_stream[k]);
     if (b->s_join[k]) (void)hipEventDestroy(b->s_join[k]);
@@ -801,12 +807,8 @@ int mt_batch_backward(mt_batch* b, const double* const* W_D, const double* const
 int mt_batch_search(mt_batch* b, int use_graph, void* stream) {
   if (!b) return bfail(MT_EINVAL, "mt_batch_search: null");
   if (b->ctxs.empty()) return bfail(MT_ESTATE, "mt_batch_search: no instances");
-  // A HIP-graph capture of this sequence (the caller's stream forked to the
-  // internal streams, each forking again to its instances' internal
-  // streams) ended the process with a segmentation fault inside the
-  // capturing call; the cause is not found, so capture is refused.
-  if (use_graph) return bfail(MT_EUNSUPPORTED, "mt_batch_search: graph capture is not supported");
   hipStream_t st = (hipStream_t)stream;
+  if (use_graph && st == nullptr) return bfail(MT_EINVAL, "mt_batch_search: graph capture needs a created stream");
   B_HIP(hipSetDevice(b->device));
   for (mt_ctx* c : b->ctxs) {
     if (!c->ws || c->static_gen != 0)
@@ -820,16 +822,64 @@ int mt_batch_search(mt_batch* b, int use_graph, void* stream) {
       B_HIP(hipEventCreateWithFlags(&b->s_join[k], hipEventDisableTiming));
     }
   }
-  B_HIP(hipEventRecord(b->s_fork, st));
-  for (int k = 0; k < mt_batch::NSEARCH; ++k) B_HIP(hipStreamWaitEvent(b->s_stream[k], b->s_fork, 0));
+  // Instances go round-robin onto the internal streams, forked from and
+  // joined back into st.  Eagerly, each instance's pattern may fork again to
+  // its own internal streams; in a graph it does not (one level of streams
+  // under the capture: a capture that forked again from the forked streams
+  // ended the process with a segmentation fault inside the capturing call).
+  auto search_all = [&](bool fork) -> int {
+    B_HIP(hipEventRecord(b->s_fork, st));
+    for (int k = 0; k < mt_batch::NSEARCH; ++k) B_HIP(hipStreamWaitEvent(b->s_stream[k], b->s_fork, 0));
+    int rc = MT_OK;
+    for (size_t i = 0; i < b->ctxs.size() && rc == MT_OK; ++i)
+      rc = search_no_wait(b->ctxs[i], b->s_stream[i % mt_batch::NSEARCH], fork);
+    // joined back also after an error, so that st orders after whatever was
+    // launched (and a capture ends on a joined graph)
+    for (int k = 0; k < mt_batch::NSEARCH; ++k) {
+      B_HIP(hipEventRecord(b->s_join[k], b->s_stream[k]));
+      B_HIP(hipStreamWaitEvent(st, b->s_join[k], 0));
+    }
+    return rc;
+  };
   int rc = MT_OK;
-  for (size_t i = 0; i < b->ctxs.size() && rc == MT_OK; ++i)
-    rc = search_no_wait(b->ctxs[i], b->s_stream[i % mt_batch::NSEARCH]);
-  // joined back also after an error, so that the caller's stream orders
-  // after whatever was launched
-  for (int k = 0; k < mt_batch::NSEARCH; ++k) {
-    B_HIP(hipEventRecord(b->s_join[k], b->s_stream[k]));
-    B_HIP(hipStreamWaitEvent(st, b->s_join[k], 0));
+  if (!use_graph) {
+    rc = search_all(true);
+  } else {
+    std::vector<std::string> sig;
+    sig.reserve(b->ctxs.size());
+    for (mt_ctx* c : b->ctxs) sig.push_back(search_signature(c));
+    if (b->g_search && (b->g_search_stream != st || sig != b->g_search_sig)) {
+      (void)hipGraphExecDestroy(b->g_search);
+      b->g_search = nullptr;
+    }
+    if (b->g_search) {
+      B_HIP(hipGraphLaunch(b->g_search, st));
+      for (mt_ctx* c : b->ctxs) search_replayed(c, st);
+    } else {
+      // the host side of every call runs once here, while the kernels are
+      // recorded; the graph launch below runs them
+      hipGraph_t g = nullptr;
+      B_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      rc = search_all(false);
+      const hipError_t e = hipStreamEndCapture(st, &g);
+      if (rc == MT_OK && e != hipSuccess) rc = bfail(MT_EHIP, "mt_batch_search: hipStreamEndCapture failed");
+      if (rc == MT_OK) {
+        const hipError_t ei = hipGraphInstantiate(&b->g_search, g, nullptr, nullptr, 0);
+        if (ei != hipSuccess) {
+          b->g_search = nullptr;
+          rc = bfail(MT_EHIP, "mt_batch_search: hipGraphInstantiate failed");
+        }
+      }
+      if (g) (void)hipGraphDestroy(g);
+      if (rc == MT_OK) {
+        b->g_search_stream = st;
+        b->g_search_sig = std::move(sig);
+        B_HIP(hipGraphLaunch(b->g_search, st));
+      } else {
+        // nothing ran: the instances hold no valid pair list
+        for (mt_ctx* c : b->ctxs) c->have_pairs = c->have_pattern = false;
+      }
+    }
   }
   // read-backs of the instances' counts wait on the caller's stream
   for (mt_ctx* c : b->ctxs) c->last_stream = st;

@@ -427,11 +427,20 @@ int ws_live(mt_ctx* c);
 
 // ---- search of many interfaces (mt_batch_search) ------------------------------
 // mt_build_pairs into the bound workspace and capacities, then mt_csr_pattern,
-// without read-back (and without phase timers) on stream st.
-int search_no_wait(mt_ctx* c, hipStream_t st);
+// without read-back (and without phase timers) on stream st; without `fork`
+// every kernel on st (none on the context's internal streams; the
+// pairs-by-master index is then built by the first backward).
+int search_no_wait(mt_ctx* c, hipStream_t st, bool fork = true);
+// The host side of search_no_wait(c, st, false) for a replay of a graph
+// captured from it: the flags and generations that call sets.
+void search_replayed(mt_ctx* c, hipStream_t st);
+// What a captured search_no_wait(c, st, false) depends on besides device
+// memory contents: workspace, capacities, parameters, mesh arrays.
+std::string search_signature(const mt_ctx* c);
 // mt_csr_pattern on stream st; without `blocks` the pair blocks of the coming
-// integration are not computed beside it (a batch computes its own).
-int csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, hipStream_t st, bool blocks);
+// integration are not computed beside it (a batch computes its own); without
+// `fork` nothing runs on the internal streams.
+int csr_pattern(mt_ctx* c, int64_t* nnz_D, int64_t* nnz_M, hipStream_t st, bool blocks, bool fork = true);
 // The context's internal streams and their events, created on first use.
 int ensure_aux(mt_ctx* c);
 

@@ -180,14 +180,11 @@ def _moved(itf, step):
 
 
 # The search of all instances in one call (Alg. 1 and 2 per instance, then
-# the pattern) while the instances move: candidates, pairs, patterns and the
-# batched forward and backward after it bitwise equal to fresh per-interface
-# builds at the moved coordinates.
-@pytest.mark.parametrize("use_graph", [
-    pytest.param(True, marks=pytest.mark.skip(
-        reason="HIP-graph capture of the batched search ended the process with a segmentation fault inside "
-               "the capturing call; cause not found, capture switched off in the library")),
-    False])
+# the pattern) while the instances move, eagerly and as a HIP graph captured
+# at the first step and replayed at the next two: candidates, pairs, patterns
+# and the batched forward and backward after it bitwise equal to fresh
+# per-interface builds at the moved coordinates.
+@pytest.mark.parametrize("use_graph", [True, False])
 def test_batch_search_moving_instances(use_graph):
     from paper_2202_03933_amd import MortarBatch
     instances = synth.batched_instances(n_inst=12, max_side=48)
@@ -217,10 +214,39 @@ def test_batch_search_moving_instances(use_graph):
         assert all(equal_outs(x, r) for x, r in zip(g, ref_g)), step
 
 
-def test_batch_search_graph_capture_refused():
-    from paper_2202_03933_amd import MortarBatch, MortarError
-    from paper_2202_03933_amd import _capi as C
-    b = MortarBatch(make_ifaces(synth.batched_instances(n_inst=2, max_side=20)))
-    with pytest.raises(MortarError) as e:
-        b.search(use_graph=True)
-    assert e.value.code == C.MT_EUNSUPPORTED
+def _assert_same_search(ifaces, refs):
+    for it, ref in zip(ifaces, refs):
+        assert (it.n_cand, it.n_pairs, it.nnz_D, it.nnz_M) == (ref.n_cand, ref.n_pairs, ref.nnz_D, ref.nnz_M)
+        for x, y in zip(it.candidates() + it.pairs(), ref.candidates() + ref.pairs()):
+            assert torch.equal(x, y)
+        for x, y in zip((it.D_rowptr, it.D_col, it.M_rowptr, it.M_col),
+                        (ref.D_rowptr, ref.D_col, ref.M_rowptr, ref.M_col)):
+            assert torch.equal(x, y)
+
+
+# The captured search is replayed only while what it was captured from holds:
+# an instance bound to other capacities (a new workspace layout) makes the
+# next graph search capture again, with the same results as fresh builds;
+# the eager search in between leaves the graph alone.
+def test_batch_search_graph_recaptured_after_rebind():
+    from paper_2202_03933_amd import MortarBatch
+    instances = synth.batched_instances(n_inst=6, max_side=40)
+    ifaces = make_ifaces(instances)
+    b = MortarBatch(ifaces)
+    b.search(use_graph=True)
+    _assert_same_search(ifaces, make_ifaces(instances))
+    it0 = ifaces[0]
+    it0.set_capacity(pairs=it0.capacity.pairs + 4096)
+    it0.build_pairs()
+    for step in range(3):  # graph (captured again), eager, graph (replayed)
+        moved = [_moved(itf, step) for itf in instances]
+        print(f"[gpu] graph search after a rebind, step {step}", flush=True)
+        for it, itf in zip(ifaces, moved):
+            it.move_coordinates(itf.slave.X, itf.master.X)
+        b.search(use_graph=step != 1)
+        refs = make_ifaces(moved)
+        _assert_same_search(ifaces, refs)
+        outs = b.forward()
+        ref_out = [tuple(t.clone() for t in r.integrate()) for r in refs]
+        torch.cuda.synchronize()
+        assert all(equal_outs(o, r) for o, r in zip(outs, ref_out)), step
