@@ -595,6 +595,8 @@ def main():
     iface.check()
     st = iface.stats()
     assert st["n_pairs"] == n_pairs
+    # device memory of the interface (before the legs below allocate their own)
+    mem_gb = (free0 - torch.cuda.mem_get_info(dev)[0]) / 2**30
     # the same step on a context that runs every kernel on the caller's
     # stream (single_stream): what the library's internal concurrency buys,
     # and each phase's time alone
@@ -602,7 +604,6 @@ def main():
     if not args.no_single_stream:
         single = bench_variant(itf, (wD, wM, wg), args.steps, args.warmup, sync=False, single_stream=1)
     ms_step = min(ms_graph, ms_async, ms_fused, single["ms_per_step"] if single else float("inf"))
-    mem_gb = (free0 - torch.cuda.mem_get_info(dev)[0]) / 2**30
 
     if args.calib_copy:
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
