@@ -250,3 +250,10 @@ def test_batch_search_graph_recaptured_after_rebind():
         ref_out = [tuple(t.clone() for t in r.integrate()) for r in refs]
         torch.cuda.synchronize()
         assert all(equal_outs(o, r) for o, r in zip(outs, ref_out)), step
+        # an instance's own calls after the batched search: its host state
+        # (pair list, pattern, generations) is that of a search call
+        W = weights_for(refs[1], 4200 + step)
+        own = tuple(t.clone() for t in ifaces[1].integrate()) + tuple(t.clone() for t in ifaces[1].backward(*W))
+        ref = tuple(t.clone() for t in refs[1].integrate()) + tuple(t.clone() for t in refs[1].backward(*W))
+        torch.cuda.synchronize()
+        assert equal_outs(own, ref), step
