@@ -633,19 +633,22 @@ int mt_build_pairs(mt_ctx* c, const mt_capacity* cap_in, void* ws, size_t ws_byt
     double* part = c->prep_part.as<double>();
     MT_HIP(launch_prep(S, true, c->box_s.as<double>(), c->sdata.as<double>(), nullptr, part, st));
     MT_HIP(launch_prep(M, false, c->box_m.as<double>(), nullptr, c->mdata.as<double>(), part + 9 * (size_t)nb_s, st));
-    MT_HIP(launch_prep_reduce(part, nb_s, nb_m, red, st));
-    MT_HIP(launch_grid(red, c->params.delta, c->params.bin_size, cap.cells, dst, st));
+    MT_HIP(launch_prep_reduce(part, nb_s, nb_m, red, c->params.delta, c->params.bin_size, cap.cells, dst, st));
   }
   const Grid* g = &dst->grid;
   {
     // master elements sorted by cell, cell ranges from segment heads
     PhaseTimer t(c, MT_T_BIN_SORT, st);
-    MT_HIP(launch_master_keys(c->box_m.as<double>(), nm, g, c->keys.as<uint32_t>(), c->vals.as<uint32_t>(), st));
     int bits = 1;
     while ((int64_t(1) << bits) < cap.cells) ++bits;
+    // keys written where an odd number of sort passes starts, so that the
+    // sorted pairs end in (keys, vals) without a copy
+    const bool in_tmp = radix_passes(bits) % 2 == 1;
+    MT_HIP(launch_master_keys(c->box_m.as<double>(), nm, g, cap.cells,
+                              (in_tmp ? c->keys_tmp : c->keys).as<uint32_t>(),
+                              (in_tmp ? c->vals_tmp : c->vals).as<uint32_t>(), c->cell_range.as<int2>(), st));
     MT_HIP(radix_sort_pairs(c->keys.as<uint32_t>(), c->vals.as<uint32_t>(), c->keys_tmp.as<uint32_t>(),
-                            c->vals_tmp.as<uint32_t>(), nm, nullptr, bits, c->sort_hist, c->scan_tmp, st));
-    MT_HIP(launch_clear_cells(c->cell_range.as<int2>(), g, cap.cells, st));
+                            c->vals_tmp.as<uint32_t>(), nm, nullptr, bits, c->sort_hist, c->scan_tmp, st, in_tmp));
     MT_HIP(launch_cell_ranges(c->keys.as<uint32_t>(), c->vals.as<uint32_t>(), nm, c->box_m.as<double>(), g,
                               c->cell_range.as<int2>(), c->sbox.as<double>(), c->qbox.as<uint64_t>(), st));
   }

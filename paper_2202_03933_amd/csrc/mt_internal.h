@@ -265,8 +265,13 @@ int64_t radix_hist_elems(int64_t n);
 // Stable LSD radix sort of (key, value) pairs on key bits [0, bits).
 // Results end in (keys, vals); (keys_tmp, vals_tmp) are scratch of size n.
 // With n_dev, only the first *n_dev <= n pairs are sorted.
+// in_tmp: the input is in (keys_tmp, vals_tmp) instead (then an odd number
+// of passes ends in (keys, vals) without a copy).
 hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp, int64_t n,
-                            const int32_t* n_dev, int bits, const Buf& hist, const Buf& scan_tmp, hipStream_t s);
+                            const int32_t* n_dev, int bits, const Buf& hist, const Buf& scan_tmp, hipStream_t s,
+                            bool in_tmp = false);
+// Passes of radix_sort_pairs for `bits` key bits.
+inline int radix_passes(int bits) { return (bits + 7) / 8; }
 hipError_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 hipError_t fill_f64(double* p, double v, int64_t n, hipStream_t s);
 
@@ -276,14 +281,14 @@ hipError_t fill_f64(double* p, double v, int64_t n, hipStream_t s);
 int prep_blocks(int32_t n_el);
 hipError_t launch_prep(const DeviceMesh& m, bool slave, double* box, double* sd, double* md, double* part,
                        hipStream_t s);
-hipError_t launch_prep_reduce(const double* part, int nb_s, int nb_m, PrepReduce* red, hipStream_t s);
-// The search grid (st->grid) from the reductions, at most max_cells cells;
-// flags non-finite coordinates.
-hipError_t launch_grid(const PrepReduce* red, double delta, double bin_size, int64_t max_cells, DevState* st,
-                       hipStream_t s);
-hipError_t launch_master_keys(const double* box_m, int32_t n_m, const Grid* g, uint32_t* keys, uint32_t* vals,
-                              hipStream_t s);
-hipError_t launch_clear_cells(int2* range, const Grid* g, int64_t max_cells, hipStream_t s);
+// The reductions of both sides, then the search grid (st->grid) from them,
+// at most max_cells cells; flags non-finite coordinates.
+hipError_t launch_prep_reduce(const double* part, int nb_s, int nb_m, PrepReduce* red, double delta,
+                              double bin_size, int64_t max_cells, DevState* st, hipStream_t s);
+// Master keys and values for the bin sort; the cell table cleared in the
+// same launch.
+hipError_t launch_master_keys(const double* box_m, int32_t n_m, const Grid* g, int64_t max_cells, uint32_t* keys,
+                              uint32_t* vals, int2* range, hipStream_t s);
 hipError_t launch_cell_ranges(const uint32_t* keys, const uint32_t* vals, int32_t n, const double* box_m,
                               const Grid* g, int2* range, double* sbox, uint64_t* qbox, hipStream_t s);
 hipError_t launch_cand_count(const double* box_s, int32_t n_s, const double* sbox, const uint64_t* qbox,

@@ -336,15 +336,32 @@ hipError_t scan_exclusive_dev(const int32_t* in, int32_t* out, const int32_t* n_
 int64_t radix_hist_elems(int64_t n) { return 2 * ((n + RS_TILE - 1) / RS_TILE) * RS_RADIX + 1; }
 
 hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, uint32_t* vals_tmp, int64_t n,
-                            const int32_t* n_dev, int bits, const Buf& hist, const Buf& scan_tmp, hipStream_t s) {
-  if (n <= 1 || bits <= 0) return hipSuccess;
+                            const int32_t* n_dev, int bits, const Buf& hist, const Buf& scan_tmp, hipStream_t s,
+                            bool in_tmp) {
+  if (in_tmp) {
+    std::swap(keys, keys_tmp);
+    std::swap(vals, vals_tmp);
+  }
+  // from here the input is in (keys, vals); the result goes to (keys, vals)
+  // of the caller: the other pair when in_tmp
+  uint32_t* const out_k = in_tmp ? keys_tmp : keys;
+  uint32_t* const out_v = in_tmp ? vals_tmp : vals;
+  if (n <= 1 || bits <= 0) {  // no pass: the input is the result
+    if (in_tmp && n > 0) {
+      const unsigned nb = (unsigned)((n + 255) / 256);
+      k_copy_u32<<<nb, 256, 0, s>>>(keys, out_k, n, n_dev);
+      k_copy_u32<<<nb, 256, 0, s>>>(vals, out_v, n, n_dev);
+      return hipGetLastError();
+    }
+    return hipSuccess;
+  }
   const int64_t tiles = (n + RS_TILE - 1) / RS_TILE;
   const int64_t hn = tiles * RS_RADIX;
   if ((int64_t)(hist.bytes / sizeof(int32_t)) < radix_hist_elems(n)) return hipErrorInvalidValue;
   int32_t* h = hist.as<int32_t>();
   int32_t* off = h + hn;
   hipError_t e;
-  int passes = (bits + 7) / 8;
+  const int passes = radix_passes(bits);
   uint32_t *ki = keys, *vi = vals, *ko = keys_tmp, *vo = vals_tmp;
   for (int p = 0; p < passes; ++p) {
     k_rs_hist<<<(unsigned)tiles, RS_BS, 0, s>>>(ki, n, n_dev, 8 * p, h, tiles);
@@ -355,10 +372,10 @@ hipError_t radix_sort_pairs(uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp, 
     std::swap(ki, ko);
     std::swap(vi, vo);
   }
-  if (ki != keys) {
+  if (ki != out_k) {
     const unsigned nb = (unsigned)((n + 255) / 256);
-    k_copy_u32<<<nb, 256, 0, s>>>(ki, keys, n, n_dev);
-    k_copy_u32<<<nb, 256, 0, s>>>(vi, vals, n, n_dev);
+    k_copy_u32<<<nb, 256, 0, s>>>(ki, out_k, n, n_dev);
+    k_copy_u32<<<nb, 256, 0, s>>>(vi, out_v, n, n_dev);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   return hipSuccess;

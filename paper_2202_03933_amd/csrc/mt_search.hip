@@ -135,10 +135,15 @@ __global__ __launch_bounds__(BS) void k_prep(const double* __restrict__ x, const
   if (threadIdx.x == 8) part[(int64_t)blockIdx.x * PREP_PART + 8] = (double)bad;
 }
 
+__device__ void grid_from(const PrepReduce* __restrict__ red, double delta, double bin_size, int64_t max_cells,
+                          DevState* st);
+
 // Final reduction of the per-block partials of both sides (nb_s slave
-// blocks first, then nb_m master blocks) into the grid quantities.
+// blocks first, then nb_m master blocks) into the grid quantities, then the
+// search grid from them (grid_from, by the same thread).
 __global__ __launch_bounds__(BS) void k_prep_reduce(const double* __restrict__ part, int nb_s, int nb_m,
-                                                     PrepReduce* red) {
+                                                     PrepReduce* red, double delta, double bin_size,
+                                                     int64_t max_cells, DevState* st) {
   __shared__ double sh[BS / 64][PREP_PART];
   double v[PREP_PART];
 #pragma unroll
@@ -179,6 +184,7 @@ __global__ __launch_bounds__(BS) void k_prep_reduce(const double* __restrict__ p
     }
     red->bad_index = sbits;
     red->pad = 0;
+    grid_from(red, delta, bin_size, max_cells, st);
   }
 }
 
@@ -191,7 +197,6 @@ __device__ __forceinline__ int cell_coord(double c, double lo, double inv_beta, 
   return (int)t;
 }
 
-// Search grid from the element reductions (one thread): the minimal bin size
 // ---- box prefilter ------------------------------------------------------------
 // The candidate test compares (slave lo - delta) with master hi and master lo
 // with (slave hi + delta) on each axis.  Master box bounds are stored as
@@ -265,14 +270,14 @@ __device__ __forceinline__ QSlave q_slave(const Grid& g, const double lo[3], con
   return t;
 }
 
+// Search grid from the element reductions (one thread):
 // beta_min = max(longest slave edge, largest box extent + delta, bin_size)
 // (the paper's rule without a motion term, raised so that 27 cells are
 // complete), the node bounding box expanded by beta_min, max(1, floor(L /
 // beta_min)) cells per axis, the dense cell table coarsened to at most
 // max_cells cells (coarser cells stay complete).
-__global__ void k_grid(const PrepReduce* __restrict__ red, double delta, double bin_size, int64_t max_cells,
-                       DevState* st) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ void grid_from(const PrepReduce* __restrict__ red, double delta, double bin_size, int64_t max_cells,
+                          DevState* st) {
   const double emax = __longlong_as_double((long long)red->emax_bits);
   const double edge = __longlong_as_double((long long)red->edge_bits);
   double beta_min = fmax(fmax(edge, emax + delta), bin_size) * (1.0 + 0x1p-20);
@@ -318,17 +323,15 @@ __global__ void k_grid(const PrepReduce* __restrict__ red, double delta, double 
   if (red->bad_index & 2) st->flags |= DS_NONFINITE;
 }
 
-// Empty cells hold the range (0, 0): the cell table is cleared over the
-// grid's cells (grid-stride), so no memset node enters a captured graph.
-__global__ __launch_bounds__(BS) void k_clear_cells(int2* __restrict__ range, const Grid* __restrict__ gp) {
+
+// Master keys (cell of each master box centre, master index as value); the
+// same launch clears the cell table over the grid's cells (grid-stride).
+__global__ __launch_bounds__(BS) void k_master_keys(const double* __restrict__ box, int32_t n,
+                                                     const Grid* __restrict__ gp, uint32_t* __restrict__ keys,
+                                                     uint32_t* __restrict__ vals, int2* __restrict__ range) {
   const int64_t nc = gp->ncells;
   for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < nc; i += (int64_t)gridDim.x * BS)
     range[i] = make_int2(0, 0);
-}
-
-__global__ __launch_bounds__(BS) void k_master_keys(const double* __restrict__ box, int32_t n,
-                                                     const Grid* __restrict__ gp, uint32_t* __restrict__ keys,
-                                                     uint32_t* __restrict__ vals) {
   const int m = blockIdx.x * BS + threadIdx.x;
   if (m >= n) return;
   const Grid g = *gp;
@@ -734,27 +737,16 @@ hipError_t launch_prep(const DeviceMesh& m, bool slave, double* box, double* sd,
   return hipGetLastError();
 }
 
-hipError_t launch_prep_reduce(const double* part, int nb_s, int nb_m, PrepReduce* red, hipStream_t s) {
-  k_prep_reduce<<<1, BS, 0, s>>>(part, nb_s, nb_m, red);
+hipError_t launch_prep_reduce(const double* part, int nb_s, int nb_m, PrepReduce* red, double delta,
+                              double bin_size, int64_t max_cells, DevState* st, hipStream_t s) {
+  k_prep_reduce<<<1, BS, 0, s>>>(part, nb_s, nb_m, red, delta, bin_size, max_cells, st);
   return hipGetLastError();
 }
 
-hipError_t launch_grid(const PrepReduce* red, double delta, double bin_size, int64_t max_cells, DevState* st,
-                       hipStream_t s) {
-  k_grid<<<1, 64, 0, s>>>(red, delta, bin_size, max_cells, st);
-  return hipGetLastError();
-}
-
-hipError_t launch_master_keys(const double* box_m, int32_t n_m, const Grid* g, uint32_t* keys, uint32_t* vals,
-                              hipStream_t s) {
-  if (n_m == 0) return hipSuccess;
-  k_master_keys<<<(n_m + BS - 1) / BS, BS, 0, s>>>(box_m, n_m, g, keys, vals);
-  return hipGetLastError();
-}
-
-hipError_t launch_clear_cells(int2* range, const Grid* g, int64_t max_cells, hipStream_t s) {
-  const unsigned nb = (unsigned)std::min<int64_t>(2048, (max_cells + BS - 1) / BS);
-  k_clear_cells<<<nb, BS, 0, s>>>(range, g);
+hipError_t launch_master_keys(const double* box_m, int32_t n_m, const Grid* g, int64_t max_cells, uint32_t* keys,
+                              uint32_t* vals, int2* range, hipStream_t s) {
+  const int64_t nb = std::max<int64_t>((n_m + BS - 1) / BS, std::min<int64_t>(2048, (max_cells + BS - 1) / BS));
+  k_master_keys<<<(unsigned)std::max<int64_t>(nb, 1), BS, 0, s>>>(box_m, n_m, g, keys, vals, range);
   return hipGetLastError();
 }
 
