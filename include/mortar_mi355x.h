@@ -444,7 +444,7 @@ int mt_batch_backward(mt_batch* b, const double* const* W_D, const double* const
  * bound, then mt_csr_pattern (without the pair blocks it computes beside
  * the pattern for the next mt_integrate: the batched forward computes its
  * own), neither reading anything back, the instances
- * spread round-robin over four internal streams that are ordered after
+ * spread round-robin over eight internal streams that are ordered after
  * `stream` on entry and before it on exit.  Counts and device-side status
  * per instance as after mt_build_pairs without read-back (mt_get_stats,
  * mt_check, mt_required_capacity); the pair counts may have changed, so

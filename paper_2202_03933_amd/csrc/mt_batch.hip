@@ -324,9 +324,9 @@ struct mt_batch {
   int64_t max_pitems = 0;  // pair items the workspace holds (buckets of at least MIN_BUCKET pairs)
   hipGraphExec_t g_fwd = nullptr, g_bwd = nullptr;
   hipStream_t g_fwd_stream = nullptr, g_bwd_stream = nullptr;
-  // the search of all instances (mt_batch_search): instances go round-robin
-  // onto internal streams forked from and joined back into the caller's
-  static constexpr int NSEARCH = 4;
+  // the search of all instances (mt_batch_search): instances spread over
+  // internal streams forked from and joined back into the caller's
+  static constexpr int NSEARCH = 8;
   hipStream_t s_stream[NSEARCH] = {};
   hipEvent_t s_fork = nullptr, s_join[NSEARCH] = {};
   // the search captured in a HIP graph: replayed while the capture stream
