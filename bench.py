@@ -589,6 +589,18 @@ def main():
     del graph
     ms_fused = wall(lambda: step_fused(False), args.steps)
     iface.check()
+    # the same step with mt_integrate_backward, captured once and replayed
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step_fused(False)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        step_fused(False)
+    ms_fused_graph = wall(graph.replay, args.steps)
+    iface.check()
+    del graph
     # forward path alone (search + pattern + forward), no timers
     fwd_ms = wall(lambda: (iface.build_pairs(sync=False), iface.csr_pattern(sync=False), iface.integrate(outs)),
                   args.steps)
@@ -603,7 +615,7 @@ def main():
     single = None
     if not args.no_single_stream:
         single = bench_variant(itf, (wD, wM, wg), args.steps, args.warmup, sync=False, single_stream=1)
-    ms_step = min(ms_graph, ms_async, ms_fused, single["ms_per_step"] if single else float("inf"))
+    ms_step = min(ms_graph, ms_async, ms_fused, ms_fused_graph, single["ms_per_step"] if single else float("inf"))
 
     if args.calib_copy:
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
@@ -675,14 +687,14 @@ def main():
                                "normal offsets U[-1e-3,1e-3], delta 1.25e-3: search + forward + backward per step",
                    "n_pairs": n_pairs, "n_candidates": n_cand, "nnz_D": iface.nnz_D, "nnz_M": iface.nnz_M},
         "step_modes_ms": {"graph_replay": ms_graph, "async": ms_async, "sync_counts": ms_sync,
-                          "fused_async": ms_fused,
+                          "fused_async": ms_fused, "fused_graph_replay": ms_fused_graph,
                           "single_stream_async": single["ms_per_step"] if single else None},
         "single_stream_phase_ms_per_step": single["phase_ms_per_step"] if single else None,
         "step_note": "value: the fastest of the eager no-wait step, its graph replay, the eager step with "
                      "mt_integrate_backward in place of mt_integrate + mt_backward (the same outputs bit for bit; "
-                     "the assembly beside the reverse sweep), and the eager step on a context with every kernel "
-                     "on the caller's stream (single_stream); inputs resident, every phase recomputed; "
-                     "sync_counts reads the counts back in every call",
+                     "the assembly beside the reverse sweep) and its graph replay, and the eager step on a context "
+                     "with every kernel on the caller's stream (single_stream); inputs resident, every phase "
+                     "recomputed; sync_counts reads the counts back in every call",
         "fwd_pairs_per_s": n_pairs / (fwd_ms * 1e-3),
         "fwd_ms_per_step": fwd_ms,
         "phase_ms_per_step": per_step,

@@ -101,7 +101,18 @@ def _step(it, W, out, gout):
     it.backward(*W, out=gout)
 
 
-def test_graph_captured_whole_step_wavy1024():
+def _step_fused(it, W, out, gout):
+    it.build_pairs(sync=False)
+    it.csr_pattern(sync=False)
+    it.integrate_backward(*W, out=out, grad_out=gout)
+
+
+# The whole step captured into one HIP graph, with mt_integrate +
+# mt_backward or with mt_integrate_backward (the assembly beside the reverse
+# sweep on the library's internal stream, joined into the capture).
+@pytest.mark.parametrize("fused", [False, True])
+def test_graph_captured_whole_step_wavy1024(fused):
+    step = _step_fused if fused else _step
     itf = synth.interface_config(2)
     dev = torch.device("cuda", 0)
     Xs = torch.from_numpy(itf.slave.X).to(dev)
@@ -115,13 +126,13 @@ def test_graph_captured_whole_step_wavy1024():
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
-        _step(it, W, out, gout)  # warm-up on the capture stream
+        step(it, W, out, gout)  # warm-up on the capture stream
     torch.cuda.current_stream().wait_stream(s)
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=s):
-        _step(it, W, out, gout)
-    print("[gpu] captured; replaying", flush=True)
+        step(it, W, out, gout)
+    print(f"[gpu] captured (fused={fused}); replaying", flush=True)
     for rep in range(3):
         for t in out + gout:
             t.fill_(float("nan"))
