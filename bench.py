@@ -661,6 +661,14 @@ def main():
     roof = roofline(dominant)
     others = {KERNELS[k][0]: roofline(k) for k in ("pair_poly", "pair_fwd", "pair_bwd")
               if k != dominant and per_launch.get(k)}
+    # the forward's launch time above is taken beside the pattern kernels (on
+    # the internal stream); its time alone comes from the single-stream leg
+    fwd_alone = single["phase_ms_per_step"].get("pair_fwd") if single else None
+    if fwd_alone and others.get("k_pair_fwd") and others["k_pair_fwd"].get("achieved"):
+        e = others["k_pair_fwd"]
+        executed = e["executed_flops_per_pair"] * n_pairs
+        e["alone"] = {"launch_ms": fwd_alone, "achieved": executed / (fwd_alone * 1e-3) / 1e12,
+                      "frac": executed / (fwd_alone * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS}
     ab = algorithmic_bytes(itf.slave.n_nodes, itf.master.n_nodes, itf.slave.n_el, itf.master.n_el, n_cand, n_pairs,
                            iface.nnz_D, iface.nnz_M)
     search_ms = sum(per_step.get(k, 0.0) for k in ("prep", "bin_sort", "cand", "clip", "compact"))
