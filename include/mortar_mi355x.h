@@ -453,7 +453,8 @@ int mt_batch_backward(mt_batch* b, const double* const* W_D, const double* const
  * captured into a HIP graph at the first such call and the graph is replayed
  * by the next ones while `stream`, and each instance's workspace,
  * capacities, parameters and mesh arrays (pointers and sizes), are those of
- * the capture; otherwise it is captured again.  Coordinates moved in place
+ * the capture and no instance was uploaded since; otherwise it is captured
+ * again.  Coordinates moved in place
  * are read by the replay.  In the graph no instance's pattern uses the
  * instance's internal streams, so the pairs-by-master index is built by the
  * first backward after it.  Errors: MT_EINVAL (use_graph on the null

@@ -517,6 +517,7 @@ int mt_upload(mt_ctx* c, int side, int64_t n_nodes, const double* x, const doubl
   DeviceMesh& m = c->side[side];
   m.set = false;
   c->have_inc[side] = false;
+  ++c->upload_gen;
   c->have_pairs = c->have_pattern = c->have_master_index = false;
   ++c->coord_gen;
   if (n_el > 0) {
@@ -1129,6 +1130,9 @@ std::string mt::search_signature(const mt_ctx* c) {
   add(&c->ws_bytes, sizeof(c->ws_bytes));
   add(&c->cap, sizeof(c->cap));
   add(&c->params, sizeof(c->params));
+  // a new upload may bring other connectivity at the same addresses, and
+  // the graph does not rebuild node incidences it found built
+  add(&c->upload_gen, sizeof(c->upload_gen));
   for (const DeviceMesh& m : c->side) {
     const void* ptrs[4] = {m.x, m.y, m.z, m.conn};
     const int32_t n[2] = {m.n_nodes, m.n_el};

@@ -212,6 +212,7 @@ struct mt_ctx {
   mt::Buf pair_slot;       // int32 [pair capacity] entry of each pair's polygon in the mpoly buffers
   int64_t coord_gen = 0, poly_gen = -1;
   int64_t pattern_gen = 0;  // counts completed mt_csr_pattern calls
+  int64_t upload_gen = 0;   // counts mt_upload calls (connectivity possibly new)
   // forward / backward staging
   mt::Buf nrm_node;        // [n_s_nodes][4] nodal normals (continuous normal field)
   mt::Buf nrm_el;          // [n_s_el][4] element plane normals
@@ -440,7 +441,7 @@ int search_no_wait(mt_ctx* c, hipStream_t st, bool fork = true);
 // captured from it: the flags and generations that call sets.
 void search_replayed(mt_ctx* c, hipStream_t st);
 // What a captured search_no_wait(c, st, false) depends on besides device
-// memory contents: workspace, capacities, parameters, mesh arrays.
+// memory contents: workspace, capacities, parameters, mesh arrays, uploads.
 std::string search_signature(const mt_ctx* c);
 // mt_csr_pattern on stream st; without `blocks` the pair blocks of the coming
 // integration are not computed beside it (a batch computes its own); without
