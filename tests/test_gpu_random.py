@@ -1,9 +1,14 @@
 """GPU parity with the oracle on randomly drawn interfaces: wavy surfaces of
 random amplitude and resolution ratio (slave finer or coarser than master),
 master nodes moved off the surface, master orientation reversed at random,
-and the whole interface in a random position and orientation in space.
-Candidates, pairs, vertex counts and patterns bit-exact; D, M, gap and the
-gradients within TOL."""
+and the whole interface in a random position and orientation in space; in
+the default mode and with the dual basis, the continuous normal field and
+the 3-point rule.
+Candidates, pairs, vertex counts and patterns bit-exact; D, M and gap within
+TOL; the gradients within TOL, or within ten times the oracle's own change
+under a translation where a draw is that sensitive to rounding."""
+
+import math
 
 import numpy as np
 import pytest
@@ -18,8 +23,15 @@ pytestmark = pytest.mark.gpu
 
 def random_interface(seed):
     rng = np.random.default_rng(9000 + seed)
+    # resolutions at least 10% apart and without a common factor: grid lines
+    # of both sides at the same parameter put slave and master edges almost
+    # on one line in the projection, where a clip crossing, and with it the
+    # gradient, is ill-conditioned (per-pair gradients up to 1e3 that cancel
+    # in the sums), as for the tied configuration
     ns = int(rng.integers(6, 41))
     nm = int(rng.integers(5, 41))
+    while abs(ns / nm - 1.0) < 0.1 or math.gcd(ns, nm) != 1:
+        nm = int(rng.integers(5, 41))
     amp = float(rng.uniform(0.0, 0.08))
     itf = synth.wavy(ns, nm, seed=9100 + seed, amp=amp)
     if rng.random() < 0.5:
@@ -36,17 +48,46 @@ def random_interface(seed):
                      name=f"random {seed}: {itf.name}, amp {amp:.3f}", meta=itf.meta)
 
 
-@pytest.mark.parametrize("seed", range(6))
+def oracle_gradients(itf, prm, o, seed):
+    """The oracle's gradient, with the chain through the nodal normal field
+    (element normal gradients to the slave coordinates) when it is on."""
+    ps, pm = o["pair_s"], o["pair_m"]
+    w = oracle.pair_weights(itf.slave, itf.master, ps, pm, *weight_fns(seed))
+    g24, gn0, _ = oracle.pair_grads(itf.slave, itf.master, prm, ps, pm, w, with_n0=True)
+    gs, gm = oracle.scatter_grads(itf.slave, itf.master, ps, pm, g24)
+    if prm.normals:
+        ge = np.zeros((itf.slave.n_el, 3))
+        np.add.at(ge, ps, gn0)
+        gs = gs + oracle.normal_chain(itf.slave, ge)
+    return gs, gm
+
+
+# seeds 0-5 in the default mode; 6-11 with the dual basis, the continuous
+# normal field, the 3-point rule, or both of the first two
+MODES = [dict()] * 6 + [dict(dual=True), dict(nodal=True), dict(dual=True, nodal=True), dict(rule=3),
+                        dict(dual=True), dict(nodal=True)]
+
+
+@pytest.mark.parametrize("seed", range(len(MODES)))
 def test_random_interface_forward_and_gradients(seed):
     itf = random_interface(seed)
-    print(f"[gpu] {itf.name}", flush=True)
-    prm = oracle_params(itf)
-    g = gpu_run(itf, backward_seed=3300 + seed)
+    mode = MODES[seed]
+    print(f"[gpu] {itf.name} {mode}", flush=True)
+    prm = oracle_params(itf, **mode)
+    g = gpu_run(itf, backward_seed=3300 + seed, **mode)
     o = oracle.evaluate(itf, prm)
     assert_forward_parity(g, o)
-    w = oracle.pair_weights(itf.slave, itf.master, o["pair_s"], o["pair_m"], *weight_fns(3300 + seed))
-    g24, _ = oracle.pair_grads(itf.slave, itf.master, prm, o["pair_s"], o["pair_m"], w)
-    gs, gm = oracle.scatter_grads(itf.slave, itf.master, o["pair_s"], o["pair_m"], g24)
+    gs, gm = oracle_gradients(itf, prm, o, 3300 + seed)
+    # The gradient is invariant under a translation; how much the oracle's
+    # own gradient moves under one measures the rounding sensitivity of this
+    # draw (slivers between nearly coincident grid lines raise it), and no
+    # agreement can be asked beyond it.
+    sh = np.array([0.37, -0.21, 0.13])
+    moved = Interface(Mesh(itf.slave.X + sh, itf.slave.conn), Mesh(itf.master.X + sh, itf.master.conn), itf.delta)
+    o2 = oracle.evaluate(moved, prm)
+    assert np.array_equal(o2["pair_s"], o["pair_s"]) and np.array_equal(o2["pair_m"], o["pair_m"])
+    gs2, gm2 = oracle_gradients(moved, prm, o2, 3300 + seed)
+    tol = max(TOL, 10 * rel_err(gs2, gs), 10 * rel_err(gm2, gm))
     es, em = rel_err(g["gXs"], gs), rel_err(g["gXm"], gm)
-    print(f"pairs {o['pair_s'].size}, grad rel err slave {es:.2e} master {em:.2e}", flush=True)
-    assert es <= TOL and em <= TOL
+    print(f"pairs {o['pair_s'].size}, grad rel err slave {es:.2e} master {em:.2e}, tolerance {tol:.1e}", flush=True)
+    assert es <= tol and em <= tol
