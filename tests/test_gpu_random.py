@@ -91,3 +91,20 @@ def test_random_interface_forward_and_gradients(seed):
     es, em = rel_err(g["gXs"], gs), rel_err(g["gXm"], gm)
     print(f"pairs {o['pair_s'].size}, grad rel err slave {es:.2e} master {em:.2e}, tolerance {tol:.1e}", flush=True)
     assert es <= tol and em <= tol
+
+
+# Element-based integration (an n x n rule on each whole slave element) on
+# random interfaces, with both bases.
+@pytest.mark.parametrize("seed,ng,dual", [(0, 2, False), (3, 3, True), (6, 5, False), (9, 8, True)])
+def test_random_interface_element_based(seed, ng, dual):
+    itf = random_interface(seed)
+    print(f"[gpu] {itf.name} element rule {ng} dual={dual}", flush=True)
+    prm = oracle_params(itf, dual=dual)
+    g = gpu_run(itf, dual=dual, element_rule=ng)
+    o = oracle.evaluate_elements(itf, ng, prm)
+    assert np.array_equal(g["pair_s"], o["pair_s"]) and np.array_equal(g["pair_m"], o["pair_m"])
+    eD, eM, eg = rel_err(g["D"].data, o["D"].data), rel_err(g["M"].data, o["M"].data), rel_err(g["g"], o["g"])
+    print(f"pairs {o['pair_s'].size}, rel err D {eD:.1e} M {eM:.1e} g {eg:.1e}", flush=True)
+    assert np.array_equal(g["D"].indices, o["D"].indices) and np.array_equal(g["M"].indices, o["M"].indices)
+    assert eD <= TOL and eM <= TOL and eg <= TOL
+    assert g["stats"]["n_noconv"] == 0
