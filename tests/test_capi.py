@@ -4,6 +4,8 @@ point the C header declares, and the binding declares exactly those."""
 import ctypes
 import os
 import re
+import shutil
+import subprocess
 
 import pytest
 
@@ -72,3 +74,38 @@ def test_header_is_c_and_the_example_links(tmp_path):
     if not os.path.exists(_capi.LIB_PATH):
         pytest.fail("HIP library not built (run __graft_entry__.build())")
     assert os.path.exists(build_c_example(tmp_path))
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    # every struct the binding passes by pointer has, in C, the size and the
+    # field offsets and sizes of its ctypes twin (a field renamed, retyped or
+    # moved in the header shows here)
+    from paper_2202_03933_amd import _capi as C
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    structs = [C.mt_params, C.mt_stats, C.mt_capacity, C.mt_timings, C.mt_batch_tuning]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mortar_mi355x.h"', "int main(void) {"]
+    for st in structs:
+        n = st.__name__
+        lines.append(f'  printf("{n} . %zu\\n", sizeof({n}));')
+        for f, _ in st._fields_:
+            lines.append(f'  printf("{n} {f} %zu %zu\\n", offsetof({n}, {f}), sizeof((({n}*)0)->{f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = str(tmp_path / "layout")
+    subprocess.run([gcc, "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), str(src), "-o", exe],
+                   check=True, capture_output=True, text=True)
+    out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split("\n")
+    seen = 0
+    for line in filter(None, out):
+        n, f, *v = line.split()
+        st = getattr(C, n)
+        if f == ".":
+            assert int(v[0]) == ctypes.sizeof(st), n
+        else:
+            fd = getattr(st, f)
+            assert (int(v[0]), int(v[1])) == (fd.offset, fd.size), (n, f)
+        seen += 1
+    assert seen == sum(len(st._fields_) + 1 for st in structs)
