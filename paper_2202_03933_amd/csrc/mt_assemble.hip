@@ -316,8 +316,10 @@ __global__ __launch_bounds__(BS) void k_positions(int64_t n_items, const int32_t
   __shared__ int32_t span[POS_SPAN];
   __shared__ int32_t red[2][BS / 64];
   const int64_t n = MCOLS ? (int64_t)*n_dev : n_items;
-  const int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x;
-  if ((int64_t)blockIdx.x * BS >= n) return;  // whole workgroups past the end
+  // XCD-major tiles: neighbouring pairs (and the rows they stage) share an L2
+  const int64_t tile = dyn_tile(blockIdx.x, n, BS);
+  if (tile < 0) return;  // whole workgroups past the end
+  const int64_t i = tile * BS + threadIdx.x;
   bool act = i < n;
   int4 cs = make_int4(0, 0, 0, 0), key4 = make_int4(0, 0, 0, 0);
   if (act) {
@@ -611,13 +613,13 @@ hipError_t launch_pattern_positions(const int32_t* pair_s, const int32_t* pair_m
                                     const int32_t* M_rowptr, const int32_t* M_col, int32_t* posD, int32_t* posM,
                                     hipStream_t s) {
   if (n_s_el > 0) {
-    k_positions<false><<<grid_of(n_s_el), BS, 0, s>>>(n_s_el, nullptr, nullptr, nullptr, pair_off, conn_s, nullptr,
+    k_positions<false><<<xcd_grid(grid_of(n_s_el)), BS, 0, s>>>(n_s_el, nullptr, nullptr, nullptr, pair_off, conn_s, nullptr,
                                                       D_rowptr, D_col, posD, n_s_el);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   if (cap > 0)
-    k_positions<true><<<grid_of(cap), BS, 0, s>>>(cap, n_pairs, pair_s, pair_m, nullptr, conn_s, conn_m, M_rowptr,
+    k_positions<true><<<xcd_grid(grid_of(cap)), BS, 0, s>>>(cap, n_pairs, pair_s, pair_m, nullptr, conn_s, conn_m, M_rowptr,
                                                   M_col, posM, cap);
   return hipGetLastError();
 }
