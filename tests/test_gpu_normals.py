@@ -172,3 +172,53 @@ def test_batch_bitwise_equal_to_single_interfaces(dual):
                   flush=True)
             assert all(all(torch.equal(x, y) for x, y in zip(o, r)) for o, r in zip(g, ref_g))
     b.close()
+
+
+def _deformed(itf, step):
+    """The instance with its master slid tangentially (as in the batched
+    search tests) and its slave nodes moved by a seeded random 2% of an
+    element edge, so that the normal field changes from step to step."""
+    from synth.meshes import Interface, Mesh
+    from tests.test_gpu_batch import _moved
+    c = itf.slave.conn
+    h = float(np.linalg.norm(itf.slave.X[c[:, 1]] - itf.slave.X[c[:, 0]], axis=1).mean())
+    Xs = itf.slave.X + 0.02 * h * np.random.default_rng(50 + step).standard_normal(itf.slave.X.shape)
+    return Interface(Mesh(Xs, c), _moved(itf, step).master, itf.delta, name=itf.name + f", deformed {step}",
+                     meta=itf.meta)
+
+
+# The search of all instances in one call with the normal field, while both
+# sides move: a search captured as a HIP graph recomputes the field from the
+# coordinates at every replay, so candidates, pairs, patterns and the batched
+# forward and backward equal fresh per-interface builds bit for bit.
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_batch_search_moving_instances(use_graph):
+    from paper_2202_03933_amd import MortarBatch, MortarInterface
+    from tests.test_gpu_batch import _assert_same_search, equal_outs, weights_for
+    dev = torch.device("cuda", 0)
+
+    def build(insts):
+        return [MortarInterface(torch.from_numpy(i.slave.X), torch.from_numpy(i.slave.conn),
+                                torch.from_numpy(i.master.X), torch.from_numpy(i.master.conn),
+                                params=gpu_params(i, nodal=True), device=dev).setup() for i in insts]
+
+    instances = synth.batched_instances(n_inst=8, max_side=40)
+    ifaces = build(instances)
+    b = MortarBatch(ifaces)
+    for step in range(3):
+        moved = [_deformed(itf, step) for itf in instances]
+        print(f"[gpu] batched search with the normal field, graph={use_graph}, step {step}", flush=True)
+        for it, itf in zip(ifaces, moved):
+            it.move_coordinates(itf.slave.X, itf.master.X)
+        b.search(use_graph=use_graph)
+        refs = build(moved)
+        _assert_same_search(ifaces, refs)
+        outs = b.forward(use_graph=use_graph)
+        ref_out = [tuple(t.clone() for t in r.integrate()) for r in refs]
+        W = [weights_for(r, 4300 + k) for k, r in enumerate(refs)]
+        g = b.backward(W, use_graph=use_graph)
+        ref_g = [tuple(t.clone() for t in r.backward(*w)) for r, w in zip(refs, W)]
+        torch.cuda.synchronize()
+        assert all(equal_outs(o, r) for o, r in zip(outs, ref_out)), step
+        assert all(equal_outs(x, r) for x, r in zip(g, ref_g)), step
+    b.close()
