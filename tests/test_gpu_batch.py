@@ -257,3 +257,37 @@ def test_batch_search_graph_recaptured_after_rebind():
         ref = tuple(t.clone() for t in refs[1].integrate()) + tuple(t.clone() for t in refs[1].backward(*W))
         torch.cuda.synchronize()
         assert equal_outs(own, ref), step
+
+
+# Instances that run every kernel on the caller's stream (single_stream) in
+# a batch: the batched search (eager, then captured and replayed), forward
+# and backward equal fresh builds with the internal streams bit for bit.
+def test_batch_single_stream_instances():
+    from paper_2202_03933_amd import MortarBatch, MortarInterface
+    dev = torch.device("cuda", 0)
+    instances = synth.batched_instances(n_inst=6, max_side=40)
+    ifaces = []
+    for itf in instances:
+        p = gpu_params(itf)
+        p.single_stream = 1
+        ifaces.append(MortarInterface(torch.from_numpy(itf.slave.X), torch.from_numpy(itf.slave.conn),
+                                      torch.from_numpy(itf.master.X), torch.from_numpy(itf.master.conn),
+                                      params=p, device=dev).setup())
+    b = MortarBatch(ifaces)
+    for step in range(3):  # eager, graph (captured), graph (replayed)
+        moved = [_moved(itf, step) for itf in instances]
+        print(f"[gpu] batch of single-stream instances, step {step}", flush=True)
+        for it, itf in zip(ifaces, moved):
+            it.move_coordinates(itf.slave.X, itf.master.X)
+        b.search(use_graph=step > 0)
+        refs = make_ifaces(moved)
+        _assert_same_search(ifaces, refs)
+        outs = b.forward(use_graph=step > 0)
+        ref_out = [tuple(t.clone() for t in r.integrate()) for r in refs]
+        W = [weights_for(r, 4400 + k) for k, r in enumerate(refs)]
+        g = b.backward(W, use_graph=step > 0)
+        ref_g = [tuple(t.clone() for t in r.backward(*w)) for r, w in zip(refs, W)]
+        torch.cuda.synchronize()
+        assert all(equal_outs(o, r) for o, r in zip(outs, ref_out)), step
+        assert all(equal_outs(x, r) for x, r in zip(g, ref_g)), step
+    b.close()
