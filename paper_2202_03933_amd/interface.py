@@ -22,15 +22,21 @@ def _stream(stream=None):
 
 
 def default_params(**kw):
+    """The library's default mt_params with the given fields replaced
+    (`dual` and `nodal_normals` as booleans); an unknown name raises
+    TypeError."""
     p = C.mt_params()
     C.check(C.lib().mt_default_params(ctypes.byref(p)))
+    fields = {f[0] for f in C.mt_params._fields_}
     for k, v in kw.items():
         if k == "dual":
             p.lm_basis = C.MT_BASIS_DUAL if v else C.MT_BASIS_STANDARD
         elif k == "nodal_normals":
             p.normals = C.MT_NORMALS_NODAL if v else C.MT_NORMALS_ELEMENT
-        else:
+        elif k in fields:
             setattr(p, k, v)
+        else:
+            raise TypeError(f"default_params: mt_params has no field {k!r}")
     return p
 
 

@@ -109,3 +109,15 @@ def test_binding_structs_match_the_header(tmp_path):
             assert (int(v[0]), int(v[1])) == (fd.offset, fd.size), (n, f)
         seen += 1
     assert seen == sum(len(st._fields_) + 1 for st in structs)
+
+
+def test_default_params_sets_fields_and_refuses_unknown_names():
+    # mt_default_params is host code only (no device call), so it runs here
+    from paper_2202_03933_amd import _capi as C, default_params
+    p = default_params(delta=2.5e-3, dual=True, nodal_normals=True, rule=3, single_stream=1)
+    assert (p.delta, p.lm_basis, p.normals, p.rule, p.single_stream) == (2.5e-3, C.MT_BASIS_DUAL,
+                                                                          C.MT_NORMALS_NODAL, 3, 1)
+    q = default_params()
+    assert (q.lm_basis, q.normals, q.rule, q.newton_maxit) == (C.MT_BASIS_STANDARD, C.MT_NORMALS_ELEMENT, 7, 30)
+    with pytest.raises(TypeError):
+        default_params(delat=1e-3)
