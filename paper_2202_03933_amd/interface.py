@@ -7,6 +7,7 @@ library through the C ABI.  Coordinates are kept as structure-of-arrays
 
 import ctypes
 
+import numpy as np
 import torch
 
 from . import _capi as C
@@ -48,6 +49,23 @@ def workspace(nbytes, device):
     return t, t.data_ptr() + off
 
 
+def _check_mesh_shapes(X, conn, side, n_nodes=None):
+    """Coordinates must be (n, 3) and connectivity (n_el, 4) (quad4): the
+    kernels read three coordinates per node and four node indices per
+    element.  A coordinate update without new connectivity (n_nodes given)
+    keeps the node count of the upload.  Raises ValueError."""
+    xs = tuple(X.shape) if hasattr(X, "shape") else tuple(np.shape(X))
+    if len(xs) != 2 or xs[1] != 3:
+        raise ValueError(f"{side} coordinates: shape {xs}, expected (n_nodes, 3)")
+    if n_nodes is not None and xs[0] != n_nodes:
+        raise ValueError(f"{side} coordinates: {xs[0]} nodes, the uploaded mesh has {n_nodes} "
+                         "(new connectivity needs a full upload)")
+    if conn is not None:
+        cs = tuple(conn.shape) if hasattr(conn, "shape") else tuple(np.shape(conn))
+        if len(cs) != 2 or cs[1] != 4:
+            raise ValueError(f"{side} connectivity: shape {cs}, expected (n_elements, 4)")
+
+
 class MortarInterface:
     """One slave/master interface registered with a library context.
 
@@ -81,6 +99,9 @@ class MortarInterface:
         list is invalidated; without, only the coordinates are replaced and
         the pair list and pattern are kept."""
         dev = self.device
+        full = conn_s is not None or conn_m is not None or not self._uploaded
+        _check_mesh_shapes(Xs, conn_s, "slave", None if full else self.Xs.shape[1])
+        _check_mesh_shapes(Xm, conn_m, "master", None if full else self.Xm.shape[1])
         self.Xs = torch.as_tensor(Xs, dtype=torch.float64, device=dev).t().contiguous()
         self.Xm = torch.as_tensor(Xm, dtype=torch.float64, device=dev).t().contiguous()
         if conn_s is not None:
@@ -88,7 +109,6 @@ class MortarInterface:
         if conn_m is not None:
             self.conn_m = torch.as_tensor(conn_m, dtype=torch.int32, device=dev).contiguous()
         L = C.lib()
-        full = conn_s is not None or conn_m is not None or not self._uploaded
         for side, X, conn in ((C.MT_SIDE_SLAVE, self.Xs, self.conn_s), (C.MT_SIDE_MASTER, self.Xm, self.conn_m)):
             n = X.shape[1]
             if full:

@@ -121,3 +121,20 @@ def test_default_params_sets_fields_and_refuses_unknown_names():
     assert (q.lm_basis, q.normals, q.rule, q.newton_maxit) == (C.MT_BASIS_STANDARD, C.MT_NORMALS_ELEMENT, 7, 30)
     with pytest.raises(TypeError):
         default_params(delat=1e-3)
+
+
+def test_mesh_shapes_checked_before_any_device_call():
+    # the kernels read 3 coordinates per node and 4 node indices per element:
+    # the binding refuses other shapes, and a coordinate update that changes
+    # the node count, before anything reaches the library
+    import numpy as np
+    from paper_2202_03933_amd.interface import _check_mesh_shapes
+    X, conn = np.zeros((9, 3)), np.zeros((4, 4), np.int32)
+    _check_mesh_shapes(X, conn, "slave")
+    _check_mesh_shapes(X, None, "slave", n_nodes=9)
+    for bad in (dict(X=np.zeros((9, 2)), conn=conn), dict(X=np.zeros(27), conn=conn),
+                dict(X=X, conn=np.zeros((4, 3), np.int32)), dict(X=X, conn=np.zeros(16, np.int32))):
+        with pytest.raises(ValueError):
+            _check_mesh_shapes(bad["X"], bad["conn"], "slave")
+    with pytest.raises(ValueError):
+        _check_mesh_shapes(np.zeros((10, 3)), None, "master", n_nodes=9)
