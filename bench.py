@@ -515,7 +515,7 @@ def main():
     iface = MortarInterface(Xs, torch.from_numpy(itf.slave.conn), Xm, torch.from_numpy(itf.master.conn),
                             params=default_params(delta=itf.delta), device=dev)
     iface.setup()
-    n_pairs, n_cand = iface.n_pairs, iface.n_cand
+    n_pairs, n_cand, nnz_D, nnz_M = iface.n_pairs, iface.n_cand, iface.nnz_D, iface.nnz_M
     Dr = np.repeat(np.arange(itf.slave.n_nodes), np.diff(iface.D_rowptr.cpu().numpy()))
     Mr = np.repeat(np.arange(itf.slave.n_nodes), np.diff(iface.M_rowptr.cpu().numpy()))
     wD = torch.from_numpy(keyed_normal(3000, TAG_D, Dr, iface.D_col.cpu().numpy())).to(dev)
@@ -670,7 +670,7 @@ def main():
         e["alone"] = {"launch_ms": fwd_alone, "achieved": executed / (fwd_alone * 1e-3) / 1e12,
                       "frac": executed / (fwd_alone * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFLOPS}
     ab = algorithmic_bytes(itf.slave.n_nodes, itf.master.n_nodes, itf.slave.n_el, itf.master.n_el, n_cand, n_pairs,
-                           iface.nnz_D, iface.nnz_M)
+                           nnz_D, nnz_M)
     search_ms = sum(per_step.get(k, 0.0) for k in ("prep", "bin_sort", "cand", "clip", "compact"))
     hbm = {"search": hbm_entry(ab["search"], search_ms),
            "assemble": hbm_entry(ab["forward"] - (24 * (itf.slave.n_nodes + itf.master.n_nodes)
@@ -693,7 +693,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "wavy z=0.05 sin(2 pi x) sin(2 pi y), slave 1024x1024 / master 777x777 quad4, "
                                "normal offsets U[-1e-3,1e-3], delta 1.25e-3: search + forward + backward per step",
-                   "n_pairs": n_pairs, "n_candidates": n_cand, "nnz_D": iface.nnz_D, "nnz_M": iface.nnz_M},
+                   "n_pairs": n_pairs, "n_candidates": n_cand, "nnz_D": nnz_D, "nnz_M": nnz_M},
         "step_modes_ms": {"graph_replay": ms_graph, "async": ms_async, "sync_counts": ms_sync,
                           "fused_async": ms_fused, "fused_graph_replay": ms_fused_graph,
                           "single_stream_async": single["ms_per_step"] if single else None},

@@ -112,6 +112,10 @@ class MortarBatch:
 
     def forward(self, outs=None, use_graph=False):
         outs = outs if outs is not None else self.alloc_outputs()
+        if len(outs) != len(self.ifaces):
+            raise ValueError(f"{len(outs)} output triples for {len(self.ifaces)} instances")
+        for it, o in zip(self.ifaces, outs):
+            it._check_values(*o)
         self._keep = (_ptr_table([o[0] for o in outs]), _ptr_table([o[1] for o in outs]),
                       _ptr_table([o[2] for o in outs]))
         cur = torch.cuda.current_stream(self.device)
@@ -127,7 +131,13 @@ class MortarBatch:
         if outs is None:
             outs = [(torch.empty(3, it.n_slave_nodes, dtype=torch.float64, device=dev),
                      torch.empty(3, it.n_master_nodes, dtype=torch.float64, device=dev)) for it in self.ifaces]
+        if len(weights) != len(self.ifaces) or len(outs) != len(self.ifaces):
+            raise ValueError(f"{len(weights)} weight triples and {len(outs)} gradient pairs for "
+                             f"{len(self.ifaces)} instances")
         w = [tuple(x.contiguous() for x in ws) for ws in weights]
+        for it, ws, o in zip(self.ifaces, w, outs):
+            it._check_values(*ws, what="weights")
+            it._check_grads(*o)
         self._keep_w = w
         tabs = (_ptr_table([x[0] for x in w]), _ptr_table([x[1] for x in w]), _ptr_table([x[2] for x in w]),
                 _ptr_table([o[0] for o in outs]), _ptr_table([o[1] for o in outs]))

@@ -66,6 +66,26 @@ def _check_mesh_shapes(X, conn, side, n_nodes=None):
             raise ValueError(f"{side} connectivity: shape {cs}, expected (n_elements, 4)")
 
 
+def _check_f64(t, n, name, device, rows=None):
+    """A float64 tensor on `device` that the kernels read or write as n
+    values (rows x n for gradients); n None: not known on the host (a search
+    without read-back), only the type and device are checked.  Outputs and
+    gradients must also be contiguous (the library writes through the
+    pointer).  Raises TypeError / ValueError."""
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64:
+        raise TypeError(f"{name}: expected a float64 torch tensor, got "
+                        f"{t.dtype if isinstance(t, torch.Tensor) else type(t).__name__}")
+    if t.device.type != device.type or (device.type == "cuda" and t.device.index != device.index):
+        raise ValueError(f"{name}: on {t.device}, the interface is on {device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: not contiguous")
+    if rows is not None:
+        if t.dim() != 2 or t.shape[0] != rows or (n is not None and t.shape[1] != n):
+            raise ValueError(f"{name}: shape {tuple(t.shape)}, expected ({rows}, {n})")
+    elif n is not None and t.numel() < n:
+        raise ValueError(f"{name}: {t.numel()} values, at least {n} needed")
+
+
 class MortarInterface:
     """One slave/master interface registered with a library context.
 
@@ -78,6 +98,8 @@ class MortarInterface:
         if device is None:
             device = torch.device("cuda", torch.cuda.current_device())
         self.device = torch.device(device)
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
         self.stream = stream
         h = ctypes.c_void_p()
         C.check(C.lib().mt_create(ctypes.byref(h), self.device.index or 0))
@@ -86,7 +108,8 @@ class MortarInterface:
         C.check(C.lib().mt_set_params(self.h, ctypes.byref(self.params)))
         self._uploaded = False
         self.set_coordinates(Xs, Xm, conn_s, conn_m)
-        self.n_cand = self.n_pairs = self.nnz_D = self.nnz_M = None
+        self.n_cand = self.n_pairs = None
+        self._nnz = None  # (nnz_D, nnz_M) of the last pattern, None: not read back
         self.capacity = None
         self._ws = None
         self._ws_ptr = 0
@@ -133,7 +156,8 @@ class MortarInterface:
 
     def _searched(self):
         # a search without read-back ran (mt_batch_search): counts unknown
-        self.n_cand = self.n_pairs = self.nnz_D = self.nnz_M = None
+        self.n_cand = self.n_pairs = None
+        self._nnz = None
         self._csr = None
 
     def refresh(self):
@@ -142,7 +166,7 @@ class MortarInterface:
         self.check()
         st = self.stats()
         self.n_cand, self.n_pairs = st["n_candidates"], st["n_pairs"]
-        self.nnz_D, self.nnz_M = st["nnz_D"], st["nnz_M"]
+        self._nnz = (st["nnz_D"], st["nnz_M"])
         self._csr = None
 
     @property
@@ -240,13 +264,29 @@ class MortarInterface:
         self._csr = None
         if not sync:
             C.check(C.lib().mt_csr_pattern(self.h, None, None, _stream(self.stream)))
+            self._nnz = None  # read back on first use of nnz_D / nnz_M (refresh)
             return None
         a, b = ctypes.c_int64(), ctypes.c_int64()
         C.check(C.lib().mt_csr_pattern(self.h, ctypes.byref(a), ctypes.byref(b), _stream(self.stream)))
-        self.nnz_D, self.nnz_M = a.value, b.value
+        self._nnz = (a.value, b.value)
         st = self.stats()
         self.n_cand, self.n_pairs = st["n_candidates"], st["n_pairs"]
-        return self.nnz_D, self.nnz_M
+        return self._nnz
+
+    @property
+    def nnz_D(self):
+        """Nonzeros of D in the last pattern (read back first, waiting for
+        the device, after a call that did not read the counts)."""
+        if self._nnz is None:
+            self.refresh()
+        return self._nnz[0]
+
+    @property
+    def nnz_M(self):
+        """Nonzeros of M in the last pattern (read back as nnz_D)."""
+        if self._nnz is None:
+            self.refresh()
+        return self._nnz[1]
 
     def _fetch_csr(self):
         if getattr(self, "_csr", None) is None:
@@ -274,8 +314,21 @@ class MortarInterface:
                 torch.empty(self.nnz_M, dtype=torch.float64, device=dev),
                 torch.empty(self.n_slave_nodes, dtype=torch.float64, device=dev))
 
+    def _check_values(self, D, M, g, what="output"):
+        # the counts as known on the host: no read-back (a sync-free step
+        # stays sync-free)
+        nD, nM = self._nnz if self._nnz is not None else (None, None)
+        _check_f64(D, nD, f"D {what}", self.device)
+        _check_f64(M, nM, f"M {what}", self.device)
+        _check_f64(g, self.n_slave_nodes, f"gap {what}", self.device)
+
+    def _check_grads(self, gXs, gXm):
+        _check_f64(gXs, self.n_slave_nodes, "slave gradient", self.device, rows=3)
+        _check_f64(gXm, self.n_master_nodes, "master gradient", self.device, rows=3)
+
     def integrate(self, out=None):
         D, M, g = out if out is not None else self.alloc_outputs()
+        self._check_values(D, M, g)
         C.check(C.lib().mt_integrate(self.h, _ptr(D), _ptr(M), _ptr(g), _stream(self.stream)))
         return D, M, g
 
@@ -289,6 +342,8 @@ class MortarInterface:
         W_D = W_D.contiguous()
         W_M = W_M.contiguous()
         w_g = w_g.contiguous()
+        self._check_values(W_D, W_M, w_g, "weights")
+        self._check_grads(gXs, gXm)
         C.check(C.lib().mt_backward(self.h, _ptr(W_D), _ptr(W_M), _ptr(w_g), _ptr(gXs), _ptr(gXm),
                                     _stream(self.stream)))
         return gXs, gXm
@@ -307,6 +362,9 @@ class MortarInterface:
         W_D = W_D.contiguous()
         W_M = W_M.contiguous()
         w_g = w_g.contiguous()
+        self._check_values(D, M, g)
+        self._check_values(W_D, W_M, w_g, "weights")
+        self._check_grads(gXs, gXm)
         C.check(C.lib().mt_integrate_backward(self.h, _ptr(D), _ptr(M), _ptr(g), _ptr(W_D), _ptr(W_M), _ptr(w_g),
                                               _ptr(gXs), _ptr(gXm), _stream(self.stream)))
         return (D, M, g), (gXs, gXm)

@@ -138,3 +138,30 @@ def test_mesh_shapes_checked_before_any_device_call():
             _check_mesh_shapes(bad["X"], bad["conn"], "slave")
     with pytest.raises(ValueError):
         _check_mesh_shapes(np.zeros((10, 3)), None, "master", n_nodes=9)
+
+
+def test_value_buffers_checked_before_any_device_call():
+    # weights, values and gradients: float64, on the interface's device,
+    # contiguous, at least the counted length (gradients exactly (3, n));
+    # unknown counts (a search without read-back) skip the length only
+    import torch
+    from paper_2202_03933_amd.interface import _check_f64
+    cpu = torch.device("cpu")
+    _check_f64(torch.zeros(10, dtype=torch.float64), 10, "W_D", cpu)
+    _check_f64(torch.zeros(12, dtype=torch.float64), 10, "W_D", cpu)  # a capacity-sized buffer
+    _check_f64(torch.zeros(3, dtype=torch.float64), None, "W_D", cpu)
+    _check_f64(torch.zeros(3, 7, dtype=torch.float64), 7, "gXs", cpu, rows=3)
+    with pytest.raises(ValueError):
+        _check_f64(torch.zeros(9, dtype=torch.float64), 10, "W_D", cpu)
+    with pytest.raises(TypeError):
+        _check_f64(torch.zeros(10, dtype=torch.float32), 10, "W_D", cpu)
+    with pytest.raises(TypeError):
+        _check_f64([0.0] * 10, 10, "W_D", cpu)
+    with pytest.raises(ValueError):
+        _check_f64(torch.zeros(10, 2, dtype=torch.float64)[:, 0], 10, "D", cpu)  # strided view
+    with pytest.raises(ValueError):
+        _check_f64(torch.zeros(7, 3, dtype=torch.float64), 7, "gXs", cpu, rows=3)  # (n, 3) instead of (3, n)
+    with pytest.raises(ValueError):
+        _check_f64(torch.zeros(3, 8, dtype=torch.float64), 7, "gXs", cpu, rows=3)
+    with pytest.raises(ValueError):
+        _check_f64(torch.zeros(10, dtype=torch.float64), 10, "W_D", torch.device("cuda", 0))

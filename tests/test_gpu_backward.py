@@ -310,9 +310,15 @@ def test_error_codes():
     iface = MortarInterface(torch.from_numpy(itf.slave.X), torch.from_numpy(itf.slave.conn),
                             torch.from_numpy(itf.master.X), torch.from_numpy(itf.master.conn),
                             params=default_params(dual=True), device=dev)
+    # integrate before any build: the library reports the state (the binding
+    # checks the gap buffer's length, which it knows, and not D and M, whose
+    # lengths no build has counted yet); a short gap buffer never reaches it
+    one = torch.empty(1, dtype=torch.float64, device=dev)
     with pytest.raises(MortarError) as e:
-        iface.integrate(out=(torch.empty(1, dtype=torch.float64, device=dev),) * 3)
+        iface.integrate(out=(one, one, torch.empty(itf.slave.n_nodes, dtype=torch.float64, device=dev)))
     assert e.value.code == C.MT_ESTATE
+    with pytest.raises(ValueError):
+        iface.integrate(out=(one, one, one))
     p = default_params()
     p.single_stream = 2
     assert C.lib().mt_set_params(iface.h, ctypes.byref(p)) == C.MT_EINVAL

@@ -121,3 +121,36 @@ def test_pairs_lost_after_update(dual):
     Do, Mo, go = oracle.assemble(moved.slave, moved.master, ps, pm, blocks)
     assert rel_err(D.cpu().numpy(), Do.data) <= TOL and rel_err(M.cpu().numpy(), Mo.data) <= TOL
     assert np.abs(g.cpu().numpy()).max() == 0.0 and np.abs(go).max() == 0.0  # all on z = 0
+
+
+# The binding's own checks, before anything reaches the library: buffers of
+# the wrong type, length or layout raise; after the sync-free build and
+# pattern calls the host counts are read back on first use (nnz_D, the CSR
+# arrays), so the arrays copied out have the lengths of the new pattern.
+def test_binding_checks_buffers_and_counts_after_sync_free_calls():
+    itf = synth.interface_config(2, scale=24)
+    it = _iface(itf).setup()
+    nnz = (it.nnz_D, it.nnz_M)
+    cols = (it.D_col.clone(), it.M_col.clone())
+    it.build_pairs(sync=False)
+    it.csr_pattern(sync=False)
+    assert torch.equal(it.D_col, cols[0]) and torch.equal(it.M_col, cols[1])
+    assert (it.nnz_D, it.nnz_M) == nnz
+    D, M, g = it.integrate()
+    W = (torch.ones_like(D), torch.ones_like(M), torch.ones_like(g))
+    ns, nm = it.n_slave_nodes, it.n_master_nodes
+    with pytest.raises(TypeError):
+        it.backward(W[0].float(), W[1], W[2])
+    with pytest.raises(ValueError):
+        it.backward(W[0][:-1], W[1], W[2])
+    with pytest.raises(ValueError):
+        it.backward(W[0].cpu(), W[1], W[2])
+    with pytest.raises(ValueError):
+        it.backward(*W, out=(torch.empty(ns, 3, dtype=torch.float64, device=D.device),
+                             torch.empty(3, nm, dtype=torch.float64, device=D.device)))
+    with pytest.raises(ValueError):
+        it.integrate(out=(D, M[:-1], g))
+    gXs, gXm = it.backward(*W)
+    torch.cuda.synchronize()
+    assert gXs.shape == (3, ns) and gXm.shape == (3, nm)
+    assert torch.isfinite(gXs).all() and torch.isfinite(gXm).all()
