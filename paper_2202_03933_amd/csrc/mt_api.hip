@@ -632,8 +632,8 @@ int mt_build_pairs(mt_ctx* c, const mt_capacity* cap_in, void* ws, size_t ws_byt
     int rc = normals_for_coords(c, st);
     if (rc) return rc;
     double* part = c->prep_part.as<double>();
-    MT_HIP(launch_prep(S, true, c->box_s.as<double>(), c->sdata.as<double>(), nullptr, part, st));
-    MT_HIP(launch_prep(M, false, c->box_m.as<double>(), nullptr, c->mdata.as<double>(), part + 9 * (size_t)nb_s, st));
+    MT_HIP(launch_prep(S, M, c->box_s.as<double>(), c->sdata.as<double>(), c->box_m.as<double>(),
+                       c->mdata.as<double>(), part, st));
     MT_HIP(launch_prep_reduce(part, nb_s, nb_m, red, c->params.delta, c->params.bin_size, cap.cells, dst, st));
   }
   const Grid* g = &dst->grid;

@@ -277,11 +277,12 @@ hipError_t fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
 hipError_t fill_f64(double* p, double v, int64_t n, hipStream_t s);
 
 // ---- search (mt_search.hip) ------------------------------------------------
-// Element preparation of one side; per-block partial reductions go to
-// part[prep_blocks(n_el)][9], reduced for both sides by launch_prep_reduce.
+// Element preparation of both sides in one launch; per-block partial
+// reductions go to part[prep_blocks(S.n_el) + prep_blocks(M.n_el)][9] (slave
+// blocks first), reduced by launch_prep_reduce.
 int prep_blocks(int32_t n_el);
-hipError_t launch_prep(const DeviceMesh& m, bool slave, double* box, double* sd, double* md, double* part,
-                       hipStream_t s);
+hipError_t launch_prep(const DeviceMesh& S, const DeviceMesh& M, double* box_s, double* sd, double* box_m,
+                       double* md, double* part, hipStream_t s);
 // The reductions of both sides, then the search grid (st->grid) from them,
 // at most max_cells cells; flags non-finite coordinates.
 hipError_t launch_prep_reduce(const double* part, int nb_s, int nb_m, PrepReduce* red, double delta,

@@ -53,20 +53,44 @@ __device__ __forceinline__ T wave_min(T x) {
 // elements the precomputed frame and projected polygon of the candidate
 // pass, for master elements their node coordinates gathered element by
 // element (md[12 e + 3 k + d], read with 16-byte loads by the candidate
-// pass).  Grid-stride loop; one atomic per block and quantity.
-__global__ __launch_bounds__(BS) void k_prep(const double* __restrict__ x, const double* __restrict__ y,
-                                              const double* __restrict__ z, const int32_t* __restrict__ conn,
-                                              int32_t n_el, int32_t n_nodes, int slave,
-                                              const double* __restrict__ nrm,
-                                              double* __restrict__ box, double* __restrict__ sd,
-                                              double* __restrict__ md, double* __restrict__ part) {
+// pass).  Both sides in one launch (blockIdx.y: 0 slave, 1 master), so that
+// the shorter master pass fills the slave pass's tail; within a side a
+// grid-stride loop over its P.nb blocks, each writing its partials of the
+// reductions to P.part[block].
+struct PrepSide {
+  const double* x;
+  const double* y;
+  const double* z;
+  const int32_t* conn;
+  const double* nrm;  // slave element plane normals (continuous field) or null
+  double* box;
+  double* sd;  // slave: frame data
+  double* md;  // master: gathered node coordinates
+  double* part;
+  int32_t n_el, n_nodes, nb;
+};
+
+__global__ __launch_bounds__(BS) void k_prep(PrepSide s_side, PrepSide m_side) {
+  const bool slave = blockIdx.y == 0;
+  const PrepSide& P = slave ? s_side : m_side;
+  if ((int)blockIdx.x >= P.nb) return;  // the whole block: the side has fewer blocks
+  const double* __restrict__ x = P.x;
+  const double* __restrict__ y = P.y;
+  const double* __restrict__ z = P.z;
+  const int32_t* __restrict__ conn = P.conn;
+  const int32_t n_el = P.n_el, n_nodes = P.n_nodes;
+  const double* __restrict__ nrm = P.nrm;
+  double* __restrict__ box = P.box;
+  double* __restrict__ sd = P.sd;
+  double* __restrict__ md = P.md;
+  double* __restrict__ part = P.part;
   __shared__ double sh[BS / 64][8];
   __shared__ int bad;  // 1: connectivity out of range, 2: a coordinate not finite
   if (threadIdx.x == 0) bad = 0;
   __syncthreads();
   double ext = 0.0, edge = 0.0;
   double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  for (int e = blockIdx.x * BS + threadIdx.x; e < n_el; e += gridDim.x * BS) {
+  for (int e = blockIdx.x * BS + threadIdx.x; e < n_el; e += P.nb * BS) {
     const int4 c = load_conn(conn, e);
     const bool ok = c.x >= 0 && c.y >= 0 && c.z >= 0 && c.w >= 0 && c.x < n_nodes && c.y < n_nodes &&
                     c.z < n_nodes && c.w < n_nodes;
@@ -729,11 +753,14 @@ __global__ __launch_bounds__(BS) void k_cand_fill_long(const double* __restrict_
 
 int prep_blocks(int32_t n_el) { return n_el == 0 ? 0 : std::min(2048, (n_el + BS - 1) / BS); }
 
-hipError_t launch_prep(const DeviceMesh& m, bool slave, double* box, double* sd, double* md, double* part,
-                       hipStream_t s) {
-  if (m.n_el == 0) return hipSuccess;
-  k_prep<<<prep_blocks(m.n_el), BS, 0, s>>>(m.x, m.y, m.z, m.conn, m.n_el, m.n_nodes, slave ? 1 : 0,
-                                             slave ? m.nrm : nullptr, box, sd, md, part);
+hipError_t launch_prep(const DeviceMesh& S, const DeviceMesh& M, double* box_s, double* sd, double* box_m,
+                       double* md, double* part, hipStream_t s) {
+  const int nb_s = prep_blocks(S.n_el), nb_m = prep_blocks(M.n_el);
+  if (nb_s == 0 && nb_m == 0) return hipSuccess;
+  const PrepSide ps{S.x, S.y, S.z, S.conn, S.nrm, box_s, sd, nullptr, part, S.n_el, S.n_nodes, nb_s};
+  const PrepSide pm{M.x, M.y, M.z, M.conn, nullptr, box_m, nullptr, md, part + (size_t)PREP_PART * nb_s,
+                    M.n_el, M.n_nodes, nb_m};
+  k_prep<<<dim3((unsigned)std::max(nb_s, nb_m), 2), BS, 0, s>>>(ps, pm);
   return hipGetLastError();
 }
 
